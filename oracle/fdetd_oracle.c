@@ -1,0 +1,640 @@
+/*
+ * fdetd_oracle.c -- plain, slow, obviously correct CPU FP64 reference of the FDETD field update
+ * and of the laser-envelope exponential propagator (arXiv 2605.12132).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, by the smoke check and by the CPU-baseline leg of the
+ * benchmark.  The product (GPU) path never includes, links or calls it, and the two share no code.
+ *
+ * The oracle follows the paper's own order of operations:
+ *   - every operator is a banded matrix applied row by row (section 2.2, banded-matrix products),
+ *     values outside the grid are extended by the radial symmetry rules (section 2.4, Table 1) or
+ *     ignored (outside [0, M_z) in z and beyond the last radial node);
+ *   - H_m is the discrete Ampere/Faraday system of section 2.5 written in complex modes
+ *     (d/dtheta -> i m, the complex form of the real 2x2 rotation of the mode pair);
+ *   - a step is the midpoint solution exp(dt H) psi - dt exp(dt H/2) Jbar (section 2.1, with the
+ *     factor dt of the midpoint quadrature written out), each exponential being the explicit Taylor
+ *     sum sum_{n=0..N} (dt^n / n!) H^n (section 2.5, algorithm summary), summed forward;
+ *   - the envelope step is the Taylor sum of exp(dt H_a) (section 4.1/4.2).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math, no FMA contraction).
+ * Parity of this file against the mathematics is pinned by the CPU test suite.
+ */
+#include "fdetd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define IDX(P, k, i) ((size_t)(k) * (size_t)(P)->nz + (size_t)(i))
+
+enum { ER = 0, ETH = 1, EZ = 2, BR = 3, BTH = 4, BZ = 5 };
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Coefficients.  All are Lagrange-interpolation weights written as closed products.           */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Staggered first derivative of order 2*nd (section 2.3, staggered differences D^(+-)):
+ * f'(0) ~ sum_j a_j [f((j-1/2)h) - f(-(j-1/2)h)] / h.  Exactness on x^(2p-1), p=1..nd, gives
+ * a_j (2j-1) = prod_{i!=j} (2i-1)^2 / ((2i-1)^2 - (2j-1)^2). */
+void oracle_coef_staggered(int nd, double *a)
+{
+    for (int j = 1; j <= nd; ++j) {
+        double yj = 2.0 * j - 1.0, prod = 1.0;
+        for (int i = 1; i <= nd; ++i) {
+            if (i == j) continue;
+            double yi = 2.0 * i - 1.0;
+            prod *= (yi * yi) / (yi * yi - yj * yj);
+        }
+        a[j - 1] = prod / yj;
+    }
+}
+
+/* Lagrange half-cell shift of the same order (section 2.3, S^(+-)):
+ * f(0) ~ sum_j s_j [f((j-1/2)h) + f(-(j-1/2)h)],  2 s_j = prod_{i!=j} (2i-1)^2/((2i-1)^2-(2j-1)^2). */
+void oracle_coef_halfshift(int nd, double *s)
+{
+    for (int j = 1; j <= nd; ++j) {
+        double yj = 2.0 * j - 1.0, prod = 1.0;
+        for (int i = 1; i <= nd; ++i) {
+            if (i == j) continue;
+            double yi = 2.0 * i - 1.0;
+            prod *= (yi * yi) / (yi * yi - yj * yj);
+        }
+        s[j - 1] = 0.5 * prod;
+    }
+}
+
+/* Centred (non-staggered) first derivative D^(C) (section 2.3 radial Laplacian, section 4.2):
+ * f'(0) ~ sum_j d_j [f(jh) - f(-jh)] / h,  2 j d_j = prod_{i!=j} i^2/(i^2-j^2). */
+void oracle_coef_centred_d1(int nd, double *d)
+{
+    for (int j = 1; j <= nd; ++j) {
+        double prod = 1.0;
+        for (int i = 1; i <= nd; ++i) {
+            if (i == j) continue;
+            prod *= ((double)i * i) / ((double)i * i - (double)j * j);
+        }
+        d[j - 1] = prod / (2.0 * j);
+    }
+}
+
+/* Centred second derivative D^2 (section 2.3): f''(0) ~ [b_0 f(0) + sum_j b_j (f(jh)+f(-jh))]/h^2,
+ * j^2 b_j = prod_{i!=j} i^2/(i^2-j^2), and b_0 = -2 sum_j b_j (constants are annihilated). */
+void oracle_coef_centred_d2(int nd, double *b)
+{
+    double sum = 0.0;
+    for (int j = 1; j <= nd; ++j) {
+        double prod = 1.0;
+        for (int i = 1; i <= nd; ++i) {
+            if (i == j) continue;
+            prod *= ((double)i * i) / ((double)i * i - (double)j * j);
+        }
+        b[j] = prod / ((double)j * j);
+        sum += b[j];
+    }
+    b[0] = -2.0 * sum;
+}
+
+/* On-axis value of a staggered field that is constant (even) at rho = 0 (section 2.4, axis
+ * boundary values): Lagrange extrapolation in rho^2 through the nodes rho = k' drho, k'=1..nd:
+ * c_k' = prod_{i!=k'} i^2/(i^2-k'^2).  At nd = 5 this is 5/3, -20/21, 5/14, -5/63, 1/126. */
+void oracle_coef_axis(int nd, double *c)
+{
+    for (int k = 1; k <= nd; ++k) {
+        double prod = 1.0;
+        for (int i = 1; i <= nd; ++i) {
+            if (i == k) continue;
+            prod *= ((double)i * i) / ((double)i * i - (double)k * k);
+        }
+        c[k - 1] = prod;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Grid values with the boundary rules.                                                         */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Radial symmetry type of section 2.4: mS is S (even) for even m, A (odd) for odd m;
+ * mA is S for even |m-1|, A for odd |m-1|.  Returned as the sign of the extension. */
+static int parity_mS(int m) { return (m % 2 == 0) ? +1 : -1; }
+static int parity_mA(int m) { return (abs(m - 1) % 2 == 0) ? +1 : -1; }
+
+/* Primary radial grid rho_k = (k+1/2) drho.  A row q<0 is the mirror image of row -1-q (the point
+ * -rho_q'), multiplied by the extension sign; rows >= nr and z outside [0, nz) are ignored (0). */
+static cplx prim_val(const oracle_problem *P, const cplx *f, int parity, int q, int i)
+{
+    if (i < 0 || i >= P->nz) return 0.0;
+    if (q < 0) {
+        int mirror = -1 - q;
+        if (mirror >= P->nr) return 0.0;
+        return (double)parity * f[IDX(P, mirror, i)];
+    }
+    if (q >= P->nr) return 0.0;
+    return f[IDX(P, q, i)];
+}
+
+/* Staggered radial grid rho_(-),q = q drho.  Row 0 is the axis and takes the value 'axis'; a row
+ * q<0 mirrors row -q with the extension sign; rows >= nr and z outside [0, nz) are ignored. */
+static cplx stag_val(const oracle_problem *P, const cplx *f, int parity, cplx axis, int q, int i)
+{
+    if (i < 0 || i >= P->nz) return 0.0;
+    if (q == 0) return axis;
+    if (q < 0) {
+        int mirror = -q;
+        if (mirror >= P->nr) return 0.0;
+        return (double)parity * f[IDX(P, mirror, i)];
+    }
+    if (q >= P->nr) return 0.0;
+    return f[IDX(P, q, i)];
+}
+
+/* Axis value of a staggered plane at column i: sum_{k'=1..N_D} c_k' f_k' when the field is constant
+ * on the axis, else 0 (section 2.4). */
+static cplx axis_value(const oracle_problem *P, const double *c, int nd, const cplx *f, int i,
+                       int extrapolate)
+{
+    if (!extrapolate) return 0.0;
+    cplx s = 0.0;
+    for (int k = 1; k <= nd; ++k) {
+        if (k >= P->nr) break;
+        s += c[k - 1] * f[IDX(P, k, i)];
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Banded operators (section 2.2 product rule, section 2.3 definitions).                         */
+/* ------------------------------------------------------------------------------------------ */
+
+/* D_z^(-): primary z -> staggered z (output at z_i - dz/2). */
+static void op_dz_minus(const oracle_problem *P, const double *a, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += a[j - 1] * (prim_val(P, in, +1, k, i + j - 1) - prim_val(P, in, +1, k, i - j));
+            out[IDX(P, k, i)] = s / P->dz;
+        }
+}
+
+/* D_z^(+): staggered z -> primary z. */
+static void op_dz_plus(const oracle_problem *P, const double *a, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += a[j - 1] * (prim_val(P, in, +1, k, i + j) - prim_val(P, in, +1, k, i - j + 1));
+            out[IDX(P, k, i)] = s / P->dz;
+        }
+}
+
+/* D_rho^(-): primary rho -> staggered rho, evaluated on the evolved rows k >= 1; the axis row of the
+ * result is left 0 (it is not part of the system, section 2.5). */
+static void op_dr_minus(const oracle_problem *P, const double *a, int nd, int parity, const cplx *in,
+                        cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            if (k >= 1)
+                for (int j = 1; j <= nd; ++j)
+                    s += a[j - 1] * (prim_val(P, in, parity, k + j - 1, i) - prim_val(P, in, parity, k - j, i));
+            out[IDX(P, k, i)] = s / P->dr;
+        }
+}
+
+/* D_rho^(+): staggered rho -> primary rho; the axis value of the operand is placed into the operator
+ * (section 2.4). */
+static void op_dr_plus(const oracle_problem *P, const double *a, const double *c, int nd, int parity,
+                       int extrapolate, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx ax = axis_value(P, c, nd, in, i, extrapolate);
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += a[j - 1] * (stag_val(P, in, parity, ax, k + j, i) - stag_val(P, in, parity, ax, k - j + 1, i));
+            out[IDX(P, k, i)] = s / P->dr;
+        }
+}
+
+/* D_div^(-) = rho_(-)^-1 D^(-) (rho F): the operand rho*F lives on the primary grid and is extended
+ * with the parity given for the operator (section 2.3 staggered divergence).  Rows k >= 1. */
+static void op_div_minus(const oracle_problem *P, const double *a, int nd, int parity, const cplx *in,
+                         cplx *out)
+{
+    size_t n = (size_t)P->nr * P->nz;
+    cplx *g = malloc(n * sizeof(cplx));
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) g[IDX(P, k, i)] = (k + 0.5) * P->dr * in[IDX(P, k, i)];
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            if (k >= 1) {
+                for (int j = 1; j <= nd; ++j)
+                    s += a[j - 1] * (prim_val(P, g, parity, k + j - 1, i) - prim_val(P, g, parity, k - j, i));
+                s = s / P->dr / (k * P->dr);
+            }
+            out[IDX(P, k, i)] = s;
+        }
+    free(g);
+}
+
+/* D_div^(+) = rho^-1 D^(+) (rho_(-) F): operand rho_(-) F on the staggered grid, zero on the axis
+ * (its matrix elements at rho = 0 vanish, section 2.3). */
+static void op_div_plus(const oracle_problem *P, const double *a, int nd, int parity, const cplx *in,
+                        cplx *out)
+{
+    size_t n = (size_t)P->nr * P->nz;
+    cplx *g = malloc(n * sizeof(cplx));
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) g[IDX(P, k, i)] = (k * P->dr) * in[IDX(P, k, i)];
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += a[j - 1] * (stag_val(P, g, parity, 0.0, k + j, i) - stag_val(P, g, parity, 0.0, k - j + 1, i));
+            out[IDX(P, k, i)] = s / P->dr / ((k + 0.5) * P->dr);
+        }
+    free(g);
+}
+
+/* S_rho^(-): Lagrange shift primary rho -> staggered rho, rows k >= 1 (section 2.3). */
+static void op_shift_minus(const oracle_problem *P, const double *s_, int nd, int parity,
+                           const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            if (k >= 1)
+                for (int j = 1; j <= nd; ++j)
+                    s += s_[j - 1] * (prim_val(P, in, parity, k + j - 1, i) + prim_val(P, in, parity, k - j, i));
+            out[IDX(P, k, i)] = s;
+        }
+}
+
+/* Radial Laplacian L_rho = D^2 + rho^-1 D^(C) on the primary grid (section 2.3). */
+static void op_lap_rho(const oracle_problem *P, const double *b, const double *d, int nd, int parity,
+                       const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s2 = b[0] * prim_val(P, in, parity, k, i);
+            cplx s1 = 0.0;
+            for (int j = 1; j <= nd; ++j) {
+                s2 += b[j] * (prim_val(P, in, parity, k + j, i) + prim_val(P, in, parity, k - j, i));
+                s1 += d[j - 1] * (prim_val(P, in, parity, k + j, i) - prim_val(P, in, parity, k - j, i));
+            }
+            double rho = (k + 0.5) * P->dr;
+            out[IDX(P, k, i)] = s2 / (P->dr * P->dr) + (s1 / P->dr) / rho;
+        }
+}
+
+/* L_z = D_z^2 on the primary z grid. */
+static void op_lap_z(const oracle_problem *P, const double *b, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = b[0] * prim_val(P, in, +1, k, i);
+            for (int j = 1; j <= nd; ++j)
+                s += b[j] * (prim_val(P, in, +1, k, i + j) + prim_val(P, in, +1, k, i - j));
+            out[IDX(P, k, i)] = s / (P->dz * P->dz);
+        }
+}
+
+/* D_z^(C): centred first derivative in z. */
+static void op_dz_centred(const oracle_problem *P, const double *d, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += d[j - 1] * (prim_val(P, in, +1, k, i + j) - prim_val(P, in, +1, k, i - j));
+            out[IDX(P, k, i)] = s / P->dz;
+        }
+}
+
+static int check_problem(const oracle_problem *P)
+{
+    if (P->nz < 1 || P->nr < 1) return -1;
+    if (P->fd_order < 2 || P->fd_order > 32 || (P->fd_order % 2)) return -1;
+    if (P->nr < P->fd_order / 2 + 1) return -1;
+    if (P->m < 0) return -1;
+    return 0;
+}
+
+int oracle_apply_op(const oracle_problem *P, int op, int parity, int axis_extrapolate,
+                    const double complex *in, double complex *out)
+{
+    if (check_problem(P)) return -1;
+    int nd = P->fd_order / 2;
+    double a[16], s[16], d[16], b[17], c[16];
+    oracle_coef_staggered(nd, a);
+    oracle_coef_halfshift(nd, s);
+    oracle_coef_centred_d1(nd, d);
+    oracle_coef_centred_d2(nd, b);
+    oracle_coef_axis(nd, c);
+    switch (op) {
+    case 0: op_dz_minus(P, a, nd, in, out); break;
+    case 1: op_dz_plus(P, a, nd, in, out); break;
+    case 2: op_dr_minus(P, a, nd, parity, in, out); break;
+    case 3: op_dr_plus(P, a, c, nd, parity, axis_extrapolate, in, out); break;
+    case 4: op_div_minus(P, a, nd, parity, in, out); break;
+    case 5: op_div_plus(P, a, nd, parity, in, out); break;
+    case 6: op_shift_minus(P, s, nd, parity, in, out); break;
+    case 7: op_lap_rho(P, b, d, nd, parity, in, out); break;
+    case 8: op_lap_z(P, b, nd, in, out); break;
+    case 9: op_dz_centred(P, d, nd, in, out); break;
+    case 10:
+        memset(out, 0, (size_t)P->nr * P->nz * sizeof(cplx));
+        for (int i = 0; i < P->nz; ++i) out[IDX(P, 0, i)] = axis_value(P, c, nd, in, i, axis_extrapolate);
+        break;
+    default: return -1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Maxwell operator H_m (section 2.5) in complex modes: E_rho, B_theta, B_z on the staggered rho grid, */
+/* E_z, B_rho, B_theta on the staggered z grid (Table 1).  Only staggered rows k >= 1 are evolved.     */
+/* ------------------------------------------------------------------------------------------ */
+
+int oracle_apply_H(const oracle_problem *P, const double complex *v, double complex *out)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2, m = P->m;
+    const size_t n = (size_t)P->nr * P->nz;
+    double a[16], c[16];
+    oracle_coef_staggered(nd, a);
+    oracle_coef_axis(nd, c);
+    const int pS = parity_mS(m);
+    const cplx *Er = v + ER * n, *Eth = v + ETH * n, *Ez = v + EZ * n;
+    const cplx *Br = v + BR * n, *Bth = v + BTH * n, *Bz = v + BZ * n;
+    cplx *t = malloc(n * sizeof(cplx));
+    cplx *o;
+
+    /* dE_rho = -D_z^(+) B_theta + (i m / rho_(-)) B_z            (rows k >= 1) */
+    o = out + ER * n;
+    op_dz_plus(P, a, nd, Bth, t);
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i)
+            o[IDX(P, k, i)] = (k == 0) ? 0.0 : -t[IDX(P, k, i)] + (I * m / (k * P->dr)) * Bz[IDX(P, k, i)];
+
+    /* dE_theta = D_z^(+) B_rho - D_rho^(+,mS) B_z   (B_z axis value extrapolated iff m = 0) */
+    o = out + ETH * n;
+    op_dz_plus(P, a, nd, Br, o);
+    op_dr_plus(P, a, c, nd, pS, m == 0, Bz, t);
+    for (size_t q = 0; q < n; ++q) o[q] -= t[q];
+
+    /* dE_z = -(i m / rho) B_rho + D_div^(+,mS) B_theta */
+    o = out + EZ * n;
+    op_div_plus(P, a, nd, pS, Bth, o);
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i)
+            o[IDX(P, k, i)] += -(I * m / ((k + 0.5) * P->dr)) * Br[IDX(P, k, i)];
+
+    /* dB_rho = D_z^(-) E_theta - (i m / rho) E_z */
+    o = out + BR * n;
+    op_dz_minus(P, a, nd, Eth, o);
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i)
+            o[IDX(P, k, i)] += -(I * m / ((k + 0.5) * P->dr)) * Ez[IDX(P, k, i)];
+
+    /* dB_theta = -D_z^(-) E_rho + D_rho^(-,mS) E_z                (rows k >= 1) */
+    o = out + BTH * n;
+    op_dz_minus(P, a, nd, Er, t);
+    op_dr_minus(P, a, nd, pS, Ez, o);
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i)
+            o[IDX(P, k, i)] = (k == 0) ? 0.0 : o[IDX(P, k, i)] - t[IDX(P, k, i)];
+
+    /* dB_z = (i m / rho_(-)) E_rho - D_div^(-,mS) E_theta         (rows k >= 1) */
+    o = out + BZ * n;
+    op_div_minus(P, a, nd, pS, Eth, o);
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i)
+            o[IDX(P, k, i)] = (k == 0) ? 0.0 : (I * m / (k * P->dr)) * Er[IDX(P, k, i)] - o[IDX(P, k, i)];
+
+    free(t);
+    /* the rho = 0 slots of the result follow the boundary rule */
+    return oracle_set_axis(P, out);
+}
+
+int oracle_set_axis(const oracle_problem *P, double complex *psi)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2, m = P->m;
+    const size_t n = (size_t)P->nr * P->nz;
+    double c[16];
+    oracle_coef_axis(nd, c);
+    /* E_rho and B_theta are polar-like (mA): constant on the axis only for m = 1.
+     * B_z is scalar-like (mS): constant on the axis only for m = 0.  Otherwise zero. */
+    for (int i = 0; i < P->nz; ++i) {
+        cplx er = axis_value(P, c, nd, psi + ER * n, i, m == 1);
+        cplx bt = axis_value(P, c, nd, psi + BTH * n, i, m == 1);
+        cplx bz = axis_value(P, c, nd, psi + BZ * n, i, m == 0);
+        psi[ER * n + IDX(P, 0, i)] = er;
+        psi[BTH * n + IDX(P, 0, i)] = bt;
+        psi[BZ * n + IDX(P, 0, i)] = bz;
+    }
+    return 0;
+}
+
+/* Jbar_rho = S_rho^(-,mA) J_rho, Jbar_theta = J_theta, Jbar_z = J_z (section 2.5 current
+ * pre-processing with the z filters taken as the identity). */
+int oracle_stage_current(const oracle_problem *P, const double complex *j, double complex *jbar)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2;
+    const size_t n = (size_t)P->nr * P->nz;
+    double s[16];
+    oracle_coef_halfshift(nd, s);
+    op_shift_minus(P, s, nd, parity_mA(P->m), j, jbar);
+    memcpy(jbar + n, j + n, 2 * n * sizeof(cplx));
+    return 0;
+}
+
+/* One or more midpoint exponential steps (section 2.1 midpoint solution, Taylor sums of
+ * section 2.5):  psi' = sum_n (dt^n/n!) H^n psi  -  dt * sum_n ((dt/2)^n/n!) H^n Jbar. */
+int oracle_step(const oracle_problem *P, double complex *psi, const double complex *j,
+                int64_t j_stride, int n_steps)
+{
+    if (check_problem(P) || P->taylor_order < 1 || n_steps < 0) return -1;
+    const size_t n = (size_t)P->nr * P->nz, n6 = 6 * n;
+    const int N = P->taylor_order;
+    const double dt = P->dt;
+    cplx *term = malloc(n6 * sizeof(cplx));
+    cplx *next = malloc(n6 * sizeof(cplx));
+    cplx *sum = malloc(n6 * sizeof(cplx));
+    cplx *usum = malloc(n6 * sizeof(cplx));
+    for (int step = 0; step < n_steps; ++step) {
+        /* source-free series  S = sum_n t_n,  t_0 = psi,  t_n = (dt/n) H t_{n-1} */
+        memcpy(term, psi, n6 * sizeof(cplx));
+        memcpy(sum, psi, n6 * sizeof(cplx));
+        for (int k = 1; k <= N; ++k) {
+            oracle_apply_H(P, term, next);
+            for (size_t q = 0; q < n6; ++q) {
+                term[q] = (dt / k) * next[q];
+                sum[q] += term[q];
+            }
+        }
+        if (j) {
+            /* source series  U = sum_n u_n,  u_0 = (Jbar, 0),  u_n = (dt/(2n)) H u_{n-1} */
+            const cplx *js = j + (size_t)(j_stride * step);
+            memset(term, 0, n6 * sizeof(cplx));
+            oracle_stage_current(P, js, term);
+            memcpy(usum, term, n6 * sizeof(cplx));
+            for (int k = 1; k <= N; ++k) {
+                oracle_apply_H(P, term, next);
+                for (size_t q = 0; q < n6; ++q) {
+                    term[q] = (dt / (2.0 * k)) * next[q];
+                    usum[q] += term[q];
+                }
+            }
+            for (size_t q = 0; q < n6; ++q) sum[q] -= dt * usum[q];
+        }
+        memcpy(psi, sum, n6 * sizeof(cplx));
+        oracle_set_axis(P, psi);
+    }
+    free(term);
+    free(next);
+    free(sum);
+    free(usum);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Laser envelope (section 4): d/dt a = a~, d/dt a~ = (L_rho + L_z - m^2/rho^2 - chi) a             */
+/*                                        + 2 i k0 D_z^(C) a + 2 i k0 a~                          */
+/* (the complex envelope equation of section 4.1; a is scalar-like, radial symmetry mS).            */
+/* ------------------------------------------------------------------------------------------ */
+
+int oracle_apply_Ha(const oracle_problem *P, const double complex *a, const double complex *at,
+                    const double *chi, double complex *out_a, double complex *out_at)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2, m = P->m;
+    const size_t n = (size_t)P->nr * P->nz;
+    double b[17], d[16];
+    oracle_coef_centred_d2(nd, b);
+    oracle_coef_centred_d1(nd, d);
+    cplx *lr = malloc(n * sizeof(cplx)), *lz = malloc(n * sizeof(cplx)), *dz = malloc(n * sizeof(cplx));
+    op_lap_rho(P, b, d, nd, parity_mS(m), a, lr);
+    op_lap_z(P, b, nd, a, lz);
+    op_dz_centred(P, d, nd, a, dz);
+    for (int k = 0; k < P->nr; ++k) {
+        double rho = (k + 0.5) * P->dr;
+        for (int i = 0; i < P->nz; ++i) {
+            size_t q = IDX(P, k, i);
+            out_a[q] = at[q];
+            out_at[q] = lr[q] + lz[q] - ((double)m * m / (rho * rho)) * a[q] - chi[q] * a[q]
+                        + 2.0 * I * P->k0 * dz[q] + 2.0 * I * P->k0 * at[q];
+        }
+    }
+    free(lr);
+    free(lz);
+    free(dz);
+    return 0;
+}
+
+/* psi_a' = sum_{n=0..N} (dt^n/n!) H_a^n psi_a with chi held at its mid-step value (section 4.1). */
+int oracle_envelope_step(const oracle_problem *P, double complex *a, double complex *at,
+                         const double *chi, int n_steps)
+{
+    if (check_problem(P) || P->taylor_order < 1 || n_steps < 0) return -1;
+    const size_t n = (size_t)P->nr * P->nz;
+    const int N = P->taylor_order;
+    cplx *ta = malloc(n * sizeof(cplx)), *tt = malloc(n * sizeof(cplx));
+    cplx *na = malloc(n * sizeof(cplx)), *nt = malloc(n * sizeof(cplx));
+    cplx *sa = malloc(n * sizeof(cplx)), *st = malloc(n * sizeof(cplx));
+    for (int step = 0; step < n_steps; ++step) {
+        memcpy(ta, a, n * sizeof(cplx));
+        memcpy(tt, at, n * sizeof(cplx));
+        memcpy(sa, a, n * sizeof(cplx));
+        memcpy(st, at, n * sizeof(cplx));
+        for (int k = 1; k <= N; ++k) {
+            oracle_apply_Ha(P, ta, tt, chi, na, nt);
+            for (size_t q = 0; q < n; ++q) {
+                ta[q] = (P->dt / k) * na[q];
+                tt[q] = (P->dt / k) * nt[q];
+                sa[q] += ta[q];
+                st[q] += tt[q];
+            }
+        }
+        memcpy(a, sa, n * sizeof(cplx));
+        memcpy(at, st, n * sizeof(cplx));
+    }
+    free(ta); free(tt); free(na); free(nt); free(sa); free(st);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Diagnostics (section 5.1): energy integral of |E|^2 + |B|^2 over the volume and its z-centroid.  */
+/* The theta integral of a complex mode gives 2 pi |F|^2 for m = 0 and pi |F|^2 for m >= 1.          */
+/* ------------------------------------------------------------------------------------------ */
+
+void oracle_energy(const oracle_problem *P, const double complex *psi, double *energy, double *zc)
+{
+    const size_t n = (size_t)P->nr * P->nz;
+    const double w = (P->m == 0) ? 2.0 * M_PI : M_PI;
+    /* staggering per component (Table 1): rho-staggered and z-staggered flags */
+    static const int rst[6] = {1, 0, 0, 0, 1, 1};
+    static const int zst[6] = {0, 0, 1, 1, 1, 0};
+    double W = 0.0, Wz = 0.0;
+    for (int f = 0; f < 6; ++f)
+        for (int k = 0; k < P->nr; ++k) {
+            double r = rst[f] ? k * P->dr : (k + 0.5) * P->dr;
+            for (int i = 0; i < P->nz; ++i) {
+                double z = zst[f] ? (i - 0.5) * P->dz : i * P->dz;
+                cplx F = psi[f * n + IDX(P, k, i)];
+                double e = w * r * P->dr * P->dz * (creal(F) * creal(F) + cimag(F) * cimag(F));
+                W += e;
+                Wz += z * e;
+            }
+        }
+    *energy = W;
+    *zc = (W > 0.0) ? Wz / W : 0.0;
+}
+
+void oracle_envelope_energy(const oracle_problem *P, const double complex *a,
+                            const double complex *at, double *energy, double *zc)
+{
+    const double w = (P->m == 0) ? 2.0 * M_PI : M_PI;
+    double W = 0.0, Wz = 0.0;
+    for (int k = 0; k < P->nr; ++k) {
+        double r = (k + 0.5) * P->dr;
+        for (int i = 0; i < P->nz; ++i) {
+            cplx e = at[IDX(P, k, i)] - I * P->k0 * a[IDX(P, k, i)];
+            double v = w * r * P->dr * P->dz * (creal(e) * creal(e) + cimag(e) * cimag(e));
+            W += v;
+            Wz += i * P->dz * v;
+        }
+    }
+    *energy = W;
+    *zc = (W > 0.0) ? Wz / W : 0.0;
+}

@@ -1,0 +1,265 @@
+"""Pins of the oracle's Maxwell operator H_m and of its midpoint exponential step.
+
+* Bessel modes: TM / TE waves exp(i(kz + m theta - w t)) J_m(g rho) are exact solutions of the continuous
+  modal Maxwell equations (section 2.1).  Sampled on the Yee grid (Table 1), the discrete H_m of section 2.5
+  must reproduce d/dt = -i w on every row, the near-axis rows included, with an error that falls as
+  (grid step)^(2 N_D).  This pins every term, sign, parity and grid offset of H_m.
+* The real half-system printed in section 2.5 (y-symmetric pair) is reproduced by the complex-mode form.
+* m = 1 transverse plane waves are exact discrete eigenvectors; after K steps the interior equals the
+  closed-form amplification T_N(-i kappa dt)^K (numerical dispersion of the staggered stencil).
+* On tiny grids the step equals the dense matrix exponential within the Taylor remainder bound, and the
+  midpoint source term matches the exact (Van Loan) integral up to the known O(dt^3) quadrature error.
+* The stored rho = 0 slots are never read; the source-free step conserves the field energy.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+from scipy.special import jv, jvp
+
+import oracle
+
+ER, ETH, EZ, BR, BTH, BZ = range(6)
+
+
+def positions(g):
+    """(rho, z) sampling points of the six components (Table 1 staggering)."""
+    rp = (np.arange(g.nr) + 0.5) * g.dr
+    rs = np.arange(g.nr) * g.dr
+    zp = np.arange(g.nz) * g.dz
+    zs = (np.arange(g.nz) - 0.5) * g.dz
+    return {ER: (rs, zp), ETH: (rp, zp), EZ: (rp, zs), BR: (rp, zs), BTH: (rs, zs), BZ: (rs, zp)}
+
+
+def bessel_mode(g, kind, kz, gam):
+    """Fields of a TM (E_z = J_m) or TE (B_z = J_m) mode at each component's grid points."""
+    m = g.m
+    w = math.sqrt(kz * kz + gam * gam)
+    pos = positions(g)
+    psi = np.zeros((6, g.nr, g.nz), complex)
+    for c in range(6):
+        r, z = pos[c]
+        R, Z = np.meshgrid(r, z, indexing="ij")
+        x = gam * R
+        Jm = jv(m, x)
+        Jp = jvp(m, x)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Jr = np.where(R > 0, Jm / np.where(R > 0, R, 1), 0.0)
+        ph = np.exp(1j * kz * Z)
+        if kind == "TM":
+            f = {ER: 1j * kz / gam * Jp, ETH: -kz * m / gam ** 2 * Jr, EZ: Jm,
+                 BR: w * m / gam ** 2 * Jr, BTH: 1j * w / gam * Jp, BZ: 0 * Jm}[c]
+        else:
+            f = {BR: 1j * kz / gam * Jp, BTH: -kz * m / gam ** 2 * Jr, BZ: Jm,
+                 ER: -w * m / gam ** 2 * Jr, ETH: -1j * w / gam * Jp, EZ: 0 * Jm}[c]
+        psi[c] = f * ph
+    return psi, w
+
+
+def bessel_residual(kind, m, order, scale, near_axis):
+    """Max |H psi - (-i w) psi| over the rows next to the axis (index <= N_D, the rows whose stencils
+    reach the mirrored ghosts or the axis value) or over rows at rho >= 1.5 (fixed physical interior)."""
+    nd = order // 2
+    nr, nz = int(24 * scale) + nd, int(24 * scale) + 2 * nd
+    g = oracle.Grid(nz=nz, nr=nr, m=m, fd_order=order, taylor_order=1, dz=0.25 / scale, dr=0.3 / scale,
+                    dt=0.0)
+    psi, w = bessel_mode(g, kind, kz=1.1, gam=1.3)
+    h = oracle.apply_H(g, psi)
+    want = -1j * w * psi
+    cols = slice(nd, nz - nd)
+    idx = np.arange(nr)
+    err = 0.0
+    for c in range(6):
+        r0 = 1 if c in (ER, BTH, BZ) else 0          # staggered axis row is derived, not evolved
+        if near_axis:
+            rows = idx[r0:nd + 1]
+        else:
+            rows = idx[(idx * g.dr >= 1.5) & (idx < nr - nd)]
+        d = h[c][rows][:, cols] - want[c][rows][:, cols]
+        err = max(err, np.max(np.abs(d)))
+    return err
+
+
+@pytest.mark.parametrize("kind", ["TM", "TE"])
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_bessel_modes_converge_at_design_order(kind, m, order):
+    # interior: order 2N_D.  Next to the axis the 1/rho factors (rho ~ drho) and the axis
+    # extrapolation (exact to degree 2N_D - 2, then differenced) cost one order: 2N_D - 1.
+    e1 = bessel_residual(kind, m, order, 2, False)
+    e2 = bessel_residual(kind, m, order, 4, False)
+    assert math.log2(e1 / e2) > order - 0.2, (e1, e2)
+    e1 = bessel_residual(kind, m, order, 2, True)
+    e2 = bessel_residual(kind, m, order, 4, True)
+    assert math.log2(e1 / e2) > order - 1.1, (e1, e2)
+
+
+@pytest.mark.parametrize("kind", ["TM", "TE"])
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+def test_bessel_modes_high_order_small_residual(kind, m):
+    assert bessel_residual(kind, m, 16, 2, False) < 1e-9
+    assert bessel_residual(kind, m, 16, 2, True) < 1e-8
+
+
+def test_real_half_system_of_section_2_5():
+    """The complex form reproduces the printed real equations for both y- and x-symmetric halves."""
+    rng = np.random.default_rng(5)
+    for m in (0, 1, 2, 3):
+        g = oracle.Grid(nz=14, nr=9, m=m, fd_order=6, taylor_order=1, dz=0.3, dr=0.5, dt=0.0)
+        pS = 1 if m % 2 == 0 else -1
+        rp = ((np.arange(g.nr) + 0.5) * g.dr)[:, None]
+        rs = (np.arange(g.nr) * g.dr)[:, None]
+        rs_inv = np.where(rs > 0, 1 / np.where(rs > 0, rs, 1), 0.0)
+        op = lambda o, f, par=1, ax=False: oracle.apply_op(g, o, f.astype(complex), par, ax).real
+        for half, sm in (("y", m), ("x", -m)):
+            # real coefficients: E_rho, E_z, B_theta of one parity; E_theta, B_rho, B_z of the other
+            er, ez, bt = (rng.standard_normal((g.nr, g.nz)) for _ in range(3))
+            et, br, bz = (rng.standard_normal((g.nr, g.nz)) for _ in range(3))
+            for f in (er, bt, bz):
+                f[0] = 0.0
+            # y-symmetric: (E_rho,2m, E_theta,2m+1, ...) -> complex: real part / i * imag part
+            u = 1.0 if half == "y" else 1j
+            v = 1j if half == "y" else 1.0
+            psi = np.stack([u * er, v * et, u * ez, v * br, u * bt, v * bz])
+            h = oracle.apply_H(g, psi)
+            # equations of section 2.5 with the sign of m flipped for the other half
+            d_er = -op(oracle.OP_DZ_PLUS, bt) - sm * rs_inv * bz
+            d_et = op(oracle.OP_DZ_PLUS, br) - op(oracle.OP_DR_PLUS, bz, pS, m == 0)
+            d_ez = sm / rp * br + op(oracle.OP_DIV_PLUS, bt, pS)
+            d_br = op(oracle.OP_DZ_MINUS, et) - sm / rp * ez
+            d_bt = -op(oracle.OP_DZ_MINUS, er) + op(oracle.OP_DR_MINUS, ez, pS)
+            d_bz = sm * rs_inv * er - op(oracle.OP_DIV_MINUS, et, pS)
+            want = [d_er, d_et, d_ez, d_br, d_bt, d_bz]
+            phase = [u, v, u, v, u, v]
+            for c in range(6):
+                r0 = 1 if c in (ER, BTH, BZ) else 0
+                got = h[c, r0:] / phase[c]
+                assert np.max(np.abs(got.imag)) < 1e-12
+                assert np.allclose(got.real, want[c][r0:], rtol=1e-12, atol=1e-12), (m, half, c)
+
+
+def taylor(x, N):
+    return sum(x ** n / math.factorial(n) for n in range(N + 1))
+
+
+@pytest.mark.parametrize("order,N,K", [(8, 4, 3), (16, 8, 2), (4, 12, 2)])
+def test_plane_wave_closed_form_dispersion(order, N, K):
+    nd = order // 2
+    reach = K * N * nd
+    nz, nr = 2 * reach + 40, reach + 12
+    g = oracle.Grid(nz=nz, nr=nr, m=1, fd_order=order, taylor_order=N, dz=0.2, dr=0.35, dt=0.1)
+    a = oracle.coef("staggered", nd)
+    kz = 2 * np.pi / (12 * g.dz)
+    kappa = 2 / g.dz * sum(a[j] * np.sin((2 * j + 1) * kz * g.dz / 2) for j in range(nd))
+    pos = positions(g)
+    psi = np.zeros((6, nr, nz), complex)
+    E = np.exp(1j * kz * pos[ER][1])[None, :].repeat(nr, 0)
+    B = np.exp(1j * kz * pos[BTH][1])[None, :].repeat(nr, 0)
+    psi[ER], psi[ETH], psi[BTH], psi[BR] = E, 1j * E, B, -1j * B
+    out = oracle.step(g, psi, None, K)
+    amp = taylor(-1j * kappa * g.dt, N) ** K
+    cols = slice(reach + 1, nz - reach - 1)
+    rows = slice(0, nr - reach - 1)
+    for c in range(6):
+        r0 = 1 if c in (ER, BTH, BZ) else 0
+        d = out[c, r0:rows.stop, cols] - amp * psi[c, r0:rows.stop, cols]
+        assert np.max(np.abs(d)) < 1e-12, (c, np.max(np.abs(d)))
+
+
+def dense_H(g):
+    n = 6 * g.nr * g.nz
+    H = np.zeros((n, n), complex)
+    e = np.zeros(n, complex)
+    for q in range(n):
+        e[q] = 1.0
+        H[:, q] = oracle.apply_H(g, e.reshape(6, g.nr, g.nz)).ravel()
+        e[q] = 0.0
+    return H
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_step_equals_dense_expm_within_taylor_bound(m):
+    g = oracle.Grid(nz=10, nr=5, m=m, fd_order=4, taylor_order=8, dz=0.4, dr=0.7, dt=0.1)
+    H = dense_H(g)
+    rng = np.random.default_rng(11 + m)
+    psi = oracle.set_axis(g, rng.standard_normal((6, 5, 10)) + 1j * rng.standard_normal((6, 5, 10)))
+    nrm = np.linalg.norm(H, 2)
+    for dt, N in ((0.1, 8), (0.02, 12), (0.3, 4)):
+        g.dt, g.taylor_order = dt, N
+        got = oracle.step(g, psi, None, 1).ravel()
+        want = scipy.linalg.expm(dt * H) @ psi.ravel()
+        bound = sum((dt * nrm) ** n / math.factorial(n) for n in range(N + 1, N + 40)) * np.linalg.norm(psi)
+        err = np.linalg.norm(got - want)
+        assert err <= bound + 1e-13 * np.linalg.norm(psi), (dt, N, err, bound)
+
+
+@pytest.mark.parametrize("m", [0, 1])
+def test_midpoint_source_matches_van_loan_integral(m):
+    """exp(dt H) psi - integral_0^dt exp((dt-s)H) Jbar ds, exact for constant Jbar, via the augmented
+    matrix [[H, -Jbar], [0, 0]]; the midpoint rule differs by dt (dt H)^2 Jbar / 24 + O(dt^4)."""
+    g = oracle.Grid(nz=10, nr=5, m=m, fd_order=4, taylor_order=12, dz=0.4, dr=0.7, dt=0.1)
+    H = dense_H(g)
+    n = H.shape[0]
+    rng = np.random.default_rng(3)
+    psi = oracle.set_axis(g, rng.standard_normal((6, 5, 10)) + 1j * rng.standard_normal((6, 5, 10)))
+    J = np.zeros((3, 5, 10), complex)
+    J[1:] = rng.standard_normal((2, 5, 10)) + 1j * rng.standard_normal((2, 5, 10))  # J_rho = 0: Jbar = J
+    jb = np.zeros((6, 5, 10), complex)
+    jb[:3] = J
+    jb = jb.ravel()
+    ratios = []
+    for dt in (0.08, 0.04, 0.02):
+        g.dt = dt
+        got = oracle.step(g, psi, J, 1).ravel()
+        M = np.zeros((n + 1, n + 1), complex)
+        M[:n, :n] = H
+        M[:n, n] = -jb
+        exact = (scipy.linalg.expm(dt * M) @ np.concatenate([psi.ravel(), [1.0]]))[:n]
+        lead = dt * (dt ** 2) * (H @ (H @ jb)) / 24
+        ratios.append(np.linalg.norm(got - exact - lead) / np.linalg.norm(lead))
+    # the remainder after the leading O(dt^3) term is O(dt^4): the ratio halves with dt
+    assert ratios[-1] < 0.1 and ratios[0] / ratios[1] > 1.8 and ratios[1] / ratios[2] > 1.8, ratios
+
+
+def test_axis_slots_are_never_read():
+    rng = np.random.default_rng(8)
+    for m in (0, 1, 2):
+        g = oracle.Grid(nz=20, nr=10, m=m, fd_order=8, taylor_order=6, dz=0.3, dr=0.5, dt=0.12)
+        psi = rng.standard_normal((6, 10, 20)) + 1j * rng.standard_normal((6, 10, 20))
+        J = rng.standard_normal((3, 10, 20)) + 1j * rng.standard_normal((3, 10, 20))
+        a = oracle.step(g, psi, J, 2)
+        psi2 = psi.copy()
+        for c in (ER, BTH, BZ):
+            psi2[c, 0] = rng.standard_normal(20) * 1e3
+        b = oracle.step(g, psi2, J, 2)
+        assert np.array_equal(a, b)
+        # and the output slots follow the boundary rule of section 2.4
+        assert np.array_equal(a, oracle.set_axis(g, a))
+        c = oracle.coef("axis", 4)
+        if m == 0:
+            assert np.allclose(a[BZ, 0], c @ a[BZ, 1:5]) and np.all(a[ER, 0] == 0)
+        elif m == 1:
+            assert np.allclose(a[ER, 0], c @ a[ER, 1:5]) and np.all(a[BZ, 0] == 0)
+        else:
+            assert np.all(a[[ER, BTH, BZ], 0] == 0)
+
+
+def test_source_free_step_conserves_energy_away_from_axis():
+    # a smooth pulse far from the axis, the outer edge and the z ends: the interior operator is
+    # skew-adjoint in the rho-weighted norm, so |T_N(i x)| <= 1 bounds the energy change.
+    g = oracle.Grid(nz=160, nr=64, m=1, fd_order=8, taylor_order=8, dz=0.3, dr=0.6, dt=0.15)
+    pos = positions(g)
+    psi = np.zeros((6, g.nr, g.nz), complex)
+    k = 2 * np.pi / (10 * g.dz)
+    for c, amp in ((ER, 1.0), (ETH, 1j), (BTH, 1.0), (BR, -1j)):
+        r, z = pos[c]
+        R, Z = np.meshgrid(r, z, indexing="ij")
+        psi[c] = amp * np.exp(-((R - 19.0) / 4.0) ** 2 - ((Z - 24.0) / 4.0) ** 2 + 1j * k * Z)
+    w0, _ = oracle.energy(g, psi)
+    out = oracle.step(g, psi, None, 20)
+    w1, _ = oracle.energy(g, out)
+    x = 2.6 * math.sqrt(1 / g.dz ** 2 + 1 / g.dr ** 2) * g.dt   # upper bound of dt * |lambda|
+    loss = 1 - abs(taylor(1j * x, 8)) ** 2
+    assert w1 <= w0 * (1 + 1e-12)
+    assert w1 >= w0 * (1 - 20 * loss - 1e-12), (w0, w1)
