@@ -1,0 +1,243 @@
+"""Benchmark: field cell-updates/s of the FDETD step on the current-driven workload (modes m = 0, 1 on a
+2048 x 256 grid, 16th-order staggered differences, Taylor order 8, dt = dz/2, Gaussian bunch + noise
+current, 500 steps), FP64 and FP32-compensated, on one MI355X.
+
+Prints ONE JSON line.  `value` is the FP64 rate (cells x modes x steps / s) over exactly --steps steps,
+with every input (fields, the per-step currents of all steps) resident in HBM before the timed region,
+replayed from a captured hipGraph.  Also reported:
+  roofline     achieved algorithmic HBM bytes / stage-kernel time of the dominant kernel (Maxwell Horner
+               stage), from HIP events around every stage launch in a profiled pass of the same workload;
+  fp32c        the same measurement for the FP32-compensated path, with its error against the FP64 path;
+  cpu_baseline the CPU FP64 oracle timed on a bounded sample (one mode, a few steps) on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "field cell-updates/s (cells×modes×steps/s), FP64 vs FP32-comp at fixed error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_currents(w, steps, dtype, seed):
+    """Per-step currents [steps, 3, nr, nz] of every problem, generated on the GPU (seeded): the Gaussian
+    bunch moving at c on the axis (J_z of mode 0) plus uniform white noise of relative amplitude 1e-3
+    (mode 0: real part only) -- the recipe of inputs.bunch_current, drawn with torch's device RNG."""
+    import torch
+    e = w.extra
+    out = []
+    g = torch.Generator(device="cuda")
+    for p in range(w.n):
+        g.manual_seed(seed * 1000 + p)
+        nz, nr, m = w.nz[p], w.nr[p], w.m[p]
+        rdt = torch.float64
+        shape = (steps, 3, nr, nz)
+        amp = e["noise"] * e["nb"]
+        re = (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
+        im = torch.zeros_like(re) if m == 0 else (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
+        if m == 0:
+            t = (torch.arange(steps, device="cuda", dtype=rdt) + 0.5) * w.dt
+            rp = (torch.arange(nr, device="cuda", dtype=rdt) + 0.5) * w.dr
+            zs = (torch.arange(nz, device="cuda", dtype=rdt) - 0.5) * w.dz
+            zb = 0.25 * nz * w.dz + t
+            bunch = -e["nb"] * torch.exp(-((zs[None, None, :] - zb[:, None, None]) ** 2) / (2 * e["sigz"] ** 2)
+                                         - rp[None, :, None] ** 2 / (2 * e["sigr"] ** 2))
+            re[:, 2] += bunch
+        out.append(torch.complex(re, im).to(dtype).contiguous())
+        del re, im
+    return out
+
+
+def energy_weights(w, p):
+    """Volume weights w_m r dr dz of the six components (rho-staggered rows at k dr)."""
+    rp = (np.arange(w.nr[p]) + 0.5) * w.dr
+    rs = np.arange(w.nr[p]) * w.dr
+    wm = 2 * math.pi if w.m[p] == 0 else math.pi
+    r = np.stack([rs, rp, rp, rp, rs, rs])
+    return wm * r * w.dr * w.dz  # [6, nr]
+
+
+def run_path(w, precision, steps, warmup, J, use_graph=True):
+    """Warm up, capture the K-step graph once (untimed, then restore the state), time exactly K steps."""
+    import torch
+    import paper_2605_12132_amd as F
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+        flags = F.PLAN_USE_GRAPH if use_graph else 0
+        t0 = time.time()
+        plan = F.Plan(w.problems(), precision=precision, flags=flags)
+        plan_s = time.time() - t0
+        if warmup:
+            plan.step(psi, [j[:warmup] for j in J], n_steps=warmup)
+        jt = [j[warmup:warmup + steps] for j in J]
+        saved = [x.clone() for x in psi]
+        lo = plan.export_state() if precision == F.FP32C else b""
+        # capture + one untimed replay of the exact timed call, then restore the state it started from
+        plan.step(psi, jt, n_steps=steps)
+        for x, s in zip(psi, saved):
+            x.copy_(s)
+        if precision == F.FP32C:
+            stream.synchronize()
+            plan.import_state(lo)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        plan.step(psi, jt, n_steps=steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        info = plan.query()
+        plan.close()
+    return psi, ms, plan_s, info
+
+
+def profile_pass(w, precision, steps, J):
+    """Eager pass with HIP events around every stage kernel: average duration and algorithmic bytes."""
+    import torch
+    import paper_2605_12132_amd as F
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
+    plan.step(psi, [j[:steps] for j in J], n_steps=steps)
+    info = plan.query()
+    plan.close()
+    n = info["profiled_launches"]
+    avg_ms = info["profiled_ms"] / n
+    bytes_per_launch = info["profiled_bytes"] / n
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_maxwell_stage",
+                launches=n, avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch))
+
+
+def fp32c_errors(w, psi64, psi32):
+    num = den = e64 = e32 = 0.0
+    ax = []
+    for p in range(w.n):
+        a = psi64[p].cpu().numpy()
+        b = psi32[p].cpu().numpy().astype(np.complex128)
+        wt = energy_weights(w, p)[:, :, None]
+        num += float(np.sum(wt * np.abs(a - b) ** 2))
+        den += float(np.sum(wt * np.abs(a) ** 2))
+        e64 += float(np.sum(wt * np.abs(a) ** 2))
+        e32 += float(np.sum(wt * np.abs(b) ** 2))
+        # on-axis amplitude: E_rho on the axis for m = 1, E_z next to the axis otherwise
+        c = 0 if w.m[p] == 1 else 2
+        ref = np.max(np.abs(a[c, 0]))
+        ax.append(float(np.max(np.abs(a[c, 0] - b[c, 0])) / ref) if ref > 0 else 0.0)
+    return dict(field_rel_l2=math.sqrt(num / den), energy_rel_diff=abs(e32 / e64 - 1), axis_amp_rel_err=max(ax))
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle (plain C, OpenMP over rows) on one mode of the workload with its current, for as many
+    steps as fit in the time budget (at least one)."""
+    import oracle
+    import paper_2605_12132_amd.inputs as I
+    p = 1
+    g = oracle.Grid(nz=w.nz[p], nr=w.nr[p], m=w.m[p], fd_order=w.fd_order[p], taylor_order=w.taylor_order,
+                    dz=w.dz, dr=w.dr, dt=w.dt)
+    psi = np.zeros((6, w.nr[p], w.nz[p]), np.complex128)
+    J = I.currents(w, p, 8)
+    steps, t_total = 0, 0.0
+    while steps < 8 and (steps == 0 or t_total + t_total / steps < budget_s):
+        t0 = time.time()
+        psi = oracle.step(g, psi, J[steps], 1)
+        t_total += time.time() - t0
+        steps += 1
+    cells = w.nz[p] * w.nr[p]
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return dict(value=cells * steps / t_total, unit="cell-updates/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{steps} step(s) of mode m={w.m[p]} ({w.nz[p]}x{w.nr[p]}, order {w.fd_order[p]}, Taylor "
+                       f"{w.taylor_order}, with current) in {t_total:.1f} s; host reports {ncpu} usable cores")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the problems of this workload are "
+              "independent modes and would be distributed one plan per GPU with no communication.", flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+
+    w = I.current_driven()
+    K, W = args.steps, args.warmup
+    cells = w.cells()
+    log(f"workload {w.name}: {w.n} modes x {w.nz[0]}x{w.nr[0]}, order {w.fd_order[0]}, N={w.taylor_order}, "
+        f"K={K}, W={W}")
+    t0 = time.time()
+    J64 = make_currents(w, W + K, torch.complex128, w.seed)
+    torch.cuda.synchronize()
+    log(f"currents resident: {sum(j.numel() for j in J64) * 16 / 1e9:.1f} GB in {time.time() - t0:.1f} s")
+
+    psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph)
+    rate64 = cells * K / (ms64 * 1e-3)
+    log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s (plan {plan_s:.2f} s, dt*rho {info64['dt_rho_max']:.3f})")
+    roof64 = profile_pass(w, F.FP64, args.profile_steps, J64)
+    log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
+
+    fp32c = None
+    if not args.fp64_only:
+        J32 = [j.to(torch.complex64) for j in J64]
+        del J64
+        torch.cuda.empty_cache()
+        psi32, ms32, _, _ = run_path(w, F.FP32C, K, W, J32, not args.no_graph)
+        rate32 = cells * K / (ms32 * 1e-3)
+        roof32 = profile_pass(w, F.FP32C, args.profile_steps, J32)
+        errs = fp32c_errors(w, psi64, psi32)
+        log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, errors {errs}")
+        fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
+                     error_vs_fp64_after_steps=W + K, **errs)
+        del J32
+    else:
+        del J64
+
+    cpu = None if args.no_cpu else cpu_baseline(w)
+    if cpu:
+        log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
+    out = {
+        "metric": METRIC, "value": rate64, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms64 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "modes": w.m, "nz": w.nz[0], "nr": w.nr[0], "fd_order": w.fd_order[0],
+                   "taylor_order": w.taylor_order, "dt_over_dz": 0.5, "dr_over_dz": 2.0, "current": "bunch+noise",
+                   "graph": not args.no_graph, "parallelism": "single GPU, modes batched in one plan"},
+        "roofline": roof64,
+        "cpu_baseline": cpu,
+        "fp32c": fp32c,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

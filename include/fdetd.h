@@ -1,0 +1,160 @@
+/*
+ * fdetd.h -- C-ABI of the MI355X (gfx950) FDETD library: the finite-difference exponential time-domain
+ * field update of a cylindrical (z, rho) particle-in-cell code with azimuthal mode decomposition, and
+ * the exponential propagator of the laser-envelope potential (Majorosi, Hafz & Lecz, arXiv 2605.12132).
+ *
+ * Plain C types and pointers only.  Field, current and susceptibility buffers are DEVICE pointers owned
+ * by the caller (any allocator; PyTorch in the provided binding).  All calls enqueue work on the plan's
+ * HIP stream and return immediately; results are valid once that stream has synchronised.
+ *
+ * ---------------------------------------------------------------------------------------------------
+ * Storage (all arrays contiguous, 16-byte aligned):
+ *   plane          [nr][nz] interleaved complex, z fastest: double2 for FDETD_FP64, float2 for FDETD_FP32C.
+ *   Maxwell state  psi: 6 consecutive planes E_rho, E_theta, E_z, B_rho, B_theta, B_z of one azimuthal
+ *                  mode m in the complex form F_m = F_{2m} + i F_{2m+1} of the paper's real mode pair
+ *                  (section 2.1: the angular derivative acts as i*m).  Yee staggering (Table 1): E_rho,
+ *                  B_theta, B_z sit on the staggered radial grid rho_(-),k = k*dr (row 0 is the axis);
+ *                  E_theta, E_z, B_rho on rho_k = (k + 1/2) dr; E_z, B_rho, B_theta on the staggered z
+ *                  grid z_i - dz/2, the others on z_i = i*dz.
+ *                  Row 0 of E_rho, B_theta, B_z is the rho = 0 slot: ignored on input, written on output
+ *                  by the boundary rule of section 2.4 (sum_k' c_k' F_k' where the component is constant
+ *                  on the axis -- B_z for m = 0, E_rho and B_theta for m = 1 -- and 0 otherwise).
+ *   current        j: 3 consecutive planes J_rho, J_theta, J_z at t + dt/2, deposited on the primary
+ *                  radial grid (section 2.5 current pre-processing); J_rho and J_theta on z_i, J_z on
+ *                  z_i - dz/2.  J_rho is staggered to rho_(-) by the library (S_rho^(-,mA)).
+ *   envelope       a, a_tilde: one plane each on the primary grids; chi: [nr][nz] real (double for
+ *                  FDETD_FP64, float for FDETD_FP32C), the susceptibility chi_0 at t + dt/2.
+ *
+ * Errors: every call returns FDETD_OK (0) or a negative code; no exception crosses the ABI.
+ * fdetd_last_error() returns a human-readable message for the last failure on that plan
+ * (or of the last failed fdetd_plan() on this thread when called with NULL).
+ * ---------------------------------------------------------------------------------------------------
+ */
+#ifndef FDETD_H
+#define FDETD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define FDETD_API __attribute__((visibility("default")))
+#else
+#define FDETD_API
+#endif
+
+#define FDETD_OK          0
+#define FDETD_E_ARG      -1  /* bad sizes, order, pointer, alignment or call sequence              */
+#define FDETD_E_UNSTABLE -2  /* dt * (estimated spectral radius of H) exceeds the Taylor bound X_N */
+#define FDETD_E_NOMEM    -3  /* device allocation failed                                          */
+#define FDETD_E_HIP      -4  /* a HIP runtime call failed (message carries hipGetErrorString)       */
+
+#define FDETD_FP64  0        /* everything in double                                                */
+#define FDETD_FP32C 1        /* float fields + float compensation word per value (see fdetd_step)   */
+
+#define FDETD_MAXWELL  0
+#define FDETD_ENVELOPE 1
+
+/* plan flags */
+#define FDETD_PLAN_SKIP_STABILITY 1u  /* do not estimate the spectral radius at plan time           */
+#define FDETD_PLAN_USE_GRAPH      2u  /* fdetd_step / envelope_step replay a captured hipGraph        */
+#define FDETD_PLAN_PROFILE        4u  /* time every stage kernel with HIP events (not with USE_GRAPH)  */
+
+typedef struct fdetd_plan_s *fdetd_plan_t;
+
+/* One independent problem: one grid and one azimuthal mode (modes never couple, section 2.1). */
+typedef struct {
+    int32_t kind;          /* FDETD_MAXWELL or FDETD_ENVELOPE                                      */
+    int32_t nz, nr;        /* M_z >= 2*N_D + 1, M_rho >= N_D + 1 (section 2.2)                     */
+    int32_t m;             /* azimuthal mode number, 0 <= m <= 64                                 */
+    int32_t fd_order;      /* 2*N_D, even, 2..32 (section 2.3 staggered differences)               */
+    int32_t taylor_order;  /* N, 1..32: terms of the Taylor sum of each exponential (section 2.5)  */
+    double dz, dr, dt;     /* cell sizes and time step, normalised units (c = 1), all > 0          */
+    double k0;             /* envelope carrier wavenumber (section 4.1); ignored for Maxwell       */
+} fdetd_problem_desc;
+
+typedef struct {
+    int32_t n_probs;
+    int32_t precision;
+    double dt_rho_max;        /* max over problems of dt * estimated spectral radius of H (0: skipped) */
+    double stability_margin;  /* min over problems of X_N / (dt * rho_hat) (0: skipped)                */
+    int64_t cells;            /* sum over problems of nz * nr                                      */
+    int64_t bytes_per_step;   /* algorithmic HBM bytes of one step of all problems                 */
+    int64_t scratch_bytes;    /* device memory owned by the plan                                  */
+    int64_t launches_per_step;
+    /* FDETD_PLAN_PROFILE: stage kernels timed since the previous fdetd_query (query synchronises) */
+    int64_t profiled_launches;
+    double profiled_ms;          /* sum of their durations                                       */
+    double profiled_bytes;       /* sum of their algorithmic HBM bytes                           */
+} fdetd_plan_info;
+
+/* Build a plan for n_probs problems (all FDETD_MAXWELL or all FDETD_ENVELOPE).
+ *   probs      host array of n_probs descriptors (copied; caller keeps ownership).
+ *   precision  FDETD_FP64 or FDETD_FP32C.
+ *   flags      FDETD_PLAN_* bits.
+ *   stream     hipStream_t the plan enqueues on (NULL = default stream); the plan is bound to it.
+ *   out        receives the plan handle; free it with fdetd_destroy.
+ * Generates the coefficient tables in FP64 (section 2.3: staggered, centred and Lagrange weights; section
+ * 2.4: axis extrapolation weights), allocates the plan's scratch (ping-pong stage vectors, staggered
+ * current, FP32C compensation words) and, unless FDETD_PLAN_SKIP_STABILITY, estimates the spectral radius
+ * of each H by power iteration on the GPU and rejects the plan with FDETD_E_UNSTABLE when
+ * dt * rho_hat * 1.02 >= X_N (largest x with |T_N(i y)| <= 1 + 1e-9 for all y <= x).  Synchronises the
+ * stream before returning. */
+FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precision, uint32_t flags,
+               void *stream, fdetd_plan_t *out);
+
+/* Advance every Maxwell problem by n_steps midpoint exponential steps (section 2.1, midpoint rule
+ * with the factor dt, and the algorithm summary of section 2.5):
+ *     psi(t + dt) = T_N(dt H_m) psi(t) - dt * T_N(dt H_m / 2) Jbar(t + dt/2),
+ * T_N(X) = sum_{n=0..N} X^n / n!, Jbar = (S_rho^(-,mA) J_rho, J_theta, J_z) (current filters = identity).
+ *   psi     n_probs device pointers, each to the 6-plane state of that problem; updated in place.
+ *           FDETD_FP32C: float2 planes holding the rounded state; the plan keeps one float compensation
+ *           word per real value so that the stored state plus compensation carries ~2x float precision
+ *           across steps (export/import with fdetd_export_state / fdetd_import_state).  The
+ *           compensation is reset to zero whenever a psi pointer differs from the previous call's.
+ *   j_half  NULL (no current) or n_probs device pointers to 3-plane currents at t + dt/2.
+ *   j_step_stride  elements (complex values) between the currents of consecutive steps; step s uses
+ *           j_half[p] + s * j_step_stride; 0 reuses one current for all steps.
+ *   n_steps >= 0.
+ * Enqueue only.  Error (nothing enqueued) on NULL or misaligned pointers or a plan of the wrong kind. */
+FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_stride,
+               int32_t n_steps);
+
+/* Advance every envelope problem by n_steps of psi_a(t + dt) = T_N(dt H_a(chi(t + dt/2))) psi_a(t)
+ * (section 4.1 exponential solution, section 4.2 discrete operator with L_rho + L_z - m^2/rho^2 and the
+ * centred D_z^(C), complex form of the envelope equation with +2 i k0 terms).
+ *   a, a_tilde  n_probs device pointers to one plane each; updated in place.
+ *   chi_half    n_probs device pointers to real [nr][nz] susceptibility planes; step s uses
+ *               chi_half[p] + s * chi_step_stride (0: the same plane every step).  Must not be NULL.
+ * Enqueue only. */
+FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
+                  int64_t chi_step_stride, int32_t n_steps);
+
+/* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
+FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);
+
+/* FP32C compensation words of all problems (bytes = fdetd_query().scratch needed: pass *bytes = 0 to
+ * query the size).  FDETD_FP64 plans have no state (size 0).  Synchronises the stream. */
+FDETD_API int fdetd_export_state(fdetd_plan_t plan, void *host_blob, size_t *bytes);
+FDETD_API int fdetd_import_state(fdetd_plan_t plan, const void *host_blob, size_t bytes);
+
+/* Coefficient tables as the library generates them (host only, no GPU needed), FP64:
+ *   which 0: staggered first derivative a_1..a_nd      1: Lagrange half shift s_1..s_nd
+ *         2: centred first derivative d_1..d_nd       3: centred second derivative b_0..b_nd
+ *         4: axis extrapolation c_1..c_nd
+ *   out must hold nd + 1 doubles. */
+FDETD_API int fdetd_coefficients(int32_t which, int32_t nd, double *out);
+
+/* Largest x with |T_N(i y)| <= 1 + 1e-9 for all 0 <= y <= x (the plan's stability bound). Host only. */
+FDETD_API double fdetd_taylor_stability_bound(int32_t taylor_order);
+
+FDETD_API const char *fdetd_last_error(fdetd_plan_t plan);
+FDETD_API void fdetd_destroy(fdetd_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,244 @@
+"""ctypes binding of the FDETD C-ABI (include/fdetd.h).
+
+Argument marshalling only: every operation runs in the HIP kernels of libfdetd.so.  The functions keep
+the C names (fdetd_plan, fdetd_step, envelope_step, ...); ``Plan`` is a small convenience wrapper that
+takes PyTorch device tensors and enqueues on torch's current stream.  If the library is missing the
+import of this module raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libfdetd.so")
+
+FDETD_OK, FDETD_E_ARG, FDETD_E_UNSTABLE, FDETD_E_NOMEM, FDETD_E_HIP = 0, -1, -2, -3, -4
+FP64, FP32C = 0, 1
+MAXWELL, ENVELOPE = 0, 1
+PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE = 1, 2, 4
+
+# every symbol declared in include/fdetd.h
+EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "fdetd_query", "fdetd_export_state",
+           "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
+           "fdetd_destroy")
+
+
+class FdetdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"FDETD error {code}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nz", C.c_int32), ("nr", C.c_int32), ("m", C.c_int32),
+                ("fd_order", C.c_int32), ("taylor_order", C.c_int32),
+                ("dz", C.c_double), ("dr", C.c_double), ("dt", C.c_double), ("k0", C.c_double)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_probs", C.c_int32), ("precision", C.c_int32), ("dt_rho_max", C.c_double),
+                ("stability_margin", C.c_double), ("cells", C.c_int64), ("bytes_per_step", C.c_int64),
+                ("scratch_bytes", C.c_int64), ("launches_per_step", C.c_int64),
+                ("profiled_launches", C.c_int64), ("profiled_ms", C.c_double), ("profiled_bytes", C.c_double)]
+
+
+@dataclass
+class Problem:
+    """One grid and one azimuthal mode (normalised units, c = 1)."""
+    nz: int
+    nr: int
+    m: int
+    fd_order: int
+    taylor_order: int
+    dz: float
+    dr: float
+    dt: float
+    k0: float = 1.0
+    kind: int = MAXWELL
+
+    def c(self) -> ProblemDesc:
+        return ProblemDesc(self.kind, self.nz, self.nr, self.m, self.fd_order, self.taylor_order,
+                           self.dz, self.dr, self.dt, self.k0)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run paper_2605_12132_amd/build.py (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, pp = C.c_void_p, C.POINTER(C.c_void_p)
+    L.fdetd_plan.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.c_int32, C.c_uint32, vp, C.POINTER(vp)]
+    L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
+    L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
+    L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
+    L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.fdetd_import_state.argtypes = [vp, vp, C.c_size_t]
+    L.fdetd_coefficients.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.fdetd_taylor_stability_bound.argtypes = [C.c_int32]
+    L.fdetd_taylor_stability_bound.restype = C.c_double
+    L.fdetd_last_error.argtypes = [vp]
+    L.fdetd_last_error.restype = C.c_char_p
+    L.fdetd_destroy.argtypes = [vp]
+    L.fdetd_destroy.restype = None
+    return L
+
+
+lib = _load()
+
+
+def fdetd_last_error(plan=None) -> str:
+    s = lib.fdetd_last_error(plan)
+    return s.decode() if s else ""
+
+
+def _check(rc: int, plan=None):
+    if rc != FDETD_OK:
+        raise FdetdError(rc, fdetd_last_error(plan))
+
+
+def _ptrs(xs) -> C.Array:
+    arr = (C.c_void_p * len(xs))()
+    for i, x in enumerate(xs):
+        arr[i] = x
+    return arr
+
+
+def fdetd_plan(problems: Sequence[Problem], precision: int = FP64, flags: int = 0, stream: int = 0):
+    descs = (ProblemDesc * len(problems))(*[p.c() for p in problems])
+    out = C.c_void_p()
+    rc = lib.fdetd_plan(descs, len(problems), precision, flags, C.c_void_p(stream), C.byref(out))
+    _check(rc, None)
+    return out.value
+
+
+def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_stride: int = 0, n_steps: int = 1):
+    rc = lib.fdetd_step(plan, _ptrs(psi_ptrs), _ptrs(j_ptrs) if j_ptrs is not None else None,
+                        j_step_stride, n_steps)
+    _check(rc, plan)
+
+
+def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_stride: int = 0, n_steps: int = 1):
+    rc = lib.envelope_step(plan, _ptrs(a_ptrs), _ptrs(at_ptrs), _ptrs(chi_ptrs), chi_step_stride, n_steps)
+    _check(rc, plan)
+
+
+def fdetd_query(plan) -> dict:
+    info = PlanInfo()
+    _check(lib.fdetd_query(plan, C.byref(info)), plan)
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+def fdetd_export_state(plan) -> bytes:
+    n = C.c_size_t(0)
+    _check(lib.fdetd_export_state(plan, None, C.byref(n)), plan)
+    buf = C.create_string_buffer(max(n.value, 1))
+    _check(lib.fdetd_export_state(plan, buf, C.byref(n)), plan)
+    return buf.raw[:n.value]
+
+
+def fdetd_import_state(plan, blob: bytes):
+    _check(lib.fdetd_import_state(plan, blob if blob else None, len(blob)), plan)
+
+
+def fdetd_coefficients(which: int, nd: int):
+    out = (C.c_double * (nd + 1))()
+    _check(lib.fdetd_coefficients(which, nd, out), None)
+    n = nd + 1 if which == 3 else nd
+    return [out[i] for i in range(n)]
+
+
+def fdetd_taylor_stability_bound(n: int) -> float:
+    return float(lib.fdetd_taylor_stability_bound(n))
+
+
+def fdetd_destroy(plan):
+    lib.fdetd_destroy(plan)
+
+
+class Plan:
+    """Owns one fdetd plan bound to torch's current CUDA (HIP) stream at construction."""
+
+    def __init__(self, problems: Sequence[Problem], precision: int = FP64, flags: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("FDETD needs a gfx950 GPU; none is visible")
+        self.problems = list(problems)
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = fdetd_plan(self.problems, precision, flags, self.stream.cuda_stream)
+
+    # --- tensor checks (shape / dtype / device / contiguity), then raw pointers ---
+    def _cdtype(self):
+        import torch
+        return torch.complex128 if self.precision == FP64 else torch.complex64
+
+    def _rdtype(self):
+        import torch
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+    def _nchk(self, xs, what):
+        if len(xs) != len(self.problems):
+            raise ValueError(f"{what}: {len(xs)} tensors for {len(self.problems)} problems")
+
+    def _chk(self, t, shape_tail, dtype, what):
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape[-len(shape_tail):]) != shape_tail:
+            raise ValueError(f"{what}: need contiguous {dtype} cuda tensor [..., {shape_tail}], got "
+                             f"{t.dtype} {tuple(t.shape)} cuda={t.is_cuda} contiguous={t.is_contiguous()}")
+        return t.data_ptr()
+
+    def step(self, psi, j_half=None, n_steps: int = 1):
+        """psi: list of [6, nr, nz] tensors; j_half: None, list of [3, nr, nz] (same current every step)
+        or [n_steps, 3, nr, nz] (one current per step)."""
+        cd = self._cdtype()
+        self._nchk(psi, "psi")
+        if j_half is not None:
+            self._nchk(j_half, "j_half")
+        pp = [self._chk(x, (6, p.nr, p.nz), cd, "psi") for x, p in zip(psi, self.problems)]
+        jp, stride = None, 0
+        if j_half is not None:
+            jp = [self._chk(x, (3, p.nr, p.nz), cd, "j_half") for x, p in zip(j_half, self.problems)]
+            if j_half[0].dim() == 4 and n_steps > 1:
+                if any(x.shape[0] < n_steps for x in j_half):
+                    raise ValueError("j_half has fewer steps than n_steps")
+                stride = 3 * self.problems[0].nr * self.problems[0].nz
+                if any(3 * p.nr * p.nz != stride for p in self.problems):
+                    raise ValueError("per-step currents need equal grid sizes across problems")
+        fdetd_step(self._h, pp, jp, stride, n_steps)
+
+    def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):
+        cd, rd = self._cdtype(), self._rdtype()
+        for x, what in ((a, "a"), (a_tilde, "a_tilde"), (chi, "chi")):
+            self._nchk(x, what)
+        ap = [self._chk(x, (p.nr, p.nz), cd, "a") for x, p in zip(a, self.problems)]
+        tp = [self._chk(x, (p.nr, p.nz), cd, "a_tilde") for x, p in zip(a_tilde, self.problems)]
+        cp = [self._chk(x, (p.nr, p.nz), rd, "chi") for x, p in zip(chi, self.problems)]
+        stride = 0
+        if chi[0].dim() == 3 and n_steps > 1:
+            if any(x.shape[0] < n_steps for x in chi):
+                raise ValueError("chi has fewer steps than n_steps")
+            stride = self.problems[0].nr * self.problems[0].nz
+            if any(p.nr * p.nz != stride for p in self.problems):
+                raise ValueError("per-step chi needs equal grid sizes across problems")
+        envelope_step(self._h, ap, tp, cp, stride, n_steps)
+
+    def query(self) -> dict:
+        return fdetd_query(self._h)
+
+    def export_state(self) -> bytes:
+        return fdetd_export_state(self._h)
+
+    def import_state(self, blob: bytes):
+        fdetd_import_state(self._h, blob)
+
+    def close(self):
+        if self._h:
+            fdetd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

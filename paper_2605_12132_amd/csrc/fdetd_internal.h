@@ -1,0 +1,87 @@
+// Internal declarations shared by the host runtime (fdetd_plan.cpp), the coefficient generator
+// (fdetd_coeffs.cpp) and the gfx950 kernels (fdetd_kernels.hip).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fdetd {
+
+constexpr int kMaxND = 16;  // fd_order <= 32
+
+enum { COEF_STAGGERED = 0, COEF_HALFSHIFT = 1, COEF_CENTRED_D1 = 2, COEF_CENTRED_D2 = 3, COEF_AXIS = 4 };
+
+bool make_coefficients(int which, int nd, double *out);
+double taylor_stability_bound(int N);
+
+enum Prec { P64 = 0, P32 = 1 };
+
+// Component order inside a 6-plane Maxwell vector.
+enum { ER = 0, ETH = 1, EZ = 2, BR = 3, BTH = 4, BZ = 5 };
+
+// One Horner stage of the Maxwell propagator for one problem:
+//   vout = w + coef * H vin,    w = psi + beta * Jbar   (Jbar only in the E slots)
+// In the first stage of a step the input is w_N = psi + beta_in * Jbar, formed while loading (vin = psi).
+// FP32C: the last stage (vout == psi_hi) adds the increment into the (hi, lo) pair instead of storing w.
+struct MaxwellStageArgs {
+    const void *vin;
+    const void *psi;
+    const void *jr, *jt, *jz;  // Jbar planes (jr on the staggered rho grid); all null when no source
+    void *vout;
+    float *lo;                 // FP32C compensation words of psi (6 planes of float2); null otherwise
+    const double *rinv_p;      // 1 / rho_k, k in [0, nr)
+    const double *rinv_s;      // 1 / rho_(-),k for k >= 1, 0 at the axis
+    double beta_in, beta, coef;
+    double dr;
+    double pS;                 // +1 / -1: radial extension sign of scalar-like (mS) components
+    int nz, nr, m;
+    int first, has_src, last_compensated;
+    int axis_rows;             // rows k < axis_rows use FP64 arithmetic in the FP32C kernels
+    double az[kMaxND];         // a_j / dz
+    double ar[kMaxND];         // a_j / dr
+    double cax[kMaxND];        // axis extrapolation weights c_k'
+};
+
+struct EnvelopeStageArgs {
+    const void *vin_a, *vin_t;  // stage input (a, a~)
+    const void *psi_a, *psi_t;  // state at t
+    const void *chi;            // real plane
+    void *out_a, *out_t;
+    float *lo_a, *lo_t;         // FP32C compensation (last stage only)
+    const double *rinv_p;       // 1 / rho_k
+    const double *m2rinv2;      // m^2 / rho_k^2
+    double coef, k0, pS;
+    int nz, nr, last_compensated, axis_rows;
+    double bz[kMaxND + 1];      // centred second-difference weights / dz^2 (b_0 .. b_nd)
+    double br[kMaxND + 1];      // ... / dr^2
+    double dzc[kMaxND];         // centred first-difference weights / dz
+    double drc[kMaxND];         // ... / dr
+};
+
+struct StaggerArgs {
+    const void *jr;  // J_rho on the primary grid
+    void *out;       // Jbar_rho on the staggered rho grid (row 0 written as 0)
+    double pA;       // extension sign of polar-like (mA) components
+    int nz, nr;
+    double s[kMaxND];
+};
+
+struct AxisArgs {
+    void *psi;  // 6 planes
+    int nz, nr, m;
+    double cax[kMaxND];
+};
+
+hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s);
+hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s);
+hipError_t launch_stagger_jr(int prec, int nd, const StaggerArgs &a, hipStream_t s);
+hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s);
+// Per-block partial sums of |x|^2 over n complex values (double2 or float2); nblocks written to partial.
+hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s);
+hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s);
+// Device-to-device copy of a multiple of 8 bytes by kernel (graph-capture friendly).
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace fdetd

@@ -1,0 +1,509 @@
+// gfx950 kernels of the FDETD field update and the envelope propagator (arXiv 2605.12132).
+//
+// Every kernel here is one banded-matrix sweep over a (z, rho) grid (section 2.2): lanes run along z
+// (z is the contiguous axis, so a wave's loads of one row are fully coalesced 1 KiB (FP64) / 512 B (FP32)
+// transactions), the four waves of a workgroup cover four consecutive rows, and neighbouring rows' loads
+// are shared through the L1/L2 caches.  The work is HBM-bound (about 1.3 flop per byte at FP64), so no
+// matrix cores are used.
+#include <hip/hip_runtime.h>
+
+#include "fdetd_internal.h"
+
+namespace fdetd {
+namespace {
+
+constexpr int TZ = 64;  // z extent of a workgroup tile (one wave)
+constexpr int TR = 4;   // rows per workgroup (one wave each)
+
+template <typename AR>
+struct cx {
+    AR x, y;
+};
+
+template <typename AR>
+__device__ __forceinline__ cx<AR> operator+(cx<AR> a, cx<AR> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename AR>
+__device__ __forceinline__ cx<AR> operator-(cx<AR> a, cx<AR> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename AR>
+__device__ __forceinline__ cx<AR> operator*(AR s, cx<AR> a) { return {s * a.x, s * a.y}; }
+// i * s * a
+template <typename AR>
+__device__ __forceinline__ cx<AR> times_i(AR s, cx<AR> a) { return {-s * a.y, s * a.x}; }
+
+template <typename V> struct storage;
+template <> struct storage<double2> { using R = double; };
+template <> struct storage<float2> { using R = float; };
+
+template <typename AR, typename V>
+__device__ __forceinline__ cx<AR> ld(const V *p, size_t o)
+{
+    const V v = p[o];
+    return {(AR)v.x, (AR)v.y};
+}
+
+// --------------------------------------------------------------------------------------------------
+// Maxwell Horner stage: vout = w + coef * H vin (section 2.5 discrete Ampere/Faraday equations).
+// Radial values outside the grid follow section 2.4: a primary row q < 0 is row -1-q, a staggered row
+// q < 0 is row -q, times the extension sign of the component; rows >= nr and z outside [0, nz) are 0.
+// The divergence operands rho*F of D_div^(+-) are formed from the extended F and the signed coordinate
+// of the row (negative on the mirror side), which is the extension of rho*F with the opposite sign.
+// --------------------------------------------------------------------------------------------------
+template <typename AR, typename V, int ND>
+__device__ __forceinline__ void maxwell_cell(const MaxwellStageArgs &A, int k, int i, cx<AR> d[6])
+{
+    const int nz = A.nz, nr = A.nr;
+    const size_t P = (size_t)nz * nr;
+    const V *vin = (const V *)A.vin;
+    const bool addj = A.first && A.has_src;
+    const V *jp[3] = {(const V *)A.jr, (const V *)A.jt, (const V *)A.jz};
+    const AR beta_in = (AR)A.beta_in;
+
+    auto at = [&](int c, int q, int ii) -> cx<AR> {  // 0 <= q < nr, 0 <= ii < nz
+        const size_t o = (size_t)q * nz + ii;
+        cx<AR> x = ld<AR>(vin + c * P, o);
+        if (addj && c < 3) x = x + beta_in * ld<AR>(jp[c], o);
+        return x;
+    };
+    auto zv = [&](int c, int q, int ii) -> cx<AR> {
+        if (ii < 0 || ii >= nz) return {0, 0};
+        return at(c, q, ii);
+    };
+    auto prim = [&](int c, int q, AR par) -> cx<AR> {
+        if (q < 0) {
+            q = -1 - q;
+            if (q >= nr) return {0, 0};
+            return par * at(c, q, i);
+        }
+        if (q >= nr) return {0, 0};
+        return at(c, q, i);
+    };
+    auto stag = [&](int c, int q, AR par, cx<AR> axis) -> cx<AR> {
+        if (q == 0) return axis;
+        if (q < 0) {
+            q = -q;
+            if (q >= nr) return {0, 0};
+            return par * at(c, q, i);
+        }
+        if (q >= nr) return {0, 0};
+        return at(c, q, i);
+    };
+
+    const AR pS = (AR)A.pS, pA = -(AR)A.pS;
+    const AR dr = (AR)A.dr;
+    const AR mm = (AR)A.m;
+    const AR rip = (AR)A.rinv_p[k];
+    const AR ris = (AR)A.rinv_s[k];
+    const cx<AR> zero = {0, 0};
+
+    // B_z on the axis: extrapolated for m = 0 (constant on the axis), else 0 (section 2.4)
+    cx<AR> bz_axis = zero;
+    if (A.m == 0 && k < ND) {
+#pragma unroll
+        for (int q = 1; q <= ND; ++q) bz_axis = bz_axis + (AR)A.cax[q - 1] * at(BZ, q, i);
+    }
+
+    // dE_rho = -D_z^(+) B_theta + (i m / rho_(-)) B_z           (staggered rows k >= 1)
+    {
+        cx<AR> s = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) s = s + (AR)A.az[j - 1] * (zv(BTH, k, i + j) - zv(BTH, k, i - j + 1));
+        d[ER] = (k >= 1) ? times_i(mm * ris, at(BZ, k, i)) - s : zero;
+    }
+    // dE_theta = D_z^(+) B_rho - D_rho^(+,mS) B_z
+    {
+        cx<AR> s = zero, t = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            s = s + (AR)A.az[j - 1] * (zv(BR, k, i + j) - zv(BR, k, i - j + 1));
+            t = t + (AR)A.ar[j - 1] * (stag(BZ, k + j, pS, bz_axis) - stag(BZ, k - j + 1, pS, bz_axis));
+        }
+        d[ETH] = s - t;
+    }
+    // dE_z = -(i m / rho) B_rho + rho^-1 D^(+) (rho_(-) B_theta)
+    {
+        cx<AR> t = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const int q1 = k + j, q2 = k - j + 1;
+            t = t + (AR)A.ar[j - 1] * ((dr * (AR)q1) * stag(BTH, q1, pA, zero) - (dr * (AR)q2) * stag(BTH, q2, pA, zero));
+        }
+        d[EZ] = rip * t - times_i(mm * rip, at(BR, k, i));
+    }
+    // dB_rho = D_z^(-) E_theta - (i m / rho) E_z
+    {
+        cx<AR> s = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) s = s + (AR)A.az[j - 1] * (zv(ETH, k, i + j - 1) - zv(ETH, k, i - j));
+        d[BR] = s - times_i(mm * rip, at(EZ, k, i));
+    }
+    // dB_theta = -D_z^(-) E_rho + D_rho^(-,mS) E_z               (k >= 1)
+    {
+        cx<AR> s = zero, t = zero;
+        if (k >= 1) {
+#pragma unroll
+            for (int j = 1; j <= ND; ++j) {
+                s = s + (AR)A.az[j - 1] * (zv(ER, k, i + j - 1) - zv(ER, k, i - j));
+                t = t + (AR)A.ar[j - 1] * (prim(EZ, k + j - 1, pS) - prim(EZ, k - j, pS));
+            }
+        }
+        d[BTH] = t - s;
+    }
+    // dB_z = (i m / rho_(-)) E_rho - rho_(-)^-1 D^(-) (rho E_theta)  (k >= 1)
+    {
+        cx<AR> t = zero;
+        if (k >= 1) {
+#pragma unroll
+            for (int j = 1; j <= ND; ++j) {
+                const int q1 = k + j - 1, q2 = k - j;
+                t = t + (AR)A.ar[j - 1] * ((dr * ((AR)q1 + (AR)0.5)) * prim(ETH, q1, pA) -
+                                           (dr * ((AR)q2 + (AR)0.5)) * prim(ETH, q2, pA));
+            }
+            d[BZ] = times_i(mm * ris, at(ER, k, i)) - ris * t;
+        } else {
+            d[BZ] = zero;
+        }
+    }
+}
+
+// Error-free sum of two floats (Knuth's TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename AR, typename V>
+__device__ __forceinline__ void maxwell_store(const MaxwellStageArgs &A, int k, int i, const cx<AR> d[6])
+{
+    const size_t P = (size_t)A.nz * A.nr;
+    const size_t o = (size_t)k * A.nz + i;
+    const V *psi = (const V *)A.psi;
+    V *out = (V *)A.vout;
+    const V *jp[3] = {(const V *)A.jr, (const V *)A.jt, (const V *)A.jz};
+    const AR coef = (AR)A.coef, beta = (AR)A.beta;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const bool axis_slot = (k == 0) && (c == ER || c == BTH || c == BZ);
+        // increment relative to psi: beta * Jbar (E slots) + coef * H v
+        cx<AR> inc = coef * d[c];
+        if (A.has_src && c < 3) inc = inc + beta * ld<AR>(jp[c], o);
+        if constexpr (sizeof(V) == 8) {
+            if (A.last_compensated) {
+                // psi_hi + lo + inc -> (psi_hi, lo), both float, carried exactly by TwoSum
+                float2 *lo = (float2 *)A.lo;
+                const float2 h = ((const float2 *)psi)[c * P + o];
+                const float2 l = lo[c * P + o];
+                float sx, ex, sy, ey;
+                two_sum(h.x, (float)(inc.x + (AR)l.x), sx, ex);
+                two_sum(h.y, (float)(inc.y + (AR)l.y), sy, ey);
+                if (axis_slot) sx = sy = ex = ey = 0.f;
+                out[c * P + o] = V{sx, sy};
+                lo[c * P + o] = float2{ex, ey};
+                continue;
+            }
+        }
+        cx<AR> w = ld<AR>(psi + c * P, o) + inc;
+        if (axis_slot) w = {0, 0};
+        out[c * P + o] = V{(typename storage<V>::R)w.x, (typename storage<V>::R)w.y};
+    }
+}
+
+template <typename V, int ND>
+__global__ __launch_bounds__(TZ *TR) void k_maxwell_stage(MaxwellStageArgs A)
+{
+    using R = typename storage<V>::R;
+    const int i = blockIdx.x * TZ + threadIdx.x;
+    const int k = blockIdx.y * TR + threadIdx.y;
+    if (i >= A.nz || k >= A.nr) return;
+    if constexpr (sizeof(R) == 4) {
+        if (k < A.axis_rows) {  // near-axis rows: 1/rho amplifies rounding, keep FP64 arithmetic
+            cx<double> d[6];
+            maxwell_cell<double, V, ND>(A, k, i, d);
+            maxwell_store<double, V>(A, k, i, d);
+            return;
+        }
+    }
+    cx<R> d[6];
+    maxwell_cell<R, V, ND>(A, k, i, d);
+    maxwell_store<R, V>(A, k, i, d);
+}
+
+// --------------------------------------------------------------------------------------------------
+// Envelope Horner stage (section 4.2):  out = psi + coef * H_a vin,
+//   H_a (a, a~) = (a~, (L_rho + L_z - m^2/rho^2 - chi) a + 2 i k0 (D_z^(C) a + a~)),
+// L_rho = D^2 + rho^-1 D^(C) with the scalar-like (mS) extension at rho < 0.
+// --------------------------------------------------------------------------------------------------
+template <typename AR, typename V, int ND>
+__device__ __forceinline__ void envelope_cell(const EnvelopeStageArgs &A, int k, int i)
+{
+    using R = typename storage<V>::R;
+    const int nz = A.nz, nr = A.nr;
+    const V *va = (const V *)A.vin_a;
+    const size_t o = (size_t)k * nz + i;
+    const AR pS = (AR)A.pS;
+    auto rv = [&](int q) -> cx<AR> {
+        if (q < 0) {
+            q = -1 - q;
+            if (q >= nr) return {0, 0};
+            return pS * ld<AR>(va, (size_t)q * nz + i);
+        }
+        if (q >= nr) return {0, 0};
+        return ld<AR>(va, (size_t)q * nz + i);
+    };
+    auto zv = [&](int ii) -> cx<AR> {
+        if (ii < 0 || ii >= nz) return {0, 0};
+        return ld<AR>(va, (size_t)k * nz + ii);
+    };
+    const cx<AR> a0 = ld<AR>(va, o);
+    cx<AR> lr = (AR)A.br[0] * a0, dr1 = {0, 0}, lz = (AR)A.bz[0] * a0, dz1 = {0, 0};
+#pragma unroll
+    for (int j = 1; j <= ND; ++j) {
+        const cx<AR> rp = rv(k + j), rm = rv(k - j);
+        lr = lr + (AR)A.br[j] * (rp + rm);
+        dr1 = dr1 + (AR)A.drc[j - 1] * (rp - rm);
+        const cx<AR> zp = zv(i + j), zm = zv(i - j);
+        lz = lz + (AR)A.bz[j] * (zp + zm);
+        dz1 = dz1 + (AR)A.dzc[j - 1] * (zp - zm);
+    }
+    const cx<AR> tin = ld<AR>((const V *)A.vin_t, o);
+    const AR pot = (AR)A.m2rinv2[k] + (AR)((const R *)A.chi)[o];
+    const cx<AR> da = tin;
+    const cx<AR> dt = lr + (AR)A.rinv_p[k] * dr1 + lz - pot * a0 + times_i((AR)(2.0 * A.k0), dz1 + tin);
+    const AR coef = (AR)A.coef;
+    const cx<AR> ia = coef * da, it = coef * dt;
+    if constexpr (sizeof(R) == 4) {
+        if (A.last_compensated) {
+            float2 *loa = (float2 *)A.lo_a, *lot = (float2 *)A.lo_t;
+            const float2 ha = ((const float2 *)A.psi_a)[o], ht = ((const float2 *)A.psi_t)[o];
+            const float2 la = loa[o], lt = lot[o];
+            float s0, e0, s1, e1, s2, e2, s3, e3;
+            two_sum(ha.x, (float)(ia.x + (AR)la.x), s0, e0);
+            two_sum(ha.y, (float)(ia.y + (AR)la.y), s1, e1);
+            two_sum(ht.x, (float)(it.x + (AR)lt.x), s2, e2);
+            two_sum(ht.y, (float)(it.y + (AR)lt.y), s3, e3);
+            ((float2 *)A.out_a)[o] = float2{s0, s1};
+            ((float2 *)A.out_t)[o] = float2{s2, s3};
+            loa[o] = float2{e0, e1};
+            lot[o] = float2{e2, e3};
+            return;
+        }
+    }
+    const cx<AR> wa = ld<AR>((const V *)A.psi_a, o) + ia;
+    const cx<AR> wt = ld<AR>((const V *)A.psi_t, o) + it;
+    ((V *)A.out_a)[o] = V{(R)wa.x, (R)wa.y};
+    ((V *)A.out_t)[o] = V{(R)wt.x, (R)wt.y};
+}
+
+template <typename V, int ND>
+__global__ __launch_bounds__(TZ *TR) void k_envelope_stage(EnvelopeStageArgs A)
+{
+    using R = typename storage<V>::R;
+    const int i = blockIdx.x * TZ + threadIdx.x;
+    const int k = blockIdx.y * TR + threadIdx.y;
+    if (i >= A.nz || k >= A.nr) return;
+    if constexpr (sizeof(R) == 4) {
+        if (k < A.axis_rows) {
+            envelope_cell<double, V, ND>(A, k, i);
+            return;
+        }
+    }
+    envelope_cell<R, V, ND>(A, k, i);
+}
+
+// --------------------------------------------------------------------------------------------------
+// Current staging (section 2.5): Jbar_rho = S_rho^(-,mA) J_rho on the staggered rows k >= 1.
+// --------------------------------------------------------------------------------------------------
+template <typename V, int ND>
+__global__ __launch_bounds__(TZ *TR) void k_stagger_jr(StaggerArgs A)
+{
+    using R = typename storage<V>::R;
+    const int i = blockIdx.x * TZ + threadIdx.x;
+    const int k = blockIdx.y * TR + threadIdx.y;
+    if (i >= A.nz || k >= A.nr) return;
+    const V *j = (const V *)A.jr;
+    const double pA = A.pA;
+    auto rv = [&](int q) -> cx<double> {
+        if (q < 0) {
+            q = -1 - q;
+            if (q >= A.nr) return {0, 0};
+            return pA * ld<double>(j, (size_t)q * A.nz + i);
+        }
+        if (q >= A.nr) return {0, 0};
+        return ld<double>(j, (size_t)q * A.nz + i);
+    };
+    cx<double> s = {0, 0};
+    if (k >= 1) {
+#pragma unroll
+        for (int t = 1; t <= ND; ++t) s = s + A.s[t - 1] * (rv(k + t - 1) + rv(k - t));
+    }
+    ((V *)A.out)[(size_t)k * A.nz + i] = V{(R)s.x, (R)s.y};
+}
+
+// --------------------------------------------------------------------------------------------------
+// rho = 0 slots of E_rho, B_theta, B_z after a step (section 2.4): constant components take the
+// extrapolation sum c_k' F_k' (B_z for m = 0, E_rho and B_theta for m = 1); all others are 0.
+// --------------------------------------------------------------------------------------------------
+template <typename V, int ND>
+__global__ __launch_bounds__(256) void k_axis_fix(AxisArgs A)
+{
+    using R = typename storage<V>::R;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.nz) return;
+    const size_t P = (size_t)A.nz * A.nr;
+    V *psi = (V *)A.psi;
+    const int comps[3] = {ER, BTH, BZ};
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int c = comps[t];
+        const bool extrap = (c == BZ) ? (A.m == 0) : (A.m == 1);
+        cx<double> s = {0, 0};
+        if (extrap) {
+#pragma unroll
+            for (int q = 1; q <= ND; ++q) s = s + A.cax[q - 1] * ld<double>(psi + c * P, (size_t)q * A.nz + i);
+        }
+        psi[c * P + i] = V{(R)s.x, (R)s.y};
+    }
+}
+
+// --------------------------------------------------------------------------------------------------
+// Reductions for the plan-time power iteration: per-block sums of |x|^2 (wave shuffles, then LDS).
+// --------------------------------------------------------------------------------------------------
+template <typename V>
+__global__ __launch_bounds__(256) void k_norm2(const V *x, size_t n, double *partial)
+{
+    double acc = 0.0;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+        const V v = x[q];
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double wsum[4];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_scale(V *x, size_t n, double alpha)
+{
+    using R = typename storage<V>::R;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+        V v = x[q];
+        x[q] = V{(R)(alpha * v.x), (R)(alpha * v.y)};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy8(const uint2 *src, uint2 *dst, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) dst[q] = src[q];
+}
+
+// compile-time dispatch over the stencil half width N_D = 1..16
+template <template <typename, int> class L, typename V, typename Args>
+hipError_t dispatch_nd(int nd, const Args &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (nd) {
+#define FDETD_CASE(N) \
+    case N: return L<V, N>::go(a, grid, block, s);
+        FDETD_CASE(1) FDETD_CASE(2) FDETD_CASE(3) FDETD_CASE(4) FDETD_CASE(5) FDETD_CASE(6) FDETD_CASE(7)
+        FDETD_CASE(8) FDETD_CASE(9) FDETD_CASE(10) FDETD_CASE(11) FDETD_CASE(12) FDETD_CASE(13)
+        FDETD_CASE(14) FDETD_CASE(15) FDETD_CASE(16)
+#undef FDETD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename V, int ND>
+struct MaxwellL {
+    static hipError_t go(const MaxwellStageArgs &a, dim3 g, dim3 b, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_maxwell_stage<V, ND>), g, b, 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <typename V, int ND>
+struct EnvelopeL {
+    static hipError_t go(const EnvelopeStageArgs &a, dim3 g, dim3 b, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_envelope_stage<V, ND>), g, b, 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <typename V, int ND>
+struct StaggerL {
+    static hipError_t go(const StaggerArgs &a, dim3 g, dim3 b, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_stagger_jr<V, ND>), g, b, 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <typename V, int ND>
+struct AxisL {
+    static hipError_t go(const AxisArgs &a, dim3 g, dim3 b, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_axis_fix<V, ND>), g, b, 0, s, a);
+        return hipGetLastError();
+    }
+};
+
+dim3 tile_grid(int nz, int nr) { return dim3((nz + TZ - 1) / TZ, (nr + TR - 1) / TR, 1); }
+
+}  // namespace
+
+hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s)
+{
+    const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
+    return prec == P64 ? dispatch_nd<MaxwellL, double2>(nd, a, g, b, s)
+                       : dispatch_nd<MaxwellL, float2>(nd, a, g, b, s);
+}
+
+hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s)
+{
+    const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
+    return prec == P64 ? dispatch_nd<EnvelopeL, double2>(nd, a, g, b, s)
+                       : dispatch_nd<EnvelopeL, float2>(nd, a, g, b, s);
+}
+
+hipError_t launch_stagger_jr(int prec, int nd, const StaggerArgs &a, hipStream_t s)
+{
+    const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
+    return prec == P64 ? dispatch_nd<StaggerL, double2>(nd, a, g, b, s)
+                       : dispatch_nd<StaggerL, float2>(nd, a, g, b, s);
+}
+
+hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s)
+{
+    const dim3 g((a.nz + 255) / 256, 1, 1), b(256, 1, 1);
+    return prec == P64 ? dispatch_nd<AxisL, double2>(nd, a, g, b, s)
+                       : dispatch_nd<AxisL, float2>(nd, a, g, b, s);
+}
+
+hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s)
+{
+    if (prec == P64)
+        hipLaunchKernelGGL(k_norm2<double2>, dim3(nblocks), dim3(256), 0, s, (const double2 *)x, n, partial);
+    else
+        hipLaunchKernelGGL(k_norm2<float2>, dim3(nblocks), dim3(256), 0, s, (const float2 *)x, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s)
+{
+    const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    if (prec == P64)
+        hipLaunchKernelGGL(k_scale<double2>, dim3(nb), dim3(256), 0, s, (double2 *)x, n, alpha);
+    else
+        hipLaunchKernelGGL(k_scale<float2>, dim3(nb), dim3(256), 0, s, (float2 *)x, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 8;
+    const int nb = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    if (n) hipLaunchKernelGGL(k_copy8, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, (const uint2 *)src, (uint2 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace fdetd

@@ -1,0 +1,762 @@
+// Host runtime of the FDETD library: plans, scratch ownership, the per-step launch sequence, hipGraph
+// capture of the time loop, and the C-ABI declared in include/fdetd.h.
+//
+// One step of a Maxwell problem (section 2.1 midpoint solution, section 2.5 algorithm) is evaluated as a
+// Horner recurrence with the source folded in:
+//     psi' = sum_n (dt^n/n!) H^n (psi - dt 2^-n Jbar) = v_0,
+//     v_N = w_N,  v_n = w_n + dt/(n+1) H v_{n+1},  w_n = psi - dt 2^-n Jbar,
+// the same polynomial as T_N(dt H) psi - dt T_N(dt H/2) Jbar with N instead of 2N applications of H.
+// The first stage forms w_N while loading psi, intermediate v_n ping-pong between two plan buffers and
+// the last stage writes psi in place.  The envelope step is the same recurrence without source.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdetd.h"
+#include "fdetd_internal.h"
+
+using namespace fdetd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Prob {
+    fdetd_problem_desc d{};
+    int nd = 0;
+    size_t cells = 0;           // nz * nr
+    void *buf[2] = {nullptr, nullptr};  // stage vectors (6 planes Maxwell, 2 planes envelope)
+    void *jbar = nullptr;       // staggered J_rho plane
+    float *lo = nullptr;        // FP32C compensation words (6 or 2 planes of float2)
+    double *rinv_p = nullptr, *rinv_s = nullptr, *m2rinv2 = nullptr;
+    double a[kMaxND], s[kMaxND], d1[kMaxND], d2[kMaxND + 1], c[kMaxND];
+    const void *last_state = nullptr;   // psi (or a) of the previous call, for the FP32C reset rule
+    double rho_hat = 0.0;
+};
+
+}  // namespace
+
+struct fdetd_plan_s {
+    int precision = FDETD_FP64;
+    uint32_t flags = 0;
+    int kind = FDETD_MAXWELL;
+    hipStream_t stream = nullptr;
+    std::vector<Prob> probs;
+    std::string err;
+    fdetd_plan_info info{};
+    // cached graph of the last captured call
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void *> gkey;
+    // FDETD_PLAN_PROFILE: event pairs around stage kernels, pending until the next query
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<double> ev_bytes;
+};
+
+namespace {
+
+int fail(fdetd_plan_t p, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (p)
+        p->err = buf;
+    else
+        g_last_error = buf;
+    return code;
+}
+
+#define HIPCHK(p, call)                                                                             \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail((p), e_ == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                          \
+    } while (0)
+
+size_t elem_bytes(int precision) { return precision == FDETD_FP64 ? 16 : 8; }
+int prec_code(int precision) { return precision == FDETD_FP64 ? P64 : P32; }
+int planes(int kind) { return kind == FDETD_MAXWELL ? 6 : 2; }
+
+double parity_mS(int m) { return (m % 2 == 0) ? 1.0 : -1.0; }
+
+// rows whose stencils reach the axis region: arithmetic kept in FP64 for FP32C
+int axis_rows(const Prob &q) { return 2 * q.nd; }
+
+void free_prob(Prob &q)
+{
+    for (void *b : q.buf)
+        if (b) (void)hipFree(b);
+    if (q.jbar) (void)hipFree(q.jbar);
+    if (q.lo) (void)hipFree(q.lo);
+    if (q.rinv_p) (void)hipFree(q.rinv_p);
+    if (q.rinv_s) (void)hipFree(q.rinv_s);
+    if (q.m2rinv2) (void)hipFree(q.m2rinv2);
+    q = Prob{};
+}
+
+void fill_maxwell_args(const fdetd_plan_t P, const Prob &q, MaxwellStageArgs &A)
+{
+    std::memset(&A, 0, sizeof A);
+    A.rinv_p = q.rinv_p;
+    A.rinv_s = q.rinv_s;
+    A.dr = q.d.dr;
+    A.pS = parity_mS(q.d.m);
+    A.nz = q.d.nz;
+    A.nr = q.d.nr;
+    A.m = q.d.m;
+    A.axis_rows = P->precision == FDETD_FP32C ? axis_rows(q) : 0;
+    for (int j = 0; j < q.nd; ++j) {
+        A.az[j] = q.a[j] / q.d.dz;
+        A.ar[j] = q.a[j] / q.d.dr;
+        A.cax[j] = q.c[j];
+    }
+}
+
+void fill_envelope_args(const fdetd_plan_t P, const Prob &q, EnvelopeStageArgs &A)
+{
+    std::memset(&A, 0, sizeof A);
+    A.rinv_p = q.rinv_p;
+    A.m2rinv2 = q.m2rinv2;
+    A.k0 = q.d.k0;
+    A.pS = parity_mS(q.d.m);
+    A.nz = q.d.nz;
+    A.nr = q.d.nr;
+    A.axis_rows = P->precision == FDETD_FP32C ? axis_rows(q) : 0;
+    for (int j = 0; j <= q.nd; ++j) {
+        A.bz[j] = q.d2[j] / (q.d.dz * q.d.dz);
+        A.br[j] = q.d2[j] / (q.d.dr * q.d.dr);
+    }
+    for (int j = 0; j < q.nd; ++j) {
+        A.dzc[j] = q.d1[j] / q.d.dz;
+        A.drc[j] = q.d1[j] / q.d.dr;
+    }
+}
+
+// FDETD_PLAN_PROFILE: record an event pair around the next stage kernel.
+int profile_begin(fdetd_plan_t P, double bytes)
+{
+    if (!(P->flags & FDETD_PLAN_PROFILE)) return FDETD_OK;
+    while (P->ev_pool.size() < P->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHK(P, hipEventCreate(&e));
+        P->ev_pool.push_back(e);
+    }
+    HIPCHK(P, hipEventRecord(P->ev_pool[P->ev_used], P->stream));
+    P->ev_bytes.push_back(bytes);
+    return FDETD_OK;
+}
+
+int profile_end(fdetd_plan_t P)
+{
+    if (!(P->flags & FDETD_PLAN_PROFILE)) return FDETD_OK;
+    HIPCHK(P, hipEventRecord(P->ev_pool[P->ev_used + 1], P->stream));
+    P->ev_used += 2;
+    return FDETD_OK;
+}
+
+// Zero fill of plan-owned words.  Called from fdetd_step / envelope_step before any graph capture, so
+// it never becomes a node of a captured graph.
+int zero_device(fdetd_plan_t P, void *ptr, size_t bytes)
+{
+    HIPCHK(P, hipMemsetAsync(ptr, 0, bytes, P->stream));
+    return FDETD_OK;
+}
+
+int enqueue_maxwell_step(fdetd_plan_t P, Prob &q, void *psi, const void *j, int last_step_of_call)
+{
+    const int prec = prec_code(P->precision);
+    const size_t eb = elem_bytes(P->precision);
+    const size_t plane_b = q.cells * eb;
+    const int N = q.d.taylor_order;
+    const double dt = q.d.dt;
+    MaxwellStageArgs A;
+    fill_maxwell_args(P, q, A);
+    A.psi = psi;
+    if (j) {
+        StaggerArgs S{};
+        S.jr = j;
+        S.out = q.jbar;
+        S.pA = -parity_mS(q.d.m);
+        S.nz = q.d.nz;
+        S.nr = q.d.nr;
+        for (int t = 0; t < q.nd; ++t) S.s[t] = q.s[t];
+        HIPCHK(P, launch_stagger_jr(prec, q.nd, S, P->stream));
+        A.has_src = 1;
+        A.jr = q.jbar;
+        A.jt = (const char *)j + plane_b;
+        A.jz = (const char *)j + 2 * plane_b;
+    }
+    const void *vin = psi;
+    for (int n = N - 1; n >= 0; --n) {
+        A.vin = vin;
+        A.first = (n == N - 1);
+        A.beta_in = -dt * std::ldexp(1.0, -N);
+        A.beta = -dt * std::ldexp(1.0, -n);
+        A.coef = dt / (n + 1);
+        const bool in_place = (n == 0) && (N > 1);
+        A.vout = in_place ? psi : q.buf[(N - 1 - n) & 1];
+        A.last_compensated = (n == 0) && P->precision == FDETD_FP32C;
+        A.lo = A.last_compensated ? q.lo : nullptr;
+        // algorithmic bytes: vin (6c) + psi (6c, the same data in the first stage) + Jbar (3c) + vout (6c)
+        double cvals = (A.first ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
+        double bytes = cvals * q.cells * eb + (A.last_compensated ? 2.0 * 6 * q.cells * 8 : 0.0);
+        int rc = profile_begin(P, bytes);
+        if (rc) return rc;
+        HIPCHK(P, launch_maxwell_stage(prec, q.nd, A, P->stream));
+        if ((rc = profile_end(P))) return rc;
+        vin = A.vout;
+    }
+    if (N == 1) HIPCHK(P, launch_copy(q.buf[0], psi, 6 * plane_b, P->stream));
+    if (last_step_of_call) {
+        AxisArgs X{};
+        X.psi = psi;
+        X.nz = q.d.nz;
+        X.nr = q.d.nr;
+        X.m = q.d.m;
+        for (int t = 0; t < q.nd; ++t) X.cax[t] = q.c[t];
+        HIPCHK(P, launch_axis_fix(prec, q.nd, X, P->stream));
+    }
+    return FDETD_OK;
+}
+
+int enqueue_envelope_step(fdetd_plan_t P, Prob &q, void *a, void *at, const void *chi)
+{
+    const int prec = prec_code(P->precision);
+    const size_t plane_b = q.cells * elem_bytes(P->precision);
+    const int N = q.d.taylor_order;
+    EnvelopeStageArgs A;
+    fill_envelope_args(P, q, A);
+    A.psi_a = a;
+    A.psi_t = at;
+    A.chi = chi;
+    const void *ia = a, *it = at;
+    for (int n = N - 1; n >= 0; --n) {
+        A.vin_a = ia;
+        A.vin_t = it;
+        A.coef = q.d.dt / (n + 1);
+        void *ob = q.buf[(N - 1 - n) & 1];
+        const bool in_place = (n == 0) && (N > 1);
+        A.out_a = in_place ? a : ob;
+        A.out_t = in_place ? at : (char *)ob + plane_b;
+        A.last_compensated = (n == 0) && P->precision == FDETD_FP32C;
+        A.lo_a = A.last_compensated ? q.lo : nullptr;
+        A.lo_t = A.last_compensated ? q.lo + 2 * q.cells : nullptr;
+        // algorithmic bytes: vin (2c) + psi (2c, the same data in the first stage) + chi + vout (2c)
+        const double cvals = (n == N - 1 ? 4.0 : 6.0) + 0.5;
+        const double bytes = cvals * plane_b + (A.last_compensated ? 2.0 * 2 * q.cells * 8 : 0.0);
+        int rc = profile_begin(P, bytes);
+        if (rc) return rc;
+        HIPCHK(P, launch_envelope_stage(prec, q.nd, A, P->stream));
+        if ((rc = profile_end(P))) return rc;
+        ia = A.out_a;
+        it = A.out_t;
+    }
+    if (N == 1) {
+        HIPCHK(P, launch_copy(q.buf[0], a, plane_b, P->stream));
+        HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at, plane_b, P->stream));
+    }
+    return FDETD_OK;
+}
+
+// Spectral radius of H by power iteration on -H^2 over a grid of at most 64 x 64 cells with the same
+// mode, orders and spacings (the extreme eigenvectors live at the grid scale and near the axis, both
+// present in the reduced grid).
+int estimate_rho(fdetd_plan_t P, Prob &q, double &rho)
+{
+    Prob r = q;  // shares coefficients; own small buffers below
+    r.d.nz = std::min(q.d.nz, 64);
+    r.d.nr = std::min(q.d.nr, 64);
+    r.cells = (size_t)r.d.nz * r.d.nr;
+    const int prec = prec_code(P->precision);
+    const size_t eb = elem_bytes(P->precision);
+    const int np = planes(P->kind);
+    const size_t n = np * r.cells;
+    void *x = nullptr, *t = nullptr, *y = nullptr, *zero = nullptr, *chi = nullptr;
+    double *part = nullptr, *rp = nullptr, *rs = nullptr, *m2 = nullptr;
+    const int nblk = 64;
+    int rc = FDETD_OK;
+    auto cleanup = [&]() {
+        for (void *b : {x, t, y, zero, chi, (void *)part, (void *)rp, (void *)rs, (void *)m2})
+            if (b) (void)hipFree(b);
+    };
+    do {
+        hipError_t e = hipSuccess;
+        if ((e = hipMalloc(&x, n * eb)) || (e = hipMalloc(&t, n * eb)) || (e = hipMalloc(&y, n * eb)) ||
+            (e = hipMalloc(&zero, n * eb)) || (e = hipMalloc(&chi, r.cells * eb)) ||
+            (e = hipMalloc(&part, nblk * sizeof(double))) || (e = hipMalloc(&rp, r.d.nr * sizeof(double))) ||
+            (e = hipMalloc(&rs, r.d.nr * sizeof(double))) || (e = hipMalloc(&m2, r.d.nr * sizeof(double)))) {
+            rc = fail(P, FDETD_E_NOMEM, "stability estimate: %s", hipGetErrorString(e));
+            break;
+        }
+        std::vector<double> hr(r.d.nr), hs(r.d.nr), hm(r.d.nr);
+        for (int k = 0; k < r.d.nr; ++k) {
+            const double rho_k = (k + 0.5) * r.d.dr;
+            hr[k] = 1.0 / rho_k;
+            hs[k] = k ? 1.0 / (k * r.d.dr) : 0.0;
+            hm[k] = (double)r.d.m * r.d.m / (rho_k * rho_k);
+        }
+        if (hipMemcpy(rp, hr.data(), r.d.nr * 8, hipMemcpyHostToDevice) ||
+            hipMemcpy(rs, hs.data(), r.d.nr * 8, hipMemcpyHostToDevice) ||
+            hipMemcpy(m2, hm.data(), r.d.nr * 8, hipMemcpyHostToDevice) || hipMemset(zero, 0, n * eb) ||
+            hipMemset(chi, 0, r.cells * eb)) {
+            rc = fail(P, FDETD_E_HIP, "stability estimate: copy failed");
+            break;
+        }
+        r.rinv_p = rp;
+        r.rinv_s = rs;
+        r.m2rinv2 = m2;
+        // deterministic pseudo-random start vector (splitmix64 stream)
+        std::vector<double> h(2 * n);
+        uint64_t st = 0x9E3779B97F4A7C15ull ^ (uint64_t)q.d.m;
+        for (auto &v : h) {
+            uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            v = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+        }
+        if (P->precision == FDETD_FP64) {
+            if (hipMemcpy(x, h.data(), n * 16, hipMemcpyHostToDevice)) { rc = FDETD_E_HIP; break; }
+        } else {
+            std::vector<float> hf(h.begin(), h.end());
+            if (hipMemcpy(x, hf.data(), n * 8, hipMemcpyHostToDevice)) { rc = FDETD_E_HIP; break; }
+        }
+        auto applyH = [&](const void *in, void *out) -> int {
+            if (P->kind == FDETD_MAXWELL) {
+                MaxwellStageArgs A;
+                fill_maxwell_args(P, r, A);
+                A.vin = in;
+                A.psi = zero;
+                A.vout = out;
+                A.coef = 1.0;
+                HIPCHK(P, launch_maxwell_stage(prec, r.nd, A, P->stream));
+            } else {
+                EnvelopeStageArgs A;
+                fill_envelope_args(P, r, A);
+                A.vin_a = in;
+                A.vin_t = (const char *)in + r.cells * eb;
+                A.psi_a = zero;
+                A.psi_t = zero;
+                A.chi = chi;
+                A.out_a = out;
+                A.out_t = (char *)out + r.cells * eb;
+                A.coef = 1.0;
+                HIPCHK(P, launch_envelope_stage(prec, r.nd, A, P->stream));
+            }
+            return FDETD_OK;
+        };
+        auto norm = [&](const void *v, double &out) -> int {
+            HIPCHK(P, launch_norm2(prec, v, n, part, nblk, P->stream));
+            std::vector<double> hp(nblk);
+            HIPCHK(P, hipMemcpyAsync(hp.data(), part, nblk * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+            HIPCHK(P, hipStreamSynchronize(P->stream));
+            out = 0.0;
+            for (double v2 : hp) out += v2;
+            out = std::sqrt(out);
+            return FDETD_OK;
+        };
+        double nx = 0.0;
+        if ((rc = norm(x, nx))) break;
+        HIPCHK(P, launch_scale(prec, x, n, 1.0 / nx, P->stream));
+        double lam = 0.0;
+        for (int it = 0; it < 60 && rc == FDETD_OK; ++it) {
+            if ((rc = applyH(x, t)) || (rc = applyH(t, y))) break;
+            double ny = 0.0;
+            if ((rc = norm(y, ny))) break;
+            lam = ny;  // |H^2 x| with |x| = 1
+            if (!(ny > 0.0) || !std::isfinite(ny)) break;
+            HIPCHK(P, launch_scale(prec, y, n, 1.0 / ny, P->stream));
+            std::swap(x, y);
+        }
+        rho = std::sqrt(lam);
+    } while (0);
+    (void)hipStreamSynchronize(P->stream);
+    cleanup();
+    return rc;
+}
+
+int validate(const fdetd_problem_desc &d, int idx)
+{
+    const int nd = d.fd_order / 2;
+    if (d.kind != FDETD_MAXWELL && d.kind != FDETD_ENVELOPE)
+        return fail(nullptr, FDETD_E_ARG, "problem %d: unknown kind %d", idx, d.kind);
+    if (d.fd_order < 2 || d.fd_order > 2 * kMaxND || (d.fd_order & 1))
+        return fail(nullptr, FDETD_E_ARG, "problem %d: fd_order %d not even in [2, 32]", idx, d.fd_order);
+    if (d.nz < 2 * nd + 1 || d.nr < nd + 1)
+        return fail(nullptr, FDETD_E_ARG, "problem %d: grid %d x %d too small for order %d (need nz >= %d, nr >= %d)",
+                    idx, d.nz, d.nr, d.fd_order, 2 * nd + 1, nd + 1);
+    if ((int64_t)d.nz * d.nr > (int64_t)1 << 31)
+        return fail(nullptr, FDETD_E_ARG, "problem %d: more than 2^31 cells", idx);
+    if (d.m < 0 || d.m > 64) return fail(nullptr, FDETD_E_ARG, "problem %d: mode %d not in [0, 64]", idx, d.m);
+    if (d.taylor_order < 1 || d.taylor_order > 32)
+        return fail(nullptr, FDETD_E_ARG, "problem %d: taylor_order %d not in [1, 32]", idx, d.taylor_order);
+    if (!(d.dz > 0) || !(d.dr > 0) || !(d.dt > 0) || !std::isfinite(d.dz + d.dr + d.dt))
+        return fail(nullptr, FDETD_E_ARG, "problem %d: dz, dr, dt must be finite and > 0", idx);
+    if (d.kind == FDETD_ENVELOPE && !std::isfinite(d.k0))
+        return fail(nullptr, FDETD_E_ARG, "problem %d: k0 not finite", idx);
+    return FDETD_OK;
+}
+
+bool aligned(const void *p) { return p && ((uintptr_t)p % 16) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int fdetd_coefficients(int32_t which, int32_t nd, double *out)
+{
+    if (!out || !make_coefficients(which, nd, out))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_coefficients: bad table %d or nd %d", which, nd);
+    return FDETD_OK;
+}
+
+double fdetd_taylor_stability_bound(int32_t taylor_order) { return taylor_stability_bound(taylor_order); }
+
+const char *fdetd_last_error(fdetd_plan_t plan) { return plan ? plan->err.c_str() : g_last_error.c_str(); }
+
+void fdetd_destroy(fdetd_plan_t plan)
+{
+    if (!plan) return;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+    for (auto &q : plan->probs) free_prob(q);
+    delete plan;
+}
+
+int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precision, uint32_t flags,
+               void *stream, fdetd_plan_t *out)
+{
+    if (!out) return fail(nullptr, FDETD_E_ARG, "fdetd_plan: out is NULL");
+    *out = nullptr;
+    if (!probs || n_probs < 1) return fail(nullptr, FDETD_E_ARG, "fdetd_plan: need at least one problem");
+    if (precision != FDETD_FP64 && precision != FDETD_FP32C)
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown precision %d", precision);
+    for (int p = 0; p < n_probs; ++p) {
+        int rc = validate(probs[p], p);
+        if (rc) return rc;
+        if (probs[p].kind != probs[0].kind)
+            return fail(nullptr, FDETD_E_ARG, "fdetd_plan: all problems of a plan must have the same kind");
+    }
+    if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: graph capture needs a non-default stream");
+    if ((flags & FDETD_PLAN_USE_GRAPH) && (flags & FDETD_PLAN_PROFILE))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_PROFILE times eager launches only");
+    fdetd_plan_t P = new (std::nothrow) fdetd_plan_s;
+    if (!P) return fail(nullptr, FDETD_E_NOMEM, "fdetd_plan: host allocation failed");
+    P->precision = precision;
+    P->flags = flags;
+    P->kind = probs[0].kind;
+    P->stream = (hipStream_t)stream;
+    P->probs.resize(n_probs);
+    const size_t eb = elem_bytes(precision);
+    const int np = planes(P->kind);
+    int64_t scratch = 0, bytes_step = 0, cells = 0, launches = 0;
+    double worst = 0.0, margin = 0.0;
+    int rc = FDETD_OK;
+    for (int p = 0; p < n_probs && rc == FDETD_OK; ++p) {
+        Prob &q = P->probs[p];
+        q.d = probs[p];
+        q.nd = q.d.fd_order / 2;
+        q.cells = (size_t)q.d.nz * q.d.nr;
+        make_coefficients(COEF_STAGGERED, q.nd, q.a);
+        make_coefficients(COEF_HALFSHIFT, q.nd, q.s);
+        make_coefficients(COEF_CENTRED_D1, q.nd, q.d1);
+        make_coefficients(COEF_CENTRED_D2, q.nd, q.d2);
+        make_coefficients(COEF_AXIS, q.nd, q.c);
+        hipError_t e = hipSuccess;
+        const size_t vec_b = np * q.cells * eb;
+        if ((e = hipMalloc(&q.buf[0], vec_b)) || (e = hipMalloc(&q.buf[1], vec_b)) ||
+            (P->kind == FDETD_MAXWELL && (e = hipMalloc(&q.jbar, q.cells * eb))) ||
+            (precision == FDETD_FP32C && (e = hipMalloc((void **)&q.lo, np * q.cells * sizeof(float) * 2))) ||
+            (e = hipMalloc((void **)&q.rinv_p, q.d.nr * sizeof(double))) ||
+            (e = hipMalloc((void **)&q.rinv_s, q.d.nr * sizeof(double))) ||
+            (e = hipMalloc((void **)&q.m2rinv2, q.d.nr * sizeof(double)))) {
+            rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
+                      hipGetErrorString(e));
+            break;
+        }
+        scratch += 2 * vec_b + (P->kind == FDETD_MAXWELL ? q.cells * eb : 0) +
+                   (precision == FDETD_FP32C ? np * q.cells * 8 : 0) + 3 * q.d.nr * 8;
+        std::vector<double> hr(q.d.nr), hs(q.d.nr), hm(q.d.nr);
+        for (int k = 0; k < q.d.nr; ++k) {
+            const double rho_k = (k + 0.5) * q.d.dr;
+            hr[k] = 1.0 / rho_k;
+            hs[k] = k ? 1.0 / (k * q.d.dr) : 0.0;
+            hm[k] = (double)q.d.m * q.d.m / (rho_k * rho_k);
+        }
+        if ((e = hipMemcpy(q.rinv_p, hr.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(q.rinv_s, hs.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(q.m2rinv2, hm.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
+            (precision == FDETD_FP32C && (e = hipMemset(q.lo, 0, np * q.cells * 8)))) {
+            rc = fail(P, FDETD_E_HIP, "fdetd_plan: problem %d: %s", p, hipGetErrorString(e));
+            break;
+        }
+        const int N = q.d.taylor_order;
+        cells += q.cells;
+        if (P->kind == FDETD_MAXWELL) {
+            // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w
+            bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
+            launches += N + 2;
+        } else {
+            // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
+            bytes_step += (int64_t)q.cells * (eb * 6 + eb / 2) * N + (precision == FDETD_FP32C ? q.cells * 2 * 8 * 2 : 0);
+            launches += N;
+        }
+        if (!(flags & FDETD_PLAN_SKIP_STABILITY)) {
+            double rho = 0.0;
+            if ((rc = estimate_rho(P, q, rho))) break;
+            q.rho_hat = rho;
+            const double xn = taylor_stability_bound(N);
+            const double x = q.d.dt * rho;
+            worst = std::max(worst, x);
+            const double mg = x > 0 ? xn / x : 1e300;
+            margin = (p == 0) ? mg : std::min(margin, mg);
+            if (x * 1.02 >= xn) {
+                rc = fail(P, FDETD_E_UNSTABLE,
+                          "problem %d: dt * rho(H) = %.4f (rho estimated %.6g) exceeds the Taylor order-%d bound %.4f / 1.02",
+                          p, x, rho, N, xn);
+                break;
+            }
+        }
+    }
+    if (rc != FDETD_OK) {
+        g_last_error = P->err;
+        fdetd_destroy(P);
+        return rc;
+    }
+    P->info.n_probs = n_probs;
+    P->info.precision = precision;
+    P->info.dt_rho_max = worst;
+    P->info.stability_margin = margin;
+    P->info.cells = cells;
+    P->info.bytes_per_step = bytes_step;
+    P->info.scratch_bytes = scratch;
+    P->info.launches_per_step = launches;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fail(P, FDETD_E_HIP, "fdetd_plan: %s", hipGetErrorString(e));
+        g_last_error = P->err;
+        fdetd_destroy(P);
+        return FDETD_E_HIP;
+    }
+    *out = P;
+    return FDETD_OK;
+}
+
+int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info)
+{
+    if (!plan || !info) return fail(plan, FDETD_E_ARG, "fdetd_query: NULL argument");
+    *info = plan->info;
+    info->profiled_launches = 0;
+    info->profiled_ms = 0.0;
+    info->profiled_bytes = 0.0;
+    if (plan->ev_used) {
+        HIPCHK(plan, hipStreamSynchronize(plan->stream));
+        for (size_t e = 0; e + 1 < plan->ev_used; e += 2) {
+            float ms = 0.f;
+            HIPCHK(plan, hipEventElapsedTime(&ms, plan->ev_pool[e], plan->ev_pool[e + 1]));
+            info->profiled_ms += ms;
+            info->profiled_bytes += plan->ev_bytes[e / 2];
+            info->profiled_launches += 1;
+        }
+        plan->ev_used = 0;
+        plan->ev_bytes.clear();
+    }
+    return FDETD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+struct StepCtx {
+    void *const *psi;
+    const void *const *j;
+    int64_t stride;
+    int n_steps;
+};
+struct EnvCtx {
+    void *const *a;
+    void *const *at;
+    const void *const *chi;
+    int64_t stride;
+    int n_steps;
+};
+
+int step_body(fdetd_plan_t P, void *vctx)
+{
+    StepCtx &c = *(StepCtx *)vctx;
+    const size_t eb = elem_bytes(P->precision);
+    for (int s = 0; s < c.n_steps; ++s)
+        for (size_t p = 0; p < P->probs.size(); ++p) {
+            const void *j = c.j ? (const char *)c.j[p] + (size_t)(c.stride * s) * eb : nullptr;
+            int rc = enqueue_maxwell_step(P, P->probs[p], c.psi[p], j, s == c.n_steps - 1);
+            if (rc) return rc;
+        }
+    return FDETD_OK;
+}
+
+int env_body(fdetd_plan_t P, void *vctx)
+{
+    EnvCtx &c = *(EnvCtx *)vctx;
+    const size_t rb = elem_bytes(P->precision) / 2;
+    for (int s = 0; s < c.n_steps; ++s)
+        for (size_t p = 0; p < P->probs.size(); ++p) {
+            const void *chi = (const char *)c.chi[p] + (size_t)(c.stride * s) * rb;
+            int rc = enqueue_envelope_step(P, P->probs[p], c.a[p], c.at[p], chi);
+            if (rc) return rc;
+        }
+    return FDETD_OK;
+}
+}  // namespace
+
+// Replay a captured graph when the call repeats the previous one exactly; otherwise capture anew.
+namespace {
+int run_maybe_graph(fdetd_plan_t P, const std::vector<const void *> &key, int (*body)(fdetd_plan_t, void *),
+                           void *ctx)
+{
+    if (!(P->flags & FDETD_PLAN_USE_GRAPH)) return body(P, ctx);
+    if (!(P->gexec && key == P->gkey)) {
+        if (P->gexec) {
+            (void)hipGraphExecDestroy(P->gexec);
+            P->gexec = nullptr;
+        }
+        HIPCHK(P, hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+        int rc = body(P, ctx);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(P->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(P, FDETD_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            P->gexec = nullptr;
+            return fail(P, FDETD_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        P->gkey = key;
+    }
+    HIPCHK(P, hipGraphLaunch(P->gexec, P->stream));
+    return FDETD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+
+int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_stride,
+               int32_t n_steps)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_step: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_step: plan is not a Maxwell plan");
+    if (!psi || n_steps < 0 || j_step_stride < 0) return fail(plan, FDETD_E_ARG, "fdetd_step: bad arguments");
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        if (!aligned(psi[p])) return fail(plan, FDETD_E_ARG, "fdetd_step: psi[%zu] NULL or not 16-byte aligned", p);
+        if (j_half && !aligned(j_half[p]))
+            return fail(plan, FDETD_E_ARG, "fdetd_step: j_half[%zu] NULL or not 16-byte aligned", p);
+    }
+    if (n_steps == 0) return FDETD_OK;
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        Prob &q = plan->probs[p];
+        if (plan->precision == FDETD_FP32C && q.last_state != psi[p]) {
+            int rc = zero_device(plan, q.lo, 6 * q.cells * 8);
+            if (rc) return rc;
+        }
+        q.last_state = psi[p];
+    }
+    StepCtx c{psi, j_half, j_step_stride, n_steps};
+    std::vector<const void *> key;
+    key.push_back((const void *)(intptr_t)n_steps);
+    key.push_back((const void *)(intptr_t)j_step_stride);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        key.push_back(psi[p]);
+        key.push_back(j_half ? j_half[p] : nullptr);
+    }
+    return run_maybe_graph(plan, key, step_body, &c);
+}
+
+int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
+                  int64_t chi_step_stride, int32_t n_steps)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_step: NULL plan");
+    if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_step: plan is not an envelope plan");
+    if (!a || !a_tilde || !chi_half || n_steps < 0 || chi_step_stride < 0)
+        return fail(plan, FDETD_E_ARG, "envelope_step: bad arguments");
+    for (size_t p = 0; p < plan->probs.size(); ++p)
+        if (!aligned(a[p]) || !aligned(a_tilde[p]) || !aligned(chi_half[p]))
+            return fail(plan, FDETD_E_ARG, "envelope_step: pointer of problem %zu NULL or not 16-byte aligned", p);
+    if (n_steps == 0) return FDETD_OK;
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        Prob &q = plan->probs[p];
+        if (plan->precision == FDETD_FP32C && q.last_state != a[p]) {
+            int rc = zero_device(plan, q.lo, 2 * q.cells * 8);
+            if (rc) return rc;
+        }
+        q.last_state = a[p];
+    }
+    EnvCtx c{a, a_tilde, chi_half, chi_step_stride, n_steps};
+    std::vector<const void *> key;
+    key.push_back((const void *)(intptr_t)n_steps);
+    key.push_back((const void *)(intptr_t)chi_step_stride);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        key.push_back(a[p]);
+        key.push_back(a_tilde[p]);
+        key.push_back(chi_half[p]);
+    }
+    return run_maybe_graph(plan, key, env_body, &c);
+}
+
+int fdetd_export_state(fdetd_plan_t plan, void *host_blob, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(plan, FDETD_E_ARG, "fdetd_export_state: NULL argument");
+    const int np = planes(plan->kind);
+    size_t need = 0;
+    if (plan->precision == FDETD_FP32C)
+        for (auto &q : plan->probs) need += np * q.cells * 8;
+    if (!host_blob || *bytes < need) {
+        *bytes = need;
+        return host_blob ? fail(plan, FDETD_E_ARG, "fdetd_export_state: buffer too small") : FDETD_OK;
+    }
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    size_t off = 0;
+    for (auto &q : plan->probs) {
+        if (plan->precision != FDETD_FP32C) break;
+        HIPCHK(plan, hipMemcpy((char *)host_blob + off, q.lo, np * q.cells * 8, hipMemcpyDeviceToHost));
+        off += np * q.cells * 8;
+    }
+    *bytes = need;
+    return FDETD_OK;
+}
+
+int fdetd_import_state(fdetd_plan_t plan, const void *host_blob, size_t bytes)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_import_state: NULL plan");
+    const int np = planes(plan->kind);
+    size_t need = 0;
+    if (plan->precision == FDETD_FP32C)
+        for (auto &q : plan->probs) need += np * q.cells * 8;
+    if (bytes != need || (need && !host_blob))
+        return fail(plan, FDETD_E_ARG, "fdetd_import_state: expected %zu bytes, got %zu", need, bytes);
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    size_t off = 0;
+    for (auto &q : plan->probs) {
+        if (plan->precision != FDETD_FP32C) break;
+        HIPCHK(plan, hipMemcpy(q.lo, (const char *)host_blob + off, np * q.cells * 8, hipMemcpyHostToDevice));
+        off += np * q.cells * 8;
+    }
+    return FDETD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""Shared helpers of the GPU tests: device transfers, running the library and the oracle on the same
+seeded inputs, and the error measures the tolerances are stated in."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(got, want) -> float:
+    got = np.asarray(got)
+    want = np.asarray(want)
+    den = np.linalg.norm(want.ravel())
+    return float(np.linalg.norm((got - want).ravel()) / (den if den > 0 else 1.0))
+
+
+def grid_of(w, p) -> oracle.Grid:
+    return oracle.Grid(nz=w.nz[p], nr=w.nr[p], m=w.m[p], fd_order=w.fd_order[p], taylor_order=w.taylor_order,
+                       dz=w.dz, dr=w.dr, dt=w.dt, k0=w.k0)
+
+
+def dev(x, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def gpu_maxwell(w, psi0, J=None, steps=1, precision=0, flags=0, calls=1):
+    """Run the library on all problems of workload w.  J: None or per-problem [steps, 3, nr, nz].
+    `calls` splits the steps over that many fdetd_step calls (exercising per-call current offsets)."""
+    import torch
+    import paper_2605_12132_amd as F
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    psi = [dev(x, cd) for x in psi0]
+    jd = [dev(j, cd) for j in J] if J is not None else None
+    stream = torch.cuda.Stream() if flags & F.PLAN_USE_GRAPH else None
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
+    ctx = torch.cuda.stream(stream) if stream is not None else _null()
+    with ctx:
+        plan = F.Plan(w.problems(), precision=precision, flags=flags)
+        per = steps // calls
+        done = 0
+        for c in range(calls):
+            n = per if c < calls - 1 else steps - done
+            plan.step(psi, [j[done:] for j in jd] if jd is not None else None, n_steps=n)
+            done += n
+        torch.cuda.synchronize()
+        info = plan.query()
+        plan.close()
+    return [x.cpu().numpy().astype(np.complex128) for x in psi], info
+
+
+def oracle_maxwell(w, psi0, J=None, steps=1):
+    return [oracle.step(grid_of(w, p), psi0[p], None if J is None else J[p], steps) for p in range(w.n)]
+
+
+class _null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
+def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0):
+    import torch
+    import paper_2605_12132_amd as F
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    rd = torch.float64 if precision == F.FP64 else torch.float32
+    a = [dev(x, cd) for x in a0]
+    at = [dev(x, cd) for x in at0]
+    ch = [dev(x, rd) for x in chi]
+    stream = torch.cuda.Stream() if flags & F.PLAN_USE_GRAPH else None
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
+    ctx = torch.cuda.stream(stream) if stream is not None else _null()
+    with ctx:
+        plan = F.Plan(w.problems(), precision=precision, flags=flags)
+        plan.envelope_step(a, at, ch, n_steps=steps)
+        torch.cuda.synchronize()
+        info = plan.query()
+        plan.close()
+    return ([x.cpu().numpy().astype(np.complex128) for x in a], [x.cpu().numpy().astype(np.complex128) for x in at],
+            info)
+
+
+def oracle_envelope(w, a0, at0, chi, steps=1):
+    out = [oracle.envelope_step(grid_of(w, p), a0[p], at0[p], chi[p], steps) for p in range(w.n)]
+    return [o[0] for o in out], [o[1] for o in out]

@@ -1,0 +1,56 @@
+"""GPU parity of the laser-envelope propagator against the CPU FP64 oracle (relative L2 <= 1e-12 over
+(a, a~)), on the envelope-in-plasma workload at full size and on ragged small grids over many steps."""
+import numpy as np
+import pytest
+
+from helpers import gpu_envelope, log, oracle_envelope, rel_l2
+
+import paper_2605_12132_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def both(a, t):
+    return np.concatenate([np.ravel(a), np.ravel(t)])
+
+
+def test_envelope_plasma_full_size_graph():
+    w = I.envelope_plasma()
+    a0, at0 = I.envelope_initial(w)
+    chi = I.envelope_chi(w)
+    steps = 3
+    log("envelope full size, 3 steps, graph")
+    ga, gt, info = gpu_envelope(w, [a0], [at0], [chi], steps, flags=2)
+    assert 0 < info["dt_rho_max"] < 2.83
+    oa, ot = oracle_envelope(w, [a0], [at0], [chi], steps)
+    err = rel_l2(both(ga[0], gt[0]), both(oa[0], ot[0]))
+    log(f"  rel L2 {err:.3e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("m,order,N", [(0, 8, 4), (1, 4, 8), (2, 16, 6), (0, 32, 4), (3, 2, 12)])
+def test_envelope_small_many_steps(m, order, N):
+    dz = I.LAMBDA0 / 5
+    w = I.Workload("env_small", 1, [203], [41], [m], [order], N, dz, 0.2 * I.UM, 0.5 * dz, 40, seed=8,
+                   extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=10 * I.UM, chi0=1e-3, mod=0.05))
+    a0, at0 = I.envelope_initial(w)
+    rng = np.random.default_rng(m + order)
+    a0 = a0 + 1e-3 * (rng.uniform(-1, 1, a0.shape) + 1j * rng.uniform(-1, 1, a0.shape))
+    chi = I.envelope_chi(w)
+    log(f"envelope small m={m} order={order} N={N}")
+    ga, gt, _ = gpu_envelope(w, [a0], [at0], [chi], w.steps, flags=1)
+    oa, ot = oracle_envelope(w, [a0], [at0], [chi], w.steps)
+    assert rel_l2(both(ga[0], gt[0]), both(oa[0], ot[0])) < 1e-12
+
+
+def test_envelope_single_stage_and_minimal_grid():
+    for order in (2, 8, 32):
+        nd = order // 2
+        w = I.Workload("env_min", 1, [2 * nd + 1], [nd + 1], [0], [order], 1, 0.5, 0.7, 0.05, 1)
+        rng = np.random.default_rng(order)
+        a0 = rng.uniform(-1, 1, (nd + 1, 2 * nd + 1)) + 1j * rng.uniform(-1, 1, (nd + 1, 2 * nd + 1))
+        at0 = rng.uniform(-1, 1, a0.shape) + 1j * rng.uniform(-1, 1, a0.shape)
+        chi = rng.uniform(0, 0.01, a0.shape)
+        ga, gt, _ = gpu_envelope(w, [a0], [at0], [chi], 1, flags=1)
+        oa, ot = oracle_envelope(w, [a0], [at0], [chi], 1)
+        assert rel_l2(both(ga[0], gt[0]), both(oa[0], ot[0])) < 1e-13, order
