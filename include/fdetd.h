@@ -116,22 +116,23 @@ FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32
  *           across steps (export/import with fdetd_export_state / fdetd_import_state).  The
  *           compensation is reset to zero whenever a psi pointer differs from the previous call's.
  *   j_half  NULL (no current) or n_probs device pointers to 3-plane currents at t + dt/2.
- *   j_step_stride  elements (complex values) between the currents of consecutive steps; step s uses
- *           j_half[p] + s * j_step_stride; 0 reuses one current for all steps.
+ *   j_step_blocks  distance between the currents of consecutive steps, in 3-plane blocks of that
+ *           problem: step s uses the block starting at j_half[p] + s * j_step_blocks * 3 * nr_p * nz_p
+ *           complex values (1: one block per step stored back to back; 0: one current for all steps).
  *   n_steps >= 0.
  * Enqueue only.  Error (nothing enqueued) on NULL or misaligned pointers or a plan of the wrong kind. */
-FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_stride,
+FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_blocks,
                int32_t n_steps);
 
 /* Advance every envelope problem by n_steps of psi_a(t + dt) = T_N(dt H_a(chi(t + dt/2))) psi_a(t)
  * (section 4.1 exponential solution, section 4.2 discrete operator with L_rho + L_z - m^2/rho^2 and the
  * centred D_z^(C), complex form of the envelope equation with +2 i k0 terms).
  *   a, a_tilde  n_probs device pointers to one plane each; updated in place.
- *   chi_half    n_probs device pointers to real [nr][nz] susceptibility planes; step s uses
- *               chi_half[p] + s * chi_step_stride (0: the same plane every step).  Must not be NULL.
+ *   chi_half    n_probs device pointers to real [nr][nz] susceptibility planes; step s uses the plane
+ *               at chi_half[p] + s * chi_step_planes * nr_p * nz_p (0: the same plane every step).
  * Enqueue only. */
 FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
-                  int64_t chi_step_stride, int32_t n_steps);
+                  int64_t chi_step_planes, int32_t n_steps);
 
 /* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
 FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);

@@ -67,6 +67,10 @@ class Problem:
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run paper_2605_12132_amd/build.py (hipcc, gfx950)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7 / libhsa-runtime64.so.1.  Loading
+    # torch first makes the library's dependencies resolve (by soname) to the copies torch already mapped,
+    # so device memory, streams and kernels all live in the same runtime.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, pp = C.c_void_p, C.POINTER(C.c_void_p)
     L.fdetd_plan.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.c_int32, C.c_uint32, vp, C.POINTER(vp)]
@@ -113,14 +117,14 @@ def fdetd_plan(problems: Sequence[Problem], precision: int = FP64, flags: int = 
     return out.value
 
 
-def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_stride: int = 0, n_steps: int = 1):
+def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_blocks: int = 0, n_steps: int = 1):
     rc = lib.fdetd_step(plan, _ptrs(psi_ptrs), _ptrs(j_ptrs) if j_ptrs is not None else None,
-                        j_step_stride, n_steps)
+                        j_step_blocks, n_steps)
     _check(rc, plan)
 
 
-def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_stride: int = 0, n_steps: int = 1):
-    rc = lib.envelope_step(plan, _ptrs(a_ptrs), _ptrs(at_ptrs), _ptrs(chi_ptrs), chi_step_stride, n_steps)
+def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_planes: int = 0, n_steps: int = 1):
+    rc = lib.envelope_step(plan, _ptrs(a_ptrs), _ptrs(at_ptrs), _ptrs(chi_ptrs), chi_step_planes, n_steps)
     _check(rc, plan)
 
 
@@ -199,12 +203,13 @@ class Plan:
         jp, stride = None, 0
         if j_half is not None:
             jp = [self._chk(x, (3, p.nr, p.nz), cd, "j_half") for x, p in zip(j_half, self.problems)]
-            if j_half[0].dim() == 4 and n_steps > 1:
+            dims = {x.dim() for x in j_half}
+            if len(dims) != 1 or dims - {3, 4}:
+                raise ValueError("j_half: all [3, nr, nz] or all [steps, 3, nr, nz]")
+            if 4 in dims and n_steps > 1:
                 if any(x.shape[0] < n_steps for x in j_half):
                     raise ValueError("j_half has fewer steps than n_steps")
-                stride = 3 * self.problems[0].nr * self.problems[0].nz
-                if any(3 * p.nr * p.nz != stride for p in self.problems):
-                    raise ValueError("per-step currents need equal grid sizes across problems")
+                stride = 1
         fdetd_step(self._h, pp, jp, stride, n_steps)
 
     def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):
@@ -215,12 +220,13 @@ class Plan:
         tp = [self._chk(x, (p.nr, p.nz), cd, "a_tilde") for x, p in zip(a_tilde, self.problems)]
         cp = [self._chk(x, (p.nr, p.nz), rd, "chi") for x, p in zip(chi, self.problems)]
         stride = 0
-        if chi[0].dim() == 3 and n_steps > 1:
+        dims = {x.dim() for x in chi}
+        if len(dims) != 1 or dims - {2, 3}:
+            raise ValueError("chi: all [nr, nz] or all [steps, nr, nz]")
+        if 3 in dims and n_steps > 1:
             if any(x.shape[0] < n_steps for x in chi):
                 raise ValueError("chi has fewer steps than n_steps")
-            stride = self.problems[0].nr * self.problems[0].nz
-            if any(p.nr * p.nz != stride for p in self.problems):
-                raise ValueError("per-step chi needs equal grid sizes across problems")
+            stride = 1
         envelope_step(self._h, ap, tp, cp, stride, n_steps)
 
     def query(self) -> dict:

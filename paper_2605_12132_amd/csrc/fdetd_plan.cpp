@@ -599,7 +599,8 @@ int step_body(fdetd_plan_t P, void *vctx)
     const size_t eb = elem_bytes(P->precision);
     for (int s = 0; s < c.n_steps; ++s)
         for (size_t p = 0; p < P->probs.size(); ++p) {
-            const void *j = c.j ? (const char *)c.j[p] + (size_t)(c.stride * s) * eb : nullptr;
+            const size_t block = 3 * P->probs[p].cells;
+            const void *j = c.j ? (const char *)c.j[p] + (size_t)(c.stride * s) * block * eb : nullptr;
             int rc = enqueue_maxwell_step(P, P->probs[p], c.psi[p], j, s == c.n_steps - 1);
             if (rc) return rc;
         }
@@ -612,7 +613,7 @@ int env_body(fdetd_plan_t P, void *vctx)
     const size_t rb = elem_bytes(P->precision) / 2;
     for (int s = 0; s < c.n_steps; ++s)
         for (size_t p = 0; p < P->probs.size(); ++p) {
-            const void *chi = (const char *)c.chi[p] + (size_t)(c.stride * s) * rb;
+            const void *chi = (const char *)c.chi[p] + (size_t)(c.stride * s) * P->probs[p].cells * rb;
             int rc = enqueue_envelope_step(P, P->probs[p], c.a[p], c.at[p], chi);
             if (rc) return rc;
         }
@@ -656,12 +657,12 @@ int run_maybe_graph(fdetd_plan_t P, const std::vector<const void *> &key, int (*
 extern "C" {
 
 
-int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_stride,
+int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_blocks,
                int32_t n_steps)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_step: NULL plan");
     if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_step: plan is not a Maxwell plan");
-    if (!psi || n_steps < 0 || j_step_stride < 0) return fail(plan, FDETD_E_ARG, "fdetd_step: bad arguments");
+    if (!psi || n_steps < 0 || j_step_blocks < 0) return fail(plan, FDETD_E_ARG, "fdetd_step: bad arguments");
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         if (!aligned(psi[p])) return fail(plan, FDETD_E_ARG, "fdetd_step: psi[%zu] NULL or not 16-byte aligned", p);
         if (j_half && !aligned(j_half[p]))
@@ -676,10 +677,10 @@ int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, i
         }
         q.last_state = psi[p];
     }
-    StepCtx c{psi, j_half, j_step_stride, n_steps};
+    StepCtx c{psi, j_half, j_step_blocks, n_steps};
     std::vector<const void *> key;
     key.push_back((const void *)(intptr_t)n_steps);
-    key.push_back((const void *)(intptr_t)j_step_stride);
+    key.push_back((const void *)(intptr_t)j_step_blocks);
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         key.push_back(psi[p]);
         key.push_back(j_half ? j_half[p] : nullptr);
@@ -688,11 +689,11 @@ int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, i
 }
 
 int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
-                  int64_t chi_step_stride, int32_t n_steps)
+                  int64_t chi_step_planes, int32_t n_steps)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_step: NULL plan");
     if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_step: plan is not an envelope plan");
-    if (!a || !a_tilde || !chi_half || n_steps < 0 || chi_step_stride < 0)
+    if (!a || !a_tilde || !chi_half || n_steps < 0 || chi_step_planes < 0)
         return fail(plan, FDETD_E_ARG, "envelope_step: bad arguments");
     for (size_t p = 0; p < plan->probs.size(); ++p)
         if (!aligned(a[p]) || !aligned(a_tilde[p]) || !aligned(chi_half[p]))
@@ -706,10 +707,10 @@ int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const
         }
         q.last_state = a[p];
     }
-    EnvCtx c{a, a_tilde, chi_half, chi_step_stride, n_steps};
+    EnvCtx c{a, a_tilde, chi_half, chi_step_planes, n_steps};
     std::vector<const void *> key;
     key.push_back((const void *)(intptr_t)n_steps);
-    key.push_back((const void *)(intptr_t)chi_step_stride);
+    key.push_back((const void *)(intptr_t)chi_step_planes);
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         key.push_back(a[p]);
         key.push_back(a_tilde[p]);

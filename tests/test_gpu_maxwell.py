@@ -128,11 +128,9 @@ def test_batched_equals_single_bitwise_and_graph_equals_eager():
     J = [random_current(w, 0, 2, rng) for w in ws]
     batch = I.Workload("mix", 0, [w.nz[0] for w in ws], [w.nr[0] for w in ws], [w.m[0] for w in ws],
                        [w.fd_order[0] for w in ws], 8, ws[0].dz, ws[0].dr, ws[0].dt, 2)
-    with pytest.raises(ValueError):
-        gpu_maxwell(batch, psi0, J, 2)  # per-step currents of unequal grids need separate calls
-    got_b, _ = gpu_maxwell(batch, psi0, [j[:1] for j in J], 1, flags=1)
+    got_b, _ = gpu_maxwell(batch, psi0, J, 2, flags=1)
     for p, w in enumerate(ws):
-        got_s, _ = gpu_maxwell(w, [psi0[p]], [J[p][:1]], 1, flags=1)
+        got_s, _ = gpu_maxwell(w, [psi0[p]], [J[p]], 2, flags=1)
         assert np.array_equal(got_b[p], got_s[0])
     eager, _ = gpu_maxwell(ws[2], [psi0[2]], [J[2]], 2, flags=1)
     graph, _ = gpu_maxwell(ws[2], [psi0[2]], [J[2]], 2, flags=3)
@@ -154,3 +152,11 @@ def test_axis_slots_ignored_and_zero_steps():
     assert np.array_equal(a[0], b[0])
     c, _ = gpu_maxwell(w, [psi0], J, 0, flags=1)
     assert np.array_equal(c[0], psi0)
+
+
+def test_single_hip_runtime_in_process():
+    import torch  # noqa: F401
+    import paper_2605_12132_amd  # noqa: F401
+    maps = open("/proc/self/maps").read()
+    hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(hip) == 1, hip
