@@ -114,7 +114,8 @@ FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32
  *           FDETD_FP32C: float2 planes holding the rounded state; the plan keeps one float compensation
  *           word per real value so that the stored state plus compensation carries ~2x float precision
  *           across steps (export/import with fdetd_export_state / fdetd_import_state).  The
- *           compensation is reset to zero whenever a psi pointer differs from the previous call's.
+ *           compensation is reset to zero whenever a psi pointer differs from the previous call's,
+ *           except on the first call after fdetd_import_state, which adopts the imported words.
  *   j_half  NULL (no current) or n_probs device pointers to 3-plane currents at t + dt/2.
  *   j_step_blocks  distance between the currents of consecutive steps, in 3-plane blocks of that
  *           problem: step s uses the block starting at j_half[p] + s * j_step_blocks * 3 * nr_p * nz_p
@@ -137,8 +138,9 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
 /* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
 FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);
 
-/* FP32C compensation words of all problems (bytes = fdetd_query().scratch needed: pass *bytes = 0 to
- * query the size).  FDETD_FP64 plans have no state (size 0).  Synchronises the stream. */
+/* FP32C compensation words of all problems, problem after problem, 8 bytes per complex value (pass
+ * host_blob = NULL to get the size in *bytes).  FDETD_FP64 plans have no state (size 0).  Export
+ * synchronises the stream; after import, the next step call keeps the imported words for its pointers. */
 FDETD_API int fdetd_export_state(fdetd_plan_t plan, void *host_blob, size_t *bytes);
 FDETD_API int fdetd_import_state(fdetd_plan_t plan, const void *host_blob, size_t bytes);
 

@@ -17,7 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libfdetd.so")
 
-SOURCES = ["fdetd_kernels.hip", "fdetd_plan.cpp", "fdetd_coeffs.cpp"]
+# (source, object name, extra defines): the row-marching kernels are instantiated per range of the stencil
+# half width N_D in separate compiler processes
+ND_RANGES = [(1, 3), (4, 6), (7, 8), (9, 10), (11, 12), (13, 14), (15, 15), (16, 16)]
+SOURCES = ([("fdetd_march.hip", f"fdetd_march_nd{lo}_{hi}", [f"-DFDETD_ND_LO={lo}", f"-DFDETD_ND_HI={hi}"])
+            for lo, hi in ND_RANGES]
+           + [(f, f, []) for f in ("fdetd_kernels.hip", "fdetd_plan.cpp", "fdetd_coeffs.cpp", "fdetd_dispatch.cpp")])
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -32,9 +37,10 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON]
+def _compile(entry) -> str:
+    src, name, defines = entry
+    obj = os.path.join(OUT_DIR, name + ".o")
+    cmd = [_hipcc(), *COMMON, *defines]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", *DEVICE]
     else:
@@ -48,8 +54,12 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 4)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
+    for stale in os.listdir(OUT_DIR):
+        if stale.endswith(".o") and os.path.join(OUT_DIR, stale) not in objs:
+            os.remove(os.path.join(OUT_DIR, stale))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -74,6 +74,58 @@ struct AxisArgs {
     double cax[kMaxND];
 };
 
+// ---------------------------------------------------------------------------------------------------
+// Row-marching stage kernels (fdetd_march.hip), batched over problems of equal N_D, N and dt.
+// ---------------------------------------------------------------------------------------------------
+constexpr int kMaxBatch = 64;  // problems per launch (pointer arrays travel in the kernel arguments)
+
+// Static per-problem facts, uploaded once at plan time.
+struct ProbDesc {
+    int nz, nr, m, taylor;
+    int seg_rows, nseg, nstrip;              // tiling: strips of z columns x segments of seg_rows rows
+    int nseg_ax;                             // FP32C: leading segments (k0 < 2 N_D) run in FP64 arithmetic
+    int tile_begin, tile_begin_ax;           // first tile of this problem in the main / near-axis launch
+    size_t plane;                            // nz * nr
+    double dr, pS, k0;
+    void *buf[2];                            // ping-pong stage vectors
+    const void *jbar;                        // staggered J_rho plane
+    float *lo;                               // FP32C compensation words
+    const double *rinv_p, *rinv_s, *m2rinv2;
+    double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
+    double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
+};
+
+// One launch: stage n of every problem in the batch.
+struct BatchArgs {
+    const ProbDesc *probs;  // device table (the batch's problems are consecutive entries)
+    int nprob, ntiles;
+    int n, N;               // stage index n (N-1 .. 0) and Taylor order N
+    int has_src, compensated;
+    int axis_launch;        // 1: the near-axis segments (FP64 arithmetic on FP32 storage), 0: the others
+    double beta_in, beta, coef;
+    const void *psi[kMaxBatch];  // Maxwell psi, or envelope a
+    const void *aux[kMaxBatch];  // Maxwell: current of this step (3 planes) or null; envelope: a_tilde
+    const void *chi[kMaxBatch];  // envelope: chi of this step
+};
+
+template <int ND>
+hipError_t march_maxwell_nd(int prec, const BatchArgs &a, hipStream_t s);  // one per N_D, in fdetd_march.hip
+template <int ND>
+hipError_t march_envelope_nd(int prec, const BatchArgs &a, hipStream_t s);
+#define FDETD_DECLARE_ND(N)                                                            \
+    template <>                                                                        \
+    hipError_t march_maxwell_nd<N>(int prec, const BatchArgs &a, hipStream_t s);       \
+    template <>                                                                        \
+    hipError_t march_envelope_nd<N>(int prec, const BatchArgs &a, hipStream_t s);
+FDETD_DECLARE_ND(1) FDETD_DECLARE_ND(2) FDETD_DECLARE_ND(3) FDETD_DECLARE_ND(4) FDETD_DECLARE_ND(5)
+FDETD_DECLARE_ND(6) FDETD_DECLARE_ND(7) FDETD_DECLARE_ND(8) FDETD_DECLARE_ND(9) FDETD_DECLARE_ND(10)
+FDETD_DECLARE_ND(11) FDETD_DECLARE_ND(12) FDETD_DECLARE_ND(13) FDETD_DECLARE_ND(14) FDETD_DECLARE_ND(15)
+FDETD_DECLARE_ND(16)
+#undef FDETD_DECLARE_ND
+hipError_t launch_maxwell_march(int prec, int nd, const BatchArgs &a, hipStream_t s);   // dispatch on nd
+hipError_t launch_envelope_march(int prec, int nd, const BatchArgs &a, hipStream_t s);
+int march_columns_per_wave(int prec);  // z columns covered by one wavefront (32 FP64, 64 FP32)
+
 hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s);
 hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s);
 hipError_t launch_stagger_jr(int prec, int nd, const StaggerArgs &a, hipStream_t s);

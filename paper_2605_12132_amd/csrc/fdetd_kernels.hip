@@ -1,10 +1,10 @@
-// gfx950 kernels of the FDETD field update and the envelope propagator (arXiv 2605.12132).
+// One-cell-per-thread gfx950 kernels: the operator application used by the plan-time power iteration
+// (k_maxwell_apply, k_envelope_apply), current staging, the axis rule, reductions and copies.
 //
 // Every kernel here is one banded-matrix sweep over a (z, rho) grid (section 2.2): lanes run along z
-// (z is the contiguous axis, so a wave's loads of one row are fully coalesced 1 KiB (FP64) / 512 B (FP32)
-// transactions), the four waves of a workgroup cover four consecutive rows, and neighbouring rows' loads
-// are shared through the L1/L2 caches.  The work is HBM-bound (about 1.3 flop per byte at FP64), so no
-// matrix cores are used.
+// (z is the contiguous axis, so a wave's loads of one row are coalesced), the four waves of a workgroup
+// cover four consecutive rows, and neighbouring rows' loads are shared through the L1/L2 caches.  The
+// time-stepping hot path uses the row-marching kernels of fdetd_march.hip instead.
 #include <hip/hip_runtime.h>
 
 #include "fdetd_internal.h"
@@ -210,7 +210,7 @@ __device__ __forceinline__ void maxwell_store(const MaxwellStageArgs &A, int k, 
 }
 
 template <typename V, int ND>
-__global__ __launch_bounds__(TZ *TR) void k_maxwell_stage(MaxwellStageArgs A)
+__global__ __launch_bounds__(TZ *TR) void k_maxwell_apply(MaxwellStageArgs A)
 {
     using R = typename storage<V>::R;
     const int i = blockIdx.x * TZ + threadIdx.x;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void envelope_cell(const EnvelopeStageArgs &A, int k,
 }
 
 template <typename V, int ND>
-__global__ __launch_bounds__(TZ *TR) void k_envelope_stage(EnvelopeStageArgs A)
+__global__ __launch_bounds__(TZ *TR) void k_envelope_apply(EnvelopeStageArgs A)
 {
     using R = typename storage<V>::R;
     const int i = blockIdx.x * TZ + threadIdx.x;
@@ -418,7 +418,7 @@ template <typename V, int ND>
 struct MaxwellL {
     static hipError_t go(const MaxwellStageArgs &a, dim3 g, dim3 b, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_maxwell_stage<V, ND>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_maxwell_apply<V, ND>), g, b, 0, s, a);
         return hipGetLastError();
     }
 };
@@ -426,7 +426,7 @@ template <typename V, int ND>
 struct EnvelopeL {
     static hipError_t go(const EnvelopeStageArgs &a, dim3 g, dim3 b, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_envelope_stage<V, ND>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_envelope_apply<V, ND>), g, b, 0, s, a);
         return hipGetLastError();
     }
 };

@@ -1,0 +1,851 @@
+// Row-marching gfx950 kernels of the FDETD Horner stage (Maxwell) and of the envelope stage.
+//
+// Layout of the work.  H_m = [[0, R], [-R, 0]] (section 2.1): the E part of H v reads only the B part of
+// v and vice versa, so one Horner stage splits into two independent halves (E outputs from B inputs,
+// B outputs from E inputs) that run as the two kinds of wavefront of one launch.  A wavefront owns a strip
+// of consecutive z columns and marches down a segment of rho rows:
+//   * FP64: lane pairs share a column (even lane: real part, odd lane: imaginary part), 32 columns per
+//     wave; FP32: one lane per column holds the whole complex value, 64 columns per wave.  Either way a
+//     row load of the strip is one coalesced 512-byte transaction and every stencil coefficient is real,
+//     so lanes only meet for the i*m/rho terms (one lane swap in FP64);
+//   * the two rho-stencilled inputs of its half live in a register window of 2 N_D rows that slides by
+//     one row per step: each input row is loaded once per segment (section 2.3 staggered D^(+-) and
+//     divergence D_div^(+-) along rho);
+//   * the two z-stencilled inputs of the current row are staged in a per-wave LDS row with an N_D-column
+//     halo on each side and read back at the 2 N_D tap offsets (section 2.3 D^(+-) along z);
+//   * rows below the axis and the axis value (section 2.4) only occur while the window is first filled,
+//     as wave-uniform branches.
+// Tiles are numbered problem by problem and handed out so that each XCD (with its own L2) receives a
+// contiguous range of them: neighbouring tiles, whose halos overlap, share an L2.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fdetd_internal.h"
+#include "fdetd_tiles.h"
+
+namespace fdetd {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;
+
+// The share of one complex value a lane holds: one part (K = 1, FP64 lane pairs) or both (K = 2).
+template <typename AR, int K>
+struct lv {
+    AR p[K];
+};
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> operator+(lv<AR, K> a, lv<AR, K> b)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) a.p[c] += b.p[c];
+    return a;
+}
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> operator-(lv<AR, K> a, lv<AR, K> b)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) a.p[c] -= b.p[c];
+    return a;
+}
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> operator*(AR s, lv<AR, K> a)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) a.p[c] *= s;
+    return a;
+}
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> fmav(AR s, lv<AR, K> a, lv<AR, K> acc)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc.p[c] = fma(s, a.p[c], acc.p[c]);
+    return acc;
+}
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> zero_lv()
+{
+    lv<AR, K> z;
+#pragma unroll
+    for (int c = 0; c < K; ++c) z.p[c] = (AR)0;
+    return z;
+}
+// i * s * x: (re, im) -> (-s im, s re); with lane pairs the partner lane holds the other part
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> times_i(AR s, lv<AR, K> x)
+{
+    lv<AR, K> r;
+    if constexpr (K == 2) {
+        r.p[0] = -s * x.p[1];
+        r.p[1] = s * x.p[0];
+    } else {
+        const AR other = __shfl_xor(x.p[0], 1, WAVE);
+        r.p[0] = (threadIdx.x & 1) ? s * other : -s * other;
+    }
+    return r;
+}
+
+template <typename V> struct scal;
+template <> struct scal<double2> { using R = double; };
+template <> struct scal<float2> { using R = float; };
+
+// Global-memory access through address-space-1 pointers.  The kernels' pointers come from a descriptor
+// table and the kernel arguments, so without the cast the compiler emits flat instructions, which also
+// count against the LDS/scalar wait counter and make every LDS wait drain the prefetched loads.
+#define FDETD_GLOBAL __attribute__((address_space(1)))
+template <typename T> struct ibits;  // an integer of the same size, to move T through global memory
+template <> struct ibits<double> { using I = unsigned long long; };
+template <> struct ibits<float2> { using I = unsigned long long; };
+template <> struct ibits<float> { using I = unsigned int; };
+template <typename T>
+__device__ __forceinline__ T gld(const void *p, size_t i)
+{
+    using I = typename ibits<T>::I;
+    return __builtin_bit_cast(T, ((const FDETD_GLOBAL I *)p)[i]);
+}
+template <typename T>
+__device__ __forceinline__ void gst(void *p, size_t i, T v)
+{
+    using I = typename ibits<T>::I;
+    ((FDETD_GLOBAL I *)p)[i] = __builtin_bit_cast(I, v);
+}
+// The descriptor table and the per-row tables are written by the host before the launch and only read
+// here: through the constant address space they become scalar loads the compiler may hoist, instead of
+// vector loads whose in-order wait counter would also wait for the prefetched rows.
+#define FDETD_CONST __attribute__((address_space(4)))
+using CDesc = const FDETD_CONST ProbDesc;
+__device__ __forceinline__ double cld(const double *p, int i) { return ((const FDETD_CONST double *)p)[i]; }
+
+// Storage access.  FP64 (double2 storage, K = 1): element = one double, index 2*(row*nz + col) + part.
+// FP32 (float2 storage, K = 2): element = one float2, index row*nz + col.
+template <typename V> struct elem;
+template <> struct elem<double2> {
+    using E = double;
+    static constexpr int S = 2;  // lanes per column
+    static constexpr int K = 1;
+};
+template <> struct elem<float2> {
+    using E = float2;
+    static constexpr int S = 1;
+    static constexpr int K = 2;
+};
+
+template <typename AR>
+__device__ __forceinline__ lv<AR, 1> to_lv(double e) { return lv<AR, 1>{{(AR)e}}; }
+template <typename AR>
+__device__ __forceinline__ lv<AR, 2> to_lv(float2 e) { return lv<AR, 2>{{(AR)e.x, (AR)e.y}}; }
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Wave-uniform facts of one tile of one problem in one stage.
+struct Ctx {
+    CDesc *D;
+    const void *vin, *psi;
+    void *vout;
+    const void *jr, *jt, *jz;  // Jbar planes (null without source)
+    int has_src, compensated;
+    double beta_in, beta, coef;
+};
+
+// Lane geometry: column i = i0 + lane / S, element offset of (row 0, column i, part) = eidx.
+template <typename V>
+struct Lane {
+    using T = elem<V>;
+    int lane, i, eidx;
+    bool col;
+    __device__ Lane(int i0, int nz)
+    {
+        lane = threadIdx.x;
+        i = i0 + lane / T::S;
+        col = i < nz;
+        const int ic = col ? i : nz - 1;  // clamped column: loads stay in bounds, values are masked
+        eidx = ic * T::S + lane % T::S;
+    }
+};
+
+template <typename V, typename AR>
+__device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const V *plane, int nz, int q, const Lane<V> &L)
+{
+    using E = typename elem<V>::E;
+    const E e = gld<E>(plane, (size_t)q * nz * elem<V>::S + L.eidx);
+    lv<AR, elem<V>::K> x = to_lv<AR>(e);
+    return L.col ? x : zero_lv<AR, elem<V>::K>();
+}
+
+// Store one output value: out = psi + inc (inc already holds beta*Jbar + coef*H v), or, in the last stage
+// of an FP32C step, the exact TwoSum of (psi_hi, lo + inc) into (psi_hi, lo).  psi_v / lo_v are the values
+// at the output position, loaded one row ahead.
+template <typename V, typename AR, bool COMP>
+__device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane<V> &L, lv<AR, elem<V>::K> inc,
+                                          bool zero_slot, typename elem<V>::E psi_v, float2 lo_v)
+{
+    using E = typename elem<V>::E;
+    constexpr int S = elem<V>::S;
+    CDesc &D = *A.D;
+    const size_t o = (size_t)c * D.plane * S + (size_t)k * D.nz * S + L.eidx;
+    if constexpr (S == 1) {
+        if constexpr (COMP) {
+            float sx, ex, sy, ey;
+            two_sum(psi_v.x, (float)(inc.p[0] + (AR)lo_v.x), sx, ex);
+            two_sum(psi_v.y, (float)(inc.p[1] + (AR)lo_v.y), sy, ey);
+            if (zero_slot) sx = sy = ex = ey = 0.f;
+            gst<float2>(A.vout, o, float2{sx, sy});
+            gst<float2>(D.lo, o, float2{ex, ey});
+            return;
+        }
+        float2 w{(float)((AR)psi_v.x + inc.p[0]), (float)((AR)psi_v.y + inc.p[1])};
+        if (zero_slot) w = float2{0.f, 0.f};
+        gst<float2>(A.vout, o, w);
+    } else {
+        double w = (double)((AR)psi_v + inc.p[0]);
+        if (zero_slot) w = 0.0;
+        gst<double>(A.vout, o, w);
+    }
+}
+
+// Raw element of (row q, this lane) of a 6-plane vector's component c, and the compensation word.
+template <typename V>
+__device__ __forceinline__ typename elem<V>::E ld_elem(const void *base, int c, int q, CDesc &D, const Lane<V> &L)
+{
+    using E = typename elem<V>::E;
+    constexpr int S = elem<V>::S;
+    return gld<E>(base, (size_t)c * D.plane * S + (size_t)q * D.nz * S + L.eidx);
+}
+
+// One row of a plane as this lane contributes it to an LDS row with N_D columns of halo on each side:
+// its own element and (lanes < 2 N_D S) one halo element, in registers until put_row stores them.
+template <typename V>
+struct RowPart {
+    typename elem<V>::E own, halo;
+};
+
+template <typename V, int ND, bool ADDJ>
+__device__ __forceinline__ RowPart<V> fetch_row(const V *plane, const V *jplane, double beta_in, int nz, int q,
+                                                int i0, const Lane<V> &L)
+{
+    using E = typename elem<V>::E;
+    constexpr int S = elem<V>::S;
+    const size_t rb = (size_t)q * nz * S;
+    auto get = [&](int e, bool ok) -> E {
+        E x = gld<E>(plane, rb + e);
+        if constexpr (ADDJ) {
+            const E j = gld<E>(jplane, rb + e);
+            if constexpr (S == 1) {
+                x.x += (float)beta_in * j.x;
+                x.y += (float)beta_in * j.y;
+            } else {
+                x += beta_in * j;
+            }
+        }
+        if (!ok) {
+            if constexpr (S == 1) x = float2{0.f, 0.f};
+            else x = 0.0;
+        }
+        return x;
+    };
+    RowPart<V> r;
+    r.own = get(L.eidx, L.col);
+    const int h = L.lane < ND * S ? L.lane : WAVE + L.lane;  // LDS slot of this lane's halo element
+    const int ii = i0 - ND + h / S;                          // its column
+    const bool ok = L.lane < 2 * ND * S && ii >= 0 && ii < nz;
+    r.halo = get((ok ? ii : 0) * S + h % S, ok);
+    return r;
+}
+
+template <typename V, int ND>
+__device__ __forceinline__ void put_row(const RowPart<V> &r, const Lane<V> &L, typename elem<V>::E *row)
+{
+    constexpr int S = elem<V>::S;
+    row[L.lane + ND * S] = r.own;
+    if (L.lane < 2 * ND * S) row[L.lane < ND * S ? L.lane : WAVE + L.lane] = r.halo;
+}
+
+template <typename AR, typename V>
+__device__ __forceinline__ lv<AR, elem<V>::K> lds_at(const typename elem<V>::E *row, int idx)
+{
+    return to_lv<AR>(row[idx]);
+}
+
+// --------------------------------------------------------------------------------------------------
+// E half:  dE_rho   = -D_z^(+) B_theta + (i m / rho_(-)) B_z          (staggered rows k >= 1)
+//          dE_theta =  D_z^(+) B_rho   - D_rho^(+,mS) B_z
+//          dE_z     = -(i m / rho) B_rho + rho^-1 D^(+) (rho_(-) B_theta)
+// Window (staggered rows q = k - N_D + 1 + t, t = 0 .. 2N_D-1): B_z and g = rho_(-) B_theta.
+// --------------------------------------------------------------------------------------------------
+template <typename V, typename AR, int ND, bool SRC, bool COMP>
+__device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
+{
+    constexpr int K = elem<V>::K, S = elem<V>::S;
+    using L_ = lv<AR, K>;
+    CDesc &D = *A.D;
+    const int nz = D.nz, nr = D.nr;
+    const Lane<V> L(i0, nz);
+    const size_t P = D.plane;
+    const V *vin = (const V *)A.vin;
+    const V *Bth = vin + BTH * P, *Br = vin + BR * P, *Bz = vin + BZ * P;
+    const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
+    const L_ zero = zero_lv<AR, K>();
+
+    L_ ax = zero;  // B_z on the axis: extrapolated for m = 0, else 0
+    if (D.m == 0 && k0 < ND) {
+#pragma unroll
+        for (int q = 1; q <= ND; ++q) ax = fmav((AR)D.cax[q - 1], ldrow<V, AR>(Bz, nz, q, L), ax);
+    }
+    // staggered-grid window rows q = k0 - N_D + 1 + t: row 0 is the axis (B_z: ax; rho_(-) B_theta: 0),
+    // rows q < 0 mirror row -q with the component's sign, rows >= nr are 0.  All loads are issued first
+    // (clamped, valid rows), the rules are applied as selects afterwards.
+    L_ Wz[2 * ND], Wg[2 * ND];
+#pragma unroll
+    for (int t = 0; t < 2 * ND - 1; ++t) {
+        const int q = k0 - ND + 1 + t;
+        const int r = min(q < 0 ? -q : q, nr - 1);
+        Wz[t] = ldrow<V, AR>(Bz, nz, r, L);
+        Wg[t] = ldrow<V, AR>(Bth, nz, r, L);
+    }
+#pragma unroll
+    for (int t = 0; t < 2 * ND - 1; ++t) {
+        const int q = k0 - ND + 1 + t;
+        const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
+        Wz[t] = q >= nr ? zero : (q == 0 ? ax : sz * Wz[t]);
+        Wg[t] = (q >= nr || q == 0) ? zero : ((AR)q * dr * sg) * Wg[t];
+    }
+    const int own = L.lane + ND * S;
+    using E = typename elem<V>::E;
+    // everything row k needs from memory, fetched one row ahead of its use
+    struct In {
+        L_ wz, wg, j0, j1, j2;
+        RowPart<V> th, br;
+        E p0, p1, p2;
+        float2 l0, l1, l2;
+    };
+    // Branch-free: every load reads a valid row (indices clamped), values are selected afterwards, so the
+    // loop body is one basic block and the next row's loads stay in flight during this row's arithmetic.
+    auto fetch = [&](int k) -> In {
+        In x;
+        const int qn = k + ND;
+        const int qc = qn < nr ? qn : nr - 1;
+        const L_ bz = ldrow<V, AR>(Bz, nz, qc, L), bt = ldrow<V, AR>(Bth, nz, qc, L);
+        x.wz = qn < nr ? bz : zero;
+        x.wg = qn < nr ? ((AR)qn * dr) * bt : zero;
+        x.th = fetch_row<V, ND, false>(Bth, nullptr, 0.0, nz, k, i0, L);
+        x.br = fetch_row<V, ND, false>(Br, nullptr, 0.0, nz, k, i0, L);
+        x.j0 = x.j1 = x.j2 = zero;
+        if constexpr (SRC) {
+            x.j0 = ldrow<V, AR>((const V *)A.jr, nz, k, L);
+            x.j1 = ldrow<V, AR>((const V *)A.jt, nz, k, L);
+            x.j2 = ldrow<V, AR>((const V *)A.jz, nz, k, L);
+        }
+        x.p0 = ld_elem<V>(A.psi, ER, k, D, L);
+        x.p1 = ld_elem<V>(A.psi, ETH, k, D, L);
+        x.p2 = ld_elem<V>(A.psi, EZ, k, D, L);
+        x.l0 = x.l1 = x.l2 = float2{0.f, 0.f};
+        if constexpr (COMP) {
+            x.l0 = ld_elem<V>(D.lo, ER, k, D, L);
+            x.l1 = ld_elem<V>(D.lo, ETH, k, D, L);
+            x.l2 = ld_elem<V>(D.lo, EZ, k, D, L);
+        }
+        return x;
+    };
+    In nx = fetch(k0);
+    for (int k = k0; k < k1; ++k) {
+        const In cu = nx;
+        nx = fetch(k + 1 < k1 ? k + 1 : k);  // the last iteration re-reads its own row, unused
+        Wz[2 * ND - 1] = cu.wz;
+        Wg[2 * ND - 1] = cu.wg;
+        put_row<V, ND>(cu.th, L, lds[0]);
+        put_row<V, ND>(cu.br, L, lds[1]);
+        __syncthreads();
+        L_ zth = zero, zr = zero, rz = zero, rg = zero;
+        // D_z^(+) at primary column i: staggered columns i + j and i - j + 1
+#pragma unroll 4
+        for (int j = 1; j <= ND; ++j) {
+            const AR az = (AR)D.az[j - 1];
+            zth = fmav(az, lds_at<AR, V>(lds[0], own + j * S) - lds_at<AR, V>(lds[0], own - (j - 1) * S), zth);
+            zr = fmav(az, lds_at<AR, V>(lds[1], own + j * S) - lds_at<AR, V>(lds[1], own - (j - 1) * S), zr);
+        }
+        // D^(+) along rho at primary row k: staggered rows k + j (slot ND-1+j) and k - j + 1 (slot ND-j)
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const AR ar = (AR)D.ar[j - 1];
+            rz = fmav(ar, Wz[ND - 1 + j] - Wz[ND - j], rz);
+            rg = fmav(ar, Wg[ND - 1 + j] - Wg[ND - j], rg);
+        }
+        const L_ br = to_lv<AR>(cu.br.own);
+        const L_ bzk = Wz[ND - 1];
+        const AR rip = (AR)cld(D.rinv_p, k), ris = (AR)cld(D.rinv_s, k);
+        const L_ t0 = times_i(mm * ris, bzk);  // lane swaps: every lane of the wave takes part
+        const L_ t2 = times_i(mm * rip, br);
+        __syncthreads();
+        if (L.col) {
+            const AR coef = (AR)A.coef, beta = (AR)A.beta;
+            const L_ i0v = fmav(beta, cu.j0, coef * (t0 - zth));
+            const L_ i1v = fmav(beta, cu.j1, coef * (zr - rz));
+            const L_ i2v = fmav(beta, cu.j2, coef * (rip * rg - t2));
+            store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, cu.p0, cu.l0);
+            store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, cu.p1, cu.l1);
+            store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, cu.p2, cu.l2);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            Wz[t] = Wz[t + 1];
+            Wg[t] = Wg[t + 1];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------------
+// B half:  dB_rho   =  D_z^(-) E_theta - (i m / rho) E_z
+//          dB_theta = -D_z^(-) E_rho   + D_rho^(-,mS) E_z              (staggered rows k >= 1)
+//          dB_z     =  (i m / rho_(-)) E_rho - rho_(-)^-1 D^(-) (rho E_theta)   (k >= 1)
+// Window (primary rows q = k - N_D + t, t = 0 .. 2N_D-1): E_z and g = rho E_theta.
+// In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed while
+// loading (FIRST); without a current, or in later stages, the input is read as it is.
+// --------------------------------------------------------------------------------------------------
+template <typename V, typename AR, int ND, bool FIRST, bool COMP>
+__device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
+{
+    constexpr int K = elem<V>::K, S = elem<V>::S;
+    using L_ = lv<AR, K>;
+    CDesc &D = *A.D;
+    const int nz = D.nz, nr = D.nr;
+    const Lane<V> L(i0, nz);
+    const size_t P = D.plane;
+    const V *vin = (const V *)A.vin;
+    const V *Er = vin + ER * P, *Eth = vin + ETH * P, *Ez = vin + EZ * P;
+    const V *Jr = (const V *)A.jr, *Jt = (const V *)A.jt, *Jz = (const V *)A.jz;
+    const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
+    const AR bin = (AR)A.beta_in;
+    const L_ zero = zero_lv<AR, K>();
+    auto ldw = [&](const V *f, const V *jf, int q) -> L_ {
+        L_ x = ldrow<V, AR>(f, nz, q, L);
+        if constexpr (FIRST) x = fmav(bin, ldrow<V, AR>(jf, nz, q, L), x);
+        return x;
+    };
+    // primary-grid window rows q = k0 - N_D + t: rows q < 0 mirror row -1-q with the component's sign,
+    // rows >= nr are 0; loads first (clamped rows), rules as selects.
+    L_ Wz[2 * ND], Wg[2 * ND];
+#pragma unroll
+    for (int t = 0; t < 2 * ND - 1; ++t) {
+        const int q = k0 - ND + t;
+        const int r = min(q < 0 ? -1 - q : q, nr - 1);
+        Wz[t] = ldw(Ez, Jz, r);
+        Wg[t] = ldw(Eth, Jt, r);
+    }
+#pragma unroll
+    for (int t = 0; t < 2 * ND - 1; ++t) {
+        const int q = k0 - ND + t;
+        const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
+        Wz[t] = q >= nr ? zero : sz * Wz[t];
+        Wg[t] = q >= nr ? zero : ((((AR)q + (AR)0.5) * dr) * sg) * Wg[t];
+    }
+    const int own = L.lane + ND * S;
+    using E = typename elem<V>::E;
+    struct In {
+        L_ wz, wg;
+        RowPart<V> th, er;
+        E p0, p1, p2;
+        float2 l0, l1, l2;
+    };
+    auto fetch = [&](int k) -> In {
+        In x;
+        const int qn = k + ND - 1;
+        const int qc = qn < nr ? qn : nr - 1;
+        const L_ ez = ldw(Ez, Jz, qc), et = ldw(Eth, Jt, qc);
+        x.wz = qn < nr ? ez : zero;
+        x.wg = qn < nr ? (((AR)qn + (AR)0.5) * dr) * et : zero;
+        x.th = fetch_row<V, ND, FIRST>(Eth, Jt, A.beta_in, nz, k, i0, L);
+        x.er = fetch_row<V, ND, FIRST>(Er, Jr, A.beta_in, nz, k, i0, L);
+        x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
+        x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
+        x.p2 = ld_elem<V>(A.psi, BZ, k, D, L);
+        x.l0 = x.l1 = x.l2 = float2{0.f, 0.f};
+        if constexpr (COMP) {
+            x.l0 = ld_elem<V>(D.lo, BR, k, D, L);
+            x.l1 = ld_elem<V>(D.lo, BTH, k, D, L);
+            x.l2 = ld_elem<V>(D.lo, BZ, k, D, L);
+        }
+        return x;
+    };
+    In nx = fetch(k0);
+    for (int k = k0; k < k1; ++k) {
+        const In cu = nx;
+        nx = fetch(k + 1 < k1 ? k + 1 : k);
+        Wz[2 * ND - 1] = cu.wz;
+        Wg[2 * ND - 1] = cu.wg;
+        put_row<V, ND>(cu.th, L, lds[0]);
+        put_row<V, ND>(cu.er, L, lds[1]);
+        __syncthreads();
+        L_ zth = zero, zr = zero, rz = zero, rg = zero;
+        // D_z^(-) at staggered column i: primary columns i + j - 1 and i - j
+#pragma unroll 4
+        for (int j = 1; j <= ND; ++j) {
+            const AR az = (AR)D.az[j - 1];
+            zth = fmav(az, lds_at<AR, V>(lds[0], own + (j - 1) * S) - lds_at<AR, V>(lds[0], own - j * S), zth);
+            zr = fmav(az, lds_at<AR, V>(lds[1], own + (j - 1) * S) - lds_at<AR, V>(lds[1], own - j * S), zr);
+        }
+        // D^(-) along rho at staggered row k: primary rows k + j - 1 (slot ND+j-1) and k - j (slot ND-j)
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const AR ar = (AR)D.ar[j - 1];
+            rz = fmav(ar, Wz[ND + j - 1] - Wz[ND - j], rz);
+            rg = fmav(ar, Wg[ND + j - 1] - Wg[ND - j], rg);
+        }
+        const L_ erk = to_lv<AR>(cu.er.own);
+        const L_ ezk = Wz[ND];
+        const AR rip = (AR)cld(D.rinv_p, k), ris = (AR)cld(D.rinv_s, k);
+        const L_ t0 = times_i(mm * rip, ezk);
+        const L_ t2 = times_i(mm * ris, erk);
+        __syncthreads();
+        if (L.col) {
+            const AR coef = (AR)A.coef;
+            store_out<V, AR, COMP>(A, BR, k, L, coef * (zth - t0), false, cu.p0, cu.l0);
+            store_out<V, AR, COMP>(A, BTH, k, L, coef * (rz - zr), k == 0, cu.p1, cu.l1);
+            store_out<V, AR, COMP>(A, BZ, k, L, coef * (t2 - ris * rg), k == 0, cu.p2, cu.l2);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            Wz[t] = Wz[t + 1];
+            Wg[t] = Wg[t + 1];
+        }
+    }
+}
+
+// Tile of block b: tiles are numbered problem by problem, (half,) segment, strip -- strips fastest -- and
+// XCD x (blocks b with b % 8 == x) receives the contiguous range [x * per, (x + 1) * per).
+__device__ __forceinline__ int tile_of_block(int ntiles)
+{
+    const int per = (ntiles + NXCD - 1) / NXCD;
+    const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+    return t < ntiles ? t : -1;
+}
+
+template <bool AXIS>
+__device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
+{
+    CDesc *T = (CDesc *)A.probs;
+    int p = 0;
+    while (p + 1 < A.nprob && (AXIS ? T[p + 1].tile_begin_ax : T[p + 1].tile_begin) <= t) ++p;
+    return p;
+}
+
+// AXIS = false: segments nseg_ax .. nseg-1 in the storage precision; AXIS = true (FP32 storage only): the
+// leading nseg_ax segments, whose stencils reach the axis and its 1/rho factors, in FP64 arithmetic.
+template <typename V, int ND, bool FIRST, bool SRC, bool COMP, bool AXIS>
+__global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
+{
+    using E = typename elem<V>::E;
+    constexpr int S = elem<V>::S, CPW = WAVE / S;
+    __shared__ E lds[2][WAVE + 2 * ND * S];
+    const int t = tile_of_block(A.ntiles);
+    if (t < 0) return;
+    const int p = problem_of_tile<AXIS>(A, t);
+    CDesc &D = ((CDesc *)A.probs)[p];
+    TileCoord tc;
+    if (!decode_tile(D, t - (AXIS ? D.tile_begin_ax : D.tile_begin), 2, AXIS, CPW, tc)) return;
+    const int half = tc.half, i0 = tc.i0, k0 = tc.k0, k1 = tc.k1;
+    Ctx C;
+    C.D = &D;
+    const bool first = A.n == A.N - 1;
+    C.psi = A.psi[p];
+    C.vin = first ? C.psi : D.buf[(A.N - 2 - A.n) & 1];
+    C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
+    C.has_src = A.has_src;
+    const size_t pb = D.plane * sizeof(V);
+    C.jr = A.has_src ? D.jbar : nullptr;
+    C.jt = A.has_src ? (const char *)A.aux[p] + pb : nullptr;
+    C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
+    C.compensated = A.compensated && A.n == 0;
+    C.beta_in = A.beta_in;
+    C.beta = A.beta;
+    C.coef = A.coef;
+    using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
+    if (half == 0) e_half<V, AR, ND, SRC, COMP>(C, i0, k0, k1, lds);
+    else b_half<V, AR, ND, FIRST, COMP>(C, i0, k0, k1, lds);
+}
+
+// --------------------------------------------------------------------------------------------------
+// Envelope stage (section 4.2): out = psi + coef * H_a vin with
+//   H_a (a, a~) = (a~, (L_rho + L_z - m^2/rho^2 - chi) a + 2 i k0 (D_z^(C) a + a~)),
+// window of a over primary rows k - N_D .. k + N_D (scalar-like extension), current row of a in LDS.
+// --------------------------------------------------------------------------------------------------
+struct EnvCtx {
+    CDesc *D;
+    const void *vin_a, *vin_t, *psi_a, *psi_t, *chi;
+    void *out_a, *out_t;
+    int compensated;
+    double coef;
+};
+
+template <typename V, typename AR, int ND, bool COMP>
+__device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k1, typename elem<V>::E *lds)
+{
+    constexpr int K = elem<V>::K, S = elem<V>::S;
+    using E = typename elem<V>::E;
+    using R = typename scal<V>::R;
+    using L_ = lv<AR, K>;
+    CDesc &D = *A.D;
+    const int nz = D.nz, nr = D.nr;
+    const Lane<V> L(i0, nz);
+    const V *va = (const V *)A.vin_a, *vt = (const V *)A.vin_t;
+    const L_ zero = zero_lv<AR, K>();
+    const AR pS = (AR)D.pS;
+    constexpr int W = 2 * ND + 1;
+    L_ Wa[W];
+#pragma unroll
+    for (int t = 0; t < W - 1; ++t) {
+        const int q = k0 - ND + t;
+        Wa[t] = ldrow<V, AR>(va, nz, min(q < 0 ? -1 - q : q, nr - 1), L);
+    }
+#pragma unroll
+    for (int t = 0; t < W - 1; ++t) {
+        const int q = k0 - ND + t;
+        Wa[t] = q >= nr ? zero : (q < 0 ? pS : (AR)1) * Wa[t];
+    }
+    const AR k2 = (AR)(2.0 * D.k0);
+    const int own = L.lane + ND * S;
+    const int cc = L.col ? L.i : nz - 1;
+    struct In {
+        L_ wa, tin;
+        RowPart<V> a;
+        AR chi;
+        E pa, pt;
+        float2 la, lt;
+    };
+    auto fetch = [&](int k) -> In {
+        In x;
+        const int qn = k + ND;
+        const L_ an = ldrow<V, AR>(va, nz, qn < nr ? qn : nr - 1, L);
+        x.wa = qn < nr ? an : zero;
+        x.a = fetch_row<V, ND, false>(va, nullptr, 0.0, nz, k, i0, L);
+        x.tin = ldrow<V, AR>(vt, nz, k, L);
+        x.chi = (AR)gld<R>(A.chi, (size_t)k * nz + cc);
+        const size_t o = (size_t)k * nz * S + L.eidx;
+        x.pa = gld<E>(A.psi_a, o);
+        x.pt = gld<E>(A.psi_t, o);
+        x.la = x.lt = float2{0.f, 0.f};
+        if constexpr (COMP) {
+            x.la = gld<float2>(D.lo, o);
+            x.lt = gld<float2>(D.lo, D.plane + o);
+        }
+        return x;
+    };
+    In nx = fetch(k0);
+    for (int k = k0; k < k1; ++k) {
+        const In cu = nx;
+        nx = fetch(k + 1 < k1 ? k + 1 : k);
+        Wa[W - 1] = cu.wa;
+        put_row<V, ND>(cu.a, L, lds);
+        __syncthreads();
+        const L_ a0 = Wa[ND];
+        L_ lz = (AR)D.bz[0] * a0, d1z = zero;
+#pragma unroll 4
+        for (int j = 1; j <= ND; ++j) {
+            const L_ zp = lds_at<AR, V>(lds, own + j * S), zm = lds_at<AR, V>(lds, own - j * S);
+            lz = fmav((AR)D.bz[j], zp + zm, lz);
+            d1z = fmav((AR)D.dzc[j - 1], zp - zm, d1z);
+        }
+        L_ lr = (AR)D.br[0] * a0, d1r = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const L_ rp = Wa[ND + j], rm = Wa[ND - j];
+            lr = fmav((AR)D.br[j], rp + rm, lr);
+            d1r = fmav((AR)D.drc[j - 1], rp - rm, d1r);
+        }
+        const AR pot = (AR)cld(D.m2rinv2, k) + cu.chi;
+        const L_ rot = times_i(k2, d1z + cu.tin);
+        __syncthreads();
+        if (L.col) {
+            const L_ dtv = lr + (AR)cld(D.rinv_p, k) * d1r + lz - pot * a0 + rot;
+            const AR coef = (AR)A.coef;
+            const L_ ia = coef * cu.tin, it = coef * dtv;
+            const size_t o = (size_t)k * nz * S + L.eidx;
+            if constexpr (S == 1) {
+                if constexpr (COMP) {
+                    float s0, e0, s1, e1, s2, e2, s3, e3;
+                    two_sum(cu.pa.x, (float)(ia.p[0] + (AR)cu.la.x), s0, e0);
+                    two_sum(cu.pa.y, (float)(ia.p[1] + (AR)cu.la.y), s1, e1);
+                    two_sum(cu.pt.x, (float)(it.p[0] + (AR)cu.lt.x), s2, e2);
+                    two_sum(cu.pt.y, (float)(it.p[1] + (AR)cu.lt.y), s3, e3);
+                    gst<float2>(A.out_a, o, float2{s0, s1});
+                    gst<float2>(A.out_t, o, float2{s2, s3});
+                    gst<float2>(D.lo, o, float2{e0, e1});
+                    gst<float2>(D.lo, D.plane + o, float2{e2, e3});
+                } else {
+                    gst<float2>(A.out_a, o, float2{(float)((AR)cu.pa.x + ia.p[0]), (float)((AR)cu.pa.y + ia.p[1])});
+                    gst<float2>(A.out_t, o, float2{(float)((AR)cu.pt.x + it.p[0]), (float)((AR)cu.pt.y + it.p[1])});
+                }
+            } else {
+                gst<double>(A.out_a, o, (double)((AR)cu.pa + ia.p[0]));
+                gst<double>(A.out_t, o, (double)((AR)cu.pt + it.p[0]));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < W - 1; ++t) Wa[t] = Wa[t + 1];
+    }
+}
+
+template <typename V, int ND, bool COMP, bool AXIS>
+__global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
+{
+    using E = typename elem<V>::E;
+    constexpr int S = elem<V>::S, CPW = WAVE / S;
+    __shared__ E lds[WAVE + 2 * ND * S];
+    const int t = tile_of_block(A.ntiles);
+    if (t < 0) return;
+    const int p = problem_of_tile<AXIS>(A, t);
+    CDesc &D = ((CDesc *)A.probs)[p];
+    TileCoord tc;
+    if (!decode_tile(D, t - (AXIS ? D.tile_begin_ax : D.tile_begin), 1, AXIS, CPW, tc)) return;
+    const int i0 = tc.i0, k0 = tc.k0, k1 = tc.k1;
+    EnvCtx C;
+    C.D = &D;
+    const bool first = A.n == A.N - 1;
+    const size_t pb = D.plane * sizeof(V);
+    C.psi_a = A.psi[p];
+    C.psi_t = A.aux[p];
+    const void *ib = D.buf[(A.N - 2 - A.n) & 1], *ob = D.buf[(A.N - 1 - A.n) & 1];
+    C.vin_a = first ? C.psi_a : ib;
+    C.vin_t = first ? C.psi_t : (const char *)ib + pb;
+    const bool in_place = A.n == 0 && A.N > 1;
+    C.out_a = in_place ? (void *)C.psi_a : (void *)ob;
+    C.out_t = in_place ? (void *)C.psi_t : (void *)((const char *)ob + pb);
+    C.chi = A.chi[p];
+    C.compensated = A.compensated && A.n == 0;
+    C.coef = A.coef;
+    using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
+    env_march<V, AR, ND, COMP>(C, i0, k0, k1, lds);
+}
+
+// Launch stage n of a batch with the kernel variant its flags select.
+template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
+hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
+{
+    const int per = (a.ntiles + NXCD - 1) / NXCD;
+    const dim3 g(per * NXCD), b(WAVE);
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (a.axis_launch) {
+            hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP, true>), g, b, 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP, false>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename V, int ND>
+hipError_t go_maxwell(const BatchArgs &a, hipStream_t s)
+{
+    // FIRST adds beta_in * Jbar while loading the E input: only in the first stage, and only with a current
+    const bool first = a.n == a.N - 1 && a.has_src;
+    const bool comp = sizeof(typename scal<V>::R) == 4 && a.compensated && a.n == 0;
+    if (comp) {
+        if constexpr (sizeof(typename scal<V>::R) == 4) {
+            if (first) return go_maxwell_v<V, ND, true, true, true>(a, s);
+            if (a.has_src) return go_maxwell_v<V, ND, false, true, true>(a, s);
+            return go_maxwell_v<V, ND, false, false, true>(a, s);
+        }
+    }
+    if (first) return go_maxwell_v<V, ND, true, true, false>(a, s);
+    if (a.has_src) return go_maxwell_v<V, ND, false, true, false>(a, s);
+    return go_maxwell_v<V, ND, false, false, false>(a, s);
+}
+
+template <typename V, int ND, bool COMP>
+hipError_t go_envelope_v(const BatchArgs &a, hipStream_t s)
+{
+    const int per = (a.ntiles + NXCD - 1) / NXCD;
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (a.axis_launch) {
+            hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP, true>), dim3(per * NXCD), dim3(WAVE), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP, false>), dim3(per * NXCD), dim3(WAVE), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename V, int ND>
+hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
+{
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (a.compensated && a.n == 0) return go_envelope_v<V, ND, true>(a, s);
+    }
+    return go_envelope_v<V, ND, false>(a, s);
+}
+
+}  // namespace
+
+// Per-N_D entry points; fdetd_march.hip is compiled once per N_D range (FDETD_ND_LO .. FDETD_ND_HI) so
+// that the many kernel variants build in parallel.
+#define FDETD_MARCH_INST(N)                                                                          \
+    template <>                                                                                      \
+    hipError_t march_maxwell_nd<N>(int prec, const BatchArgs &a, hipStream_t s)                      \
+    {                                                                                                \
+        return prec == P64 ? go_maxwell<double2, N>(a, s) : go_maxwell<float2, N>(a, s);             \
+    }                                                                                                \
+    template <>                                                                                      \
+    hipError_t march_envelope_nd<N>(int prec, const BatchArgs &a, hipStream_t s)                     \
+    {                                                                                                \
+        return prec == P64 ? go_envelope<double2, N>(a, s) : go_envelope<float2, N>(a, s);           \
+    }
+
+#ifndef FDETD_ND_LO
+#define FDETD_ND_LO 1
+#define FDETD_ND_HI 16
+#endif
+#if FDETD_ND_LO <= 1 && 1 <= FDETD_ND_HI
+FDETD_MARCH_INST(1)
+#endif
+#if FDETD_ND_LO <= 2 && 2 <= FDETD_ND_HI
+FDETD_MARCH_INST(2)
+#endif
+#if FDETD_ND_LO <= 3 && 3 <= FDETD_ND_HI
+FDETD_MARCH_INST(3)
+#endif
+#if FDETD_ND_LO <= 4 && 4 <= FDETD_ND_HI
+FDETD_MARCH_INST(4)
+#endif
+#if FDETD_ND_LO <= 5 && 5 <= FDETD_ND_HI
+FDETD_MARCH_INST(5)
+#endif
+#if FDETD_ND_LO <= 6 && 6 <= FDETD_ND_HI
+FDETD_MARCH_INST(6)
+#endif
+#if FDETD_ND_LO <= 7 && 7 <= FDETD_ND_HI
+FDETD_MARCH_INST(7)
+#endif
+#if FDETD_ND_LO <= 8 && 8 <= FDETD_ND_HI
+FDETD_MARCH_INST(8)
+#endif
+#if FDETD_ND_LO <= 9 && 9 <= FDETD_ND_HI
+FDETD_MARCH_INST(9)
+#endif
+#if FDETD_ND_LO <= 10 && 10 <= FDETD_ND_HI
+FDETD_MARCH_INST(10)
+#endif
+#if FDETD_ND_LO <= 11 && 11 <= FDETD_ND_HI
+FDETD_MARCH_INST(11)
+#endif
+#if FDETD_ND_LO <= 12 && 12 <= FDETD_ND_HI
+FDETD_MARCH_INST(12)
+#endif
+#if FDETD_ND_LO <= 13 && 13 <= FDETD_ND_HI
+FDETD_MARCH_INST(13)
+#endif
+#if FDETD_ND_LO <= 14 && 14 <= FDETD_ND_HI
+FDETD_MARCH_INST(14)
+#endif
+#if FDETD_ND_LO <= 15 && 15 <= FDETD_ND_HI
+FDETD_MARCH_INST(15)
+#endif
+#if FDETD_ND_LO <= 16 && 16 <= FDETD_ND_HI
+FDETD_MARCH_INST(16)
+#endif
+
+}  // namespace fdetd

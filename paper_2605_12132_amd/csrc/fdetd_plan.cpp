@@ -10,7 +10,9 @@
 // the last stage writes psi in place.  The envelope step is the same recurrence without source.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +22,7 @@
 
 #include "../../include/fdetd.h"
 #include "fdetd_internal.h"
+#include "fdetd_tiles.h"
 
 using namespace fdetd;
 
@@ -42,12 +45,23 @@ struct Prob {
 
 }  // namespace
 
+// Problems of equal N_D, N and dt that share one launch per stage (FP32C: two, the near-axis segments
+// separately): table entries [d0, d0 + count).
+struct Batch {
+    int nd, N, d0, count, ntiles, ntiles_ax;
+    double dt;
+    std::vector<int> members;  // user indices, in table order
+};
+
 struct fdetd_plan_s {
     int precision = FDETD_FP64;
     uint32_t flags = 0;
     int kind = FDETD_MAXWELL;
     hipStream_t stream = nullptr;
     std::vector<Prob> probs;
+    std::vector<Batch> batches;
+    std::vector<ProbDesc> desc;   // host copy of the device table
+    ProbDesc *ddesc = nullptr;
     std::string err;
     fdetd_plan_info info{};
     // cached graph of the last captured call
@@ -57,6 +71,7 @@ struct fdetd_plan_s {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<double> ev_bytes;
+    bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
 };
 
 namespace {
@@ -172,99 +187,252 @@ int zero_device(fdetd_plan_t P, void *ptr, size_t bytes)
     return FDETD_OK;
 }
 
-int enqueue_maxwell_step(fdetd_plan_t P, Prob &q, void *psi, const void *j, int last_step_of_call)
+// One Maxwell step of every problem: stage the currents, N batched Horner stages, the axis rule.
+int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j, int last_step_of_call)
 {
     const int prec = prec_code(P->precision);
     const size_t eb = elem_bytes(P->precision);
-    const size_t plane_b = q.cells * eb;
-    const int N = q.d.taylor_order;
-    const double dt = q.d.dt;
-    MaxwellStageArgs A;
-    fill_maxwell_args(P, q, A);
-    A.psi = psi;
     if (j) {
-        StaggerArgs S{};
-        S.jr = j;
-        S.out = q.jbar;
-        S.pA = -parity_mS(q.d.m);
-        S.nz = q.d.nz;
-        S.nr = q.d.nr;
-        for (int t = 0; t < q.nd; ++t) S.s[t] = q.s[t];
-        HIPCHK(P, launch_stagger_jr(prec, q.nd, S, P->stream));
-        A.has_src = 1;
-        A.jr = q.jbar;
-        A.jt = (const char *)j + plane_b;
-        A.jz = (const char *)j + 2 * plane_b;
+        for (size_t p = 0; p < P->probs.size(); ++p) {
+            const Prob &q = P->probs[p];
+            StaggerArgs S{};
+            S.jr = j[p];
+            S.out = q.jbar;
+            S.pA = -parity_mS(q.d.m);
+            S.nz = q.d.nz;
+            S.nr = q.d.nr;
+            for (int t = 0; t < q.nd; ++t) S.s[t] = q.s[t];
+            HIPCHK(P, launch_stagger_jr(prec, q.nd, S, P->stream));
+        }
     }
-    const void *vin = psi;
-    for (int n = N - 1; n >= 0; --n) {
-        A.vin = vin;
-        A.first = (n == N - 1);
-        A.beta_in = -dt * std::ldexp(1.0, -N);
-        A.beta = -dt * std::ldexp(1.0, -n);
-        A.coef = dt / (n + 1);
-        const bool in_place = (n == 0) && (N > 1);
-        A.vout = in_place ? psi : q.buf[(N - 1 - n) & 1];
-        A.last_compensated = (n == 0) && P->precision == FDETD_FP32C;
-        A.lo = A.last_compensated ? q.lo : nullptr;
-        // algorithmic bytes: vin (6c) + psi (6c, the same data in the first stage) + Jbar (3c) + vout (6c)
-        double cvals = (A.first ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
-        double bytes = cvals * q.cells * eb + (A.last_compensated ? 2.0 * 6 * q.cells * 8 : 0.0);
-        int rc = profile_begin(P, bytes);
-        if (rc) return rc;
-        HIPCHK(P, launch_maxwell_stage(prec, q.nd, A, P->stream));
-        if ((rc = profile_end(P))) return rc;
-        vin = A.vout;
+    for (const Batch &b : P->batches) {
+        BatchArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = P->ddesc + b.d0;
+        A.nprob = b.count;
+        A.ntiles = b.ntiles;
+        A.N = b.N;
+        A.has_src = j != nullptr;
+        A.compensated = P->precision == FDETD_FP32C;
+        size_t cells = 0;
+        for (int t = 0; t < b.count; ++t) {
+            A.psi[t] = psi[b.members[t]];
+            A.aux[t] = j ? j[b.members[t]] : nullptr;
+            cells += P->probs[b.members[t]].cells;
+        }
+        for (int n = b.N - 1; n >= 0; --n) {
+            A.n = n;
+            A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
+            A.beta = -b.dt * std::ldexp(1.0, -n);
+            A.coef = b.dt / (n + 1);
+            // algorithmic bytes: vin (6c) + psi (6c; the same data in the first stage) + Jbar (3c) + vout (6c)
+            const double cvals = (n == b.N - 1 ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
+            const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
+            int rc = profile_begin(P, bytes);
+            if (rc) return rc;
+            if (b.ntiles_ax) {
+                A.axis_launch = 1;
+                A.ntiles = b.ntiles_ax;
+                HIPCHK(P, launch_maxwell_march(prec, b.nd, A, P->stream));
+            }
+            if (b.ntiles) {
+                A.axis_launch = 0;
+                A.ntiles = b.ntiles;
+                HIPCHK(P, launch_maxwell_march(prec, b.nd, A, P->stream));
+            }
+            if ((rc = profile_end(P))) return rc;
+        }
     }
-    if (N == 1) HIPCHK(P, launch_copy(q.buf[0], psi, 6 * plane_b, P->stream));
-    if (last_step_of_call) {
-        AxisArgs X{};
-        X.psi = psi;
-        X.nz = q.d.nz;
-        X.nr = q.d.nr;
-        X.m = q.d.m;
-        for (int t = 0; t < q.nd; ++t) X.cax[t] = q.c[t];
-        HIPCHK(P, launch_axis_fix(prec, q.nd, X, P->stream));
+    for (size_t p = 0; p < P->probs.size(); ++p) {
+        const Prob &q = P->probs[p];
+        if (q.d.taylor_order == 1) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, P->stream));
+        if (last_step_of_call) {
+            AxisArgs X{};
+            X.psi = psi[p];
+            X.nz = q.d.nz;
+            X.nr = q.d.nr;
+            X.m = q.d.m;
+            for (int t = 0; t < q.nd; ++t) X.cax[t] = q.c[t];
+            HIPCHK(P, launch_axis_fix(prec, q.nd, X, P->stream));
+        }
     }
     return FDETD_OK;
 }
 
-int enqueue_envelope_step(fdetd_plan_t P, Prob &q, void *a, void *at, const void *chi)
+int enqueue_envelope_step(fdetd_plan_t P, void *const *a, void *const *at, const void *const *chi)
 {
     const int prec = prec_code(P->precision);
-    const size_t plane_b = q.cells * elem_bytes(P->precision);
-    const int N = q.d.taylor_order;
-    EnvelopeStageArgs A;
-    fill_envelope_args(P, q, A);
-    A.psi_a = a;
-    A.psi_t = at;
-    A.chi = chi;
-    const void *ia = a, *it = at;
-    for (int n = N - 1; n >= 0; --n) {
-        A.vin_a = ia;
-        A.vin_t = it;
-        A.coef = q.d.dt / (n + 1);
-        void *ob = q.buf[(N - 1 - n) & 1];
-        const bool in_place = (n == 0) && (N > 1);
-        A.out_a = in_place ? a : ob;
-        A.out_t = in_place ? at : (char *)ob + plane_b;
-        A.last_compensated = (n == 0) && P->precision == FDETD_FP32C;
-        A.lo_a = A.last_compensated ? q.lo : nullptr;
-        A.lo_t = A.last_compensated ? q.lo + 2 * q.cells : nullptr;
-        // algorithmic bytes: vin (2c) + psi (2c, the same data in the first stage) + chi + vout (2c)
-        const double cvals = (n == N - 1 ? 4.0 : 6.0) + 0.5;
-        const double bytes = cvals * plane_b + (A.last_compensated ? 2.0 * 2 * q.cells * 8 : 0.0);
-        int rc = profile_begin(P, bytes);
-        if (rc) return rc;
-        HIPCHK(P, launch_envelope_stage(prec, q.nd, A, P->stream));
-        if ((rc = profile_end(P))) return rc;
-        ia = A.out_a;
-        it = A.out_t;
+    const size_t eb = elem_bytes(P->precision);
+    for (const Batch &b : P->batches) {
+        BatchArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = P->ddesc + b.d0;
+        A.nprob = b.count;
+        A.ntiles = b.ntiles;
+        A.N = b.N;
+        A.compensated = P->precision == FDETD_FP32C;
+        size_t cells = 0;
+        for (int t = 0; t < b.count; ++t) {
+            A.psi[t] = a[b.members[t]];
+            A.aux[t] = at[b.members[t]];
+            A.chi[t] = chi[b.members[t]];
+            cells += P->probs[b.members[t]].cells;
+        }
+        for (int n = b.N - 1; n >= 0; --n) {
+            A.n = n;
+            A.coef = b.dt / (n + 1);
+            // algorithmic bytes: vin (2c) + psi (2c; the same data in the first stage) + chi + vout (2c)
+            const double cvals = (n == b.N - 1 ? 4.0 : 6.0) + 0.5;
+            const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 2 * cells * 8 : 0.0);
+            int rc = profile_begin(P, bytes);
+            if (rc) return rc;
+            if (b.ntiles_ax) {
+                A.axis_launch = 1;
+                A.ntiles = b.ntiles_ax;
+                HIPCHK(P, launch_envelope_march(prec, b.nd, A, P->stream));
+            }
+            if (b.ntiles) {
+                A.axis_launch = 0;
+                A.ntiles = b.ntiles;
+                HIPCHK(P, launch_envelope_march(prec, b.nd, A, P->stream));
+            }
+            if ((rc = profile_end(P))) return rc;
+        }
     }
-    if (N == 1) {
-        HIPCHK(P, launch_copy(q.buf[0], a, plane_b, P->stream));
-        HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at, plane_b, P->stream));
+    for (size_t p = 0; p < P->probs.size(); ++p) {
+        const Prob &q = P->probs[p];
+        if (q.d.taylor_order == 1) {
+            const size_t plane_b = q.cells * eb;
+            HIPCHK(P, launch_copy(q.buf[0], a[p], plane_b, P->stream));
+            HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at[p], plane_b, P->stream));
+        }
     }
+    return FDETD_OK;
+}
+
+// Rows per marching segment: long segments load each rho-stencilled row once per segment (the window
+// warm-up costs 2 N_D - 1 extra rows), short ones give more wavefronts.  Aim at ~8192 wavefronts per launch.
+int pick_seg_rows(int64_t row_strips_total)
+{
+    if (const char *e = std::getenv("FDETD_SEG_ROWS")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 4096) return v;
+    }
+    int s = 8;
+    while (s < 64 && row_strips_total / (2 * s) >= 8192) s *= 2;
+    return s;
+}
+
+// Group problems into launch batches, fill the descriptor table and upload it.
+int build_batches(fdetd_plan_t P)
+{
+    const int n = (int)P->probs.size();
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const auto &a = P->probs[x].d, &b = P->probs[y].d;
+        if (a.fd_order != b.fd_order) return a.fd_order < b.fd_order;
+        if (a.taylor_order != b.taylor_order) return a.taylor_order < b.taylor_order;
+        return a.dt < b.dt;
+    });
+    const int halves = P->kind == FDETD_MAXWELL ? 2 : 1;
+    const int cpw = march_columns_per_wave(prec_code(P->precision));
+    for (int t = 0; t < n;) {
+        const auto &d0 = P->probs[order[t]].d;
+        Batch b;
+        b.nd = d0.fd_order / 2;
+        b.N = d0.taylor_order;
+        b.dt = d0.dt;
+        b.d0 = (int)P->desc.size();
+        int64_t row_strips = 0;
+        int u = t;
+        while (u < n && u - t < kMaxBatch) {
+            const auto &du = P->probs[order[u]].d;
+            if (du.fd_order != d0.fd_order || du.taylor_order != d0.taylor_order || du.dt != d0.dt) break;
+            row_strips += (int64_t)halves * ((du.nz + cpw - 1) / cpw) * du.nr;
+            ++u;
+        }
+        const int seg = pick_seg_rows(row_strips);
+        int tiles = 0, tiles_ax = 0;
+        for (int v = t; v < u; ++v) {
+            const Prob &q = P->probs[order[v]];
+            ProbDesc D;
+            std::memset(&D, 0, sizeof D);
+            D.nz = q.d.nz;
+            D.nr = q.d.nr;
+            D.m = q.d.m;
+            D.taylor = q.d.taylor_order;
+            D.seg_rows = seg;
+            D.nseg = (q.d.nr + seg - 1) / seg;
+            D.nstrip = (q.d.nz + cpw - 1) / cpw;
+            D.nseg_ax = P->precision == FDETD_FP32C ? std::min(D.nseg, (axis_rows(q) + seg - 1) / seg) : 0;
+            D.tile_begin = tiles;
+            D.tile_begin_ax = tiles_ax;
+            D.plane = q.cells;
+            D.dr = q.d.dr;
+            D.pS = parity_mS(q.d.m);
+            D.k0 = q.d.k0;
+            D.buf[0] = q.buf[0];
+            D.buf[1] = q.buf[1];
+            D.jbar = q.jbar;
+            D.lo = q.lo;
+            D.rinv_p = q.rinv_p;
+            D.rinv_s = q.rinv_s;
+            D.m2rinv2 = q.m2rinv2;
+            for (int k = 0; k < q.nd; ++k) {
+                D.az[k] = q.a[k] / q.d.dz;
+                D.ar[k] = q.a[k] / q.d.dr;
+                D.cax[k] = q.c[k];
+                D.dzc[k] = q.d1[k] / q.d.dz;
+                D.drc[k] = q.d1[k] / q.d.dr;
+            }
+            for (int k = 0; k <= q.nd; ++k) {
+                D.bz[k] = q.d2[k] / (q.d.dz * q.d.dz);
+                D.br[k] = q.d2[k] / (q.d.dr * q.d.dr);
+            }
+            tiles += halves * (D.nseg - D.nseg_ax) * D.nstrip;
+            tiles_ax += halves * D.nseg_ax * D.nstrip;
+            P->desc.push_back(D);
+            b.members.push_back(order[v]);
+        }
+        b.count = u - t;
+        b.ntiles = tiles;
+        b.ntiles_ax = tiles_ax;
+        P->batches.push_back(b);
+        t = u;
+    }
+    // every launch must cover each (half, segment, strip) of each problem exactly once, inside the grid
+    for (const Batch &b : P->batches)
+        for (int axis = 0; axis < 2; ++axis) {
+            int expect = 0;
+            for (int t = 0; t < b.count; ++t) {
+                const ProbDesc &D = P->desc[b.d0 + t];
+                const int nl = halves * (axis ? D.nseg_ax : D.nseg - D.nseg_ax) * D.nstrip;
+                if ((axis ? D.tile_begin_ax : D.tile_begin) != expect)
+                    return fail(P, FDETD_E_ARG, "internal: tile ranges of the batch are not contiguous");
+                std::vector<char> seen((size_t)halves * D.nseg * D.nstrip, 0);
+                for (int r = 0; r < nl; ++r) {
+                    TileCoord c;
+                    if (!decode_tile(D, r, halves, axis != 0, cpw, c))
+                        return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid leaves the grid", r, D.nz, D.nr);
+                    const size_t key = ((size_t)c.half * D.nseg + c.k0 / D.seg_rows) * D.nstrip + c.i0 / cpw;
+                    if (c.i0 % cpw || c.k0 % D.seg_rows || key >= seen.size() || seen[key]++)
+                        return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid is decoded twice", r, D.nz, D.nr);
+                }
+                expect += nl;
+            }
+            if (expect != (axis ? b.ntiles_ax : b.ntiles))
+                return fail(P, FDETD_E_ARG, "internal: tile count mismatch");
+        }
+    for (const Batch &b : P->batches) {
+        // the two launches together cover every tile exactly once
+        for (int t = 0; t < b.count; ++t) {
+            const ProbDesc &D = P->desc[b.d0 + t];
+            if (D.nseg_ax < 0 || D.nseg_ax > D.nseg) return fail(P, FDETD_E_ARG, "internal: near-axis segments");
+        }
+    }
+    HIPCHK(P, hipMalloc(&P->ddesc, P->desc.size() * sizeof(ProbDesc)));
+    HIPCHK(P, hipMemcpy(P->ddesc, P->desc.data(), P->desc.size() * sizeof(ProbDesc), hipMemcpyHostToDevice));
     return FDETD_OK;
 }
 
@@ -431,6 +599,7 @@ void fdetd_destroy(fdetd_plan_t plan)
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
+    if (plan->ddesc) (void)hipFree(plan->ddesc);
     delete plan;
 }
 
@@ -507,11 +676,10 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if (P->kind == FDETD_MAXWELL) {
             // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
-            launches += N + 2;
+            launches += 2;  // current staging and axis rule (stage launches counted per batch below)
         } else {
             // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
             bytes_step += (int64_t)q.cells * (eb * 6 + eb / 2) * N + (precision == FDETD_FP32C ? q.cells * 2 * 8 * 2 : 0);
-            launches += N;
         }
         if (!(flags & FDETD_PLAN_SKIP_STABILITY)) {
             double rho = 0.0;
@@ -530,6 +698,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             }
         }
     }
+    if (rc == FDETD_OK) rc = build_batches(P);
     if (rc != FDETD_OK) {
         g_last_error = P->err;
         fdetd_destroy(P);
@@ -542,6 +711,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.cells = cells;
     P->info.bytes_per_step = bytes_step;
     P->info.scratch_bytes = scratch;
+    for (const Batch &b : P->batches) launches += (int64_t)b.N * ((b.ntiles > 0) + (b.ntiles_ax > 0));
     P->info.launches_per_step = launches;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -597,13 +767,13 @@ int step_body(fdetd_plan_t P, void *vctx)
 {
     StepCtx &c = *(StepCtx *)vctx;
     const size_t eb = elem_bytes(P->precision);
-    for (int s = 0; s < c.n_steps; ++s)
-        for (size_t p = 0; p < P->probs.size(); ++p) {
-            const size_t block = 3 * P->probs[p].cells;
-            const void *j = c.j ? (const char *)c.j[p] + (size_t)(c.stride * s) * block * eb : nullptr;
-            int rc = enqueue_maxwell_step(P, P->probs[p], c.psi[p], j, s == c.n_steps - 1);
-            if (rc) return rc;
-        }
+    std::vector<const void *> js(P->probs.size());
+    for (int s = 0; s < c.n_steps; ++s) {
+        for (size_t p = 0; p < P->probs.size() && c.j; ++p)
+            js[p] = (const char *)c.j[p] + (size_t)(c.stride * s) * 3 * P->probs[p].cells * eb;
+        int rc = enqueue_maxwell_step(P, c.psi, c.j ? js.data() : nullptr, s == c.n_steps - 1);
+        if (rc) return rc;
+    }
     return FDETD_OK;
 }
 
@@ -611,12 +781,13 @@ int env_body(fdetd_plan_t P, void *vctx)
 {
     EnvCtx &c = *(EnvCtx *)vctx;
     const size_t rb = elem_bytes(P->precision) / 2;
-    for (int s = 0; s < c.n_steps; ++s)
-        for (size_t p = 0; p < P->probs.size(); ++p) {
-            const void *chi = (const char *)c.chi[p] + (size_t)(c.stride * s) * P->probs[p].cells * rb;
-            int rc = enqueue_envelope_step(P, P->probs[p], c.a[p], c.at[p], chi);
-            if (rc) return rc;
-        }
+    std::vector<const void *> chis(P->probs.size());
+    for (int s = 0; s < c.n_steps; ++s) {
+        for (size_t p = 0; p < P->probs.size(); ++p)
+            chis[p] = (const char *)c.chi[p] + (size_t)(c.stride * s) * P->probs[p].cells * rb;
+        int rc = enqueue_envelope_step(P, c.a, c.at, chis.data());
+        if (rc) return rc;
+    }
     return FDETD_OK;
 }
 }  // namespace
@@ -671,12 +842,13 @@ int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, i
     if (n_steps == 0) return FDETD_OK;
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         Prob &q = plan->probs[p];
-        if (plan->precision == FDETD_FP32C && q.last_state != psi[p]) {
+        if (plan->precision == FDETD_FP32C && q.last_state != psi[p] && !plan->adopt_next) {
             int rc = zero_device(plan, q.lo, 6 * q.cells * 8);
             if (rc) return rc;
         }
         q.last_state = psi[p];
     }
+    plan->adopt_next = false;
     StepCtx c{psi, j_half, j_step_blocks, n_steps};
     std::vector<const void *> key;
     key.push_back((const void *)(intptr_t)n_steps);
@@ -701,12 +873,13 @@ int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const
     if (n_steps == 0) return FDETD_OK;
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         Prob &q = plan->probs[p];
-        if (plan->precision == FDETD_FP32C && q.last_state != a[p]) {
+        if (plan->precision == FDETD_FP32C && q.last_state != a[p] && !plan->adopt_next) {
             int rc = zero_device(plan, q.lo, 2 * q.cells * 8);
             if (rc) return rc;
         }
         q.last_state = a[p];
     }
+    plan->adopt_next = false;
     EnvCtx c{a, a_tilde, chi_half, chi_step_planes, n_steps};
     std::vector<const void *> key;
     key.push_back((const void *)(intptr_t)n_steps);
@@ -757,6 +930,7 @@ int fdetd_import_state(fdetd_plan_t plan, const void *host_blob, size_t bytes)
         HIPCHK(plan, hipMemcpy(q.lo, (const char *)host_blob + off, np * q.cells * 8, hipMemcpyHostToDevice));
         off += np * q.cells * 8;
     }
+    plan->adopt_next = true;
     return FDETD_OK;
 }
 

@@ -47,6 +47,17 @@ def test_single_stage_random_state(m, order):
     assert rel_l2(got[0], want[0]) < 1e-13
 
 
+@pytest.mark.parametrize("m,order,N", [(1, 8, 4), (0, 16, 8)])
+def test_steps_without_source(m, order, N):
+    w = small(m, order, N, steps=2)
+    rng = np.random.default_rng(3 + m + order)
+    psi0 = [random_state(w, 0, rng)]
+    log(f"2 steps without current m={m} order={order} N={N}")
+    got, _ = gpu_maxwell(w, psi0, None, 2, flags=1)
+    want = oracle_maxwell(w, psi0, None, 2)
+    assert rel_l2(got[0], want[0]) < TOL64
+
+
 @pytest.mark.parametrize("m,order,N", [(0, 4, 8), (1, 16, 8), (2, 32, 8), (3, 8, 12), (1, 6, 4), (5, 10, 8)])
 def test_steps_with_source(m, order, N):
     w = small(m, order, N, steps=3)

@@ -1,0 +1,91 @@
+"""FP32-compensated path (float fields, float compensation words, FP64 arithmetic on the near-axis
+segments) against the FP64 oracle, and the state export/import that makes it resumable.
+
+Tolerance: the FP32 stencil sums carry a relative rounding error of a few float epsilons (6e-8) of the
+field per stage, growing ~sqrt(steps); after a few steps the relative L2 error is ~1e-6, so 2e-5 is
+the stated bound on these short runs.  The compensated accumulation keeps the stored state's rounding
+(otherwise eps/2 per step) out of the sum.
+"""
+import numpy as np
+import pytest
+
+from helpers import dev, gpu_envelope, gpu_maxwell, log, oracle_envelope, oracle_maxwell, rel_l2
+
+import paper_2605_12132_amd as F
+import paper_2605_12132_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 2e-5
+
+
+def small(m, order, N, nz=150, nr=37, steps=1):
+    dz = I.LAMBDA0 / 20
+    return I.Workload(f"small32_m{m}_o{order}", 0, [nz], [nr], [m], [order], N, dz, 2 * dz, 0.5 * dz, steps)
+
+
+@pytest.mark.parametrize("m,order,N", [(0, 8, 8), (1, 16, 8), (2, 32, 4), (1, 2, 1)])
+def test_fp32c_matches_oracle(m, order, N):
+    w = small(m, order, N, steps=3)
+    rng = np.random.default_rng(31 + m + order)
+    psi0 = [rng.uniform(-1, 1, (6, 37, 150)) + 1j * rng.uniform(-1, 1, (6, 37, 150))]
+    J = [0.1 * (rng.uniform(-1, 1, (3, 3, 37, 150)) + 1j * rng.uniform(-1, 1, (3, 3, 37, 150)))]
+    log(f"fp32c m={m} order={order} N={N}")
+    got, _ = gpu_maxwell(w, psi0, J, 3, precision=F.FP32C, flags=1)
+    want = oracle_maxwell(w, psi0, J, 3)
+    err = rel_l2(got[0], want[0])
+    log(f"  rel L2 {err:.3e}")
+    assert err < TOL32
+
+
+def test_fp32c_without_source_and_graph():
+    w = I.vacuum_pulse().shrink(steps=20)
+    psi0 = [I.initial_fields(w, 0)]
+    eager, _ = gpu_maxwell(w, psi0, None, 20, precision=F.FP32C)
+    graph, _ = gpu_maxwell(w, psi0, None, 20, precision=F.FP32C, flags=2)
+    assert np.array_equal(eager[0], graph[0])
+    want = oracle_maxwell(w, psi0, None, 20)
+    assert rel_l2(eager[0], want[0]) < TOL32
+
+
+def test_fp32c_envelope_matches_oracle():
+    dz = I.LAMBDA0 / 5
+    w = I.Workload("env32", 1, [203], [41], [0], [8], 4, dz, 0.2 * I.UM, 0.5 * dz, 10, seed=8,
+                   extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=10 * I.UM, chi0=1e-3, mod=0.05))
+    a0, at0 = I.envelope_initial(w)
+    chi = I.envelope_chi(w)
+    ga, gt, _ = gpu_envelope(w, [a0], [at0], [chi], 10, precision=F.FP32C, flags=1)
+    oa, ot = oracle_envelope(w, [a0], [at0], [chi], 10)
+    err = rel_l2(np.concatenate([ga[0].ravel(), gt[0].ravel()]), np.concatenate([oa[0].ravel(), ot[0].ravel()]))
+    assert err < TOL32
+
+
+def test_export_import_resume_is_bitwise():
+    """2K steps in one plan == K steps, export the compensation words, a new plan imports them, K steps."""
+    import torch
+    w = small(1, 8, 8, steps=4)
+    rng = np.random.default_rng(77)
+    psi0 = rng.uniform(-1, 1, (6, 37, 150)) + 1j * rng.uniform(-1, 1, (6, 37, 150))
+    J = 0.1 * (rng.uniform(-1, 1, (4, 3, 37, 150)) + 1j * rng.uniform(-1, 1, (4, 3, 37, 150)))
+    jd = dev(J, torch.complex64)
+    a = dev(psi0, torch.complex64)
+    pa = F.Plan(w.problems(), precision=F.FP32C, flags=1)
+    pa.step([a], [jd], n_steps=4)
+    b = dev(psi0, torch.complex64)
+    pb = F.Plan(w.problems(), precision=F.FP32C, flags=1)
+    pb.step([b], [jd[:2]], n_steps=2)
+    blob = pb.export_state()
+    assert len(blob) == 6 * 37 * 150 * 8
+    saved = b.clone()
+    pb.close()
+    c = saved.clone()
+    pc = F.Plan(w.problems(), precision=F.FP32C, flags=1)
+    pc.import_state(blob)                   # the next call adopts the words for its pointers
+    pc.step([c], [jd[2:]], n_steps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    # FP64 plans carry no state
+    p64 = F.Plan(w.problems(), precision=F.FP64, flags=1)
+    assert p64.export_state() == b""
+    for p in (pa, pc, p64):
+        p.close()
