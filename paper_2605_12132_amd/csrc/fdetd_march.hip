@@ -98,17 +98,25 @@ template <typename T> struct ibits;  // an integer of the same size, to move T t
 template <> struct ibits<double> { using I = unsigned long long; };
 template <> struct ibits<float2> { using I = unsigned long long; };
 template <> struct ibits<float> { using I = unsigned int; };
+// Element i of the array at p.  Callers pass a wave-uniform p (a row start, kept in scalar registers) and a
+// small per-lane i, so the loads use the scalar-base + 32-bit-vector-offset addressing form.
 template <typename T>
-__device__ __forceinline__ T gld(const void *p, size_t i)
+__device__ __forceinline__ T gld(const void *p, unsigned i)
 {
     using I = typename ibits<T>::I;
     return __builtin_bit_cast(T, ((const FDETD_GLOBAL I *)p)[i]);
 }
 template <typename T>
-__device__ __forceinline__ void gst(void *p, size_t i, T v)
+__device__ __forceinline__ void gst(void *p, unsigned i, T v)
 {
     using I = typename ibits<T>::I;
     ((FDETD_GLOBAL I *)p)[i] = __builtin_bit_cast(I, v);
+}
+// Start of row q of component c of a vector of planes of P elements each (row length nz S elements).
+template <typename E>
+__device__ __forceinline__ const E *row_ptr(const void *base, int c, size_t P, int nz, int S, int q)
+{
+    return (const E *)base + (size_t)c * P * S + (size_t)q * nz * S;
 }
 // The descriptor table and the per-row tables are written by the host before the launch and only read
 // here: through the constant address space they become scalar loads the compiler may hoist, instead of
@@ -169,13 +177,18 @@ struct Lane {
     }
 };
 
+// Element of row q of a plane for this lane.  A lane past the last grid column reads that column (clamped
+// index): its results are never stored and never reach another lane, so the value needs no mask.
+template <typename V>
+__device__ __forceinline__ typename elem<V>::E ldraw(const V *plane, int nz, int q, const Lane<V> &L)
+{
+    using E = typename elem<V>::E;
+    return gld<E>(row_ptr<E>(plane, 0, 0, nz, elem<V>::S, q), (unsigned)L.eidx);
+}
 template <typename V, typename AR>
 __device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const V *plane, int nz, int q, const Lane<V> &L)
 {
-    using E = typename elem<V>::E;
-    const E e = gld<E>(plane, (size_t)q * nz * elem<V>::S + L.eidx);
-    lv<AR, elem<V>::K> x = to_lv<AR>(e);
-    return L.col ? x : zero_lv<AR, elem<V>::K>();
+    return to_lv<AR>(ldraw<V>(plane, nz, q, L));
 }
 
 // Store one output value: out = psi + inc (inc already holds beta*Jbar + coef*H v), or, in the last stage
@@ -188,24 +201,81 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
     using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
     CDesc &D = *A.D;
-    const size_t o = (size_t)c * D.plane * S + (size_t)k * D.nz * S + L.eidx;
+    void *orow = (void *)row_ptr<E>(A.vout, c, D.plane, D.nz, S, k);
+    void *lrow = (void *)row_ptr<E>(D.lo, c, D.plane, D.nz, S, k);
+    const unsigned o = (unsigned)L.eidx;
     if constexpr (S == 1) {
         if constexpr (COMP) {
             float sx, ex, sy, ey;
             two_sum(psi_v.x, (float)(inc.p[0] + (AR)lo_v.x), sx, ex);
             two_sum(psi_v.y, (float)(inc.p[1] + (AR)lo_v.y), sy, ey);
             if (zero_slot) sx = sy = ex = ey = 0.f;
-            gst<float2>(A.vout, o, float2{sx, sy});
-            gst<float2>(D.lo, o, float2{ex, ey});
+            gst<float2>(orow, o, float2{sx, sy});
+            gst<float2>(lrow, o, float2{ex, ey});
             return;
         }
         float2 w{(float)((AR)psi_v.x + inc.p[0]), (float)((AR)psi_v.y + inc.p[1])};
         if (zero_slot) w = float2{0.f, 0.f};
-        gst<float2>(A.vout, o, w);
+        gst<float2>(orow, o, w);
     } else {
         double w = (double)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.0;
-        gst<double>(A.vout, o, w);
+        gst<double>(orow, o, w);
+    }
+}
+
+// Rows of input held in flight ahead of the row being computed.  One row of one wave is ~3 KB, and the
+// launches have about two waves per SIMD, so HBM latency is covered only with several rows outstanding.
+#ifndef FDETD_PREFETCH
+#define FDETD_PREFETCH 4
+#endif
+
+// x if c, else +0.  The mask goes through an empty asm so that the compiler cannot see it is all-ones or
+// zero: a select between a freshly loaded value and zero under a wave-uniform condition would otherwise
+// become a branch around the load, and the wave would wait at its join for every load in flight.
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> keep_if(bool c, lv<AR, K> x)
+{
+    unsigned m = c ? ~0u : 0u;
+    asm volatile("" : "+v"(m));
+    lv<AR, K> r;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if constexpr (sizeof(AR) == 8) {
+            const unsigned long long mm = ((unsigned long long)m << 32) | m;
+            r.p[i] = __builtin_bit_cast(AR, __builtin_bit_cast(unsigned long long, x.p[i]) & mm);
+        } else {
+            r.p[i] = __builtin_bit_cast(AR, __builtin_bit_cast(unsigned, x.p[i]) & m);
+        }
+    }
+    return r;
+}
+
+// March rows k0 .. k1-1: fill() loads the window of rows above k0, row(in, k, live) consumes the inputs of
+// row k, fetch(k) issues the loads of row k.  FDETD_PREFETCH rows are in flight.  The loop is unrolled by the ring length and each slot is
+// refilled in place once its row has been consumed: moving a slot whose loads are still in flight to
+// another register would make the wave wait for them.  For the same reason a slot holds the loaded words
+// only; masks, scale factors and sums are applied in row().  Rows past the segment end (fewer than
+// FDETD_PREFETCH) run on the clamped last row with live = false and store nothing.
+template <typename In, typename Fetch, typename Row, typename Fill>
+__device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &row, Fill &fill)
+{
+    In ring[FDETD_PREFETCH];
+#pragma unroll
+    for (int p = 0; p < FDETD_PREFETCH; ++p) ring[p] = fetch(k0 + p < k1 ? k0 + p : k1 - 1);
+    fill();
+    // Drain the first loads before the loop: the wait counter is in-order, and a loop entered with the
+    // ring's loads outstanding in another order than the loop issues them would have every row wait as if
+    // for its slot being the newest.  (vmcnt 0; expcnt and lgkmcnt left at their maxima 7 and 15.)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    for (int kb = k0; kb < k1; kb += FDETD_PREFETCH) {
+#pragma unroll
+        for (int p = 0; p < FDETD_PREFETCH; ++p) {
+            const int k = kb + p;
+            row(ring[p], k < k1 ? k : k1 - 1, k < k1);
+            const int kn = k + FDETD_PREFETCH;
+            ring[p] = fetch(kn < k1 ? kn : k1 - 1);
+        }
     }
 }
 
@@ -215,55 +285,76 @@ __device__ __forceinline__ typename elem<V>::E ld_elem(const void *base, int c, 
 {
     using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
-    return gld<E>(base, (size_t)c * D.plane * S + (size_t)q * D.nz * S + L.eidx);
+    return gld<E>(row_ptr<E>(base, c, D.plane, D.nz, S, q), (unsigned)L.eidx);
 }
 
 // One row of a plane as this lane contributes it to an LDS row with N_D columns of halo on each side:
-// its own element and (lanes < 2 N_D S) one halo element, in registers until put_row stores them.
+// its own element and (lanes < 2 N_D S) one halo element, with the matching current elements when the
+// row is w_N = psi + beta_in Jbar.  Raw loads; put_row forms and masks them.
 template <typename V>
 struct RowPart {
-    typename elem<V>::E own, halo;
+    typename elem<V>::E own, halo, jown, jhalo;
 };
-
-template <typename V, int ND, bool ADDJ>
-__device__ __forceinline__ RowPart<V> fetch_row(const V *plane, const V *jplane, double beta_in, int nz, int q,
-                                                int i0, const Lane<V> &L)
+// Where this lane's halo element comes from and where it goes in the LDS row (fixed for a tile).
+struct Halo {
+    int slot;      // LDS slot
+    unsigned idx;  // element index within a grid row (column 0 when outside the grid)
+    bool ok;       // a halo lane whose column lies inside the grid
+};
+template <typename V, int ND>
+__device__ __forceinline__ Halo halo_of(int i0, int nz, const Lane<V> &L)
+{
+    constexpr int S = elem<V>::S;
+    Halo h;
+    h.slot = L.lane < ND * S ? L.lane : WAVE + L.lane;
+    const int ii = i0 - ND + h.slot / S;
+    h.ok = L.lane < 2 * ND * S && ii >= 0 && ii < nz;
+    h.idx = (unsigned)((h.ok ? ii : 0) * S + h.slot % S);
+    return h;
+}
+template <typename V, bool ADDJ>
+__device__ __forceinline__ RowPart<V> fetch_row(const V *plane, const V *jplane, int nz, int q, const Lane<V> &L,
+                                                const Halo &H)
 {
     using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
-    const size_t rb = (size_t)q * nz * S;
-    auto get = [&](int e, bool ok) -> E {
-        E x = gld<E>(plane, rb + e);
-        if constexpr (ADDJ) {
-            const E j = gld<E>(jplane, rb + e);
-            if constexpr (S == 1) {
-                x.x += (float)beta_in * j.x;
-                x.y += (float)beta_in * j.y;
-            } else {
-                x += beta_in * j;
-            }
-        }
-        if (!ok) {
-            if constexpr (S == 1) x = float2{0.f, 0.f};
-            else x = 0.0;
-        }
-        return x;
-    };
+    const E *prow = row_ptr<E>(plane, 0, 0, nz, S, q);
     RowPart<V> r;
-    r.own = get(L.eidx, L.col);
-    const int h = L.lane < ND * S ? L.lane : WAVE + L.lane;  // LDS slot of this lane's halo element
-    const int ii = i0 - ND + h / S;                          // its column
-    const bool ok = L.lane < 2 * ND * S && ii >= 0 && ii < nz;
-    r.halo = get((ok ? ii : 0) * S + h % S, ok);
+    r.own = gld<E>(prow, (unsigned)L.eidx);
+    r.halo = gld<E>(prow, H.idx);
+    if constexpr (ADDJ) {
+        const E *jrow = row_ptr<E>(jplane, 0, 0, nz, S, q);
+        r.jown = gld<E>(jrow, (unsigned)L.eidx);
+        r.jhalo = gld<E>(jrow, H.idx);
+    } else {
+        r.jown = r.jhalo = E{};
+    }
     return r;
 }
-
-template <typename V, int ND>
-__device__ __forceinline__ void put_row(const RowPart<V> &r, const Lane<V> &L, typename elem<V>::E *row)
+// x + beta_in j in storage precision (the w_N input of a first stage), or x.
+template <bool ADDJ, typename E>
+__device__ __forceinline__ E form_in(E x, E j, double beta_in)
 {
+    if constexpr (ADDJ) {
+        if constexpr (std::is_same<E, float2>::value) {
+            x.x += (float)beta_in * j.x;
+            x.y += (float)beta_in * j.y;
+        } else {
+            x += beta_in * j;
+        }
+    }
+    return x;
+}
+// Columns outside the grid enter the z stencils as zeros.
+template <typename V, int ND, bool ADDJ>
+__device__ __forceinline__ void put_row(const RowPart<V> &r, double beta_in, const Lane<V> &L, const Halo &H,
+                                        typename elem<V>::E *row)
+{
+    using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
-    row[L.lane + ND * S] = r.own;
-    if (L.lane < 2 * ND * S) row[L.lane < ND * S ? L.lane : WAVE + L.lane] = r.halo;
+    const E own = form_in<ADDJ>(r.own, r.jown, beta_in), halo = form_in<ADDJ>(r.halo, r.jhalo, beta_in);
+    row[L.lane + ND * S] = L.col ? own : E{};
+    if (L.lane < 2 * ND * S) row[H.slot] = H.ok ? halo : E{};
 }
 
 template <typename AR, typename V>
@@ -292,54 +383,55 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
     const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
     const L_ zero = zero_lv<AR, K>();
 
-    L_ ax = zero;  // B_z on the axis: extrapolated for m = 0, else 0
-    if (D.m == 0 && k0 < ND) {
-#pragma unroll
-        for (int q = 1; q <= ND; ++q) ax = fmav((AR)D.cax[q - 1], ldrow<V, AR>(Bz, nz, q, L), ax);
-    }
-    // staggered-grid window rows q = k0 - N_D + 1 + t: row 0 is the axis (B_z: ax; rho_(-) B_theta: 0),
-    // rows q < 0 mirror row -q with the component's sign, rows >= nr are 0.  All loads are issued first
-    // (clamped, valid rows), the rules are applied as selects afterwards.
     L_ Wz[2 * ND], Wg[2 * ND];
+    // filled after the ring's first loads are issued, so that both arrive within one latency
+    auto fill = [&]() {
+        L_ ax = zero;  // B_z on the axis: extrapolated for m = 0, else 0
+        if (D.m == 0 && k0 < ND) {
 #pragma unroll
-    for (int t = 0; t < 2 * ND - 1; ++t) {
-        const int q = k0 - ND + 1 + t;
-        const int r = min(q < 0 ? -q : q, nr - 1);
-        Wz[t] = ldrow<V, AR>(Bz, nz, r, L);
-        Wg[t] = ldrow<V, AR>(Bth, nz, r, L);
-    }
+            for (int q = 1; q <= ND; ++q) ax = fmav((AR)D.cax[q - 1], ldrow<V, AR>(Bz, nz, q, L), ax);
+        }
+        // staggered-grid window rows q = k0 - N_D + 1 + t: row 0 is the axis (B_z: ax; rho_(-) B_theta: 0),
+        // rows q < 0 mirror row -q with the component's sign, rows >= nr are 0.  All loads are issued first
+        // (clamped, valid rows), the rules are applied as selects afterwards.
 #pragma unroll
-    for (int t = 0; t < 2 * ND - 1; ++t) {
-        const int q = k0 - ND + 1 + t;
-        const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
-        Wz[t] = q >= nr ? zero : (q == 0 ? ax : sz * Wz[t]);
-        Wg[t] = (q >= nr || q == 0) ? zero : ((AR)q * dr * sg) * Wg[t];
-    }
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            const int q = k0 - ND + 1 + t;
+            const int r = min(q < 0 ? -q : q, nr - 1);
+            Wz[t] = ldrow<V, AR>(Bz, nz, r, L);
+            Wg[t] = ldrow<V, AR>(Bth, nz, r, L);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            const int q = k0 - ND + 1 + t;
+            const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
+            Wz[t] = q >= nr ? zero : (q == 0 ? ax : sz * Wz[t]);
+            Wg[t] = (q >= nr || q == 0) ? zero : ((AR)q * dr * sg) * Wg[t];
+        }
+    };
     const int own = L.lane + ND * S;
     using E = typename elem<V>::E;
-    // everything row k needs from memory, fetched one row ahead of its use
+    const Halo H = halo_of<V, ND>(i0, nz, L);
+    // everything row k needs from memory: loads of valid rows only (indices clamped), formed in row()
     struct In {
-        L_ wz, wg, j0, j1, j2;
+        E bz, bt, j0, j1, j2;
         RowPart<V> th, br;
         E p0, p1, p2;
         float2 l0, l1, l2;
     };
-    // Branch-free: every load reads a valid row (indices clamped), values are selected afterwards, so the
-    // loop body is one basic block and the next row's loads stay in flight during this row's arithmetic.
     auto fetch = [&](int k) -> In {
         In x;
         const int qn = k + ND;
         const int qc = qn < nr ? qn : nr - 1;
-        const L_ bz = ldrow<V, AR>(Bz, nz, qc, L), bt = ldrow<V, AR>(Bth, nz, qc, L);
-        x.wz = qn < nr ? bz : zero;
-        x.wg = qn < nr ? ((AR)qn * dr) * bt : zero;
-        x.th = fetch_row<V, ND, false>(Bth, nullptr, 0.0, nz, k, i0, L);
-        x.br = fetch_row<V, ND, false>(Br, nullptr, 0.0, nz, k, i0, L);
-        x.j0 = x.j1 = x.j2 = zero;
+        x.bz = ldraw<V>(Bz, nz, qc, L);
+        x.bt = ldraw<V>(Bth, nz, qc, L);
+        x.th = fetch_row<V, false>(Bth, nullptr, nz, k, L, H);
+        x.br = fetch_row<V, false>(Br, nullptr, nz, k, L, H);
+        x.j0 = x.j1 = x.j2 = E{};
         if constexpr (SRC) {
-            x.j0 = ldrow<V, AR>((const V *)A.jr, nz, k, L);
-            x.j1 = ldrow<V, AR>((const V *)A.jt, nz, k, L);
-            x.j2 = ldrow<V, AR>((const V *)A.jz, nz, k, L);
+            x.j0 = ldraw<V>((const V *)A.jr, nz, k, L);
+            x.j1 = ldraw<V>((const V *)A.jt, nz, k, L);
+            x.j2 = ldraw<V>((const V *)A.jz, nz, k, L);
         }
         x.p0 = ld_elem<V>(A.psi, ER, k, D, L);
         x.p1 = ld_elem<V>(A.psi, ETH, k, D, L);
@@ -352,14 +444,12 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         }
         return x;
     };
-    In nx = fetch(k0);
-    for (int k = k0; k < k1; ++k) {
-        const In cu = nx;
-        nx = fetch(k + 1 < k1 ? k + 1 : k);  // the last iteration re-reads its own row, unused
-        Wz[2 * ND - 1] = cu.wz;
-        Wg[2 * ND - 1] = cu.wg;
-        put_row<V, ND>(cu.th, L, lds[0]);
-        put_row<V, ND>(cu.br, L, lds[1]);
+    auto row = [&](const In &cu, int k, bool live) {
+        const int qn = k + ND;  // the window's new row
+        Wz[2 * ND - 1] = keep_if(qn < nr, to_lv<AR>(cu.bz));
+        Wg[2 * ND - 1] = keep_if(qn < nr, ((AR)qn * dr) * to_lv<AR>(cu.bt));
+        put_row<V, ND, false>(cu.th, 0.0, L, H, lds[0]);
+        put_row<V, ND, false>(cu.br, 0.0, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
         // D_z^(+) at primary column i: staggered columns i + j and i - j + 1
@@ -382,11 +472,11 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const L_ t0 = times_i(mm * ris, bzk);  // lane swaps: every lane of the wave takes part
         const L_ t2 = times_i(mm * rip, br);
         __syncthreads();
-        if (L.col) {
+        if (L.col && live) {
             const AR coef = (AR)A.coef, beta = (AR)A.beta;
-            const L_ i0v = fmav(beta, cu.j0, coef * (t0 - zth));
-            const L_ i1v = fmav(beta, cu.j1, coef * (zr - rz));
-            const L_ i2v = fmav(beta, cu.j2, coef * (rip * rg - t2));
+            const L_ i0v = fmav(beta, to_lv<AR>(cu.j0), coef * (t0 - zth));
+            const L_ i1v = fmav(beta, to_lv<AR>(cu.j1), coef * (zr - rz));
+            const L_ i2v = fmav(beta, to_lv<AR>(cu.j2), coef * (rip * rg - t2));
             store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, cu.p0, cu.l0);
             store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, cu.p1, cu.l1);
             store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, cu.p2, cu.l2);
@@ -396,7 +486,8 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             Wz[t] = Wz[t + 1];
             Wg[t] = Wg[t + 1];
         }
-    }
+    };
+    march_rows<In>(k0, k1, fetch, row, fill);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -427,27 +518,31 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         if constexpr (FIRST) x = fmav(bin, ldrow<V, AR>(jf, nz, q, L), x);
         return x;
     };
-    // primary-grid window rows q = k0 - N_D + t: rows q < 0 mirror row -1-q with the component's sign,
-    // rows >= nr are 0; loads first (clamped rows), rules as selects.
     L_ Wz[2 * ND], Wg[2 * ND];
+    // filled after the ring's first loads are issued, so that both arrive within one latency
+    auto fill = [&]() {
+        // primary-grid window rows q = k0 - N_D + t: rows q < 0 mirror row -1-q with the component's sign,
+        // rows >= nr are 0; loads first (clamped rows), rules as selects.
 #pragma unroll
-    for (int t = 0; t < 2 * ND - 1; ++t) {
-        const int q = k0 - ND + t;
-        const int r = min(q < 0 ? -1 - q : q, nr - 1);
-        Wz[t] = ldw(Ez, Jz, r);
-        Wg[t] = ldw(Eth, Jt, r);
-    }
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            const int q = k0 - ND + t;
+            const int r = min(q < 0 ? -1 - q : q, nr - 1);
+            Wz[t] = ldw(Ez, Jz, r);
+            Wg[t] = ldw(Eth, Jt, r);
+        }
 #pragma unroll
-    for (int t = 0; t < 2 * ND - 1; ++t) {
-        const int q = k0 - ND + t;
-        const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
-        Wz[t] = q >= nr ? zero : sz * Wz[t];
-        Wg[t] = q >= nr ? zero : ((((AR)q + (AR)0.5) * dr) * sg) * Wg[t];
-    }
+        for (int t = 0; t < 2 * ND - 1; ++t) {
+            const int q = k0 - ND + t;
+            const AR sz = q < 0 ? pS : (AR)1, sg = q < 0 ? pA : (AR)1;
+            Wz[t] = q >= nr ? zero : sz * Wz[t];
+            Wg[t] = q >= nr ? zero : ((((AR)q + (AR)0.5) * dr) * sg) * Wg[t];
+        }
+    };
     const int own = L.lane + ND * S;
     using E = typename elem<V>::E;
+    const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
-        L_ wz, wg;
+        E ez, et, jz, jt;
         RowPart<V> th, er;
         E p0, p1, p2;
         float2 l0, l1, l2;
@@ -456,11 +551,15 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         In x;
         const int qn = k + ND - 1;
         const int qc = qn < nr ? qn : nr - 1;
-        const L_ ez = ldw(Ez, Jz, qc), et = ldw(Eth, Jt, qc);
-        x.wz = qn < nr ? ez : zero;
-        x.wg = qn < nr ? (((AR)qn + (AR)0.5) * dr) * et : zero;
-        x.th = fetch_row<V, ND, FIRST>(Eth, Jt, A.beta_in, nz, k, i0, L);
-        x.er = fetch_row<V, ND, FIRST>(Er, Jr, A.beta_in, nz, k, i0, L);
+        x.ez = ldraw<V>(Ez, nz, qc, L);
+        x.et = ldraw<V>(Eth, nz, qc, L);
+        x.jz = x.jt = E{};
+        if constexpr (FIRST) {
+            x.jz = ldraw<V>(Jz, nz, qc, L);
+            x.jt = ldraw<V>(Jt, nz, qc, L);
+        }
+        x.th = fetch_row<V, FIRST>(Eth, Jt, nz, k, L, H);
+        x.er = fetch_row<V, FIRST>(Er, Jr, nz, k, L, H);
         x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
         x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
         x.p2 = ld_elem<V>(A.psi, BZ, k, D, L);
@@ -472,14 +571,17 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         }
         return x;
     };
-    In nx = fetch(k0);
-    for (int k = k0; k < k1; ++k) {
-        const In cu = nx;
-        nx = fetch(k + 1 < k1 ? k + 1 : k);
-        Wz[2 * ND - 1] = cu.wz;
-        Wg[2 * ND - 1] = cu.wg;
-        put_row<V, ND>(cu.th, L, lds[0]);
-        put_row<V, ND>(cu.er, L, lds[1]);
+    auto row = [&](const In &cu, int k, bool live) {
+        const int qn = k + ND - 1;  // the window's new row
+        L_ ez = to_lv<AR>(cu.ez), et = to_lv<AR>(cu.et);
+        if constexpr (FIRST) {
+            ez = fmav(bin, to_lv<AR>(cu.jz), ez);
+            et = fmav(bin, to_lv<AR>(cu.jt), et);
+        }
+        Wz[2 * ND - 1] = keep_if(qn < nr, ez);
+        Wg[2 * ND - 1] = keep_if(qn < nr, (((AR)qn + (AR)0.5) * dr) * et);
+        put_row<V, ND, FIRST>(cu.th, A.beta_in, L, H, lds[0]);
+        put_row<V, ND, FIRST>(cu.er, A.beta_in, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
         // D_z^(-) at staggered column i: primary columns i + j - 1 and i - j
@@ -496,13 +598,13 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             rz = fmav(ar, Wz[ND + j - 1] - Wz[ND - j], rz);
             rg = fmav(ar, Wg[ND + j - 1] - Wg[ND - j], rg);
         }
-        const L_ erk = to_lv<AR>(cu.er.own);
+        const L_ erk = to_lv<AR>(form_in<FIRST>(cu.er.own, cu.er.jown, A.beta_in));
         const L_ ezk = Wz[ND];
         const AR rip = (AR)cld(D.rinv_p, k), ris = (AR)cld(D.rinv_s, k);
         const L_ t0 = times_i(mm * rip, ezk);
         const L_ t2 = times_i(mm * ris, erk);
         __syncthreads();
-        if (L.col) {
+        if (L.col && live) {
             const AR coef = (AR)A.coef;
             store_out<V, AR, COMP>(A, BR, k, L, coef * (zth - t0), false, cu.p0, cu.l0);
             store_out<V, AR, COMP>(A, BTH, k, L, coef * (rz - zr), k == 0, cu.p1, cu.l1);
@@ -513,7 +615,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wz[t] = Wz[t + 1];
             Wg[t] = Wg[t + 1];
         }
-    }
+    };
+    march_rows<In>(k0, k1, fetch, row, fill);
 }
 
 // Tile of block b: tiles are numbered problem by problem, (half,) segment, strip -- strips fastest -- and
@@ -597,50 +700,52 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
     const AR pS = (AR)D.pS;
     constexpr int W = 2 * ND + 1;
     L_ Wa[W];
+    // filled after the ring's first loads are issued, so that both arrive within one latency
+    auto fill = [&]() {
 #pragma unroll
-    for (int t = 0; t < W - 1; ++t) {
-        const int q = k0 - ND + t;
-        Wa[t] = ldrow<V, AR>(va, nz, min(q < 0 ? -1 - q : q, nr - 1), L);
-    }
+        for (int t = 0; t < W - 1; ++t) {
+            const int q = k0 - ND + t;
+            Wa[t] = ldrow<V, AR>(va, nz, min(q < 0 ? -1 - q : q, nr - 1), L);
+        }
 #pragma unroll
-    for (int t = 0; t < W - 1; ++t) {
-        const int q = k0 - ND + t;
-        Wa[t] = q >= nr ? zero : (q < 0 ? pS : (AR)1) * Wa[t];
-    }
+        for (int t = 0; t < W - 1; ++t) {
+            const int q = k0 - ND + t;
+            Wa[t] = q >= nr ? zero : (q < 0 ? pS : (AR)1) * Wa[t];
+        }
+    };
     const AR k2 = (AR)(2.0 * D.k0);
     const int own = L.lane + ND * S;
     const int cc = L.col ? L.i : nz - 1;
+    const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
-        L_ wa, tin;
+        E an, tin;
         RowPart<V> a;
-        AR chi;
+        R chi;
         E pa, pt;
         float2 la, lt;
     };
     auto fetch = [&](int k) -> In {
         In x;
         const int qn = k + ND;
-        const L_ an = ldrow<V, AR>(va, nz, qn < nr ? qn : nr - 1, L);
-        x.wa = qn < nr ? an : zero;
-        x.a = fetch_row<V, ND, false>(va, nullptr, 0.0, nz, k, i0, L);
-        x.tin = ldrow<V, AR>(vt, nz, k, L);
-        x.chi = (AR)gld<R>(A.chi, (size_t)k * nz + cc);
-        const size_t o = (size_t)k * nz * S + L.eidx;
-        x.pa = gld<E>(A.psi_a, o);
-        x.pt = gld<E>(A.psi_t, o);
+        x.an = ldraw<V>(va, nz, qn < nr ? qn : nr - 1, L);
+        x.a = fetch_row<V, false>(va, nullptr, nz, k, L, H);
+        x.tin = ldraw<V>(vt, nz, k, L);
+        x.chi = gld<R>((const R *)A.chi + (size_t)k * nz, (unsigned)cc);
+        const unsigned o = (unsigned)L.eidx;
+        x.pa = gld<E>(row_ptr<E>(A.psi_a, 0, 0, nz, S, k), o);
+        x.pt = gld<E>(row_ptr<E>(A.psi_t, 0, 0, nz, S, k), o);
         x.la = x.lt = float2{0.f, 0.f};
         if constexpr (COMP) {
-            x.la = gld<float2>(D.lo, o);
-            x.lt = gld<float2>(D.lo, D.plane + o);
+            x.la = gld<float2>(row_ptr<float2>(D.lo, 0, D.plane, nz, 1, k), o);
+            x.lt = gld<float2>(row_ptr<float2>(D.lo, 1, D.plane, nz, 1, k), o);
         }
         return x;
     };
-    In nx = fetch(k0);
-    for (int k = k0; k < k1; ++k) {
-        const In cu = nx;
-        nx = fetch(k + 1 < k1 ? k + 1 : k);
-        Wa[W - 1] = cu.wa;
-        put_row<V, ND>(cu.a, L, lds);
+    auto row = [&](const In &cu, int k, bool live) {
+        const int qn = k + ND;
+        Wa[W - 1] = keep_if(qn < nr, to_lv<AR>(cu.an));
+        const L_ tin = to_lv<AR>(cu.tin);
+        put_row<V, ND, false>(cu.a, 0.0, L, H, lds);
         __syncthreads();
         const L_ a0 = Wa[ND];
         L_ lz = (AR)D.bz[0] * a0, d1z = zero;
@@ -657,14 +762,15 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
             lr = fmav((AR)D.br[j], rp + rm, lr);
             d1r = fmav((AR)D.drc[j - 1], rp - rm, d1r);
         }
-        const AR pot = (AR)cld(D.m2rinv2, k) + cu.chi;
-        const L_ rot = times_i(k2, d1z + cu.tin);
+        const AR pot = (AR)cld(D.m2rinv2, k) + (AR)cu.chi;
+        const L_ rot = times_i(k2, d1z + tin);
         __syncthreads();
-        if (L.col) {
+        if (L.col && live) {
             const L_ dtv = lr + (AR)cld(D.rinv_p, k) * d1r + lz - pot * a0 + rot;
             const AR coef = (AR)A.coef;
-            const L_ ia = coef * cu.tin, it = coef * dtv;
-            const size_t o = (size_t)k * nz * S + L.eidx;
+            const L_ ia = coef * tin, it = coef * dtv;
+            const unsigned o = (unsigned)L.eidx;
+            void *ra = (void *)row_ptr<E>(A.out_a, 0, 0, nz, S, k), *rt = (void *)row_ptr<E>(A.out_t, 0, 0, nz, S, k);
             if constexpr (S == 1) {
                 if constexpr (COMP) {
                     float s0, e0, s1, e1, s2, e2, s3, e3;
@@ -672,22 +778,23 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
                     two_sum(cu.pa.y, (float)(ia.p[1] + (AR)cu.la.y), s1, e1);
                     two_sum(cu.pt.x, (float)(it.p[0] + (AR)cu.lt.x), s2, e2);
                     two_sum(cu.pt.y, (float)(it.p[1] + (AR)cu.lt.y), s3, e3);
-                    gst<float2>(A.out_a, o, float2{s0, s1});
-                    gst<float2>(A.out_t, o, float2{s2, s3});
-                    gst<float2>(D.lo, o, float2{e0, e1});
-                    gst<float2>(D.lo, D.plane + o, float2{e2, e3});
+                    gst<float2>(ra, o, float2{s0, s1});
+                    gst<float2>(rt, o, float2{s2, s3});
+                    gst<float2>((void *)row_ptr<float2>(D.lo, 0, D.plane, nz, 1, k), o, float2{e0, e1});
+                    gst<float2>((void *)row_ptr<float2>(D.lo, 1, D.plane, nz, 1, k), o, float2{e2, e3});
                 } else {
-                    gst<float2>(A.out_a, o, float2{(float)((AR)cu.pa.x + ia.p[0]), (float)((AR)cu.pa.y + ia.p[1])});
-                    gst<float2>(A.out_t, o, float2{(float)((AR)cu.pt.x + it.p[0]), (float)((AR)cu.pt.y + it.p[1])});
+                    gst<float2>(ra, o, float2{(float)((AR)cu.pa.x + ia.p[0]), (float)((AR)cu.pa.y + ia.p[1])});
+                    gst<float2>(rt, o, float2{(float)((AR)cu.pt.x + it.p[0]), (float)((AR)cu.pt.y + it.p[1])});
                 }
             } else {
-                gst<double>(A.out_a, o, (double)((AR)cu.pa + ia.p[0]));
-                gst<double>(A.out_t, o, (double)((AR)cu.pt + it.p[0]));
+                gst<double>(ra, o, (double)((AR)cu.pa + ia.p[0]));
+                gst<double>(rt, o, (double)((AR)cu.pt + it.p[0]));
             }
         }
 #pragma unroll
         for (int t = 0; t < W - 1; ++t) Wa[t] = Wa[t + 1];
-    }
+    };
+    march_rows<In>(k0, k1, fetch, row, fill);
 }
 
 template <typename V, int ND, bool COMP, bool AXIS>
