@@ -27,6 +27,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "field cell-updates/s (cells×modes×steps/s), FP64 vs FP32-comp at fixed error"
+# HBM traffic of the stage kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this benchmark, with the
+# hash of the kernel sources it was taken on; reported only while the sources still match.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_maxwell_stage_current_driven_2048x256_o16_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_12132_amd", "csrc", f)
+                  for f in ("fdetd_march.hip", "fdetd_tiles.h", "fdetd_internal.h", "fdetd_plan.cpp")]
 
 
 def log(*a):
@@ -108,13 +113,22 @@ def run_path(w, precision, steps, warmup, J, use_graph=True):
     return psi, ms, plan_s, info
 
 
-def profile_pass(w, precision, steps, J):
-    """Eager pass with HIP events around every stage kernel: average duration and algorithmic bytes."""
+def profile_pass(w, precision, steps, J, seg_rows):
+    """Eager pass with HIP events around every stage kernel: average duration and algorithmic bytes.  The
+    plan is given the segment length the timed plan's autotuning picked, so both run the same tiling."""
     import torch
     import paper_2605_12132_amd as F
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
-    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
+    old = os.environ.get("FDETD_SEG_ROWS")
+    os.environ["FDETD_SEG_ROWS"] = str(seg_rows)
+    try:
+        plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
+    finally:
+        if old is None:
+            del os.environ["FDETD_SEG_ROWS"]
+        else:
+            os.environ["FDETD_SEG_ROWS"] = old
     plan.step(psi, [j[:steps] for j in J], n_steps=steps)
     info = plan.query()
     plan.close()
@@ -123,8 +137,52 @@ def profile_pass(w, precision, steps, J):
     bytes_per_launch = info["profiled_bytes"] / n
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_maxwell_stage",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c"), kernel="k_maxwell_stage",
                 launches=n, avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch))
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision_tag):
+    """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration) from
+    the committed PMC summary, or None when it is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_") and ":" in line)
+    if fields.get("traffic_source_hash", "").strip() != kernel_source_hash():
+        return None
+    v = fields.get(f"traffic_bytes_per_launch_{precision_tag}")
+    return int(float(v)) if v else None
+
+
+def copy_calibration(n_bytes=1 << 30, reps=10):
+    """A plain device-to-device copy of n_bytes, reps times: the known-size kernel against which the
+    FETCH_SIZE / WRITE_SIZE counters are scaled, and the HBM rate a plain copy reaches on this GPU."""
+    import torch
+    a = torch.empty(n_bytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    return dict(copy_bytes_read=n_bytes, copy_bytes_written=n_bytes, reps=reps, ms_per_copy=ms,
+                copy_GBs=2 * n_bytes / (ms * 1e-3) / 1e9)
 
 
 def fp32c_errors(w, psi64, psi32):
@@ -180,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the problems of this workload are "
@@ -190,6 +250,9 @@ def main():
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
 
+    if args.calibrate_copy:
+        print(json.dumps(copy_calibration()), flush=True)
+        return
     w = I.current_driven()
     K, W = args.steps, args.warmup
     cells = w.cells()
@@ -203,7 +266,7 @@ def main():
     psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph)
     rate64 = cells * K / (ms64 * 1e-3)
     log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s (plan {plan_s:.2f} s, dt*rho {info64['dt_rho_max']:.3f})")
-    roof64 = profile_pass(w, F.FP64, args.profile_steps, J64)
+    roof64 = profile_pass(w, F.FP64, args.profile_steps, J64, info64["seg_rows"])
     log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
 
     fp32c = None
@@ -211,13 +274,15 @@ def main():
         J32 = [j.to(torch.complex64) for j in J64]
         del J64
         torch.cuda.empty_cache()
-        psi32, ms32, _, _ = run_path(w, F.FP32C, K, W, J32, not args.no_graph)
+        psi32, ms32, _, info32 = run_path(w, F.FP32C, K, W, J32, not args.no_graph)
         rate32 = cells * K / (ms32 * 1e-3)
-        roof32 = profile_pass(w, F.FP32C, args.profile_steps, J32)
+        roof32 = profile_pass(w, F.FP32C, args.profile_steps, J32, info32["seg_rows"])
         errs = fp32c_errors(w, psi64, psi32)
         log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, errors {errs}")
         fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
-                     error_vs_fp64_after_steps=W + K, **errs)
+                     error_vs_fp64_after_steps=W + K, **errs,
+                     tiling=dict(seg_rows=info32["seg_rows"], seg_rows_axis=info32["seg_rows_axis"],
+                                 autotune_ms=round(info32["autotune_ms"], 1)))
         del J32
     else:
         del J64
@@ -234,6 +299,7 @@ def main():
                    "graph": not args.no_graph, "parallelism": "single GPU, modes batched in one plan"},
         "roofline": roof64,
         "cpu_baseline": cpu,
+        "tiling": dict(seg_rows=info64["seg_rows"], autotune_ms=round(info64["autotune_ms"], 1)),
         "fp32c": fp32c,
     }
     print(json.dumps(out), flush=True)

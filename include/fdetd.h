@@ -62,6 +62,7 @@ extern "C" {
 #define FDETD_PLAN_SKIP_STABILITY 1u  /* do not estimate the spectral radius at plan time           */
 #define FDETD_PLAN_USE_GRAPH      2u  /* fdetd_step / envelope_step replay a captured hipGraph        */
 #define FDETD_PLAN_PROFILE        4u  /* time every stage kernel with HIP events (not with USE_GRAPH)  */
+#define FDETD_PLAN_NO_AUTOTUNE    8u  /* keep the default tiling instead of timing candidates at plan time */
 
 typedef struct fdetd_plan_s *fdetd_plan_t;
 
@@ -89,6 +90,10 @@ typedef struct {
     int64_t profiled_launches;
     double profiled_ms;          /* sum of their durations                                       */
     double profiled_bytes;       /* sum of their algorithmic HBM bytes                           */
+    /* tiling of the first launch batch: rho rows per marching segment of the main launch and of the
+     * FP32C near-axis launch (0 without one), and the plan-time autotuning that picked them (0 ms: none) */
+    int32_t seg_rows, seg_rows_axis;
+    double autotune_ms;
 } fdetd_plan_info;
 
 /* Build a plan for n_probs problems (all FDETD_MAXWELL or all FDETD_ENVELOPE).

@@ -82,8 +82,10 @@ constexpr int kMaxBatch = 64;  // problems per launch (pointer arrays travel in 
 // Static per-problem facts, uploaded once at plan time.
 struct ProbDesc {
     int nz, nr, m, taylor;
-    int seg_rows, nseg, nstrip;              // tiling: strips of z columns x segments of seg_rows rows
-    int nseg_ax;                             // FP32C: leading segments (k0 < 2 N_D) run in FP64 arithmetic
+    int nstrip;                              // tiling: strips of z columns ...
+    int seg_rows, nseg;                      // ... x segments of seg_rows rows from row ax_rows down (main launch)
+    int seg_ax, nseg_ax, ax_rows;            // FP32C: rows 0 .. ax_rows-1 (= 2 N_D) in segments of seg_ax rows,
+                                             // FP64 arithmetic (near-axis launch); FP64 plans: 0, 0, 0
     int tile_begin, tile_begin_ax;           // first tile of this problem in the main / near-axis launch
     size_t plane;                            // nz * nr
     double dr, pS, k0;

@@ -637,8 +637,8 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
     return p;
 }
 
-// AXIS = false: segments nseg_ax .. nseg-1 in the storage precision; AXIS = true (FP32 storage only): the
-// leading nseg_ax segments, whose stencils reach the axis and its 1/rho factors, in FP64 arithmetic.
+// AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage only): rows
+// 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the axis and its 1/rho factors, in FP64 arithmetic.
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP, bool AXIS>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {

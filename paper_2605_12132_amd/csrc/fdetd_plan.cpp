@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdarg>
@@ -49,6 +50,7 @@ struct Prob {
 // separately): table entries [d0, d0 + count).
 struct Batch {
     int nd, N, d0, count, ntiles, ntiles_ax;
+    int seg;                   // rows per marching segment of the main launch
     double dt;
     std::vector<int> members;  // user indices, in table order
 };
@@ -72,6 +74,10 @@ struct fdetd_plan_s {
     size_t ev_used = 0;
     std::vector<double> ev_bytes;
     bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
+    // FP32C: the near-axis launch of a stage runs on a second stream beside the main launch
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<int> seg_rows;  // per launch batch: rows per marching segment of the main launch
 };
 
 namespace {
@@ -187,6 +193,35 @@ int zero_device(fdetd_plan_t P, void *ptr, size_t bytes)
     return FDETD_OK;
 }
 
+// One stage of one launch batch.  FP32C: the near-axis launch goes to the side stream and runs beside
+// the main launch (both read only the stage's inputs and each writes its own rows); the plan's stream
+// waits for it before the next stage.  Under graph capture the fork and join become graph edges.
+int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A)
+{
+    const int prec = prec_code(P->precision);
+    auto go = [&](hipStream_t st) {
+        return P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, st) : launch_envelope_march(prec, b.nd, A, st);
+    };
+    const bool fork = b.ntiles_ax && b.ntiles && P->side;
+    if (b.ntiles_ax) {
+        A.axis_launch = 1;
+        A.ntiles = b.ntiles_ax;
+        if (fork) {
+            HIPCHK(P, hipEventRecord(P->ev_fork, P->stream));
+            HIPCHK(P, hipStreamWaitEvent(P->side, P->ev_fork, 0));
+        }
+        HIPCHK(P, go(fork ? P->side : P->stream));
+        if (fork) HIPCHK(P, hipEventRecord(P->ev_join, P->side));
+    }
+    if (b.ntiles) {
+        A.axis_launch = 0;
+        A.ntiles = b.ntiles;
+        HIPCHK(P, go(P->stream));
+    }
+    if (fork) HIPCHK(P, hipStreamWaitEvent(P->stream, P->ev_join, 0));
+    return FDETD_OK;
+}
+
 // One Maxwell step of every problem: stage the currents, N batched Horner stages, the axis rule.
 int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j, int last_step_of_call)
 {
@@ -230,16 +265,7 @@ int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j,
             const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
             int rc = profile_begin(P, bytes);
             if (rc) return rc;
-            if (b.ntiles_ax) {
-                A.axis_launch = 1;
-                A.ntiles = b.ntiles_ax;
-                HIPCHK(P, launch_maxwell_march(prec, b.nd, A, P->stream));
-            }
-            if (b.ntiles) {
-                A.axis_launch = 0;
-                A.ntiles = b.ntiles;
-                HIPCHK(P, launch_maxwell_march(prec, b.nd, A, P->stream));
-            }
+            if ((rc = launch_stage(P, b, A))) return rc;
             if ((rc = profile_end(P))) return rc;
         }
     }
@@ -261,7 +287,6 @@ int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j,
 
 int enqueue_envelope_step(fdetd_plan_t P, void *const *a, void *const *at, const void *const *chi)
 {
-    const int prec = prec_code(P->precision);
     const size_t eb = elem_bytes(P->precision);
     for (const Batch &b : P->batches) {
         BatchArgs A;
@@ -286,16 +311,7 @@ int enqueue_envelope_step(fdetd_plan_t P, void *const *a, void *const *at, const
             const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 2 * cells * 8 : 0.0);
             int rc = profile_begin(P, bytes);
             if (rc) return rc;
-            if (b.ntiles_ax) {
-                A.axis_launch = 1;
-                A.ntiles = b.ntiles_ax;
-                HIPCHK(P, launch_envelope_march(prec, b.nd, A, P->stream));
-            }
-            if (b.ntiles) {
-                A.axis_launch = 0;
-                A.ntiles = b.ntiles;
-                HIPCHK(P, launch_envelope_march(prec, b.nd, A, P->stream));
-            }
+            if ((rc = launch_stage(P, b, A))) return rc;
             if ((rc = profile_end(P))) return rc;
         }
     }
@@ -311,21 +327,32 @@ int enqueue_envelope_step(fdetd_plan_t P, void *const *a, void *const *at, const
 }
 
 // Rows per marching segment: long segments load each rho-stencilled row once per segment (the window
-// warm-up costs 2 N_D - 1 extra rows), short ones give more wavefronts.  Aim at ~8192 wavefronts per launch.
-int pick_seg_rows(int64_t row_strips_total)
+// warm-up costs 2 N_D - 1 extra rows), short ones give more wavefronts.  Default before autotuning: the
+// longest segment (8 .. 64 rows) that still gives every SIMD of the chip (1024) one wavefront.
+int forced_seg_rows()
 {
     if (const char *e = std::getenv("FDETD_SEG_ROWS")) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 4096) return v;
     }
+    return 0;
+}
+int default_seg_rows(int64_t row_strips_total)
+{
+    if (const int f = forced_seg_rows()) return f;
     int s = 8;
-    while (s < 64 && row_strips_total / (2 * s) >= 8192) s *= 2;
+    while (s < 64 && row_strips_total / (2 * s) >= 1024) s *= 2;
     return s;
 }
+constexpr int kSegAxis = 8;  // rows per segment of the FP32C near-axis launch
 
-// Group problems into launch batches, fill the descriptor table and upload it.
+// Group problems into launch batches, fill the descriptor table and upload it.  P->seg_rows gives the
+// segment length of each batch; when it does not match the batch count the defaults are taken.
 int build_batches(fdetd_plan_t P)
 {
+    P->batches.clear();
+    P->desc.clear();
+    const bool have_segs = !P->seg_rows.empty();
     const int n = (int)P->probs.size();
     std::vector<int> order(n);
     for (int p = 0; p < n; ++p) order[p] = p;
@@ -352,7 +379,8 @@ int build_batches(fdetd_plan_t P)
             row_strips += (int64_t)halves * ((du.nz + cpw - 1) / cpw) * du.nr;
             ++u;
         }
-        const int seg = pick_seg_rows(row_strips);
+        const size_t bi = P->batches.size();
+        const int seg = have_segs && bi < P->seg_rows.size() ? P->seg_rows[bi] : default_seg_rows(row_strips);
         int tiles = 0, tiles_ax = 0;
         for (int v = t; v < u; ++v) {
             const Prob &q = P->probs[order[v]];
@@ -362,10 +390,14 @@ int build_batches(fdetd_plan_t P)
             D.nr = q.d.nr;
             D.m = q.d.m;
             D.taylor = q.d.taylor_order;
-            D.seg_rows = seg;
-            D.nseg = (q.d.nr + seg - 1) / seg;
             D.nstrip = (q.d.nz + cpw - 1) / cpw;
-            D.nseg_ax = P->precision == FDETD_FP32C ? std::min(D.nseg, (axis_rows(q) + seg - 1) / seg) : 0;
+            if (P->precision == FDETD_FP32C) {
+                D.ax_rows = std::min(q.d.nr, axis_rows(q));
+                D.seg_ax = std::min(kSegAxis, D.ax_rows);
+                D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
+            }
+            D.seg_rows = seg;
+            D.nseg = (q.d.nr - D.ax_rows + seg - 1) / seg;
             D.tile_begin = tiles;
             D.tile_begin_ax = tiles_ax;
             D.plane = q.cells;
@@ -390,49 +422,152 @@ int build_batches(fdetd_plan_t P)
                 D.bz[k] = q.d2[k] / (q.d.dz * q.d.dz);
                 D.br[k] = q.d2[k] / (q.d.dr * q.d.dr);
             }
-            tiles += halves * (D.nseg - D.nseg_ax) * D.nstrip;
+            tiles += halves * D.nseg * D.nstrip;
             tiles_ax += halves * D.nseg_ax * D.nstrip;
             P->desc.push_back(D);
             b.members.push_back(order[v]);
         }
         b.count = u - t;
+        b.seg = seg;
         b.ntiles = tiles;
         b.ntiles_ax = tiles_ax;
         P->batches.push_back(b);
         t = u;
     }
-    // every launch must cover each (half, segment, strip) of each problem exactly once, inside the grid
+    // the two launches together must produce every (half, z strip, rho row) of each problem exactly once,
+    // from tiles that stay inside the grid
     for (const Batch &b : P->batches)
-        for (int axis = 0; axis < 2; ++axis) {
-            int expect = 0;
-            for (int t = 0; t < b.count; ++t) {
-                const ProbDesc &D = P->desc[b.d0 + t];
-                const int nl = halves * (axis ? D.nseg_ax : D.nseg - D.nseg_ax) * D.nstrip;
-                if ((axis ? D.tile_begin_ax : D.tile_begin) != expect)
-                    return fail(P, FDETD_E_ARG, "internal: tile ranges of the batch are not contiguous");
-                std::vector<char> seen((size_t)halves * D.nseg * D.nstrip, 0);
-                for (int r = 0; r < nl; ++r) {
-                    TileCoord c;
-                    if (!decode_tile(D, r, halves, axis != 0, cpw, c))
-                        return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid leaves the grid", r, D.nz, D.nr);
-                    const size_t key = ((size_t)c.half * D.nseg + c.k0 / D.seg_rows) * D.nstrip + c.i0 / cpw;
-                    if (c.i0 % cpw || c.k0 % D.seg_rows || key >= seen.size() || seen[key]++)
-                        return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid is decoded twice", r, D.nz, D.nr);
-                }
-                expect += nl;
-            }
-            if (expect != (axis ? b.ntiles_ax : b.ntiles))
-                return fail(P, FDETD_E_ARG, "internal: tile count mismatch");
-        }
-    for (const Batch &b : P->batches) {
-        // the two launches together cover every tile exactly once
         for (int t = 0; t < b.count; ++t) {
             const ProbDesc &D = P->desc[b.d0 + t];
-            if (D.nseg_ax < 0 || D.nseg_ax > D.nseg) return fail(P, FDETD_E_ARG, "internal: near-axis segments");
+            std::vector<unsigned char> seen((size_t)halves * D.nstrip * D.nr, 0);
+            for (int axis = 0; axis < 2; ++axis) {
+                const int nl = halves * (axis ? D.nseg_ax : D.nseg) * D.nstrip;
+                int begin = 0;
+                for (int u = 0; u < t; ++u) {
+                    const ProbDesc &E = P->desc[b.d0 + u];
+                    begin += halves * (axis ? E.nseg_ax : E.nseg) * E.nstrip;
+                }
+                if ((axis ? D.tile_begin_ax : D.tile_begin) != begin)
+                    return fail(P, FDETD_E_ARG, "internal: tile ranges of the batch are not contiguous");
+                for (int r = 0; r < nl; ++r) {
+                    TileCoord c;
+                    if (!decode_tile(D, r, halves, axis != 0, cpw, c) || c.i0 % cpw || c.k1 > D.nr)
+                        return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid leaves the grid", r, D.nz, D.nr);
+                    for (int k = c.k0; k < c.k1; ++k)
+                        if (seen[((size_t)c.half * D.nstrip + c.i0 / cpw) * D.nr + k]++)
+                            return fail(P, FDETD_E_ARG, "internal: a row of a %dx%d grid is produced twice", D.nz, D.nr);
+                }
+            }
+            for (unsigned char v : seen)
+                if (v != 1) return fail(P, FDETD_E_ARG, "internal: a row of a %dx%d grid is not produced", D.nz, D.nr);
+        }
+    for (const Batch &b : P->batches) {
+        int n_main = 0, n_ax = 0;
+        for (int t = 0; t < b.count; ++t) {
+            const ProbDesc &D = P->desc[b.d0 + t];
+            n_main += halves * D.nseg * D.nstrip;
+            n_ax += halves * D.nseg_ax * D.nstrip;
+        }
+        if (n_main != b.ntiles || n_ax != b.ntiles_ax) return fail(P, FDETD_E_ARG, "internal: tile count mismatch");
+    }
+    if (!P->ddesc) HIPCHK(P, hipMalloc(&P->ddesc, P->desc.size() * sizeof(ProbDesc)));
+    HIPCHK(P, hipMemcpy(P->ddesc, P->desc.data(), P->desc.size() * sizeof(ProbDesc), hipMemcpyHostToDevice));
+    return FDETD_OK;
+}
+
+// Arguments of one timing launch of batch b: a middle stage (the first when N < 3) with a current, on
+// the plan's own buffers only.  Inputs are read and outputs written at their usual positions inside those
+// buffers, so a timing launch touches nothing the caller owns.
+BatchArgs tuning_args(fdetd_plan_t P, const Batch &b)
+{
+    BatchArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.probs = P->ddesc + b.d0;
+    A.nprob = b.count;
+    A.N = b.N;
+    A.n = b.N >= 3 ? b.N - 2 : b.N - 1;
+    A.has_src = P->kind == FDETD_MAXWELL;
+    A.compensated = P->precision == FDETD_FP32C;
+    A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
+    A.beta = -b.dt * std::ldexp(1.0, -A.n);
+    A.coef = b.dt / (A.n + 1);
+    const size_t pb = elem_bytes(P->precision);
+    for (int t = 0; t < b.count; ++t) {
+        const Prob &q = P->probs[b.members[t]];
+        // the first stage reads its input from psi and writes buf[0]; later stages read buf[0]
+        void *own = q.buf[A.n == b.N - 1 ? 1 : 0];
+        A.psi[t] = own;
+        A.aux[t] = P->kind == FDETD_MAXWELL ? own : (const void *)((const char *)own + q.cells * pb);
+        A.chi[t] = own;
+    }
+    return A;
+}
+
+// Plan-time autotuning of the marching segment length: each launch batch runs a few timed stages at every
+// candidate length on the plan's zeroed buffers and keeps the fastest.  The stage results do not depend on
+// the tiling (every output is formed by the same operations in the same order), only the speed does.
+int autotune(fdetd_plan_t P, double &ms_spent)
+{
+    ms_spent = 0.0;
+    if ((P->flags & FDETD_PLAN_NO_AUTOTUNE) || forced_seg_rows()) return FDETD_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t eb = elem_bytes(P->precision);
+    const int np = planes(P->kind);
+    for (const Prob &q : P->probs) {
+        HIPCHK(P, hipMemsetAsync(q.buf[0], 0, np * q.cells * eb, P->stream));
+        HIPCHK(P, hipMemsetAsync(q.buf[1], 0, np * q.cells * eb, P->stream));
+        if (q.jbar) HIPCHK(P, hipMemsetAsync(q.jbar, 0, q.cells * eb, P->stream));
+    }
+    const size_t nb = P->batches.size();
+    // rows a main launch of each batch marches over: longer candidates than the first one covering them
+    // give the same tiling
+    std::vector<int> rows(nb, 0);
+    for (size_t bi = 0; bi < nb; ++bi)
+        for (int t = 0; t < P->batches[bi].count; ++t) {
+            const ProbDesc &D = P->desc[P->batches[bi].d0 + t];
+            rows[bi] = std::max(rows[bi], D.nr - D.ax_rows);
+        }
+    static const int kCand[] = {8, 16, 32, 64};
+    std::vector<double> best_ms(nb, 1e300);
+    std::vector<int> best(nb, kCand[0]), prev(nb, 0);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = FDETD_OK;
+    hipError_t e = hipSuccess;
+    if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])))
+        rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+    for (int c : kCand) {
+        if (rc) break;
+        P->seg_rows.assign(nb, c);
+        if ((rc = build_batches(P))) break;
+        for (size_t bi = 0; bi < nb && !rc; ++bi) {
+            if (prev[bi] >= rows[bi]) continue;  // same tiling as the previous candidate
+            prev[bi] = c;
+            const Batch &b = P->batches[bi];
+            BatchArgs A = tuning_args(P, b);
+            constexpr int kReps = 3;
+            for (int r = 0; r <= kReps && !rc; ++r) {  // one untimed launch, then kReps timed
+                if (r == 1 && (e = hipEventRecord(ev[0], P->stream)))
+                    rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+                if (!rc) rc = launch_stage(P, b, A);
+            }
+            float ms = 0.f;
+            if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
+                        (e = hipEventElapsedTime(&ms, ev[0], ev[1]))))
+                rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+            if (!rc && ms / kReps < 0.99 * best_ms[bi]) {
+                best_ms[bi] = ms / kReps;
+                best[bi] = c;
+            }
         }
     }
-    HIPCHK(P, hipMalloc(&P->ddesc, P->desc.size() * sizeof(ProbDesc)));
-    HIPCHK(P, hipMemcpy(P->ddesc, P->desc.data(), P->desc.size() * sizeof(ProbDesc), hipMemcpyHostToDevice));
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc) return rc;
+    P->seg_rows = best;
+    if ((rc = build_batches(P))) return rc;
+    for (const Prob &q : P->probs)
+        if (q.lo) HIPCHK(P, hipMemsetAsync(q.lo, 0, np * q.cells * 8, P->stream));
+    ms_spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return FDETD_OK;
 }
 
@@ -596,7 +731,11 @@ void fdetd_destroy(fdetd_plan_t plan)
 {
     if (!plan) return;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    if (plan->side) (void)hipStreamSynchronize(plan->side);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
     if (plan->ddesc) (void)hipFree(plan->ddesc);
@@ -698,7 +837,16 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             }
         }
     }
+    if (rc == FDETD_OK && precision == FDETD_FP32C) {
+        hipError_t e = hipSuccess;
+        if ((e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking)) ||
+            (e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming)) ||
+            (e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming)))
+            rc = fail(P, FDETD_E_HIP, "fdetd_plan: side stream: %s", hipGetErrorString(e));
+    }
     if (rc == FDETD_OK) rc = build_batches(P);
+    double tune_ms = 0.0;
+    if (rc == FDETD_OK) rc = autotune(P, tune_ms);
     if (rc != FDETD_OK) {
         g_last_error = P->err;
         fdetd_destroy(P);
@@ -713,6 +861,9 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.scratch_bytes = scratch;
     for (const Batch &b : P->batches) launches += (int64_t)b.N * ((b.ntiles > 0) + (b.ntiles_ax > 0));
     P->info.launches_per_step = launches;
+    P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
+    P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
+    P->info.autotune_ms = tune_ms;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         fail(P, FDETD_E_HIP, "fdetd_plan: %s", hipGetErrorString(e));

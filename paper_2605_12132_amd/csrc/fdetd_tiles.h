@@ -17,22 +17,24 @@ struct TileCoord {
 };
 
 // Tile r (0-based within problem D of one launch) -> coordinates.  halves = 2 (Maxwell) or 1 (envelope);
-// axis = the near-axis launch (segments 0 .. nseg_ax-1) or the main one (segments nseg_ax .. nseg-1);
-// cpw = z columns per tile.  Returns false if the tile would leave the grid.
+// axis = the near-axis launch (rows 0 .. ax_rows-1 in segments of seg_ax rows) or the main one (rows
+// ax_rows .. nr-1 in segments of seg_rows rows); cpw = z columns per tile.  Returns false if the tile
+// would leave the grid or its launch's rows.
 template <typename DESC>
 FDETD_HD inline bool decode_tile(DESC &D, int r, int halves, bool axis, int cpw, TileCoord &c)
 {
-    const int nseg_l = axis ? D.nseg_ax : D.nseg - D.nseg_ax;
+    const int nseg_l = axis ? D.nseg_ax : D.nseg;
     const int per_half = nseg_l * D.nstrip;
     if (per_half <= 0 || r < 0 || r >= halves * per_half) return false;
     c.half = r / per_half;
     r -= c.half * per_half;
     const int sl = r / D.nstrip;  // segment index within this launch
     c.i0 = (r - sl * D.nstrip) * cpw;
-    const int seg = sl + (axis ? 0 : D.nseg_ax);
-    c.k0 = seg * D.seg_rows;
-    c.k1 = c.k0 + D.seg_rows < D.nr ? c.k0 + D.seg_rows : D.nr;
-    return c.i0 >= 0 && c.i0 < D.nz && c.k0 >= 0 && c.k0 < D.nr && c.k1 > c.k0;
+    const int seg = axis ? D.seg_ax : D.seg_rows;
+    const int begin = axis ? 0 : D.ax_rows, end = axis ? D.ax_rows : D.nr;
+    c.k0 = begin + sl * seg;
+    c.k1 = c.k0 + seg < end ? c.k0 + seg : end;
+    return seg > 0 && c.i0 >= 0 && c.i0 < D.nz && c.k0 >= begin && c.k0 < end && end <= D.nr && c.k1 > c.k0;
 }
 
 }  // namespace fdetd

@@ -171,3 +171,31 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
+    """Every output is formed by the same operations whatever the marching segment length, so plans with
+    forced segment lengths, the default and the autotuned one give bitwise equal fields (FP64 and FP32C,
+    eager and graph)."""
+    import paper_2605_12132_amd as F
+    w = small(1, 16, 8, nz=300, nr=90, steps=2, seed=4)
+    rng = np.random.default_rng(71)
+    psi0 = [random_state(w, 0, rng)]
+    J = [random_current(w, 0, 2, rng)]
+    runs = {}
+    for seg in ("1", "5", "64"):
+        monkeypatch.setenv("FDETD_SEG_ROWS", seg)
+        runs[seg], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1)
+        assert info["seg_rows"] == int(seg) and info["autotune_ms"] == 0.0
+    monkeypatch.delenv("FDETD_SEG_ROWS")
+    runs["default"], _ = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1 | F.PLAN_NO_AUTOTUNE)
+    runs["tuned"], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1)
+    runs["graph"], _ = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=3)
+    log(f"autotuned: {info['seg_rows']} rows per segment (near-axis {info['seg_rows_axis']}), {info['autotune_ms']:.1f} ms")
+    assert info["seg_rows"] in (8, 16, 32, 64) and info["autotune_ms"] > 0
+    assert info["seg_rows_axis"] == (0 if precision == 0 else 8)
+    for k, v in runs.items():
+        assert np.array_equal(v[0], runs["1"][0]), k
+    if precision == 0:
+        assert rel_l2(runs["1"][0], oracle_maxwell(w, psi0, J, 2)[0]) < TOL64
