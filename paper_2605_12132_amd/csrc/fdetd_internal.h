@@ -100,10 +100,10 @@ struct ProbDesc {
 // One launch: stage n of every problem in the batch.
 struct BatchArgs {
     const ProbDesc *probs;  // device table (the batch's problems are consecutive entries)
-    int nprob, ntiles;
+    int nprob;
+    int ntiles, ntiles_ax;  // main tiles and (FP32 storage) near-axis tiles, FP64 arithmetic, in one launch
     int n, N;               // stage index n (N-1 .. 0) and Taylor order N
     int has_src, compensated;
-    int axis_launch;        // 1: the near-axis segments (FP64 arithmetic on FP32 storage), 0: the others
     double beta_in, beta, coef;
     const void *psi[kMaxBatch];  // Maxwell psi, or envelope a
     const void *aux[kMaxBatch];  // Maxwell: current of this step (3 planes) or null; envelope: a_tilde

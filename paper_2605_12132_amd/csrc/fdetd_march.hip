@@ -257,26 +257,35 @@ __device__ __forceinline__ lv<AR, K> keep_if(bool c, lv<AR, K> x)
 // another register would make the wave wait for them.  For the same reason a slot holds the loaded words
 // only; masks, scale factors and sums are applied in row().  Rows past the segment end (fewer than
 // FDETD_PREFETCH) run on the clamped last row with live = false and store nothing.
-template <typename In, typename Fetch, typename Row, typename Fill>
+template <typename In, int PF, typename Fetch, typename Row, typename Fill>
 __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &row, Fill &fill)
 {
-    In ring[FDETD_PREFETCH];
+    In ring[PF];
 #pragma unroll
-    for (int p = 0; p < FDETD_PREFETCH; ++p) ring[p] = fetch(k0 + p < k1 ? k0 + p : k1 - 1);
+    for (int p = 0; p < PF; ++p) ring[p] = fetch(k0 + p < k1 ? k0 + p : k1 - 1);
     fill();
     // Drain the first loads before the loop: the wait counter is in-order, and a loop entered with the
     // ring's loads outstanding in another order than the loop issues them would have every row wait as if
     // for its slot being the newest.  (vmcnt 0; expcnt and lgkmcnt left at their maxima 7 and 15.)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    for (int kb = k0; kb < k1; kb += FDETD_PREFETCH) {
+    for (int kb = k0; kb < k1; kb += PF) {
 #pragma unroll
-        for (int p = 0; p < FDETD_PREFETCH; ++p) {
+        for (int p = 0; p < PF; ++p) {
             const int k = kb + p;
             row(ring[p], k < k1 ? k : k1 - 1, k < k1);
-            const int kn = k + FDETD_PREFETCH;
+            const int kn = k + PF;
             ring[p] = fetch(kn < k1 ? kn : k1 - 1);
         }
     }
+}
+
+// Prefetch depth of a code path: the near-axis tiles of FP32 storage (FP64 arithmetic, twice the registers
+// per value) share a launch with the main tiles and keep fewer rows in flight, so that the launch's
+// register allocation, the larger of the two paths, stays that of the main path.
+template <typename V, typename AR>
+constexpr int prefetch_of()
+{
+    return sizeof(AR) > sizeof(typename scal<V>::R) ? 2 : FDETD_PREFETCH;
 }
 
 // Raw element of (row q, this lane) of a 6-plane vector's component c, and the compensation word.
@@ -487,7 +496,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -616,16 +625,26 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
 }
 
-// Tile of block b: tiles are numbered problem by problem, (half,) segment, strip -- strips fastest -- and
-// XCD x (blocks b with b % 8 == x) receives the contiguous range [x * per, (x + 1) * per).
-__device__ __forceinline__ int tile_of_block(int ntiles)
+// Tile of block b.  Tiles are numbered problem by problem, (half,) segment, strip -- strips fastest --
+// separately for the near-axis tiles (FP32 storage only) and the main tiles.  XCD x (the blocks with
+// b % 8 == x) first receives the near-axis range [x * per_ax, (x + 1) * per_ax), then the main range
+// [x * per, (x + 1) * per): every XCD (with its own L2) gets neighbouring tiles, and the slower near-axis
+// tiles are dispatched first and spread over all XCDs.  Returns -1 past the end of either range.
+__device__ __forceinline__ int tile_of_block(int ntiles_ax, int ntiles, bool &axis)
 {
-    const int per = (ntiles + NXCD - 1) / NXCD;
-    const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
-    return t < ntiles ? t : -1;
+    const int per_ax = (ntiles_ax + NXCD - 1) / NXCD, per = (ntiles + NXCD - 1) / NXCD;
+    const int x = (int)(blockIdx.x % NXCD), slot = (int)(blockIdx.x / NXCD);
+    axis = slot < per_ax;
+    const int t = axis ? x * per_ax + slot : x * per + (slot - per_ax);
+    return t < (axis ? ntiles_ax : ntiles) ? t : -1;
+}
+// Blocks of a launch: NXCD * (per_ax + per).
+inline int blocks_of(int ntiles_ax, int ntiles)
+{
+    return NXCD * ((ntiles_ax + NXCD - 1) / NXCD + (ntiles + NXCD - 1) / NXCD);
 }
 
 template <bool AXIS>
@@ -640,13 +659,9 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
 // AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage only): rows
 // 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the axis and its 1/rho factors, in FP64 arithmetic.
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP, bool AXIS>
-__global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
+__device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
-    using E = typename elem<V>::E;
     constexpr int S = elem<V>::S, CPW = WAVE / S;
-    __shared__ E lds[2][WAVE + 2 * ND * S];
-    const int t = tile_of_block(A.ntiles);
-    if (t < 0) return;
     const int p = problem_of_tile<AXIS>(A, t);
     CDesc &D = ((CDesc *)A.probs)[p];
     TileCoord tc;
@@ -670,6 +685,24 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
     if (half == 0) e_half<V, AR, ND, SRC, COMP>(C, i0, k0, k1, lds);
     else b_half<V, AR, ND, FIRST, COMP>(C, i0, k0, k1, lds);
+}
+
+// One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
+template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
+__global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
+{
+    using E = typename elem<V>::E;
+    __shared__ E lds[2][WAVE + 2 * ND * elem<V>::S];
+    bool axis;
+    const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
+    if (t < 0) return;
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (axis) {
+            maxwell_tile<V, ND, FIRST, SRC, COMP, true>(A, t, lds);
+            return;
+        }
+    }
+    maxwell_tile<V, ND, FIRST, SRC, COMP, false>(A, t, lds);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -794,17 +827,13 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
 #pragma unroll
         for (int t = 0; t < W - 1; ++t) Wa[t] = Wa[t + 1];
     };
-    march_rows<In>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
 }
 
 template <typename V, int ND, bool COMP, bool AXIS>
-__global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
+__device__ __forceinline__ void envelope_tile(const BatchArgs &A, int t, typename elem<V>::E *lds)
 {
-    using E = typename elem<V>::E;
     constexpr int S = elem<V>::S, CPW = WAVE / S;
-    __shared__ E lds[WAVE + 2 * ND * S];
-    const int t = tile_of_block(A.ntiles);
-    if (t < 0) return;
     const int p = problem_of_tile<AXIS>(A, t);
     CDesc &D = ((CDesc *)A.probs)[p];
     TileCoord tc;
@@ -829,19 +858,30 @@ __global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
     env_march<V, AR, ND, COMP>(C, i0, k0, k1, lds);
 }
 
+template <typename V, int ND, bool COMP>
+__global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
+{
+    using E = typename elem<V>::E;
+    __shared__ E lds[WAVE + 2 * ND * elem<V>::S];
+    bool axis;
+    const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
+    if (t < 0) return;
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (axis) {
+            envelope_tile<V, ND, COMP, true>(A, t, lds);
+            return;
+        }
+    }
+    envelope_tile<V, ND, COMP, false>(A, t, lds);
+}
+
 // Launch stage n of a batch with the kernel variant its flags select.
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 {
-    const int per = (a.ntiles + NXCD - 1) / NXCD;
-    const dim3 g(per * NXCD), b(WAVE);
-    if constexpr (sizeof(typename scal<V>::R) == 4) {
-        if (a.axis_launch) {
-            hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP, true>), g, b, 0, s, a);
-            return hipGetLastError();
-        }
-    }
-    hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP, false>), g, b, 0, s, a);
+    if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE),
+                       0, s, a);
     return hipGetLastError();
 }
 
@@ -866,14 +906,8 @@ hipError_t go_maxwell(const BatchArgs &a, hipStream_t s)
 template <typename V, int ND, bool COMP>
 hipError_t go_envelope_v(const BatchArgs &a, hipStream_t s)
 {
-    const int per = (a.ntiles + NXCD - 1) / NXCD;
-    if constexpr (sizeof(typename scal<V>::R) == 4) {
-        if (a.axis_launch) {
-            hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP, true>), dim3(per * NXCD), dim3(WAVE), 0, s, a);
-            return hipGetLastError();
-        }
-    }
-    hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP, false>), dim3(per * NXCD), dim3(WAVE), 0, s, a);
+    if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
+    hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 

@@ -74,9 +74,6 @@ struct fdetd_plan_s {
     size_t ev_used = 0;
     std::vector<double> ev_bytes;
     bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
-    // FP32C: the near-axis launch of a stage runs on a second stream beside the main launch
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int> seg_rows;  // per launch batch: rows per marching segment of the main launch
 };
 
@@ -193,32 +190,15 @@ int zero_device(fdetd_plan_t P, void *ptr, size_t bytes)
     return FDETD_OK;
 }
 
-// One stage of one launch batch.  FP32C: the near-axis launch goes to the side stream and runs beside
-// the main launch (both read only the stage's inputs and each writes its own rows); the plan's stream
-// waits for it before the next stage.  Under graph capture the fork and join become graph edges.
+// One stage of one launch batch: the main tiles and, FP32C, the near-axis tiles in one launch.
 int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A)
 {
     const int prec = prec_code(P->precision);
-    auto go = [&](hipStream_t st) {
-        return P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, st) : launch_envelope_march(prec, b.nd, A, st);
-    };
-    const bool fork = b.ntiles_ax && b.ntiles && P->side;
-    if (b.ntiles_ax) {
-        A.axis_launch = 1;
-        A.ntiles = b.ntiles_ax;
-        if (fork) {
-            HIPCHK(P, hipEventRecord(P->ev_fork, P->stream));
-            HIPCHK(P, hipStreamWaitEvent(P->side, P->ev_fork, 0));
-        }
-        HIPCHK(P, go(fork ? P->side : P->stream));
-        if (fork) HIPCHK(P, hipEventRecord(P->ev_join, P->side));
-    }
-    if (b.ntiles) {
-        A.axis_launch = 0;
-        A.ntiles = b.ntiles;
-        HIPCHK(P, go(P->stream));
-    }
-    if (fork) HIPCHK(P, hipStreamWaitEvent(P->stream, P->ev_join, 0));
+    A.ntiles = b.ntiles;
+    A.ntiles_ax = b.ntiles_ax;
+    if (A.ntiles + A.ntiles_ax == 0) return FDETD_OK;
+    HIPCHK(P, P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, P->stream)
+                                       : launch_envelope_march(prec, b.nd, A, P->stream));
     return FDETD_OK;
 }
 
@@ -731,11 +711,7 @@ void fdetd_destroy(fdetd_plan_t plan)
 {
     if (!plan) return;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
-    if (plan->side) (void)hipStreamSynchronize(plan->side);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
-    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
-    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
-    if (plan->side) (void)hipStreamDestroy(plan->side);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
     if (plan->ddesc) (void)hipFree(plan->ddesc);
@@ -837,13 +813,6 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             }
         }
     }
-    if (rc == FDETD_OK && precision == FDETD_FP32C) {
-        hipError_t e = hipSuccess;
-        if ((e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking)) ||
-            (e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming)) ||
-            (e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming)))
-            rc = fail(P, FDETD_E_HIP, "fdetd_plan: side stream: %s", hipGetErrorString(e));
-    }
     if (rc == FDETD_OK) rc = build_batches(P);
     double tune_ms = 0.0;
     if (rc == FDETD_OK) rc = autotune(P, tune_ms);
@@ -859,7 +828,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.cells = cells;
     P->info.bytes_per_step = bytes_step;
     P->info.scratch_bytes = scratch;
-    for (const Batch &b : P->batches) launches += (int64_t)b.N * ((b.ntiles > 0) + (b.ntiles_ax > 0));
+    for (const Batch &b : P->batches) launches += (int64_t)b.N * (b.ntiles + b.ntiles_ax > 0);
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
