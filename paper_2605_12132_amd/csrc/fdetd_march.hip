@@ -281,11 +281,16 @@ __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &ro
 
 // Prefetch depth of a code path: the near-axis tiles of FP32 storage (FP64 arithmetic, twice the registers
 // per value) share a launch with the main tiles and keep fewer rows in flight, so that the launch's
-// register allocation, the larger of the two paths, stays that of the main path.
-template <typename V, typename AR>
+// register allocation, the larger of the two paths, stays that of the main path.  HEAVY paths (the first
+// stage's current rows, the last stage's compensation words) carry more words per row and keep one row
+// less.  Wider stencils hold a longer rho window (2 N_D rows) and keep fewer rows in flight.  The aim is two
+// wavefronts per SIMD (at most 256 registers per lane).
+template <typename V, typename AR, int ND, bool HEAVY>
 constexpr int prefetch_of()
 {
-    return sizeof(AR) > sizeof(typename scal<V>::R) ? 2 : FDETD_PREFETCH;
+    constexpr int base = ND <= 8 ? FDETD_PREFETCH : (ND <= 12 ? FDETD_PREFETCH - 1 : FDETD_PREFETCH - 2);
+    constexpr int pf = sizeof(AR) > sizeof(typename scal<V>::R) ? (ND <= 8 ? 2 : 1) : (HEAVY ? base - 1 : base);
+    return pf < 1 ? 1 : pf;
 }
 
 // Raw element of (row q, this lane) of a 6-plane vector's component c, and the compensation word.
@@ -496,7 +501,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -625,7 +630,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, FIRST || COMP>()>(k0, k1, fetch, row, fill);
 }
 
 // Tile of block b.  Tiles are numbered problem by problem, (half,) segment, strip -- strips fastest --
@@ -827,7 +832,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
 #pragma unroll
         for (int t = 0; t < W - 1; ++t) Wa[t] = Wa[t + 1];
     };
-    march_rows<In, prefetch_of<V, AR>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 template <typename V, int ND, bool COMP, bool AXIS>

@@ -455,10 +455,10 @@ int build_batches(fdetd_plan_t P)
     return FDETD_OK;
 }
 
-// Arguments of one timing launch of batch b: a middle stage (the first when N < 3) with a current, on
-// the plan's own buffers only.  Inputs are read and outputs written at their usual positions inside those
-// buffers, so a timing launch touches nothing the caller owns.
-BatchArgs tuning_args(fdetd_plan_t P, const Batch &b)
+// Arguments of one timing launch of batch b: a middle stage (the first when N < 3) with a current.  The
+// stage vectors are the plan's own; psi and the current come from scratch[p] (np + 3 planes per problem,
+// allocated for the tuning only), so that every operand is a separate stream of memory as in a real step.
+BatchArgs tuning_args(fdetd_plan_t P, const Batch &b, const std::vector<void *> &scratch)
 {
     BatchArgs A;
     std::memset(&A, 0, sizeof A);
@@ -471,14 +471,15 @@ BatchArgs tuning_args(fdetd_plan_t P, const Batch &b)
     A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
     A.beta = -b.dt * std::ldexp(1.0, -A.n);
     A.coef = b.dt / (A.n + 1);
-    const size_t pb = elem_bytes(P->precision);
+    const size_t eb = elem_bytes(P->precision);
+    const int np = planes(P->kind);
     for (int t = 0; t < b.count; ++t) {
-        const Prob &q = P->probs[b.members[t]];
-        // the first stage reads its input from psi and writes buf[0]; later stages read buf[0]
-        void *own = q.buf[A.n == b.N - 1 ? 1 : 0];
-        A.psi[t] = own;
-        A.aux[t] = P->kind == FDETD_MAXWELL ? own : (const void *)((const char *)own + q.cells * pb);
-        A.chi[t] = own;
+        const int u = b.members[t];
+        const size_t pb = P->probs[u].cells * eb;
+        char *base = (char *)scratch[u];
+        A.psi[t] = base;
+        A.aux[t] = P->kind == FDETD_MAXWELL ? base + np * pb : base + pb;  // current, or a_tilde
+        A.chi[t] = base + np * pb;
     }
     return A;
 }
@@ -493,6 +494,25 @@ int autotune(fdetd_plan_t P, double &ms_spent)
     const auto t0 = std::chrono::steady_clock::now();
     const size_t eb = elem_bytes(P->precision);
     const int np = planes(P->kind);
+    // tuning-only psi and current (np + 3 planes per problem); without the memory the defaults stay
+    std::vector<void *> scratch(P->probs.size(), nullptr);
+    struct Free {
+        std::vector<void *> &v;
+        ~Free()
+        {
+            for (void *x : v)
+                if (x) (void)hipFree(x);
+        }
+    } free_scratch{scratch};
+    for (size_t u = 0; u < P->probs.size(); ++u) {
+        const size_t bytes = (np + 3) * P->probs[u].cells * eb;
+        if (hipMalloc(&scratch[u], bytes) != hipSuccess) {
+            scratch[u] = nullptr;
+            (void)hipGetLastError();
+            return FDETD_OK;
+        }
+        HIPCHK(P, hipMemsetAsync(scratch[u], 0, bytes, P->stream));
+    }
     for (const Prob &q : P->probs) {
         HIPCHK(P, hipMemsetAsync(q.buf[0], 0, np * q.cells * eb, P->stream));
         HIPCHK(P, hipMemsetAsync(q.buf[1], 0, np * q.cells * eb, P->stream));
@@ -508,37 +528,46 @@ int autotune(fdetd_plan_t P, double &ms_spent)
             rows[bi] = std::max(rows[bi], D.nr - D.ax_rows);
         }
     static const int kCand[] = {8, 16, 32, 64};
-    std::vector<double> best_ms(nb, 1e300);
-    std::vector<int> best(nb, kCand[0]), prev(nb, 0);
+    constexpr int kNC = 4;
+    // candidate c of batch bi is timed unless a shorter candidate already covers the batch's rows
+    auto distinct = [&](int ci, size_t bi) { return ci == 0 || kCand[ci - 1] < rows[bi]; };
+    std::vector<double> t_ms(nb * kNC, 1e300);
     hipEvent_t ev[2] = {nullptr, nullptr};
     int rc = FDETD_OK;
     hipError_t e = hipSuccess;
     if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])))
         rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
-    for (int c : kCand) {
-        if (rc) break;
-        P->seg_rows.assign(nb, c);
-        if ((rc = build_batches(P))) break;
-        for (size_t bi = 0; bi < nb && !rc; ++bi) {
-            if (prev[bi] >= rows[bi]) continue;  // same tiling as the previous candidate
-            prev[bi] = c;
-            const Batch &b = P->batches[bi];
-            BatchArgs A = tuning_args(P, b);
-            constexpr int kReps = 3;
-            for (int r = 0; r <= kReps && !rc; ++r) {  // one untimed launch, then kReps timed
-                if (r == 1 && (e = hipEventRecord(ev[0], P->stream)))
+    // two passes, ascending then descending, keeping each candidate's faster time
+    for (int pass = 0; pass < 2 && !rc; ++pass)
+        for (int k = 0; k < kNC && !rc; ++k) {
+            const int ci = pass == 0 ? k : kNC - 1 - k;
+            P->seg_rows.assign(nb, kCand[ci]);
+            if ((rc = build_batches(P))) break;
+            for (size_t bi = 0; bi < nb && !rc; ++bi) {
+                if (!distinct(ci, bi)) continue;
+                const Batch &b = P->batches[bi];
+                BatchArgs A = tuning_args(P, b, scratch);
+                constexpr int kReps = 4;
+                for (int r = 0; r <= kReps && !rc; ++r) {  // one untimed launch, then kReps timed
+                    if (r == 1 && (e = hipEventRecord(ev[0], P->stream)))
+                        rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+                    if (!rc) rc = launch_stage(P, b, A);
+                }
+                float ms = 0.f;
+                if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
+                            (e = hipEventElapsedTime(&ms, ev[0], ev[1]))))
                     rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
-                if (!rc) rc = launch_stage(P, b, A);
-            }
-            float ms = 0.f;
-            if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
-                        (e = hipEventElapsedTime(&ms, ev[0], ev[1]))))
-                rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
-            if (!rc && ms / kReps < 0.99 * best_ms[bi]) {
-                best_ms[bi] = ms / kReps;
-                best[bi] = c;
+                if (!rc) t_ms[bi * kNC + ci] = std::min(t_ms[bi * kNC + ci], (double)ms / kReps);
             }
         }
+    std::vector<int> best(nb, kCand[0]);
+    for (size_t bi = 0; bi < nb; ++bi) {
+        double bm = 1e300;
+        for (int ci = 0; ci < kNC; ++ci)
+            if (distinct(ci, bi) && t_ms[bi * kNC + ci] < bm) {
+                bm = t_ms[bi * kNC + ci];
+                best[bi] = kCand[ci];
+            }
     }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
