@@ -76,7 +76,28 @@ def energy_weights(w, p):
     return wm * r * w.dr * w.dz  # [6, nr]
 
 
-def run_path(w, precision, steps, warmup, J, use_graph=True):
+class seg_rows_env:
+    """Plans built inside get FDETD_SEG_ROWS = n (no autotuning) when n is given."""
+
+    def __init__(self, n):
+        self.n, self.old = n, None
+
+    def __enter__(self):
+        if self.n:
+            self.old = os.environ.get("FDETD_SEG_ROWS")
+            os.environ["FDETD_SEG_ROWS"] = str(self.n)
+        return self
+
+    def __exit__(self, *a):
+        if self.n:
+            if self.old is None:
+                del os.environ["FDETD_SEG_ROWS"]
+            else:
+                os.environ["FDETD_SEG_ROWS"] = self.old
+        return False
+
+
+def run_path(w, precision, steps, warmup, J, use_graph=True, seg_rows=None):
     """Warm up, capture the K-step graph once (untimed, then restore the state), time exactly K steps."""
     import torch
     import paper_2605_12132_amd as F
@@ -87,7 +108,8 @@ def run_path(w, precision, steps, warmup, J, use_graph=True):
         psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
         flags = F.PLAN_USE_GRAPH if use_graph else 0
         t0 = time.time()
-        plan = F.Plan(w.problems(), precision=precision, flags=flags)
+        with seg_rows_env(seg_rows):
+            plan = F.Plan(w.problems(), precision=precision, flags=flags)
         plan_s = time.time() - t0
         if warmup:
             plan.step(psi, [j[:warmup] for j in J], n_steps=warmup)
@@ -120,15 +142,8 @@ def profile_pass(w, precision, steps, J, seg_rows):
     import paper_2605_12132_amd as F
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
-    old = os.environ.get("FDETD_SEG_ROWS")
-    os.environ["FDETD_SEG_ROWS"] = str(seg_rows)
-    try:
+    with seg_rows_env(seg_rows):
         plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
-    finally:
-        if old is None:
-            del os.environ["FDETD_SEG_ROWS"]
-        else:
-            os.environ["FDETD_SEG_ROWS"] = old
     plan.step(psi, [j[:steps] for j in J], n_steps=steps)
     info = plan.query()
     plan.close()
@@ -168,21 +183,33 @@ def measured_traffic(precision_tag):
 
 def copy_calibration(n_bytes=1 << 30, reps=10):
     """A plain device-to-device copy of n_bytes, reps times: the known-size kernel against which the
-    FETCH_SIZE / WRITE_SIZE counters are scaled, and the HBM rate a plain copy reaches on this GPU."""
+    FETCH_SIZE / WRITE_SIZE counters are scaled.  Also times plain streaming kernels (torch elementwise
+    ops over the same sizes, read:write ratios 1:1, 2:1, 3:1, 0:1) for the HBM rate a simple stream
+    reaches on this GPU."""
     import torch
-    a = torch.empty(n_bytes // 8, dtype=torch.float64, device="cuda").uniform_()
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
-    return dict(copy_bytes_read=n_bytes, copy_bytes_written=n_bytes, reps=reps, ms_per_copy=ms,
-                copy_GBs=2 * n_bytes / (ms * 1e-3) / 1e9)
+    n = n_bytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    b, c, d = torch.empty_like(a).uniform_(), torch.empty_like(a).uniform_(), torch.empty_like(a)
+
+    def rate(fn, words):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        return ms, words * n_bytes / (ms * 1e-3) / 1e9
+
+    ms, copy_gbs = rate(lambda: d.copy_(a), 2)
+    streams = {"scale_r1w1": rate(lambda: torch.mul(a, 2.0, out=d), 2)[1],
+               "add_r2w1": rate(lambda: torch.add(a, b, out=d), 3)[1],
+               "addcmul_r3w1": rate(lambda: torch.addcmul(a, b, c, out=d), 4)[1],
+               "fill_w1": rate(lambda: d.fill_(1.0), 1)[1]}
+    return dict(copy_bytes_read=n_bytes, copy_bytes_written=n_bytes, reps=reps, ms_per_copy=ms, copy_GBs=copy_gbs,
+                stream_GBs={k: round(v, 1) for k, v in streams.items()})
 
 
 def fp32c_errors(w, psi64, psi32):
@@ -238,6 +265,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--seg-rows-fp64", type=int, default=None,
+                    help="fixed rows per marching segment of the FP64 plans instead of plan-time autotuning")
+    ap.add_argument("--seg-rows-fp32c", type=int, default=None, help="the same for the FP32C plans")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -263,7 +293,7 @@ def main():
     torch.cuda.synchronize()
     log(f"currents resident: {sum(j.numel() for j in J64) * 16 / 1e9:.1f} GB in {time.time() - t0:.1f} s")
 
-    psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph)
+    psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph, args.seg_rows_fp64)
     rate64 = cells * K / (ms64 * 1e-3)
     log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s (plan {plan_s:.2f} s, dt*rho {info64['dt_rho_max']:.3f})")
     roof64 = profile_pass(w, F.FP64, args.profile_steps, J64, info64["seg_rows"])
@@ -274,7 +304,7 @@ def main():
         J32 = [j.to(torch.complex64) for j in J64]
         del J64
         torch.cuda.empty_cache()
-        psi32, ms32, _, info32 = run_path(w, F.FP32C, K, W, J32, not args.no_graph)
+        psi32, ms32, _, info32 = run_path(w, F.FP32C, K, W, J32, not args.no_graph, args.seg_rows_fp32c)
         rate32 = cells * K / (ms32 * 1e-3)
         roof32 = profile_pass(w, F.FP32C, args.profile_steps, J32, info32["seg_rows"])
         errs = fp32c_errors(w, psi64, psi32)
