@@ -181,3 +181,32 @@ def test_out_of_range_terms_are_ignored():
     assert np.allclose(out[5], [0, 0, 0, 0, 0, 0, a[1], a[0]])
     out = oracle.apply_op(g, OP_DR_MINUS, f, parity=1)
     assert np.allclose(out[:, 7], [0, 0, 0, 0, a[1], a[0]])
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [4, 8, 16])
+def test_current_staging_exact_with_mode_parity(m, order):
+    """J_rho of mode m behaves as rho^|m-1| times an even polynomial near the axis (the m_A parity of
+    section 2.4), so its half-shift to the rho-staggered rows (the current staging of section 2.5) with m_A mirror ghosts is exact
+    on such polynomials up to degree 2N_D - 1, next to the axis included; a current of the other parity
+    is not reproduced there.  J_theta and J_z pass through unchanged."""
+    nd = order // 2
+    g = grid(nd)
+    g.m = m
+    rows = np.arange(1, g.nr - nd + 1)
+    rng = np.random.default_rng(m * 100 + order)
+    par = abs(m - 1) % 2
+    powers = [p for p in range(0, 2 * nd) if p % 2 == par]
+    coef = rng.uniform(-1, 1, len(powers))
+    J = np.zeros((3, g.nr, g.nz), np.complex128)
+    J[0] = as_plane(g, sum(c * rho_prim(g) ** p for c, p in zip(coef, powers)))
+    J[1] = rng.uniform(-1, 1, (g.nr, g.nz)) + 1j * rng.uniform(-1, 1, (g.nr, g.nz))
+    J[2] = rng.uniform(-1, 1, (g.nr, g.nz))
+    out = oracle.stage_current(g, J)
+    check_rows(out[0], sum(c * rho_stag(g) ** p for c, p in zip(coef, powers)), rows, tol(nd, 2 * nd))
+    assert np.array_equal(out[1], J[1]) and np.array_equal(out[2], J[2])
+    # the other parity: the mirrored ghosts no longer continue the polynomial, row 1 is off
+    wrong = np.zeros_like(J)
+    wrong[0] = as_plane(g, rho_prim(g) ** (1 - par))
+    got = oracle.stage_current(g, wrong)[0][1, 0].real
+    assert abs(got - rho_stag(g)[1] ** (1 - par)) > 1e-6
