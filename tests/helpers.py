@@ -94,3 +94,31 @@ def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0):
 def oracle_envelope(w, a0, at0, chi, steps=1):
     out = [oracle.envelope_step(grid_of(w, p), a0[p], at0[p], chi[p], steps) for p in range(w.n)]
     return [o[0] for o in out], [o[1] for o in out]
+
+
+def dependence_radius(w, p, steps) -> int:
+    """Cells (in z and rho) over which `steps` steps can carry information: each application of H reaches
+    N_D cells, a step applies H up to N times to a vector that already holds the staged current (half-shift
+    of N_D rows), plus a margin."""
+    return steps * (w.taylor_order + 1) * (w.fd_order[p] // 2) + 2
+
+
+def oracle_window(w, p, psi0, J, steps, zc, half, kmax):
+    """The oracle on a crop of problem p -- rows [0, kr) and columns [z0, z1) -- that extends the sampled
+    region (rows [0, kmax), columns [zc - half, zc + half)) by the dependence radius wherever it does not
+    meet the grid's own edge.  Terms beyond a crop edge count as zero, like terms beyond the grid (the
+    out-of-range rule of section 2.2), and can reach only cells within the dependence radius of that edge,
+    so on the sampled region the crop gives the full grid's result.  Returns (window of the oracle result,
+    (row slice, column slice) of the sampled region in full-grid indices)."""
+    R = dependence_radius(w, p, steps)
+    nz, nr = w.nz[p], w.nr[p]
+    a, b = max(0, zc - half), min(nz, zc + half)
+    z0, z1 = max(0, a - R), min(nz, b + R)
+    kmax = min(kmax, nr)
+    kr = min(nr, kmax + R)
+    g = oracle.Grid(nz=z1 - z0, nr=kr, m=w.m[p], fd_order=w.fd_order[p], taylor_order=w.taylor_order,
+                    dz=w.dz, dr=w.dr, dt=w.dt, k0=w.k0)
+    psi = np.ascontiguousarray(psi0[:, :kr, z0:z1])
+    jj = None if J is None else np.ascontiguousarray(J[..., :kr, z0:z1])
+    out = oracle.step(g, psi, jj, steps)
+    return out[:, :kmax, a - z0:b - z0], (slice(0, kmax), slice(a, b))

@@ -1,0 +1,81 @@
+"""Full-size GPU runs of the two largest workloads, checked against the oracle on sampled windows.
+
+- batched uneven workload: 64 problems, N_z in [512, 4096], N_rho in [64, 512], modes 0..2, orders 8..32,
+  in one plan with graph replay;
+- LWFA-scale grid: modes 0, 1, 2 on 8192 x 1024, order 32.
+
+Running the oracle on these grids in full would take minutes per step. Instead it runs on crops: rows
+from the axis, columns around a sample point, grown by the dependence radius of the steps taken.
+`tests/test_oracle_maxwell.py::test_cropped_window_equals_full_grid` checks on the CPU that such a crop
+reproduces the full grid bit for bit on the sampled region. The windows cover the near-axis rows, the z
+ends and the laser pulse.
+
+FP64 must match the oracle to relative L2 <= 1e-12 on every window. FP32C is compared with the FP64 GPU
+path over the full grids to the FP32C bound 2e-5 (a few steps).
+"""
+import numpy as np
+import pytest
+
+from helpers import gpu_maxwell, log, oracle_window, rel_l2
+
+import paper_2605_12132_amd as F
+import paper_2605_12132_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def _inputs(w, steps):
+    psi0 = [I.initial_fields(w, p) for p in range(w.n)]
+    J = [I.currents(w, p, steps) for p in range(w.n)]
+    return psi0, J
+
+
+def _check_windows(w, psi0, J, steps, got, samples):
+    worst = 0.0
+    for p, zc, kmax in samples:
+        want, (rs, cs) = oracle_window(w, p, psi0[p], J[p], steps, zc, 16, kmax)
+        err = rel_l2(got[p][:, rs, cs], want)
+        worst = max(worst, err)
+        assert err < TOL64, (p, zc, err)
+    return worst
+
+
+def test_batched_uneven_64_problems_full_size():
+    w = I.batched_uneven()
+    steps = 2
+    psi0, J = _inputs(w, steps)
+    log(f"batched uneven: {w.n} problems, {w.cells() / 1e6:.1f} M cells, orders {sorted(set(w.fd_order))}")
+    got, info = gpu_maxwell(w, psi0, J, steps, precision=F.FP64, flags=F.PLAN_USE_GRAPH)
+    log(f"  FP64 done: {info['launches_per_step']} launches per step, autotune {info['autotune_ms']:.1f} ms")
+    rng = np.random.default_rng(404)
+    samples = []
+    for p in range(0, w.n, 4):
+        zc = int(rng.integers(0, w.nz[p]))
+        samples.append((p, zc, 2 * (w.fd_order[p] // 2) + 8))
+    samples += [(1, 3, 24), (2, w.nz[2] - 4, 24)]  # both z ends
+    worst = _check_windows(w, psi0, J, steps, got, samples)
+    log(f"  FP64 vs oracle on {len(samples)} windows: worst rel L2 {worst:.2e}")
+    got32, _ = gpu_maxwell(w, psi0, J, steps, precision=F.FP32C, flags=F.PLAN_USE_GRAPH)
+    errs = [rel_l2(got32[p], got[p]) for p in range(w.n) if np.any(got[p])]
+    log(f"  FP32C vs FP64 over the full grids: worst rel L2 {max(errs):.2e}")
+    assert max(errs) < TOL32
+
+
+def test_lwfa_scale_full_size():
+    w = I.lwfa_scale()
+    steps = 1
+    psi0, J = _inputs(w, steps)
+    log(f"LWFA scale: {w.n} modes x {w.nz[0]}x{w.nr[0]}, order {w.fd_order[0]}")
+    got, info = gpu_maxwell(w, psi0, J, steps, precision=F.FP64, flags=F.PLAN_USE_GRAPH)
+    log(f"  FP64 done, dt*rho {info['dt_rho_max']:.3f}, {info['seg_rows']} rows per segment")
+    zc_pulse = int(w.extra["zc"] / w.dz)
+    samples = [(p, zc, 48) for p in range(w.n) for zc in (3, zc_pulse, w.nz[p] - 4)]
+    worst = _check_windows(w, psi0, J, steps, got, samples)
+    log(f"  FP64 vs oracle on {len(samples)} windows: worst rel L2 {worst:.2e}")
+    got32, _ = gpu_maxwell(w, psi0, J, steps, precision=F.FP32C, flags=F.PLAN_USE_GRAPH)
+    errs = [rel_l2(got32[p], got[p]) for p in range(w.n)]
+    log(f"  FP32C vs FP64 over the full grids: rel L2 {[f'{e:.1e}' for e in errs]}")
+    assert max(errs) < TOL32

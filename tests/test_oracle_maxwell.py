@@ -263,3 +263,30 @@ def test_source_free_step_conserves_energy_away_from_axis():
     loss = 1 - abs(taylor(1j * x, 8)) ** 2
     assert w1 <= w0 * (1 + 1e-12)
     assert w1 >= w0 * (1 - 20 * loss - 1e-12), (w0, w1)
+
+
+@pytest.mark.parametrize("m,order,steps", [(0, 8, 2), (1, 16, 1), (2, 4, 3)])
+def test_cropped_window_equals_full_grid(m, order, steps):
+    """The windowed oracle used for the full-size GPU parity tests: on the sampled region a crop grown by
+    the dependence radius reproduces the full grid bit for bit (every term there is formed from the same
+    values in the same order), next to the axis and at both z ends included."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import dependence_radius, oracle_window
+    import paper_2605_12132_amd.inputs as I
+    dz = I.LAMBDA0 / 20
+    w = I.Workload("win", 0, [420], [150], [m], [order], 4, dz, 2 * dz, 0.5 * dz, steps)
+    rng = np.random.default_rng(order + m)
+    psi0 = rng.uniform(-1, 1, (6, 150, 420)) + 1j * rng.uniform(-1, 1, (6, 150, 420))
+    J = 0.1 * (rng.uniform(-1, 1, (steps, 3, 150, 420)) + 1j * rng.uniform(-1, 1, (steps, 3, 150, 420)))
+    g = oracle.Grid(nz=420, nr=150, m=m, fd_order=order, taylor_order=4, dz=dz, dr=2 * dz, dt=0.5 * dz)
+    full = oracle.step(g, psi0, J, steps)
+    R = dependence_radius(w, 0, steps)
+    assert R < 200
+    for zc in (5, 210, 415):
+        win, (rs, cs) = oracle_window(w, 0, psi0, J, steps, zc, 6, 20)
+        assert np.array_equal(win, full[:, rs, cs]), zc
+    # a crop that is too small is not exact: the test would notice a wrong radius
+    g2 = oracle.Grid(nz=40, nr=150, m=m, fd_order=order, taylor_order=4, dz=dz, dr=2 * dz, dt=0.5 * dz)
+    small = oracle.step(g2, np.ascontiguousarray(psi0[:, :, 190:230]), np.ascontiguousarray(J[..., 190:230]), steps)
+    assert not np.array_equal(small[:, :20, 14:26], full[:, :20, 204:216])
