@@ -256,6 +256,41 @@ def cpu_baseline(w, budget_s=12.0):
                        f"{w.taylor_order}, with current) in {t_total:.1f} s; host reports {ncpu} usable cores")
 
 
+def batched_pass(steps, warmup):
+    """The batched uneven workload (64 problems, N_z in [512, 4096], N_rho in [64, 512], modes 0..2,
+    orders 8..32, Taylor 8, dt = dz/2): FP32C and FP64 plans over all problems, graph replay of `steps`
+    steps with a fresh bunch + noise current per step resident in HBM, fields starting at zero.  Reports
+    cell-updates/s, the step-level algorithmic HBM rate (plan's bytes per step / step time) and the
+    FP32C error against FP64 after the same steps."""
+    import torch
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+    w = I.batched_uneven()
+    cells = w.cells()
+    res, psis = {}, {}
+    for tag, prec, cd in (("fp32c", F.FP32C, torch.complex64), ("fp64", F.FP64, torch.complex128)):
+        J = make_currents(w, warmup + steps, cd, w.seed)
+        torch.cuda.synchronize()
+        psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
+        del J
+        torch.cuda.empty_cache()
+        gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
+        res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
+                        frac=round(gbs / HBM_PEAK_GBS, 4), launches_per_step=info["launches_per_step"],
+                        plan_s=round(plan_s, 2), autotune_ms=round(info["autotune_ms"], 1))
+        psis[tag] = psi
+        log(f"batched {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, "
+            f"{gbs:.0f} GB/s algorithmic ({info['launches_per_step']} launches/step, plan {plan_s:.1f} s)")
+    num = den = 0.0
+    for a, b in zip(psis["fp64"], psis["fp32c"]):
+        d = a - b.to(torch.complex128)
+        num += float(torch.sum(torch.abs(d) ** 2))
+        den += float(torch.sum(torch.abs(a) ** 2))
+    return dict(workload=w.name, problems=w.n, cells=cells, steps=steps, warmup=warmup, graph=True,
+                fp32c=res["fp32c"], fp64=res["fp64"], fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
+                fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +303,8 @@ def main():
     ap.add_argument("--seg-rows-fp64", type=int, default=None,
                     help="fixed rows per marching segment of the FP64 plans instead of plan-time autotuning")
     ap.add_argument("--seg-rows-fp32c", type=int, default=None, help="the same for the FP32C plans")
+    ap.add_argument("--batched-steps", type=int, default=20,
+                    help="steps of the 64-problem batched workload reported beside the headline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -317,6 +354,11 @@ def main():
     else:
         del J64
 
+    batched = None
+    if args.batched_steps > 0 and not args.fp64_only:
+        del psi64
+        torch.cuda.empty_cache()
+        batched = batched_pass(args.batched_steps, W)
     cpu = None if args.no_cpu else cpu_baseline(w)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
@@ -331,6 +373,7 @@ def main():
         "cpu_baseline": cpu,
         "tiling": dict(seg_rows=info64["seg_rows"], autotune_ms=round(info64["autotune_ms"], 1)),
         "fp32c": fp32c,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -77,15 +77,22 @@ struct AxisArgs {
 // ---------------------------------------------------------------------------------------------------
 // Row-marching stage kernels (fdetd_march.hip), batched over problems of equal N_D, N and dt.
 // ---------------------------------------------------------------------------------------------------
+// Near-axis tiles of FP32 storage (FP64 arithmetic): up to N_D = kAxisWholeND each lane holds a whole
+// complex value (64 columns per wavefront, like the main tiles); wider stencils need twice the window
+// registers and read the storage in lane pairs instead (32 columns per wavefront).
+constexpr int kAxisWholeND = 8;
+constexpr int kAxisColumns = 32;  // the narrower width; divides every tile width
+constexpr int axis_columns(int nd) { return nd <= kAxisWholeND ? 64 : kAxisColumns; }
 constexpr int kMaxBatch = 64;  // problems per launch (pointer arrays travel in the kernel arguments)
 
 // Static per-problem facts, uploaded once at plan time.
 struct ProbDesc {
     int nz, nr, m, taylor;
     int nstrip;                              // tiling: strips of z columns ...
-    int seg_rows, nseg;                      // ... x segments of seg_rows rows from row ax_rows down (main launch)
-    int seg_ax, nseg_ax, ax_rows;            // FP32C: rows 0 .. ax_rows-1 (= 2 N_D) in segments of seg_ax rows,
-                                             // FP64 arithmetic (near-axis launch); FP64 plans: 0, 0, 0
+    int seg_rows, nseg;                      // ... x segments of seg_rows rows from row ax_rows down (main tiles)
+    int seg_ax, nseg_ax, ax_rows, nstrip_ax; // FP32C: rows 0 .. ax_rows-1 (= 2 N_D) in segments of seg_ax rows
+                                             // and strips of kAxisColumns columns, FP64 arithmetic (near-axis
+                                             // tiles); FP64 plans: 0, 0, 0, 0
     int tile_begin, tile_begin_ax;           // first tile of this problem in the main / near-axis launch
     size_t plane;                            // nz * nr
     double dr, pS, k0;

@@ -86,9 +86,18 @@ __device__ __forceinline__ lv<AR, K> times_i(AR s, lv<AR, K> x)
     return r;
 }
 
+// FP32 storage read in lane pairs (one float part per lane, 32 columns per wave, as FP64 storage is read):
+// the layout of the FP32C near-axis tiles, whose FP64 arithmetic on a whole complex value per lane would
+// need twice the registers.
+struct f2pair {};
+
 template <typename V> struct scal;
 template <> struct scal<double2> { using R = double; };
 template <> struct scal<float2> { using R = float; };
+template <> struct scal<f2pair> { using R = float; };
+// storage element type of a layout (what pointers into the planes point at)
+template <typename V> struct stor { using T = V; };
+template <> struct stor<f2pair> { using T = float2; };
 
 // Global-memory access through address-space-1 pointers.  The kernels' pointers come from a descriptor
 // table and the kernel arguments, so without the cast the compiler emits flat instructions, which also
@@ -128,21 +137,32 @@ __device__ __forceinline__ double cld(const double *p, int i) { return ((const F
 // Storage access.  FP64 (double2 storage, K = 1): element = one double, index 2*(row*nz + col) + part.
 // FP32 (float2 storage, K = 2): element = one float2, index row*nz + col.
 template <typename V> struct elem;
+// Lo = the element of the FP32C compensation words in the same layout (unused with FP64 storage).
 template <> struct elem<double2> {
     using E = double;
+    using Lo = float2;
     static constexpr int S = 2;  // lanes per column
     static constexpr int K = 1;
 };
 template <> struct elem<float2> {
     using E = float2;
+    using Lo = float2;
     static constexpr int S = 1;
     static constexpr int K = 2;
+};
+template <> struct elem<f2pair> {
+    using E = float;
+    using Lo = float;
+    static constexpr int S = 2;
+    static constexpr int K = 1;
 };
 
 template <typename AR>
 __device__ __forceinline__ lv<AR, 1> to_lv(double e) { return lv<AR, 1>{{(AR)e}}; }
 template <typename AR>
 __device__ __forceinline__ lv<AR, 2> to_lv(float2 e) { return lv<AR, 2>{{(AR)e.x, (AR)e.y}}; }
+template <typename AR>
+__device__ __forceinline__ lv<AR, 1> to_lv(float e) { return lv<AR, 1>{{(AR)e}}; }
 
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
@@ -180,13 +200,13 @@ struct Lane {
 // Element of row q of a plane for this lane.  A lane past the last grid column reads that column (clamped
 // index): its results are never stored and never reach another lane, so the value needs no mask.
 template <typename V>
-__device__ __forceinline__ typename elem<V>::E ldraw(const V *plane, int nz, int q, const Lane<V> &L)
+__device__ __forceinline__ typename elem<V>::E ldraw(const typename stor<V>::T *plane, int nz, int q, const Lane<V> &L)
 {
     using E = typename elem<V>::E;
     return gld<E>(row_ptr<E>(plane, 0, 0, nz, elem<V>::S, q), (unsigned)L.eidx);
 }
 template <typename V, typename AR>
-__device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const V *plane, int nz, int q, const Lane<V> &L)
+__device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const typename stor<V>::T *plane, int nz, int q, const Lane<V> &L)
 {
     return to_lv<AR>(ldraw<V>(plane, nz, q, L));
 }
@@ -196,7 +216,7 @@ __device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const V *plane, int nz, int 
 // at the output position, loaded one row ahead.
 template <typename V, typename AR, bool COMP>
 __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane<V> &L, lv<AR, elem<V>::K> inc,
-                                          bool zero_slot, typename elem<V>::E psi_v, float2 lo_v)
+                                          bool zero_slot, typename elem<V>::E psi_v, typename elem<V>::Lo lo_v)
 {
     using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
@@ -217,6 +237,18 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
         float2 w{(float)((AR)psi_v.x + inc.p[0]), (float)((AR)psi_v.y + inc.p[1])};
         if (zero_slot) w = float2{0.f, 0.f};
         gst<float2>(orow, o, w);
+    } else if constexpr (std::is_same<E, float>::value) {  // FP32 storage in lane pairs
+        if constexpr (COMP) {
+            float sx, ex;
+            two_sum(psi_v, (float)(inc.p[0] + (AR)lo_v), sx, ex);
+            if (zero_slot) sx = ex = 0.f;
+            gst<float>(orow, o, sx);
+            gst<float>(lrow, o, ex);
+            return;
+        }
+        float w = (float)((AR)psi_v + inc.p[0]);
+        if (zero_slot) w = 0.f;
+        gst<float>(orow, o, w);
     } else {
         double w = (double)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.0;
@@ -279,9 +311,7 @@ __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &ro
     }
 }
 
-// Prefetch depth of a code path: the near-axis tiles of FP32 storage (FP64 arithmetic, twice the registers
-// per value) share a launch with the main tiles and keep fewer rows in flight, so that the launch's
-// register allocation, the larger of the two paths, stays that of the main path.  HEAVY paths (the first
+// Prefetch depth of a code path.  HEAVY paths (the first
 // stage's current rows, the last stage's compensation words) carry more words per row and keep one row
 // less.  Wider stencils hold a longer rho window (2 N_D rows) and keep fewer rows in flight.  The aim is two
 // wavefronts per SIMD (at most 256 registers per lane).
@@ -289,7 +319,9 @@ template <typename V, typename AR, int ND, bool HEAVY>
 constexpr int prefetch_of()
 {
     constexpr int base = ND <= 8 ? FDETD_PREFETCH : (ND <= 12 ? FDETD_PREFETCH - 1 : FDETD_PREFETCH - 2);
-    constexpr int pf = sizeof(AR) > sizeof(typename scal<V>::R) ? (ND <= 8 ? 2 : 1) : (HEAVY ? base - 1 : base);
+    // FP64 arithmetic on whole complex values per lane (near-axis tiles of narrow stencils): 2 rows
+    constexpr bool wide = sizeof(AR) > sizeof(typename scal<V>::R) && elem<V>::K == 2;
+    constexpr int pf = wide ? 2 : (HEAVY ? base - 1 : base);
     return pf < 1 ? 1 : pf;
 }
 
@@ -327,7 +359,8 @@ __device__ __forceinline__ Halo halo_of(int i0, int nz, const Lane<V> &L)
     return h;
 }
 template <typename V, bool ADDJ>
-__device__ __forceinline__ RowPart<V> fetch_row(const V *plane, const V *jplane, int nz, int q, const Lane<V> &L,
+__device__ __forceinline__ RowPart<V> fetch_row(const typename stor<V>::T *plane, const typename stor<V>::T *jplane, int nz,
+                                                int q, const Lane<V> &L,
                                                 const Halo &H)
 {
     using E = typename elem<V>::E;
@@ -392,8 +425,9 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
     const int nz = D.nz, nr = D.nr;
     const Lane<V> L(i0, nz);
     const size_t P = D.plane;
-    const V *vin = (const V *)A.vin;
-    const V *Bth = vin + BTH * P, *Br = vin + BR * P, *Bz = vin + BZ * P;
+    using SV = typename stor<V>::T;
+    const SV *vin = (const SV *)A.vin;
+    const SV *Bth = vin + BTH * P, *Br = vin + BR * P, *Bz = vin + BZ * P;
     const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
     const L_ zero = zero_lv<AR, K>();
 
@@ -431,7 +465,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         E bz, bt, j0, j1, j2;
         RowPart<V> th, br;
         E p0, p1, p2;
-        float2 l0, l1, l2;
+        typename elem<V>::Lo l0, l1, l2;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -443,14 +477,14 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         x.br = fetch_row<V, false>(Br, nullptr, nz, k, L, H);
         x.j0 = x.j1 = x.j2 = E{};
         if constexpr (SRC) {
-            x.j0 = ldraw<V>((const V *)A.jr, nz, k, L);
-            x.j1 = ldraw<V>((const V *)A.jt, nz, k, L);
-            x.j2 = ldraw<V>((const V *)A.jz, nz, k, L);
+            x.j0 = ldraw<V>((const SV *)A.jr, nz, k, L);
+            x.j1 = ldraw<V>((const SV *)A.jt, nz, k, L);
+            x.j2 = ldraw<V>((const SV *)A.jz, nz, k, L);
         }
         x.p0 = ld_elem<V>(A.psi, ER, k, D, L);
         x.p1 = ld_elem<V>(A.psi, ETH, k, D, L);
         x.p2 = ld_elem<V>(A.psi, EZ, k, D, L);
-        x.l0 = x.l1 = x.l2 = float2{0.f, 0.f};
+        x.l0 = x.l1 = x.l2 = typename elem<V>::Lo{};
         if constexpr (COMP) {
             x.l0 = ld_elem<V>(D.lo, ER, k, D, L);
             x.l1 = ld_elem<V>(D.lo, ETH, k, D, L);
@@ -521,13 +555,14 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     const int nz = D.nz, nr = D.nr;
     const Lane<V> L(i0, nz);
     const size_t P = D.plane;
-    const V *vin = (const V *)A.vin;
-    const V *Er = vin + ER * P, *Eth = vin + ETH * P, *Ez = vin + EZ * P;
-    const V *Jr = (const V *)A.jr, *Jt = (const V *)A.jt, *Jz = (const V *)A.jz;
+    using SV = typename stor<V>::T;
+    const SV *vin = (const SV *)A.vin;
+    const SV *Er = vin + ER * P, *Eth = vin + ETH * P, *Ez = vin + EZ * P;
+    const SV *Jr = (const SV *)A.jr, *Jt = (const SV *)A.jt, *Jz = (const SV *)A.jz;
     const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
     const AR bin = (AR)A.beta_in;
     const L_ zero = zero_lv<AR, K>();
-    auto ldw = [&](const V *f, const V *jf, int q) -> L_ {
+    auto ldw = [&](const SV *f, const SV *jf, int q) -> L_ {
         L_ x = ldrow<V, AR>(f, nz, q, L);
         if constexpr (FIRST) x = fmav(bin, ldrow<V, AR>(jf, nz, q, L), x);
         return x;
@@ -559,7 +594,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         E ez, et, jz, jt;
         RowPart<V> th, er;
         E p0, p1, p2;
-        float2 l0, l1, l2;
+        typename elem<V>::Lo l0, l1, l2;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -577,7 +612,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
         x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
         x.p2 = ld_elem<V>(A.psi, BZ, k, D, L);
-        x.l0 = x.l1 = x.l2 = float2{0.f, 0.f};
+        x.l0 = x.l1 = x.l2 = typename elem<V>::Lo{};
         if constexpr (COMP) {
             x.l0 = ld_elem<V>(D.lo, BR, k, D, L);
             x.l1 = ld_elem<V>(D.lo, BTH, k, D, L);
@@ -661,8 +696,9 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
     return p;
 }
 
-// AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage only): rows
-// 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the axis and its 1/rho factors, in FP64 arithmetic.
+// AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage; V = float2 or,
+// for wide stencils, f2pair read in lane pairs): rows 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the
+// axis and its 1/rho factors, in FP64 arithmetic.
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP, bool AXIS>
 __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
@@ -679,7 +715,7 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.vin = first ? C.psi : D.buf[(A.N - 2 - A.n) & 1];
     C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
     C.has_src = A.has_src;
-    const size_t pb = D.plane * sizeof(V);
+    const size_t pb = D.plane * sizeof(typename stor<V>::T);
     C.jr = A.has_src ? D.jbar : nullptr;
     C.jt = A.has_src ? (const char *)A.aux[p] + pb : nullptr;
     C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
@@ -693,21 +729,33 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
 }
 
 // One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
+// Bytes of one LDS row of a layout.
+template <typename V, int ND>
+constexpr int lds_row_bytes()
+{
+    return (WAVE + 2 * ND * elem<V>::S) * (int)sizeof(typename elem<V>::E);
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
-    using E = typename elem<V>::E;
-    __shared__ E lds[2][WAVE + 2 * ND * elem<V>::S];
+    // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
+    using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
+    // two LDS rows, sized for the main layout and the near-axis one
+    __shared__ __align__(16) unsigned char smem[2 * cmax(lds_row_bytes<V, ND>(), lds_row_bytes<VA, ND>())];
     bool axis;
     const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
     if (t < 0) return;
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
-            maxwell_tile<V, ND, FIRST, SRC, COMP, true>(A, t, lds);
+            using EA = typename elem<VA>::E;
+            maxwell_tile<VA, ND, FIRST, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
-    maxwell_tile<V, ND, FIRST, SRC, COMP, false>(A, t, lds);
+    using E = typename elem<V>::E;
+    maxwell_tile<V, ND, FIRST, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -733,7 +781,8 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
     CDesc &D = *A.D;
     const int nz = D.nz, nr = D.nr;
     const Lane<V> L(i0, nz);
-    const V *va = (const V *)A.vin_a, *vt = (const V *)A.vin_t;
+    using SV = typename stor<V>::T;
+    const SV *va = (const SV *)A.vin_a, *vt = (const SV *)A.vin_t;
     const L_ zero = zero_lv<AR, K>();
     const AR pS = (AR)D.pS;
     constexpr int W = 2 * ND + 1;
@@ -760,7 +809,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         RowPart<V> a;
         R chi;
         E pa, pt;
-        float2 la, lt;
+        typename elem<V>::Lo la, lt;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -772,10 +821,11 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         const unsigned o = (unsigned)L.eidx;
         x.pa = gld<E>(row_ptr<E>(A.psi_a, 0, 0, nz, S, k), o);
         x.pt = gld<E>(row_ptr<E>(A.psi_t, 0, 0, nz, S, k), o);
-        x.la = x.lt = float2{0.f, 0.f};
+        x.la = x.lt = typename elem<V>::Lo{};
         if constexpr (COMP) {
-            x.la = gld<float2>(row_ptr<float2>(D.lo, 0, D.plane, nz, 1, k), o);
-            x.lt = gld<float2>(row_ptr<float2>(D.lo, 1, D.plane, nz, 1, k), o);
+            using Lo = typename elem<V>::Lo;
+            x.la = gld<Lo>(row_ptr<Lo>(D.lo, 0, D.plane, nz, S, k), o);
+            x.lt = gld<Lo>(row_ptr<Lo>(D.lo, 1, D.plane, nz, S, k), o);
         }
         return x;
     };
@@ -824,6 +874,19 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
                     gst<float2>(ra, o, float2{(float)((AR)cu.pa.x + ia.p[0]), (float)((AR)cu.pa.y + ia.p[1])});
                     gst<float2>(rt, o, float2{(float)((AR)cu.pt.x + it.p[0]), (float)((AR)cu.pt.y + it.p[1])});
                 }
+            } else if constexpr (std::is_same<E, float>::value) {  // FP32 storage in lane pairs
+                if constexpr (COMP) {
+                    float s0, e0, s1, e1;
+                    two_sum(cu.pa, (float)(ia.p[0] + (AR)cu.la), s0, e0);
+                    two_sum(cu.pt, (float)(it.p[0] + (AR)cu.lt), s1, e1);
+                    gst<float>(ra, o, s0);
+                    gst<float>(rt, o, s1);
+                    gst<float>((void *)row_ptr<float>(D.lo, 0, D.plane, nz, 2, k), o, e0);
+                    gst<float>((void *)row_ptr<float>(D.lo, 1, D.plane, nz, 2, k), o, e1);
+                } else {
+                    gst<float>(ra, o, (float)((AR)cu.pa + ia.p[0]));
+                    gst<float>(rt, o, (float)((AR)cu.pt + it.p[0]));
+                }
             } else {
                 gst<double>(ra, o, (double)((AR)cu.pa + ia.p[0]));
                 gst<double>(rt, o, (double)((AR)cu.pt + it.p[0]));
@@ -847,7 +910,7 @@ __device__ __forceinline__ void envelope_tile(const BatchArgs &A, int t, typenam
     EnvCtx C;
     C.D = &D;
     const bool first = A.n == A.N - 1;
-    const size_t pb = D.plane * sizeof(V);
+    const size_t pb = D.plane * sizeof(typename stor<V>::T);
     C.psi_a = A.psi[p];
     C.psi_t = A.aux[p];
     const void *ib = D.buf[(A.N - 2 - A.n) & 1], *ob = D.buf[(A.N - 1 - A.n) & 1];
@@ -866,18 +929,18 @@ __device__ __forceinline__ void envelope_tile(const BatchArgs &A, int t, typenam
 template <typename V, int ND, bool COMP>
 __global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
 {
-    using E = typename elem<V>::E;
-    __shared__ E lds[WAVE + 2 * ND * elem<V>::S];
+    using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
+    __shared__ __align__(16) unsigned char smem[cmax(lds_row_bytes<V, ND>(), lds_row_bytes<VA, ND>())];
     bool axis;
     const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
     if (t < 0) return;
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
-            envelope_tile<V, ND, COMP, true>(A, t, lds);
+            envelope_tile<VA, ND, COMP, true>(A, t, (typename elem<VA>::E *)smem);
             return;
         }
     }
-    envelope_tile<V, ND, COMP, false>(A, t, lds);
+    envelope_tile<V, ND, COMP, false>(A, t, (typename elem<V>::E *)smem);
 }
 
 // Launch stage n of a batch with the kernel variant its flags select.

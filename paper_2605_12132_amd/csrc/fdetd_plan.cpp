@@ -375,6 +375,7 @@ int build_batches(fdetd_plan_t P)
                 D.ax_rows = std::min(q.d.nr, axis_rows(q));
                 D.seg_ax = std::min(kSegAxis, D.ax_rows);
                 D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
+                D.nstrip_ax = (q.d.nz + axis_columns(q.nd) - 1) / axis_columns(q.nd);
             }
             D.seg_rows = seg;
             D.nseg = (q.d.nr - D.ax_rows + seg - 1) / seg;
@@ -403,7 +404,7 @@ int build_batches(fdetd_plan_t P)
                 D.br[k] = q.d2[k] / (q.d.dr * q.d.dr);
             }
             tiles += halves * D.nseg * D.nstrip;
-            tiles_ax += halves * D.nseg_ax * D.nstrip;
+            tiles_ax += halves * D.nseg_ax * D.nstrip_ax;
             P->desc.push_back(D);
             b.members.push_back(order[v]);
         }
@@ -414,39 +415,45 @@ int build_batches(fdetd_plan_t P)
         P->batches.push_back(b);
         t = u;
     }
-    // the two launches together must produce every (half, z strip, rho row) of each problem exactly once,
-    // from tiles that stay inside the grid
+    // the near-axis and main tiles together must produce every (half, z column, rho row) of each problem
+    // exactly once, from tiles that stay inside the grid (columns counted in units of kAxisColumns, which
+    // divides the main tiles' width)
+    if (cpw % kAxisColumns) return fail(P, FDETD_E_ARG, "internal: tile widths");
     for (const Batch &b : P->batches)
         for (int t = 0; t < b.count; ++t) {
             const ProbDesc &D = P->desc[b.d0 + t];
-            std::vector<unsigned char> seen((size_t)halves * D.nstrip * D.nr, 0);
+            const int units = (D.nz + kAxisColumns - 1) / kAxisColumns;
+            std::vector<unsigned char> seen((size_t)halves * units * D.nr, 0);
             for (int axis = 0; axis < 2; ++axis) {
-                const int nl = halves * (axis ? D.nseg_ax : D.nseg) * D.nstrip;
+                const int w = axis ? axis_columns(b.nd) : cpw;
+                const int nl = halves * (axis ? D.nseg_ax * D.nstrip_ax : D.nseg * D.nstrip);
                 int begin = 0;
                 for (int u = 0; u < t; ++u) {
                     const ProbDesc &E = P->desc[b.d0 + u];
-                    begin += halves * (axis ? E.nseg_ax : E.nseg) * E.nstrip;
+                    begin += halves * (axis ? E.nseg_ax * E.nstrip_ax : E.nseg * E.nstrip);
                 }
                 if ((axis ? D.tile_begin_ax : D.tile_begin) != begin)
                     return fail(P, FDETD_E_ARG, "internal: tile ranges of the batch are not contiguous");
                 for (int r = 0; r < nl; ++r) {
                     TileCoord c;
-                    if (!decode_tile(D, r, halves, axis != 0, cpw, c) || c.i0 % cpw || c.k1 > D.nr)
+                    if (!decode_tile(D, r, halves, axis != 0, w, c) || c.i0 % w || c.k1 > D.nr)
                         return fail(P, FDETD_E_ARG, "internal: tile %d of a %dx%d grid leaves the grid", r, D.nz, D.nr);
-                    for (int k = c.k0; k < c.k1; ++k)
-                        if (seen[((size_t)c.half * D.nstrip + c.i0 / cpw) * D.nr + k]++)
-                            return fail(P, FDETD_E_ARG, "internal: a row of a %dx%d grid is produced twice", D.nz, D.nr);
+                    const int u1 = std::min(units, (c.i0 + w) / kAxisColumns);
+                    for (int u = c.i0 / kAxisColumns; u < u1; ++u)
+                        for (int k = c.k0; k < c.k1; ++k)
+                            if (seen[((size_t)c.half * units + u) * D.nr + k]++)
+                                return fail(P, FDETD_E_ARG, "internal: a cell of a %dx%d grid is produced twice", D.nz, D.nr);
                 }
             }
             for (unsigned char v : seen)
-                if (v != 1) return fail(P, FDETD_E_ARG, "internal: a row of a %dx%d grid is not produced", D.nz, D.nr);
+                if (v != 1) return fail(P, FDETD_E_ARG, "internal: a cell of a %dx%d grid is not produced", D.nz, D.nr);
         }
     for (const Batch &b : P->batches) {
         int n_main = 0, n_ax = 0;
         for (int t = 0; t < b.count; ++t) {
             const ProbDesc &D = P->desc[b.d0 + t];
             n_main += halves * D.nseg * D.nstrip;
-            n_ax += halves * D.nseg_ax * D.nstrip;
+            n_ax += halves * D.nseg_ax * D.nstrip_ax;
         }
         if (n_main != b.ntiles || n_ax != b.ntiles_ax) return fail(P, FDETD_E_ARG, "internal: tile count mismatch");
     }
