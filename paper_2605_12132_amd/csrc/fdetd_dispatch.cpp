@@ -26,6 +26,17 @@ hipError_t launch_envelope_march(int prec, int nd, const BatchArgs &a, hipStream
     }
 }
 
+hipError_t launch_stagger_march(int prec, int nd, const BatchArgs &a, hipStream_t s)
+{
+    switch (nd) {
+#define C_(N) \
+    case N: return march_stagger_nd<N>(prec, a, s);
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10) C_(11) C_(12) C_(13) C_(14) C_(15) C_(16)
+#undef C_
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // A wavefront of 64 lanes covers 32 z columns in FP64 (a lane pair per complex value) and 64 in FP32 (one
 // lane per value); the kernels' lane mapping (elem<double2>::S = 2, elem<float2>::S = 1) matches this.
 int march_columns_per_wave(int prec) { return prec == P64 ? 32 : 64; }

@@ -60,14 +60,6 @@ struct EnvelopeStageArgs {
     double drc[kMaxND];         // ... / dr
 };
 
-struct StaggerArgs {
-    const void *jr;  // J_rho on the primary grid
-    void *out;       // Jbar_rho on the staggered rho grid (row 0 written as 0)
-    double pA;       // extension sign of polar-like (mA) components
-    int nz, nr;
-    double s[kMaxND];
-};
-
 struct AxisArgs {
     void *psi;  // 6 planes
     int nz, nr, m;
@@ -101,6 +93,7 @@ struct ProbDesc {
     float *lo;                               // FP32C compensation words
     const double *rinv_p, *rinv_s, *m2rinv2;
     double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
+    double sh[kMaxND];                                   // half-shift weights s_j (current staging)
     double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
 };
 
@@ -121,11 +114,15 @@ template <int ND>
 hipError_t march_maxwell_nd(int prec, const BatchArgs &a, hipStream_t s);  // one per N_D, in fdetd_march.hip
 template <int ND>
 hipError_t march_envelope_nd(int prec, const BatchArgs &a, hipStream_t s);
+template <int ND>
+hipError_t march_stagger_nd(int prec, const BatchArgs &a, hipStream_t s);
 #define FDETD_DECLARE_ND(N)                                                            \
     template <>                                                                        \
     hipError_t march_maxwell_nd<N>(int prec, const BatchArgs &a, hipStream_t s);       \
     template <>                                                                        \
-    hipError_t march_envelope_nd<N>(int prec, const BatchArgs &a, hipStream_t s);
+    hipError_t march_envelope_nd<N>(int prec, const BatchArgs &a, hipStream_t s);      \
+    template <>                                                                        \
+    hipError_t march_stagger_nd<N>(int prec, const BatchArgs &a, hipStream_t s);
 FDETD_DECLARE_ND(1) FDETD_DECLARE_ND(2) FDETD_DECLARE_ND(3) FDETD_DECLARE_ND(4) FDETD_DECLARE_ND(5)
 FDETD_DECLARE_ND(6) FDETD_DECLARE_ND(7) FDETD_DECLARE_ND(8) FDETD_DECLARE_ND(9) FDETD_DECLARE_ND(10)
 FDETD_DECLARE_ND(11) FDETD_DECLARE_ND(12) FDETD_DECLARE_ND(13) FDETD_DECLARE_ND(14) FDETD_DECLARE_ND(15)
@@ -133,11 +130,11 @@ FDETD_DECLARE_ND(16)
 #undef FDETD_DECLARE_ND
 hipError_t launch_maxwell_march(int prec, int nd, const BatchArgs &a, hipStream_t s);   // dispatch on nd
 hipError_t launch_envelope_march(int prec, int nd, const BatchArgs &a, hipStream_t s);
+hipError_t launch_stagger_march(int prec, int nd, const BatchArgs &a, hipStream_t s);  // aux = the step's currents
 int march_columns_per_wave(int prec);  // z columns covered by one wavefront (32 FP64, 64 FP32)
 
 hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s);
 hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s);
-hipError_t launch_stagger_jr(int prec, int nd, const StaggerArgs &a, hipStream_t s);
 hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s);
 // Per-block partial sums of |x|^2 over n complex values (double2 or float2); nblocks written to partial.
 hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s);

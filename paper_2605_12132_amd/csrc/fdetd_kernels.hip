@@ -312,35 +312,6 @@ __global__ __launch_bounds__(TZ *TR) void k_envelope_apply(EnvelopeStageArgs A)
 }
 
 // --------------------------------------------------------------------------------------------------
-// Current staging (section 2.5): Jbar_rho = S_rho^(-,mA) J_rho on the staggered rows k >= 1.
-// --------------------------------------------------------------------------------------------------
-template <typename V, int ND>
-__global__ __launch_bounds__(TZ *TR) void k_stagger_jr(StaggerArgs A)
-{
-    using R = typename storage<V>::R;
-    const int i = blockIdx.x * TZ + threadIdx.x;
-    const int k = blockIdx.y * TR + threadIdx.y;
-    if (i >= A.nz || k >= A.nr) return;
-    const V *j = (const V *)A.jr;
-    const double pA = A.pA;
-    auto rv = [&](int q) -> cx<double> {
-        if (q < 0) {
-            q = -1 - q;
-            if (q >= A.nr) return {0, 0};
-            return pA * ld<double>(j, (size_t)q * A.nz + i);
-        }
-        if (q >= A.nr) return {0, 0};
-        return ld<double>(j, (size_t)q * A.nz + i);
-    };
-    cx<double> s = {0, 0};
-    if (k >= 1) {
-#pragma unroll
-        for (int t = 1; t <= ND; ++t) s = s + A.s[t - 1] * (rv(k + t - 1) + rv(k - t));
-    }
-    ((V *)A.out)[(size_t)k * A.nz + i] = V{(R)s.x, (R)s.y};
-}
-
-// --------------------------------------------------------------------------------------------------
 // rho = 0 slots of E_rho, B_theta, B_z after a step (section 2.4): constant components take the
 // extrapolation sum c_k' F_k' (B_z for m = 0, E_rho and B_theta for m = 1); all others are 0.
 // --------------------------------------------------------------------------------------------------
@@ -431,14 +402,6 @@ struct EnvelopeL {
     }
 };
 template <typename V, int ND>
-struct StaggerL {
-    static hipError_t go(const StaggerArgs &a, dim3 g, dim3 b, hipStream_t s)
-    {
-        hipLaunchKernelGGL((k_stagger_jr<V, ND>), g, b, 0, s, a);
-        return hipGetLastError();
-    }
-};
-template <typename V, int ND>
 struct AxisL {
     static hipError_t go(const AxisArgs &a, dim3 g, dim3 b, hipStream_t s)
     {
@@ -463,13 +426,6 @@ hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, h
     const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
     return prec == P64 ? dispatch_nd<EnvelopeL, double2>(nd, a, g, b, s)
                        : dispatch_nd<EnvelopeL, float2>(nd, a, g, b, s);
-}
-
-hipError_t launch_stagger_jr(int prec, int nd, const StaggerArgs &a, hipStream_t s)
-{
-    const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
-    return prec == P64 ? dispatch_nd<StaggerL, double2>(nd, a, g, b, s)
-                       : dispatch_nd<StaggerL, float2>(nd, a, g, b, s);
 }
 
 hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s)

@@ -150,11 +150,11 @@ template <> struct elem<float2> {
     static constexpr int S = 1;
     static constexpr int K = 2;
 };
-template <> struct elem<f2pair> {
+template <> struct elem<f2pair> {  // used only by the translation units of wide stencils
     using E = float;
     using Lo = float;
-    static constexpr int S = 2;
-    static constexpr int K = 1;
+    [[maybe_unused]] static constexpr int S = 2;
+    [[maybe_unused]] static constexpr int K = 1;
 };
 
 template <typename AR>
@@ -943,6 +943,93 @@ __global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
     envelope_tile<V, ND, COMP, false>(A, t, (typename elem<V>::E *)smem);
 }
 
+// --------------------------------------------------------------------------------------------------
+// Current staging (section 2.5): Jbar_rho = S_rho^(-) J_rho on the rho-staggered rows k >= 1 (row 0 = 0),
+// the half-shift with the m_A mirror ghosts of section 2.4, in FP64 arithmetic.  J_theta and J_z are read
+// by the stages as they are.  Same tiling as the stage launch of the batch; only the tiles of the first
+// half carry work.  Window: primary rows q = k - N_D .. k + N_D - 1 of J_rho.
+// --------------------------------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ void store_value(void *row, unsigned o, const lv<double, elem<V>::K> &x)
+{
+    if constexpr (std::is_same<typename elem<V>::E, float2>::value) gst<float2>(row, o, float2{(float)x.p[0], (float)x.p[1]});
+    else if constexpr (std::is_same<typename elem<V>::E, float>::value) gst<float>(row, o, (float)x.p[0]);
+    else gst<double>(row, o, x.p[0]);
+}
+
+template <typename V, int ND, bool AXIS>
+__device__ __forceinline__ void stagger_tile(const BatchArgs &A, int t)
+{
+    constexpr int S = elem<V>::S, K = elem<V>::K, CPW = WAVE / S;
+    using E = typename elem<V>::E;
+    using SV = typename stor<V>::T;
+    using L_ = lv<double, K>;
+    const int p = problem_of_tile<AXIS>(A, t);
+    CDesc &D = ((CDesc *)A.probs)[p];
+    TileCoord tc;
+    if (!decode_tile(D, t - (AXIS ? D.tile_begin_ax : D.tile_begin), 2, AXIS, CPW, tc) || tc.half) return;
+    const int k0 = tc.k0, k1 = tc.k1, nz = D.nz, nr = D.nr;
+    const Lane<V> L(tc.i0, nz);
+    const SV *jr = (const SV *)A.aux[p];
+    const double pA = -D.pS;
+    const L_ zero = zero_lv<double, K>();
+    L_ W[2 * ND];
+    auto fill = [&]() {
+#pragma unroll
+        for (int t2 = 0; t2 < 2 * ND - 1; ++t2) {
+            const int q = k0 - ND + t2;
+            W[t2] = ldrow<V, double>(jr, nz, min(q < 0 ? -1 - q : q, nr - 1), L);
+        }
+#pragma unroll
+        for (int t2 = 0; t2 < 2 * ND - 1; ++t2) {
+            const int q = k0 - ND + t2;
+            W[t2] = q >= nr ? zero : (q < 0 ? pA : 1.0) * W[t2];
+        }
+    };
+    struct In {
+        E j;
+    };
+    auto fetch = [&](int k) -> In {
+        const int qn = k + ND - 1;
+        return In{ldraw<V>(jr, nz, qn < nr ? qn : nr - 1, L)};
+    };
+    auto row = [&](const In &cu, int k, bool live) {
+        const int qn = k + ND - 1;
+        W[2 * ND - 1] = keep_if(qn < nr, to_lv<double>(cu.j));
+        L_ s = zero;
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) s = fmav((double)D.sh[j - 1], W[ND + j - 1] + W[ND - j], s);
+        if (L.col && live)
+            store_value<V>((void *)row_ptr<E>(D.jbar, 0, 0, nz, S, k), (unsigned)L.eidx, k == 0 ? zero : s);
+#pragma unroll
+        for (int t2 = 0; t2 < 2 * ND - 1; ++t2) W[t2] = W[t2 + 1];
+    };
+    march_rows<In, FDETD_PREFETCH>(k0, k1, fetch, row, fill);
+}
+
+template <typename V, int ND>
+__global__ __launch_bounds__(WAVE) void k_stagger_march(BatchArgs A)
+{
+    bool axis;
+    const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
+    if (t < 0) return;
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (axis) {
+            stagger_tile<typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type, ND, true>(A, t);
+            return;
+        }
+    }
+    stagger_tile<V, ND, false>(A, t);
+}
+
+template <typename V, int ND>
+hipError_t go_stagger(const BatchArgs &a, hipStream_t s)
+{
+    if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
+    hipLaunchKernelGGL((k_stagger_march<V, ND>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0, s, a);
+    return hipGetLastError();
+}
+
 // Launch stage n of a batch with the kernel variant its flags select.
 template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
@@ -1002,6 +1089,11 @@ hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
     hipError_t march_envelope_nd<N>(int prec, const BatchArgs &a, hipStream_t s)                     \
     {                                                                                                \
         return prec == P64 ? go_envelope<double2, N>(a, s) : go_envelope<float2, N>(a, s);           \
+    }                                                                                                \
+    template <>                                                                                      \
+    hipError_t march_stagger_nd<N>(int prec, const BatchArgs &a, hipStream_t s)                      \
+    {                                                                                                \
+        return prec == P64 ? go_stagger<double2, N>(a, s) : go_stagger<float2, N>(a, s);             \
     }
 
 #ifndef FDETD_ND_LO

@@ -208,16 +208,16 @@ int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j,
     const int prec = prec_code(P->precision);
     const size_t eb = elem_bytes(P->precision);
     if (j) {
-        for (size_t p = 0; p < P->probs.size(); ++p) {
-            const Prob &q = P->probs[p];
-            StaggerArgs S{};
-            S.jr = j[p];
-            S.out = q.jbar;
-            S.pA = -parity_mS(q.d.m);
-            S.nz = q.d.nz;
-            S.nr = q.d.nr;
-            for (int t = 0; t < q.nd; ++t) S.s[t] = q.s[t];
-            HIPCHK(P, launch_stagger_jr(prec, q.nd, S, P->stream));
+        // stage the current of every problem: one launch per batch, over the batch's stage tiling
+        for (const Batch &b : P->batches) {
+            BatchArgs A;
+            std::memset(&A, 0, sizeof A);
+            A.probs = P->ddesc + b.d0;
+            A.nprob = b.count;
+            A.ntiles = b.ntiles;
+            A.ntiles_ax = b.ntiles_ax;
+            for (int t = 0; t < b.count; ++t) A.aux[t] = j[b.members[t]];
+            if (b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, P->stream));
         }
     }
     for (const Batch &b : P->batches) {
@@ -396,6 +396,7 @@ int build_batches(fdetd_plan_t P)
                 D.az[k] = q.a[k] / q.d.dz;
                 D.ar[k] = q.a[k] / q.d.dr;
                 D.cax[k] = q.c[k];
+                D.sh[k] = q.s[k];
                 D.dzc[k] = q.d1[k] / q.d.dz;
                 D.drc[k] = q.d1[k] / q.d.dr;
             }
@@ -827,7 +828,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if (P->kind == FDETD_MAXWELL) {
             // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
-            launches += 2;  // current staging and axis rule (stage launches counted per batch below)
+            launches += 1;  // axis rule (staging and stage launches are counted per batch below)
         } else {
             // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
             bytes_step += (int64_t)q.cells * (eb * 6 + eb / 2) * N + (precision == FDETD_FP32C ? q.cells * 2 * 8 * 2 : 0);
@@ -864,7 +865,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.cells = cells;
     P->info.bytes_per_step = bytes_step;
     P->info.scratch_bytes = scratch;
-    for (const Batch &b : P->batches) launches += (int64_t)b.N * (b.ntiles + b.ntiles_ax > 0);
+    for (const Batch &b : P->batches)
+        launches += (int64_t)(b.N + (P->kind == FDETD_MAXWELL)) * (b.ntiles + b.ntiles_ax > 0);
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
