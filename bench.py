@@ -291,6 +291,48 @@ def batched_pass(steps, warmup):
                 fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
 
 
+def envelope_pass(steps):
+    """The envelope-in-plasma workload (4096 x 512, order 8, Taylor 4, dt = dz/2, static chi): FP64 and
+    FP32C plans, graph replay of `steps` steps.  Its working set (about 220 MB in FP64) mostly fits the
+    256 MB Infinity Cache, so the rate is reported without an HBM fraction."""
+    import torch
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+    w = I.envelope_plasma()
+    a0, at0 = I.envelope_initial(w)
+    chi = I.envelope_chi(w)
+    cells = w.cells()
+    out, res = {}, {}
+    for tag, prec, cd, rd in (("fp64", F.FP64, torch.complex128, torch.float64),
+                              ("fp32c", F.FP32C, torch.complex64, torch.float32)):
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            a = torch.from_numpy(a0).to(device="cuda", dtype=cd)
+            at = torch.from_numpy(at0).to(device="cuda", dtype=cd)
+            ch = torch.from_numpy(chi).to(device="cuda", dtype=rd)
+            plan = F.Plan(w.problems(), precision=prec, flags=F.PLAN_USE_GRAPH)
+            plan.envelope_step([a], [at], [ch], n_steps=steps)      # capture + first replay (untimed)
+            a.copy_(torch.from_numpy(a0).to(device="cuda", dtype=cd))
+            at.copy_(torch.from_numpy(at0).to(device="cuda", dtype=cd))
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            plan.envelope_step([a], [at], [ch], n_steps=steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            plan.close()
+        out[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps)
+        res[tag] = (a.cpu().numpy().astype(np.complex128), at.cpu().numpy().astype(np.complex128))
+        log(f"envelope {tag}: {ms / steps:.4f} ms/step, {out[tag]['value']:.4g} cell-updates/s")
+    x64 = np.concatenate([res["fp64"][0].ravel(), res["fp64"][1].ravel()])
+    x32 = np.concatenate([res["fp32c"][0].ravel(), res["fp32c"][1].ravel()])
+    return dict(workload=w.name, cells=cells, steps=steps, graph=True, cache_resident=True,
+                fp64=out["fp64"], fp32c=out["fp32c"], fp32c_vs_fp64=out["fp32c"]["value"] / out["fp64"]["value"],
+                fp32c_rel_l2=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +347,8 @@ def main():
     ap.add_argument("--seg-rows-fp32c", type=int, default=None, help="the same for the FP32C plans")
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="steps of the 64-problem batched workload reported beside the headline (0: skip)")
+    ap.add_argument("--envelope-steps", type=int, default=2000,
+                    help="steps of the envelope workload reported beside the headline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -359,6 +403,7 @@ def main():
         del psi64
         torch.cuda.empty_cache()
         batched = batched_pass(args.batched_steps, W)
+    envelope = envelope_pass(args.envelope_steps) if args.envelope_steps > 0 and not args.fp64_only else None
     cpu = None if args.no_cpu else cpu_baseline(w)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
@@ -374,6 +419,7 @@ def main():
         "tiling": dict(seg_rows=info64["seg_rows"], autotune_ms=round(info64["autotune_ms"], 1)),
         "fp32c": fp32c,
         "batched": batched,
+        "envelope": envelope,
     }
     print(json.dumps(out), flush=True)
 

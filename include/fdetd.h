@@ -8,7 +8,8 @@
  * HIP stream and return immediately; results are valid once that stream has synchronised.
  *
  * ---------------------------------------------------------------------------------------------------
- * Storage (all arrays contiguous, 16-byte aligned):
+ * Storage (all arrays contiguous, each aligned to its element: 16 B FP64 / 8 B FP32C complex,
+ * 8 B / 4 B real):
  *   plane          [nr][nz] interleaved complex, z fastest: double2 for FDETD_FP64, float2 for FDETD_FP32C.
  *   Maxwell state  psi: 6 consecutive planes E_rho, E_theta, E_z, B_rho, B_theta, B_z of one azimuthal
  *                  mode m in the complex form F_m = F_{2m} + i F_{2m+1} of the paper's real mode pair

@@ -727,7 +727,8 @@ int validate(const fdetd_problem_desc &d, int idx)
     return FDETD_OK;
 }
 
-bool aligned(const void *p) { return p && ((uintptr_t)p % 16) == 0; }
+// Non-null and aligned to a bytes (the element: complex 16 B FP64 / 8 B FP32C, real 8 / 4 B).
+bool aligned(const void *p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
 
 }  // namespace
 
@@ -993,9 +994,11 @@ int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, i
     if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_step: plan is not a Maxwell plan");
     if (!psi || n_steps < 0 || j_step_blocks < 0) return fail(plan, FDETD_E_ARG, "fdetd_step: bad arguments");
     for (size_t p = 0; p < plan->probs.size(); ++p) {
-        if (!aligned(psi[p])) return fail(plan, FDETD_E_ARG, "fdetd_step: psi[%zu] NULL or not 16-byte aligned", p);
-        if (j_half && !aligned(j_half[p]))
-            return fail(plan, FDETD_E_ARG, "fdetd_step: j_half[%zu] NULL or not 16-byte aligned", p);
+        const size_t eb = elem_bytes(plan->precision);
+        if (!aligned(psi[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_step: psi[%zu] NULL or not %zu-byte aligned", p, eb);
+        if (j_half && !aligned(j_half[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_step: j_half[%zu] NULL or not %zu-byte aligned", p, eb);
     }
     if (n_steps == 0) return FDETD_OK;
     for (size_t p = 0; p < plan->probs.size(); ++p) {
@@ -1025,9 +1028,10 @@ int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const
     if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_step: plan is not an envelope plan");
     if (!a || !a_tilde || !chi_half || n_steps < 0 || chi_step_planes < 0)
         return fail(plan, FDETD_E_ARG, "envelope_step: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
     for (size_t p = 0; p < plan->probs.size(); ++p)
-        if (!aligned(a[p]) || !aligned(a_tilde[p]) || !aligned(chi_half[p]))
-            return fail(plan, FDETD_E_ARG, "envelope_step: pointer of problem %zu NULL or not 16-byte aligned", p);
+        if (!aligned(a[p], eb) || !aligned(a_tilde[p], eb) || !aligned(chi_half[p], eb / 2))
+            return fail(plan, FDETD_E_ARG, "envelope_step: pointer of problem %zu NULL or misaligned", p);
     if (n_steps == 0) return FDETD_OK;
     for (size_t p = 0; p < plan->probs.size(); ++p) {
         Prob &q = plan->probs[p];

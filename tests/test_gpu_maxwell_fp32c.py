@@ -48,9 +48,11 @@ def test_fp32c_without_source_and_graph():
     assert rel_l2(eager[0], want[0]) < TOL32
 
 
-def test_fp32c_envelope_matches_oracle():
+@pytest.mark.parametrize("order,m", [(8, 0), (24, 1)])
+def test_fp32c_envelope_matches_oracle(order, m):
+    """Order 8: near-axis tiles with a whole complex value per lane; order 24: read in lane pairs."""
     dz = I.LAMBDA0 / 5
-    w = I.Workload("env32", 1, [203], [41], [0], [8], 4, dz, 0.2 * I.UM, 0.5 * dz, 10, seed=8,
+    w = I.Workload("env32", 1, [203], [41], [m], [order], 4, dz, 0.2 * I.UM, 0.5 * dz, 10, seed=8,
                    extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=10 * I.UM, chi0=1e-3, mod=0.05))
     a0, at0 = I.envelope_initial(w)
     chi = I.envelope_chi(w)
@@ -89,3 +91,43 @@ def test_export_import_resume_is_bitwise():
     assert p64.export_state() == b""
     for p in (pa, pc, p64):
         p.close()
+
+
+@pytest.mark.parametrize("order,nr,nz", [(32, 20, 70), (16, 20, 33), (4, 8, 9)])
+def test_fp32c_grid_all_near_axis(order, nr, nz):
+    """Grids with fewer than 2 N_D rows: every row is a near-axis row (FP64 arithmetic), the launch has
+    near-axis tiles only; minimal z extents included (N_z = 2 N_D + 1)."""
+    w = small(1, order, 8, nz=nz, nr=nr, steps=2)
+    rng = np.random.default_rng(order + nr)
+    psi0 = [rng.uniform(-1, 1, (6, nr, nz)) + 1j * rng.uniform(-1, 1, (6, nr, nz))]
+    J = [0.1 * (rng.uniform(-1, 1, (2, 3, nr, nz)) + 1j * rng.uniform(-1, 1, (2, 3, nr, nz)))]
+    got, info = gpu_maxwell(w, psi0, J, 2, precision=F.FP32C, flags=1)
+    want = oracle_maxwell(w, psi0, J, 2)
+    err = rel_l2(got[0], want[0])
+    log(f"fp32c all near-axis order {order} {nz}x{nr}: rel L2 {err:.2e}")
+    assert err < TOL32
+
+
+def test_fp32c_element_alignment():
+    """FP32C buffers need only their element's alignment (8 bytes): with an odd cell count the current of
+    step 1 starts 8 bytes past a 16-byte boundary and is accepted; a pointer 4 bytes off is rejected on the
+    host before anything is enqueued."""
+    import torch
+    from paper_2605_12132_amd import binding as B
+    w = small(1, 8, 4, nz=151, nr=37, steps=2)
+    assert (3 * 37 * 151 * 8) % 16 == 8
+    rng = np.random.default_rng(5)
+    psi0 = rng.uniform(-1, 1, (6, 37, 151)) + 1j * rng.uniform(-1, 1, (6, 37, 151))
+    J = 0.1 * (rng.uniform(-1, 1, (3, 3, 37, 151)) + 1j * rng.uniform(-1, 1, (3, 3, 37, 151)))
+    jd = dev(J, torch.complex64)
+    psi = dev(psi0, torch.complex64)
+    plan = F.Plan(w.problems(), precision=F.FP32C, flags=1)
+    assert jd[1:].data_ptr() % 16 == 8
+    plan.step([psi], [jd[1:]], n_steps=2)
+    torch.cuda.synchronize()
+    want = oracle_maxwell(w, [psi0], [J[1:]], 2)
+    assert rel_l2(psi.cpu().numpy().astype(np.complex128), want[0]) < TOL32
+    with pytest.raises(F.FdetdError) as e:
+        B.fdetd_step(plan._h, [psi.data_ptr() + 4], None, 0, 1)
+    assert e.value.code == -1 and "aligned" in str(e.value)
+    plan.close()
