@@ -90,6 +90,8 @@ def lib():
         L.oracle_envelope_energy.argtypes = [P, vp, vp, vp, vp]
         L.oracle_envelope_energy.restype = None
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_deposit_rho.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
+        L.oracle_deposit_jz.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
         _lib = L
     return _lib
 
@@ -144,6 +146,32 @@ def stage_current(g: Grid, j) -> np.ndarray:
     out = np.zeros_like(x)
     P = g.c()
     _chk(lib().oracle_stage_current(C.byref(P), _ptr(x), _ptr(out)), "stage_current")
+    return out
+
+
+def _samples(samples) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
+    if x.ndim != 2 or x.shape[1] != 4:
+        raise ValueError("samples: [n, 4] array of (z, x, y, q w)")
+    return x
+
+
+def deposit_rho(g: Grid, samples, dz_shift: float = 0.0, eps: float = 0.5) -> np.ndarray:
+    """Charge density of mode g.m of the samples shifted by dz_shift along z, [nr, nz] complex."""
+    x = _samples(samples)
+    out = np.zeros((g.nr, g.nz), np.complex128)
+    P = g.c()
+    _chk(lib().oracle_deposit_rho(C.byref(P), _ptr(x), x.shape[0], dz_shift, eps, _ptr(out)), "deposit_rho")
+    return out
+
+
+def deposit_jz(g: Grid, samples, vz: float = 1.0, eps: float = 0.5, j=None) -> np.ndarray:
+    """Longitudinal current of the samples moving with vz, added into plane 2 of j ([3, nr, nz], zeros
+    when None); returns j."""
+    x = _samples(samples)
+    out = np.zeros((3, g.nr, g.nz), np.complex128) if j is None else _cplx(j, (3, g.nr, g.nz)).copy()
+    P = g.c()
+    _chk(lib().oracle_deposit_jz(C.byref(P), _ptr(x), x.shape[0], vz, eps, _ptr(out)), "deposit_jz")
     return out
 
 

@@ -638,3 +638,112 @@ void oracle_envelope_energy(const oracle_problem *P, const double complex *a,
     *energy = W;
     *zc = (W > 0.0) ? Wz / W : 0.0;
 }
+
+/* ---------------------------------------------------------------------------------------------------
+ * Deposition of point samples (sections 3.2, 3.5, 3.6), the source of the prescribed bunch current.
+ * A sample is (z, x, y, q w); it moves with velocity vz along z (no transverse motion).
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Cubic B-spline particle shape (3rd order) of a distance x in cells; its integer shifts sum to 1. */
+static double bspline3(double x)
+{
+    x = fabs(x);
+    if (x < 1.0) return 2.0 / 3.0 - x * x + 0.5 * x * x * x;
+    if (x < 2.0) {
+        const double t = 2.0 - x;
+        return t * t * t / 6.0;
+    }
+    return 0.0;
+}
+
+/* Quadrature weights of the radial integral from the axis on the primary rows (section 3.5). */
+static double h_weight(int k) { return k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0); }
+
+/* Radial shape of section 3.5 of a sample at rho_p on primary row k >= 0 (rho_k = (k + 1/2) dr), with
+ * the part at rho < 0 folded back onto row k with the component's parity p (reading A21):
+ *   N^-1 rho_k^(eps - 1) (w_k + p w_(-1-k)),   w_j = S3((rho_j - rho_p) / dr),
+ *   N = sum_(k >= 0) h_k rho_k^eps (w_k + w_(-1-k)) dr   (the sample's shape on the folded grid). */
+static double radial_norm(const oracle_problem *P, double rho_p, double eps)
+{
+    double N = 0.0;
+    for (int k = 0; (k + 0.5) * P->dr < rho_p + 3.0 * P->dr; ++k) {
+        const double rk = (k + 0.5) * P->dr;
+        const double w = bspline3((rk - rho_p) / P->dr) + bspline3((-rk - rho_p) / P->dr);
+        N += h_weight(k) * pow(rk, eps) * w * P->dr;
+    }
+    return N;
+}
+static double radial_shape(const oracle_problem *P, double rho_p, double eps, double N, int parity, int k)
+{
+    const double rk = (k + 0.5) * P->dr;
+    const double w = bspline3((rk - rho_p) / P->dr) + parity * bspline3((-rk - rho_p) / P->dr);
+    return pow(rk, eps - 1.0) * w / N;
+}
+
+/* Angular shape of section 3.2, deposition form (l = 1), as the complex mode coefficient of the
+ * convention F = Re sum_m F_m e^(i m theta) (reading A22): 1/(2 pi) for m = 0, e^(-i m theta_p)/pi else. */
+static cplx angular_shape(int m, double theta)
+{
+    if (m == 0) return 1.0 / (2.0 * M_PI);
+    return (cos(m * theta) - I * sin(m * theta)) / M_PI;
+}
+
+/* Charge density of mode m (m_S parity) of the samples shifted by dz_shift along z, added into rho. */
+int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, double dz_shift, double eps,
+                       double complex *rho)
+{
+    if (check_problem(P) || !samples || !rho || n < 0) return -1;
+    const int nz = P->nz, nr = P->nr, p = parity_mS(P->m);
+    for (long s = 0; s < n; ++s) {
+        const double z = samples[4 * s] + dz_shift, x = samples[4 * s + 1], y = samples[4 * s + 2];
+        const double qw = samples[4 * s + 3];
+        const double rho_p = sqrt(x * x + y * y);
+        const double N = radial_norm(P, rho_p, eps);
+        const cplx ang = angular_shape(P->m, atan2(y, x));
+        for (int k = 0; k < nr; ++k) {
+            const double rs = radial_shape(P, rho_p, eps, N, p, k);
+            if (rs == 0.0) continue;
+            for (int i = 0; i < nz; ++i) {
+                const double sz = bspline3(i - z / P->dz) / P->dz;
+                if (sz != 0.0) rho[(size_t)k * nz + i] += qw * sz * rs * ang;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Longitudinal current of section 3.6 (samples moving with vz, no transverse motion), added into plane
+ * 2 of j (3 planes J_rho, J_theta, J_z; J_z on the z-staggered points z_i - dz/2).  The integrated shape
+ * F(i) = sum_(i' < i) S3(i' - z/dz) of the positions z -+ vz dt/2 gives, from the discrete continuity
+ * equation (reading A20),  J_z(i - 1/2) = q w (F_-(i) - F_+(i)) / dt * radial shape * angular shape. */
+int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, double vz, double eps,
+                      double complex *j)
+{
+    if (check_problem(P) || !samples || !j || n < 0 || !(P->dt > 0)) return -1;
+    const int nz = P->nz, nr = P->nr, p = parity_mS(P->m);
+    double complex *jz = j + 2 * (size_t)nz * nr;
+    double *dF = malloc(sizeof(double) * (size_t)nz);
+    if (!dF) return -2;
+    for (long s = 0; s < n; ++s) {
+        const double z = samples[4 * s], x = samples[4 * s + 1], y = samples[4 * s + 2];
+        const double qw = samples[4 * s + 3];
+        const double zp = (z + 0.5 * vz * P->dt) / P->dz, zm = (z - 0.5 * vz * P->dt) / P->dz;
+        double Fp = 0.0, Fm = 0.0;
+        for (int i = 0; i < nz; ++i) {  /* F(i): nodes i' < i */
+            dF[i] = (Fm - Fp) / P->dt;
+            Fp += bspline3(i - zp);
+            Fm += bspline3(i - zm);
+        }
+        const double rho_p = sqrt(x * x + y * y);
+        const double N = radial_norm(P, rho_p, eps);
+        const cplx ang = angular_shape(P->m, atan2(y, x));
+        for (int k = 0; k < nr; ++k) {
+            const double rs = radial_shape(P, rho_p, eps, N, p, k);
+            if (rs == 0.0) continue;
+            for (int i = 0; i < nz; ++i)
+                if (dF[i] != 0.0) jz[(size_t)k * nz + i] += qw * dF[i] * rs * ang;
+        }
+    }
+    free(dF);
+    return 0;
+}

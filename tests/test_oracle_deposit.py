@@ -1,0 +1,90 @@
+"""Pins of the oracle's sample deposition (sections 3.2, 3.5, 3.6; readings A20-A22):
+
+- the current and the shifted charge densities satisfy the discrete continuity equation exactly, which
+  fixes the sign and scale of the integrated z shape;
+- the deposited charge, integrated with the cylindrical volume weights (h_k rho_k dr dz 2 pi for mode 0),
+  equals the samples' total, next to the axis (where the shape is folded) included;
+- the angular shape is a Fourier projection: a ring of equally spaced samples cancels modes 1 and 2, and the
+  modes resummed on a theta grid peak at the sample's angle;
+- a sample on the axis has no odd-mode content (the folded radial shape cancels).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def grid(m, nz=64, nr=24, dz=0.2, dr=0.5, dt=0.1):
+    return oracle.Grid(nz=nz, nr=nr, m=m, fd_order=4, taylor_order=4, dz=dz, dr=dr, dt=dt)
+
+
+def bunch(rng, n, g, zlo, zhi, rmax, near_axis=True):
+    z = rng.uniform(zlo, zhi, n)
+    r = rng.uniform(0.0, rmax, n)
+    if near_axis:
+        r[: n // 4] = rng.uniform(0.0, 1.5 * g.dr, n // 4)
+    th = rng.uniform(-math.pi, math.pi, n)
+    w = rng.uniform(0.5, 1.5, n)
+    return np.stack([z, r * np.cos(th), r * np.sin(th), w], axis=1)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_deposit_continuity_equation(m):
+    g = grid(m)
+    rng = np.random.default_rng(10 + m)
+    s = bunch(rng, 300, g, 3.0, 9.0, 6.0)
+    vz = 1.0
+    rho_p = oracle.deposit_rho(g, s, +0.5 * vz * g.dt)
+    rho_m = oracle.deposit_rho(g, s, -0.5 * vz * g.dt)
+    jz = oracle.deposit_jz(g, s, vz)[2]
+    # J_z plane index i sits at z_i - dz/2: the divergence at node i is (J[i+1] - J[i]) / dz
+    div = (jz[:, 1:] - jz[:, :-1]) / g.dz
+    res = (rho_p - rho_m)[:, :-1] / g.dt + div
+    assert np.max(np.abs(res)) < 1e-12 * np.max(np.abs(rho_p) / g.dt)
+    assert np.max(np.abs(jz)) > 0
+    # a bunch moving forward carries a current of the sign of its charge
+    if m == 0:
+        assert np.sum(jz.real) > 0
+
+
+def test_deposit_charge_conservation():
+    g = grid(0)
+    rng = np.random.default_rng(3)
+    s = bunch(rng, 400, g, 3.0, 9.0, 6.0)
+    rho = oracle.deposit_rho(g, s).real
+    rk = (np.arange(g.nr) + 0.5) * g.dr
+    h = np.ones(g.nr)
+    h[0], h[1] = 7.0 / 8.0, 73.0 / 72.0
+    total = np.sum(rho * (h * rk)[:, None]) * g.dr * g.dz * 2 * math.pi
+    assert abs(total / np.sum(s[:, 3]) - 1) < 1e-13
+
+
+def test_deposit_ring_and_reconstruction():
+    rng = np.random.default_rng(8)
+    z, r, th0 = 6.0, 2.3, 0.7
+    M = 7
+    ring = np.array([[z, r * math.cos(th0 + 2 * math.pi * j / M), r * math.sin(th0 + 2 * math.pi * j / M), 1.0]
+                     for j in range(M)])
+    one = ring[:1]
+    F = {m: oracle.deposit_rho(grid(m), one) for m in range(3)}
+    R = {m: oracle.deposit_rho(grid(m), ring) for m in range(3)}
+    for m in (1, 2):
+        assert np.max(np.abs(R[m])) < 1e-13 * np.max(np.abs(F[m]))
+    assert np.allclose(R[0], M * F[0], rtol=1e-13, atol=0)
+    # resum the modes on a theta grid at the sample's cell: F(theta) = Re sum_m F_m e^(i m theta)
+    k, i = int(r / 0.5), int(round(z / 0.2))
+    thetas = np.linspace(-math.pi, math.pi, 3601)
+    f = sum((F[m][k, i] * np.exp(1j * m * thetas)).real for m in range(3))
+    assert abs(thetas[np.argmax(f)] - th0) < 2e-3
+    del rng
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_deposit_on_axis_has_no_odd_modes(m):
+    g = grid(m)
+    s = np.array([[6.0, 0.0, 0.0, 1.0]])
+    assert np.max(np.abs(oracle.deposit_rho(g, s))) == 0.0
+    assert np.max(np.abs(oracle.deposit_jz(g, s))) == 0.0
+    assert np.max(np.abs(oracle.deposit_rho(grid(0), s))) > 0
