@@ -688,6 +688,14 @@ static cplx angular_shape(int m, double theta)
     return (cos(m * theta) - I * sin(m * theta)) / M_PI;
 }
 
+/* A sample is deposited only when its z shape lies on grid nodes: nodes floor(z/dz) - 1 .. floor(z/dz) + 2
+ * inside [0, nz) (for the current: for both positions z -+ vz dt/2).  Charge entering or leaving at a z
+ * end would otherwise show up in the integrated shape as a current along the whole grid. */
+static int z_inside(const oracle_problem *P, double zc)
+{
+    return floor(zc) - 1 >= 0 && floor(zc) + 2 <= P->nz - 1;
+}
+
 /* Charge density of mode m (m_S parity) of the samples shifted by dz_shift along z, added into rho. */
 int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, double dz_shift, double eps,
                        double complex *rho)
@@ -696,6 +704,7 @@ int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, d
     const int nz = P->nz, nr = P->nr, p = parity_mS(P->m);
     for (long s = 0; s < n; ++s) {
         const double z = samples[4 * s] + dz_shift, x = samples[4 * s + 1], y = samples[4 * s + 2];
+        if (!z_inside(P, z / P->dz)) continue;
         const double qw = samples[4 * s + 3];
         const double rho_p = sqrt(x * x + y * y);
         const double N = radial_norm(P, rho_p, eps);
@@ -728,9 +737,13 @@ int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, do
         const double z = samples[4 * s], x = samples[4 * s + 1], y = samples[4 * s + 2];
         const double qw = samples[4 * s + 3];
         const double zp = (z + 0.5 * vz * P->dt) / P->dz, zm = (z - 0.5 * vz * P->dt) / P->dz;
+        if (!z_inside(P, zp) || !z_inside(P, zm)) continue;
+        /* F(i) over nodes i' < i; outside nodes lo .. hi both shapes are wholly left or wholly right of
+         * i - 1/2, so F_- = F_+ there and the current is zero */
+        const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
         double Fp = 0.0, Fm = 0.0;
-        for (int i = 0; i < nz; ++i) {  /* F(i): nodes i' < i */
-            dF[i] = (Fm - Fp) / P->dt;
+        for (int i = 0; i < nz; ++i) {
+            dF[i] = (i >= lo && i <= hi) ? (Fm - Fp) / P->dt : 0.0;
             Fp += bspline3(i - zp);
             Fm += bspline3(i - zm);
         }

@@ -80,7 +80,8 @@ void oracle_envelope_energy(const oracle_problem *P, const double complex *a,
 
 /* Deposition of point samples (z, x, y, q w per sample; sections 3.2, 3.5, 3.6, readings A20-A22):
  * the charge density of mode m of the samples shifted by dz_shift along z, and the longitudinal current
- * of samples moving with vz (plane 2 of the 3-plane j).  Both add into their output. */
+ * of samples moving with vz (plane 2 of the 3-plane j).  Both add into their output.  Samples whose z
+ * shape reaches past either z end of the grid are not deposited. */
 int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, double dz_shift, double eps,
                        double complex *rho);
 int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, double vz, double eps,

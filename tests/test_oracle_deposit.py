@@ -88,3 +88,15 @@ def test_deposit_on_axis_has_no_odd_modes(m):
     assert np.max(np.abs(oracle.deposit_rho(g, s))) == 0.0
     assert np.max(np.abs(oracle.deposit_jz(g, s))) == 0.0
     assert np.max(np.abs(oracle.deposit_rho(grid(0), s))) > 0
+
+
+def test_deposit_skips_samples_at_the_z_ends():
+    """A sample whose shape reaches past a z end is not deposited; one just inside is, wholly."""
+    g = grid(0)
+    inside = np.array([[1.0 * g.dz + 0.01 + 0.5 * g.dt, 1.0, 0.5, 1.0]])   # node floor - 1 = 0 at z -+ dt/2
+    outside = np.array([[0.5 * g.dz, 1.0, 0.5, 1.0]])
+    end = np.array([[(g.nz - 1.5) * g.dz, 1.0, 0.5, 1.0]])
+    assert np.max(np.abs(oracle.deposit_jz(g, inside))) > 0
+    for s in (outside, end):
+        assert np.max(np.abs(oracle.deposit_jz(g, s))) == 0.0
+        assert np.max(np.abs(oracle.deposit_rho(g, s))) == 0.0
