@@ -333,6 +333,62 @@ def envelope_pass(steps):
                 fp32c_rel_l2=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)))
 
 
+def lwfa_pass(steps, warmup, n_samples=10 ** 6):
+    """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
+    each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
+    of peak density n_b) moving at c, deposited with fdetd_deposit_jz (timed separately, including the
+    advance of the sample positions), then graph replay of `steps` field steps.  FP64 and FP32C; the FP32C
+    error against FP64 after the same steps."""
+    import torch
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+    w = I.lwfa_scale()
+    e = w.extra
+    nz, nr = w.nz[0], w.nr[0]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.seed)
+    base = torch.randn((n_samples, 4), generator=g, device="cuda", dtype=torch.float64)
+    base[:, 0] = 0.25 * nz * w.dz + e["sigz"] * base[:, 0]
+    base[:, 1:3] *= e["sigr"]
+    base[:, 3] = -e["nb"] * (2 * math.pi) ** 1.5 * e["sigz"] * e["sigr"] ** 2 / n_samples
+    cells = w.cells()
+    res, psis = {}, {}
+    for tag, prec, cd in (("fp64", F.FP64, torch.complex128), ("fp32c", F.FP32C, torch.complex64)):
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            plan = F.Plan(w.problems(), precision=prec, flags=0)
+            J = [torch.zeros((warmup + steps, 3, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            smp = base.clone()
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for st in range(warmup + steps):
+                smp[:, 0] = base[:, 0] + (st + 0.5) * w.dt
+                plan.deposit_jz(smp, [j[st] for j in J], vz=1.0, eps=0.5)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            dep_ms = ev0.elapsed_time(ev1) / (warmup + steps)
+            plan.close()
+        psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
+        del J
+        torch.cuda.empty_cache()
+        gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
+        res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
+                        frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms,
+                        seg_rows=info["seg_rows"])
+        psis[tag] = psi
+        log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
+            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step")
+    num = den = 0.0
+    for a, b in zip(psis["fp64"], psis["fp32c"]):
+        num += float(torch.sum(torch.abs(a - b.to(torch.complex128)) ** 2))
+        den += float(torch.sum(torch.abs(a) ** 2))
+    return dict(workload=w.name, cells=cells, steps=steps, warmup=warmup, samples=n_samples, graph=True,
+                fp64=res["fp64"], fp32c=res["fp32c"], fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
+                fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +403,8 @@ def main():
     ap.add_argument("--seg-rows-fp32c", type=int, default=None, help="the same for the FP32C plans")
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="steps of the 64-problem batched workload reported beside the headline (0: skip)")
+    ap.add_argument("--lwfa-steps", type=int, default=20,
+                    help="steps of the LWFA-scale workload reported beside the headline (0: skip)")
     ap.add_argument("--envelope-steps", type=int, default=2000,
                     help="steps of the envelope workload reported beside the headline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -404,6 +462,7 @@ def main():
         torch.cuda.empty_cache()
         batched = batched_pass(args.batched_steps, W)
     envelope = envelope_pass(args.envelope_steps) if args.envelope_steps > 0 and not args.fp64_only else None
+    lwfa = lwfa_pass(args.lwfa_steps, W) if args.lwfa_steps > 0 and not args.fp64_only else None
     cpu = None if args.no_cpu else cpu_baseline(w)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
@@ -420,6 +479,7 @@ def main():
         "fp32c": fp32c,
         "batched": batched,
         "envelope": envelope,
+        "lwfa": lwfa,
     }
     print(json.dumps(out), flush=True)
 

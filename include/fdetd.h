@@ -141,6 +141,23 @@ FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const 
 FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
                   int64_t chi_step_planes, int32_t n_steps);
 
+/* Deposit the longitudinal current of n point samples (a prescribed particle bunch) into J_z, plane 2
+ * of j_half[p], of every problem p of a Maxwell plan, adding to what is there (sections 3.2, 3.5, 3.6):
+ *   J_z(z_i - dz/2, rho_k) += q w (F_-(i) - F_+(i)) / dt * R_k * A_m
+ * with F_-+(i) the cubic-spline weight of the positions z -+ vz dt/2 on the nodes left of z_i - dz/2 (the
+ * integrated shape of section 3.6, signed by the discrete continuity equation), R_k the radial shape of
+ * section 3.5 (rho_k^(eps-1) times the spline weight, the part beyond the axis folded back with the mode's
+ * m_S parity, normalised with the quadrature weights h_0 = 7/8, h_1 = 73/72, h_k = 1) and A_m the
+ * deposition form of the angular shape of section 3.2 (1/(2 pi) for m = 0, e^(-i m theta)/pi otherwise,
+ * for the mode convention of fdetd_step).  Samples move along z only; a sample whose shape reaches past
+ * a z end of a grid is not deposited into it.
+ *   samples  device array of n x 4 doubles: z, x, y, charge * weight (normalised units), 8-byte aligned.
+ *   vz       velocity along z, |vz| dt <= 3 dz for every problem; eps in [0, 1] (0.5 in the paper).
+ *   j_half   n_probs device pointers as for fdetd_step (3 planes each, the plan's precision).
+ * Enqueue only.  The adds are atomic, so the order of the summation, and the last bits, vary between runs. */
+FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
+                               void *const *j_half);
+
 /* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
 FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);
 

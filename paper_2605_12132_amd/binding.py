@@ -21,7 +21,7 @@ MAXWELL, ENVELOPE = 0, 1
 PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE = 1, 2, 4, 8
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "fdetd_query", "fdetd_export_state",
+EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "fdetd_deposit_jz", "fdetd_query", "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
 
@@ -77,6 +77,7 @@ def _load():
     L.fdetd_plan.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.c_int32, C.c_uint32, vp, C.POINTER(vp)]
     L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
+    L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
     L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.fdetd_import_state.argtypes = [vp, vp, C.c_size_t]
@@ -126,6 +127,11 @@ def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_blocks: int = 0, n_steps: int
 
 def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_planes: int = 0, n_steps: int = 1):
     rc = lib.envelope_step(plan, _ptrs(a_ptrs), _ptrs(at_ptrs), _ptrs(chi_ptrs), chi_step_planes, n_steps)
+    _check(rc, plan)
+
+
+def fdetd_deposit_jz(plan, samples_ptr, n: int, vz: float, eps: float, j_ptrs):
+    rc = lib.fdetd_deposit_jz(plan, samples_ptr, n, vz, eps, _ptrs(j_ptrs))
     _check(rc, plan)
 
 
@@ -212,6 +218,17 @@ class Plan:
                     raise ValueError("j_half has fewer steps than n_steps")
                 stride = 1
         fdetd_step(self._h, pp, jp, stride, n_steps)
+
+    def deposit_jz(self, samples, j_half, vz: float = 1.0, eps: float = 0.5):
+        """Add the longitudinal current of point samples (float64 [n, 4] cuda tensor of z, x, y, q w) into
+        plane 2 of each problem's current (list of [3, nr, nz] tensors of the plan's precision)."""
+        import torch
+        if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 4
+                and samples.is_contiguous()):
+            raise ValueError("samples: contiguous float64 cuda tensor [n, 4]")
+        self._nchk(j_half, "j_half")
+        jp = [self._chk(x, (3, p.nr, p.nz), self._cdtype(), "j_half") for x, p in zip(j_half, self.problems)]
+        fdetd_deposit_jz(self._h, samples.data_ptr(), samples.shape[0], vz, eps, jp)
 
     def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):
         cd, rd = self._cdtype(), self._rdtype()

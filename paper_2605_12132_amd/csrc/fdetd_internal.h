@@ -88,6 +88,7 @@ struct ProbDesc {
     int tile_begin, tile_begin_ax;           // first tile of this problem in the main / near-axis launch
     size_t plane;                            // nz * nr
     double dr, pS, k0;
+    double dz, dt;                           // cell length in z and time step (sample deposition)
     void *buf[2];                            // ping-pong stage vectors
     const void *jbar;                        // staggered J_rho plane
     float *lo;                               // FP32C compensation words
@@ -136,6 +137,17 @@ int march_columns_per_wave(int prec);  // z columns covered by one wavefront (32
 hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s);
 hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s);
 hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s);
+
+// Deposition of point samples into J_z of every problem of a batch (atomic adds in the storage precision).
+struct DepositArgs {
+    const ProbDesc *probs;  // device table of the batch's problems
+    int nprob;
+    int64_t n;              // samples
+    const double *samples;  // n x 4: z, x, y, q w
+    double vz, eps;
+    void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2)
+};
+hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
 // Per-block partial sums of |x|^2 over n complex values (double2 or float2); nblocks written to partial.
 hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s);
 hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s);

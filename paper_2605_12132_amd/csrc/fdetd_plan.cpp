@@ -383,6 +383,8 @@ int build_batches(fdetd_plan_t P)
             D.tile_begin_ax = tiles_ax;
             D.plane = q.cells;
             D.dr = q.d.dr;
+            D.dz = q.d.dz;
+            D.dt = q.d.dt;
             D.pS = parity_mS(q.d.m);
             D.k0 = q.d.k0;
             D.buf[0] = q.buf[0];
@@ -880,6 +882,38 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         return FDETD_E_HIP;
     }
     *out = P;
+    return FDETD_OK;
+}
+
+int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
+                     void *const *j_half)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_deposit_jz: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: plan is not a Maxwell plan");
+    if (n < 0 || !j_half || (n > 0 && !aligned(samples, 8)) || !(eps >= 0.0 && eps <= 1.0) || !std::isfinite(vz))
+        return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        const Prob &q = plan->probs[p];
+        if (!aligned(j_half[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: j_half[%zu] NULL or not %zu-byte aligned", p, eb);
+        // the two shapes of a sample span at most 8 nodes
+        if (std::fabs(vz) * q.d.dt > 3.0 * q.d.dz)
+            return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: problem %zu: |vz| dt exceeds 3 cells", p);
+    }
+    if (n == 0) return FDETD_OK;
+    for (const Batch &b : plan->batches) {
+        DepositArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = plan->ddesc + b.d0;
+        A.nprob = b.count;
+        A.n = n;
+        A.samples = samples;
+        A.vz = vz;
+        A.eps = eps;
+        for (int t = 0; t < b.count; ++t) A.j[t] = j_half[b.members[t]];
+        HIPCHK(plan, launch_deposit_jz(prec_code(plan->precision), A, plan->stream));
+    }
     return FDETD_OK;
 }
 
