@@ -495,8 +495,9 @@ BatchArgs tuning_args(fdetd_plan_t P, const Batch &b, const std::vector<void *> 
 }
 
 // Plan-time autotuning of the marching segment length: each launch batch runs a few timed stages at every
-// candidate length on the plan's zeroed buffers and keeps the fastest.  The stage results do not depend on
-// the tiling (every output is formed by the same operations in the same order), only the speed does.
+// candidate length (8 .. 256 rows) on tuning-only buffers and keeps the fastest.  The stage results do
+// not depend on the tiling (every output is formed by the same operations in the same order), only the
+// speed does.
 int autotune(fdetd_plan_t P, double &ms_spent)
 {
     ms_spent = 0.0;
@@ -537,8 +538,9 @@ int autotune(fdetd_plan_t P, double &ms_spent)
             const ProbDesc &D = P->desc[P->batches[bi].d0 + t];
             rows[bi] = std::max(rows[bi], D.nr - D.ax_rows);
         }
-    static const int kCand[] = {8, 16, 32, 64};
-    constexpr int kNC = 4;
+    // longer segments repay on tall grids and wide stencils (the window fill is 2 N_D - 1 rows per segment)
+    static const int kCand[] = {8, 16, 32, 64, 128, 256};
+    constexpr int kNC = 6;
     // candidate c of batch bi is timed unless a shorter candidate already covers the batch's rows
     auto distinct = [&](int ci, size_t bi) { return ci == 0 || kCand[ci - 1] < rows[bi]; };
     std::vector<double> t_ms(nb * kNC, 1e300);

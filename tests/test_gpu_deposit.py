@@ -3,8 +3,10 @@
 A bunch of samples concentrated near the axis (the shapes fold across it there) plus a spread of samples,
 including some within two cells of the z ends (skipped by both sides), is deposited for modes 0, 1, 2 of
 one grid in one batched plan.  The adds are atomic, so only the order of the summation differs from the
-oracle: FP64 agrees to relative L2 <= 1e-12 per mode, FP32C (float atomics of values formed in FP64) to
-1e-6.  The deposit adds into plane 2 only.
+oracle: FP64 agrees to relative L2 <= 1e-12 per mode.  FP32C adds values formed in FP64 with float atomics
+in a varying order: each add rounds the running sum (float epsilon 6e-8), a cell takes a few hundred adds
+of random-sign weights whose partial sums exceed the final value several times, so the bound is 1e-5
+(runs measure 5e-7 .. 1.3e-6).  The deposit adds into plane 2 only.
 """
 import math
 
@@ -42,7 +44,7 @@ def test_deposit_matches_oracle(precision):
     J = [dev(b, cd) for b in base]
     plan.deposit_jz(dev(s, torch.float64), J, vz=1.0, eps=0.5)
     torch.cuda.synchronize()
-    tol = 1e-12 if precision == F.FP64 else 1e-6
+    tol = 1e-12 if precision == F.FP64 else 1e-5
     for p in range(3):
         g = oracle.Grid(nz=nz, nr=nr, m=p, fd_order=16, taylor_order=8, dz=dz, dr=2 * dz, dt=0.5 * dz)
         want = oracle.deposit_jz(g, s, vz=1.0, eps=0.5)

@@ -54,3 +54,33 @@ def test_envelope_single_stage_and_minimal_grid():
         ga, gt, _ = gpu_envelope(w, [a0], [at0], [chi], 1, flags=1)
         oa, ot = oracle_envelope(w, [a0], [at0], [chi], 1)
         assert rel_l2(both(ga[0], gt[0]), both(oa[0], ot[0])) < 1e-13, order
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_envelope_batched_uneven(precision):
+    """Envelope problems of different sizes, orders and modes in one plan (one launch per batch of equal
+    order): each matches the oracle and, bitwise, its single-problem plan (eager and graph)."""
+    import paper_2605_12132_amd as F
+    dz = I.LAMBDA0 / 5
+    nz, nr, m, order = [203, 97, 150, 64], [41, 23, 60, 17], [0, 1, 2, 0], [8, 8, 16, 4]
+    w = I.Workload("env_batch", 1, nz, nr, m, order, 4, dz, 0.2 * I.UM, 0.5 * dz, 6, seed=9,
+                   extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=8 * I.UM, chi0=1e-3, mod=0.05))
+    rng = np.random.default_rng(19)
+    a0, at0, chi = [], [], []
+    for p in range(w.n):
+        a0.append(rng.uniform(-1, 1, (nr[p], nz[p])) + 1j * rng.uniform(-1, 1, (nr[p], nz[p])))
+        at0.append(rng.uniform(-1, 1, (nr[p], nz[p])) + 1j * rng.uniform(-1, 1, (nr[p], nz[p])))
+        chi.append(1e-3 * (1 + 0.05 * rng.uniform(-1, 1, (nr[p], nz[p]))))
+    ga, gt, info = gpu_envelope(w, a0, at0, chi, 6, precision=precision, flags=1)
+    gga, ggt, _ = gpu_envelope(w, a0, at0, chi, 6, precision=precision, flags=3)
+    oa, ot = oracle_envelope(w, a0, at0, chi, 6)
+    tol = 1e-12 if precision == 0 else 2e-5
+    for p in range(w.n):
+        err = rel_l2(both(ga[p], gt[p]), both(oa[p], ot[p]))
+        log(f"envelope batch problem {p} (order {order[p]}, m={m[p]}, precision {precision}): rel L2 {err:.2e}")
+        assert err < tol
+        assert np.array_equal(ga[p], gga[p]) and np.array_equal(gt[p], ggt[p])
+        ws = I.Workload("env_one", 1, [nz[p]], [nr[p]], [m[p]], [order[p]], 4, dz, 0.2 * I.UM, 0.5 * dz, 6)
+        sa, st, _ = gpu_envelope(ws, [a0[p]], [at0[p]], [chi[p]], 6, precision=precision, flags=1)
+        assert np.array_equal(sa[0], ga[p]) and np.array_equal(st[0], gt[p])
+    del F

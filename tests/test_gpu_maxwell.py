@@ -193,9 +193,37 @@ def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
     runs["tuned"], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1)
     runs["graph"], _ = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=3)
     log(f"autotuned: {info['seg_rows']} rows per segment (near-axis {info['seg_rows_axis']}), {info['autotune_ms']:.1f} ms")
-    assert info["seg_rows"] in (8, 16, 32, 64) and info["autotune_ms"] > 0
+    assert info["seg_rows"] in (8, 16, 32, 64, 128, 256) and info["autotune_ms"] > 0
     assert info["seg_rows_axis"] == (0 if precision == 0 else 8)
     for k, v in runs.items():
         assert np.array_equal(v[0], runs["1"][0]), k
     if precision == 0:
         assert rel_l2(runs["1"][0], oracle_maxwell(w, psi0, J, 2)[0]) < TOL64
+
+
+def test_graph_recaptures_when_pointers_change():
+    """A graph plan replays its captured graph only for the exact previous call (same pointers, step count,
+    current stride); other calls capture anew.  Alternating two state buffers and step counts gives the
+    eager results each time."""
+    import torch
+    import paper_2605_12132_amd as F
+    from helpers import dev
+    w = small(1, 8, 8, nz=160, nr=40, steps=3, seed=6)
+    rng = np.random.default_rng(12)
+    psi0 = random_state(w, 0, rng)
+    J = random_current(w, 0, 3, rng)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        jd = dev(J, torch.complex128)
+        a, b = dev(psi0, torch.complex128), dev(psi0, torch.complex128)
+        g = F.Plan(w.problems(), precision=F.FP64, flags=F.PLAN_USE_GRAPH | 1)
+        e = F.Plan(w.problems(), precision=F.FP64, flags=1)
+        ea, eb = dev(psi0, torch.complex128), dev(psi0, torch.complex128)
+        for x, ex, n in ((a, ea, 1), (b, eb, 1), (a, ea, 1), (a, ea, 2), (b, eb, 2), (b, eb, 2)):
+            g.step([x], [jd], n_steps=n)
+            e.step([ex], [jd], n_steps=n)
+        torch.cuda.synchronize()
+        assert torch.equal(a, ea) and torch.equal(b, eb)
+        g.close()
+        e.close()
