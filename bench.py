@@ -277,7 +277,7 @@ def batched_pass(steps, warmup):
         gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
         res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
                         frac=round(gbs / HBM_PEAK_GBS, 4), launches_per_step=info["launches_per_step"],
-                        plan_s=round(plan_s, 2), autotune_ms=round(info["autotune_ms"], 1))
+                        plan_s=round(plan_s, 2), autotune_ms=round(info["autotune_ms"], 1), streams=info["streams"])
         psis[tag] = psi
         log(f"batched {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, "
             f"{gbs:.0f} GB/s algorithmic ({info['launches_per_step']} launches/step, plan {plan_s:.1f} s)")

@@ -64,6 +64,7 @@ extern "C" {
 #define FDETD_PLAN_USE_GRAPH      2u  /* fdetd_step / envelope_step replay a captured hipGraph        */
 #define FDETD_PLAN_PROFILE        4u  /* time every stage kernel with HIP events (not with USE_GRAPH)  */
 #define FDETD_PLAN_NO_AUTOTUNE    8u  /* keep the default tiling instead of timing candidates at plan time */
+#define FDETD_PLAN_ONE_STREAM    16u  /* enqueue every launch on the plan's stream (no side streams)    */
 
 typedef struct fdetd_plan_s *fdetd_plan_t;
 
@@ -95,6 +96,7 @@ typedef struct {
      * FP32C near-axis launch (0 without one), and the plan-time autotuning that picked them (0 ms: none) */
     int32_t seg_rows, seg_rows_axis;
     double autotune_ms;
+    int32_t streams;  /* streams a step call runs on: 1, or up to 4 when the plan has several launch batches */
 } fdetd_plan_info;
 
 /* Build a plan for n_probs problems (all FDETD_MAXWELL or all FDETD_ENVELOPE).
@@ -107,8 +109,12 @@ typedef struct {
  * 2.4: axis extrapolation weights), allocates the plan's scratch (ping-pong stage vectors, staggered
  * current, FP32C compensation words) and, unless FDETD_PLAN_SKIP_STABILITY, estimates the spectral radius
  * of each H by power iteration on the GPU and rejects the plan with FDETD_E_UNSTABLE when
- * dt * rho_hat * 1.02 >= X_N (largest x with |T_N(i y)| <= 1 + 1e-9 for all y <= x).  Synchronises the
- * stream before returning. */
+ * dt * rho_hat * 1.02 >= X_N (largest x with |T_N(i y)| <= 1 + 1e-9 for all y <= x).  Problems are
+ * grouped into launch batches by (fd_order, taylor_order, dt); a plan with several batches also creates
+ * up to three side streams (default priority, non-blocking) and runs the batches concurrently: each step
+ * call forks them from `stream` with an event and joins them back into it, so the call still orders like
+ * work enqueued on `stream` alone (FDETD_PLAN_ONE_STREAM or FDETD_PLAN_PROFILE: no side streams).
+ * Synchronises the stream before returning. */
 FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precision, uint32_t flags,
                void *stream, fdetd_plan_t *out);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libfdetd.so")
 FDETD_OK, FDETD_E_ARG, FDETD_E_UNSTABLE, FDETD_E_NOMEM, FDETD_E_HIP = 0, -1, -2, -3, -4
 FP64, FP32C = 0, 1
 MAXWELL, ENVELOPE = 0, 1
-PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE = 1, 2, 4, 8
+PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_STREAM = 1, 2, 4, 8, 16
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "fdetd_deposit_jz", "fdetd_query", "fdetd_export_state",
@@ -43,7 +43,8 @@ class PlanInfo(C.Structure):
                 ("stability_margin", C.c_double), ("cells", C.c_int64), ("bytes_per_step", C.c_int64),
                 ("scratch_bytes", C.c_int64), ("launches_per_step", C.c_int64),
                 ("profiled_launches", C.c_int64), ("profiled_ms", C.c_double), ("profiled_bytes", C.c_double),
-                ("seg_rows", C.c_int32), ("seg_rows_axis", C.c_int32), ("autotune_ms", C.c_double)]
+                ("seg_rows", C.c_int32), ("seg_rows_axis", C.c_int32), ("autotune_ms", C.c_double),
+                ("streams", C.c_int32)]
 
 
 @dataclass

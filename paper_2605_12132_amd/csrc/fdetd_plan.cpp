@@ -51,6 +51,7 @@ struct Prob {
 struct Batch {
     int nd, N, d0, count, ntiles, ntiles_ax;
     int seg;                   // rows per marching segment of the main launch
+    int lane = 0;              // stream of the batch's launches: 0 = the plan's stream, l > 0 = lanes[l - 1]
     double dt;
     std::vector<int> members;  // user indices, in table order
 };
@@ -75,6 +76,10 @@ struct fdetd_plan_s {
     std::vector<double> ev_bytes;
     bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
     std::vector<int> seg_rows;  // per launch batch: rows per marching segment of the main launch
+    // side streams of a plan whose launch batches run concurrently, with the fork and join events
+    std::vector<hipStream_t> lanes;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
 };
 
 namespace {
@@ -191,117 +196,163 @@ int zero_device(fdetd_plan_t P, void *ptr, size_t bytes)
 }
 
 // One stage of one launch batch: the main tiles and, FP32C, the near-axis tiles in one launch.
-int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A)
+int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A, hipStream_t s)
 {
     const int prec = prec_code(P->precision);
     A.ntiles = b.ntiles;
     A.ntiles_ax = b.ntiles_ax;
     if (A.ntiles + A.ntiles_ax == 0) return FDETD_OK;
-    HIPCHK(P, P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, P->stream)
-                                       : launch_envelope_march(prec, b.nd, A, P->stream));
+    HIPCHK(P, P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, s) : launch_envelope_march(prec, b.nd, A, s));
     return FDETD_OK;
 }
 
-// One Maxwell step of every problem: stage the currents, N batched Horner stages, the axis rule.
-int enqueue_maxwell_step(fdetd_plan_t P, void *const *psi, const void *const *j, int last_step_of_call)
+// One Maxwell step of the problems of batch b on stream s: stage the currents, N Horner stages, then the
+// N = 1 copy and, at the end of a call, the axis rule of each problem.
+int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, const void *const *j,
+                          int last_step_of_call, hipStream_t s)
 {
     const int prec = prec_code(P->precision);
     const size_t eb = elem_bytes(P->precision);
-    if (j) {
-        // stage the current of every problem: one launch per batch, over the batch's stage tiling
-        for (const Batch &b : P->batches) {
-            BatchArgs A;
-            std::memset(&A, 0, sizeof A);
-            A.probs = P->ddesc + b.d0;
-            A.nprob = b.count;
-            A.ntiles = b.ntiles;
-            A.ntiles_ax = b.ntiles_ax;
-            for (int t = 0; t < b.count; ++t) A.aux[t] = j[b.members[t]];
-            if (b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, P->stream));
-        }
+    BatchArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.probs = P->ddesc + b.d0;
+    A.nprob = b.count;
+    A.ntiles = b.ntiles;
+    A.ntiles_ax = b.ntiles_ax;
+    size_t cells = 0;
+    for (int t = 0; t < b.count; ++t) {
+        A.psi[t] = psi[b.members[t]];
+        A.aux[t] = j ? j[b.members[t]] : nullptr;
+        cells += P->probs[b.members[t]].cells;
     }
-    for (const Batch &b : P->batches) {
-        BatchArgs A;
-        std::memset(&A, 0, sizeof A);
-        A.probs = P->ddesc + b.d0;
-        A.nprob = b.count;
-        A.ntiles = b.ntiles;
-        A.N = b.N;
-        A.has_src = j != nullptr;
-        A.compensated = P->precision == FDETD_FP32C;
-        size_t cells = 0;
-        for (int t = 0; t < b.count; ++t) {
-            A.psi[t] = psi[b.members[t]];
-            A.aux[t] = j ? j[b.members[t]] : nullptr;
-            cells += P->probs[b.members[t]].cells;
-        }
-        for (int n = b.N - 1; n >= 0; --n) {
-            A.n = n;
-            A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
-            A.beta = -b.dt * std::ldexp(1.0, -n);
-            A.coef = b.dt / (n + 1);
-            // algorithmic bytes: vin (6c) + psi (6c; the same data in the first stage) + Jbar (3c) + vout (6c)
-            const double cvals = (n == b.N - 1 ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
-            const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
-            int rc = profile_begin(P, bytes);
-            if (rc) return rc;
-            if ((rc = launch_stage(P, b, A))) return rc;
-            if ((rc = profile_end(P))) return rc;
-        }
+    if (j && b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, s));
+    A.N = b.N;
+    A.has_src = j != nullptr;
+    A.compensated = P->precision == FDETD_FP32C;
+    for (int n = b.N - 1; n >= 0; --n) {
+        A.n = n;
+        A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
+        A.beta = -b.dt * std::ldexp(1.0, -n);
+        A.coef = b.dt / (n + 1);
+        // algorithmic bytes: vin (6c) + psi (6c; the same data in the first stage) + Jbar (3c) + vout (6c)
+        const double cvals = (n == b.N - 1 ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
+        const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
+        int rc = profile_begin(P, bytes);
+        if (rc) return rc;
+        if ((rc = launch_stage(P, b, A, s))) return rc;
+        if ((rc = profile_end(P))) return rc;
     }
-    for (size_t p = 0; p < P->probs.size(); ++p) {
+    for (int t = 0; t < b.count; ++t) {
+        const int p = b.members[t];
         const Prob &q = P->probs[p];
-        if (q.d.taylor_order == 1) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, P->stream));
+        if (q.d.taylor_order == 1) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, s));
         if (last_step_of_call) {
             AxisArgs X{};
             X.psi = psi[p];
             X.nz = q.d.nz;
             X.nr = q.d.nr;
             X.m = q.d.m;
-            for (int t = 0; t < q.nd; ++t) X.cax[t] = q.c[t];
-            HIPCHK(P, launch_axis_fix(prec, q.nd, X, P->stream));
+            for (int u = 0; u < q.nd; ++u) X.cax[u] = q.c[u];
+            HIPCHK(P, launch_axis_fix(prec, q.nd, X, s));
         }
     }
     return FDETD_OK;
 }
 
-int enqueue_envelope_step(fdetd_plan_t P, void *const *a, void *const *at, const void *const *chi)
+// One envelope step of the problems of batch b on stream s.
+int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void *const *at, const void *const *chi,
+                           hipStream_t s)
 {
     const size_t eb = elem_bytes(P->precision);
-    for (const Batch &b : P->batches) {
-        BatchArgs A;
-        std::memset(&A, 0, sizeof A);
-        A.probs = P->ddesc + b.d0;
-        A.nprob = b.count;
-        A.ntiles = b.ntiles;
-        A.N = b.N;
-        A.compensated = P->precision == FDETD_FP32C;
-        size_t cells = 0;
-        for (int t = 0; t < b.count; ++t) {
-            A.psi[t] = a[b.members[t]];
-            A.aux[t] = at[b.members[t]];
-            A.chi[t] = chi[b.members[t]];
-            cells += P->probs[b.members[t]].cells;
-        }
-        for (int n = b.N - 1; n >= 0; --n) {
-            A.n = n;
-            A.coef = b.dt / (n + 1);
-            // algorithmic bytes: vin (2c) + psi (2c; the same data in the first stage) + chi + vout (2c)
-            const double cvals = (n == b.N - 1 ? 4.0 : 6.0) + 0.5;
-            const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 2 * cells * 8 : 0.0);
-            int rc = profile_begin(P, bytes);
-            if (rc) return rc;
-            if ((rc = launch_stage(P, b, A))) return rc;
-            if ((rc = profile_end(P))) return rc;
-        }
+    BatchArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.probs = P->ddesc + b.d0;
+    A.nprob = b.count;
+    A.ntiles = b.ntiles;
+    A.N = b.N;
+    A.compensated = P->precision == FDETD_FP32C;
+    size_t cells = 0;
+    for (int t = 0; t < b.count; ++t) {
+        A.psi[t] = a[b.members[t]];
+        A.aux[t] = at[b.members[t]];
+        A.chi[t] = chi[b.members[t]];
+        cells += P->probs[b.members[t]].cells;
     }
-    for (size_t p = 0; p < P->probs.size(); ++p) {
+    for (int n = b.N - 1; n >= 0; --n) {
+        A.n = n;
+        A.coef = b.dt / (n + 1);
+        // algorithmic bytes: vin (2c) + psi (2c; the same data in the first stage) + chi + vout (2c)
+        const double cvals = (n == b.N - 1 ? 4.0 : 6.0) + 0.5;
+        const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 2 * cells * 8 : 0.0);
+        int rc = profile_begin(P, bytes);
+        if (rc) return rc;
+        if ((rc = launch_stage(P, b, A, s))) return rc;
+        if ((rc = profile_end(P))) return rc;
+    }
+    for (int t = 0; t < b.count; ++t) {
+        const int p = b.members[t];
         const Prob &q = P->probs[p];
         if (q.d.taylor_order == 1) {
             const size_t plane_b = q.cells * eb;
-            HIPCHK(P, launch_copy(q.buf[0], a[p], plane_b, P->stream));
-            HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at[p], plane_b, P->stream));
+            HIPCHK(P, launch_copy(q.buf[0], a[p], plane_b, s));
+            HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at[p], plane_b, s));
         }
+    }
+    return FDETD_OK;
+}
+
+// Launch batches hold disjoint problems, so a call can run them on several streams: the side streams
+// wait for an event recorded on the plan's stream when the call starts, and the plan's stream waits for
+// an event recorded on each side stream when it ends.  Under graph capture the same pattern gives a
+// graph with one branch per stream.
+int fork_lanes(fdetd_plan_t P)
+{
+    if (P->lanes.empty()) return FDETD_OK;
+    HIPCHK(P, hipEventRecord(P->fork_ev, P->stream));
+    for (hipStream_t s : P->lanes) HIPCHK(P, hipStreamWaitEvent(s, P->fork_ev, 0));
+    return FDETD_OK;
+}
+
+int join_lanes(fdetd_plan_t P)
+{
+    for (size_t l = 0; l < P->lanes.size(); ++l) {
+        HIPCHK(P, hipEventRecord(P->join_ev[l], P->lanes[l]));
+        HIPCHK(P, hipStreamWaitEvent(P->stream, P->join_ev[l], 0));
+    }
+    return FDETD_OK;
+}
+
+hipStream_t lane_stream(fdetd_plan_t P, const Batch &b) { return b.lane ? P->lanes[b.lane - 1] : P->stream; }
+
+// Streams of a plan with more than one launch batch: longest-processing-time assignment of the batches
+// (work ~ cells x (N + 1)) to at most kMaxLanes streams, the plan's own stream being lane 0.  Profiled
+// plans and FDETD_PLAN_ONE_STREAM keep every launch on the plan's stream.
+int assign_lanes(fdetd_plan_t P)
+{
+    constexpr int kMaxLanes = 4;
+    for (Batch &b : P->batches) b.lane = 0;
+    const int nl = std::min<int>(kMaxLanes, (int)P->batches.size());
+    if (nl < 2 || (P->flags & (FDETD_PLAN_PROFILE | FDETD_PLAN_ONE_STREAM))) return FDETD_OK;
+    std::vector<int> order(P->batches.size());
+    std::vector<double> work(P->batches.size(), 0.0), load(nl, 0.0);
+    for (size_t i = 0; i < order.size(); ++i) {
+        order[i] = (int)i;
+        for (int p : P->batches[i].members) work[i] += (double)P->probs[p].cells * (P->batches[i].N + 1);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        P->batches[i].lane = l;
+        load[l] += work[i];
+    }
+    HIPCHK(P, hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+    for (int l = 1; l < nl; ++l) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        HIPCHK(P, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        P->lanes.push_back(s);
+        HIPCHK(P, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        P->join_ev.push_back(e);
     }
     return FDETD_OK;
 }
@@ -563,7 +614,7 @@ int autotune(fdetd_plan_t P, double &ms_spent)
                 for (int r = 0; r <= kReps && !rc; ++r) {  // one untimed launch, then kReps timed
                     if (r == 1 && (e = hipEventRecord(ev[0], P->stream)))
                         rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
-                    if (!rc) rc = launch_stage(P, b, A);
+                    if (!rc) rc = launch_stage(P, b, A, P->stream);
                 }
                 float ms = 0.f;
                 if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
@@ -753,6 +804,12 @@ void fdetd_destroy(fdetd_plan_t plan)
 {
     if (!plan) return;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    for (hipStream_t s : plan->lanes) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : plan->join_ev) (void)hipEventDestroy(e);
+    if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
@@ -858,6 +915,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     if (rc == FDETD_OK) rc = build_batches(P);
     double tune_ms = 0.0;
     if (rc == FDETD_OK) rc = autotune(P, tune_ms);
+    if (rc == FDETD_OK) rc = assign_lanes(P);
     if (rc != FDETD_OK) {
         g_last_error = P->err;
         fdetd_destroy(P);
@@ -876,6 +934,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
     P->info.autotune_ms = tune_ms;
+    P->info.streams = 1 + (int32_t)P->lanes.size();
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         fail(P, FDETD_E_HIP, "fdetd_plan: %s", hipGetErrorString(e));
@@ -963,13 +1022,16 @@ int step_body(fdetd_plan_t P, void *vctx)
     StepCtx &c = *(StepCtx *)vctx;
     const size_t eb = elem_bytes(P->precision);
     std::vector<const void *> js(P->probs.size());
-    for (int s = 0; s < c.n_steps; ++s) {
+    int rc = fork_lanes(P);
+    for (int s = 0; s < c.n_steps && !rc; ++s) {
         for (size_t p = 0; p < P->probs.size() && c.j; ++p)
             js[p] = (const char *)c.j[p] + (size_t)(c.stride * s) * 3 * P->probs[p].cells * eb;
-        int rc = enqueue_maxwell_step(P, c.psi, c.j ? js.data() : nullptr, s == c.n_steps - 1);
-        if (rc) return rc;
+        for (size_t b = 0; b < P->batches.size() && !rc; ++b)
+            rc = enqueue_maxwell_batch(P, P->batches[b], c.psi, c.j ? js.data() : nullptr, s == c.n_steps - 1,
+                                       lane_stream(P, P->batches[b]));
     }
-    return FDETD_OK;
+    const int rj = join_lanes(P);  // also after an error, so that a capture ends with every stream joined
+    return rc ? rc : rj;
 }
 
 int env_body(fdetd_plan_t P, void *vctx)
@@ -977,13 +1039,15 @@ int env_body(fdetd_plan_t P, void *vctx)
     EnvCtx &c = *(EnvCtx *)vctx;
     const size_t rb = elem_bytes(P->precision) / 2;
     std::vector<const void *> chis(P->probs.size());
-    for (int s = 0; s < c.n_steps; ++s) {
+    int rc = fork_lanes(P);
+    for (int s = 0; s < c.n_steps && !rc; ++s) {
         for (size_t p = 0; p < P->probs.size(); ++p)
             chis[p] = (const char *)c.chi[p] + (size_t)(c.stride * s) * P->probs[p].cells * rb;
-        int rc = enqueue_envelope_step(P, c.a, c.at, chis.data());
-        if (rc) return rc;
+        for (size_t b = 0; b < P->batches.size() && !rc; ++b)
+            rc = enqueue_envelope_batch(P, P->batches[b], c.a, c.at, chis.data(), lane_stream(P, P->batches[b]));
     }
-    return FDETD_OK;
+    const int rj = join_lanes(P);
+    return rc ? rc : rj;
 }
 }  // namespace
 

@@ -72,6 +72,7 @@ def test_envelope_batched_uneven(precision):
         at0.append(rng.uniform(-1, 1, (nr[p], nz[p])) + 1j * rng.uniform(-1, 1, (nr[p], nz[p])))
         chi.append(1e-3 * (1 + 0.05 * rng.uniform(-1, 1, (nr[p], nz[p]))))
     ga, gt, info = gpu_envelope(w, a0, at0, chi, 6, precision=precision, flags=1)
+    assert info["streams"] == 3  # three launch batches (orders 4, 8, 16) on three streams
     gga, ggt, _ = gpu_envelope(w, a0, at0, chi, 6, precision=precision, flags=3)
     oa, ot = oracle_envelope(w, a0, at0, chi, 6)
     tol = 1e-12 if precision == 0 else 2e-5

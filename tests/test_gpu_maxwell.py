@@ -227,3 +227,51 @@ def test_graph_recaptures_when_pointers_change():
         assert torch.equal(a, ea) and torch.equal(b, eb)
         g.close()
         e.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_concurrent_batches_equal_one_stream(precision):
+    """A plan with five launch batches (five stencil widths) runs them on four streams.  Batches hold
+    disjoint problems, so the fields equal, bitwise, those of the same plan on one stream.  A graph plan
+    (one branch per stream) replayed over several calls, with eager work of another plan and
+    synchronisation between the replays, matches the eager plan after every call."""
+    import torch
+    import paper_2605_12132_amd as F
+    from helpers import dev
+    ws = [small(0, 8, 8, nz=300, nr=70, steps=3, seed=11), small(2, 12, 8, nz=130, nr=19, steps=3, seed=12),
+          small(1, 32, 8, nz=517, nr=33, steps=3, seed=13), small(1, 4, 8, nz=257, nr=45, steps=3, seed=14),
+          small(0, 16, 8, nz=180, nr=64, steps=3, seed=15), small(3, 8, 8, nz=96, nr=30, steps=3, seed=16)]
+    rng = np.random.default_rng(77)
+    psi0 = [random_state(w, 0, rng) for w in ws]
+    J = [random_current(w, 0, 3, rng) for w in ws]
+    batch = I.Workload("mix5", 0, [w.nz[0] for w in ws], [w.nr[0] for w in ws], [w.m[0] for w in ws],
+                       [w.fd_order[0] for w in ws], 8, ws[0].dz, ws[0].dr, ws[0].dt, 3)
+    lanes, info = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1)
+    one, info1 = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1 | F.PLAN_ONE_STREAM)
+    log(f"five batches: {info['streams']} streams, one-stream plan {info1['streams']}")
+    assert info["streams"] == 4 and info1["streams"] == 1
+    for p in range(batch.n):
+        assert np.array_equal(lanes[p], one[p]), p
+    if precision == 0:
+        want = oracle_maxwell(batch, psi0, J, 3)
+        for p in range(batch.n):
+            assert rel_l2(lanes[p], want[p]) < TOL64, p
+    cd = torch.complex128 if precision == 0 else torch.complex64
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        jd = [dev(j, cd) for j in J]
+        g_psi = [dev(x, cd) for x in psi0]
+        e_psi = [dev(x, cd) for x in psi0]
+        g = F.Plan(batch.problems(), precision=precision, flags=F.PLAN_USE_GRAPH | 1)
+        e = F.Plan(batch.problems(), precision=precision, flags=1)
+        assert g.query()["streams"] == 4
+        for call in range(4):  # the same pointers each call: one capture, then replays
+            g.step(g_psi, [j[0] for j in jd], n_steps=1)
+            torch.cuda.synchronize()
+            e.step(e_psi, [j[0] for j in jd], n_steps=1)
+            torch.cuda.synchronize()
+            for p in range(batch.n):
+                assert torch.equal(g_psi[p], e_psi[p]), (call, p)
+        g.close()
+        e.close()

@@ -80,3 +80,41 @@ def test_plan_rejects_mixed_kinds_and_bad_flags():
         F.fdetd_plan([a], flags=F.PLAN_USE_GRAPH, stream=0)   # graphs need a real stream
     with pytest.raises(F.FdetdError):
         F.fdetd_plan([a], precision=7)
+
+
+def test_header_layout_matches_binding(tmp_path):
+    """The ctypes mirror of the C-ABI agrees with include/fdetd.h as a C compiler reads it: sizes and field
+    offsets of both structs, and the value of every constant the binding restates."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"fdetd_problem_desc": binding.ProblemDesc, "fdetd_plan_info": binding.PlanInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fdetd.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    consts = {"FDETD_OK": binding.FDETD_OK, "FDETD_E_ARG": binding.FDETD_E_ARG,
+              "FDETD_E_UNSTABLE": binding.FDETD_E_UNSTABLE, "FDETD_E_NOMEM": binding.FDETD_E_NOMEM,
+              "FDETD_E_HIP": binding.FDETD_E_HIP, "FDETD_FP64": binding.FP64, "FDETD_FP32C": binding.FP32C,
+              "FDETD_MAXWELL": binding.MAXWELL, "FDETD_ENVELOPE": binding.ENVELOPE,
+              "FDETD_PLAN_SKIP_STABILITY": binding.PLAN_SKIP_STABILITY, "FDETD_PLAN_USE_GRAPH": binding.PLAN_USE_GRAPH,
+              "FDETD_PLAN_PROFILE": binding.PLAN_PROFILE, "FDETD_PLAN_NO_AUTOTUNE": binding.PLAN_NO_AUTOTUNE,
+              "FDETD_PLAN_ONE_STREAM": binding.PLAN_ONE_STREAM}
+    for k in consts:
+        lines.append(f'printf("const {k} %lld\\n", (long long)({k}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for cname, ct in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert got[(cname, f)] == getattr(ct, f).offset, (cname, f)
+    for k, v in consts.items():
+        assert got[("const", k)] == v, k
