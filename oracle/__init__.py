@@ -85,6 +85,8 @@ def lib():
         L.oracle_step.argtypes = [P, vp, vp, C.c_int64, C.c_int]
         L.oracle_apply_Ha.argtypes = [P, vp, vp, vp, vp, vp]
         L.oracle_envelope_step.argtypes = [P, vp, vp, vp, C.c_int]
+        L.oracle_absorber_profile.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, vp]
+        L.oracle_envelope_step_absorbing.argtypes = [P, vp, vp, vp, vp, C.c_int]
         L.oracle_energy.argtypes = [P, vp, vp, vp]
         L.oracle_energy.restype = None
         L.oracle_envelope_energy.argtypes = [P, vp, vp, vp, vp]
@@ -218,6 +220,27 @@ def envelope_step(g: Grid, a, at, chi, n_steps: int = 1):
     assert chi.shape == (g.nr, g.nz)
     P = g.c()
     _chk(lib().oracle_envelope_step(C.byref(P), _ptr(a), _ptr(at), _ptr(chi), n_steps), "envelope_step")
+    return a, at
+
+
+def absorber_profile(g: Grid, lz: int, lr: int, sigma_max: float, power: float = 2.0):
+    """Layer functions sigma [nr][nz] of the scalar absorbing layer (polynomial grading: a reading, since the paper leaves the layer functions to a companion paper)."""
+    sigma = np.zeros((g.nr, g.nz))
+    P = g.c()
+    _chk(lib().oracle_absorber_profile(C.byref(P), lz, lr, sigma_max, power, _ptr(sigma)), "absorber_profile")
+    return sigma
+
+
+def envelope_step_absorbing(g: Grid, a, at, chi, sigma, n_steps: int = 1):
+    """n_steps of exp(-sigma dt/4) T_N(dt H_a(chi + sigma^2)) exp(-sigma dt/4) on (a, a_tilde)."""
+    a = _cplx(a, (g.nr, g.nz)).copy()
+    at = _cplx(at, (g.nr, g.nz)).copy()
+    chi = np.ascontiguousarray(chi, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    assert chi.shape == (g.nr, g.nz) and sigma.shape == (g.nr, g.nz)
+    P = g.c()
+    _chk(lib().oracle_envelope_step_absorbing(C.byref(P), _ptr(a), _ptr(at), _ptr(chi), _ptr(sigma), n_steps),
+         "envelope_step_absorbing")
     return a, at
 
 

@@ -594,6 +594,61 @@ int oracle_envelope_step(const oracle_problem *P, double complex *a, double comp
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Scalar absorbing layer (appendix on the scalar absorbing layer, applied to the envelope state as */
+/* section 4.2 allows): the damped wave equation with sigma = sigma_z(z) + sigma_rho(rho) is split   */
+/* symmetrically as exp(-sigma dt/4) exp(dt H) exp(-sigma dt/4), where H is the undamped operator     */
+/* with sigma^2 merged into the susceptibility (chi~ = chi + sigma^2).                               */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Layer functions (reading: the companion paper that defines them is not available): polynomial grading
+ * sigma_max * d^power with d = depth into the layer in cells / width, d = 1 on the outermost cell; layers
+ * of lz columns at both z ends and lr rows at the outer rho edge, none at the axis.  sigma is [nr][nz]. */
+int oracle_absorber_profile(const oracle_problem *P, int lz, int lr, double sigma_max, double power,
+                            double *sigma)
+{
+    if (check_problem(P) || lz < 0 || lr < 0 || 2 * lz > P->nz || lr > P->nr || !(sigma_max >= 0.0)) return -1;
+    for (int k = 0; k < P->nr; ++k) {
+        double sr = 0.0;
+        if (lr > 0 && k >= P->nr - lr) sr = sigma_max * pow((double)(k - (P->nr - 1 - lr)) / lr, power);
+        for (int i = 0; i < P->nz; ++i) {
+            double sz = 0.0;
+            if (lz > 0 && i < lz) sz = sigma_max * pow((double)(lz - i) / lz, power);
+            if (lz > 0 && i >= P->nz - lz) sz = sigma_max * pow((double)(i - (P->nz - 1 - lz)) / lz, power);
+            sigma[IDX(P, k, i)] = sz + sr;
+        }
+    }
+    return 0;
+}
+
+/* n_steps of psi_a' = exp(-sigma dt/4) T_N(dt H_a(chi + sigma^2)) exp(-sigma dt/4) psi_a. */
+int oracle_envelope_step_absorbing(const oracle_problem *P, double complex *a, double complex *at,
+                                   const double *chi, const double *sigma, int n_steps)
+{
+    if (check_problem(P) || n_steps < 0) return -1;
+    const size_t n = (size_t)P->nr * P->nz;
+    double *chit = malloc(n * sizeof(double)), *damp = malloc(n * sizeof(double));
+    for (size_t q = 0; q < n; ++q) {
+        chit[q] = chi[q] + sigma[q] * sigma[q];
+        damp[q] = exp(-sigma[q] * P->dt / 4.0);
+    }
+    int rc = 0;
+    for (int step = 0; step < n_steps && !rc; ++step) {
+        for (size_t q = 0; q < n; ++q) {
+            a[q] *= damp[q];
+            at[q] *= damp[q];
+        }
+        rc = oracle_envelope_step(P, a, at, chit, 1);
+        for (size_t q = 0; q < n; ++q) {
+            a[q] *= damp[q];
+            at[q] *= damp[q];
+        }
+    }
+    free(chit);
+    free(damp);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Diagnostics (section 5.1): energy integral of |E|^2 + |B|^2 over the volume and its z-centroid.  */
 /* The theta integral of a complex mode gives 2 pi |F|^2 for m = 0 and pi |F|^2 for m >= 1.          */
 /* ------------------------------------------------------------------------------------------ */
@@ -660,7 +715,8 @@ static double bspline3(double x)
 static double h_weight(int k) { return k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0); }
 
 /* Radial shape of section 3.5 of a sample at rho_p on primary row k >= 0 (rho_k = (k + 1/2) dr), with
- * the part at rho < 0 folded back onto row k with the component's parity p (reading A21):
+ * the part at rho < 0 folded back onto row k with the component's parity p (a reading: the mirror rule of
+ * section 3.5 applied to the shape):
  *   N^-1 rho_k^(eps - 1) (w_k + p w_(-1-k)),   w_j = S3((rho_j - rho_p) / dr),
  *   N = sum_(k >= 0) h_k rho_k^eps (w_k + w_(-1-k)) dr   (the sample's shape on the folded grid). */
 static double radial_norm(const oracle_problem *P, double rho_p, double eps)
@@ -681,7 +737,8 @@ static double radial_shape(const oracle_problem *P, double rho_p, double eps, do
 }
 
 /* Angular shape of section 3.2, deposition form (l = 1), as the complex mode coefficient of the
- * convention F = Re sum_m F_m e^(i m theta) (reading A22): 1/(2 pi) for m = 0, e^(-i m theta_p)/pi else. */
+ * convention F = Re sum_m F_m e^(i m theta) (a reading of the normalisation): 1/(2 pi) for m = 0,
+ * e^(-i m theta_p)/pi else. */
 static cplx angular_shape(int m, double theta)
 {
     if (m == 0) return 1.0 / (2.0 * M_PI);
@@ -724,7 +781,7 @@ int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, d
 /* Longitudinal current of section 3.6 (samples moving with vz, no transverse motion), added into plane
  * 2 of j (3 planes J_rho, J_theta, J_z; J_z on the z-staggered points z_i - dz/2).  The integrated shape
  * F(i) = sum_(i' < i) S3(i' - z/dz) of the positions z -+ vz dt/2 gives, from the discrete continuity
- * equation (reading A20),  J_z(i - 1/2) = q w (F_-(i) - F_+(i)) / dt * radial shape * angular shape. */
+ * equation (a reading of section 3.6),  J_z(i - 1/2) = q w (F_-(i) - F_+(i)) / dt * radial shape * angular shape. */
 int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, double vz, double eps,
                       double complex *j)
 {

@@ -70,6 +70,13 @@ int oracle_apply_Ha(const oracle_problem *P, const double complex *a, const doub
                     const double *chi, double complex *out_a, double complex *out_at);
 int oracle_envelope_step(const oracle_problem *P, double complex *a, double complex *at,
                          const double *chi, int n_steps);
+/* Scalar absorbing layer (appendix on the scalar absorbing layer): layer functions sigma [nr][nz]
+ * (polynomial grading over lz columns at both z ends and lr rows at the outer rho edge) and the split
+ * step exp(-sigma dt/4) T_N(dt H_a(chi + sigma^2)) exp(-sigma dt/4). */
+int oracle_absorber_profile(const oracle_problem *P, int lz, int lr, double sigma_max, double power,
+                            double *sigma);
+int oracle_envelope_step_absorbing(const oracle_problem *P, double complex *a, double complex *at,
+                                   const double *chi, const double *sigma, int n_steps);
 
 /* --- diagnostics (section 5.1) --- */
 /* Field energy sum_fields sum_cells w_m r dr dz |F|^2 and its z-centroid (Maxwell state). */
@@ -78,7 +85,7 @@ void oracle_energy(const oracle_problem *P, const double complex *psi, double *e
 void oracle_envelope_energy(const oracle_problem *P, const double complex *a,
                             const double complex *at, double *energy, double *zc);
 
-/* Deposition of point samples (z, x, y, q w per sample; sections 3.2, 3.5, 3.6, readings A20-A22):
+/* Deposition of point samples (z, x, y, q w per sample; sections 3.2, 3.5, 3.6, with the readings stated in fdetd_oracle.c):
  * the charge density of mode m of the samples shifted by dz_shift along z, and the longitudinal current
  * of samples moving with vz (plane 2 of the 3-plane j).  Both add into their output.  Samples whose z
  * shape reaches past either z end of the grid are not deposited. */

@@ -1,4 +1,4 @@
-"""Pins of the oracle's sample deposition (sections 3.2, 3.5, 3.6; readings A20-A22):
+"""Pins of the oracle's sample deposition (sections 3.2, 3.5, 3.6):
 
 - the current and the shifted charge densities satisfy the discrete continuity equation exactly, which
   fixes the sign and scale of the integrated z shape;
