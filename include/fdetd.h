@@ -164,6 +164,24 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
 FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
                                void *const *j_half);
 
+/* Absorbing layers of envelope problems (appendix on the scalar absorbing layer, which the envelope
+ * solver of section 4.2 may use): from the next envelope_step on, every step of the problem is
+ *     psi_a(t + dt) = exp(-sigma dt/4) T_N(dt H_a(chi~)) exp(-sigma dt/4) psi_a(t),   chi~ = chi + sigma^2,
+ * with sigma(z, rho) = sigma_z(z) + sigma_rho(rho) graded as sigma_max d^power: d = (depth of the cell
+ * into the layer, in cells) / width, 1 on the outermost cell.  Layers of lz columns at both z ends and lr
+ * rows at the outer rho edge; none at the axis.  (The paper defines the layer functions in a companion
+ * paper; this grading is the usual PML one.)
+ *   problem    index of the problem, or -1 for every problem of the plan.
+ *   lz, lr     layer widths in cells: 0 <= 2 lz <= nz, 0 <= lr <= nr (0: no layer on that side).
+ *   sigma_max  >= 0, in units of 1/time (0, or lz = lr = 0: remove the layers).
+ *   power      >= 0.
+ * Error FDETD_E_ARG on an envelope-less plan or bad values; FDETD_E_UNSTABLE when the plan estimated the
+ * spectral radius rho_hat and dt (rho_hat + sigma_max per overlapping layer) * 1.02 >= X_N.  Synchronises
+ * the plan's stream, then writes the layer tables; a captured graph is captured anew on the next call.
+ * FP32C: the damping scales each (value, compensation word) pair in FP64. */
+FDETD_API int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max,
+                                double power);
+
 /* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
 FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);
 

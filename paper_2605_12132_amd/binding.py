@@ -21,7 +21,8 @@ MAXWELL, ENVELOPE = 0, 1
 PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_STREAM = 1, 2, 4, 8, 16
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "fdetd_deposit_jz", "fdetd_query", "fdetd_export_state",
+EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_query",
+           "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
 
@@ -79,6 +80,7 @@ def _load():
     L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
+    L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
     L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.fdetd_import_state.argtypes = [vp, vp, C.c_size_t]
@@ -134,6 +136,10 @@ def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_planes: int = 0, n_s
 def fdetd_deposit_jz(plan, samples_ptr, n: int, vz: float, eps: float, j_ptrs):
     rc = lib.fdetd_deposit_jz(plan, samples_ptr, n, vz, eps, _ptrs(j_ptrs))
     _check(rc, plan)
+
+
+def envelope_absorber(plan, problem: int, lz: int, lr: int, sigma_max: float, power: float = 2.0):
+    _check(lib.envelope_absorber(plan, problem, lz, lr, sigma_max, power), plan)
 
 
 def fdetd_query(plan) -> dict:
@@ -247,6 +253,11 @@ class Plan:
                 raise ValueError("chi has fewer steps than n_steps")
             stride = 1
         envelope_step(self._h, ap, tp, cp, stride, n_steps)
+
+    def absorber(self, lz: int, lr: int, sigma_max: float, power: float = 2.0, problem: int = -1):
+        """Absorbing layers (lz columns at both z ends, lr rows at the outer rho edge, sigma graded as
+        sigma_max d^power) for envelope problem `problem`, or all problems (-1)."""
+        envelope_absorber(self._h, problem, lz, lr, sigma_max, power)
 
     def query(self) -> dict:
         return fdetd_query(self._h)

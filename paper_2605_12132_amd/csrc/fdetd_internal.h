@@ -93,6 +93,8 @@ struct ProbDesc {
     const void *jbar;                        // staggered J_rho plane
     float *lo;                               // FP32C compensation words
     const double *rinv_p, *rinv_s, *m2rinv2;
+    const double *sz, *sr;                   // envelope absorbing layer: sigma_z per column, sigma_rho per
+                                             // row (all zero without a layer); null for Maxwell problems
     double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
     double sh[kMaxND];                                   // half-shift weights s_j (current staging)
     double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
@@ -148,6 +150,17 @@ struct DepositArgs {
     void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2)
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
+// Damping exp(-sigma dt/4) of an envelope state (a, a~) on the cells of its absorbing layers: lz columns
+// at each z end and lr rows at the outer rho edge.  FP32C: the (hi, lo) pair of each value is scaled in
+// FP64 and split again.
+struct DampArgs {
+    void *a, *at;            // the state planes
+    float *lo;               // FP32C compensation words (planes a, a~ of float2), null for FP64
+    const double *sz, *sr;   // sigma per column and per row
+    int nz, nr, lz, lr;
+    double qdt;              // dt / 4
+};
+hipError_t launch_absorb_damp(int prec, const DampArgs &a, hipStream_t s);
 // Per-block partial sums of |x|^2 over n complex values (double2 or float2); nblocks written to partial.
 hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s);
 hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s);

@@ -489,6 +489,65 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 
 }  // namespace
 
+// --------------------------------------------------------------------------------------------------
+// Absorbing-layer damping (appendix on the scalar absorbing layer): both factors exp(-sigma dt/4) of the
+// split step, applied to the cells where sigma = sigma_z + sigma_rho can be non-zero.  Thread t < lr nz
+// takes row nr - lr + t / nz (the rho layer, every column); the others take the z layers of the rows
+// above it, 2 lz cells per row.
+// --------------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_absorb_damp(DampArgs A)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nrho = (long long)A.lr * A.nz, nzl = (long long)(A.nr - A.lr) * 2 * A.lz;
+    if (t >= nrho + nzl) return;
+    int k, i;
+    if (t < nrho) {
+        k = A.nr - A.lr + (int)(t / A.nz);
+        i = (int)(t % A.nz);
+    } else {
+        const long long u = t - nrho;
+        k = (int)(u / (2 * A.lz));
+        const int c = (int)(u % (2 * A.lz));
+        i = c < A.lz ? c : A.nz - 2 * A.lz + c;
+    }
+    const size_t q = (size_t)k * A.nz + i;
+    const double d = exp(-(A.sz[i] + A.sr[k]) * A.qdt);
+    if constexpr (std::is_same<R, double>::value) {
+        double2 *a = (double2 *)A.a, *at = (double2 *)A.at;
+        const double2 x = a[q], y = at[q];
+        a[q] = double2{d * x.x, d * x.y};
+        at[q] = double2{d * y.x, d * y.y};
+    } else {
+        float2 *a = (float2 *)A.a, *at = (float2 *)A.at;
+        float2 *la = (float2 *)A.lo, *lt = la + (size_t)A.nz * A.nr;
+        auto scale = [d](float &hi, float &lo) {
+            const double x = d * ((double)hi + (double)lo);
+            hi = (float)x;
+            lo = (float)(x - (double)hi);
+        };
+        float2 x = a[q], y = at[q], lx = la[q], ly = lt[q];
+        scale(x.x, lx.x);
+        scale(x.y, lx.y);
+        scale(y.x, ly.x);
+        scale(y.y, ly.y);
+        a[q] = x;
+        at[q] = y;
+        la[q] = lx;
+        lt[q] = ly;
+    }
+}
+
+hipError_t launch_absorb_damp(int prec, const DampArgs &a, hipStream_t s)
+{
+    const long long n = (long long)a.lr * a.nz + (long long)(a.nr - a.lr) * 2 * a.lz;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_absorb_damp<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_absorb_damp<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;

@@ -803,6 +803,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
     const AR k2 = (AR)(2.0 * D.k0);
     const int own = L.lane + ND * S;
     const int cc = L.col ? L.i : nz - 1;
+    const AR szi = (AR)gld<double>(D.sz, (unsigned)cc);  // absorbing layer: sigma_z of this column
     const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
         E an, tin;
@@ -850,7 +851,9 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
             lr = fmav((AR)D.br[j], rp + rm, lr);
             d1r = fmav((AR)D.drc[j - 1], rp - rm, d1r);
         }
-        const AR pot = (AR)cld(D.m2rinv2, k) + (AR)cu.chi;
+        // m^2 / rho^2 + chi~ with chi~ = chi + sigma^2 (absorbing layer; sigma = 0 outside it)
+        const AR sig = szi + (AR)cld(D.sr, k);
+        const AR pot = fma(sig, sig, (AR)cld(D.m2rinv2, k) + (AR)cu.chi);
         const L_ rot = times_i(k2, d1z + tin);
         __syncthreads();
         if (L.col && live) {

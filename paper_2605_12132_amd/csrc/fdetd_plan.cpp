@@ -39,6 +39,8 @@ struct Prob {
     void *jbar = nullptr;       // staggered J_rho plane
     float *lo = nullptr;        // FP32C compensation words (6 or 2 planes of float2)
     double *rinv_p = nullptr, *rinv_s = nullptr, *m2rinv2 = nullptr;
+    double *sz = nullptr, *sr = nullptr;  // envelope absorbing layer: sigma per column and per row
+    int lz = 0, lr = 0;                   // its widths (0, 0: no layer)
     double a[kMaxND], s[kMaxND], d1[kMaxND], d2[kMaxND + 1], c[kMaxND];
     const void *last_state = nullptr;   // psi (or a) of the previous call, for the FP32C reset rule
     double rho_hat = 0.0;
@@ -124,6 +126,8 @@ void free_prob(Prob &q)
     if (q.rinv_p) (void)hipFree(q.rinv_p);
     if (q.rinv_s) (void)hipFree(q.rinv_s);
     if (q.m2rinv2) (void)hipFree(q.m2rinv2);
+    if (q.sz) (void)hipFree(q.sz);
+    if (q.sr) (void)hipFree(q.sr);
     q = Prob{};
 }
 
@@ -259,6 +263,29 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     return FDETD_OK;
 }
 
+// exp(-sigma dt/4) on the absorbing layers of the problems of batch b that have one.
+int damp_layers(fdetd_plan_t P, const Batch &b, void *const *a, void *const *at, hipStream_t s)
+{
+    for (int t = 0; t < b.count; ++t) {
+        const int p = b.members[t];
+        const Prob &q = P->probs[p];
+        if (q.lz == 0 && q.lr == 0) continue;
+        DampArgs X{};
+        X.a = a[p];
+        X.at = at[p];
+        X.lo = q.lo;
+        X.sz = q.sz;
+        X.sr = q.sr;
+        X.nz = q.d.nz;
+        X.nr = q.d.nr;
+        X.lz = q.lz;
+        X.lr = q.lr;
+        X.qdt = q.d.dt / 4.0;
+        HIPCHK(P, launch_absorb_damp(prec_code(P->precision), X, s));
+    }
+    return FDETD_OK;
+}
+
 // One envelope step of the problems of batch b on stream s.
 int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void *const *at, const void *const *chi,
                            hipStream_t s)
@@ -278,14 +305,15 @@ int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void 
         A.chi[t] = chi[b.members[t]];
         cells += P->probs[b.members[t]].cells;
     }
+    int rc = damp_layers(P, b, a, at, s);  // first factor exp(-sigma dt/4) of the split step
+    if (rc) return rc;
     for (int n = b.N - 1; n >= 0; --n) {
         A.n = n;
         A.coef = b.dt / (n + 1);
         // algorithmic bytes: vin (2c) + psi (2c; the same data in the first stage) + chi + vout (2c)
         const double cvals = (n == b.N - 1 ? 4.0 : 6.0) + 0.5;
         const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 2 * cells * 8 : 0.0);
-        int rc = profile_begin(P, bytes);
-        if (rc) return rc;
+        if ((rc = profile_begin(P, bytes))) return rc;
         if ((rc = launch_stage(P, b, A, s))) return rc;
         if ((rc = profile_end(P))) return rc;
     }
@@ -298,7 +326,7 @@ int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void 
             HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at[p], plane_b, s));
         }
     }
-    return FDETD_OK;
+    return damp_layers(P, b, a, at, s);  // second factor
 }
 
 // Launch batches hold disjoint problems, so a call can run them on several streams: the side streams
@@ -445,6 +473,8 @@ int build_batches(fdetd_plan_t P)
             D.rinv_p = q.rinv_p;
             D.rinv_s = q.rinv_s;
             D.m2rinv2 = q.m2rinv2;
+            D.sz = q.sz;
+            D.sr = q.sr;
             for (int k = 0; k < q.nd; ++k) {
                 D.az[k] = q.a[k] / q.d.dz;
                 D.ar[k] = q.a[k] / q.d.dr;
@@ -864,13 +894,16 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             (precision == FDETD_FP32C && (e = hipMalloc((void **)&q.lo, np * q.cells * sizeof(float) * 2))) ||
             (e = hipMalloc((void **)&q.rinv_p, q.d.nr * sizeof(double))) ||
             (e = hipMalloc((void **)&q.rinv_s, q.d.nr * sizeof(double))) ||
-            (e = hipMalloc((void **)&q.m2rinv2, q.d.nr * sizeof(double)))) {
+            (e = hipMalloc((void **)&q.m2rinv2, q.d.nr * sizeof(double))) ||
+            (P->kind == FDETD_ENVELOPE && ((e = hipMalloc((void **)&q.sz, q.d.nz * sizeof(double))) ||
+                                           (e = hipMalloc((void **)&q.sr, q.d.nr * sizeof(double)))))) {
             rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
                       hipGetErrorString(e));
             break;
         }
         scratch += 2 * vec_b + (P->kind == FDETD_MAXWELL ? q.cells * eb : 0) +
-                   (precision == FDETD_FP32C ? np * q.cells * 8 : 0) + 3 * q.d.nr * 8;
+                   (precision == FDETD_FP32C ? np * q.cells * 8 : 0) + 3 * q.d.nr * 8 +
+                   (P->kind == FDETD_ENVELOPE ? (q.d.nz + q.d.nr) * 8 : 0);
         std::vector<double> hr(q.d.nr), hs(q.d.nr), hm(q.d.nr);
         for (int k = 0; k < q.d.nr; ++k) {
             const double rho_k = (k + 0.5) * q.d.dr;
@@ -881,7 +914,9 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if ((e = hipMemcpy(q.rinv_p, hr.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
             (e = hipMemcpy(q.rinv_s, hs.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
             (e = hipMemcpy(q.m2rinv2, hm.data(), q.d.nr * 8, hipMemcpyHostToDevice)) ||
-            (precision == FDETD_FP32C && (e = hipMemset(q.lo, 0, np * q.cells * 8)))) {
+            (precision == FDETD_FP32C && (e = hipMemset(q.lo, 0, np * q.cells * 8))) ||
+            (q.sz && (e = hipMemset(q.sz, 0, q.d.nz * sizeof(double)))) ||
+            (q.sr && (e = hipMemset(q.sr, 0, q.d.nr * sizeof(double))))) {
             rc = fail(P, FDETD_E_HIP, "fdetd_plan: problem %d: %s", p, hipGetErrorString(e));
             break;
         }
@@ -974,6 +1009,61 @@ int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double
         A.eps = eps;
         for (int t = 0; t < b.count; ++t) A.j[t] = j_half[b.members[t]];
         HIPCHK(plan, launch_deposit_jz(prec_code(plan->precision), A, plan->stream));
+    }
+    return FDETD_OK;
+}
+
+int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max, double power)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_absorber: NULL plan");
+    if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_absorber: plan is not an envelope plan");
+    const int np = (int)plan->probs.size();
+    if (problem < -1 || problem >= np || lz < 0 || lr < 0 || !(sigma_max >= 0.0) || !std::isfinite(sigma_max) ||
+        !(power >= 0.0) || !std::isfinite(power))
+        return fail(plan, FDETD_E_ARG, "envelope_absorber: bad arguments");
+    const int p0 = problem < 0 ? 0 : problem, p1 = problem < 0 ? np : problem + 1;
+    const bool on = sigma_max > 0.0 && (lz > 0 || lr > 0);
+    for (int p = p0; p < p1; ++p) {
+        const Prob &q = plan->probs[p];
+        if (2 * lz > q.d.nz || lr > q.d.nr)
+            return fail(plan, FDETD_E_ARG, "envelope_absorber: problem %d: layers wider than the grid", p);
+        // the central exponential carries chi + sigma^2: its spectral radius grows by at most sigma_max per
+        // layer that can overlap (z and rho in the corners)
+        const double smax = sigma_max * ((lz > 0) + (lr > 0));
+        if (on && q.rho_hat > 0.0 && q.d.dt * (q.rho_hat + smax) * 1.02 >= taylor_stability_bound(q.d.taylor_order))
+            return fail(plan, FDETD_E_UNSTABLE, "envelope_absorber: problem %d: dt (rho + sigma_max) = %.4f exceeds the "
+                        "Taylor order-%d bound %.4f / 1.02", p, q.d.dt * (q.rho_hat + smax), q.d.taylor_order,
+                        taylor_stability_bound(q.d.taylor_order));
+    }
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    const size_t eb = elem_bytes(plan->precision);
+    for (int p = p0; p < p1; ++p) {
+        Prob &q = plan->probs[p];
+        const int nz = q.d.nz, nr = q.d.nr;
+        // layer functions: sigma_max d^power, d = depth into the layer / width, 1 on the outermost cell
+        std::vector<double> hz(nz, 0.0), hr(nr, 0.0);
+        if (on) {
+            for (int i = 0; i < lz; ++i) {
+                const double v = sigma_max * std::pow((double)(lz - i) / lz, power);
+                hz[i] = v;
+                hz[nz - 1 - i] = v;
+            }
+            for (int k = 0; k < lr; ++k) hr[nr - 1 - k] = sigma_max * std::pow((double)(lr - k) / lr, power);
+        }
+        HIPCHK(plan, hipMemcpy(q.sz, hz.data(), nz * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(plan, hipMemcpy(q.sr, hr.data(), nr * sizeof(double), hipMemcpyHostToDevice));
+        // bytes of the two damping passes over the layer cells: (a, a~) read and written, FP32C also lo
+        const int64_t old_cells = (int64_t)q.lr * nz + (int64_t)(nr - q.lr) * 2 * q.lz;
+        q.lz = on ? lz : 0;
+        q.lr = on ? lr : 0;
+        const int64_t cells = (int64_t)q.lr * nz + (int64_t)(nr - q.lr) * 2 * q.lz;
+        const int64_t per_cell = 2 * 2 * 2 * ((int64_t)eb + (plan->precision == FDETD_FP32C ? 8 : 0));
+        plan->info.bytes_per_step += (cells - old_cells) * per_cell;
+    }
+    if (plan->gexec) {  // the next call captures anew, with or without the damping launches
+        (void)hipGraphExecDestroy(plan->gexec);
+        plan->gexec = nullptr;
+        plan->gkey.clear();
     }
     return FDETD_OK;
 }

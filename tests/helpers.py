@@ -69,7 +69,9 @@ class _null:
         return False
 
 
-def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0):
+def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0, absorbers=(), calls=1):
+    """absorbers: (problem, lz, lr, sigma_max, power) layers set on the plan before stepping; `calls` splits
+    the steps over that many envelope_step calls."""
     import torch
     import paper_2605_12132_amd as F
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
@@ -83,7 +85,11 @@ def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0):
     ctx = torch.cuda.stream(stream) if stream is not None else _null()
     with ctx:
         plan = F.Plan(w.problems(), precision=precision, flags=flags)
-        plan.envelope_step(a, at, ch, n_steps=steps)
+        for p, lz, lr, smax, power in absorbers:
+            plan.absorber(lz, lr, smax, power, problem=p)
+        per = steps // calls
+        for c in range(calls):
+            plan.envelope_step(a, at, ch, n_steps=per if c < calls - 1 else steps - per * (calls - 1))
         torch.cuda.synchronize()
         info = plan.query()
         plan.close()
@@ -91,8 +97,17 @@ def gpu_envelope(w, a0, at0, chi, steps=1, precision=0, flags=0):
             info)
 
 
-def oracle_envelope(w, a0, at0, chi, steps=1):
-    out = [oracle.envelope_step(grid_of(w, p), a0[p], at0[p], chi[p], steps) for p in range(w.n)]
+def oracle_envelope(w, a0, at0, chi, steps=1, absorbers=()):
+    """absorbers as for gpu_envelope: those problems take the oracle's absorbing-layer step."""
+    lay = {p: (lz, lr, smax, power) for p, lz, lr, smax, power in absorbers}
+    out = []
+    for p in range(w.n):
+        g = grid_of(w, p)
+        if p in lay:
+            sigma = oracle.absorber_profile(g, *lay[p])
+            out.append(oracle.envelope_step_absorbing(g, a0[p], at0[p], chi[p], sigma, steps))
+        else:
+            out.append(oracle.envelope_step(g, a0[p], at0[p], chi[p], steps))
     return [o[0] for o in out], [o[1] for o in out]
 
 
