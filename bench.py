@@ -28,10 +28,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "field cell-updates/s (cells×modes×steps/s), FP64 vs FP32-comp at fixed error"
 # HBM traffic of the stage kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this benchmark, with the
-# hash of the kernel sources it was taken on; reported only while the sources still match.
+# hash of the sources the kernel is compiled from and the segment length of the launches counted;
+# reported only while both still match (the kernel code, and the tiling the timed plan runs).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_maxwell_stage_current_driven_2048x256_o16_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_12132_amd", "csrc", f)
-                  for f in ("fdetd_march.hip", "fdetd_tiles.h", "fdetd_internal.h", "fdetd_plan.cpp")]
+                  for f in ("fdetd_march.hip", "fdetd_tiles.h", "fdetd_internal.h")]
 
 
 def log(*a):
@@ -153,7 +154,8 @@ def profile_pass(w, precision, steps, J, seg_rows):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c"), kernel="k_maxwell_stage",
+                traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c", seg_rows),
+                kernel="k_maxwell_stage",
                 launches=n, avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch))
 
 
@@ -166,9 +168,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision_tag):
+def measured_traffic(precision_tag, seg_rows):
     """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration) from
-    the committed PMC summary, or None when it is missing or was taken on other kernel sources."""
+    the committed PMC summary, or None when it is missing, was taken on other kernel sources or at
+    another segment length than seg_rows."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -176,6 +179,8 @@ def measured_traffic(precision_tag):
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_") and ":" in line)
     if fields.get("traffic_source_hash", "").strip() != kernel_source_hash():
+        return None
+    if fields.get(f"traffic_seg_rows_{precision_tag}", "").strip() != str(seg_rows):
         return None
     v = fields.get(f"traffic_bytes_per_launch_{precision_tag}")
     return int(float(v)) if v else None
@@ -291,10 +296,12 @@ def batched_pass(steps, warmup):
                 fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
 
 
-def envelope_pass(steps):
+def envelope_pass(steps, layer=32):
     """The envelope-in-plasma workload (4096 x 512, order 8, Taylor 4, dt = dz/2, static chi): FP64 and
     FP32C plans, graph replay of `steps` steps.  Its working set (about 220 MB in FP64) mostly fits the
-    256 MB Infinity Cache, so the rate is reported without an HBM fraction."""
+    256 MB Infinity Cache, so the rate is reported without an HBM fraction.  Each precision is also run
+    with absorbing layers (`layer` cells at both z ends and at the outer rho edge, sigma_max half the
+    largest the plan's stability bound admits, quadratic grading)."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -303,8 +310,8 @@ def envelope_pass(steps):
     chi = I.envelope_chi(w)
     cells = w.cells()
     out, res = {}, {}
-    for tag, prec, cd, rd in (("fp64", F.FP64, torch.complex128, torch.float64),
-                              ("fp32c", F.FP32C, torch.complex64, torch.float32)):
+
+    def run(prec, cd, rd, absorbing):
         stream = torch.cuda.Stream()
         stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
@@ -312,6 +319,11 @@ def envelope_pass(steps):
             at = torch.from_numpy(at0).to(device="cuda", dtype=cd)
             ch = torch.from_numpy(chi).to(device="cuda", dtype=rd)
             plan = F.Plan(w.problems(), precision=prec, flags=F.PLAN_USE_GRAPH)
+            smax = 0.0
+            if absorbing:
+                rho = plan.query()["dt_rho_max"] / w.dt
+                smax = 0.5 * (F.fdetd_taylor_stability_bound(w.taylor_order) / (1.02 * w.dt) - rho) / 2
+                plan.absorber(layer, layer, smax, 2.0)
             plan.envelope_step([a], [at], [ch], n_steps=steps)      # capture + first replay (untimed)
             a.copy_(torch.from_numpy(a0).to(device="cuda", dtype=cd))
             at.copy_(torch.from_numpy(at0).to(device="cuda", dtype=cd))
@@ -323,9 +335,18 @@ def envelope_pass(steps):
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1)
             plan.close()
+        return ms, smax, a, at
+
+    for tag, prec, cd, rd in (("fp64", F.FP64, torch.complex128, torch.float64),
+                              ("fp32c", F.FP32C, torch.complex64, torch.float32)):
+        ms, _, a, at = run(prec, cd, rd, False)
         out[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps)
         res[tag] = (a.cpu().numpy().astype(np.complex128), at.cpu().numpy().astype(np.complex128))
         log(f"envelope {tag}: {ms / steps:.4f} ms/step, {out[tag]['value']:.4g} cell-updates/s")
+        ms, smax, _, _ = run(prec, cd, rd, True)
+        out[tag]["absorbing"] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, lz=layer, lr=layer,
+                                     sigma_max=round(smax, 4))
+        log(f"envelope {tag} with absorbing layers: {ms / steps:.4f} ms/step")
     x64 = np.concatenate([res["fp64"][0].ravel(), res["fp64"][1].ravel()])
     x32 = np.concatenate([res["fp32c"][0].ravel(), res["fp32c"][1].ravel()])
     return dict(workload=w.name, cells=cells, steps=steps, graph=True, cache_resident=True,
