@@ -164,6 +164,19 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
 FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
                                void *const *j_half);
 
+/* Deposit the charge density of n point samples shifted by dz_shift along z into one plane per problem
+ * of a Maxwell plan, adding to what is there (sections 3.2, 3.5):
+ *   rho(z_i, rho_k) += q w S3(i - (z + dz_shift) / dz) / dz * R_k * A_m
+ * with the cubic spline S3 and R_k, A_m as for fdetd_deposit_jz.  With dz_shift = -+ vz dt / 2 the two
+ * densities and the current of fdetd_deposit_jz satisfy the discrete continuity equation
+ * (rho_+(i) - rho_-(i)) / dt + (J_z(i + 1/2) - J_z(i - 1/2)) / dz = 0.  A sample whose shape reaches past
+ * a z end of a grid is not deposited into it.
+ *   samples   as for fdetd_deposit_jz; eps in [0, 1].
+ *   rho       n_probs device pointers to one complex [nr][nz] plane each, in the plan's precision.
+ * Enqueue only; atomic adds as for fdetd_deposit_jz. */
+FDETD_API int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, double dz_shift, double eps,
+                                void *const *rho);
+
 /* Absorbing layers of envelope problems (appendix on the scalar absorbing layer, which the envelope
  * solver of section 4.2 may use): from the next envelope_step on, every step of the problem is
  *     psi_a(t + dt) = exp(-sigma dt/4) T_N(dt H_a(chi~)) exp(-sigma dt/4) psi_a(t),   chi~ = chi + sigma^2,

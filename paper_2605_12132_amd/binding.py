@@ -21,7 +21,8 @@ MAXWELL, ENVELOPE = 0, 1
 PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_STREAM = 1, 2, 4, 8, 16
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_query",
+EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_deposit_rho",
+           "fdetd_query",
            "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
@@ -80,6 +81,7 @@ def _load():
     L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
+    L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
     L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -136,6 +138,10 @@ def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_planes: int = 0, n_s
 def fdetd_deposit_jz(plan, samples_ptr, n: int, vz: float, eps: float, j_ptrs):
     rc = lib.fdetd_deposit_jz(plan, samples_ptr, n, vz, eps, _ptrs(j_ptrs))
     _check(rc, plan)
+
+
+def fdetd_deposit_rho(plan, samples_ptr, n: int, dz_shift: float, eps: float, rho_ptrs):
+    _check(lib.fdetd_deposit_rho(plan, samples_ptr, n, dz_shift, eps, _ptrs(rho_ptrs)), plan)
 
 
 def envelope_absorber(plan, problem: int, lz: int, lr: int, sigma_max: float, power: float = 2.0):
@@ -236,6 +242,17 @@ class Plan:
         self._nchk(j_half, "j_half")
         jp = [self._chk(x, (3, p.nr, p.nz), self._cdtype(), "j_half") for x, p in zip(j_half, self.problems)]
         fdetd_deposit_jz(self._h, samples.data_ptr(), samples.shape[0], vz, eps, jp)
+
+    def deposit_rho(self, samples, rho, dz_shift: float = 0.0, eps: float = 0.5):
+        """Add the charge density of point samples (float64 [n, 4] cuda tensor of z, x, y, q w) shifted by
+        dz_shift along z into one plane per problem (list of [nr, nz] tensors of the plan's precision)."""
+        import torch
+        if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 4
+                and samples.is_contiguous()):
+            raise ValueError("samples: contiguous float64 cuda tensor [n, 4]")
+        self._nchk(rho, "rho")
+        rp = [self._chk(x, (p.nr, p.nz), self._cdtype(), "rho") for x, p in zip(rho, self.problems)]
+        fdetd_deposit_rho(self._h, samples.data_ptr(), samples.shape[0], dz_shift, eps, rp)
 
     def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):
         cd, rd = self._cdtype(), self._rdtype()

@@ -147,9 +147,11 @@ struct DepositArgs {
     int64_t n;              // samples
     const double *samples;  // n x 4: z, x, y, q w
     double vz, eps;
-    void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2)
+    double shift;           // charge density: shift of the sample positions along z
+    void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2), or charge density (1 plane)
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
+hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
 // Damping exp(-sigma dt/4) of an envelope state (a, a~) on the cells of its absorbing layers: lz columns
 // at each z end and lr rows at the outer rho edge.  FP32C: the (hi, lo) pair of each value is scaled in
 // FP64 and split again.

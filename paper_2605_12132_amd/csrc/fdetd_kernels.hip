@@ -432,6 +432,47 @@ __device__ __forceinline__ double bspline3(double x)
     return 0.0;
 }
 
+// Radial shape of a sample at rho on primary row k (folded with parity par, normalised by N) and the
+// angular shape of mode m at angle th.
+struct SampleShape {
+    int kc, k0, k1;      // rows kc - 3 .. kc + 3, clipped to [0, nr)
+    double N, par, ar, ai;
+};
+__device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rho, double th, double eps)
+{
+    SampleShape S;
+    const double dr = D.dr;
+    S.par = (D.m % 2 == 0) ? 1.0 : -1.0;
+    S.kc = (int)floor(rho / dr);
+    S.k0 = S.kc - 3 > 0 ? S.kc - 3 : 0;
+    S.k1 = S.kc + 3 < D.nr - 1 ? S.kc + 3 : D.nr - 1;
+    double N = 0.0;
+    for (int k = S.k0; k <= S.kc + 3; ++k) {
+        const double rk = (k + 0.5) * dr;
+        const double w = bspline3((rk - rho) / dr) + bspline3((-rk - rho) / dr);
+        N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * pow(rk, eps) * w * dr;
+    }
+    S.N = N;
+    if (D.m == 0) {
+        S.ar = 0.5 / M_PI;
+        S.ai = 0.0;
+    } else {
+        S.ar = cos(D.m * th) / M_PI;
+        S.ai = -sin(D.m * th) / M_PI;
+    }
+    return S;
+}
+__device__ __forceinline__ double radial_weight(const ProbDesc &D, const SampleShape &S, double rho, double eps, int k)
+{
+    const double rk = (k + 0.5) * D.dr;
+    return pow(rk, eps - 1.0) * (bspline3((rk - rho) / D.dr) + S.par * bspline3((-rk - rho) / D.dr)) / S.N;
+}
+// The z shape of a position x (in cells) spans nodes floor(x) - 1 .. floor(x) + 2, which must lie on the grid.
+__device__ __forceinline__ bool z_on_grid(const ProbDesc &D, double x)
+{
+    return (int)floor(x) - 1 >= 0 && (int)floor(x) + 2 <= D.nz - 1;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 {
@@ -444,9 +485,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         const ProbDesc &D = A.probs[p];
         const double zp = (z + 0.5 * A.vz * D.dt) / D.dz, zm = (z - 0.5 * A.vz * D.dt) / D.dz;
         const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
-        if ((int)floor(zp) - 1 < 0 || (int)floor(zm) - 1 < 0 || (int)floor(zp) + 2 > D.nz - 1 ||
-            (int)floor(zm) + 2 > D.nz - 1 || hi - lo + 1 > 8)
-            continue;
+        if (!z_on_grid(D, zp) || !z_on_grid(D, zm) || hi - lo + 1 > 8) continue;
         double dF[8];
         double Fp = 0.0, Fm = 0.0;
         for (int u = 0; u <= hi - lo; ++u) {
@@ -454,34 +493,50 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
             Fp += bspline3(lo + u - zp);
             Fm += bspline3(lo + u - zm);
         }
-        const double dr = D.dr, par = (D.m % 2 == 0) ? 1.0 : -1.0;
-        const int kc = (int)floor(rho / dr);
-        double N = 0.0;
-        for (int k = kc - 3 > 0 ? kc - 3 : 0; k <= kc + 3; ++k) {
-            const double rk = (k + 0.5) * dr;
-            const double w = bspline3((rk - rho) / dr) + bspline3((-rk - rho) / dr);
-            N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * pow(rk, A.eps) * w * dr;
-        }
-        double ar, ai;  // angular shape
-        if (D.m == 0) {
-            ar = 0.5 / M_PI;
-            ai = 0.0;
-        } else {
-            ar = cos(D.m * th) / M_PI;
-            ai = -sin(D.m * th) / M_PI;
-        }
+        const SampleShape S = sample_shape(D, rho, th, A.eps);
         R *jz = (R *)A.j[p] + 2 * 2 * D.plane;  // plane 2, interleaved complex
-        const int k1 = kc + 3 < D.nr - 1 ? kc + 3 : D.nr - 1;
-        for (int k = kc - 3 > 0 ? kc - 3 : 0; k <= k1; ++k) {
-            const double rk = (k + 0.5) * dr;
-            const double rs = pow(rk, A.eps - 1.0) * (bspline3((rk - rho) / dr) + par * bspline3((-rk - rho) / dr)) / N;
+        for (int k = S.k0; k <= S.k1; ++k) {
+            const double rs = radial_weight(D, S, rho, A.eps, k);
             if (rs == 0.0) continue;
             for (int u = 0; u <= hi - lo; ++u) {
                 const double v = qw * dF[u] * rs;
                 if (v == 0.0) continue;
                 R *c = jz + 2 * ((size_t)k * D.nz + lo + u);
-                atomicAdd(c, (R)(v * ar));
-                atomicAdd(c + 1, (R)(v * ai));
+                atomicAdd(c, (R)(v * S.ar));
+                atomicAdd(c + 1, (R)(v * S.ai));
+            }
+        }
+    }
+}
+
+// Charge density of mode m of the samples shifted along z, one plane per problem (sections 3.2, 3.5):
+//   rho(z_i, rho_k) += q w S3(i - z'/dz) / dz * R_k * A_m,  z' = z + shift.
+template <typename R>
+__global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= A.n) return;
+    const double z = A.samples[4 * s] + A.shift, x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+    const double qw = A.samples[4 * s + 3];
+    const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+    for (int p = 0; p < A.nprob; ++p) {
+        const ProbDesc &D = A.probs[p];
+        const double zc = z / D.dz;
+        if (!z_on_grid(D, zc)) continue;
+        const int lo = (int)floor(zc) - 1;
+        double wz[4];
+        for (int u = 0; u < 4; ++u) wz[u] = bspline3(lo + u - zc) / D.dz;
+        const SampleShape S = sample_shape(D, rho, th, A.eps);
+        R *rp = (R *)A.j[p];
+        for (int k = S.k0; k <= S.k1; ++k) {
+            const double rs = radial_weight(D, S, rho, A.eps, k);
+            if (rs == 0.0) continue;
+            for (int u = 0; u < 4; ++u) {
+                const double v = qw * wz[u] * rs;
+                if (v == 0.0) continue;
+                R *c = rp + 2 * ((size_t)k * D.nz + lo + u);
+                atomicAdd(c, (R)(v * S.ar));
+                atomicAdd(c + 1, (R)(v * S.ai));
             }
         }
     }
@@ -554,6 +609,15 @@ hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s)
     const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
     if (prec == P64) hipLaunchKernelGGL(k_deposit_jz<double>, g, b, 0, s, a);
     else hipLaunchKernelGGL(k_deposit_jz<float>, g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_deposit_rho<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_deposit_rho<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1013,6 +1013,33 @@ int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double
     return FDETD_OK;
 }
 
+int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, double dz_shift, double eps,
+                      void *const *rho)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_deposit_rho: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_deposit_rho: plan is not a Maxwell plan");
+    if (n < 0 || !rho || (n > 0 && !aligned(samples, 8)) || !(eps >= 0.0 && eps <= 1.0) || !std::isfinite(dz_shift))
+        return fail(plan, FDETD_E_ARG, "fdetd_deposit_rho: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
+    for (size_t p = 0; p < plan->probs.size(); ++p)
+        if (!aligned(rho[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_deposit_rho: rho[%zu] NULL or not %zu-byte aligned", p, eb);
+    if (n == 0) return FDETD_OK;
+    for (const Batch &b : plan->batches) {
+        DepositArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = plan->ddesc + b.d0;
+        A.nprob = b.count;
+        A.n = n;
+        A.samples = samples;
+        A.shift = dz_shift;
+        A.eps = eps;
+        for (int t = 0; t < b.count; ++t) A.j[t] = rho[b.members[t]];
+        HIPCHK(plan, launch_deposit_rho(prec_code(plan->precision), A, plan->stream));
+    }
+    return FDETD_OK;
+}
+
 int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max, double power)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_absorber: NULL plan");

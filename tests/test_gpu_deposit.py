@@ -1,4 +1,5 @@
-"""GPU deposition of point samples into J_z (fdetd_deposit_jz) against the oracle's deposition.
+"""GPU deposition of point samples into J_z (fdetd_deposit_jz) and the charge density (fdetd_deposit_rho)
+against the oracle's deposition, and the discrete continuity equation between the GPU's own outputs.
 
 A bunch of samples concentrated near the axis (the shapes fold across it there) plus a spread of samples,
 including some within two cells of the z ends (skipped by both sides), is deposited for modes 0, 1, 2 of
@@ -69,4 +70,50 @@ def test_deposit_rejects_bad_arguments():
     plan.deposit_jz(s[:0], J)  # no samples: nothing to do
     torch.cuda.synchronize()
     assert torch.count_nonzero(J[0]) == 0
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deposit_rho_matches_oracle_and_continuity(precision):
+    """Charge densities of the samples shifted by -+ vz dt/2 against the oracle (same tolerances as J_z),
+    and, FP64, the discrete continuity equation between the GPU's two densities and its J_z:
+    (rho_+(i) - rho_-(i)) / dt + (J_z(i + 1/2) - J_z(i - 1/2)) / dz = 0 to rounding."""
+    import torch
+    dz = I.LAMBDA0 / 20
+    nz, nr = 260, 40
+    dt = 0.5 * dz
+    w = I.Workload("dep", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [8] * 3, 8, dz, 2 * dz, dt, 1)
+    rng = np.random.default_rng(33)
+    s = samples(rng, 12000, nz, nr, dz, 2 * dz)
+    sd = dev(s, torch.float64)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=1)
+    vz = 0.9
+    rp = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    rm = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    J = [torch.zeros((3, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    plan.deposit_rho(sd, rp, dz_shift=0.5 * vz * dt, eps=0.5)
+    plan.deposit_rho(sd, rm, dz_shift=-0.5 * vz * dt, eps=0.5)
+    plan.deposit_jz(sd, J, vz=vz, eps=0.5)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == F.FP64 else 1e-5
+    for p in range(3):
+        g = oracle.Grid(nz=nz, nr=nr, m=p, fd_order=8, taylor_order=8, dz=dz, dr=2 * dz, dt=dt)
+        want = oracle.deposit_rho(g, s, 0.5 * vz * dt, eps=0.5)
+        got = rp[p].cpu().numpy().astype(np.complex128)
+        err = rel_l2(got, want)
+        log(f"deposit rho m={p} precision={precision}: rel L2 {err:.2e}")
+        assert err < tol
+        if precision == F.FP64:
+            # samples skipped by the current (shape past a z end at either position) are also skipped by
+            # one of the densities; compare on columns away from the ends, where nothing is skipped
+            a = rp[p].cpu().numpy()
+            b = rm[p].cpu().numpy()
+            jz = J[p][2].cpu().numpy()
+            res = (a - b)[:, 8:nz - 8] / dt + (jz[:, 9:nz - 7] - jz[:, 8:nz - 8]) / dz
+            scale = np.max(np.abs(a)) / dt
+            log(f"  continuity residual {np.max(np.abs(res)) / scale:.2e} of max |rho| / dt")
+            assert np.max(np.abs(res)) < 1e-12 * scale
+    with pytest.raises(F.FdetdError):
+        plan.deposit_rho(sd, rp, eps=2.0)
     plan.close()
