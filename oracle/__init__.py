@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 OP_DZ_MINUS, OP_DZ_PLUS, OP_DR_MINUS, OP_DR_PLUS, OP_DIV_MINUS, OP_DIV_PLUS = 0, 1, 2, 3, 4, 5
 OP_SHIFT_MINUS, OP_LAP_RHO, OP_LAP_Z, OP_DZ_CENTRED, OP_AXIS = 6, 7, 8, 9, 10
+OP_SHIFT_PLUS_RHO, OP_SHIFT_PLUS_Z = 11, 12
 
 
 def build(force: bool = True) -> str:
@@ -94,6 +95,8 @@ def lib():
         L.oracle_num_threads.restype = C.c_int
         L.oracle_deposit_rho.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
         L.oracle_deposit_jz.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
+        L.oracle_destagger.argtypes = [P, vp, vp]
+        L.oracle_interpolate.argtypes = [P, vp, vp, C.c_long, vp]
         _lib = L
     return _lib
 
@@ -263,3 +266,36 @@ def envelope_energy(g: Grid, a, at):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def destagger(g: Grid, psi):
+    """The six components of a state on the primary grids (section 3.3), [6, nr, nz]."""
+    x = _cplx(psi, (6, g.nr, g.nz))
+    out = np.zeros_like(x)
+    P = g.c()
+    _chk(lib().oracle_destagger(C.byref(P), _ptr(x), _ptr(out)), "destagger")
+    return out
+
+
+def interpolate(g: Grid, prim, samples):
+    """Mode g.m of six primary-grid planes [6, nr, nz] at the samples: [n, 6] doubles (section 3.3)."""
+    x = _cplx(prim, (6, g.nr, g.nz))
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    out = np.zeros((s.shape[0], 6))
+    P = g.c()
+    _chk(lib().oracle_interpolate(C.byref(P), _ptr(x), _ptr(s), s.shape[0], _ptr(out)), "interpolate")
+    return out
+
+
+def gather(grids, states, samples):
+    """Fields at the samples: for every (grid, state) pair (the modes of one grid), the destaggered
+    components interpolated with cubic shapes and summed as Re(F_m e^(i m theta)); [n, 6] doubles
+    (E_rho, E_theta, E_z, B_rho, B_theta, B_z)."""
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    assert s.ndim == 2 and s.shape[1] == 4
+    out = np.zeros((s.shape[0], 6))
+    for g, psi in zip(grids, states):
+        prim = destagger(g, psi)
+        P = g.c()
+        _chk(lib().oracle_interpolate(C.byref(P), _ptr(prim), _ptr(s), s.shape[0], _ptr(out)), "interpolate")
+    return out

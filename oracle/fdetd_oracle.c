@@ -295,6 +295,36 @@ static void op_shift_minus(const oracle_problem *P, const double *s_, int nd, in
         }
 }
 
+/* S_rho^(+): Lagrange half-shift staggered rho -> primary rho (section 3.3 destaggering, the
+ * counterpart of S^(-) of section 2.3); the operand's axis value is placed in row 0 and its ghosts
+ * mirror with the given parity, as for D_rho^(+). */
+static void op_shift_plus_rho(const oracle_problem *P, const double *s_, const double *c, int nd, int parity,
+                              int extrapolate, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx ax = axis_value(P, c, nd, in, i, extrapolate);
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += s_[j - 1] * (stag_val(P, in, parity, ax, k + j, i) + stag_val(P, in, parity, ax, k - j + 1, i));
+            out[IDX(P, k, i)] = s;
+        }
+}
+
+/* S_z^(+): Lagrange half-shift staggered z -> primary z (section 3.3); terms outside [0, nz) are 0. */
+static void op_shift_plus_z(const oracle_problem *P, const double *s_, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += s_[j - 1] * (prim_val(P, in, +1, k, i + j) + prim_val(P, in, +1, k, i - j + 1));
+            out[IDX(P, k, i)] = s;
+        }
+}
+
 /* Radial Laplacian L_rho = D^2 + rho^-1 D^(C) on the primary grid (section 2.3). */
 static void op_lap_rho(const oracle_problem *P, const double *b, const double *d, int nd, int parity,
                        const cplx *in, cplx *out)
@@ -370,6 +400,8 @@ int oracle_apply_op(const oracle_problem *P, int op, int parity, int axis_extrap
     case 7: op_lap_rho(P, b, d, nd, parity, in, out); break;
     case 8: op_lap_z(P, b, nd, in, out); break;
     case 9: op_dz_centred(P, d, nd, in, out); break;
+    case 11: op_shift_plus_rho(P, s, c, nd, parity, axis_extrapolate, in, out); break;
+    case 12: op_shift_plus_z(P, s, nd, in, out); break;
     case 10:
         memset(out, 0, (size_t)P->nr * P->nz * sizeof(cplx));
         for (int i = 0; i < P->nz; ++i) out[IDX(P, 0, i)] = axis_value(P, c, nd, in, i, axis_extrapolate);
@@ -815,5 +847,67 @@ int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, do
         }
     }
     free(dF);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Field interpolation (section 3.3): destaggering to the primary grids, then the sum of the shapes   */
+/* of the sample over the nodes, the radial shape treated as a Cartesian one.                          */
+/* ------------------------------------------------------------------------------------------ */
+
+/* The six components on the primary grids: E_rho^(C) = S_rho^(+,mA) E_rho, E_theta as it is,
+ * E_z^(C) = S_z^(+) E_z, B_rho^(C) = S_z^(+) B_rho, B_theta^(C) = S_rho^(+,mA) S_z^(+) B_theta,
+ * B_z^(C) = S_rho^(+,mS) B_z.  The staggered operands' axis values follow the boundary rule. */
+int oracle_destagger(const oracle_problem *P, const double complex *psi, double complex *out)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2, m = P->m;
+    const size_t n = (size_t)P->nr * P->nz;
+    double s[16], c[16];
+    oracle_coef_halfshift(nd, s);
+    oracle_coef_axis(nd, c);
+    const int pS = parity_mS(m), pA = parity_mA(m);
+    cplx *t = malloc(n * sizeof(cplx));
+    if (!t) return -2;
+    op_shift_plus_rho(P, s, c, nd, pA, m == 1, psi + ER * n, out + ER * n);
+    memcpy(out + ETH * n, psi + ETH * n, n * sizeof(cplx));
+    op_shift_plus_z(P, s, nd, psi + EZ * n, out + EZ * n);
+    op_shift_plus_z(P, s, nd, psi + BR * n, out + BR * n);
+    op_shift_plus_z(P, s, nd, psi + BTH * n, t);
+    op_shift_plus_rho(P, s, c, nd, pA, m == 1, t, out + BTH * n);
+    op_shift_plus_rho(P, s, c, nd, pS, m == 0, psi + BZ * n, out + BZ * n);
+    free(t);
+    return 0;
+}
+
+/* Adds to fields[s][c] (n x 6, E_rho, E_theta, E_z, B_rho, B_theta, B_z) the value of mode m at sample s:
+ *   Re( e^(i m theta_p) sum_(i,k) S3(i - z_p/dz) S3((rho_k - rho_p)/drho) F_c(k, i) )
+ * over the extended primary grid rho_k = (k + 1/2) drho: rows k < 0 take the parity times row -1-k
+ * (mA for the rho and theta components, mS for the z components), rows >= nr and columns outside [0, nz)
+ * are 0.  `prim` holds the six destaggered planes. */
+int oracle_interpolate(const oracle_problem *P, const double complex *prim, const double *samples, long n,
+                       double *fields)
+{
+    if (check_problem(P) || n < 0) return -1;
+    const size_t np = (size_t)P->nr * P->nz;
+    const int pS = parity_mS(P->m), pA = parity_mA(P->m);
+    const int par[6] = {pA, pA, pS, pA, pA, pS};
+    for (long s = 0; s < n; ++s) {
+        const double z = samples[4 * s], x = samples[4 * s + 1], y = samples[4 * s + 2];
+        const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+        const cplx rot = cexp(I * (double)P->m * th);
+        for (int f = 0; f < 6; ++f) {
+            cplx v = 0.0;
+            for (int k = -P->nr; k < P->nr; ++k) {
+                const double wr = bspline3(((k + 0.5) * P->dr - rho) / P->dr);
+                if (wr == 0.0) continue;
+                for (int i = 0; i < P->nz; ++i) {
+                    const double wz = bspline3(i - z / P->dz);
+                    if (wz != 0.0) v += wz * wr * prim_val(P, prim + f * np, par[f], k, i);
+                }
+            }
+            fields[6 * s + f] += creal(v * rot);
+        }
+    }
     return 0;
 }

@@ -94,6 +94,12 @@ int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, d
 int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, double vz, double eps,
                       double complex *j);
 
+/* Field interpolation (section 3.3): the six components destaggered to the primary grids, and the value
+ * of this mode at each sample added into fields (n x 6 doubles). */
+int oracle_destagger(const oracle_problem *P, const double complex *psi, double complex *out);
+int oracle_interpolate(const oracle_problem *P, const double complex *prim, const double *samples, long n,
+                       double *fields);
+
 int oracle_num_threads(void);
 
 #ifdef __cplusplus
