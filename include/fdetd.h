@@ -177,6 +177,23 @@ FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t
 FDETD_API int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, double dz_shift, double eps,
                                 void *const *rho);
 
+/* Fields at n sample positions (section 3.3 field interpolation), for a plan whose problems are modes of
+ * one grid (equal nz, nr, dz, dr; at most 16): the components are destaggered to the primary grids,
+ *   E_rho = S_rho^(+,mA) E_rho,  E_theta as stored,  E_z = S_z^(+) E_z,  B_rho = S_z^(+) B_rho,
+ *   B_theta = S_rho^(+,mA) S_z^(+) B_theta,  B_z = S_rho^(+,mS) B_z
+ * (Lagrange half-shifts with the weights s_j, the staggered operand's axis value by the boundary rule,
+ * terms beyond the grid 0), then interpolated with cubic shapes in z and rho, the radial shape treated as
+ * a Cartesian one over the grid extended below the axis with each component's parity (m_A for the rho and
+ * theta components, m_S for the z components), and summed over the modes as Re(F_m e^(i m theta)):
+ *   fields[s][c] = sum_m Re( e^(i m theta_s) sum_(i,k) S3(i - z_s/dz) S3(k + 1/2 - rho_s/dr) F_m,c(k, i) ).
+ *   psi      n_probs device pointers to the states (as for fdetd_step); read only.
+ *   samples  device array of n x 4 doubles (z, x, y, unused), 8-byte aligned.
+ *   fields   device array of n x 6 doubles (E_rho, E_theta, E_z, B_rho, B_theta, B_z), overwritten.
+ * Uses the plan's stage buffers as scratch (ordered on the plan's stream).  FP32C: destaggers the stored
+ * floats (not the compensation words) in FP64 arithmetic and stores the destaggered planes as floats.
+ * Enqueue only. */
+FDETD_API int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields);
+
 /* Absorbing layers of envelope problems (appendix on the scalar absorbing layer, which the envelope
  * solver of section 4.2 may use): from the next envelope_step on, every step of the problem is
  *     psi_a(t + dt) = exp(-sigma dt/4) T_N(dt H_a(chi~)) exp(-sigma dt/4) psi_a(t),   chi~ = chi + sigma^2,

@@ -22,7 +22,7 @@ PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_ST
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_deposit_rho",
-           "fdetd_query",
+           "fdetd_gather", "fdetd_query",
            "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
@@ -82,6 +82,7 @@ def _load():
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
+    L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
     L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -142,6 +143,10 @@ def fdetd_deposit_jz(plan, samples_ptr, n: int, vz: float, eps: float, j_ptrs):
 
 def fdetd_deposit_rho(plan, samples_ptr, n: int, dz_shift: float, eps: float, rho_ptrs):
     _check(lib.fdetd_deposit_rho(plan, samples_ptr, n, dz_shift, eps, _ptrs(rho_ptrs)), plan)
+
+
+def fdetd_gather(plan, psi_ptrs, samples_ptr, n: int, fields_ptr):
+    _check(lib.fdetd_gather(plan, _ptrs(psi_ptrs), samples_ptr, n, fields_ptr), plan)
 
 
 def envelope_absorber(plan, problem: int, lz: int, lr: int, sigma_max: float, power: float = 2.0):
@@ -253,6 +258,23 @@ class Plan:
         self._nchk(rho, "rho")
         rp = [self._chk(x, (p.nr, p.nz), self._cdtype(), "rho") for x, p in zip(rho, self.problems)]
         fdetd_deposit_rho(self._h, samples.data_ptr(), samples.shape[0], dz_shift, eps, rp)
+
+    def gather(self, psi, samples, fields=None):
+        """Fields (float64 [n, 6] cuda tensor: E_rho, E_theta, E_z, B_rho, B_theta, B_z) at the samples
+        (float64 [n, 4] cuda tensor of z, x, y, w) of the plan's modes of one grid."""
+        import torch
+        if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 4
+                and samples.is_contiguous()):
+            raise ValueError("samples: contiguous float64 cuda tensor [n, 4]")
+        self._nchk(psi, "psi")
+        pp = [self._chk(x, (6, p.nr, p.nz), self._cdtype(), "psi") for x, p in zip(psi, self.problems)]
+        if fields is None:
+            fields = torch.empty((samples.shape[0], 6), dtype=torch.float64, device=samples.device)
+        if not (fields.is_cuda and fields.dtype == torch.float64 and fields.is_contiguous()
+                and tuple(fields.shape) == (samples.shape[0], 6)):
+            raise ValueError("fields: contiguous float64 cuda tensor [n, 6]")
+        fdetd_gather(self._h, pp, samples.data_ptr(), samples.shape[0], fields.data_ptr())
+        return fields
 
     def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):
         cd, rd = self._cdtype(), self._rdtype()

@@ -152,6 +152,28 @@ struct DepositArgs {
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
+// Field interpolation (section 3.3).  Destaggering of one plane to the primary grid: along z (S_z^(+),
+// columns outside the grid 0) or along rho (S_rho^(+) with the operand's parity and axis rule).
+struct DestaggerArgs {
+    const void *src;
+    void *dst;
+    int nz, nr, nd, along_rho, parity, extrapolate;
+    double s[kMaxND];    // half-shift weights s_j
+    double c[kMaxND];    // axis extrapolation weights c_k'
+};
+hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s);
+constexpr int kMaxGather = 16;  // modes of one grid per gather
+struct GatherArgs {
+    int64_t n;
+    const double *samples;  // n x 4: z, x, y, (unused)
+    double *fields;         // n x 6: E_rho, E_theta, E_z, B_rho, B_theta, B_z (overwritten)
+    int nprob, nz, nr;
+    double dz, dr;
+    int m[kMaxGather];
+    const void *plane[kMaxGather][6];  // the destaggered components on the primary grid
+};
+hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
+
 // Damping exp(-sigma dt/4) of an envelope state (a, a~) on the cells of its absorbing layers: lz columns
 // at each z end and lr rows at the outer rho edge.  FP32C: the (hi, lo) pair of each value is scaled in
 // FP64 and split again.

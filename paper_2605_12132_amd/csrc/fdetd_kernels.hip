@@ -542,7 +542,134 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
     }
 }
 
+// --------------------------------------------------------------------------------------------------
+// Field interpolation (section 3.3).  Destaggering, one thread per output cell:
+//   along z:   out(k, i) = sum_j s_j (f(k, i + j) + f(k, i - j + 1)),  columns outside [0, nz) are 0;
+//   along rho: out(k, i) = sum_j s_j (f(k + j, i) + f(k - j + 1, i)) on the staggered rows, row 0 = the
+//              axis value (sum_k' c_k' f(k', i) when extrapolated, else 0), rows q < 0 = parity f(-q),
+//              rows >= nr are 0.  FP64 arithmetic, storage precision in and out.
+// --------------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_destagger(DestaggerArgs A)
+{
+    using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (i >= A.nz) return;
+    const V *f = (const V *)A.src;
+    auto at = [&](int q, int c) -> double2 {
+        const V v = f[(size_t)q * A.nz + c];
+        return double2{(double)v.x, (double)v.y};
+    };
+    double re = 0.0, im = 0.0;
+    if (!A.along_rho) {
+        for (int j = 1; j <= A.nd; ++j) {
+            const int c0 = i + j, c1 = i - j + 1;
+            if (c0 < A.nz) {
+                const double2 v = at(k, c0);
+                re += A.s[j - 1] * v.x;
+                im += A.s[j - 1] * v.y;
+            }
+            if (c1 >= 0) {
+                const double2 v = at(k, c1);
+                re += A.s[j - 1] * v.x;
+                im += A.s[j - 1] * v.y;
+            }
+        }
+    } else {
+        double axr = 0.0, axi = 0.0;
+        if (A.extrapolate)
+            for (int q = 1; q <= A.nd && q < A.nr; ++q) {
+                const double2 v = at(q, i);
+                axr += A.c[q - 1] * v.x;
+                axi += A.c[q - 1] * v.y;
+            }
+        auto row = [&](int q, double &x, double &y) {
+            if (q >= A.nr) { x = y = 0.0; return; }
+            if (q == 0) { x = axr; y = axi; return; }
+            if (-q >= A.nr) { x = y = 0.0; return; }
+            const double sg = q < 0 ? (double)A.parity : 1.0;
+            const double2 v = at(q < 0 ? -q : q, i);
+            x = sg * v.x;
+            y = sg * v.y;
+        };
+        for (int j = 1; j <= A.nd; ++j) {
+            double x0, y0, x1, y1;
+            row(k + j, x0, y0);
+            row(k - j + 1, x1, y1);
+            re += A.s[j - 1] * (x0 + x1);
+            im += A.s[j - 1] * (y0 + y1);
+        }
+    }
+    V *o = (V *)A.dst;
+    o[(size_t)k * A.nz + i] = V{(R)re, (R)im};
+}
+
+// Interpolation, one thread per sample: for each mode m and component c,
+//   Re( e^(i m theta) sum_(i,k) S3(i - z/dz) S3(k + 1/2 - rho/drho) F_c(k, i) )
+// over the extended primary grid (rows k < 0 take parity * row -1-k: m_A for the rho and theta
+// components, m_S for the z ones; rows >= nr and columns outside the grid are 0), summed over the modes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather(GatherArgs A)
+{
+    using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= A.n) return;
+    const double z = A.samples[4 * s], x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+    const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+    const double zc = z / A.dz, rc = rho / A.dr - 0.5;
+    const int i0 = (int)floor(zc) - 1, k0 = (int)floor(rc) - 1;
+    double wz[4], wr[4];
+    for (int u = 0; u < 4; ++u) {
+        wz[u] = bspline3(i0 + u - zc);
+        wr[u] = bspline3(k0 + u - rc);
+    }
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < A.nprob; ++p) {
+        const int m = A.m[p];
+        const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
+        const double cr = cos(m * th), ci = sin(m * th);
+        for (int c = 0; c < 6; ++c) {
+            const double par = (c == 2 || c == 5) ? pS : pA;
+            const V *f = (const V *)A.plane[p][c];
+            double re = 0.0, im = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const int k = k0 + a;
+                const int q = k < 0 ? -1 - k : k;
+                if (q >= A.nr || wr[a] == 0.0) continue;
+                const double sg = k < 0 ? par : 1.0;
+                for (int b = 0; b < 4; ++b) {
+                    const int i = i0 + b;
+                    if (i < 0 || i >= A.nz) continue;
+                    const V v = f[(size_t)q * A.nz + i];
+                    const double w = sg * wr[a] * wz[b];
+                    re += w * (double)v.x;
+                    im += w * (double)v.y;
+                }
+            }
+            acc[c] += re * cr - im * ci;
+        }
+    }
+    for (int c = 0; c < 6; ++c) A.fields[6 * s + c] = acc[c];
+}
+
 }  // namespace
+
+hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr);
+    if (prec == P64) hipLaunchKernelGGL(k_destagger<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_destagger<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 // --------------------------------------------------------------------------------------------------
 // Absorbing-layer damping (appendix on the scalar absorbing layer): both factors exp(-sigma dt/4) of the

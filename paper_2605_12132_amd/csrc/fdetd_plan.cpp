@@ -1040,6 +1040,73 @@ int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, doubl
     return FDETD_OK;
 }
 
+int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_gather: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_gather: plan is not a Maxwell plan");
+    const int np = (int)plan->probs.size();
+    if (!psi || n < 0 || (n > 0 && (!aligned(samples, 8) || !aligned(fields, 8))))
+        return fail(plan, FDETD_E_ARG, "fdetd_gather: bad arguments");
+    if (np > kMaxGather) return fail(plan, FDETD_E_ARG, "fdetd_gather: at most %d problems (modes of one grid)", kMaxGather);
+    const size_t eb = elem_bytes(plan->precision);
+    const fdetd_problem_desc &d0 = plan->probs[0].d;
+    for (int p = 0; p < np; ++p) {
+        const fdetd_problem_desc &d = plan->probs[p].d;
+        if (d.nz != d0.nz || d.nr != d0.nr || d.dz != d0.dz || d.dr != d0.dr)
+            return fail(plan, FDETD_E_ARG, "fdetd_gather: problem %d is not a mode of the same grid as problem 0", p);
+        if (!aligned(psi[p], eb)) return fail(plan, FDETD_E_ARG, "fdetd_gather: psi[%d] NULL or misaligned", p);
+    }
+    if (n == 0) return FDETD_OK;
+    const int prec = prec_code(plan->precision);
+    GatherArgs G;
+    std::memset(&G, 0, sizeof G);
+    G.n = n;
+    G.samples = samples;
+    G.fields = fields;
+    G.nprob = np;
+    G.nz = d0.nz;
+    G.nr = d0.nr;
+    G.dz = d0.dz;
+    G.dr = d0.dr;
+    for (int p = 0; p < np; ++p) {
+        const Prob &q = plan->probs[p];
+        const size_t pb = q.cells * eb;
+        auto plane = [&](const void *base, int c) { return (const void *)((const char *)base + c * pb); };
+        // destaggered components in buf[0] (E_theta is read from psi), B_theta's z shift in buf[1]
+        DestaggerArgs X;
+        std::memset(&X, 0, sizeof X);
+        X.nz = q.d.nz;
+        X.nr = q.d.nr;
+        X.nd = q.nd;
+        for (int j = 0; j < q.nd; ++j) {
+            X.s[j] = q.s[j];
+            X.c[j] = q.c[j];
+        }
+        const int m = q.d.m, pS = (m % 2 == 0) ? 1 : -1, pA = (std::abs(m - 1) % 2 == 0) ? 1 : -1;
+        struct Pass { const void *src; void *dst; int rho, parity, extrapolate; };
+        const Pass passes[6] = {
+            {plane(psi[p], ER), (void *)plane(q.buf[0], ER), 1, pA, m == 1},
+            {plane(psi[p], EZ), (void *)plane(q.buf[0], EZ), 0, 1, 0},
+            {plane(psi[p], BR), (void *)plane(q.buf[0], BR), 0, 1, 0},
+            {plane(psi[p], BTH), (void *)plane(q.buf[1], 0), 0, 1, 0},
+            {plane(q.buf[1], 0), (void *)plane(q.buf[0], BTH), 1, pA, m == 1},
+            {plane(psi[p], BZ), (void *)plane(q.buf[0], BZ), 1, pS, m == 0},
+        };
+        for (const Pass &ps : passes) {
+            X.src = ps.src;
+            X.dst = ps.dst;
+            X.along_rho = ps.rho;
+            X.parity = ps.parity;
+            X.extrapolate = ps.extrapolate;
+            HIPCHK(plan, launch_destagger(prec, X, plan->stream));
+        }
+        G.m[p] = m;
+        for (int c = 0; c < 6; ++c) G.plane[p][c] = c == ETH ? plane(psi[p], ETH) : plane(q.buf[0], c);
+    }
+    HIPCHK(plan, launch_gather(prec, G, plan->stream));
+    return FDETD_OK;
+}
+
 int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max, double power)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_absorber: NULL plan");

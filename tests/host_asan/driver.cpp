@@ -22,6 +22,8 @@ hipError_t launch_axis_fix(int, int, const AxisArgs &, hipStream_t) { return hip
 hipError_t launch_deposit_jz(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_gather(int, const GatherArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_norm2(int, const void *, size_t, double *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_copy(const void *, void *, size_t, hipStream_t) { return hipErrorInvalidValue; }
@@ -102,6 +104,7 @@ int main()
     EXPECT(fdetd_deposit_jz(nullptr, nullptr, 0, 1.0, 0.5, ptrs) == FDETD_E_ARG);
     EXPECT(fdetd_deposit_rho(nullptr, nullptr, 0, 0.0, 0.5, ptrs) == FDETD_E_ARG);
     EXPECT(envelope_absorber(nullptr, -1, 4, 4, 1.0, 2.0) == FDETD_E_ARG);
+    EXPECT(fdetd_gather(nullptr, ptrs, nullptr, 0, nullptr) == FDETD_E_ARG);
     fdetd_plan_info info;
     EXPECT(fdetd_query(nullptr, &info) == FDETD_E_ARG);
     size_t bytes = 0;
