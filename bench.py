@@ -358,8 +358,9 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
     of peak density n_b) moving at c, deposited with fdetd_deposit_jz (timed separately, including the
-    advance of the sample positions), then graph replay of `steps` field steps.  FP64 and FP32C; the FP32C
-    error against FP64 after the same steps."""
+    advance of the sample positions), then graph replay of `steps` field steps, then the fields of the
+    final state at the samples (fdetd_gather, timed apart).  FP64 and FP32C; the FP32C error against FP64
+    after the same steps."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -394,13 +395,25 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
         psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
         del J
         torch.cuda.empty_cache()
+        # fields of the final state at the samples' last positions (destaggering + interpolation), 5 calls
+        with torch.cuda.stream(stream):
+            plan = F.Plan(w.problems(), precision=prec, flags=F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
+            fields = plan.gather(psi, smp)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                plan.gather(psi, smp, fields)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            gather_ms = ev0.elapsed_time(ev1) / 5
+            plan.close()
         gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
         res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
-                        frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms,
+                        frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms, gather_ms=gather_ms,
                         seg_rows=info["seg_rows"])
         psis[tag] = psi
         log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
-            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step")
+            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step; gather {gather_ms:.3f} ms")
     num = den = 0.0
     for a, b in zip(psis["fp64"], psis["fp32c"]):
         num += float(torch.sum(torch.abs(a - b.to(torch.complex128)) ** 2))
@@ -456,7 +469,8 @@ def main():
     psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph, args.seg_rows_fp64)
     rate64 = cells * K / (ms64 * 1e-3)
     log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s (plan {plan_s:.2f} s, dt*rho {info64['dt_rho_max']:.3f})")
-    roof64 = profile_pass(w, F.FP64, args.profile_steps, J64, info64["seg_rows"])
+    prof_steps = min(args.profile_steps, K + W)  # the currents held resident cover K + W steps
+    roof64 = profile_pass(w, F.FP64, prof_steps, J64, info64["seg_rows"])
     log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
 
     fp32c = None
@@ -466,7 +480,7 @@ def main():
         torch.cuda.empty_cache()
         psi32, ms32, _, info32 = run_path(w, F.FP32C, K, W, J32, not args.no_graph, args.seg_rows_fp32c)
         rate32 = cells * K / (ms32 * 1e-3)
-        roof32 = profile_pass(w, F.FP32C, args.profile_steps, J32, info32["seg_rows"])
+        roof32 = profile_pass(w, F.FP32C, prof_steps, J32, info32["seg_rows"])
         errs = fp32c_errors(w, psi64, psi32)
         log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, errors {errs}")
         fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
