@@ -84,6 +84,8 @@ def lib():
         L.oracle_stage_current.argtypes = [P, vp, vp]
         L.oracle_set_axis.argtypes = [P, vp]
         L.oracle_step.argtypes = [P, vp, vp, C.c_int64, C.c_int]
+        L.oracle_step_corrected.argtypes = [P, vp, vp, C.c_int64, C.c_int]
+        L.oracle_correct_current.argtypes = [P, vp, vp]
         L.oracle_apply_Ha.argtypes = [P, vp, vp, vp, vp, vp]
         L.oracle_envelope_step.argtypes = [P, vp, vp, vp, C.c_int]
         L.oracle_absorber_profile.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, vp]
@@ -299,3 +301,24 @@ def gather(grids, states, samples):
         P = g.c()
         _chk(lib().oracle_interpolate(C.byref(P), _ptr(prim), _ptr(s), s.shape[0], _ptr(out)), "interpolate")
     return out
+
+
+def correct_current(g: Grid, jbar, rho_xy):
+    """Current correction of section 3.7 on a staged current [3, nr, nz] (J_rho staggered) with the planar
+    density differential rho_xy [nr, nz]; returns the corrected current."""
+    x = _cplx(jbar, (3, g.nr, g.nz)).copy()
+    r = _cplx(rho_xy, (g.nr, g.nz))
+    P = g.c()
+    _chk(lib().oracle_correct_current(C.byref(P), _ptr(x), _ptr(r)), "correct_current")
+    return x
+
+
+def step_corrected(g: Grid, psi, j4, n_steps: int = 1):
+    """n_steps with the current correction: j4 is [4, nr, nz] (the same block every step) or
+    [n_steps, 4, nr, nz] (J_rho, J_theta, J_z, rho_xy)."""
+    psi = _cplx(psi, (6, g.nr, g.nz)).copy()
+    j = np.ascontiguousarray(j4, dtype=np.complex128)
+    stride = 0 if j.ndim == 3 else 4 * g.nr * g.nz
+    P = g.c()
+    _chk(lib().oracle_step_corrected(C.byref(P), _ptr(psi), _ptr(j), stride, n_steps), "step_corrected")
+    return psi

@@ -511,10 +511,111 @@ int oracle_stage_current(const oracle_problem *P, const double complex *j, doubl
     return 0;
 }
 
+/* Current correction (section 3.7), on the staged current jbar (J_rho on the staggered rho grid, J_theta,
+ * J_z) with the planar density differential rho_xy of the same mode:
+ *   d = rho_xy - D_div^(+,mS) Jbar_rho - (i m / rho) Jbar_theta        (primary rows)
+ *   [L_rho^(mS) - m^2 / rho^2] phi = d                                  (one solve per z column)
+ *   Jbar_rho += D_rho^(-,mS) phi (rows k >= 1),  Jbar_theta += (i m / rho) phi,  Jbar_z unchanged.
+ * The radial operator is the one of the envelope (centred second and first differences, section 2.3);
+ * its matrix is built by applying it to unit vectors, and each column is solved by Gaussian elimination
+ * with partial pivoting.  In place on jbar. */
+int oracle_correct_current(const oracle_problem *P, double complex *jbar, const double complex *rho_xy)
+{
+    if (check_problem(P)) return -1;
+    const int nd = P->fd_order / 2, m = P->m, nr = P->nr, nz = P->nz;
+    const size_t n = (size_t)nr * nz;
+    double a[16], b[17], d1[16];
+    oracle_coef_staggered(nd, a);
+    oracle_coef_centred_d2(nd, b);
+    oracle_coef_centred_d1(nd, d1);
+    const int pS = parity_mS(m);
+    cplx *dv = malloc(n * sizeof(cplx)), *t = malloc(n * sizeof(cplx)), *e = malloc(n * sizeof(cplx));
+    double *A = malloc((size_t)nr * nr * sizeof(double));
+    cplx *x = malloc((size_t)nr * sizeof(cplx));
+    double *M = malloc((size_t)nr * nr * sizeof(double));
+    if (!dv || !t || !e || !A || !x || !M) return -2;
+    /* planar divergence error */
+    op_div_plus(P, a, nd, pS, jbar, dv);
+    for (int k = 0; k < nr; ++k)
+        for (int i = 0; i < nz; ++i) {
+            const size_t q = IDX(P, k, i);
+            dv[q] = rho_xy[q] - dv[q] - (I * m / ((k + 0.5) * P->dr)) * jbar[n + q];
+        }
+    /* matrix of L_rho - m^2/rho^2, column kk = the operator on the unit vector of row kk */
+    for (int kk = 0; kk < nr; ++kk) {
+        memset(e, 0, n * sizeof(cplx));
+        for (int i = 0; i < nz; ++i) e[IDX(P, kk, i)] = 1.0;
+        op_lap_rho(P, b, d1, nd, pS, e, t);
+        for (int k = 0; k < nr; ++k) {
+            const double rho = (k + 0.5) * P->dr;
+            A[(size_t)k * nr + kk] = creal(t[IDX(P, k, 0)]) - (k == kk ? (double)m * m / (rho * rho) : 0.0);
+        }
+    }
+    /* phi = A^-1 d per column (Gaussian elimination, partial pivoting), kept in t */
+    for (int i = 0; i < nz; ++i) {
+        memcpy(M, A, (size_t)nr * nr * sizeof(double));
+        for (int k = 0; k < nr; ++k) x[k] = dv[IDX(P, k, i)];
+        for (int c = 0; c < nr; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < nr; ++r)
+                if (fabs(M[(size_t)r * nr + c]) > fabs(M[(size_t)piv * nr + c])) piv = r;
+            if (piv != c) {
+                for (int q = 0; q < nr; ++q) {
+                    const double tmp = M[(size_t)c * nr + q];
+                    M[(size_t)c * nr + q] = M[(size_t)piv * nr + q];
+                    M[(size_t)piv * nr + q] = tmp;
+                }
+                const cplx tx = x[c];
+                x[c] = x[piv];
+                x[piv] = tx;
+            }
+            for (int r = c + 1; r < nr; ++r) {
+                const double f = M[(size_t)r * nr + c] / M[(size_t)c * nr + c];
+                if (f == 0.0) continue;
+                for (int q = c; q < nr; ++q) M[(size_t)r * nr + q] -= f * M[(size_t)c * nr + q];
+                x[r] -= f * x[c];
+            }
+        }
+        for (int c = nr - 1; c >= 0; --c) {
+            cplx v = x[c];
+            for (int q = c + 1; q < nr; ++q) v -= M[(size_t)c * nr + q] * x[q];
+            x[c] = v / M[(size_t)c * nr + c];
+        }
+        for (int k = 0; k < nr; ++k) t[IDX(P, k, i)] = x[k];
+    }
+    /* corrected currents */
+    op_dr_minus(P, a, nd, pS, t, e);
+    for (int k = 0; k < nr; ++k)
+        for (int i = 0; i < nz; ++i) {
+            const size_t q = IDX(P, k, i);
+            if (k >= 1) jbar[q] += e[q];
+            jbar[n + q] += (I * m / ((k + 0.5) * P->dr)) * t[q];
+        }
+    free(dv); free(t); free(e); free(A); free(x); free(M);
+    return 0;
+}
+
+static int step_impl(const oracle_problem *P, double complex *psi, const double complex *j, int64_t j_stride,
+                     int n_steps, int corrected);
+
 /* One or more midpoint exponential steps (section 2.1 midpoint solution, Taylor sums of
  * section 2.5):  psi' = sum_n (dt^n/n!) H^n psi  -  dt * sum_n ((dt/2)^n/n!) H^n Jbar. */
 int oracle_step(const oracle_problem *P, double complex *psi, const double complex *j,
                 int64_t j_stride, int n_steps)
+{
+    return step_impl(P, psi, j, j_stride, n_steps, 0);
+}
+
+/* The same with the current correction of section 3.7 applied to Jbar every step; a block of j holds
+ * four planes: J_rho, J_theta, J_z and the planar density differential rho_xy. */
+int oracle_step_corrected(const oracle_problem *P, double complex *psi, const double complex *j,
+                          int64_t j_stride, int n_steps)
+{
+    return step_impl(P, psi, j, j_stride, n_steps, 1);
+}
+
+static int step_impl(const oracle_problem *P, double complex *psi, const double complex *j, int64_t j_stride,
+                     int n_steps, int corrected)
 {
     if (check_problem(P) || P->taylor_order < 1 || n_steps < 0) return -1;
     const size_t n = (size_t)P->nr * P->nz, n6 = 6 * n;
@@ -540,6 +641,7 @@ int oracle_step(const oracle_problem *P, double complex *psi, const double compl
             const cplx *js = j + (size_t)(j_stride * step);
             memset(term, 0, n6 * sizeof(cplx));
             oracle_stage_current(P, js, term);
+            if (corrected) oracle_correct_current(P, term, js + 3 * n);
             memcpy(usum, term, n6 * sizeof(cplx));
             for (int k = 1; k <= N; ++k) {
                 oracle_apply_H(P, term, next);

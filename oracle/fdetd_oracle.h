@@ -65,6 +65,13 @@ int oracle_set_axis(const oracle_problem *P, double complex *psi);
 int oracle_step(const oracle_problem *P, double complex *psi, const double complex *j,
                 int64_t j_stride, int n_steps);
 
+/* Current correction of section 3.7 on a staged current jbar (3 planes, J_rho staggered) with the planar
+ * density differential rho_xy; in place.  oracle_step_corrected: steps whose current blocks hold four
+ * planes (J_rho, J_theta, J_z, rho_xy), corrected after staging. */
+int oracle_correct_current(const oracle_problem *P, double complex *jbar, const double complex *rho_xy);
+int oracle_step_corrected(const oracle_problem *P, double complex *psi, const double complex *j,
+                          int64_t j_stride, int n_steps);
+
 /* --- laser envelope (section 4) --- */
 int oracle_apply_Ha(const oracle_problem *P, const double complex *a, const double complex *at,
                     const double *chi, double complex *out_a, double complex *out_at);
