@@ -65,6 +65,8 @@ extern "C" {
 #define FDETD_PLAN_PROFILE        4u  /* time every stage kernel with HIP events (not with USE_GRAPH)  */
 #define FDETD_PLAN_NO_AUTOTUNE    8u  /* keep the default tiling instead of timing candidates at plan time */
 #define FDETD_PLAN_ONE_STREAM    16u  /* enqueue every launch on the plan's stream (no side streams)    */
+#define FDETD_PLAN_CURRENT_CORRECTION 32u /* Maxwell: current blocks carry rho_xy; fdetd_step corrects the
+                                             staged current every step (section 3.7, see fdetd_step)      */
 
 typedef struct fdetd_plan_s *fdetd_plan_t;
 
@@ -129,9 +131,17 @@ FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32
  *           compensation is reset to zero whenever a psi pointer differs from the previous call's,
  *           except on the first call after fdetd_import_state, which adopts the imported words.
  *   j_half  NULL (no current) or n_probs device pointers to 3-plane currents at t + dt/2.
- *   j_step_blocks  distance between the currents of consecutive steps, in 3-plane blocks of that
- *           problem: step s uses the block starting at j_half[p] + s * j_step_blocks * 3 * nr_p * nz_p
- *           complex values (1: one block per step stored back to back; 0: one current for all steps).
+ *   j_step_blocks  distance between the currents of consecutive steps, in blocks of that problem: step s
+ *           uses the block starting at j_half[p] + s * j_step_blocks * B * nr_p * nz_p complex values,
+ *           B = 3 planes, or 4 with FDETD_PLAN_CURRENT_CORRECTION (1: one block per step stored back to
+ *           back; 0: one current for all steps).
+ *   FDETD_PLAN_CURRENT_CORRECTION: each block holds a fourth plane, the planar density differential
+ *           rho_xy of section 3.7 (primary grid), and after staging every step applies the current
+ *           correction of section 3.7:  d = rho_xy - D_div^(+,mS) Jbar_rho - (i m / rho) J_theta,
+ *           [L_rho^(mS) - m^2/rho^2] phi = d per z column (L_rho of the centred differences of section
+ *           2.3; the plan factors it once, LU without pivoting, FP64), Jbar_rho += D_rho^(-,mS) phi on the
+ *           rows k >= 1 and J_theta += (i m / rho) phi (into a plan-owned plane; the caller's current is
+ *           only read).  FP64 arithmetic in both precisions.
  *   n_steps >= 0.
  * Enqueue only.  Error (nothing enqueued) on NULL or misaligned pointers or a plan of the wrong kind. */
 FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_blocks,

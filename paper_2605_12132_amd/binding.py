@@ -19,6 +19,7 @@ FDETD_OK, FDETD_E_ARG, FDETD_E_UNSTABLE, FDETD_E_NOMEM, FDETD_E_HIP = 0, -1, -2,
 FP64, FP32C = 0, 1
 MAXWELL, ENVELOPE = 0, 1
 PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_STREAM = 1, 2, 4, 8, 16
+PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_deposit_rho",
@@ -195,6 +196,7 @@ class Plan:
             raise RuntimeError("FDETD needs a gfx950 GPU; none is visible")
         self.problems = list(problems)
         self.precision = precision
+        self.flags = flags
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h = fdetd_plan(self.problems, precision, flags, self.stream.cuda_stream)
 
@@ -219,7 +221,8 @@ class Plan:
 
     def step(self, psi, j_half=None, n_steps: int = 1):
         """psi: list of [6, nr, nz] tensors; j_half: None, list of [3, nr, nz] (same current every step)
-        or [n_steps, 3, nr, nz] (one current per step)."""
+        or [n_steps, 3, nr, nz] (one current per step); 4 planes instead of 3 (J_rho, J_theta, J_z,
+        rho_xy) with PLAN_CURRENT_CORRECTION."""
         cd = self._cdtype()
         self._nchk(psi, "psi")
         if j_half is not None:
@@ -227,7 +230,8 @@ class Plan:
         pp = [self._chk(x, (6, p.nr, p.nz), cd, "psi") for x, p in zip(psi, self.problems)]
         jp, stride = None, 0
         if j_half is not None:
-            jp = [self._chk(x, (3, p.nr, p.nz), cd, "j_half") for x, p in zip(j_half, self.problems)]
+            nb = 4 if self.flags & PLAN_CURRENT_CORRECTION else 3  # J_rho, J_theta, J_z (, rho_xy)
+            jp = [self._chk(x, (nb, p.nr, p.nz), cd, "j_half") for x, p in zip(j_half, self.problems)]
             dims = {x.dim() for x in j_half}
             if len(dims) != 1 or dims - {3, 4}:
                 raise ValueError("j_half: all [3, nr, nz] or all [steps, 3, nr, nz]")

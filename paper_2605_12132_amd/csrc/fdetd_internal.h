@@ -93,6 +93,8 @@ struct ProbDesc {
     const void *jbar;                        // staggered J_rho plane
     float *lo;                               // FP32C compensation words
     const double *rinv_p, *rinv_s, *m2rinv2;
+    const void *jth;                         // current correction: the corrected J_theta plane the stages read
+                                             // instead of the caller's (null without correction)
     const double *sz, *sr;                   // envelope absorbing layer: sigma_z per column, sigma_rho per
                                              // row (all zero without a layer); null for Maxwell problems
     double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
@@ -152,6 +154,23 @@ struct DepositArgs {
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
+// Current correction (section 3.7) of one problem's staged current, three launches:
+//   div:   d = rho_xy - D_div^(+,mS) Jbar_rho - (i m / rho) J_theta            -> work (double2 plane)
+//   solve: [L_rho^(mS) - m^2/rho^2] phi = d per z column with the plan-time LU factors (no pivoting)
+//   apply: Jbar_rho += D_rho^(-,mS) phi (rows >= 1, in place), J_theta~ = J_theta + (i m / rho) phi -> jth
+struct CorrectArgs {
+    void *jbar;              // staged J_rho (storage precision), corrected in place
+    const void *jth_in;      // the caller's J_theta plane
+    const void *rho_xy;      // the caller's planar density differential plane
+    void *jth_out;           // corrected J_theta (storage precision)
+    double2 *work;           // d, then phi (FP64)
+    const double *band;      // nr x (2 nd + 1): L below the diagonal, 1/U_kk on it, U above it
+    int nz, nr, nd, m, parity;  // parity: m_S sign
+    double dr;
+    double a[kMaxND];        // staggered first-derivative weights a_j
+};
+hipError_t launch_correct_current(int prec, const CorrectArgs &a, hipStream_t s);
+
 // Field interpolation (section 3.3).  Destaggering of one plane to the primary grid: along z (S_z^(+),
 // columns outside the grid 0) or along rho (S_rho^(+) with the operand's parity and axis rule).
 struct DestaggerArgs {

@@ -543,6 +543,127 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
 }
 
 // --------------------------------------------------------------------------------------------------
+// Current correction (section 3.7).  FP64 arithmetic throughout; J in the storage precision.
+// --------------------------------------------------------------------------------------------------
+template <typename R>
+struct cplx_of { using V = double2; };
+template <>
+struct cplx_of<float> { using V = float2; };
+template <typename V>
+__device__ __forceinline__ double2 ld2(const V *p, size_t q)
+{
+    const V v = p[q];
+    return double2{(double)v.x, (double)v.y};
+}
+
+// d(k, i) = rho_xy - rho_k^-1 sum_j a_j (g(k + j) - g(k - j + 1)) / dr - (i m / rho_k) J_theta,
+// g(q) = q dr Jbar_rho(q) on the staggered rows, 0 on the axis, parity * g(-q) below it, 0 from nr on.
+template <typename R>
+__global__ __launch_bounds__(256) void k_corr_div(CorrectArgs A)
+{
+    using V = typename cplx_of<R>::V;
+    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (i >= A.nz) return;
+    const V *jr = (const V *)A.jbar;
+    auto g = [&](int q) -> double2 {
+        if (q == 0 || q >= A.nr || -q >= A.nr) return double2{0.0, 0.0};
+        const int qq = q < 0 ? -q : q;
+        const double2 v = ld2(jr, (size_t)qq * A.nz + i);
+        const double f = (q < 0 ? (double)A.parity : 1.0) * qq * A.dr;
+        return double2{f * v.x, f * v.y};
+    };
+    double sx = 0.0, sy = 0.0;
+    for (int j = 1; j <= A.nd; ++j) {
+        const double2 p = g(k + j), q = g(k - j + 1);
+        sx += A.a[j - 1] * (p.x - q.x);
+        sy += A.a[j - 1] * (p.y - q.y);
+    }
+    const double rho = (k + 0.5) * A.dr;
+    const size_t o = (size_t)k * A.nz + i;
+    const double2 t = ld2((const V *)A.jth_in, o), r = ld2((const V *)A.rho_xy, o);
+    const double mr = A.m / rho;
+    // (i m / rho) (tx + i ty) = (-mr ty, mr tx)
+    A.work[o] = double2{r.x - sx / (A.dr * rho) + mr * t.y, r.y - sy / (A.dr * rho) - mr * t.x};
+}
+
+// One thread per z column: forward substitution with the unit lower factor, then backward with the upper
+// factor, the last ND values of each pass held in registers; y overwrites d, x overwrites y.
+template <int ND>
+__global__ __launch_bounds__(256) void k_corr_solve(CorrectArgs A)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.nz) return;
+    constexpr int W = 2 * ND + 1;
+    double2 win[ND];
+#pragma unroll
+    for (int t = 0; t < ND; ++t) win[t] = double2{0.0, 0.0};  // win[t] = y(k - 1 - t)
+    for (int k = 0; k < A.nr; ++k) {
+        const double *row = A.band + (size_t)k * W;
+        double2 y = A.work[(size_t)k * A.nz + i];
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const double l = row[ND - j];  // L(k, k - j), 0 before row 0
+            y.x -= l * win[j - 1].x;
+            y.y -= l * win[j - 1].y;
+        }
+        A.work[(size_t)k * A.nz + i] = y;
+#pragma unroll
+        for (int t = ND - 1; t > 0; --t) win[t] = win[t - 1];
+        win[0] = y;
+    }
+#pragma unroll
+    for (int t = 0; t < ND; ++t) win[t] = double2{0.0, 0.0};  // win[t] = x(k + 1 + t)
+    for (int k = A.nr - 1; k >= 0; --k) {
+        const double *row = A.band + (size_t)k * W;
+        double2 x = A.work[(size_t)k * A.nz + i];
+#pragma unroll
+        for (int j = 1; j <= ND; ++j) {
+            const double u = row[ND + j];  // U(k, k + j), 0 past the last row
+            x.x -= u * win[j - 1].x;
+            x.y -= u * win[j - 1].y;
+        }
+        x.x *= row[ND];
+        x.y *= row[ND];
+        A.work[(size_t)k * A.nz + i] = x;
+#pragma unroll
+        for (int t = ND - 1; t > 0; --t) win[t] = win[t - 1];
+        win[0] = x;
+    }
+}
+
+// Jbar_rho(k) += sum_j a_j (phi(k + j - 1) - phi(k - j)) / dr on the staggered rows k >= 1 (phi on the
+// primary rows, parity * phi(-1-q) below the axis, 0 from nr on);  J_theta~ = J_theta + (i m / rho) phi.
+template <typename R>
+__global__ __launch_bounds__(256) void k_corr_apply(CorrectArgs A)
+{
+    using V = typename cplx_of<R>::V;
+    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (i >= A.nz) return;
+    auto phi = [&](int q) -> double2 {
+        const int qq = q < 0 ? -1 - q : q;
+        if (qq >= A.nr) return double2{0.0, 0.0};
+        const double2 v = A.work[(size_t)qq * A.nz + i];
+        const double sg = q < 0 ? (double)A.parity : 1.0;
+        return double2{sg * v.x, sg * v.y};
+    };
+    const size_t o = (size_t)k * A.nz + i;
+    if (k >= 1) {
+        double sx = 0.0, sy = 0.0;
+        for (int j = 1; j <= A.nd; ++j) {
+            const double2 p = phi(k + j - 1), q = phi(k - j);
+            sx += A.a[j - 1] * (p.x - q.x);
+            sy += A.a[j - 1] * (p.y - q.y);
+        }
+        V *jr = (V *)A.jbar;
+        const double2 v = ld2(jr, o);
+        jr[o] = V{(R)(v.x + sx / A.dr), (R)(v.y + sy / A.dr)};
+    }
+    const double mr = A.m / ((k + 0.5) * A.dr);
+    const double2 t = ld2((const V *)A.jth_in, o), f = A.work[o];
+    ((V *)A.jth_out)[o] = V{(R)(t.x - mr * f.y), (R)(t.y + mr * f.x)};
+}
+
+// --------------------------------------------------------------------------------------------------
 // Field interpolation (section 3.3).  Destaggering, one thread per output cell:
 //   along z:   out(k, i) = sum_j s_j (f(k, i + j) + f(k, i - j + 1)),  columns outside [0, nz) are 0;
 //   along rho: out(k, i) = sum_j s_j (f(k + j, i) + f(k - j + 1, i)) on the staggered rows, row 0 = the
@@ -653,6 +774,23 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A)
 }
 
 }  // namespace
+
+hipError_t launch_correct_current(int prec, const CorrectArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr), cols((unsigned)((a.nz + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_corr_div<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_corr_div<float>, grid, dim3(256), 0, s, a);
+    switch (a.nd) {
+#define C_(N) \
+    case N: hipLaunchKernelGGL(k_corr_solve<N>, cols, dim3(256), 0, s, a); break;
+        C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10) C_(11) C_(12) C_(13) C_(14) C_(15) C_(16)
+#undef C_
+    default: return hipErrorInvalidValue;
+    }
+    if (prec == P64) hipLaunchKernelGGL(k_corr_apply<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_corr_apply<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)
 {

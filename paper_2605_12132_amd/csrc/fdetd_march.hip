@@ -717,7 +717,7 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.has_src = A.has_src;
     const size_t pb = D.plane * sizeof(typename stor<V>::T);
     C.jr = A.has_src ? D.jbar : nullptr;
-    C.jt = A.has_src ? (const char *)A.aux[p] + pb : nullptr;
+    C.jt = A.has_src ? (D.jth ? D.jth : (const char *)A.aux[p] + pb) : nullptr;  // corrected J_theta if any
     C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
     C.compensated = A.compensated && A.n == 0;
     C.beta_in = A.beta_in;

@@ -40,6 +40,8 @@ struct Prob {
     float *lo = nullptr;        // FP32C compensation words (6 or 2 planes of float2)
     double *rinv_p = nullptr, *rinv_s = nullptr, *m2rinv2 = nullptr;
     double *sz = nullptr, *sr = nullptr;  // envelope absorbing layer: sigma per column and per row
+    double *band = nullptr;               // current correction: LU factors of the radial operator
+    void *jth = nullptr;                  // current correction: corrected J_theta plane
     int lz = 0, lr = 0;                   // its widths (0, 0: no layer)
     double a[kMaxND], s[kMaxND], d1[kMaxND], d2[kMaxND + 1], c[kMaxND];
     const void *last_state = nullptr;   // psi (or a) of the previous call, for the FP32C reset rule
@@ -127,6 +129,8 @@ void free_prob(Prob &q)
     if (q.rinv_s) (void)hipFree(q.rinv_s);
     if (q.m2rinv2) (void)hipFree(q.m2rinv2);
     if (q.sz) (void)hipFree(q.sz);
+    if (q.band) (void)hipFree(q.band);
+    if (q.jth) (void)hipFree(q.jth);
     if (q.sr) (void)hipFree(q.sr);
     q = Prob{};
 }
@@ -230,6 +234,29 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         cells += P->probs[b.members[t]].cells;
     }
     if (j && b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, s));
+    if (j && (P->flags & FDETD_PLAN_CURRENT_CORRECTION)) {
+        for (int t = 0; t < b.count; ++t) {
+            const int p = b.members[t];
+            const Prob &q = P->probs[p];
+            const size_t pb = q.cells * eb;
+            CorrectArgs X;
+            std::memset(&X, 0, sizeof X);
+            X.jbar = q.jbar;
+            X.jth_in = (const char *)j[p] + pb;
+            X.rho_xy = (const char *)j[p] + 3 * pb;
+            X.jth_out = q.jth;
+            X.work = (double2 *)q.buf[1];  // free until the second stage; holds >= 16 B per cell
+            X.band = q.band;
+            X.nz = q.d.nz;
+            X.nr = q.d.nr;
+            X.nd = q.nd;
+            X.m = q.d.m;
+            X.parity = parity_mS(q.d.m);
+            X.dr = q.d.dr;
+            for (int u = 0; u < q.nd; ++u) X.a[u] = q.a[u];
+            HIPCHK(P, launch_correct_current(prec, X, s));
+        }
+    }
     A.N = b.N;
     A.has_src = j != nullptr;
     A.compensated = P->precision == FDETD_FP32C;
@@ -327,6 +354,45 @@ int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void 
         }
     }
     return damp_layers(P, b, a, at, s);  // second factor
+}
+
+// Planes of one current block: J_rho, J_theta, J_z, and with the current correction rho_xy.
+int cur_planes(const fdetd_plan_t P) { return (P->flags & FDETD_PLAN_CURRENT_CORRECTION) ? 4 : 3; }
+
+// LU factors (no pivoting) of the radial operator L_rho^(mS) - m^2/rho^2 of section 3.7 on nr primary
+// rows, as rows of 2 nd + 1: L(k, k - j) at nd - j, 1 / U(k, k) at nd, U(k, k + j) at nd + j.
+// L_rho phi(k) = (b_0 phi_k + sum_j b_j (phi_(k+j) + phi_(k-j))) / dr^2 + sum_j d_j (phi_(k+j) - phi_(k-j)) / (rho_k dr),
+// rows below the axis mirrored with the m_S sign, rows from nr on 0.  False on a vanishing pivot.
+bool radial_lu(const Prob &q, std::vector<double> &band)
+{
+    const int nd = q.nd, nr = q.d.nr, W = 2 * nd + 1, m = q.d.m;
+    const double dr = q.d.dr, ps = parity_mS(m);
+    band.assign((size_t)nr * W, 0.0);
+    auto at = [&](int k, int c) -> double & { return band[(size_t)k * W + nd + (c - k)]; };
+    for (int k = 0; k < nr; ++k) {
+        const double rho = (k + 0.5) * dr;
+        at(k, k) += q.d2[0] / (dr * dr) - (double)m * m / (rho * rho);
+        for (int j = 1; j <= nd; ++j) {
+            const double cp = q.d2[j] / (dr * dr) + q.d1[j - 1] / (rho * dr);
+            const double cm = q.d2[j] / (dr * dr) - q.d1[j - 1] / (rho * dr);
+            if (k + j < nr) at(k, k + j) += cp;
+            const int r = k - j;
+            if (r >= 0) at(k, r) += cm;
+            else if (-1 - r < nr) at(k, -1 - r) += ps * cm;
+        }
+    }
+    for (int k = 0; k < nr; ++k) {
+        const double piv = at(k, k);
+        if (!(std::fabs(piv) > 1e-300) || !std::isfinite(piv)) return false;
+        const int last = std::min(k + nd, nr - 1);
+        for (int i = k + 1; i <= last; ++i) {
+            const double l = at(i, k) / piv;
+            at(i, k) = l;
+            for (int c = k + 1; c <= last; ++c) at(i, c) -= l * at(k, c);
+        }
+    }
+    for (int k = 0; k < nr; ++k) at(k, k) = 1.0 / at(k, k);
+    return true;
 }
 
 // Launch batches hold disjoint problems, so a call can run them on several streams: the side streams
@@ -474,6 +540,7 @@ int build_batches(fdetd_plan_t P)
             D.rinv_s = q.rinv_s;
             D.m2rinv2 = q.m2rinv2;
             D.sz = q.sz;
+            D.jth = q.jth;
             D.sr = q.sr;
             for (int k = 0; k < q.nd; ++k) {
                 D.az[k] = q.a[k] / q.d.dz;
@@ -863,6 +930,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     }
     if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: graph capture needs a non-default stream");
+    if ((flags & FDETD_PLAN_CURRENT_CORRECTION) && probs[0].kind != FDETD_MAXWELL)
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: the current correction needs Maxwell problems");
     if ((flags & FDETD_PLAN_USE_GRAPH) && (flags & FDETD_PLAN_PROFILE))
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_PROFILE times eager launches only");
     fdetd_plan_t P = new (std::nothrow) fdetd_plan_s;
@@ -919,6 +988,23 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             (q.sr && (e = hipMemset(q.sr, 0, q.d.nr * sizeof(double))))) {
             rc = fail(P, FDETD_E_HIP, "fdetd_plan: problem %d: %s", p, hipGetErrorString(e));
             break;
+        }
+        if (P->kind == FDETD_MAXWELL && (flags & FDETD_PLAN_CURRENT_CORRECTION)) {
+            std::vector<double> band;
+            if (!radial_lu(q, band)) {
+                rc = fail(P, FDETD_E_ARG, "fdetd_plan: problem %d: the radial operator of the current correction is singular", p);
+                break;
+            }
+            if ((e = hipMalloc((void **)&q.band, band.size() * sizeof(double))) || (e = hipMalloc(&q.jth, q.cells * eb)) ||
+                (e = hipMemcpy(q.band, band.data(), band.size() * sizeof(double), hipMemcpyHostToDevice))) {
+                rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
+                          hipGetErrorString(e));
+                break;
+            }
+            scratch += band.size() * sizeof(double) + q.cells * eb;
+            // div: read Jbar_rho, J_theta, rho_xy, write d; solve: d, y, y, phi (FP64); apply: read phi, Jbar_rho,
+            // J_theta, write Jbar_rho, J_theta~
+            bytes_step += (int64_t)q.cells * (8 * eb + 5 * 16);
         }
         const int N = q.d.taylor_order;
         cells += q.cells;
@@ -1209,7 +1295,7 @@ int step_body(fdetd_plan_t P, void *vctx)
     int rc = fork_lanes(P);
     for (int s = 0; s < c.n_steps && !rc; ++s) {
         for (size_t p = 0; p < P->probs.size() && c.j; ++p)
-            js[p] = (const char *)c.j[p] + (size_t)(c.stride * s) * 3 * P->probs[p].cells * eb;
+            js[p] = (const char *)c.j[p] + (size_t)(c.stride * s) * cur_planes(P) * P->probs[p].cells * eb;
         for (size_t b = 0; b < P->batches.size() && !rc; ++b)
             rc = enqueue_maxwell_batch(P, P->batches[b], c.psi, c.j ? js.data() : nullptr, s == c.n_steps - 1,
                                        lane_stream(P, P->batches[b]));

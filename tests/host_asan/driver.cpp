@@ -23,6 +23,7 @@ hipError_t launch_deposit_jz(int, const DepositArgs &, hipStream_t) { return hip
 hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_correct_current(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_gather(int, const GatherArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_norm2(int, const void *, size_t, double *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipErrorInvalidValue; }
@@ -97,6 +98,9 @@ int main()
     fdetd_problem_desc mixed[2] = {good(), good()};
     mixed[1].kind = FDETD_ENVELOPE;
     EXPECT(fdetd_plan(mixed, 2, FDETD_FP64, 0, nullptr, &P) == FDETD_E_ARG && !P);
+    fdetd_problem_desc env = good();
+    env.kind = FDETD_ENVELOPE;
+    EXPECT(fdetd_plan(&env, 1, FDETD_FP64, FDETD_PLAN_CURRENT_CORRECTION, nullptr, &P) == FDETD_E_ARG && !P);
     // calls on a NULL plan
     void *ptrs[1] = {nullptr};
     EXPECT(fdetd_step(nullptr, ptrs, nullptr, 0, 1) == FDETD_E_ARG);

@@ -102,7 +102,8 @@ def test_header_layout_matches_binding(tmp_path):
               "FDETD_MAXWELL": binding.MAXWELL, "FDETD_ENVELOPE": binding.ENVELOPE,
               "FDETD_PLAN_SKIP_STABILITY": binding.PLAN_SKIP_STABILITY, "FDETD_PLAN_USE_GRAPH": binding.PLAN_USE_GRAPH,
               "FDETD_PLAN_PROFILE": binding.PLAN_PROFILE, "FDETD_PLAN_NO_AUTOTUNE": binding.PLAN_NO_AUTOTUNE,
-              "FDETD_PLAN_ONE_STREAM": binding.PLAN_ONE_STREAM}
+              "FDETD_PLAN_ONE_STREAM": binding.PLAN_ONE_STREAM,
+              "FDETD_PLAN_CURRENT_CORRECTION": binding.PLAN_CURRENT_CORRECTION}
     for k in consts:
         lines.append(f'printf("const {k} %lld\\n", (long long)({k}));')
     lines.append("return 0; }")
