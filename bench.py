@@ -354,6 +354,57 @@ def envelope_pass(steps, layer=32):
                 fp32c_rel_l2=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)))
 
 
+def correction_pass(steps, warmup):
+    """The current-driven workload with the current correction of section 3.7 every step
+    (FDETD_PLAN_CURRENT_CORRECTION): current blocks of J_rho, J_theta, J_z and a planar density
+    differential (the bunch + noise recipe for the currents, uniform noise of the same scale for rho_xy),
+    graph replay of `steps` steps, FP64 and FP32C, against the same plans without the correction."""
+    import torch
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+    w = I.current_driven()
+    cells = w.cells()
+    out = {}
+    for tag, prec, cd in (("fp64", F.FP64, torch.complex128), ("fp32c", F.FP32C, torch.complex64)):
+        J = make_currents(w, warmup + steps, cd, w.seed + 7)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(w.seed + 8)
+        J4 = []
+        for j in J:
+            rxy = (torch.rand(j[:, :1].shape, generator=g, device="cuda", dtype=torch.float64) * 2 - 1)
+            rxy = (rxy * w.extra["noise"] * w.extra["nb"]).to(cd)
+            J4.append(torch.cat([j, rxy], dim=1).contiguous())
+            del rxy
+        res = {}
+        for corr in (False, True):
+            stream = torch.cuda.Stream()
+            stream.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(stream):
+                psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+                flags = F.PLAN_USE_GRAPH | (F.PLAN_CURRENT_CORRECTION if corr else 0)
+                plan = F.Plan(w.problems(), precision=prec, flags=flags)
+                cur = J4 if corr else J
+                plan.step(psi, [j[:warmup] for j in cur], n_steps=warmup)
+                jt = [j[warmup:warmup + steps] for j in cur]
+                plan.step(psi, jt, n_steps=steps)  # capture + first replay (untimed)
+                torch.cuda.synchronize()
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                plan.step(psi, jt, n_steps=steps)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1)
+                plan.close()
+            res[corr] = ms / steps
+        del J, J4
+        torch.cuda.empty_cache()
+        out[tag] = dict(value=cells * steps / (res[True] * steps * 1e-3), ms_per_step=res[True],
+                        ms_per_step_without=res[False], overhead=res[True] / res[False] - 1.0)
+        log(f"correction {tag}: {res[True]:.4f} ms/step with, {res[False]:.4f} without")
+    return dict(workload=w.name + "_corrected", cells=cells, steps=steps, graph=True, fp64=out["fp64"],
+                fp32c=out["fp32c"])
+
+
 def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
@@ -439,6 +490,8 @@ def main():
                     help="steps of the 64-problem batched workload reported beside the headline (0: skip)")
     ap.add_argument("--lwfa-steps", type=int, default=20,
                     help="steps of the LWFA-scale workload reported beside the headline (0: skip)")
+    ap.add_argument("--correction-steps", type=int, default=50,
+                    help="steps of the current-driven workload with the current correction (0: skip)")
     ap.add_argument("--envelope-steps", type=int, default=2000,
                     help="steps of the envelope workload reported beside the headline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -498,6 +551,8 @@ def main():
         batched = batched_pass(args.batched_steps, W)
     envelope = envelope_pass(args.envelope_steps) if args.envelope_steps > 0 and not args.fp64_only else None
     lwfa = lwfa_pass(args.lwfa_steps, W) if args.lwfa_steps > 0 and not args.fp64_only else None
+    correction = (correction_pass(args.correction_steps, W)
+                  if args.correction_steps > 0 and not args.fp64_only else None)
     cpu = None if args.no_cpu else cpu_baseline(w)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
@@ -515,6 +570,7 @@ def main():
         "batched": batched,
         "envelope": envelope,
         "lwfa": lwfa,
+        "correction": correction,
     }
     print(json.dumps(out), flush=True)
 

@@ -154,7 +154,7 @@ struct DepositArgs {
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
-// Current correction (section 3.7) of one problem's staged current, three launches:
+// Current correction (section 3.7) of one problem's staged current, three steps:
 //   div:   d = rho_xy - D_div^(+,mS) Jbar_rho - (i m / rho) J_theta            -> work (double2 plane)
 //   solve: [L_rho^(mS) - m^2/rho^2] phi = d per z column with the plan-time LU factors (no pivoting)
 //   apply: Jbar_rho += D_rho^(-,mS) phi (rows >= 1, in place), J_theta~ = J_theta + (i m / rho) phi -> jth
@@ -169,7 +169,24 @@ struct CorrectArgs {
     double dr;
     double a[kMaxND];        // staggered first-derivative weights a_j
 };
-hipError_t launch_correct_current(int prec, const CorrectArgs &a, hipStream_t s);
+hipError_t launch_correct_div(int prec, const CorrectArgs &a, hipStream_t s);
+hipError_t launch_correct_apply(int prec, const CorrectArgs &a, hipStream_t s);
+// The banded solves of up to kMaxSolve problems of one N_D.  Each column's rows are split into segments
+// solved in parallel from a zero start (the partition method), then a sequential sweep over the segments
+// forms the true values at each segment boundary from precomputed responses, and a last parallel pass adds
+// each segment's response to its boundary values.  Forward (L) then backward (U) substitution.
+constexpr int kMaxSolve = 16;
+struct SolveArgs {
+    int nprob, nd, smax;  // problems, N_D, most segments of a problem
+    struct {
+        double2 *work;          // d, then y, then x (in place)
+        double2 *wbuf;          // boundary values: [segment][nd][nz]
+        const double *band;     // LU factors: rows of 2 nd + 1 (L below the diagonal, 1/U_kk, U above)
+        const double *gf, *gb;  // responses [nr][nd] of a segment's rows to a unit value of boundary t
+        int nz, nr, seg, nseg;  // rows per segment, segments
+    } p[kMaxSolve];
+};
+hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s);
 
 // Field interpolation (section 3.3).  Destaggering of one plane to the primary grid: along z (S_z^(+),
 // columns outside the grid 0) or along rho (S_rho^(+) with the operand's parity and axis rule).

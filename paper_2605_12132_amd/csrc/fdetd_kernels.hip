@@ -586,48 +586,161 @@ __global__ __launch_bounds__(256) void k_corr_div(CorrectArgs A)
     A.work[o] = double2{r.x - sx / (A.dr * rho) + mr * t.y, r.y - sy / (A.dr * rho) - mr * t.x};
 }
 
-// One thread per z column: forward substitution with the unit lower factor, then backward with the upper
-// factor, the last ND values of each pass held in registers; y overwrites d, x overwrites y.
-template <int ND>
-__global__ __launch_bounds__(256) void k_corr_solve(CorrectArgs A)
+// Lane `lane` of a double held across the wave, as a wave-uniform value (two v_readlane into scalars).
+__device__ __forceinline__ double readlane_d(double x, int lane)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= A.nz) return;
-    constexpr int W = 2 * ND + 1;
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Banded triangular solves of the current correction, one thread per z column and row segment.
+// Forward: y_k = d_k - sum_j L(k, k-j) y_(k-j); backward: x_k = (y_k - sum_j U(k, k+j) x_(k+j)) / U(k, k).
+// Boundary value t of a segment [a, b): forward y(a - 1 - t), backward x(b + t), t < N_D.
+//
+// k_seg_solve: each segment from a zero boundary, in place.  Every column uses the same factors: a
+// wavefront loads those of a chunk of CH rows spread over its lanes and takes each as a wave-uniform
+// scalar with v_readlane; two chunk buffers are refilled in place a chunk ahead (no register moves of
+// loads in flight, so no wait covers the stores issued after them).  Loads read clamped rows
+// unconditionally (a branch around a load would make the wave wait for it); words and values of rows
+// outside the segment are never used.  Block (x, y, z): columns, problem y, segment z.
+template <int ND>
+__global__ __launch_bounds__(256) void k_seg_solve(SolveArgs S, int fwd)
+{
+    constexpr int CH = 16, W = 2 * ND + 1, WORDS = CH * W, NREG = (WORDS + 63) / 64;
+    const auto &P = S.p[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x % 64, sg = blockIdx.z;
+    if (sg >= P.nseg || i - lane >= P.nz) return;  // the whole wavefront is idle
+    const bool active = i < P.nz;                   // the others read column 0 and store nothing
+    const int nr = P.nr, a = sg * P.seg, b = min(nr, a + P.seg), nchunk = (b - a + CH - 1) / CH;
+    const size_t nz = (size_t)P.nz;
+    double2 *col = P.work + (active ? i : 0);
+    const double *band = P.band;
+    auto row_of = [&](int c, int r) { return fwd ? a + c * CH + r : b - 1 - c * CH - r; };
+    auto clamp_row = [&](int k) { return k < 0 ? 0 : (k >= nr ? nr - 1 : k); };
+    auto load = [&](int c, double2 (&v)[CH], double (&w)[NREG]) {
+#pragma unroll
+        for (int u = 0; u < NREG; ++u) {
+            const int e = lane + 64 * u;
+            const int ec = e < WORDS ? e : WORDS - 1;
+            w[u] = band[(size_t)clamp_row(row_of(c, ec / W)) * W + ec % W];
+        }
+#pragma unroll
+        for (int r = 0; r < CH; ++r) v[r] = col[clamp_row(row_of(c, r)) * nz];
+    };
     double2 win[ND];
 #pragma unroll
-    for (int t = 0; t < ND; ++t) win[t] = double2{0.0, 0.0};  // win[t] = y(k - 1 - t)
-    for (int k = 0; k < A.nr; ++k) {
-        const double *row = A.band + (size_t)k * W;
-        double2 y = A.work[(size_t)k * A.nz + i];
+    for (int t = 0; t < ND; ++t) win[t] = double2{0.0, 0.0};  // forward: y(k - 1 - t); backward: x(k + 1 + t)
+    auto solve = [&](int c, const double2 (&vals)[CH], const double (&cw)[NREG]) {
 #pragma unroll
-        for (int j = 1; j <= ND; ++j) {
-            const double l = row[ND - j];  // L(k, k - j), 0 before row 0
-            y.x -= l * win[j - 1].x;
-            y.y -= l * win[j - 1].y;
+        for (int r = 0; r < CH; ++r) {
+            const int k = row_of(c, r);
+            if (k < a || k >= b) continue;  // uniform: the same rows for every lane
+            auto coef = [&](int t) { return readlane_d(cw[(r * W + t) / 64], (r * W + t) % 64); };
+            // the older taps first, in two partial sums; the newest value enters last
+            double2 v = vals[r], h = double2{0.0, 0.0};
+#pragma unroll
+            for (int j = ND; j >= 2; --j) {
+                const double f = coef(fwd ? ND - j : ND + j);  // L(k, k - j) or U(k, k + j)
+                double2 &acc = (j & 1) ? v : h;
+                acc.x -= f * win[j - 1].x;
+                acc.y -= f * win[j - 1].y;
+            }
+            v.x += h.x;
+            v.y += h.y;
+            const double f1 = coef(fwd ? ND - 1 : ND + 1);
+            v.x -= f1 * win[0].x;
+            v.y -= f1 * win[0].y;
+            if (!fwd) {
+                const double d = coef(ND);
+                v.x *= d;
+                v.y *= d;
+            }
+            if (active) col[k * nz] = v;
+#pragma unroll
+            for (int t = ND - 1; t > 0; --t) win[t] = win[t - 1];
+            win[0] = v;
         }
-        A.work[(size_t)k * A.nz + i] = y;
-#pragma unroll
-        for (int t = ND - 1; t > 0; --t) win[t] = win[t - 1];
-        win[0] = y;
+    };
+    double2 va[CH], vb[CH];
+    double wa[NREG], wb[NREG];
+    load(0, va, wa);
+    for (int c = 0; c < nchunk; c += 2) {
+        load(c + 1, vb, wb);
+        solve(c, va, wa);
+        load(c + 2, va, wa);
+        if (c + 1 < nchunk) solve(c + 1, vb, wb);
     }
+}
+
+// k_seg_fix: one thread per column sweeps the segments in the order of the pass and writes the true
+// boundary values of each (but the first) to wbuf: those of the segment before it (forward) or after it
+// (backward), formed as the zero-start value plus that segment's response to its own boundary values.
+template <int ND>
+__global__ __launch_bounds__(256) void k_seg_fix(SolveArgs S, int fwd)
+{
+    const auto &P = S.p[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= P.nz) return;
+    const int nr = P.nr, seg = P.seg, ns = P.nseg;
+    const size_t nz = (size_t)P.nz;
+    const double *G = fwd ? P.gf : P.gb;
+    double2 w[ND];  // boundary values of the segment the sweep has just passed
 #pragma unroll
-    for (int t = 0; t < ND; ++t) win[t] = double2{0.0, 0.0};  // win[t] = x(k + 1 + t)
-    for (int k = A.nr - 1; k >= 0; --k) {
-        const double *row = A.band + (size_t)k * W;
-        double2 x = A.work[(size_t)k * A.nz + i];
+    for (int t = 0; t < ND; ++t) w[t] = double2{0.0, 0.0};
+    for (int step = 1; step < ns; ++step) {
+        const int sg = fwd ? step : ns - 1 - step;   // segment whose boundary values are formed
+        const int src = fwd ? sg - 1 : sg + 1;        // the segment they lie in
+        const bool src_has = fwd ? src >= 1 : src <= ns - 2;  // src itself has boundary values
+        double2 nw[ND];
 #pragma unroll
-        for (int j = 1; j <= ND; ++j) {
-            const double u = row[ND + j];  // U(k, k + j), 0 past the last row
-            x.x -= u * win[j - 1].x;
-            x.y -= u * win[j - 1].y;
+        for (int t = 0; t < ND; ++t) {
+            const int k = fwd ? sg * seg - 1 - t : (sg + 1) * seg + t;
+            double2 v = double2{0.0, 0.0};
+            if (k >= 0 && k < nr) {
+                v = P.work[(size_t)k * nz + i];
+                if (src_has) {
+#pragma unroll
+                    for (int u = 0; u < ND; ++u) {
+                        const double g = G[(size_t)k * ND + u];
+                        v.x += g * w[u].x;
+                        v.y += g * w[u].y;
+                    }
+                }
+            }
+            nw[t] = v;
         }
-        x.x *= row[ND];
-        x.y *= row[ND];
-        A.work[(size_t)k * A.nz + i] = x;
 #pragma unroll
-        for (int t = ND - 1; t > 0; --t) win[t] = win[t - 1];
-        win[0] = x;
+        for (int t = 0; t < ND; ++t) {
+            w[t] = nw[t];
+            P.wbuf[((size_t)sg * ND + t) * nz + i] = nw[t];
+        }
+    }
+}
+
+// k_seg_apply: rows of every segment but the first of the pass += response x boundary values.
+template <int ND>
+__global__ __launch_bounds__(256) void k_seg_apply(SolveArgs S, int fwd)
+{
+    const auto &P = S.p[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x, sg = blockIdx.z;
+    if (sg >= P.nseg || i >= P.nz || sg == (fwd ? 0 : P.nseg - 1)) return;
+    const int a = sg * P.seg, b = min(P.nr, a + P.seg);
+    const size_t nz = (size_t)P.nz;
+    const double *G = fwd ? P.gf : P.gb;
+    double2 w[ND];
+#pragma unroll
+    for (int t = 0; t < ND; ++t) w[t] = P.wbuf[((size_t)sg * ND + t) * nz + i];
+    for (int k = a; k < b; ++k) {
+        double2 v = P.work[(size_t)k * nz + i];
+#pragma unroll
+        for (int u = 0; u < ND; ++u) {
+            const double g = G[(size_t)k * ND + u];
+            v.x += g * w[u].x;
+            v.y += g * w[u].y;
+        }
+        P.work[(size_t)k * nz + i] = v;
     }
 }
 
@@ -775,21 +888,49 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A)
 
 }  // namespace
 
-hipError_t launch_correct_current(int prec, const CorrectArgs &a, hipStream_t s)
+hipError_t launch_correct_div(int prec, const CorrectArgs &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr), cols((unsigned)((a.nz + 255) / 256));
+    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr);
     if (prec == P64) hipLaunchKernelGGL(k_corr_div<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_corr_div<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_apply(int prec, const CorrectArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr);
+    if (prec == P64) hipLaunchKernelGGL(k_corr_apply<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_corr_apply<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ND>
+hipError_t correct_solve_nd(const SolveArgs &a, hipStream_t s)
+{
+    int nzmax = 0;
+    for (int p = 0; p < a.nprob; ++p) nzmax = a.p[p].nz > nzmax ? a.p[p].nz : nzmax;
+    const unsigned bx = (unsigned)((nzmax + 255) / 256);
+    const dim3 seg(bx, (unsigned)a.nprob, (unsigned)a.smax), cols(bx, (unsigned)a.nprob);
+    for (int fwd = 1; fwd >= 0; --fwd) {
+        hipLaunchKernelGGL(k_seg_solve<ND>, seg, dim3(256), 0, s, a, fwd);
+        if (a.smax > 1) {
+            hipLaunchKernelGGL(k_seg_fix<ND>, cols, dim3(256), 0, s, a, fwd);
+            hipLaunchKernelGGL(k_seg_apply<ND>, seg, dim3(256), 0, s, a, fwd);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s)
+{
+    if (a.nprob <= 0) return hipSuccess;
     switch (a.nd) {
 #define C_(N) \
-    case N: hipLaunchKernelGGL(k_corr_solve<N>, cols, dim3(256), 0, s, a); break;
+    case N: return correct_solve_nd<N>(a, s);
         C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10) C_(11) C_(12) C_(13) C_(14) C_(15) C_(16)
 #undef C_
     default: return hipErrorInvalidValue;
     }
-    if (prec == P64) hipLaunchKernelGGL(k_corr_apply<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_corr_apply<float>, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
 }
 
 hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)

@@ -41,6 +41,8 @@ struct Prob {
     double *rinv_p = nullptr, *rinv_s = nullptr, *m2rinv2 = nullptr;
     double *sz = nullptr, *sr = nullptr;  // envelope absorbing layer: sigma per column and per row
     double *band = nullptr;               // current correction: LU factors of the radial operator
+    double *gresp = nullptr;              // ... segment responses, forward then backward ([nr][nd] each)
+    int seg = 0, nseg = 0;                // ... rows per segment of the partitioned solve, segments
     void *jth = nullptr;                  // current correction: corrected J_theta plane
     int lz = 0, lr = 0;                   // its widths (0, 0: no layer)
     double a[kMaxND], s[kMaxND], d1[kMaxND], d2[kMaxND + 1], c[kMaxND];
@@ -130,6 +132,7 @@ void free_prob(Prob &q)
     if (q.m2rinv2) (void)hipFree(q.m2rinv2);
     if (q.sz) (void)hipFree(q.sz);
     if (q.band) (void)hipFree(q.band);
+    if (q.gresp) (void)hipFree(q.gresp);
     if (q.jth) (void)hipFree(q.jth);
     if (q.sr) (void)hipFree(q.sr);
     q = Prob{};
@@ -235,27 +238,44 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     }
     if (j && b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, s));
     if (j && (P->flags & FDETD_PLAN_CURRENT_CORRECTION)) {
+        // divergence error per problem, the banded solves of up to kMaxSolve problems per launch, then the
+        // corrected currents per problem
+        std::vector<CorrectArgs> X(b.count);
+        SolveArgs S;
+        std::memset(&S, 0, sizeof S);
+        S.nd = b.nd;
         for (int t = 0; t < b.count; ++t) {
             const int p = b.members[t];
             const Prob &q = P->probs[p];
             const size_t pb = q.cells * eb;
-            CorrectArgs X;
-            std::memset(&X, 0, sizeof X);
-            X.jbar = q.jbar;
-            X.jth_in = (const char *)j[p] + pb;
-            X.rho_xy = (const char *)j[p] + 3 * pb;
-            X.jth_out = q.jth;
-            X.work = (double2 *)q.buf[1];  // free until the second stage; holds >= 16 B per cell
-            X.band = q.band;
-            X.nz = q.d.nz;
-            X.nr = q.d.nr;
-            X.nd = q.nd;
-            X.m = q.d.m;
-            X.parity = parity_mS(q.d.m);
-            X.dr = q.d.dr;
-            for (int u = 0; u < q.nd; ++u) X.a[u] = q.a[u];
-            HIPCHK(P, launch_correct_current(prec, X, s));
+            CorrectArgs &x = X[t];
+            std::memset(&x, 0, sizeof x);
+            x.jbar = q.jbar;
+            x.jth_in = (const char *)j[p] + pb;
+            x.rho_xy = (const char *)j[p] + 3 * pb;
+            x.jth_out = q.jth;
+            x.work = (double2 *)q.buf[1];  // free until the second stage; holds >= 16 B per cell
+            x.band = q.band;
+            x.nz = q.d.nz;
+            x.nr = q.d.nr;
+            x.nd = q.nd;
+            x.m = q.d.m;
+            x.parity = parity_mS(q.d.m);
+            x.dr = q.d.dr;
+            for (int u = 0; u < q.nd; ++u) x.a[u] = q.a[u];
+            HIPCHK(P, launch_correct_div(prec, x, s));
+            // boundary values of the partitioned solve after the work plane in the same buffer: at most
+            // nseg * nd <= 2 nr rows of 16 B, within the 6 planes of 8 or 16 B it holds
+            S.p[S.nprob] = {x.work, x.work + q.cells, q.band, q.gresp, q.gresp + (size_t)q.d.nr * q.nd, q.d.nz,
+                            q.d.nr, q.seg, q.nseg};
+            S.smax = std::max(S.smax, q.nseg);
+            if (++S.nprob == kMaxSolve || t == b.count - 1) {
+                HIPCHK(P, launch_correct_solve(S, s));
+                S.nprob = 0;
+                S.smax = 0;
+            }
         }
+        for (int t = 0; t < b.count; ++t) HIPCHK(P, launch_correct_apply(prec, X[t], s));
     }
     A.N = b.N;
     A.has_src = j != nullptr;
@@ -393,6 +413,46 @@ bool radial_lu(const Prob &q, std::vector<double> &band)
     }
     for (int k = 0; k < nr; ++k) at(k, k) = 1.0 / at(k, k);
     return true;
+}
+
+// Responses of the partitioned solve (rows split into nseg segments of seg rows): for each segment but the
+// first of a pass, the values its rows take from a zero right-hand side when boundary value t is 1 and the
+// others 0.  Forward boundary t = y(a - 1 - t), backward x(b + t), for a segment [a, b).  Out: gresp =
+// forward [nr][nd] then backward [nr][nd].
+void segment_responses(const Prob &q, const std::vector<double> &band, int seg, std::vector<double> &gresp)
+{
+    const int nd = q.nd, nr = q.d.nr, W = 2 * nd + 1, ns = (nr + seg - 1) / seg;
+    gresp.assign((size_t)2 * nr * nd, 0.0);
+    double *gf = gresp.data(), *gb = gresp.data() + (size_t)nr * nd;
+    std::vector<double> v(nr);
+    for (int s = 0; s < ns; ++s) {
+        const int a = s * seg, b = std::min(nr, a + seg);
+        for (int t0 = 0; t0 < nd; ++t0) {
+            if (s >= 1) {  // forward
+                std::fill(v.begin(), v.end(), 0.0);
+                for (int t = 0; t < nd; ++t)
+                    if (a - 1 - t >= 0) v[a - 1 - t] = t == t0 ? 1.0 : 0.0;
+                for (int k = a; k < b; ++k) {
+                    double y = 0.0;
+                    for (int j = 1; j <= nd && k - j >= 0; ++j) y -= band[(size_t)k * W + nd - j] * v[k - j];
+                    v[k] = y;
+                    gf[(size_t)k * nd + t0] = y;
+                }
+            }
+            if (s <= ns - 2) {  // backward
+                std::fill(v.begin(), v.end(), 0.0);
+                for (int t = 0; t < nd; ++t)
+                    if (b + t < nr) v[b + t] = t == t0 ? 1.0 : 0.0;
+                for (int k = b - 1; k >= a; --k) {
+                    double x = 0.0;
+                    for (int j = 1; j <= nd && k + j < nr; ++j) x -= band[(size_t)k * W + nd + j] * v[k + j];
+                    x *= band[(size_t)k * W + nd];
+                    v[k] = x;
+                    gb[(size_t)k * nd + t0] = x;
+                }
+            }
+        }
+    }
 }
 
 // Launch batches hold disjoint problems, so a call can run them on several streams: the side streams
@@ -995,13 +1055,20 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
                 rc = fail(P, FDETD_E_ARG, "fdetd_plan: problem %d: the radial operator of the current correction is singular", p);
                 break;
             }
+            // segments of the partitioned solve: at least 2 nd rows, at most about 8 segments
+            q.seg = std::max(2 * q.nd, (q.d.nr + 7) / 8);
+            q.nseg = (q.d.nr + q.seg - 1) / q.seg;
+            std::vector<double> gresp;
+            segment_responses(q, band, q.seg, gresp);
             if ((e = hipMalloc((void **)&q.band, band.size() * sizeof(double))) || (e = hipMalloc(&q.jth, q.cells * eb)) ||
-                (e = hipMemcpy(q.band, band.data(), band.size() * sizeof(double), hipMemcpyHostToDevice))) {
+                (e = hipMalloc((void **)&q.gresp, gresp.size() * sizeof(double))) ||
+                (e = hipMemcpy(q.band, band.data(), band.size() * sizeof(double), hipMemcpyHostToDevice)) ||
+                (e = hipMemcpy(q.gresp, gresp.data(), gresp.size() * sizeof(double), hipMemcpyHostToDevice))) {
                 rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
                           hipGetErrorString(e));
                 break;
             }
-            scratch += band.size() * sizeof(double) + q.cells * eb;
+            scratch += (band.size() + gresp.size()) * sizeof(double) + q.cells * eb;
             // div: read Jbar_rho, J_theta, rho_xy, write d; solve: d, y, y, phi (FP64); apply: read phi, Jbar_rho,
             // J_theta, write Jbar_rho, J_theta~
             bytes_step += (int64_t)q.cells * (8 * eb + 5 * 16);

@@ -23,7 +23,9 @@ hipError_t launch_deposit_jz(int, const DepositArgs &, hipStream_t) { return hip
 hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_correct_current(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_correct_div(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_correct_apply(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_correct_solve(const SolveArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_gather(int, const GatherArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_norm2(int, const void *, size_t, double *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipErrorInvalidValue; }
