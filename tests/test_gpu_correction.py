@@ -74,3 +74,17 @@ def test_consistent_density_leaves_the_step_unchanged_and_graph_equals_eager():
     eager, _ = gpu_maxwell(w, psi0, J4, 2, flags=1 | F.PLAN_CURRENT_CORRECTION, calls=2)
     for p in range(w.n):
         assert np.array_equal(graph[p], eager[p])
+
+
+@pytest.mark.parametrize("order,nr", [(32, 130), (4, 257)])
+def test_corrected_step_many_segments(order, nr):
+    """Taller grids: the solve splits each column into 5 (order 32, the last segment 2 rows, shorter than
+    the stencil half width) or 9 segments (order 4)."""
+    w = workload([1], [order], nz=2 * (order // 2) + 31, nr=nr, steps=2)
+    rng = np.random.default_rng(order)
+    psi0, J4 = inputs(w, 2, rng)
+    got, _ = gpu_maxwell(w, psi0, J4, 2, precision=F.FP64, flags=1 | F.PLAN_CURRENT_CORRECTION)
+    want = oracle.step_corrected(grid(w, 0), psi0[0], J4[0], 2)
+    err = rel_l2(got[0], want)
+    log(f"corrected step order {order}, {nr} rows: rel L2 {err:.2e}")
+    assert err < 1e-12
