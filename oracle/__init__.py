@@ -97,6 +97,7 @@ def lib():
         L.oracle_num_threads.restype = C.c_int
         L.oracle_deposit_rho.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
         L.oracle_deposit_jz.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
+        L.oracle_deposit_current.argtypes = [P, vp, C.c_long, C.c_double, vp, vp]
         L.oracle_destagger.argtypes = [P, vp, vp]
         L.oracle_interpolate.argtypes = [P, vp, vp, C.c_long, vp]
         _lib = L
@@ -180,6 +181,19 @@ def deposit_jz(g: Grid, samples, vz: float = 1.0, eps: float = 0.5, j=None) -> n
     P = g.c()
     _chk(lib().oracle_deposit_jz(C.byref(P), _ptr(x), x.shape[0], vz, eps, _ptr(out)), "deposit_jz")
     return out
+
+
+def deposit_current(g: Grid, samples, eps: float = 0.5):
+    """Currents of moving samples ([n, 8]: z, x, y, q w, v_x, v_y, v_z, unused): returns (j [3, nr, nz],
+    rho_xy [nr, nz])."""
+    x = np.ascontiguousarray(np.asarray(samples, dtype=np.float64))
+    if x.ndim != 2 or x.shape[1] != 8:
+        raise ValueError("samples: [n, 8] array of (z, x, y, q w, v_x, v_y, v_z, unused)")
+    j = np.zeros((3, g.nr, g.nz), np.complex128)
+    r = np.zeros((g.nr, g.nz), np.complex128)
+    P = g.c()
+    _chk(lib().oracle_deposit_current(C.byref(P), _ptr(x), x.shape[0], eps, _ptr(j), _ptr(r)), "deposit_current")
+    return j, r
 
 
 def set_axis(g: Grid, psi) -> np.ndarray:

@@ -952,6 +952,64 @@ int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, do
     return 0;
 }
 
+/* Currents of moving samples (section 3.6): samples hold z, x, y, q w, v_x, v_y, v_z and one unused word.
+ * Positions z+-, x+-, y+- = position +- v dt/2 give rho+-, theta+-.  Added into j (planes J_rho, J_theta,
+ * J_z) and, when rho_xy is not NULL, into the planar density differential of section 3.7:
+ *   J_rho   += q w v_rho S(z_p) R_A(rho_p) A(theta_p),  J_theta += q w v_theta S(z_p) R_A(rho_p) A(theta_p)
+ *   J_z(i - 1/2) += q w (F_-(i) - F_+(i)) / dt * (R_S(rho+) A(theta+) + R_S(rho-) A(theta-)) / 2
+ *   rho_xy  += q w (S(z+) + S(z-)) / 2 * (R_S(rho+) A(theta+) - R_S(rho-) A(theta-)) / dt
+ * with S(z) = S3(i - z/dz)/dz, F_+- the integrated z shape of z+- (as for oracle_deposit_jz), R_A / R_S the
+ * radial shape folded with the m_A (polar components) / m_S (z component, densities) parity, A the angular
+ * shape; v_rho = (x v_x + y v_y)/rho, v_theta = (x v_y - y v_x)/rho at the sample (0 on the axis).  A sample
+ * whose z shapes at z+- reach past a z end is not deposited. */
+int oracle_deposit_current(const oracle_problem *P, const double *samples, long n, double eps, double complex *j,
+                           double complex *rho_xy)
+{
+    if (check_problem(P) || !samples || !j || n < 0 || !(P->dt > 0)) return -1;
+    const int nz = P->nz, nr = P->nr, pS = parity_mS(P->m), pA = parity_mA(P->m);
+    const size_t np = (size_t)nz * nr;
+    double *dF = malloc(sizeof(double) * (size_t)nz);
+    if (!dF) return -2;
+    for (long s = 0; s < n; ++s) {
+        const double *q = samples + 8 * s;
+        const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5], vz = q[6];
+        const double h = 0.5 * P->dt;
+        const double zp = (z + h * vz) / P->dz, zm = (z - h * vz) / P->dz;
+        if (!z_inside(P, zp) || !z_inside(P, zm)) continue;
+        const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
+        const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym), r0 = sqrt(x * x + y * y);
+        const cplx ap = angular_shape(P->m, atan2(yp, xp)), am = angular_shape(P->m, atan2(ym, xm));
+        const cplx a0 = angular_shape(P->m, atan2(y, x));
+        const double vr = r0 > 0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0 ? (x * vy - y * vx) / r0 : 0.0;
+        const double Np = radial_norm(P, rp, eps), Nm = radial_norm(P, rm, eps), N0 = radial_norm(P, r0, eps);
+        double Fp = 0.0, Fm = 0.0;
+        for (int i = 0; i < nz; ++i) {
+            dF[i] = (Fm - Fp) / P->dt;
+            Fp += bspline3(i - zp);
+            Fm += bspline3(i - zm);
+        }
+        for (int k = 0; k < nr; ++k) {
+            const double RA = radial_shape(P, r0, eps, N0, pA, k);
+            const cplx tp = radial_shape(P, rp, eps, Np, pS, k) * ap, tm = radial_shape(P, rm, eps, Nm, pS, k) * am;
+            for (int i = 0; i < nz; ++i) {
+                const size_t o = IDX(P, k, i);
+                const double s0 = bspline3(i - z / P->dz) / P->dz;
+                if (s0 != 0.0 && RA != 0.0) {
+                    j[o] += qw * vr * s0 * RA * a0;
+                    j[np + o] += qw * vt * s0 * RA * a0;
+                }
+                if (dF[i] != 0.0) j[2 * np + o] += qw * dF[i] * 0.5 * (tp + tm);
+                if (rho_xy) {
+                    const double sz = 0.5 * (bspline3(i - zp) + bspline3(i - zm)) / P->dz;
+                    if (sz != 0.0) rho_xy[o] += qw * sz * (tp - tm) / P->dt;
+                }
+            }
+        }
+    }
+    free(dF);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Field interpolation (section 3.3): destaggering to the primary grids, then the sum of the shapes   */
 /* of the sample over the nodes, the radial shape treated as a Cartesian one.                          */

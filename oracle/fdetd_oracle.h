@@ -101,6 +101,11 @@ int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, d
 int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, double vz, double eps,
                       double complex *j);
 
+/* Currents of moving samples (section 3.6; 8 doubles per sample: z, x, y, q w, v_x, v_y, v_z, unused) into
+ * j (J_rho, J_theta, J_z) and, if not NULL, the planar density differential rho_xy of section 3.7. */
+int oracle_deposit_current(const oracle_problem *P, const double *samples, long n, double eps, double complex *j,
+                           double complex *rho_xy);
+
 /* Field interpolation (section 3.3): the six components destaggered to the primary grids, and the value
  * of this mode at each sample added into fields (n x 6 doubles). */
 int oracle_destagger(const oracle_problem *P, const double complex *psi, double complex *out);
