@@ -174,6 +174,28 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
 FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
                                void *const *j_half);
 
+/* Deposit the currents of n moving point samples into the current block j_half[p] of every problem of a
+ * Maxwell plan, adding to what is there (section 3.6, and section 3.7 for rho_xy).  Positions at the half
+ * steps are (z, x, y) +- v dt/2, giving rho+-, theta+-:
+ *   J_rho   += q w v_rho   S(z_i - z) R_A(rho_k; rho) A_m(theta)              (plane 0)
+ *   J_theta += q w v_theta S(z_i - z) R_A(rho_k; rho) A_m(theta)              (plane 1)
+ *   J_z(z_i - dz/2) += q w (F_-(i) - F_+(i)) / dt * (R_S(rho+) A_m(theta+) + R_S(rho-) A_m(theta-)) / 2
+ *                                                                             (plane 2, modified Esirkepov)
+ *   rho_xy  += q w (S(z_i - z+) + S(z_i - z-)) / 2 * (R_S(rho+) A_m(theta+) - R_S(rho-) A_m(theta-)) / dt
+ *                                                   (plane 3, only for plans with FDETD_PLAN_CURRENT_CORRECTION)
+ * S(x) = S3(x/dz)/dz; F_-+ and A_m as for fdetd_deposit_jz; R_A / R_S the radial shape of fdetd_deposit_jz
+ * folded with the m_A (J_rho, J_theta) / m_S (J_z, rho_xy) parity; v_rho = (x v_x + y v_y)/rho and
+ * v_theta = (x v_y - y v_x)/rho at the sample, 0 on the axis.  With these, the densities at the end
+ * positions satisfy (rho+ - rho-)/dt + D_z^(+) J_z - rho_xy = 0.  A sample whose z shapes reach past a z
+ * end, or that moves more than 3 cells along z in dt, is not deposited.
+ *   samples  device array of n x 8 doubles: z, x, y, q w, v_x, v_y, v_z, unused; 8-byte aligned.
+ *   eps      in [0, 1].
+ *   j_half   n_probs device pointers to current blocks as for fdetd_step (3 planes, 4 with
+ *            FDETD_PLAN_CURRENT_CORRECTION), the plan's precision.
+ * Enqueue only; atomic adds. */
+FDETD_API int fdetd_deposit_current(fdetd_plan_t plan, const double *samples, int64_t n, double eps,
+                                    void *const *j_half);
+
 /* Deposit the charge density of n point samples shifted by dz_shift along z into one plane per problem
  * of a Maxwell plan, adding to what is there (sections 3.2, 3.5):
  *   rho(z_i, rho_k) += q w S3(i - (z + dz_shift) / dz) / dz * R_k * A_m

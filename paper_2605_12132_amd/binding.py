@@ -23,7 +23,7 @@ PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_deposit_rho",
-           "fdetd_gather", "fdetd_query",
+           "fdetd_deposit_current", "fdetd_gather", "fdetd_query",
            "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
@@ -84,6 +84,7 @@ def _load():
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
+    L.fdetd_deposit_current.argtypes = [vp, vp, C.c_int64, C.c_double, pp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
     L.fdetd_export_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -144,6 +145,10 @@ def fdetd_deposit_jz(plan, samples_ptr, n: int, vz: float, eps: float, j_ptrs):
 
 def fdetd_deposit_rho(plan, samples_ptr, n: int, dz_shift: float, eps: float, rho_ptrs):
     _check(lib.fdetd_deposit_rho(plan, samples_ptr, n, dz_shift, eps, _ptrs(rho_ptrs)), plan)
+
+
+def fdetd_deposit_current(plan, samples_ptr, n: int, eps: float, j_ptrs):
+    _check(lib.fdetd_deposit_current(plan, samples_ptr, n, eps, _ptrs(j_ptrs)), plan)
 
 
 def fdetd_gather(plan, psi_ptrs, samples_ptr, n: int, fields_ptr):
@@ -251,6 +256,19 @@ class Plan:
         self._nchk(j_half, "j_half")
         jp = [self._chk(x, (3, p.nr, p.nz), self._cdtype(), "j_half") for x, p in zip(j_half, self.problems)]
         fdetd_deposit_jz(self._h, samples.data_ptr(), samples.shape[0], vz, eps, jp)
+
+    def deposit_current(self, samples, j_half, eps: float = 0.5):
+        """Add the currents of moving samples (float64 [n, 8] cuda tensor: z, x, y, q w, v_x, v_y, v_z, unused)
+        into each problem's current block ([3 or 4, nr, nz] tensors of the plan's precision; plane 3 takes
+        rho_xy with PLAN_CURRENT_CORRECTION)."""
+        import torch
+        if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 8
+                and samples.is_contiguous()):
+            raise ValueError("samples: contiguous float64 cuda tensor [n, 8]")
+        self._nchk(j_half, "j_half")
+        nb = 4 if self.flags & PLAN_CURRENT_CORRECTION else 3
+        jp = [self._chk(x, (nb, p.nr, p.nz), self._cdtype(), "j_half") for x, p in zip(j_half, self.problems)]
+        fdetd_deposit_current(self._h, samples.data_ptr(), samples.shape[0], eps, jp)
 
     def deposit_rho(self, samples, rho, dz_shift: float = 0.0, eps: float = 0.5):
         """Add the charge density of point samples (float64 [n, 4] cuda tensor of z, x, y, q w) shifted by

@@ -150,10 +150,12 @@ struct DepositArgs {
     const double *samples;  // n x 4: z, x, y, q w
     double vz, eps;
     double shift;           // charge density: shift of the sample positions along z
+    int rho_xy;             // moving samples: also deposit the planar density differential into plane 3
     void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2), or charge density (1 plane)
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
+hipError_t launch_deposit_current(int prec, const DepositArgs &a, hipStream_t s);  // 8 doubles per sample
 // Current correction (section 3.7) of one problem's staged current, three steps:
 //   div:   d = rho_xy - D_div^(+,mS) Jbar_rho - (i m / rho) J_theta            -> work (double2 plane)
 //   solve: [L_rho^(mS) - m^2/rho^2] phi = d per z column with the plan-time LU factors (no pivoting)

@@ -509,6 +509,83 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
     }
 }
 
+// Currents of moving samples (section 3.6) and the planar density differential (section 3.7), one thread
+// per sample (z, x, y, q w, v_x, v_y, v_z, unused), positions +- v dt/2:
+//   J_rho, J_theta += q w v_rho|theta S(z_p) R_A(rho_p) A(theta_p)          (planes 0, 1)
+//   J_z(i - 1/2)   += q w dF(i) (R_S(rho+) A(theta+) + R_S(rho-) A(theta-)) / 2  (plane 2)
+//   rho_xy         += q w (S(z+) + S(z-)) / 2 (R_S(rho+) A(theta+) - R_S(rho-) A(theta-)) / dt  (plane 3)
+// R_A / R_S: radial shape folded with the m_A / m_S parity.  Samples whose z shapes leave the grid or that
+// move more than 3 cells along z are skipped.
+template <typename R>
+__global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= A.n) return;
+    const double *q = A.samples + 8 * s;
+    const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5], vz = q[6];
+    const double r0 = sqrt(x * x + y * y), t0 = atan2(y, x);
+    const double vr = r0 > 0.0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0.0 ? (x * vy - y * vx) / r0 : 0.0;
+    for (int p = 0; p < A.nprob; ++p) {
+        const ProbDesc &D = A.probs[p];
+        const double h = 0.5 * D.dt;
+        const double zp = (z + h * vz) / D.dz, zm = (z - h * vz) / D.dz, zc = z / D.dz;
+        if (!z_on_grid(D, zp) || !z_on_grid(D, zm) || fabs(zp - zm) > 3.0) continue;
+        const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
+        const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym);
+        const SampleShape Sp = sample_shape(D, rp, atan2(yp, xp), A.eps), Sm = sample_shape(D, rm, atan2(ym, xm), A.eps);
+        SampleShape S0 = sample_shape(D, r0, t0, A.eps);
+        S0.par = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;  // m_A fold for J_rho, J_theta
+        R *j = (R *)A.j[p];
+        const size_t pl = 2 * D.plane;  // one plane in R units (interleaved complex)
+        // transverse currents at the sample
+        if (vr != 0.0 || vt != 0.0) {
+            const int lo = (int)floor(zc) - 1;
+            for (int k = S0.k0; k <= S0.k1; ++k) {
+                const double rs = radial_weight(D, S0, r0, A.eps, k);
+                if (rs == 0.0) continue;
+                for (int u = 0; u < 4; ++u) {
+                    const double w = qw * bspline3(lo + u - zc) / D.dz * rs;
+                    if (w == 0.0) continue;
+                    R *c = j + 2 * ((size_t)k * D.nz + lo + u);
+                    atomicAdd(c, (R)(w * vr * S0.ar));
+                    atomicAdd(c + 1, (R)(w * vr * S0.ai));
+                    atomicAdd(c + pl, (R)(w * vt * S0.ar));
+                    atomicAdd(c + pl + 1, (R)(w * vt * S0.ai));
+                }
+            }
+        }
+        // longitudinal current and planar density differential over the nodes of both z shapes
+        const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
+        double dF[8], sz[8];
+        double Fp = 0.0, Fm = 0.0;
+        for (int u = 0; u <= hi - lo; ++u) {
+            dF[u] = (Fm - Fp) / D.dt;
+            const double bp = bspline3(lo + u - zp), bm = bspline3(lo + u - zm);
+            Fp += bp;
+            Fm += bm;
+            sz[u] = 0.5 * (bp + bm) / D.dz;
+        }
+        const int k0 = min(Sp.k0, Sm.k0), k1 = max(Sp.k1, Sm.k1);
+        for (int k = k0; k <= k1; ++k) {
+            const double wp = radial_weight(D, Sp, rp, A.eps, k), wm = radial_weight(D, Sm, rm, A.eps, k);
+            if (wp == 0.0 && wm == 0.0) continue;
+            const double sr = 0.5 * (wp * Sp.ar + wm * Sm.ar), si = 0.5 * (wp * Sp.ai + wm * Sm.ai);
+            const double dr_ = (wp * Sp.ar - wm * Sm.ar) / D.dt, di = (wp * Sp.ai - wm * Sm.ai) / D.dt;
+            for (int u = 0; u <= hi - lo; ++u) {
+                R *c = j + 2 * ((size_t)k * D.nz + lo + u);
+                if (dF[u] != 0.0) {
+                    atomicAdd(c + 2 * pl, (R)(qw * dF[u] * sr));
+                    atomicAdd(c + 2 * pl + 1, (R)(qw * dF[u] * si));
+                }
+                if (A.rho_xy && sz[u] != 0.0) {
+                    atomicAdd(c + 3 * pl, (R)(qw * sz[u] * dr_));
+                    atomicAdd(c + 3 * pl + 1, (R)(qw * sz[u] * di));
+                }
+            }
+        }
+    }
+}
+
 // Charge density of mode m of the samples shifted along z, one plane per problem (sections 3.2, 3.5):
 //   rho(z_i, rho_k) += q w S3(i - z'/dz) / dz * R_k * A_m,  z' = z + shift.
 template <typename R>
@@ -1015,6 +1092,15 @@ hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s)
     const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
     if (prec == P64) hipLaunchKernelGGL(k_deposit_jz<double>, g, b, 0, s, a);
     else hipLaunchKernelGGL(k_deposit_jz<float>, g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_current(int prec, const DepositArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_deposit_current<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_deposit_current<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1166,6 +1166,32 @@ int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double
     return FDETD_OK;
 }
 
+int fdetd_deposit_current(fdetd_plan_t plan, const double *samples, int64_t n, double eps, void *const *j_half)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_deposit_current: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_deposit_current: plan is not a Maxwell plan");
+    if (n < 0 || !j_half || (n > 0 && !aligned(samples, 8)) || !(eps >= 0.0 && eps <= 1.0))
+        return fail(plan, FDETD_E_ARG, "fdetd_deposit_current: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
+    for (size_t p = 0; p < plan->probs.size(); ++p)
+        if (!aligned(j_half[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_deposit_current: j_half[%zu] NULL or not %zu-byte aligned", p, eb);
+    if (n == 0) return FDETD_OK;
+    for (const Batch &b : plan->batches) {
+        DepositArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = plan->ddesc + b.d0;
+        A.nprob = b.count;
+        A.n = n;
+        A.samples = samples;
+        A.eps = eps;
+        A.rho_xy = (plan->flags & FDETD_PLAN_CURRENT_CORRECTION) != 0;
+        for (int t = 0; t < b.count; ++t) A.j[t] = j_half[b.members[t]];
+        HIPCHK(plan, launch_deposit_current(prec_code(plan->precision), A, plan->stream));
+    }
+    return FDETD_OK;
+}
+
 int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, double dz_shift, double eps,
                       void *const *rho)
 {

@@ -21,6 +21,7 @@ hipError_t launch_envelope_stage(int, int, const EnvelopeStageArgs &, hipStream_
 hipError_t launch_axis_fix(int, int, const AxisArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_deposit_jz(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_deposit_current(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_div(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
@@ -109,6 +110,7 @@ int main()
     EXPECT(envelope_step(nullptr, ptrs, ptrs, ptrs, 0, 1) == FDETD_E_ARG);
     EXPECT(fdetd_deposit_jz(nullptr, nullptr, 0, 1.0, 0.5, ptrs) == FDETD_E_ARG);
     EXPECT(fdetd_deposit_rho(nullptr, nullptr, 0, 0.0, 0.5, ptrs) == FDETD_E_ARG);
+    EXPECT(fdetd_deposit_current(nullptr, nullptr, 0, 0.5, ptrs) == FDETD_E_ARG);
     EXPECT(envelope_absorber(nullptr, -1, 4, 4, 1.0, 2.0) == FDETD_E_ARG);
     EXPECT(fdetd_gather(nullptr, ptrs, nullptr, 0, nullptr) == FDETD_E_ARG);
     fdetd_plan_info info;

@@ -88,3 +88,47 @@ def test_corrected_step_many_segments(order, nr):
     err = rel_l2(got[0], want)
     log(f"corrected step order {order}, {nr} rows: rel L2 {err:.2e}")
     assert err < 1e-12
+
+
+def test_moving_samples_deposited_corrected_and_stepped():
+    """The source chain on the GPU: currents and rho_xy of moving samples deposited with
+    fdetd_deposit_current into 4-plane blocks, then corrected steps; against the oracle's deposition and
+    corrected step (FP64, 1e-12)."""
+    import torch
+    from helpers import dev
+    w = workload([0, 1], [8, 8], nz=120, nr=40, steps=2)
+    rng = np.random.default_rng(21)
+    n = 4000
+    z = rng.normal(0.5 * w.nz[0] * w.dz, 8 * w.dz, n)
+    r = np.abs(rng.normal(0, 6 * w.dr, n))
+    th = rng.uniform(-np.pi, np.pi, n)
+    v = rng.uniform(-0.5, 0.5, (n, 3))
+    s = np.column_stack([z, r * np.cos(th), r * np.sin(th), 1e-3 * rng.uniform(-1, 1, n), v, np.zeros(n)])
+    psi0 = [rng.uniform(-1, 1, (6, w.nr[p], w.nz[p])) + 1j * rng.uniform(-1, 1, (6, w.nr[p], w.nz[p]))
+            for p in range(w.n)]
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        plan = F.Plan(w.problems(), precision=F.FP64, flags=1 | F.PLAN_CURRENT_CORRECTION)
+        J = [torch.zeros((2, 4, w.nr[p], w.nz[p]), dtype=torch.complex128, device="cuda") for p in range(w.n)]
+        sd = dev(s, torch.float64)
+        for st in range(2):
+            sd[:, 0] = torch.from_numpy(s[:, 0] + (st + 0.5) * w.dt * s[:, 6]).cuda()
+            plan.deposit_current(sd, [j[st] for j in J])
+        psi = [dev(x, torch.complex128) for x in psi0]
+        plan.step(psi, J, n_steps=2)
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy() for x in psi]
+        plan.close()
+    for p in range(w.n):
+        g = grid(w, p)
+        J4 = np.zeros((2, 4, w.nr[p], w.nz[p]), complex)
+        for st in range(2):
+            s2 = s.copy()
+            s2[:, 0] = s[:, 0] + (st + 0.5) * w.dt * s[:, 6]
+            jj, rr = oracle.deposit_current(g, s2)
+            J4[st, :3], J4[st, 3] = jj, rr
+        want = oracle.step_corrected(g, psi0[p], J4, 2)
+        err = rel_l2(got[p], want)
+        log(f"deposit + corrected step m={w.m[p]}: rel L2 {err:.2e}")
+        assert err < 1e-12

@@ -117,3 +117,45 @@ def test_deposit_rho_matches_oracle_and_continuity(precision):
     with pytest.raises(F.FdetdError):
         plan.deposit_rho(sd, rp, eps=2.0)
     plan.close()
+
+
+def moving_samples(rng, n, nz, nr, dz, dr, dt):
+    s = samples(rng, n, nz, nr, dz, dr)
+    v = rng.uniform(-0.8, 0.8, (n, 3))
+    return np.column_stack([s, v, np.zeros(n)])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deposit_current_of_moving_samples(precision):
+    """All four planes (J_rho, J_theta, J_z, rho_xy) of moving samples against the oracle, modes 0..2 in
+    one plan with the current correction (FP64 1e-12, FP32C 1e-5 as for J_z), and, FP64, the split of the
+    continuity equation between the GPU's own J_z and rho_xy and the oracle's densities at the end
+    positions."""
+    import torch
+    dz = I.LAMBDA0 / 20
+    nz, nr, dt = 200, 36, 0.5 * dz
+    w = I.Workload("dep", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [8] * 3, 8, dz, 2 * dz, dt, 1)
+    rng = np.random.default_rng(44)
+    s = moving_samples(rng, 8000, nz, nr, dz, 2 * dz, dt)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=1 | F.PLAN_CURRENT_CORRECTION)
+    J = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    plan.deposit_current(dev(s, torch.float64), J, eps=0.5)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == F.FP64 else 1e-5
+    for p in range(3):
+        g = oracle.Grid(nz=nz, nr=nr, m=p, fd_order=8, taylor_order=8, dz=dz, dr=2 * dz, dt=dt)
+        wj, wr = oracle.deposit_current(g, s)
+        got = J[p].cpu().numpy().astype(np.complex128)
+        errs = [rel_l2(got[c], wj[c]) for c in range(3)] + [rel_l2(got[3], wr)]
+        log(f"deposit current m={p} precision={precision}: rel L2 per plane {[f'{e:.1e}' for e in errs]}")
+        assert max(errs) < tol
+        if precision == F.FP64:
+            h = 0.5 * dt
+            plus, minus = s[:, :4].copy(), s[:, :4].copy()
+            plus[:, :3] += h * s[:, [6, 4, 5]]
+            minus[:, :3] -= h * s[:, [6, 4, 5]]
+            rp, rm = oracle.deposit_rho(g, plus), oracle.deposit_rho(g, minus)
+            res = (rp - rm)[:, 8:nz - 8] / dt + (got[2][:, 9:nz - 7] - got[2][:, 8:nz - 8]) / dz - got[3][:, 8:nz - 8]
+            assert np.max(np.abs(res)) < 1e-11 * np.max(np.abs(got[3]))
+    plan.close()
