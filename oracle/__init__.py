@@ -88,6 +88,7 @@ def lib():
         L.oracle_correct_current.argtypes = [P, vp, vp]
         L.oracle_apply_Ha.argtypes = [P, vp, vp, vp, vp, vp]
         L.oracle_envelope_step.argtypes = [P, vp, vp, vp, C.c_int]
+        L.oracle_ponderomotive.argtypes = [P, vp, vp]
         L.oracle_absorber_profile.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, vp]
         L.oracle_envelope_step_absorbing.argtypes = [P, vp, vp, vp, vp, C.c_int]
         L.oracle_energy.argtypes = [P, vp, vp, vp]
@@ -240,6 +241,15 @@ def envelope_step(g: Grid, a, at, chi, n_steps: int = 1):
     P = g.c()
     _chk(lib().oracle_envelope_step(C.byref(P), _ptr(a), _ptr(at), _ptr(chi), n_steps), "envelope_step")
     return a, at
+
+
+def ponderomotive(g: Grid, a):
+    """|a|^2, A~_rho = -D_rho^(-)|a|^2, A~_z = -D_z^(-)|a|^2 of an m = 0 envelope: [3, nr, nz] real."""
+    x = _cplx(a, (g.nr, g.nz))
+    out = np.zeros((3, g.nr, g.nz))
+    P = g.c()
+    _chk(lib().oracle_ponderomotive(C.byref(P), _ptr(x), _ptr(out)), "ponderomotive")
+    return out
 
 
 def absorber_profile(g: Grid, lz: int, lr: int, sigma_max: float, power: float = 2.0):

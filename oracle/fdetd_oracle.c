@@ -727,6 +727,29 @@ int oracle_envelope_step(const oracle_problem *P, double complex *a, double comp
     return 0;
 }
 
+/* Ponderomotive field of the envelope model (section 4.3): with the intensity envelope |a|^2 on the
+ * primary grid (m = 0, scalar-like), A~_rho = -D_rho^(-,mS) |a|^2 on the staggered rho rows k >= 1 (row 0:
+ * 0) and A~_z = -D_z^(-) |a|^2 on the staggered z points.  out: 3 real planes |a|^2, A~_rho, A~_z. */
+int oracle_ponderomotive(const oracle_problem *P, const double complex *a, double *out)
+{
+    if (check_problem(P) || P->m != 0) return -1;
+    const int nd = P->fd_order / 2;
+    const size_t n = (size_t)P->nr * P->nz;
+    double c[16];
+    oracle_coef_staggered(nd, c);
+    cplx *i2 = malloc(n * sizeof(cplx)), *t = malloc(n * sizeof(cplx));
+    if (!i2 || !t) return -2;
+    for (size_t q = 0; q < n; ++q) i2[q] = creal(a[q]) * creal(a[q]) + cimag(a[q]) * cimag(a[q]);
+    for (size_t q = 0; q < n; ++q) out[q] = creal(i2[q]);
+    op_dr_minus(P, c, nd, parity_mS(P->m), i2, t);
+    for (size_t q = 0; q < n; ++q) out[n + q] = -creal(t[q]);
+    op_dz_minus(P, c, nd, i2, t);
+    for (size_t q = 0; q < n; ++q) out[2 * n + q] = -creal(t[q]);
+    free(i2);
+    free(t);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Scalar absorbing layer (appendix on the scalar absorbing layer, applied to the envelope state as */
 /* section 4.2 allows): the damped wave equation with sigma = sigma_z(z) + sigma_rho(rho) is split   */

@@ -77,6 +77,9 @@ int oracle_apply_Ha(const oracle_problem *P, const double complex *a, const doub
                     const double *chi, double complex *out_a, double complex *out_at);
 int oracle_envelope_step(const oracle_problem *P, double complex *a, double complex *at,
                          const double *chi, int n_steps);
+/* Ponderomotive field of the envelope model (section 4.3), m = 0: out = 3 real planes |a|^2,
+ * A~_rho = -D_rho^(-,mS)|a|^2 (staggered rho), A~_z = -D_z^(-)|a|^2 (staggered z). */
+int oracle_ponderomotive(const oracle_problem *P, const double complex *a, double *out);
 /* Scalar absorbing layer (appendix on the scalar absorbing layer): layer functions sigma [nr][nz]
  * (polynomial grading over lz columns at both z ends and lr rows at the outer rho edge) and the split
  * step exp(-sigma dt/4) T_N(dt H_a(chi + sigma^2)) exp(-sigma dt/4). */
