@@ -226,6 +226,16 @@ FDETD_API int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_
  * Enqueue only. */
 FDETD_API int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields);
 
+/* Ponderomotive field of the envelope model (section 4.3) for the m = 0 problems of an envelope plan:
+ *   out[p] plane 0: |a|^2 on the primary grid,
+ *          plane 1: A~_rho = -D_rho^(-,mS) |a|^2 on the staggered rho rows k >= 1 (row 0 = 0),
+ *          plane 2: A~_z = -D_z^(-) |a|^2 on the staggered z points (z_i - dz/2),
+ * with the staggered first-derivative weights of the plan's order, |a|^2 extended evenly below the axis
+ * and by 0 beyond the grid.  a: n_probs device pointers to the envelope planes (as for envelope_step);
+ * out: n_probs device pointers to 3 real planes of the plan's precision (double / float).  Error
+ * FDETD_E_ARG for a Maxwell plan or a problem with m != 0.  Enqueue only. */
+FDETD_API int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, void *const *out);
+
 /* Absorbing layers of envelope problems (appendix on the scalar absorbing layer, which the envelope
  * solver of section 4.2 may use): from the next envelope_step on, every step of the problem is
  *     psi_a(t + dt) = exp(-sigma dt/4) T_N(dt H_a(chi~)) exp(-sigma dt/4) psi_a(t),   chi~ = chi + sigma^2,

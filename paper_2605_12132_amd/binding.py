@@ -22,7 +22,8 @@ PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_ST
 PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "fdetd_deposit_jz", "fdetd_deposit_rho",
+EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
+           "fdetd_deposit_jz", "fdetd_deposit_rho",
            "fdetd_deposit_current", "fdetd_gather", "fdetd_query",
            "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
@@ -84,6 +85,7 @@ def _load():
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
+    L.envelope_ponderomotive.argtypes = [vp, pp, pp]
     L.fdetd_deposit_current.argtypes = [vp, vp, C.c_int64, C.c_double, pp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.fdetd_query.argtypes = [vp, C.POINTER(PlanInfo)]
@@ -149,6 +151,10 @@ def fdetd_deposit_rho(plan, samples_ptr, n: int, dz_shift: float, eps: float, rh
 
 def fdetd_deposit_current(plan, samples_ptr, n: int, eps: float, j_ptrs):
     _check(lib.fdetd_deposit_current(plan, samples_ptr, n, eps, _ptrs(j_ptrs)), plan)
+
+
+def envelope_ponderomotive(plan, a_ptrs, out_ptrs):
+    _check(lib.envelope_ponderomotive(plan, _ptrs(a_ptrs), _ptrs(out_ptrs)), plan)
 
 
 def fdetd_gather(plan, psi_ptrs, samples_ptr, n: int, fields_ptr):
@@ -319,6 +325,17 @@ class Plan:
         """Absorbing layers (lz columns at both z ends, lr rows at the outer rho edge, sigma graded as
         sigma_max d^power) for envelope problem `problem`, or all problems (-1)."""
         envelope_absorber(self._h, problem, lz, lr, sigma_max, power)
+
+    def ponderomotive(self, a, out=None):
+        """|a|^2, A~_rho, A~_z of the plan's m = 0 envelope problems: list of [3, nr, nz] real tensors."""
+        import torch
+        self._nchk(a, "a")
+        ap = [self._chk(x, (p.nr, p.nz), self._cdtype(), "a") for x, p in zip(a, self.problems)]
+        if out is None:
+            out = [torch.empty((3, p.nr, p.nz), dtype=self._rdtype(), device=x.device) for x, p in zip(a, self.problems)]
+        op = [self._chk(x, (3, p.nr, p.nz), self._rdtype(), "out") for x, p in zip(out, self.problems)]
+        envelope_ponderomotive(self._h, ap, op)
+        return out
 
     def query(self) -> dict:
         return fdetd_query(self._h)

@@ -212,6 +212,10 @@ struct GatherArgs {
 };
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 
+// Ponderomotive field of an m = 0 envelope problem (section 4.3): 3 real planes |a|^2, A~_rho, A~_z.
+hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,
+                                hipStream_t s);
+
 // Damping exp(-sigma dt/4) of an envelope state (a, a~) on the cells of its absorbing layers: lz columns
 // at each z end and lr rows at the outer rho edge.  FP32C: the (hi, lo) pair of each value is scaled in
 // FP64 and split again.

@@ -620,6 +620,39 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
 }
 
 // --------------------------------------------------------------------------------------------------
+// Ponderomotive field of the envelope model (section 4.3), m = 0, one thread per cell:
+//   |a|^2,  A~_rho(k) = -sum_j a_j (I(k + j - 1) - I(k - j)) / dr (staggered rows k >= 1, row 0 = 0),
+//   A~_z(i) = -sum_j a_j (I(i + j - 1) - I(i - j)) / dz (staggered columns);
+// I = |a|^2 with rows below the axis mirrored (even), rows from nr on and columns outside the grid 0.
+// --------------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_ponderomotive(const ProbDesc *Dp, const void *av, void *outv, int nd)
+{
+    using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+    const ProbDesc &D = *Dp;
+    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (i >= D.nz) return;
+    const V *a = (const V *)av;
+    auto I = [&](int q, int c) -> double {
+        if (c < 0 || c >= D.nz) return 0.0;
+        const int qq = q < 0 ? -1 - q : q;
+        if (qq >= D.nr) return 0.0;
+        const V v = a[(size_t)qq * D.nz + c];
+        return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    };
+    double gr = 0.0, gz = 0.0;
+    for (int j = 1; j <= nd; ++j) {
+        if (k >= 1) gr += D.ar[j - 1] * (I(k + j - 1, i) - I(k - j, i));
+        gz += D.az[j - 1] * (I(k, i + j - 1) - I(k, i - j));
+    }
+    R *out = (R *)outv;
+    const size_t o = (size_t)k * D.nz + i;
+    out[o] = (R)I(k, i);
+    out[D.plane + o] = (R)(-gr);
+    out[2 * D.plane + o] = (R)(-gz);
+}
+
+// --------------------------------------------------------------------------------------------------
 // Current correction (section 3.7).  FP64 arithmetic throughout; J in the storage precision.
 // --------------------------------------------------------------------------------------------------
 template <typename R>
@@ -964,6 +997,15 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A)
 }
 
 }  // namespace
+
+hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,
+                                hipStream_t s)
+{
+    const dim3 grid((unsigned)((nz + 255) / 256), (unsigned)nr);
+    if (prec == P64) hipLaunchKernelGGL(k_ponderomotive<double>, grid, dim3(256), 0, s, d, a, out, nd);
+    else hipLaunchKernelGGL(k_ponderomotive<float>, grid, dim3(256), 0, s, d, a, out, nd);
+    return hipGetLastError();
+}
 
 hipError_t launch_correct_div(int prec, const CorrectArgs &a, hipStream_t s)
 {

@@ -1286,6 +1286,29 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     return FDETD_OK;
 }
 
+int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, void *const *out)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_ponderomotive: NULL plan");
+    if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_ponderomotive: plan is not an envelope plan");
+    if (!a || !out) return fail(plan, FDETD_E_ARG, "envelope_ponderomotive: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        if (plan->probs[p].d.m != 0)
+            return fail(plan, FDETD_E_ARG, "envelope_ponderomotive: problem %zu has m = %d (needs m = 0)", p,
+                        plan->probs[p].d.m);
+        if (!aligned(a[p], eb) || !aligned(out[p], eb / 2))
+            return fail(plan, FDETD_E_ARG, "envelope_ponderomotive: pointer of problem %zu NULL or misaligned", p);
+    }
+    for (const Batch &b : plan->batches)
+        for (int t = 0; t < b.count; ++t) {
+            const int p = b.members[t];
+            const Prob &q = plan->probs[p];
+            HIPCHK(plan, launch_ponderomotive(prec_code(plan->precision), plan->ddesc + b.d0 + t, q.d.nz, q.d.nr, q.nd,
+                                              a[p], out[p], plan->stream));
+        }
+    return FDETD_OK;
+}
+
 int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max, double power)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_absorber: NULL plan");

@@ -24,6 +24,7 @@ hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hi
 hipError_t launch_deposit_current(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_ponderomotive(int, const ProbDesc *, int, int, int, const void *, void *, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_div(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_apply(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_solve(const SolveArgs &, hipStream_t) { return hipErrorInvalidValue; }
@@ -113,6 +114,7 @@ int main()
     EXPECT(fdetd_deposit_current(nullptr, nullptr, 0, 0.5, ptrs) == FDETD_E_ARG);
     EXPECT(envelope_absorber(nullptr, -1, 4, 4, 1.0, 2.0) == FDETD_E_ARG);
     EXPECT(fdetd_gather(nullptr, ptrs, nullptr, 0, nullptr) == FDETD_E_ARG);
+    EXPECT(envelope_ponderomotive(nullptr, ptrs, ptrs) == FDETD_E_ARG);
     fdetd_plan_info info;
     EXPECT(fdetd_query(nullptr, &info) == FDETD_E_ARG);
     size_t bytes = 0;

@@ -85,3 +85,43 @@ def test_envelope_batched_uneven(precision):
         sa, st, _ = gpu_envelope(ws, [a0[p]], [at0[p]], [chi[p]], 6, precision=precision, flags=1)
         assert np.array_equal(sa[0], ga[p]) and np.array_equal(st[0], gt[p])
     del F
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ponderomotive_field(precision):
+    """|a|^2 and A~ = -grad |a|^2 (section 4.3) of the envelope-in-plasma pulse and of random envelopes of
+    two m = 0 problems (orders 8 and 16) against the oracle: FP64 to 1e-13 of the field scale, FP32C (float
+    input and output, FP64 sums; the oracle takes the float-rounded input) to 1e-6; m != 0 is rejected."""
+    import torch
+    import paper_2605_12132_amd as F
+    from helpers import dev
+    from oracle import Grid, ponderomotive
+    dz = I.LAMBDA0 / 5
+    w = I.Workload("pond", 1, [300, 211], [60, 45], [0, 0], [8, 16], 4, dz, 0.2 * I.UM, 0.5 * dz, 1,
+                   extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=10 * I.UM, chi0=1e-3, mod=0.05))
+    rng = np.random.default_rng(3)
+    a0 = [I.envelope_initial(I.Workload("p0", 1, [300], [60], [0], [8], 4, dz, 0.2 * I.UM, 0.5 * dz, 1,
+                                        extra=w.extra))[0],
+          rng.uniform(-1, 1, (45, 211)) + 1j * rng.uniform(-1, 1, (45, 211))]
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    out = plan.ponderomotive([dev(x, cd) for x in a0])
+    torch.cuda.synchronize()
+    tol = 1e-13 if precision == F.FP64 else 1e-6
+    for p in range(2):
+        g = Grid(nz=w.nz[p], nr=w.nr[p], m=0, fd_order=w.fd_order[p], taylor_order=4, dz=w.dz, dr=w.dr, dt=w.dt)
+        # the oracle on the input as the GPU holds it (FP32C: rounded to float), so that only the GPU's own
+        # arithmetic is compared: FP64 sums, float output rounding (6e-8) for FP32C
+        inp = a0[p] if precision == F.FP64 else a0[p].astype(np.complex64).astype(np.complex128)
+        want = ponderomotive(g, inp)
+        got = out[p].cpu().numpy().astype(np.float64)
+        for c in range(3):
+            err = np.max(np.abs(got[c] - want[c])) / np.max(np.abs(want[c]))
+            log(f"ponderomotive problem {p} plane {c} precision {precision}: {err:.2e}")
+            assert err < tol
+    plan.close()
+    w1 = I.Workload("pond1", 1, [64], [20], [1], [8], 4, dz, 0.2 * I.UM, 0.5 * dz, 1)
+    plan = F.Plan(w1.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    with pytest.raises(F.FdetdError):
+        plan.ponderomotive([torch.zeros((20, 64), dtype=cd, device="cuda")])
+    plan.close()
