@@ -408,8 +408,8 @@ def correction_pass(steps, warmup):
 def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
-    of peak density n_b) moving at c, deposited with fdetd_deposit_jz (timed separately, including the
-    advance of the sample positions), then graph replay of `steps` field steps, then the fields of the
+    of peak density n_b) moving at c, in z order, deposited with fdetd_deposit_jz (timed separately,
+    including the advance of the sample positions), then graph replay of `steps` field steps, then the fields of the
     final state at the samples (fdetd_gather, timed apart).  FP64 and FP32C; the FP32C error against FP64
     after the same steps."""
     import torch
@@ -424,6 +424,9 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     base[:, 0] = 0.25 * nz * w.dz + e["sigz"] * base[:, 0]
     base[:, 1:3] *= e["sigr"]
     base[:, 3] = -e["nb"] * (2 * math.pi) ** 1.5 * e["sigz"] * e["sigr"] ** 2 / n_samples
+    # position order, as a PIC code keeps its particles (all samples move alike, so it holds every step):
+    # blocks of consecutive samples then deposit through LDS tiles
+    base = base[torch.argsort(base[:, 0])].contiguous()
     cells = w.cells()
     res, psis = {}, {}
     for tag, prec, cd in (("fp64", F.FP64, torch.complex128), ("fp32c", F.FP32C, torch.complex64)):

@@ -7,6 +7,8 @@
 // time-stepping hot path uses the row-marching kernels of fdetd_march.hip instead.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "fdetd_internal.h"
 
 namespace fdetd {
@@ -473,38 +475,123 @@ __device__ __forceinline__ bool z_on_grid(const ProbDesc &D, double x)
     return (int)floor(x) - 1 >= 0 && (int)floor(x) + 2 <= D.nz - 1;
 }
 
+// Block-wide min and max of four ints (256 threads, wave64), through LDS.
+__device__ __forceinline__ void block_minmax(int v[4], int *red)
+{
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int x = v[c];
+        for (int o = 32; o > 0; o >>= 1) {
+            const int y = __shfl_xor(x, o);
+            x = (c & 1) ? max(x, y) : min(x, y);  // c = 0, 2: min; 1, 3: max
+        }
+        if (lane == 0) red[4 * wv + c] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int x = red[c];
+        for (int w = 1; w < 4; ++w) x = (c & 1) ? max(x, red[4 * w + c]) : min(x, red[4 * w + c]);
+        v[c] = x;
+    }
+    __syncthreads();
+}
+
+// J_z of the samples of a block (DEP_PER_THREAD per thread, consecutive).  For each problem the block
+// forms the footprint of its samples (the nodes and rows their shapes touch); when it fits an LDS tile of
+// DEP_TILE cells -- samples given in position order, as PIC codes keep them, make the footprint of a block
+// small -- the adds go to the tile (FP64 LDS atomics) and the tile is added to the grid once, one global
+// atomic per touched cell; otherwise every add is a global atomic.  Either way the result is the same sum.
+constexpr int DEP_PER_THREAD = 4, DEP_TILE = 4096;
 template <typename R>
 __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.n) return;
-    const double z = A.samples[4 * s], x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
-    const double qw = A.samples[4 * s + 3];
-    const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+    __shared__ double tile[2 * DEP_TILE];
+    __shared__ int red[16];
+    const int64_t s0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * DEP_PER_THREAD;
+    struct Smp { double z, rho, th, qw; bool ok; };
+    Smp sm[DEP_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < DEP_PER_THREAD; ++u) {
+        const int64_t s = s0 + u;
+        sm[u].ok = s < A.n;
+        const int64_t sc = sm[u].ok ? s : 0;
+        const double x = A.samples[4 * sc + 1], y = A.samples[4 * sc + 2];
+        sm[u].z = A.samples[4 * sc];
+        sm[u].qw = A.samples[4 * sc + 3];
+        sm[u].rho = sqrt(x * x + y * y);
+        sm[u].th = atan2(y, x);
+    }
     for (int p = 0; p < A.nprob; ++p) {
         const ProbDesc &D = A.probs[p];
-        const double zp = (z + 0.5 * A.vz * D.dt) / D.dz, zm = (z - 0.5 * A.vz * D.dt) / D.dz;
-        const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
-        if (!z_on_grid(D, zp) || !z_on_grid(D, zm) || hi - lo + 1 > 8) continue;
-        double dF[8];
-        double Fp = 0.0, Fm = 0.0;
-        for (int u = 0; u <= hi - lo; ++u) {
-            dF[u] = (Fm - Fp) / D.dt;
-            Fp += bspline3(lo + u - zp);
-            Fm += bspline3(lo + u - zm);
-        }
-        const SampleShape S = sample_shape(D, rho, th, A.eps);
-        R *jz = (R *)A.j[p] + 2 * 2 * D.plane;  // plane 2, interleaved complex
-        for (int k = S.k0; k <= S.k1; ++k) {
-            const double rs = radial_weight(D, S, rho, A.eps, k);
-            if (rs == 0.0) continue;
-            for (int u = 0; u <= hi - lo; ++u) {
-                const double v = qw * dF[u] * rs;
-                if (v == 0.0) continue;
-                R *c = jz + 2 * ((size_t)k * D.nz + lo + u);
-                atomicAdd(c, (R)(v * S.ar));
-                atomicAdd(c + 1, (R)(v * S.ai));
+        // footprints: nodes lo .. hi, rows kc - 3 .. kc + 3 (clipped)
+        int lo[DEP_PER_THREAD], hi[DEP_PER_THREAD];
+        int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};  // zmin, zmax, kmin, kmax
+#pragma unroll
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            const double zp = (sm[u].z + 0.5 * A.vz * D.dt) / D.dz, zm = (sm[u].z - 0.5 * A.vz * D.dt) / D.dz;
+            lo[u] = (int)floor(fmin(zp, zm)) - 1;
+            hi[u] = (int)floor(fmax(zp, zm)) + 2;
+            if (!sm[u].ok || !z_on_grid(D, zp) || !z_on_grid(D, zm) || hi[u] - lo[u] + 1 > 8) {
+                hi[u] = lo[u] - 1;  // nothing to deposit
+                continue;
             }
+            const int kc = (int)floor(sm[u].rho / D.dr);
+            fp[0] = min(fp[0], lo[u]);
+            fp[1] = max(fp[1], hi[u]);
+            fp[2] = min(fp[2], max(kc - 3, 0));
+            fp[3] = max(fp[3], min(kc + 3, D.nr - 1));
+        }
+        block_minmax(fp, red);
+        if (fp[1] < fp[0]) continue;  // no sample of the block is deposited into this problem
+        const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
+        const bool use_tile = (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
+        R *jz = (R *)A.j[p] + 2 * 2 * D.plane;               // plane 2, interleaved complex
+        if (use_tile) {
+            for (int c = threadIdx.x; c < 2 * tz * tr; c += 256) tile[c] = 0.0;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            if (hi[u] < lo[u]) continue;
+            const double zp = (sm[u].z + 0.5 * A.vz * D.dt) / D.dz, zm = (sm[u].z - 0.5 * A.vz * D.dt) / D.dz;
+            double dF[8];
+            double Fp = 0.0, Fm = 0.0;
+            for (int v = 0; v <= hi[u] - lo[u]; ++v) {
+                dF[v] = (Fm - Fp) / D.dt;
+                Fp += bspline3(lo[u] + v - zp);
+                Fm += bspline3(lo[u] + v - zm);
+            }
+            const SampleShape S = sample_shape(D, sm[u].rho, sm[u].th, A.eps);
+            for (int k = S.k0; k <= S.k1; ++k) {
+                const double rs = radial_weight(D, S, sm[u].rho, A.eps, k);
+                if (rs == 0.0) continue;
+                for (int v = 0; v <= hi[u] - lo[u]; ++v) {
+                    const double w = sm[u].qw * dF[v] * rs;
+                    if (w == 0.0) continue;
+                    if (use_tile) {
+                        double *c = tile + 2 * ((k - fp[2]) * tz + lo[u] + v - fp[0]);
+                        atomicAdd(c, w * S.ar);
+                        atomicAdd(c + 1, w * S.ai);
+                    } else {
+                        R *c = jz + 2 * ((size_t)k * D.nz + lo[u] + v);
+                        atomicAdd(c, (R)(w * S.ar));
+                        atomicAdd(c + 1, (R)(w * S.ai));
+                    }
+                }
+            }
+        }
+        if (use_tile) {
+            __syncthreads();
+            for (int c = threadIdx.x; c < tz * tr; c += 256) {
+                const double re = tile[2 * c], im = tile[2 * c + 1];
+                if (re == 0.0 && im == 0.0) continue;
+                R *g = jz + 2 * ((size_t)(fp[2] + c / tz) * D.nz + fp[0] + c % tz);
+                atomicAdd(g, (R)re);
+                atomicAdd(g + 1, (R)im);
+            }
+            __syncthreads();  // the tile is reused by the next problem
         }
     }
 }
@@ -1131,7 +1218,8 @@ hipError_t launch_absorb_damp(int prec, const DampArgs &a, hipStream_t s)
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
+    const int64_t per_block = 256 * DEP_PER_THREAD;
+    const dim3 g((unsigned)((a.n + per_block - 1) / per_block)), b(256);
     if (prec == P64) hipLaunchKernelGGL(k_deposit_jz<double>, g, b, 0, s, a);
     else hipLaunchKernelGGL(k_deposit_jz<float>, g, b, 0, s, a);
     return hipGetLastError();

@@ -159,3 +159,29 @@ def test_deposit_current_of_moving_samples(precision):
             res = (rp - rm)[:, 8:nz - 8] / dt + (got[2][:, 9:nz - 7] - got[2][:, 8:nz - 8]) / dz - got[3][:, 8:nz - 8]
             assert np.max(np.abs(res)) < 1e-11 * np.max(np.abs(got[3]))
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deposit_jz_position_ordered_samples(precision):
+    """Samples sorted by z: the blocks' footprints are small, so the deposition accumulates them in LDS
+    tiles before adding to the grid; the result matches the oracle to the same tolerances."""
+    import torch
+    dz = I.LAMBDA0 / 20
+    nz, nr = 400, 64
+    w = I.Workload("dep", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [16] * 3, 8, dz, 2 * dz, 0.5 * dz, 1)
+    rng = np.random.default_rng(8)
+    s = samples(rng, 30000, nz, nr, dz, 2 * dz)
+    s = s[np.argsort(s[:, 0], kind="stable")]
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=1)
+    J = [torch.zeros((3, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    plan.deposit_jz(dev(s, torch.float64), J, vz=1.0, eps=0.5)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == F.FP64 else 1e-5
+    for p in range(3):
+        g = oracle.Grid(nz=nz, nr=nr, m=p, fd_order=16, taylor_order=8, dz=dz, dr=2 * dz, dt=0.5 * dz)
+        want = oracle.deposit_jz(g, s, vz=1.0, eps=0.5)
+        err = rel_l2(J[p].cpu().numpy().astype(np.complex128)[2], want[2])
+        log(f"ordered deposit m={p} precision={precision}: rel L2 {err:.2e}")
+        assert err < tol
+    plan.close()
