@@ -170,7 +170,9 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
  *   samples  device array of n x 4 doubles: z, x, y, charge * weight (normalised units), 8-byte aligned.
  *   vz       velocity along z, |vz| dt <= 3 dz for every problem; eps in [0, 1] (0.5 in the paper).
  *   j_half   n_probs device pointers as for fdetd_step (3 planes each, the plan's precision).
- * Enqueue only.  The adds are atomic, so the order of the summation, and the last bits, vary between runs. */
+ * Enqueue only.  The adds are atomic, so the order of the summation, and the last bits, vary between runs.
+ * Blocks of 1024 consecutive samples whose shapes touch at most 4096 cells of a grid sum their adds in an
+ * FP64 LDS tile first: samples given in position order (as PIC codes keep them) are much faster. */
 FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double vz, double eps,
                                void *const *j_half);
 
@@ -192,7 +194,8 @@ FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t
  *   eps      in [0, 1].
  *   j_half   n_probs device pointers to current blocks as for fdetd_step (3 planes, 4 with
  *            FDETD_PLAN_CURRENT_CORRECTION), the plan's precision.
- * Enqueue only; atomic adds. */
+ * Enqueue only; atomic adds, summed first in an FP64 LDS tile by blocks of 1024 consecutive samples whose
+ * shapes touch at most 1024 cells of a grid (position-ordered samples). */
 FDETD_API int fdetd_deposit_current(fdetd_plan_t plan, const double *samples, int64_t n, double eps,
                                     void *const *j_half);
 

@@ -603,72 +603,129 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 //   rho_xy         += q w (S(z+) + S(z-)) / 2 (R_S(rho+) A(theta+) - R_S(rho-) A(theta-)) / dt  (plane 3)
 // R_A / R_S: radial shape folded with the m_A / m_S parity.  Samples whose z shapes leave the grid or that
 // move more than 3 cells along z are skipped.
+// As k_deposit_jz, blocks of DEP_PER_THREAD x 256 consecutive samples accumulate in an LDS tile of
+// DEP_TILE_CUR cells (all planes) when their footprint fits.
+constexpr int DEP_TILE_CUR = 1024;
 template <typename R>
 __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
 {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.n) return;
-    const double *q = A.samples + 8 * s;
-    const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5], vz = q[6];
-    const double r0 = sqrt(x * x + y * y), t0 = atan2(y, x);
-    const double vr = r0 > 0.0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0.0 ? (x * vy - y * vx) / r0 : 0.0;
+    __shared__ double tile[2 * 4 * DEP_TILE_CUR];
+    __shared__ int red[16];
+    const int64_t s0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * DEP_PER_THREAD;
+    const int npl = A.rho_xy ? 4 : 3;
     for (int p = 0; p < A.nprob; ++p) {
         const ProbDesc &D = A.probs[p];
         const double h = 0.5 * D.dt;
-        const double zp = (z + h * vz) / D.dz, zm = (z - h * vz) / D.dz, zc = z / D.dz;
-        if (!z_on_grid(D, zp) || !z_on_grid(D, zm) || fabs(zp - zm) > 3.0) continue;
-        const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
-        const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym);
-        const SampleShape Sp = sample_shape(D, rp, atan2(yp, xp), A.eps), Sm = sample_shape(D, rm, atan2(ym, xm), A.eps);
-        SampleShape S0 = sample_shape(D, r0, t0, A.eps);
-        S0.par = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;  // m_A fold for J_rho, J_theta
+        auto sample = [&](int u) { const int64_t s = s0 + u; return A.samples + 8 * (s < A.n ? s : 0); };
+        auto on_grid = [&](int u, double &zp, double &zm) {
+            const double *q = sample(u);
+            zp = (q[0] + h * q[6]) / D.dz;
+            zm = (q[0] - h * q[6]) / D.dz;
+            return s0 + u < A.n && z_on_grid(D, zp) && z_on_grid(D, zm) && fabs(zp - zm) <= 3.0;
+        };
+        auto rows_of = [&](double r, int &k0, int &k1) {
+            const int kc = (int)floor(r / D.dr);
+            k0 = kc - 3 > 0 ? kc - 3 : 0;
+            k1 = kc + 3 < D.nr - 1 ? kc + 3 : D.nr - 1;
+        };
+        int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};  // zmin, zmax, kmin, kmax
+#pragma unroll
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            double zp, zm;
+            if (!on_grid(u, zp, zm)) continue;
+            const double *q = sample(u);
+            fp[0] = min(fp[0], (int)floor(fmin(zp, zm)) - 1);
+            fp[1] = max(fp[1], (int)floor(fmax(zp, zm)) + 2);
+            const double xs[3] = {q[1], q[1] + h * q[4], q[1] - h * q[4]}, ys[3] = {q[2], q[2] + h * q[5], q[2] - h * q[5]};
+            for (int c = 0; c < 3; ++c) {
+                int a, b;
+                rows_of(sqrt(xs[c] * xs[c] + ys[c] * ys[c]), a, b);
+                fp[2] = min(fp[2], a);
+                fp[3] = max(fp[3], b);
+            }
+        }
+        block_minmax(fp, red);
+        if (fp[1] < fp[0]) continue;
+        const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
+        const bool use_tile = (int64_t)tz * tr <= DEP_TILE_CUR;  // uniform across the block
         R *j = (R *)A.j[p];
         const size_t pl = 2 * D.plane;  // one plane in R units (interleaved complex)
-        // transverse currents at the sample
-        if (vr != 0.0 || vt != 0.0) {
-            const int lo = (int)floor(zc) - 1;
-            for (int k = S0.k0; k <= S0.k1; ++k) {
-                const double rs = radial_weight(D, S0, r0, A.eps, k);
-                if (rs == 0.0) continue;
-                for (int u = 0; u < 4; ++u) {
-                    const double w = qw * bspline3(lo + u - zc) / D.dz * rs;
-                    if (w == 0.0) continue;
-                    R *c = j + 2 * ((size_t)k * D.nz + lo + u);
-                    atomicAdd(c, (R)(w * vr * S0.ar));
-                    atomicAdd(c + 1, (R)(w * vr * S0.ai));
-                    atomicAdd(c + pl, (R)(w * vt * S0.ar));
-                    atomicAdd(c + pl + 1, (R)(w * vt * S0.ai));
+        if (use_tile) {
+            for (int c = threadIdx.x; c < 2 * npl * tz * tr; c += 256) tile[c] = 0.0;
+            __syncthreads();
+        }
+        auto add = [&](int plane, int k, int i, double re, double im) {
+            if (use_tile) {
+                double *c = tile + 2 * ((plane * tr + k - fp[2]) * tz + i - fp[0]);
+                atomicAdd(c, re);
+                atomicAdd(c + 1, im);
+            } else {
+                R *c = j + plane * pl + 2 * ((size_t)k * D.nz + i);
+                atomicAdd(c, (R)re);
+                atomicAdd(c + 1, (R)im);
+            }
+        };
+#pragma unroll 1
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            double zp, zm;
+            if (!on_grid(u, zp, zm)) continue;
+            const double *q = sample(u);
+            const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5];
+            const double r0 = sqrt(x * x + y * y), t0 = atan2(y, x), zc = z / D.dz;
+            const double vr = r0 > 0.0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0.0 ? (x * vy - y * vx) / r0 : 0.0;
+            const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
+            const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym);
+            const SampleShape Sp = sample_shape(D, rp, atan2(yp, xp), A.eps), Sm = sample_shape(D, rm, atan2(ym, xm), A.eps);
+            // transverse currents at the sample (m_A fold)
+            if (vr != 0.0 || vt != 0.0) {
+                SampleShape S0 = sample_shape(D, r0, t0, A.eps);
+                S0.par = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;
+                const int lo = (int)floor(zc) - 1;
+                for (int k = S0.k0; k <= S0.k1; ++k) {
+                    const double rs = radial_weight(D, S0, r0, A.eps, k);
+                    if (rs == 0.0) continue;
+                    for (int u2 = 0; u2 < 4; ++u2) {
+                        const double w = qw * bspline3(lo + u2 - zc) / D.dz * rs;
+                        if (w == 0.0) continue;
+                        add(0, k, lo + u2, w * vr * S0.ar, w * vr * S0.ai);
+                        add(1, k, lo + u2, w * vt * S0.ar, w * vt * S0.ai);
+                    }
+                }
+            }
+            // longitudinal current and planar density differential over the nodes of both z shapes
+            const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
+            double dF[8], sz[8];
+            double Fp = 0.0, Fm = 0.0;
+            for (int v = 0; v <= hi - lo; ++v) {
+                dF[v] = (Fm - Fp) / D.dt;
+                const double bp = bspline3(lo + v - zp), bm = bspline3(lo + v - zm);
+                Fp += bp;
+                Fm += bm;
+                sz[v] = 0.5 * (bp + bm) / D.dz;
+            }
+            const int k0 = min(Sp.k0, Sm.k0), k1 = max(Sp.k1, Sm.k1);
+            for (int k = k0; k <= k1; ++k) {
+                const double wp = radial_weight(D, Sp, rp, A.eps, k), wm = radial_weight(D, Sm, rm, A.eps, k);
+                if (wp == 0.0 && wm == 0.0) continue;
+                const double sr = 0.5 * (wp * Sp.ar + wm * Sm.ar), si = 0.5 * (wp * Sp.ai + wm * Sm.ai);
+                const double dr_ = (wp * Sp.ar - wm * Sm.ar) / D.dt, di = (wp * Sp.ai - wm * Sm.ai) / D.dt;
+                for (int v = 0; v <= hi - lo; ++v) {
+                    if (dF[v] != 0.0) add(2, k, lo + v, qw * dF[v] * sr, qw * dF[v] * si);
+                    if (A.rho_xy && sz[v] != 0.0) add(3, k, lo + v, qw * sz[v] * dr_, qw * sz[v] * di);
                 }
             }
         }
-        // longitudinal current and planar density differential over the nodes of both z shapes
-        const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
-        double dF[8], sz[8];
-        double Fp = 0.0, Fm = 0.0;
-        for (int u = 0; u <= hi - lo; ++u) {
-            dF[u] = (Fm - Fp) / D.dt;
-            const double bp = bspline3(lo + u - zp), bm = bspline3(lo + u - zm);
-            Fp += bp;
-            Fm += bm;
-            sz[u] = 0.5 * (bp + bm) / D.dz;
-        }
-        const int k0 = min(Sp.k0, Sm.k0), k1 = max(Sp.k1, Sm.k1);
-        for (int k = k0; k <= k1; ++k) {
-            const double wp = radial_weight(D, Sp, rp, A.eps, k), wm = radial_weight(D, Sm, rm, A.eps, k);
-            if (wp == 0.0 && wm == 0.0) continue;
-            const double sr = 0.5 * (wp * Sp.ar + wm * Sm.ar), si = 0.5 * (wp * Sp.ai + wm * Sm.ai);
-            const double dr_ = (wp * Sp.ar - wm * Sm.ar) / D.dt, di = (wp * Sp.ai - wm * Sm.ai) / D.dt;
-            for (int u = 0; u <= hi - lo; ++u) {
-                R *c = j + 2 * ((size_t)k * D.nz + lo + u);
-                if (dF[u] != 0.0) {
-                    atomicAdd(c + 2 * pl, (R)(qw * dF[u] * sr));
-                    atomicAdd(c + 2 * pl + 1, (R)(qw * dF[u] * si));
-                }
-                if (A.rho_xy && sz[u] != 0.0) {
-                    atomicAdd(c + 3 * pl, (R)(qw * sz[u] * dr_));
-                    atomicAdd(c + 3 * pl + 1, (R)(qw * sz[u] * di));
-                }
+        if (use_tile) {
+            __syncthreads();
+            for (int c = threadIdx.x; c < npl * tz * tr; c += 256) {
+                const double re = tile[2 * c], im = tile[2 * c + 1];
+                if (re == 0.0 && im == 0.0) continue;
+                const int plane = c / (tz * tr), cell = c % (tz * tr);
+                R *g = j + plane * pl + 2 * ((size_t)(fp[2] + cell / tz) * D.nz + fp[0] + cell % tz);
+                atomicAdd(g, (R)re);
+                atomicAdd(g + 1, (R)im);
             }
+            __syncthreads();  // the tile is reused by the next problem
         }
     }
 }
@@ -1228,7 +1285,8 @@ hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s)
 hipError_t launch_deposit_current(int prec, const DepositArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256));
+    const int64_t per_block = 256 * DEP_PER_THREAD;
+    const dim3 grid((unsigned)((a.n + per_block - 1) / per_block));
     if (prec == P64) hipLaunchKernelGGL(k_deposit_current<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_deposit_current<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();

@@ -125,8 +125,9 @@ def moving_samples(rng, n, nz, nr, dz, dr, dt):
     return np.column_stack([s, v, np.zeros(n)])
 
 
+@pytest.mark.parametrize("ordered", [False, True])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_deposit_current_of_moving_samples(precision):
+def test_deposit_current_of_moving_samples(precision, ordered):
     """All four planes (J_rho, J_theta, J_z, rho_xy) of moving samples against the oracle, modes 0..2 in
     one plan with the current correction (FP64 1e-12, FP32C 1e-5 as for J_z), and, FP64, the split of the
     continuity equation between the GPU's own J_z and rho_xy and the oracle's densities at the end
@@ -137,6 +138,8 @@ def test_deposit_current_of_moving_samples(precision):
     w = I.Workload("dep", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [8] * 3, 8, dz, 2 * dz, dt, 1)
     rng = np.random.default_rng(44)
     s = moving_samples(rng, 8000, nz, nr, dz, 2 * dz, dt)
+    if ordered:  # z order: blocks accumulate in LDS tiles
+        s = s[np.argsort(s[:, 0], kind="stable")]
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     plan = F.Plan(w.problems(), precision=precision, flags=1 | F.PLAN_CURRENT_CORRECTION)
     J = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
@@ -148,7 +151,8 @@ def test_deposit_current_of_moving_samples(precision):
         wj, wr = oracle.deposit_current(g, s)
         got = J[p].cpu().numpy().astype(np.complex128)
         errs = [rel_l2(got[c], wj[c]) for c in range(3)] + [rel_l2(got[3], wr)]
-        log(f"deposit current m={p} precision={precision}: rel L2 per plane {[f'{e:.1e}' for e in errs]}")
+        log(f"deposit current m={p} precision={precision} ordered={ordered}: rel L2 per plane "
+            f"{[f'{e:.1e}' for e in errs]}")
         assert max(errs) < tol
         if precision == F.FP64:
             h = 0.5 * dt
