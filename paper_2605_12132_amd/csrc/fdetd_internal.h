@@ -192,14 +192,28 @@ hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s);
 
 // Field interpolation (section 3.3).  Destaggering of one plane to the primary grid: along z (S_z^(+),
 // columns outside the grid 0) or along rho (S_rho^(+) with the operand's parity and axis rule).
-struct DestaggerArgs {
+struct DestaggerPass {
     const void *src;
     void *dst;
-    int nz, nr, nd, along_rho, parity, extrapolate;
-    double s[kMaxND];    // half-shift weights s_j
-    double c[kMaxND];    // axis extrapolation weights c_k'
+    int along_rho, parity, extrapolate;
+    int grow_r;  // rows beyond the box to compute as well
+    int set;     // coefficient set (0 or 1) of the problem the planes belong to
+};
+constexpr int kMaxDestaggerPass = 6;
+// One launch runs up to kMaxDestaggerPass independent passes (blockIdx.y), over the cells of the box.
+struct DestaggerArgs {
+    int nz, nr, npass;
+    const int *box;  // cells to compute: the samples' footprint (zlo, zhi, klo, khi), clipped to the grid
+    int nd[2];
+    double s[2][kMaxND];  // half-shift weights s_j
+    double c[2][kMaxND];  // axis extrapolation weights c_k'
+    DestaggerPass pass[kMaxDestaggerPass];
 };
 hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s);
+// The nodes and rows the interpolation shapes of n samples touch on one grid (zlo, zhi, klo, khi), reduced
+// into box (reset first).
+hipError_t launch_gather_box(const double *samples, int64_t n, int nz, int nr, double dz, double dr, int *box,
+                             hipStream_t s);
 constexpr int kMaxGather = 16;  // modes of one grid per gather
 struct GatherArgs {
     int64_t n;

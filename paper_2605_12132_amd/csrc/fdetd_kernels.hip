@@ -475,7 +475,8 @@ __device__ __forceinline__ bool z_on_grid(const ProbDesc &D, double x)
     return (int)floor(x) - 1 >= 0 && (int)floor(x) + 2 <= D.nz - 1;
 }
 
-// Block-wide min and max of four ints (256 threads, wave64), through LDS.
+// Block-wide min and max of four ints (NW wave64 wavefronts), through LDS (red holds 4 NW ints).
+template <int NW = 4>
 __device__ __forceinline__ void block_minmax(int v[4], int *red)
 {
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
@@ -492,7 +493,7 @@ __device__ __forceinline__ void block_minmax(int v[4], int *red)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         int x = red[c];
-        for (int w = 1; w < 4; ++w) x = (c & 1) ? max(x, red[4 * w + c]) : min(x, red[4 * w + c]);
+        for (int w = 1; w < NW; ++w) x = (c & 1) ? max(x, red[4 * w + c]) : min(x, red[4 * w + c]);
         v[c] = x;
     }
     __syncthreads();
@@ -1031,113 +1032,233 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrectArgs A)
 }
 
 // --------------------------------------------------------------------------------------------------
-// Field interpolation (section 3.3).  Destaggering, one thread per output cell:
+// Field interpolation (section 3.3).  Destaggering, one thread per output cell of the samples' footprint
+// box (rows grown by the reach of a later pass), grid-stride, up to six independent passes per launch;
+// the other cells are not written:
 //   along z:   out(k, i) = sum_j s_j (f(k, i + j) + f(k, i - j + 1)),  columns outside [0, nz) are 0;
 //   along rho: out(k, i) = sum_j s_j (f(k + j, i) + f(k - j + 1, i)) on the staggered rows, row 0 = the
 //              axis value (sum_k' c_k' f(k', i) when extrapolated, else 0), rows q < 0 = parity f(-q),
 //              rows >= nr are 0.  FP64 arithmetic, storage precision in and out.
 // --------------------------------------------------------------------------------------------------
+// The footprint box of the samples: one thread per sample, block reductions, then global atomics.
+__global__ __launch_bounds__(256) void k_gather_box_reset(int *box)
+{
+    if (threadIdx.x == 0) {
+        box[0] = INT_MAX;
+        box[1] = INT_MIN;
+        box[2] = INT_MAX;
+        box[3] = INT_MIN;
+    }
+}
+__global__ __launch_bounds__(256) void k_gather_box(const double *samples, int64_t n, int nz, int nr, double dz,
+                                                    double dr, int *box)
+{
+    __shared__ int red[16];
+    int v[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+    // grid-stride: few blocks, so that few global atomics meet on the four words
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) {
+        const double z = samples[4 * s], x = samples[4 * s + 1], y = samples[4 * s + 2];
+        const double zc = z / dz, rc = sqrt(x * x + y * y) / dr - 0.5;
+        // shapes over nodes floor(zc) - 1 .. + 2 and rows floor(rc) - 1 .. + 2 (rows below the axis read
+        // rows 0 and 1); far-away samples are clamped, their shape reads nothing
+        const double zf = fmin(fmax(floor(zc), -4.0), (double)nz + 4.0), rf = fmin(floor(rc), (double)nr + 4.0);
+        const int a = max(0, (int)zf - 1), b = min(nz - 1, (int)zf + 2);
+        if (a > b) continue;
+        v[0] = min(v[0], a);
+        v[1] = max(v[1], b);
+        v[2] = min(v[2], max(0, (int)rf - 1));
+        v[3] = max(v[3], min(nr - 1, max(1, (int)rf + 2)));
+    }
+    block_minmax(v, red);
+    if (threadIdx.x == 0 && v[0] <= v[1]) {
+        atomicMin(box, v[0]);
+        atomicMax(box + 1, v[1]);
+        atomicMin(box + 2, v[2]);
+        atomicMax(box + 3, v[3]);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_destagger(DestaggerArgs A)
 {
     using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
-    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
-    if (i >= A.nz) return;
-    const V *f = (const V *)A.src;
-    auto at = [&](int q, int c) -> double2 {
-        const V v = f[(size_t)q * A.nz + c];
+    const DestaggerPass &P = A.pass[blockIdx.y];
+    const int nd = A.nd[P.set];
+    const double *sw = A.s[P.set], *cw = A.c[P.set];
+    // the cells of the box (rows grown by grow_r), grid-stride
+    const int z0 = max(0, A.box[0]), z1 = min(A.nz - 1, A.box[1]);
+    const int k0 = max(0, A.box[2] - P.grow_r), k1 = min(A.nr - 1, A.box[3] + P.grow_r);
+    if (z1 < z0 || k1 < k0) return;
+    const int64_t w = z1 - z0 + 1, cells = w * (int64_t)(k1 - k0 + 1);
+    const V *f = (const V *)P.src;
+    auto at = [&](int q, int col) -> double2 {
+        const V v = f[(size_t)q * A.nz + col];
         return double2{(double)v.x, (double)v.y};
     };
-    double re = 0.0, im = 0.0;
-    if (!A.along_rho) {
-        for (int j = 1; j <= A.nd; ++j) {
-            const int c0 = i + j, c1 = i - j + 1;
-            if (c0 < A.nz) {
-                const double2 v = at(k, c0);
-                re += A.s[j - 1] * v.x;
-                im += A.s[j - 1] * v.y;
+    for (int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x; cell < cells; cell += (int64_t)gridDim.x * 256) {
+        const int i = z0 + (int)(cell % w), k = k0 + (int)(cell / w);
+        // Taps outside the grid read a clamped in-range value with weight 0 (loads need no branches and can
+        // all be in flight together); the sums are the same.
+        double re = 0.0, im = 0.0;
+        if (!P.along_rho) {
+#pragma unroll 4
+            for (int j = 1; j <= nd; ++j) {
+                const int c0 = i + j, c1 = i - j + 1;
+                const double2 v0 = at(k, min(c0, A.nz - 1)), v1 = at(k, max(c1, 0));
+                const double w0 = c0 < A.nz ? sw[j - 1] : 0.0, w1 = c1 >= 0 ? sw[j - 1] : 0.0;
+                re += w0 * v0.x;
+                im += w0 * v0.y;
+                re += w1 * v1.x;
+                im += w1 * v1.y;
             }
-            if (c1 >= 0) {
-                const double2 v = at(k, c1);
-                re += A.s[j - 1] * v.x;
-                im += A.s[j - 1] * v.y;
+        } else {
+            double axr = 0.0, axi = 0.0;
+            if (P.extrapolate)
+                for (int q = 1; q <= nd && q < A.nr; ++q) {
+                    const double2 v = at(q, i);
+                    axr += cw[q - 1] * v.x;
+                    axi += cw[q - 1] * v.y;
+                }
+            // row q of the extended grid: 0 beyond the last row, the axis value on row 0, parity * row -q
+            // below the axis
+#pragma unroll 4
+            for (int j = 1; j <= nd; ++j) {
+                const int q0 = k + j, q1 = k - j + 1, a1 = q1 < 0 ? -q1 : q1;
+                const double2 v0 = at(min(q0, A.nr - 1), i), v1 = at(min(a1, A.nr - 1), i);
+                const double g0 = q0 < A.nr ? 1.0 : 0.0, g1 = a1 >= A.nr ? 0.0 : (q1 < 0 ? (double)P.parity : 1.0);
+                const double x0 = g0 * v0.x, y0 = g0 * v0.y;
+                const double x1 = q1 == 0 ? axr : g1 * v1.x, y1 = q1 == 0 ? axi : g1 * v1.y;
+                re += sw[j - 1] * (x0 + x1);
+                im += sw[j - 1] * (y0 + y1);
             }
         }
-    } else {
-        double axr = 0.0, axi = 0.0;
-        if (A.extrapolate)
-            for (int q = 1; q <= A.nd && q < A.nr; ++q) {
-                const double2 v = at(q, i);
-                axr += A.c[q - 1] * v.x;
-                axi += A.c[q - 1] * v.y;
-            }
-        auto row = [&](int q, double &x, double &y) {
-            if (q >= A.nr) { x = y = 0.0; return; }
-            if (q == 0) { x = axr; y = axi; return; }
-            if (-q >= A.nr) { x = y = 0.0; return; }
-            const double sg = q < 0 ? (double)A.parity : 1.0;
-            const double2 v = at(q < 0 ? -q : q, i);
-            x = sg * v.x;
-            y = sg * v.y;
-        };
-        for (int j = 1; j <= A.nd; ++j) {
-            double x0, y0, x1, y1;
-            row(k + j, x0, y0);
-            row(k - j + 1, x1, y1);
-            re += A.s[j - 1] * (x0 + x1);
-            im += A.s[j - 1] * (y0 + y1);
-        }
+        ((V *)P.dst)[(size_t)k * A.nz + i] = V{(R)re, (R)im};
     }
-    V *o = (V *)A.dst;
-    o[(size_t)k * A.nz + i] = V{(R)re, (R)im};
 }
 
 // Interpolation, one thread per sample: for each mode m and component c,
 //   Re( e^(i m theta) sum_(i,k) S3(i - z/dz) S3(k + 1/2 - rho/drho) F_c(k, i) )
 // over the extended primary grid (rows k < 0 take parity * row -1-k: m_A for the rho and theta
 // components, m_S for the z ones; rows >= nr and columns outside the grid are 0), summed over the modes.
+// Blocks take GATHER_BLOCK consecutive samples; two blocks share a CU, so one block's loads overlap the
+// other's arithmetic.  When the nodes and rows their shapes touch (rows below the axis read rows 0 and 1)
+// fit GATHER_TILE values over all modes and components, the block first copies them into LDS (as FP64)
+// and every sample reads its 16 nodes per mode and component from there; position-ordered samples make
+// that footprint small.  Otherwise the samples read the planes directly.
+constexpr int GATHER_BLOCK = 512, GATHER_TILE = 4096;
 template <typename R>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs A)
+__global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(GatherArgs A)
 {
     using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.n) return;
-    const double z = A.samples[4 * s], x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
-    const double rho = sqrt(x * x + y * y), th = atan2(y, x);
-    const double zc = z / A.dz, rc = rho / A.dr - 0.5;
-    const int i0 = (int)floor(zc) - 1, k0 = (int)floor(rc) - 1;
-    double wz[4], wr[4];
-    for (int u = 0; u < 4; ++u) {
-        wz[u] = bspline3(i0 + u - zc);
-        wr[u] = bspline3(k0 + u - rc);
+    __shared__ double2 tile[GATHER_TILE];
+    __shared__ int red[4 * (GATHER_BLOCK / 64)];
+    const int64_t s = (int64_t)blockIdx.x * GATHER_BLOCK + threadIdx.x;
+    const bool live = s < A.n;
+    double z = 0.0, x = 0.0, y = 0.0;
+    if (live) {
+        z = A.samples[4 * s];
+        x = A.samples[4 * s + 1];
+        y = A.samples[4 * s + 2];
     }
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int p = 0; p < A.nprob; ++p) {
-        const int m = A.m[p];
-        const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
-        const double cr = cos(m * th), ci = sin(m * th);
-        for (int c = 0; c < 6; ++c) {
-            const double par = (c == 2 || c == 5) ? pS : pA;
-            const V *f = (const V *)A.plane[p][c];
-            double re = 0.0, im = 0.0;
-            for (int a = 0; a < 4; ++a) {
-                const int k = k0 + a;
-                const int q = k < 0 ? -1 - k : k;
-                if (q >= A.nr || wr[a] == 0.0) continue;
-                const double sg = k < 0 ? par : 1.0;
-                for (int b = 0; b < 4; ++b) {
-                    const int i = i0 + b;
-                    if (i < 0 || i >= A.nz) continue;
-                    const V v = f[(size_t)q * A.nz + i];
-                    const double w = sg * wr[a] * wz[b];
-                    re += w * (double)v.x;
-                    im += w * (double)v.y;
-                }
-            }
-            acc[c] += re * cr - im * ci;
+    const double rho = sqrt(x * x + y * y);
+    // footprint of the block's samples: the nodes inside the grid that their stencils touch
+    int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+    {
+        const double zf = fmin(fmax(floor(z / A.dz), -4.0), (double)A.nz + 4.0);
+        const double rf = fmin(floor(rho / A.dr - 0.5), (double)A.nr + 4.0);
+        const int a = max(0, (int)zf - 1), b = min(A.nz - 1, (int)zf + 2);
+        if (live && a <= b) {
+            fp[0] = a;
+            fp[1] = b;
+            fp[2] = max(0, (int)rf - 1);
+            fp[3] = min(A.nr - 1, max(1, (int)rf + 2));
         }
     }
-    for (int c = 0; c < 6; ++c) A.fields[6 * s + c] = acc[c];
+    block_minmax<GATHER_BLOCK / 64>(fp, red);
+    // Tile rows are ts = tz | 1 values apart: an odd stride puts 16 consecutive rows in distinct LDS bank
+    // groups of 16-byte reads, and the lanes of a wave (samples at about the same z) differ mostly in row.
+    const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1, ts = tz | 1;
+    const bool use_tile = fp[1] >= fp[0] && fp[3] >= fp[2] && (int64_t)ts * tr * 6 * A.nprob <= GATHER_TILE;  // uniform
+    if (use_tile) {
+        const int per = tz * tr, total = per * 6 * A.nprob;
+        for (int e = threadIdx.x; e < total; e += GATHER_BLOCK) {
+            const int pc = e / per, cell = e % per, k = cell / tz, i = cell % tz;
+            const V v = ((const V *)A.plane[pc / 6][pc % 6])[(size_t)(fp[2] + k) * A.nz + fp[0] + i];
+            tile[(pc * tr + k) * ts + i] = double2{(double)v.x, (double)v.y};
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    // e^(i theta) from the position itself (theta = 0 on the axis); e^(i m theta) is its m-th power
+    const double c1 = rho > 0.0 ? x / rho : 1.0, s1 = rho > 0.0 ? y / rho : 0.0;
+    const double zc = z / A.dz, rc = rho / A.dr - 0.5;
+    const int i0 = (int)floor(zc) - 1, k0 = (int)floor(rc) - 1;
+    // Nodes outside the grid get weight zero and an index clamped into the tile (or the plane), so every
+    // read stays in bounds and the loops need no branches; the mirrored rows below the axis take the
+    // component's parity as a sign.
+    const int zlo = use_tile ? fp[0] : 0, zhi = use_tile ? fp[1] : A.nz - 1;
+    const int rlo = use_tile ? fp[2] : 0, rhi = use_tile ? fp[3] : A.nr - 1;
+    double wz[4], wr[4];
+    int col[4], row[4];
+    bool below[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + v, k = k0 + v, q = k < 0 ? -1 - k : k;
+        wz[v] = (i >= 0 && i < A.nz) ? bspline3(i - zc) : 0.0;
+        wr[v] = q < A.nr ? bspline3(k - rc) : 0.0;
+        col[v] = min(max(i, zlo), zhi) - zlo;
+        row[v] = min(max(q, rlo), rhi) - rlo;
+        below[v] = k < 0;
+    }
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        double acc = 0.0;
+        for (int p = 0; p < A.nprob; ++p) {
+            const int m = A.m[p];
+            const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
+            const double par = (c == 2 || c == 5) ? pS : pA;
+            double cr = 1.0, ci = 0.0;
+            for (int j = 0; j < (m < 0 ? -m : m); ++j) {
+                const double t = cr * c1 - ci * s1;
+                ci = cr * s1 + ci * c1;
+                cr = t;
+            }
+            if (m < 0) ci = -ci;
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double wa = below[a] ? par * wr[a] : wr[a];
+                double v[8];
+                if (use_tile) {
+                    const double2 *t = tile + ((p * 6 + c) * tr + row[a]) * ts;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const double2 g = t[col[b]];
+                        v[2 * b] = g.x;
+                        v[2 * b + 1] = g.y;
+                    }
+                } else {
+                    const V *f = (const V *)A.plane[p][c] + (size_t)row[a] * A.nz;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const V g = f[col[b]];
+                        v[2 * b] = g.x;
+                        v[2 * b + 1] = g.y;
+                    }
+                }
+                double rre = 0.0, rim = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    rre += wz[b] * v[2 * b];
+                    rim += wz[b] * v[2 * b + 1];
+                }
+                re += wa * rre;
+                im += wa * rim;
+            }
+            acc += re * cr - im * ci;
+        }
+        A.fields[6 * s + c] = acc;
+    }
 }
 
 }  // namespace
@@ -1196,9 +1317,20 @@ hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s)
     }
 }
 
+hipError_t launch_gather_box(const double *samples, int64_t n, int nz, int nr, double dz, double dr, int *box,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_box_reset, dim3(1), dim3(256), 0, s, box);
+    const int64_t blocks = (n + 255) / 256;
+    if (n > 0) hipLaunchKernelGGL(k_gather_box, dim3((unsigned)(blocks < 512 ? blocks : 512)), dim3(256), 0, s, samples,
+                                  n, nz, nr, dz, dr, box);
+    return hipGetLastError();
+}
+
 hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.nz + 255) / 256), (unsigned)a.nr);
+    if (a.npass <= 0) return hipSuccess;
+    const dim3 grid(512, (unsigned)a.npass);  // grid-stride over the box, one row of blocks per pass
     if (prec == P64) hipLaunchKernelGGL(k_destagger<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_destagger<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -1207,9 +1339,9 @@ hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256));
-    if (prec == P64) hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, s, a);
+    const dim3 grid((unsigned)((a.n + GATHER_BLOCK - 1) / GATHER_BLOCK));
+    if (prec == P64) hipLaunchKernelGGL(k_gather<double>, grid, dim3(GATHER_BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(k_gather<float>, grid, dim3(GATHER_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

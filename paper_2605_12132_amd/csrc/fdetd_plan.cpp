@@ -1237,6 +1237,10 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     }
     if (n == 0) return FDETD_OK;
     const int prec = prec_code(plan->precision);
+    // the nodes and rows the samples' shapes touch; the destagger passes compute only those (grown by the
+    // rows the second pass of B_theta reads from the first)
+    int *box = (int *)((char *)plan->probs[0].buf[1] + plan->probs[0].cells * elem_bytes(plan->precision));
+    HIPCHK(plan, launch_gather_box(samples, n, d0.nz, d0.nr, d0.dz, d0.dr, box, plan->stream));
     GatherArgs G;
     std::memset(&G, 0, sizeof G);
     G.n = n;
@@ -1247,40 +1251,54 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     G.nr = d0.nr;
     G.dz = d0.dz;
     G.dr = d0.dr;
-    for (int p = 0; p < np; ++p) {
-        const Prob &q = plan->probs[p];
-        const size_t pb = q.cells * eb;
-        auto plane = [&](const void *base, int c) { return (const void *)((const char *)base + c * pb); };
-        // destaggered components in buf[0] (E_theta is read from psi), B_theta's z shift in buf[1]
-        DestaggerArgs X;
-        std::memset(&X, 0, sizeof X);
-        X.nz = q.d.nz;
-        X.nr = q.d.nr;
-        X.nd = q.nd;
+    // Destaggered components go to buf[0] (E_theta is read from psi); B_theta's z shift goes to buf[1] and
+    // its rho pass reads that, so it runs in the next launch, beside the independent passes of the next
+    // problem: np + 1 launches in all.
+    DestaggerArgs X;
+    std::memset(&X, 0, sizeof X);
+    X.nz = d0.nz;
+    X.nr = d0.nr;
+    X.box = box;
+    auto coeffs = [&](int set, const Prob &q) {
+        X.nd[set] = q.nd;
         for (int j = 0; j < q.nd; ++j) {
-            X.s[j] = q.s[j];
-            X.c[j] = q.c[j];
+            X.s[set][j] = q.s[j];
+            X.c[set][j] = q.c[j];
         }
-        const int m = q.d.m, pS = (m % 2 == 0) ? 1 : -1, pA = (std::abs(m - 1) % 2 == 0) ? 1 : -1;
-        struct Pass { const void *src; void *dst; int rho, parity, extrapolate; };
-        const Pass passes[6] = {
-            {plane(psi[p], ER), (void *)plane(q.buf[0], ER), 1, pA, m == 1},
-            {plane(psi[p], EZ), (void *)plane(q.buf[0], EZ), 0, 1, 0},
-            {plane(psi[p], BR), (void *)plane(q.buf[0], BR), 0, 1, 0},
-            {plane(psi[p], BTH), (void *)plane(q.buf[1], 0), 0, 1, 0},
-            {plane(q.buf[1], 0), (void *)plane(q.buf[0], BTH), 1, pA, m == 1},
-            {plane(psi[p], BZ), (void *)plane(q.buf[0], BZ), 1, pS, m == 0},
+    };
+    auto plane = [&](const Prob &q, const void *base, int c) {
+        return (void *)((const char *)base + c * q.cells * eb);
+    };
+    auto parities = [](int m, int &pS, int &pA) {
+        pS = (m % 2 == 0) ? 1 : -1;
+        pA = (std::abs(m - 1) % 2 == 0) ? 1 : -1;
+    };
+    for (int p = 0; p <= np; ++p) {
+        X.npass = 0;
+        auto add = [&](const void *src, void *dst, int rho, int parity, int extrapolate, int grow_r, int set) {
+            X.pass[X.npass++] = DestaggerPass{src, dst, rho, parity, extrapolate, grow_r, set};
         };
-        for (const Pass &ps : passes) {
-            X.src = ps.src;
-            X.dst = ps.dst;
-            X.along_rho = ps.rho;
-            X.parity = ps.parity;
-            X.extrapolate = ps.extrapolate;
-            HIPCHK(plan, launch_destagger(prec, X, plan->stream));
+        if (p > 0) {  // B_theta's rho pass of the previous problem
+            const Prob &q = plan->probs[p - 1];
+            int pS, pA;
+            parities(q.d.m, pS, pA);
+            coeffs(1, q);
+            add(plane(q, q.buf[1], 0), plane(q, q.buf[0], BTH), 1, pA, q.d.m == 1, 0, 1);
         }
-        G.m[p] = m;
-        for (int c = 0; c < 6; ++c) G.plane[p][c] = c == ETH ? plane(psi[p], ETH) : plane(q.buf[0], c);
+        if (p < np) {
+            const Prob &q = plan->probs[p];
+            int pS, pA;
+            parities(q.d.m, pS, pA);
+            coeffs(0, q);
+            add(plane(q, psi[p], ER), plane(q, q.buf[0], ER), 1, pA, q.d.m == 1, 0, 0);
+            add(plane(q, psi[p], EZ), plane(q, q.buf[0], EZ), 0, 1, 0, 0, 0);
+            add(plane(q, psi[p], BR), plane(q, q.buf[0], BR), 0, 1, 0, 0, 0);
+            add(plane(q, psi[p], BTH), plane(q, q.buf[1], 0), 0, 1, 0, q.nd, 0);  // read at +-nd rows next
+            add(plane(q, psi[p], BZ), plane(q, q.buf[0], BZ), 1, pS, q.d.m == 0, 0, 0);
+            G.m[p] = q.d.m;
+            for (int c = 0; c < 6; ++c) G.plane[p][c] = c == ETH ? plane(q, psi[p], ETH) : plane(q, q.buf[0], c);
+        }
+        HIPCHK(plan, launch_destagger(prec, X, plan->stream));
     }
     HIPCHK(plan, launch_gather(prec, G, plan->stream));
     return FDETD_OK;

@@ -47,18 +47,21 @@ def run(w, states, s, precision):
     return got
 
 
+@pytest.mark.parametrize("ordered", [False, True])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("order", [8, 16])
-def test_gather_matches_oracle(precision, order):
+def test_gather_matches_oracle(precision, order, ordered):
     w = workload([0, 1, 2], order)
     rng = np.random.default_rng(order + precision)
     states = [rng.uniform(-1, 1, (6, w.nr[0], w.nz[0])) + 1j * rng.uniform(-1, 1, (6, w.nr[0], w.nz[0]))
               for _ in range(w.n)]
     s = samples(rng, 5000, w.nz[0], w.nr[0], w.dz, w.dr)
+    if ordered:  # z order: blocks read their nodes from LDS tiles
+        s = s[np.argsort(s[:, 0], kind="stable")]
     got = run(w, states, s, precision)
     want = oracle.gather(grids(w), states, s)
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    log(f"gather order {order} precision {precision}: max error {err:.2e} of the field scale")
+    log(f"gather order {order} precision {precision} ordered {ordered}: max error {err:.2e} of the field scale")
     assert err < (1e-12 if precision == F.FP64 else 1e-5)
 
 
