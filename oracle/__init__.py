@@ -101,6 +101,7 @@ def lib():
         L.oracle_deposit_current.argtypes = [P, vp, C.c_long, C.c_double, vp, vp]
         L.oracle_destagger.argtypes = [P, vp, vp]
         L.oracle_interpolate.argtypes = [P, vp, vp, C.c_long, vp]
+        L.oracle_gather_fine.argtypes = [P, vp, vp, C.c_long, C.c_int, vp]
         _lib = L
     return _lib
 
@@ -324,6 +325,20 @@ def gather(grids, states, samples):
         prim = destagger(g, psi)
         P = g.c()
         _chk(lib().oracle_interpolate(C.byref(P), _ptr(prim), _ptr(s), s.shape[0], _ptr(out)), "interpolate")
+    return out
+
+
+def gather_fine(grids, states, samples, supersample: int):
+    """Fields at the samples with the resolution doubled before the shape sum (section 3.4): supersample
+    bit 0 along z, bit 1 along rho (0 gives the plain gather); [n, 6] doubles, summed over the modes."""
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    assert s.ndim == 2 and s.shape[1] == 4
+    out = np.zeros((s.shape[0], 6))
+    for g, psi in zip(grids, states):
+        x = _cplx(psi, (6, g.nr, g.nz))
+        P = g.c()
+        _chk(lib().oracle_gather_fine(C.byref(P), _ptr(x), _ptr(s), s.shape[0], int(supersample), _ptr(out)),
+             "gather_fine")
     return out
 
 

@@ -1095,3 +1095,136 @@ int oracle_interpolate(const oracle_problem *P, const double complex *prim, cons
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* 2x supersampled interpolation (section 3.4: the fields' resolution is doubled before the shape */
+/* sum, along z, rho or both).  Reading: the doubled grid of a component is the union of the two  */
+/* position sets of the Yee layout along that direction, primary and staggered, the missing set   */
+/* filled by the same-order Lagrange half shift (S^(+) towards primary, S^(-) towards staggered), */
+/* and the cubic shape is taken in units of the doubled grid's spacing.                           */
+/* ------------------------------------------------------------------------------------------ */
+
+/* S_z^(-): primary z -> staggered z, value at (i - 1/2) dz from columns i + j - 1 and i - j. */
+static void op_shift_minus_z(const oracle_problem *P, const double *s_, int nd, const cplx *in, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += s_[j - 1] * (prim_val(P, in, +1, k, i + j - 1) + prim_val(P, in, +1, k, i - j));
+            out[IDX(P, k, i)] = s;
+        }
+}
+
+/* S_rho^(-) on every staggered row, the axis included: value at k drho from the primary rows k + j - 1
+ * and k - j, rows below the axis mirrored with the parity. */
+static void op_shift_minus_rho_all(const oracle_problem *P, const double *s_, int nd, int parity, const cplx *in,
+                                   cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < P->nr; ++k)
+        for (int i = 0; i < P->nz; ++i) {
+            cplx s = 0.0;
+            for (int j = 1; j <= nd; ++j)
+                s += s_[j - 1] * (prim_val(P, in, parity, k + j - 1, i) + prim_val(P, in, parity, k - j, i));
+            out[IDX(P, k, i)] = s;
+        }
+}
+
+/* Value of component plane set v[zs + 2 rs] (zs, rs = 1: staggered position along z, rho) at row k,
+ * column i: 0 outside the grid; on the axis row of a staggered-rho set of a component whose own rho
+ * position is staggered, the axis rule of section 2.4 (the stored axis slot is not a value). */
+static cplx fine_node(const oracle_problem *P, cplx *const v[4], int own_rs, const double *cax, int nd,
+                      int extrapolate, int zs, int rs, int k, int i)
+{
+    if (i < 0 || i >= P->nz || k >= P->nr) return 0.0;
+    const cplx *f = v[zs + 2 * rs];
+    if (rs == 1 && k == 0 && own_rs == 1) return axis_value(P, cax, nd, f, i, extrapolate);
+    return f[IDX(P, k, i)];
+}
+
+int oracle_gather_fine(const oracle_problem *P, const double complex *psi, const double *samples, long n, int ss,
+                       double *fields)
+{
+    if (check_problem(P) || n < 0 || ss < 0 || ss > 3) return -1;
+    const int nd = P->fd_order / 2, m = P->m, nz = P->nz, nr = P->nr;
+    const size_t np = (size_t)nr * nz;
+    double s[16], c[16];
+    oracle_coef_halfshift(nd, s);
+    oracle_coef_axis(nd, c);
+    const int pS = parity_mS(m), pA = parity_mA(m);
+    /* own positions (Table 1): z staggered for E_z, B_rho, B_theta; rho staggered for E_rho, B_theta, B_z */
+    const int own_z[6] = {0, 0, 1, 1, 1, 0}, own_r[6] = {1, 0, 0, 0, 1, 1};
+    const int par[6] = {pA, pA, pS, pA, pA, pS};
+    const int extrap[6] = {m == 1, 0, 0, 0, m == 1, m == 0};
+    cplx *buf = malloc(6 * 4 * np * sizeof(cplx));
+    if (!buf) return -2;
+    cplx *v[6][4];
+    for (int f = 0; f < 6; ++f) {
+        for (int t = 0; t < 4; ++t) v[f][t] = buf + (4 * f + t) * np;
+        const int zn = own_z[f], rn = own_r[f], zo = 1 - zn, ro = 1 - rn;
+        memcpy(v[f][zn + 2 * rn], psi + f * np, np * sizeof(cplx));
+        /* along z first, then along rho (the two commute) */
+        if (zn) op_shift_plus_z(P, s, nd, v[f][zn + 2 * rn], v[f][zo + 2 * rn]);
+        else op_shift_minus_z(P, s, nd, v[f][zn + 2 * rn], v[f][zo + 2 * rn]);
+        for (int zs = 0; zs < 2; ++zs) {
+            if (rn) op_shift_plus_rho(P, s, c, nd, par[f], extrap[f], v[f][zs + 2 * rn], v[f][zs + 2 * ro]);
+            else op_shift_minus_rho_all(P, s, nd, par[f], v[f][zs + 2 * rn], v[f][zs + 2 * ro]);
+        }
+    }
+    const int sz = ss & 1, sr = (ss >> 1) & 1;
+    for (long q = 0; q < n; ++q) {
+        const double z = samples[4 * q], x = samples[4 * q + 1], y = samples[4 * q + 2];
+        const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+        const cplx rot = cexp(I * (double)m * th);
+        /* nodes: along z, u dz/2 (doubled: odd u staggered at column (u+1)/2, even u primary at u/2) or
+         * i dz; along rho, g drho/2 (doubled: even g staggered row g/2, odd g primary row (g-1)/2, g < 0
+         * the mirror of -g) or (k + 1/2) drho (k < 0 the mirror of row -1-k) */
+        const int nzn = sz ? 2 * nz + 1 : nz, nrn = sr ? 2 * nr : nr;
+        for (int f = 0; f < 6; ++f) {
+            cplx acc = 0.0;
+            for (int a = -nrn; a < nrn; ++a) {
+                double wr;
+                int rs, k, sign = 1;
+                if (sr) {
+                    wr = bspline3(a - 2.0 * rho / P->dr);
+                    int g = a;
+                    if (g < 0) {
+                        g = -g;
+                        sign = par[f];
+                    }
+                    rs = (g % 2 == 0);
+                    k = rs ? g / 2 : (g - 1) / 2;
+                } else {
+                    wr = bspline3(a + 0.5 - rho / P->dr);
+                    rs = 0;
+                    k = a;
+                    if (k < 0) {
+                        k = -1 - k;
+                        sign = par[f];
+                    }
+                }
+                if (wr == 0.0) continue;
+                for (int b = -1; b < nzn; ++b) {
+                    double wz;
+                    int zs, i;
+                    if (sz) {
+                        wz = bspline3(b - 2.0 * z / P->dz);
+                        zs = (b % 2 != 0);
+                        i = zs ? (b + 1) / 2 : b / 2;
+                    } else {
+                        wz = bspline3(b - z / P->dz);
+                        zs = 0;
+                        i = b;
+                    }
+                    if (wz == 0.0) continue;
+                    acc += wz * wr * (double)sign * fine_node(P, v[f], own_r[f], c, nd, extrap[f], zs, rs, k, i);
+                }
+            }
+            fields[6 * q + f] += creal(acc * rot);
+        }
+    }
+    free(buf);
+    return 0;
+}

@@ -114,6 +114,10 @@ int oracle_deposit_current(const oracle_problem *P, const double *samples, long 
 int oracle_destagger(const oracle_problem *P, const double complex *psi, double complex *out);
 int oracle_interpolate(const oracle_problem *P, const double complex *prim, const double *samples, long n,
                        double *fields);
+/* The same with the fields' resolution doubled before the shape sum (section 3.4): ss bit 0 along z,
+ * bit 1 along rho (ss = 0: the plain interpolation); the mode's value at each sample is added into fields. */
+int oracle_gather_fine(const oracle_problem *P, const double complex *psi, const double *samples, long n, int ss,
+                       double *fields);
 
 int oracle_num_threads(void);
 
