@@ -229,6 +229,22 @@ FDETD_API int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_
  * Enqueue only. */
 FDETD_API int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields);
 
+/* fdetd_gather with the fields' resolution doubled before the shape sum (2x supersampling, section 3.4):
+ * supersample bit 0 doubles z, bit 1 doubles rho (0: fdetd_gather itself).  Along a doubled direction a
+ * component's nodes are both position sets of the staggered layout, primary and staggered, half a cell
+ * apart; the set it is not stored on is filled by a Lagrange half shift of the same order (S^(+) towards
+ * primary, S^(-) towards staggered: along z from columns i + j - 1 and i - j, along rho from rows k + j - 1
+ * and k - j, the rows below the axis mirrored with the parity, the axis row included), z shifts before rho
+ * shifts.  The axis row of a staggered-rho set of a component stored there (E_rho, B_theta, B_z) is the
+ * axis rule (extrapolated or 0, as for destaggering).  The cubic shapes are taken in units of the doubled
+ * grid, whose rho nodes g drho/2 extend below the axis as parity times node -g:
+ *   fields[s][c] = sum_m Re( e^(i m theta_s) sum_(u,g) S3(u - 2 z_s/dz) S3(g - 2 rho_s/dr) F_m,c(u, g) )
+ * (a direction not doubled keeps the nodes of fdetd_gather).  Arguments as for fdetd_gather.  The plan
+ * allocates 24 planes per problem on the first call (kept until fdetd_destroy; FDETD_E_NOMEM if that
+ * fails); FDETD_E_ARG for supersample outside 0..3.  Enqueue only. */
+FDETD_API int fdetd_gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n,
+                                        double *fields, int32_t supersample);
+
 /* Ponderomotive field of the envelope model (section 4.3) for the m = 0 problems of an envelope plan:
  *   out[p] plane 0: |a|^2 on the primary grid,
  *          plane 1: A~_rho = -D_rho^(-,mS) |a|^2 on the staggered rho rows k >= 1 (row 0 = 0),

@@ -7,5 +7,5 @@ from .binding import (ENVELOPE, FP32C, FP64, MAXWELL, PLAN_CURRENT_CORRECTION, P
                       PLAN_ONE_STREAM, PLAN_PROFILE, PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, FdetdError, Plan, Problem,
                       envelope_absorber, envelope_ponderomotive, envelope_step, fdetd_coefficients,
                       fdetd_deposit_current, fdetd_deposit_jz, fdetd_deposit_rho, fdetd_destroy, fdetd_export_state,
-                      fdetd_gather, fdetd_import_state, fdetd_last_error, fdetd_plan, fdetd_query, fdetd_step,
+                      fdetd_gather, fdetd_gather_supersampled, fdetd_import_state, fdetd_last_error, fdetd_plan, fdetd_query, fdetd_step,
                       fdetd_taylor_stability_bound)

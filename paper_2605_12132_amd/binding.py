@@ -24,7 +24,7 @@ PLAN_CURRENT_CORRECTION = 32
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
            "fdetd_deposit_jz", "fdetd_deposit_rho",
-           "fdetd_deposit_current", "fdetd_gather", "fdetd_query",
+           "fdetd_deposit_current", "fdetd_gather", "fdetd_gather_supersampled", "fdetd_query",
            "fdetd_export_state",
            "fdetd_import_state", "fdetd_coefficients", "fdetd_taylor_stability_bound", "fdetd_last_error",
            "fdetd_destroy")
@@ -85,6 +85,7 @@ def _load():
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
+    L.fdetd_gather_supersampled.argtypes = [vp, pp, vp, C.c_int64, vp, C.c_int32]
     L.envelope_ponderomotive.argtypes = [vp, pp, pp]
     L.fdetd_deposit_current.argtypes = [vp, vp, C.c_int64, C.c_double, pp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
@@ -159,6 +160,10 @@ def envelope_ponderomotive(plan, a_ptrs, out_ptrs):
 
 def fdetd_gather(plan, psi_ptrs, samples_ptr, n: int, fields_ptr):
     _check(lib.fdetd_gather(plan, _ptrs(psi_ptrs), samples_ptr, n, fields_ptr), plan)
+
+
+def fdetd_gather_supersampled(plan, psi_ptrs, samples_ptr, n: int, fields_ptr, supersample: int):
+    _check(lib.fdetd_gather_supersampled(plan, _ptrs(psi_ptrs), samples_ptr, n, fields_ptr, supersample), plan)
 
 
 def envelope_absorber(plan, problem: int, lz: int, lr: int, sigma_max: float, power: float = 2.0):
@@ -287,9 +292,10 @@ class Plan:
         rp = [self._chk(x, (p.nr, p.nz), self._cdtype(), "rho") for x, p in zip(rho, self.problems)]
         fdetd_deposit_rho(self._h, samples.data_ptr(), samples.shape[0], dz_shift, eps, rp)
 
-    def gather(self, psi, samples, fields=None):
+    def gather(self, psi, samples, fields=None, supersample: int = 0):
         """Fields (float64 [n, 6] cuda tensor: E_rho, E_theta, E_z, B_rho, B_theta, B_z) at the samples
-        (float64 [n, 4] cuda tensor of z, x, y, w) of the plan's modes of one grid."""
+        (float64 [n, 4] cuda tensor of z, x, y, w) of the plan's modes of one grid; supersample: bit 0
+        doubles the resolution along z, bit 1 along rho, before the shape sum."""
         import torch
         if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 4
                 and samples.is_contiguous()):
@@ -301,7 +307,11 @@ class Plan:
         if not (fields.is_cuda and fields.dtype == torch.float64 and fields.is_contiguous()
                 and tuple(fields.shape) == (samples.shape[0], 6)):
             raise ValueError("fields: contiguous float64 cuda tensor [n, 6]")
-        fdetd_gather(self._h, pp, samples.data_ptr(), samples.shape[0], fields.data_ptr())
+        if supersample:
+            fdetd_gather_supersampled(self._h, pp, samples.data_ptr(), samples.shape[0], fields.data_ptr(),
+                                      int(supersample))
+        else:
+            fdetd_gather(self._h, pp, samples.data_ptr(), samples.shape[0], fields.data_ptr())
         return fields
 
     def envelope_step(self, a, a_tilde, chi, n_steps: int = 1):

@@ -196,10 +196,11 @@ struct DestaggerPass {
     const void *src;
     void *dst;
     int along_rho, parity, extrapolate;
-    int grow_r;  // rows beyond the box to compute as well
-    int set;     // coefficient set (0 or 1) of the problem the planes belong to
+    int to_stag;  // 0: staggered -> primary positions (S^(+)); 1: primary -> staggered (S^(-), 2x supersampling)
+    int grow_r;   // rows beyond the box to compute as well
+    int set;      // coefficient set (0 or 1) of the problem the planes belong to
 };
-constexpr int kMaxDestaggerPass = 6;
+constexpr int kMaxDestaggerPass = 18;
 // One launch runs up to kMaxDestaggerPass independent passes (blockIdx.y), over the cells of the box.
 struct DestaggerArgs {
     int nz, nr, npass;
@@ -222,7 +223,15 @@ struct GatherArgs {
     int nprob, nz, nr;
     double dz, dr;
     int m[kMaxGather];
-    const void *plane[kMaxGather][6];  // the destaggered components on the primary grid
+    const void *plane[kMaxGather][6];  // the destaggered components on the primary grid; 2x supersampling:
+                                       // the components as stored (the state's planes)
+    // 2x supersampling only: plane sets of the doubled grids, component c's set (zs, rs) (1 = staggered
+    // position along z, rho) at fine[p] + (4 c + zs + 2 rs) * plane_bytes unless it is the stored one
+    int ss;                            // bit 0: z doubled, bit 1: rho doubled
+    size_t plane_bytes;
+    const void *fine[kMaxGather];
+    const double *cax[kMaxGather];     // axis extrapolation weights c_k' (device)
+    int nd[kMaxGather];
 };
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 

@@ -1039,6 +1039,10 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrectArgs A)
 //   along rho: out(k, i) = sum_j s_j (f(k + j, i) + f(k - j + 1, i)) on the staggered rows, row 0 = the
 //              axis value (sum_k' c_k' f(k', i) when extrapolated, else 0), rows q < 0 = parity f(-q),
 //              rows >= nr are 0.  FP64 arithmetic, storage precision in and out.
+// 2x supersampling also shifts the other way (to_stag), primary to staggered positions:
+//   along z:   out(k, i) = sum_j s_j (f(k, i + j - 1) + f(k, i - j)),
+//   along rho: out(k, i) = sum_j s_j (f(k + j - 1, i) + f(k - j, i)) for every k >= 0, rows q < 0 =
+//              parity f(-1-q).
 // --------------------------------------------------------------------------------------------------
 // The footprint box of the samples: one thread per sample, block reductions, then global atomics.
 __global__ __launch_bounds__(256) void k_gather_box_reset(int *box)
@@ -1103,13 +1107,24 @@ __global__ __launch_bounds__(256) void k_destagger(DestaggerArgs A)
         if (!P.along_rho) {
 #pragma unroll 4
             for (int j = 1; j <= nd; ++j) {
-                const int c0 = i + j, c1 = i - j + 1;
+                const int c0 = i + j - P.to_stag, c1 = i - j + 1 - P.to_stag;
                 const double2 v0 = at(k, min(c0, A.nz - 1)), v1 = at(k, max(c1, 0));
                 const double w0 = c0 < A.nz ? sw[j - 1] : 0.0, w1 = c1 >= 0 ? sw[j - 1] : 0.0;
                 re += w0 * v0.x;
                 im += w0 * v0.y;
                 re += w1 * v1.x;
                 im += w1 * v1.y;
+            }
+        } else if (P.to_stag) {
+            // primary rows k + j - 1 and k - j to the staggered row k (the axis for k = 0); rows below the
+            // axis mirror row -1-q with the parity, rows >= nr are 0
+#pragma unroll 4
+            for (int j = 1; j <= nd; ++j) {
+                const int q0 = k + j - 1, q1 = k - j, a1 = q1 < 0 ? -1 - q1 : q1;
+                const double2 v0 = at(min(q0, A.nr - 1), i), v1 = at(min(a1, A.nr - 1), i);
+                const double g0 = q0 < A.nr ? 1.0 : 0.0, g1 = a1 >= A.nr ? 0.0 : (q1 < 0 ? (double)P.parity : 1.0);
+                re += sw[j - 1] * (g0 * v0.x + g1 * v1.x);
+                im += sw[j - 1] * (g0 * v0.y + g1 * v1.y);
             }
         } else {
             double axr = 0.0, axi = 0.0;
@@ -1261,6 +1276,108 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
     }
 }
 
+// Interpolation on the doubled grid (2x supersampling, section 3.4; SS bit 0: z, bit 1: rho), one thread
+// per sample, reading the plane sets directly.  Doubled along z the nodes are u dz/2 (odd u: staggered
+// column (u+1)/2, even u: primary column u/2); doubled along rho they are g drho/2 (even g: staggered row
+// g/2, the axis for g = 0; odd g: primary row (g-1)/2; g < 0 the mirror of -g with the parity); a
+// direction not doubled keeps the primary nodes.  The cubic shape is in units of the node spacing.  On
+// the axis row of a staggered-rho set of a component whose own rho position is staggered the value is
+// the axis rule (the stored axis slot is not a value).
+template <typename R, int SS>
+__global__ __launch_bounds__(256) void k_gather_fine(GatherArgs A)
+{
+    using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= A.n) return;
+    const double z = A.samples[4 * s], x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+    const double rho = sqrt(x * x + y * y);
+    const double c1 = rho > 0.0 ? x / rho : 1.0, s1 = rho > 0.0 ? y / rho : 0.0;
+    double wz[4], wr[4];
+    int col[4], zsb[4], row[4], rsb[4];
+    bool below[4];
+    {
+        const double zc = (SS & 1) ? 2.0 * z / A.dz : z / A.dz;
+        const int u0 = (int)floor(zc) - 1;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int u = u0 + b, zs = (SS & 1) ? (u & 1) : 0, i = (SS & 1) ? (u + zs) >> 1 : u;
+            wz[b] = (i >= 0 && i < A.nz) ? bspline3(u - zc) : 0.0;
+            col[b] = min(max(i, 0), A.nz - 1);
+            zsb[b] = zs;
+        }
+        const double rc = (SS & 2) ? 2.0 * rho / A.dr : rho / A.dr - 0.5;
+        const int g0 = (int)floor(rc) - 1;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int g = g0 + a;
+            int rs, k;
+            if (SS & 2) {
+                const int gg = g < 0 ? -g : g;
+                rs = (gg & 1) ? 0 : 1;
+                k = rs ? gg >> 1 : (gg - 1) >> 1;
+            } else {
+                rs = 0;
+                k = g < 0 ? -1 - g : g;
+            }
+            wr[a] = k < A.nr ? bspline3(g - rc) : 0.0;
+            row[a] = min(k, A.nr - 1);
+            rsb[a] = rs;
+            below[a] = g < 0;
+        }
+    }
+    // own positions (Table 1): z staggered for E_z, B_rho, B_theta; rho staggered for E_rho, B_theta, B_z
+    constexpr int own_z[6] = {0, 0, 1, 1, 1, 0}, own_r[6] = {1, 0, 0, 0, 1, 1};
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        double acc = 0.0;
+        for (int p = 0; p < A.nprob; ++p) {
+            const int m = A.m[p];
+            const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
+            const double par = (c == 2 || c == 5) ? pS : pA;
+            const bool extrap = (c == 0 || c == 4) ? m == 1 : (c == 5 ? m == 0 : false);
+            const int own = own_z[c] + 2 * own_r[c];
+            double cr = 1.0, ci = 0.0;
+            for (int j = 0; j < (m < 0 ? -m : m); ++j) {
+                const double t = cr * c1 - ci * s1;
+                ci = cr * s1 + ci * c1;
+                cr = t;
+            }
+            if (m < 0) ci = -ci;
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double wa = below[a] ? par * wr[a] : wr[a];
+                double rre = 0.0, rim = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int v = zsb[b] + 2 * rsb[a];
+                    const V *f = v == own ? (const V *)A.plane[p][c]
+                                          : (const V *)((const char *)A.fine[p] + (size_t)(4 * c + v) * A.plane_bytes);
+                    double vx = 0.0, vy = 0.0;
+                    if (rsb[a] == 1 && row[a] == 0 && own_r[c] == 1) {
+                        if (extrap)
+                            for (int q = 1; q <= A.nd[p] && q < A.nr; ++q) {
+                                const V g = f[(size_t)q * A.nz + col[b]];
+                                vx += A.cax[p][q - 1] * (double)g.x;
+                                vy += A.cax[p][q - 1] * (double)g.y;
+                            }
+                    } else {
+                        const V g = f[(size_t)row[a] * A.nz + col[b]];
+                        vx = g.x;
+                        vy = g.y;
+                    }
+                    rre += wz[b] * vx;
+                    rim += wz[b] * vy;
+                }
+                re += wa * rre;
+                im += wa * rim;
+            }
+            acc += re * cr - im * ci;
+        }
+        A.fields[6 * s + c] = acc;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,
@@ -1339,6 +1456,17 @@ hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s)
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
+    if (a.ss != 0) {
+        const dim3 grid((unsigned)((a.n + 255) / 256));
+#define FDETD_FINE(SS)                                                                            \
+    if (a.ss == SS) {                                                                             \
+        if (prec == P64) hipLaunchKernelGGL((k_gather_fine<double, SS>), grid, dim3(256), 0, s, a); \
+        else hipLaunchKernelGGL((k_gather_fine<float, SS>), grid, dim3(256), 0, s, a);             \
+    }
+        FDETD_FINE(1) FDETD_FINE(2) FDETD_FINE(3)
+#undef FDETD_FINE
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((a.n + GATHER_BLOCK - 1) / GATHER_BLOCK));
     if (prec == P64) hipLaunchKernelGGL(k_gather<double>, grid, dim3(GATHER_BLOCK), 0, s, a);
     else hipLaunchKernelGGL(k_gather<float>, grid, dim3(GATHER_BLOCK), 0, s, a);

@@ -44,6 +44,8 @@ struct Prob {
     double *gresp = nullptr;              // ... segment responses, forward then backward ([nr][nd] each)
     int seg = 0, nseg = 0;                // ... rows per segment of the partitioned solve, segments
     void *jth = nullptr;                  // current correction: corrected J_theta plane
+    void *fine = nullptr;                 // 2x supersampled gather: 24 planes (4 position sets per component),
+                                          // allocated on first use
     int lz = 0, lr = 0;                   // its widths (0, 0: no layer)
     double a[kMaxND], s[kMaxND], d1[kMaxND], d2[kMaxND + 1], c[kMaxND];
     const void *last_state = nullptr;   // psi (or a) of the previous call, for the FP32C reset rule
@@ -135,6 +137,7 @@ void free_prob(Prob &q)
     if (q.gresp) (void)hipFree(q.gresp);
     if (q.jth) (void)hipFree(q.jth);
     if (q.sr) (void)hipFree(q.sr);
+    if (q.fine) (void)hipFree(q.fine);
     q = Prob{};
 }
 
@@ -1219,9 +1222,30 @@ int fdetd_deposit_rho(fdetd_plan_t plan, const double *samples, int64_t n, doubl
     return FDETD_OK;
 }
 
+namespace {
+int gather_impl(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields, int ss);
+int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields,
+                        int ss, int *box);
+}
+
+int fdetd_gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n,
+                              double *fields, int32_t supersample)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_gather_supersampled: NULL plan");
+    if (supersample < 0 || supersample > 3)
+        return fail(plan, FDETD_E_ARG, "fdetd_gather_supersampled: supersample %d not in 0..3", supersample);
+    return gather_impl(plan, psi, samples, n, fields, supersample);
+}
+
 int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_gather: NULL plan");
+    return gather_impl(plan, psi, samples, n, fields, 0);
+}
+
+namespace {
+int gather_impl(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields, int ss)
+{
     if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_gather: plan is not a Maxwell plan");
     const int np = (int)plan->probs.size();
     if (!psi || n < 0 || (n > 0 && (!aligned(samples, 8) || !aligned(fields, 8))))
@@ -1241,6 +1265,7 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     // rows the second pass of B_theta reads from the first)
     int *box = (int *)((char *)plan->probs[0].buf[1] + plan->probs[0].cells * elem_bytes(plan->precision));
     HIPCHK(plan, launch_gather_box(samples, n, d0.nz, d0.nr, d0.dz, d0.dr, box, plan->stream));
+    if (ss != 0) return gather_supersampled(plan, psi, samples, n, fields, ss, box);
     GatherArgs G;
     std::memset(&G, 0, sizeof G);
     G.n = n;
@@ -1276,7 +1301,7 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     for (int p = 0; p <= np; ++p) {
         X.npass = 0;
         auto add = [&](const void *src, void *dst, int rho, int parity, int extrapolate, int grow_r, int set) {
-            X.pass[X.npass++] = DestaggerPass{src, dst, rho, parity, extrapolate, grow_r, set};
+            X.pass[X.npass++] = DestaggerPass{src, dst, rho, parity, extrapolate, 0, grow_r, set};
         };
         if (p > 0) {  // B_theta's rho pass of the previous problem
             const Prob &q = plan->probs[p - 1];
@@ -1303,6 +1328,98 @@ int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *samples, int
     HIPCHK(plan, launch_gather(prec, G, plan->stream));
     return FDETD_OK;
 }
+
+// 2x supersampling: for each component the position sets (zs, rs) the doubled grid needs (zs over {0, 1}
+// when z is doubled, else {0}; rs likewise), each made from the stored set by at most one half shift along
+// z followed by one along rho.  Level 1 shifts the stored planes (z shifts computed on rows grown by N_D,
+// which the level-2 rho shifts and the axis rule read); level 2 shifts level 1's z output along rho.  Level
+// 2 of problem p - 1 shares a launch with level 1 of problem p.
+int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields,
+                        int ss, int *box)
+{
+    const int np = (int)plan->probs.size();
+    const size_t eb = elem_bytes(plan->precision);
+    const int prec = prec_code(plan->precision);
+    const fdetd_problem_desc &d0 = plan->probs[0].d;
+    for (int p = 0; p < np; ++p) {
+        Prob &q = plan->probs[p];
+        if (!q.fine && hipMalloc(&q.fine, 24 * q.cells * eb) != hipSuccess) {
+            q.fine = nullptr;
+            (void)hipGetLastError();
+            return fail(plan, FDETD_E_NOMEM, "fdetd_gather_supersampled: no memory for the doubled grids");
+        }
+    }
+    // device table entry of each problem (axis weights)
+    std::vector<int> entry(np, 0);
+    for (const Batch &b : plan->batches)
+        for (int t = 0; t < b.count; ++t) entry[b.members[t]] = b.d0 + t;
+    static const int own_z[6] = {0, 0, 1, 1, 1, 0}, own_r[6] = {1, 0, 0, 0, 1, 1};
+    const bool dz2 = ss & 1, dr2 = ss & 2;
+    auto needed = [&](int zs, int rs) { return (zs == 0 || dz2) && (rs == 0 || dr2); };
+    DestaggerArgs X;
+    std::memset(&X, 0, sizeof X);
+    X.nz = d0.nz;
+    X.nr = d0.nr;
+    X.box = box;
+    auto coeffs = [&](int set, const Prob &q) {
+        X.nd[set] = q.nd;
+        for (int j = 0; j < q.nd; ++j) {
+            X.s[set][j] = q.s[j];
+            X.c[set][j] = q.c[j];
+        }
+    };
+    for (int p = 0; p <= np; ++p) {
+        X.npass = 0;
+        for (int lvl = 2; lvl >= 1; --lvl) {
+            const int pp = lvl == 2 ? p - 1 : p, set = lvl == 2 ? 1 : 0;
+            if (pp < 0 || pp >= np) continue;
+            const Prob &q = plan->probs[pp];
+            coeffs(set, q);
+            const int m = q.d.m, pS = (m % 2 == 0) ? 1 : -1, pA = (std::abs(m - 1) % 2 == 0) ? 1 : -1;
+            const size_t pb = q.cells * eb;
+            auto fine = [&](int c, int zs, int rs) { return (void *)((char *)q.fine + (4 * c + zs + 2 * rs) * pb); };
+            for (int c = 0; c < 6; ++c) {
+                const int zn = own_z[c], rn = own_r[c], par = (c == EZ || c == BZ) ? pS : pA;
+                const int ext = (c == ER || c == BTH) ? m == 1 : (c == BZ ? m == 0 : 0);
+                const void *stored = (const char *)psi[pp] + c * pb;
+                auto add = [&](const void *src, void *dst, int rho, int to_stag, int grow_r) {
+                    X.pass[X.npass++] = DestaggerPass{src, dst, rho, par, rho ? ext : 0, to_stag, grow_r, set};
+                };
+                if (lvl == 1) {
+                    if (needed(1 - zn, 0) || needed(1 - zn, 1))
+                        add(stored, fine(c, 1 - zn, rn), 0, zn == 0, q.nd);
+                    if (needed(zn, 1 - rn)) add(stored, fine(c, zn, 1 - rn), 1, rn == 0, 0);
+                } else if (needed(1 - zn, 1 - rn)) {
+                    add(fine(c, 1 - zn, rn), fine(c, 1 - zn, 1 - rn), 1, rn == 0, 0);
+                }
+            }
+        }
+        HIPCHK(plan, launch_destagger(prec, X, plan->stream));
+    }
+    GatherArgs G;
+    std::memset(&G, 0, sizeof G);
+    G.n = n;
+    G.samples = samples;
+    G.fields = fields;
+    G.nprob = np;
+    G.nz = d0.nz;
+    G.nr = d0.nr;
+    G.dz = d0.dz;
+    G.dr = d0.dr;
+    G.ss = ss;
+    G.plane_bytes = plan->probs[0].cells * eb;
+    for (int p = 0; p < np; ++p) {
+        const Prob &q = plan->probs[p];
+        G.m[p] = q.d.m;
+        for (int c = 0; c < 6; ++c) G.plane[p][c] = (const char *)psi[p] + c * G.plane_bytes;
+        G.fine[p] = q.fine;
+        G.cax[p] = (const double *)((const char *)(plan->ddesc + entry[p]) + offsetof(ProbDesc, cax));
+        G.nd[p] = q.nd;
+    }
+    HIPCHK(plan, launch_gather(prec, G, plan->stream));
+    return FDETD_OK;
+}
+}  // namespace
 
 int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, void *const *out)
 {

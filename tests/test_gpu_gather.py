@@ -1,7 +1,8 @@
 """GPU field interpolation at sample positions (fdetd_gather: destaggering, then cubic shapes over the
 grid extended below the axis, summed over the modes; section 3.3) against the oracle, and against exact
 values for states whose interpolation is exact.  FP64 to 1e-12 of the field scale; FP32C (destaggered
-planes stored as floats) to 1e-5."""
+planes stored as floats) to 1e-5.  The same for 2x supersampling along z, rho and both
+(fdetd_gather_supersampled, section 3.4) against the oracle's doubled-grid gather."""
 import math
 
 import numpy as np
@@ -36,11 +37,11 @@ def samples(rng, n, nz, nr, dz, dr):
     return np.stack([z, r * np.cos(th), r * np.sin(th), np.ones(n)], axis=1)
 
 
-def run(w, states, s, precision):
+def run(w, states, s, precision, supersample=0):
     import torch
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
-    out = plan.gather([dev(x, cd) for x in states], dev(s, torch.float64))
+    out = plan.gather([dev(x, cd) for x in states], dev(s, torch.float64), supersample=supersample)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     plan.close()
@@ -117,3 +118,53 @@ def test_gather_after_steps_and_argument_checks():
                      torch.zeros((6, 30, 120), dtype=torch.complex128, device="cuda")],
                     torch.zeros((4, 4), dtype=torch.float64, device="cuda"))
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("order", [8, 16])
+def test_supersampled_gather_matches_oracle(precision, order):
+    """One plan, the three doublings in turn and the plain gather after them (the doubled-grid planes are
+    reused across calls)."""
+    import torch
+    w = workload([0, 1, 2], order)
+    rng = np.random.default_rng(40 + order + precision)
+    states = [rng.uniform(-1, 1, (6, w.nr[0], w.nz[0])) + 1j * rng.uniform(-1, 1, (6, w.nr[0], w.nz[0]))
+              for _ in range(w.n)]
+    s = samples(rng, 3000, w.nz[0], w.nr[0], w.dz, w.dr)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    psi = [dev(x, cd) for x in states]
+    sd = dev(s, torch.float64)
+    for ss in (1, 2, 3, 0):
+        got = plan.gather(psi, sd, supersample=ss).cpu().numpy()
+        want = oracle.gather_fine(grids(w), states, s, ss)
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        log(f"supersampled gather {ss} order {order} precision {precision}: max error {err:.2e} of the field scale")
+        assert err < (1e-12 if precision == F.FP64 else 1e-5), ss
+    with pytest.raises(F.FdetdError):
+        plan.gather(psi, sd, supersample=4)
+    plan.close()
+
+
+@pytest.mark.parametrize("ss", [1, 2, 3])
+def test_supersampled_gather_exact_for_linear_fields(ss):
+    w = workload([0, 1], 8, nz=90, nr=36)
+    rng = np.random.default_rng(70 + ss)
+    Fs = [rng.standard_normal((6, 2)) + 1j * rng.standard_normal((6, 2)) for _ in range(2)]
+    gs = grids(w)
+    states = [staggered_state(g, Fm) for g, Fm in zip(gs, Fs)]
+    nd = 4
+    z = rng.uniform((nd + 3) * w.dz, (w.nz[0] - nd - 4) * w.dz, 2000)
+    r = rng.uniform(0, (w.nr[0] - nd - 3) * w.dr, 2000)
+    r[:300] = rng.uniform(0, 1.5 * w.dr, 300)  # nodes on and below the axis
+    th = rng.uniform(-math.pi, math.pi, 2000)
+    s = np.stack([z, r * np.cos(th), r * np.sin(th), np.ones(2000)], axis=1)
+    got = run(w, states, s, F.FP64, supersample=ss)
+    for c in range(6):
+        want = 0.0
+        for m, Fm in ((0, Fs[0]), (1, Fs[1])):
+            pS = 1 if m % 2 == 0 else -1
+            pA = 1 if abs(m - 1) % 2 == 0 else -1
+            odd = (pA if POLAR[c] else pS) == -1
+            want = want + np.real((r if odd else 1.0) * (Fm[c, 0] + Fm[c, 1] * z / 5) * np.exp(1j * m * th))
+        assert np.max(np.abs(got[:, c] - want)) < 1e-11 * max(1.0, np.max(np.abs(want))), (ss, c)
