@@ -410,8 +410,8 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
     of peak density n_b) moving at c, in z order, deposited with fdetd_deposit_jz (timed separately,
     including the advance of the sample positions), then graph replay of `steps` field steps, then the fields of the
-    final state at the samples (fdetd_gather, timed apart).  FP64 and FP32C; the FP32C error against FP64
-    after the same steps."""
+    final state at the samples (fdetd_gather, timed apart, also with 2x supersampling along z and rho).  FP64
+    and FP32C; the FP32C error against FP64 after the same steps."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -460,14 +460,25 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
             ev1.record(stream)
             torch.cuda.synchronize()
             gather_ms = ev0.elapsed_time(ev1) / 5
+            # the same with 2x supersampling along z and rho (fdetd_gather_supersampled)
+            plan.gather(psi, smp, fields, supersample=3)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                plan.gather(psi, smp, fields, supersample=3)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            gather_ss_ms = ev0.elapsed_time(ev1) / 5
             plan.close()
         gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
         res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
                         frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms, gather_ms=gather_ms,
+                        gather_supersampled_ms=gather_ss_ms,
                         seg_rows=info["seg_rows"])
         psis[tag] = psi
         log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
-            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step; gather {gather_ms:.3f} ms")
+            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step; gather {gather_ms:.3f} ms, "
+            f"2x supersampled (z and rho) {gather_ss_ms:.3f} ms")
     num = den = 0.0
     for a, b in zip(psis["fp64"], psis["fp32c"]):
         num += float(torch.sum(torch.abs(a - b.to(torch.complex128)) ** 2))
