@@ -71,6 +71,23 @@ def test_plan_rejects_bad_problems_before_touching_the_gpu(bad):
     assert "problem 0" in F.fdetd_last_error(None)
 
 
+def test_entry_points_reject_a_null_plan():
+    """Every call that takes a plan fails cleanly with FDETD_E_ARG on NULL, before any HIP call."""
+    calls = [
+        lambda: F.fdetd_gather(None, [0], 0, 0, 0),
+        lambda: F.fdetd_gather_supersampled(None, [0], 0, 0, 0, 3),
+        lambda: F.fdetd_deposit_rho(None, 0, 0, 0.0, 0.5, [0]),
+        lambda: F.fdetd_deposit_current(None, 0, 0, 0.5, [0]),
+        lambda: F.envelope_ponderomotive(None, [0], [0]),
+        lambda: F.envelope_absorber(None, -1, 4, 4, 1.0, 2.0),
+    ]
+    for call in calls:
+        with pytest.raises(F.FdetdError) as e:
+            call()
+        assert e.value.code == binding.FDETD_E_ARG
+        assert "NULL plan" in F.fdetd_last_error(None)
+
+
 def test_plan_rejects_mixed_kinds_and_bad_flags():
     a = F.Problem(64, 32, 0, 8, 4, 0.3, 0.6, 0.15)
     b = F.Problem(64, 32, 0, 8, 4, 0.3, 0.6, 0.15, kind=F.ENVELOPE)
