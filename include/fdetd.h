@@ -241,7 +241,7 @@ FDETD_API int fdetd_gather(fdetd_plan_t plan, void *const *psi, const double *sa
  *   fields[s][c] = sum_m Re( e^(i m theta_s) sum_(u,g) S3(u - 2 z_s/dz) S3(g - 2 rho_s/dr) F_m,c(u, g) )
  * (a direction not doubled keeps the nodes of fdetd_gather).  Arguments as for fdetd_gather.  The plan
  * allocates 24 planes per problem on the first call (kept until fdetd_destroy; FDETD_E_NOMEM if that
- * fails); FDETD_E_ARG for supersample outside 0..3.  Enqueue only. */
+ * fails); FDETD_E_ARG for supersample outside 0..3 or grids of more than 2^29 cells.  Enqueue only. */
 FDETD_API int fdetd_gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n,
                                         double *fields, int32_t supersample);
 

@@ -192,15 +192,19 @@ hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s);
 
 // Field interpolation (section 3.3).  Destaggering of one plane to the primary grid: along z (S_z^(+),
 // columns outside the grid 0) or along rho (S_rho^(+) with the operand's parity and axis rule).
+enum { PASS_Z = 0, PASS_RHO = 1, PASS_COPY = 2, PASS_AXIS = 3 };
 struct DestaggerPass {
     const void *src;
     void *dst;
-    int along_rho, parity, extrapolate;
-    int to_stag;  // 0: staggered -> primary positions (S^(+)); 1: primary -> staggered (S^(-), 2x supersampling)
-    int grow_r;   // rows beyond the box to compute as well
-    int set;      // coefficient set (0 or 1) of the problem the planes belong to
+    int op;  // PASS_Z, PASS_RHO: half shift along z / rho; PASS_COPY: copy (2x supersampling);
+             // PASS_AXIS: only the axis row, by the axis rule, from rows 1..N_D of dst itself
+    int parity, extrapolate;
+    int to_stag;    // shifts: 0 staggered -> primary positions (S^(+)); 1 primary -> staggered (S^(-))
+    int grow_r;     // rows beyond the box to compute as well
+    int set;        // coefficient set (0 or 1) of the problem the planes belong to
+    int axis_rule;  // PASS_COPY: the axis row takes the axis rule instead of the stored slot
 };
-constexpr int kMaxDestaggerPass = 18;
+constexpr int kMaxDestaggerPass = 27;
 // One launch runs up to kMaxDestaggerPass independent passes (blockIdx.y), over the cells of the box.
 struct DestaggerArgs {
     int nz, nr, npass;
@@ -226,12 +230,11 @@ struct GatherArgs {
     const void *plane[kMaxGather][6];  // the destaggered components on the primary grid; 2x supersampling:
                                        // the components as stored (the state's planes)
     // 2x supersampling only: plane sets of the doubled grids, component c's set (zs, rs) (1 = staggered
-    // position along z, rho) at fine[p] + (4 c + zs + 2 rs) * plane_bytes unless it is the stored one
+    // position along z, rho) at fine[p] + (4 c + zs + 2 rs) * plane_bytes (the axis rows already hold the
+    // axis rule where it applies)
     int ss;                            // bit 0: z doubled, bit 1: rho doubled
     size_t plane_bytes;
     const void *fine[kMaxGather];
-    const double *cax[kMaxGather];     // axis extrapolation weights c_k' (device)
-    int nd[kMaxGather];
 };
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
 

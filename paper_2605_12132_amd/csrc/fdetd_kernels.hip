@@ -1042,7 +1042,9 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrectArgs A)
 // 2x supersampling also shifts the other way (to_stag), primary to staggered positions:
 //   along z:   out(k, i) = sum_j s_j (f(k, i + j - 1) + f(k, i - j)),
 //   along rho: out(k, i) = sum_j s_j (f(k + j - 1, i) + f(k - j, i)) for every k >= 0, rows q < 0 =
-//              parity f(-1-q).
+//              parity f(-1-q),
+// copies the stored sets (the axis row of a staggered-rho set by the axis rule), and writes the axis row
+// of a z-shifted staggered-rho set by the axis rule in place.
 // --------------------------------------------------------------------------------------------------
 // The footprint box of the samples: one thread per sample, block reductions, then global atomics.
 __global__ __launch_bounds__(256) void k_gather_box_reset(int *box)
@@ -1091,7 +1093,12 @@ __global__ __launch_bounds__(256) void k_destagger(DestaggerArgs A)
     const double *sw = A.s[P.set], *cw = A.c[P.set];
     // the cells of the box (rows grown by grow_r), grid-stride
     const int z0 = max(0, A.box[0]), z1 = min(A.nz - 1, A.box[1]);
-    const int k0 = max(0, A.box[2] - P.grow_r), k1 = min(A.nr - 1, A.box[3] + P.grow_r);
+    const int k0 = max(0, A.box[2] - P.grow_r);
+    int k1 = min(A.nr - 1, A.box[3] + P.grow_r);
+    if (P.op == PASS_AXIS) {
+        if (k0 > 0) return;  // the box does not reach the axis
+        k1 = 0;
+    }
     if (z1 < z0 || k1 < k0) return;
     const int64_t w = z1 - z0 + 1, cells = w * (int64_t)(k1 - k0 + 1);
     const V *f = (const V *)P.src;
@@ -1104,7 +1111,20 @@ __global__ __launch_bounds__(256) void k_destagger(DestaggerArgs A)
         // Taps outside the grid read a clamped in-range value with weight 0 (loads need no branches and can
         // all be in flight together); the sums are the same.
         double re = 0.0, im = 0.0;
-        if (!P.along_rho) {
+        if (P.op == PASS_COPY || P.op == PASS_AXIS) {
+            if (k == 0 && (P.axis_rule || P.op == PASS_AXIS)) {
+                if (P.extrapolate)
+                    for (int q = 1; q <= nd && q < A.nr; ++q) {
+                        const double2 v = at(q, i);
+                        re += cw[q - 1] * v.x;
+                        im += cw[q - 1] * v.y;
+                    }
+            } else {
+                const double2 v = at(k, i);
+                re = v.x;
+                im = v.y;
+            }
+        } else if (P.op == PASS_Z) {
 #pragma unroll 4
             for (int j = 1; j <= nd; ++j) {
                 const int c0 = i + j - P.to_stag, c1 = i - j + 1 - P.to_stag;
@@ -1277,33 +1297,49 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
 }
 
 // Interpolation on the doubled grid (2x supersampling, section 3.4; SS bit 0: z, bit 1: rho), one thread
-// per sample, reading the plane sets directly.  Doubled along z the nodes are u dz/2 (odd u: staggered
-// column (u+1)/2, even u: primary column u/2); doubled along rho they are g drho/2 (even g: staggered row
-// g/2, the axis for g = 0; odd g: primary row (g-1)/2; g < 0 the mirror of -g with the parity); a
-// direction not doubled keeps the primary nodes.  The cubic shape is in units of the node spacing.  On
-// the axis row of a staggered-rho set of a component whose own rho position is staggered the value is
-// the axis rule (the stored axis slot is not a value).
+// per sample.  Doubled along z the nodes are u dz/2 (odd u: staggered column (u+1)/2, even u: primary
+// column u/2); doubled along rho they are g drho/2 (even g: staggered row g/2, the axis for g = 0; odd g:
+// primary row (g-1)/2; g < 0 the mirror of -g with the parity); a direction not doubled keeps the primary
+// nodes.  The cubic shape is in units of the node spacing.  Every position set is read from the doubled-
+// grid planes (their axis rows already hold the axis rule where it applies).  Blocks of GATHER_BLOCK
+// consecutive samples go mode by mode: when the columns and rows the block's nodes touch fit GATHER_TILE
+// values over the mode's position sets and components, the block copies them into LDS first; otherwise
+// the samples read the planes.  Each mode's value is added into fields in mode order.
 template <typename R, int SS>
-__global__ __launch_bounds__(256) void k_gather_fine(GatherArgs A)
+__global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_fine(GatherArgs A)
 {
     using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.n) return;
-    const double z = A.samples[4 * s], x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+    constexpr int NSET = SS == 3 ? 4 : 2;  // position sets the doubled grid reads per component
+    __shared__ double2 tile[GATHER_TILE];
+    __shared__ int red[4 * (GATHER_BLOCK / 64)];
+    const int64_t s = (int64_t)blockIdx.x * GATHER_BLOCK + threadIdx.x;
+    const bool live = s < A.n;
+    double z = 0.0, x = 0.0, y = 0.0;
+    if (live) {
+        z = A.samples[4 * s];
+        x = A.samples[4 * s + 1];
+        y = A.samples[4 * s + 2];
+    }
     const double rho = sqrt(x * x + y * y);
     const double c1 = rho > 0.0 ? x / rho : 1.0, s1 = rho > 0.0 ? y / rho : 0.0;
     double wz[4], wr[4];
-    int col[4], zsb[4], row[4], rsb[4];
+    int col[4], row[4], zsb[4], rsb[4];
     bool below[4];
+    int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
     {
         const double zc = (SS & 1) ? 2.0 * z / A.dz : z / A.dz;
         const int u0 = (int)floor(zc) - 1;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int u = u0 + b, zs = (SS & 1) ? (u & 1) : 0, i = (SS & 1) ? (u + zs) >> 1 : u;
-            wz[b] = (i >= 0 && i < A.nz) ? bspline3(u - zc) : 0.0;
+            const bool ok = i >= 0 && i < A.nz;
+            wz[b] = ok ? bspline3(u - zc) : 0.0;
             col[b] = min(max(i, 0), A.nz - 1);
             zsb[b] = zs;
+            if (live && ok) {
+                fp[0] = min(fp[0], i);
+                fp[1] = max(fp[1], i);
+            }
         }
         const double rc = (SS & 2) ? 2.0 * rho / A.dr : rho / A.dr - 0.5;
         const int g0 = (int)floor(rc) - 1;
@@ -1319,62 +1355,90 @@ __global__ __launch_bounds__(256) void k_gather_fine(GatherArgs A)
                 rs = 0;
                 k = g < 0 ? -1 - g : g;
             }
-            wr[a] = k < A.nr ? bspline3(g - rc) : 0.0;
+            const bool ok = k < A.nr;
+            wr[a] = ok ? bspline3(g - rc) : 0.0;
             row[a] = min(k, A.nr - 1);
             rsb[a] = rs;
             below[a] = g < 0;
+            if (live && ok) {
+                fp[2] = min(fp[2], k);
+                fp[3] = max(fp[3], k);
+            }
         }
     }
-    // own positions (Table 1): z staggered for E_z, B_rho, B_theta; rho staggered for E_rho, B_theta, B_z
-    constexpr int own_z[6] = {0, 0, 1, 1, 1, 0}, own_r[6] = {1, 0, 0, 0, 1, 1};
-#pragma unroll 1
-    for (int c = 0; c < 6; ++c) {
-        double acc = 0.0;
-        for (int p = 0; p < A.nprob; ++p) {
-            const int m = A.m[p];
-            const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
-            const double par = (c == 2 || c == 5) ? pS : pA;
-            const bool extrap = (c == 0 || c == 4) ? m == 1 : (c == 5 ? m == 0 : false);
-            const int own = own_z[c] + 2 * own_r[c];
-            double cr = 1.0, ci = 0.0;
-            for (int j = 0; j < (m < 0 ? -m : m); ++j) {
-                const double t = cr * c1 - ci * s1;
-                ci = cr * s1 + ci * c1;
-                cr = t;
-            }
-            if (m < 0) ci = -ci;
-            double re = 0.0, im = 0.0;
+    block_minmax<GATHER_BLOCK / 64>(fp, red);
+    const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1, ts = tz | 1;
+    const bool use_tile = fp[1] >= fp[0] && fp[3] >= fp[2] && (int64_t)NSET * 6 * tr * ts <= GATHER_TILE;  // uniform
+    // Offset of each node within a component's values: in the tile (slot of the position set, then row and
+    // column, nodes outside the grid -- weight 0 -- clamped into the tile), or in its four doubled-grid
+    // planes (set, row, column; the planes of one component span less than 2^31 values).
+    int off[4][4];
+    const int cells = A.nz * A.nr;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const double wa = below[a] ? par * wr[a] : wr[a];
-                double rre = 0.0, rim = 0.0;
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int v = zsb[b] + 2 * rsb[a];
-                    const V *f = v == own ? (const V *)A.plane[p][c]
-                                          : (const V *)((const char *)A.fine[p] + (size_t)(4 * c + v) * A.plane_bytes);
-                    double vx = 0.0, vy = 0.0;
-                    if (rsb[a] == 1 && row[a] == 0 && own_r[c] == 1) {
-                        if (extrap)
-                            for (int q = 1; q <= A.nd[p] && q < A.nr; ++q) {
-                                const V g = f[(size_t)q * A.nz + col[b]];
-                                vx += A.cax[p][q - 1] * (double)g.x;
-                                vy += A.cax[p][q - 1] * (double)g.y;
-                            }
-                    } else {
-                        const V g = f[(size_t)row[a] * A.nz + col[b]];
-                        vx = g.x;
-                        vy = g.y;
-                    }
-                    rre += wz[b] * vx;
-                    rim += wz[b] * vy;
-                }
-                re += wa * rre;
-                im += wa * rim;
+        for (int b = 0; b < 4; ++b) {
+            const int v = zsb[b] + 2 * rsb[a];
+            if (use_tile) {
+                const int t = SS == 1 ? (v & 1) : (SS == 2 ? (v >> 1) : v);
+                off[a][b] = (t * tr + min(max(row[a], fp[2]), fp[3]) - fp[2]) * ts + min(max(col[b], fp[0]), fp[1]) - fp[0];
+            } else {
+                off[a][b] = v * cells + row[a] * A.nz + col[b];
             }
-            acc += re * cr - im * ci;
         }
-        A.fields[6 * s + c] = acc;
+    for (int p = 0; p < A.nprob; ++p) {
+        const char *fine = (const char *)A.fine[p];
+        if (use_tile) {
+            if (p > 0) __syncthreads();  // the previous mode's reads are done
+            const int per = tr * tz, total = NSET * 6 * per;
+            for (int e = threadIdx.x; e < total; e += GATHER_BLOCK) {
+                const int cs = e / per, cell = e % per, k = cell / tz, i = cell % tz;
+                const int c = cs / NSET, t = cs % NSET;
+                const int v = SS == 1 ? t : (SS == 2 ? 2 * t : t);
+                const V g = ((const V *)(fine + (size_t)(4 * c + v) * A.plane_bytes))[(size_t)(fp[2] + k) * A.nz + fp[0] + i];
+                tile[(cs * tr + k) * ts + i] = double2{(double)g.x, (double)g.y};
+            }
+            __syncthreads();
+        }
+        if (!live) continue;
+        const int m = A.m[p];
+        const double pS = (m % 2 == 0) ? 1.0 : -1.0, pA = ((m > 1 ? m - 1 : 1 - m) % 2 == 0) ? 1.0 : -1.0;
+        double cr = 1.0, ci = 0.0;
+        for (int j = 0; j < (m < 0 ? -m : m); ++j) {
+            const double t = cr * c1 - ci * s1;
+            ci = cr * s1 + ci * c1;
+            cr = t;
+        }
+        if (m < 0) ci = -ci;
+#pragma unroll 1
+        for (int c = 0; c < 6; ++c) {
+            const double par = (c == 2 || c == 5) ? pS : pA;
+            const double2 *tc = tile + c * NSET * tr * ts;
+            const V *gc = (const V *)(fine + (size_t)(4 * c) * A.plane_bytes);
+            double re = 0.0, im = 0.0;
+            auto sum = [&](auto fetch) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const double wa = below[a] ? par * wr[a] : wr[a];
+                    double rre = 0.0, rim = 0.0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const double2 g = fetch(off[a][b]);
+                        rre += wz[b] * g.x;
+                        rim += wz[b] * g.y;
+                    }
+                    re += wa * rre;
+                    im += wa * rim;
+                }
+            };
+            if (use_tile) sum([&](int o) { return tc[o]; });
+            else sum([&](int o) {
+                const V g = gc[o];
+                return double2{(double)g.x, (double)g.y};
+            });
+            const double val = re * cr - im * ci;
+            A.fields[6 * s + c] = p == 0 ? val : A.fields[6 * s + c] + val;
+        }
     }
 }
 
@@ -1457,11 +1521,11 @@ hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
     if (a.ss != 0) {
-        const dim3 grid((unsigned)((a.n + 255) / 256));
-#define FDETD_FINE(SS)                                                                            \
-    if (a.ss == SS) {                                                                             \
-        if (prec == P64) hipLaunchKernelGGL((k_gather_fine<double, SS>), grid, dim3(256), 0, s, a); \
-        else hipLaunchKernelGGL((k_gather_fine<float, SS>), grid, dim3(256), 0, s, a);             \
+        const dim3 grid((unsigned)((a.n + GATHER_BLOCK - 1) / GATHER_BLOCK));
+#define FDETD_FINE(SS)                                                                                     \
+    if (a.ss == SS) {                                                                                      \
+        if (prec == P64) hipLaunchKernelGGL((k_gather_fine<double, SS>), grid, dim3(GATHER_BLOCK), 0, s, a); \
+        else hipLaunchKernelGGL((k_gather_fine<float, SS>), grid, dim3(GATHER_BLOCK), 0, s, a);             \
     }
         FDETD_FINE(1) FDETD_FINE(2) FDETD_FINE(3)
 #undef FDETD_FINE

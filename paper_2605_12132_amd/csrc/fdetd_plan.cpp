@@ -1331,9 +1331,10 @@ int gather_impl(fdetd_plan_t plan, void *const *psi, const double *samples, int6
 
 // 2x supersampling: for each component the position sets (zs, rs) the doubled grid needs (zs over {0, 1}
 // when z is doubled, else {0}; rs likewise), each made from the stored set by at most one half shift along
-// z followed by one along rho.  Level 1 shifts the stored planes (z shifts computed on rows grown by N_D,
-// which the level-2 rho shifts and the axis rule read); level 2 shifts level 1's z output along rho.  Level
-// 2 of problem p - 1 shares a launch with level 1 of problem p.
+// z followed by one along rho, all in the plan's doubled-grid planes (the stored set copied there).  Level
+// 1 shifts and copies the stored planes (z shifts computed on rows grown by N_D, which the level-2 rho
+// shifts and axis rows read); level 2 shifts level 1's z output along rho and sets its axis row.  Level 2
+// of problem p - 1 shares a launch with level 1 of problem p.
 int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *samples, int64_t n, double *fields,
                         int ss, int *box)
 {
@@ -1341,6 +1342,9 @@ int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *sampl
     const size_t eb = elem_bytes(plan->precision);
     const int prec = prec_code(plan->precision);
     const fdetd_problem_desc &d0 = plan->probs[0].d;
+    if (4 * plan->probs[0].cells > (size_t)INT32_MAX)
+        return fail(plan, FDETD_E_ARG, "fdetd_gather_supersampled: grid of %zu cells too large (at most 2^29)",
+                    plan->probs[0].cells);
     for (int p = 0; p < np; ++p) {
         Prob &q = plan->probs[p];
         if (!q.fine && hipMalloc(&q.fine, 24 * q.cells * eb) != hipSuccess) {
@@ -1349,10 +1353,6 @@ int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *sampl
             return fail(plan, FDETD_E_NOMEM, "fdetd_gather_supersampled: no memory for the doubled grids");
         }
     }
-    // device table entry of each problem (axis weights)
-    std::vector<int> entry(np, 0);
-    for (const Batch &b : plan->batches)
-        for (int t = 0; t < b.count; ++t) entry[b.members[t]] = b.d0 + t;
     static const int own_z[6] = {0, 0, 1, 1, 1, 0}, own_r[6] = {1, 0, 0, 0, 1, 1};
     const bool dz2 = ss & 1, dr2 = ss & 2;
     auto needed = [&](int zs, int rs) { return (zs == 0 || dz2) && (rs == 0 || dr2); };
@@ -1382,15 +1382,20 @@ int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *sampl
                 const int zn = own_z[c], rn = own_r[c], par = (c == EZ || c == BZ) ? pS : pA;
                 const int ext = (c == ER || c == BTH) ? m == 1 : (c == BZ ? m == 0 : 0);
                 const void *stored = (const char *)psi[pp] + c * pb;
-                auto add = [&](const void *src, void *dst, int rho, int to_stag, int grow_r) {
-                    X.pass[X.npass++] = DestaggerPass{src, dst, rho, par, rho ? ext : 0, to_stag, grow_r, set};
+                auto add = [&](const void *src, void *dst, int op, int to_stag, int grow_r, int axis_rule) {
+                    X.pass[X.npass++] = DestaggerPass{src, dst, op, par, op != PASS_Z ? ext : 0, to_stag, grow_r, set,
+                                                      axis_rule};
                 };
                 if (lvl == 1) {
                     if (needed(1 - zn, 0) || needed(1 - zn, 1))
-                        add(stored, fine(c, 1 - zn, rn), 0, zn == 0, q.nd);
-                    if (needed(zn, 1 - rn)) add(stored, fine(c, zn, 1 - rn), 1, rn == 0, 0);
-                } else if (needed(1 - zn, 1 - rn)) {
-                    add(fine(c, 1 - zn, rn), fine(c, 1 - zn, 1 - rn), 1, rn == 0, 0);
+                        add(stored, fine(c, 1 - zn, rn), PASS_Z, zn == 0, q.nd, 0);
+                    if (needed(zn, 1 - rn)) add(stored, fine(c, zn, 1 - rn), PASS_RHO, rn == 0, 0, 0);
+                    if (needed(zn, rn)) add(stored, fine(c, zn, rn), PASS_COPY, 0, 0, rn == 1);
+                } else {
+                    if (needed(1 - zn, 1 - rn)) add(fine(c, 1 - zn, rn), fine(c, 1 - zn, 1 - rn), PASS_RHO, rn == 0, 0, 0);
+                    // the z-shifted staggered-rho set: its axis row by the axis rule (the rho pass above
+                    // does not read that row)
+                    if (rn == 1 && needed(1 - zn, 1)) add(fine(c, 1 - zn, 1), fine(c, 1 - zn, 1), PASS_AXIS, 0, 0, 1);
                 }
             }
         }
@@ -1409,12 +1414,8 @@ int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *sampl
     G.ss = ss;
     G.plane_bytes = plan->probs[0].cells * eb;
     for (int p = 0; p < np; ++p) {
-        const Prob &q = plan->probs[p];
-        G.m[p] = q.d.m;
-        for (int c = 0; c < 6; ++c) G.plane[p][c] = (const char *)psi[p] + c * G.plane_bytes;
-        G.fine[p] = q.fine;
-        G.cax[p] = (const double *)((const char *)(plan->ddesc + entry[p]) + offsetof(ProbDesc, cax));
-        G.nd[p] = q.nd;
+        G.m[p] = plan->probs[p].d.m;
+        G.fine[p] = plan->probs[p].fine;
     }
     HIPCHK(plan, launch_gather(prec, G, plan->stream));
     return FDETD_OK;

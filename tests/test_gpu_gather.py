@@ -120,17 +120,29 @@ def test_gather_after_steps_and_argument_checks():
     plan.close()
 
 
+def bunch(rng, n, nz, dz, dr):
+    """A compact bunch in z order (the LDS-tile path): z over 12 cells mid-grid, rho within 8 rows, a fifth
+    of the samples next to the axis."""
+    z = np.sort(rng.uniform(0.4 * nz * dz, (0.4 * nz + 12) * dz, n))
+    r = np.sqrt(rng.uniform(0, 64, n)) * dr
+    r[rng.random(n) < 0.2] = rng.uniform(0, 1.5 * dr)
+    th = rng.uniform(-math.pi, math.pi, n)
+    return np.stack([z, r * np.cos(th), r * np.sin(th), np.ones(n)], axis=1)
+
+
+@pytest.mark.parametrize("ordered", [False, True])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("order", [8, 16])
-def test_supersampled_gather_matches_oracle(precision, order):
+def test_supersampled_gather_matches_oracle(precision, order, ordered):
     """One plan, the three doublings in turn and the plain gather after them (the doubled-grid planes are
-    reused across calls)."""
+    reused across calls).  Unordered samples spread over the grid read the planes; a z-ordered compact
+    bunch goes through the LDS tiles."""
     import torch
     w = workload([0, 1, 2], order)
     rng = np.random.default_rng(40 + order + precision)
     states = [rng.uniform(-1, 1, (6, w.nr[0], w.nz[0])) + 1j * rng.uniform(-1, 1, (6, w.nr[0], w.nz[0]))
               for _ in range(w.n)]
-    s = samples(rng, 3000, w.nz[0], w.nr[0], w.dz, w.dr)
+    s = bunch(rng, 6000, w.nz[0], w.dz, w.dr) if ordered else samples(rng, 3000, w.nz[0], w.nr[0], w.dz, w.dr)
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
     psi = [dev(x, cd) for x in states]
@@ -139,7 +151,8 @@ def test_supersampled_gather_matches_oracle(precision, order):
         got = plan.gather(psi, sd, supersample=ss).cpu().numpy()
         want = oracle.gather_fine(grids(w), states, s, ss)
         err = np.max(np.abs(got - want)) / np.max(np.abs(want))
-        log(f"supersampled gather {ss} order {order} precision {precision}: max error {err:.2e} of the field scale")
+        log(f"supersampled gather {ss} order {order} precision {precision} ordered {ordered}: max error {err:.2e} "
+            f"of the field scale")
         assert err < (1e-12 if precision == F.FP64 else 1e-5), ss
     with pytest.raises(F.FdetdError):
         plan.gather(psi, sd, supersample=4)
