@@ -215,10 +215,10 @@ struct DestaggerArgs {
     DestaggerPass pass[kMaxDestaggerPass];
 };
 hipError_t launch_destagger(int prec, const DestaggerArgs &a, hipStream_t s);
-// The nodes and rows the interpolation shapes of n samples touch on one grid (zlo, zhi, klo, khi), reduced
-// into box (reset first).
+// The nodes and rows the interpolation shapes of n > 0 samples touch on one grid (zlo, zhi, klo, khi) into
+// box: partial boxes of up to max_blocks blocks in part, then one reducing block.
 hipError_t launch_gather_box(const double *samples, int64_t n, int nz, int nr, double dz, double dr, int *box,
-                             hipStream_t s);
+                             int *part, int max_blocks, hipStream_t s);  // part: 4 max_blocks ints of scratch
 constexpr int kMaxGather = 16;  // modes of one grid per gather
 struct GatherArgs {
     int64_t n;

@@ -1046,22 +1046,13 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrectArgs A)
 // copies the stored sets (the axis row of a staggered-rho set by the axis rule), and writes the axis row
 // of a z-shifted staggered-rho set by the axis rule in place.
 // --------------------------------------------------------------------------------------------------
-// The footprint box of the samples: one thread per sample, block reductions, then global atomics.
-__global__ __launch_bounds__(256) void k_gather_box_reset(int *box)
-{
-    if (threadIdx.x == 0) {
-        box[0] = INT_MAX;
-        box[1] = INT_MIN;
-        box[2] = INT_MAX;
-        box[3] = INT_MIN;
-    }
-}
+// The footprint box of the samples: a grid-stride pass whose blocks store their partial boxes, then one
+// block that reduces them (no same-address atomics).
 __global__ __launch_bounds__(256) void k_gather_box(const double *samples, int64_t n, int nz, int nr, double dz,
-                                                    double dr, int *box)
+                                                    double dr, int *part)
 {
     __shared__ int red[16];
     int v[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
-    // grid-stride: few blocks, so that few global atomics meet on the four words
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) {
         const double z = samples[4 * s], x = samples[4 * s + 1], y = samples[4 * s + 2];
         const double zc = z / dz, rc = sqrt(x * x + y * y) / dr - 0.5;
@@ -1076,12 +1067,20 @@ __global__ __launch_bounds__(256) void k_gather_box(const double *samples, int64
         v[3] = max(v[3], min(nr - 1, max(1, (int)rf + 2)));
     }
     block_minmax(v, red);
-    if (threadIdx.x == 0 && v[0] <= v[1]) {
-        atomicMin(box, v[0]);
-        atomicMax(box + 1, v[1]);
-        atomicMin(box + 2, v[2]);
-        atomicMax(box + 3, v[3]);
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = v[threadIdx.x];
+}
+__global__ __launch_bounds__(256) void k_gather_box_reduce(const int *part, int nblocks, int *box)
+{
+    __shared__ int red[16];
+    int v[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        v[0] = min(v[0], part[4 * b]);
+        v[1] = max(v[1], part[4 * b + 1]);
+        v[2] = min(v[2], part[4 * b + 2]);
+        v[3] = max(v[3], part[4 * b + 3]);
     }
+    block_minmax(v, red);
+    if (threadIdx.x < 4) box[threadIdx.x] = v[threadIdx.x];
 }
 
 template <typename R>
@@ -1499,12 +1498,13 @@ hipError_t launch_correct_solve(const SolveArgs &a, hipStream_t s)
 }
 
 hipError_t launch_gather_box(const double *samples, int64_t n, int nz, int nr, double dz, double dr, int *box,
-                             hipStream_t s)
+                             int *part, int max_blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_box_reset, dim3(1), dim3(256), 0, s, box);
-    const int64_t blocks = (n + 255) / 256;
-    if (n > 0) hipLaunchKernelGGL(k_gather_box, dim3((unsigned)(blocks < 512 ? blocks : 512)), dim3(256), 0, s, samples,
-                                  n, nz, nr, dz, dr, box);
+    if (n <= 0 || max_blocks <= 0) return hipErrorInvalidValue;
+    const int64_t want = (n + 1023) / 1024;  // about four samples per thread
+    const int blocks = (int)(want < max_blocks ? want : max_blocks);
+    hipLaunchKernelGGL(k_gather_box, dim3((unsigned)blocks), dim3(256), 0, s, samples, n, nz, nr, dz, dr, part);
+    hipLaunchKernelGGL(k_gather_box_reduce, dim3(1), dim3(256), 0, s, part, blocks, box);
     return hipGetLastError();
 }
 

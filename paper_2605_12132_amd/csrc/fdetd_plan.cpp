@@ -1263,8 +1263,13 @@ int gather_impl(fdetd_plan_t plan, void *const *psi, const double *samples, int6
     const int prec = prec_code(plan->precision);
     // the nodes and rows the samples' shapes touch; the destagger passes compute only those (grown by the
     // rows the second pass of B_theta reads from the first)
-    int *box = (int *)((char *)plan->probs[0].buf[1] + plan->probs[0].cells * elem_bytes(plan->precision));
-    HIPCHK(plan, launch_gather_box(samples, n, d0.nz, d0.nr, d0.dz, d0.dr, box, plan->stream));
+    // (box and the partial boxes of its reduction sit in planes 1..5 of problem 0's second stage vector,
+    // which the gather does not otherwise use)
+    const size_t pb0 = plan->probs[0].cells * elem_bytes(plan->precision);
+    int *box = (int *)((char *)plan->probs[0].buf[1] + pb0);
+    const size_t room = (5 * pb0) / (4 * sizeof(int)) - 1;
+    HIPCHK(plan, launch_gather_box(samples, n, d0.nz, d0.nr, d0.dz, d0.dr, box, box + 4,
+                                   (int)std::min<size_t>(room, 2048), plan->stream));
     if (ss != 0) return gather_supersampled(plan, psi, samples, n, fields, ss, box);
     GatherArgs G;
     std::memset(&G, 0, sizeof G);

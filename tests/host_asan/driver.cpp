@@ -29,7 +29,10 @@ hipError_t launch_correct_div(int, const CorrectArgs &, hipStream_t) { return hi
 hipError_t launch_correct_apply(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_solve(const SolveArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_gather(int, const GatherArgs &, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_gather_box(const double *, int64_t, int, int, double, double, int *, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_gather_box(const double *, int64_t, int, int, double, double, int *, int *, int, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
 hipError_t launch_norm2(int, const void *, size_t, double *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_copy(const void *, void *, size_t, hipStream_t) { return hipErrorInvalidValue; }
