@@ -434,13 +434,26 @@ __device__ __forceinline__ double bspline3(double x)
     return 0.0;
 }
 
+// rho_k^e; the exponents the radial shape meets for eps in {0, 1/2, 1} by their exact operations (one
+// division or square root instead of a pow)
+__device__ __forceinline__ double rk_pow(double rk, double e)
+{
+    if (e == 0.0) return 1.0;
+    if (e == 1.0) return rk;
+    if (e == -1.0) return 1.0 / rk;
+    if (e == 0.5) return sqrt(rk);
+    if (e == -0.5) return 1.0 / sqrt(rk);
+    return pow(rk, e);
+}
+
 // Radial shape of a sample at rho on primary row k (folded with parity par, normalised by N) and the
-// angular shape of mode m at angle th.
+// angular shape of mode m at the sample's angle theta, given by (x, y): e^(-i m theta) as the m-th power
+// of (x - i y) / rho (theta = 0 on the axis).
 struct SampleShape {
     int kc, k0, k1;      // rows kc - 3 .. kc + 3, clipped to [0, nr)
     double N, par, ar, ai;
 };
-__device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rho, double th, double eps)
+__device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rho, double x, double y, double eps)
 {
     SampleShape S;
     const double dr = D.dr;
@@ -452,22 +465,29 @@ __device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rh
     for (int k = S.k0; k <= S.kc + 3; ++k) {
         const double rk = (k + 0.5) * dr;
         const double w = bspline3((rk - rho) / dr) + bspline3((-rk - rho) / dr);
-        N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * pow(rk, eps) * w * dr;
+        N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * rk_pow(rk, eps) * w * dr;
     }
     S.N = N;
     if (D.m == 0) {
         S.ar = 0.5 / M_PI;
         S.ai = 0.0;
     } else {
-        S.ar = cos(D.m * th) / M_PI;
-        S.ai = -sin(D.m * th) / M_PI;
+        const double c1 = rho > 0.0 ? x / rho : 1.0, s1 = rho > 0.0 ? y / rho : 0.0;
+        double cr = 1.0, ci = 0.0;  // cos, sin of m theta
+        for (int j = 0; j < D.m; ++j) {
+            const double t = cr * c1 - ci * s1;
+            ci = cr * s1 + ci * c1;
+            cr = t;
+        }
+        S.ar = cr / M_PI;
+        S.ai = -ci / M_PI;
     }
     return S;
 }
 __device__ __forceinline__ double radial_weight(const ProbDesc &D, const SampleShape &S, double rho, double eps, int k)
 {
     const double rk = (k + 0.5) * D.dr;
-    return pow(rk, eps - 1.0) * (bspline3((rk - rho) / D.dr) + S.par * bspline3((-rk - rho) / D.dr)) / S.N;
+    return rk_pow(rk, eps - 1.0) * (bspline3((rk - rho) / D.dr) + S.par * bspline3((-rk - rho) / D.dr)) / S.N;
 }
 // The z shape of a position x (in cells) spans nodes floor(x) - 1 .. floor(x) + 2, which must lie on the grid.
 __device__ __forceinline__ bool z_on_grid(const ProbDesc &D, double x)
@@ -511,7 +531,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
     __shared__ double tile[2 * DEP_TILE];
     __shared__ int red[16];
     const int64_t s0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * DEP_PER_THREAD;
-    struct Smp { double z, rho, th, qw; bool ok; };
+    struct Smp { double z, rho, x, y, qw; bool ok; };
     Smp sm[DEP_PER_THREAD];
 #pragma unroll
     for (int u = 0; u < DEP_PER_THREAD; ++u) {
@@ -522,7 +542,8 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         sm[u].z = A.samples[4 * sc];
         sm[u].qw = A.samples[4 * sc + 3];
         sm[u].rho = sqrt(x * x + y * y);
-        sm[u].th = atan2(y, x);
+        sm[u].x = x;
+        sm[u].y = y;
     }
     for (int p = 0; p < A.nprob; ++p) {
         const ProbDesc &D = A.probs[p];
@@ -564,7 +585,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
                 Fp += bspline3(lo[u] + v - zp);
                 Fm += bspline3(lo[u] + v - zm);
             }
-            const SampleShape S = sample_shape(D, sm[u].rho, sm[u].th, A.eps);
+            const SampleShape S = sample_shape(D, sm[u].rho, sm[u].x, sm[u].y, A.eps);
             for (int k = S.k0; k <= S.k1; ++k) {
                 const double rs = radial_weight(D, S, sm[u].rho, A.eps, k);
                 if (rs == 0.0) continue;
@@ -672,14 +693,14 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             if (!on_grid(u, zp, zm)) continue;
             const double *q = sample(u);
             const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5];
-            const double r0 = sqrt(x * x + y * y), t0 = atan2(y, x), zc = z / D.dz;
+            const double r0 = sqrt(x * x + y * y), zc = z / D.dz;
             const double vr = r0 > 0.0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0.0 ? (x * vy - y * vx) / r0 : 0.0;
             const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
             const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym);
-            const SampleShape Sp = sample_shape(D, rp, atan2(yp, xp), A.eps), Sm = sample_shape(D, rm, atan2(ym, xm), A.eps);
+            const SampleShape Sp = sample_shape(D, rp, xp, yp, A.eps), Sm = sample_shape(D, rm, xm, ym, A.eps);
             // transverse currents at the sample (m_A fold)
             if (vr != 0.0 || vt != 0.0) {
-                SampleShape S0 = sample_shape(D, r0, t0, A.eps);
+                SampleShape S0 = sample_shape(D, r0, x, y, A.eps);
                 S0.par = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;
                 const int lo = (int)floor(zc) - 1;
                 for (int k = S0.k0; k <= S0.k1; ++k) {
@@ -740,7 +761,7 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
     if (s >= A.n) return;
     const double z = A.samples[4 * s] + A.shift, x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
     const double qw = A.samples[4 * s + 3];
-    const double rho = sqrt(x * x + y * y), th = atan2(y, x);
+    const double rho = sqrt(x * x + y * y);
     for (int p = 0; p < A.nprob; ++p) {
         const ProbDesc &D = A.probs[p];
         const double zc = z / D.dz;
@@ -748,7 +769,7 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
         const int lo = (int)floor(zc) - 1;
         double wz[4];
         for (int u = 0; u < 4; ++u) wz[u] = bspline3(lo + u - zc) / D.dz;
-        const SampleShape S = sample_shape(D, rho, th, A.eps);
+        const SampleShape S = sample_shape(D, rho, x, y, A.eps);
         R *rp = (R *)A.j[p];
         for (int k = S.k0; k <= S.k1; ++k) {
             const double rs = radial_weight(D, S, rho, A.eps, k);
