@@ -409,9 +409,10 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
     of peak density n_b) moving at c, in z order, deposited with fdetd_deposit_jz (timed separately,
-    including the advance of the sample positions), then graph replay of `steps` field steps, then the fields of the
-    final state at the samples (fdetd_gather, timed apart, also with 2x supersampling along z and rho).  FP64
-    and FP32C; the FP32C error against FP64 after the same steps."""
+    including the advance of the sample positions; all currents and rho_xy of the same samples with a
+    transverse velocity spread, fdetd_deposit_current, timed apart), then graph replay of `steps` field
+    steps, then the fields of the final state at the samples (fdetd_gather, timed apart, also with 2x
+    supersampling along z and rho).  FP64 and FP32C; the FP32C error against FP64 after the same steps."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -446,6 +447,25 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
             torch.cuda.synchronize()
             dep_ms = ev0.elapsed_time(ev1) / (warmup + steps)
             plan.close()
+            # all currents of moving samples (J_rho, J_theta, modified-Esirkepov J_z and rho_xy of the
+            # current correction): the bunch with a transverse velocity spread, 5 calls
+            plan = F.Plan(w.problems(), precision=prec,
+                          flags=F.PLAN_CURRENT_CORRECTION | F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
+            J4 = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            s8 = torch.zeros((n_samples, 8), dtype=torch.float64, device="cuda")
+            s8[:, :4] = smp
+            s8[:, 4:6] = 0.01 * torch.randn((n_samples, 2), generator=g, device="cuda", dtype=torch.float64)
+            s8[:, 6] = 0.999
+            plan.deposit_current(s8, J4)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                plan.deposit_current(s8, J4)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            dep_cur_ms = ev0.elapsed_time(ev1) / 5
+            plan.close()
+            del J4, s8
         psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
         del J
         torch.cuda.empty_cache()
@@ -473,11 +493,12 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
         gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
         res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
                         frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms, gather_ms=gather_ms,
-                        gather_supersampled_ms=gather_ss_ms,
+                        gather_supersampled_ms=gather_ss_ms, deposit_current_ms=dep_cur_ms,
                         seg_rows=info["seg_rows"])
         psis[tag] = psi
         log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
-            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step; gather {gather_ms:.3f} ms, "
+            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step (all currents and rho_xy "
+            f"{dep_cur_ms:.3f} ms); gather {gather_ms:.3f} ms, "
             f"2x supersampled (z and rho) {gather_ss_ms:.3f} ms")
     num = den = 0.0
     for a, b in zip(psis["fp64"], psis["fp32c"]):
