@@ -107,6 +107,11 @@ def test_gather_after_steps_and_argument_checks():
         got = out.cpu().numpy()
         with pytest.raises(F.FdetdError):
             F.fdetd_gather(plan._h, [x.data_ptr() for x in psi], 0, 10, 0)  # NULL samples
+        # no samples: nothing to do, plain or supersampled
+        empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+        for ss in (0, 1, 2, 3):
+            assert plan.gather(psi, empty, supersample=ss).shape == (0, 6)
+        torch.cuda.synchronize()
         plan.close()
     want = oracle.gather(grids(w), stepped, s)
     assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
