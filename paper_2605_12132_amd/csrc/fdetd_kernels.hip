@@ -1232,8 +1232,9 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
     block_minmax<GATHER_BLOCK / 64>(fp, red);
     // Tile rows are ts = tz | 1 values apart: an odd stride puts 16 consecutive rows in distinct LDS bank
     // groups of 16-byte reads, and the lanes of a wave (samples at about the same z) differ mostly in row.
-    const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1, ts = tz | 1;
-    const bool use_tile = fp[1] >= fp[0] && fp[3] >= fp[2] && (int64_t)ts * tr * 6 * A.nprob <= GATHER_TILE;  // uniform
+    const bool any = fp[1] >= fp[0] && fp[3] >= fp[2];  // some sample of the block touches the grid
+    const int tz = any ? fp[1] - fp[0] + 1 : 0, tr = any ? fp[3] - fp[2] + 1 : 0, ts = tz | 1;
+    const bool use_tile = any && (int64_t)ts * tr * 6 * A.nprob <= GATHER_TILE;  // uniform
     if (use_tile) {
         const int per = tz * tr, total = per * 6 * A.nprob;
         for (int e = threadIdx.x; e < total; e += GATHER_BLOCK) {
@@ -1387,8 +1388,9 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
         }
     }
     block_minmax<GATHER_BLOCK / 64>(fp, red);
-    const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1, ts = tz | 1;
-    const bool use_tile = fp[1] >= fp[0] && fp[3] >= fp[2] && (int64_t)NSET * 6 * tr * ts <= GATHER_TILE;  // uniform
+    const bool any = fp[1] >= fp[0] && fp[3] >= fp[2];  // some sample of the block touches the grid
+    const int tz = any ? fp[1] - fp[0] + 1 : 0, tr = any ? fp[3] - fp[2] + 1 : 0, ts = tz | 1;
+    const bool use_tile = any && (int64_t)NSET * 6 * tr * ts <= GATHER_TILE;  // uniform
     // Offset of each node within a component's values: in the tile (slot of the position set, then row and
     // column, nodes outside the grid -- weight 0 -- clamped into the tile), or in its four doubled-grid
     // planes (set, row, column; the planes of one component span less than 2^31 values).
