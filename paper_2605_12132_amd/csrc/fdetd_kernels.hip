@@ -446,28 +446,38 @@ __device__ __forceinline__ double rk_pow(double rk, double e)
     return pow(rk, e);
 }
 
-// Radial shape of a sample at rho on primary row k (folded with parity par, normalised by N) and the
-// angular shape of mode m at the sample's angle theta, given by (x, y): e^(-i m theta) as the m-th power
-// of (x - i y) / rho (theta = 0 on the axis).
+// Radial shape of a sample at rho on the primary rows k = kc - 3 + j, j = 0..6 (folded with parity par,
+// normalised by N; w[j] = 0 off [k0, k1]) and the angular shape of mode m at the sample's angle theta,
+// given by (x, y): e^(-i m theta) as the m-th power of (x - i y) / rho (theta = 0 on the axis).  Each
+// row's spline values and power of rho_k are formed once, for N and the weight.
 struct SampleShape {
-    int kc, k0, k1;      // rows kc - 3 .. kc + 3, clipped to [0, nr)
-    double N, par, ar, ai;
+    int kc, k0, k1;  // rows kc - 3 .. kc + 3, clipped to [0, nr)
+    double ar, ai;
+    double w[7];
 };
-__device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rho, double x, double y, double eps)
+__device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rho, double x, double y, double eps,
+                                                    double par)
 {
     SampleShape S;
     const double dr = D.dr;
-    S.par = (D.m % 2 == 0) ? 1.0 : -1.0;
     S.kc = (int)floor(rho / dr);
     S.k0 = S.kc - 3 > 0 ? S.kc - 3 : 0;
     S.k1 = S.kc + 3 < D.nr - 1 ? S.kc + 3 : D.nr - 1;
     double N = 0.0;
-    for (int k = S.k0; k <= S.kc + 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int k = S.kc - 3 + j;
+        S.w[j] = 0.0;
+        if (k < 0) continue;  // N sums rows k0 .. kc + 3, beyond the last row too
         const double rk = (k + 0.5) * dr;
-        const double w = bspline3((rk - rho) / dr) + bspline3((-rk - rho) / dr);
-        N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * rk_pow(rk, eps) * w * dr;
+        const double bp = bspline3((rk - rho) / dr), bm = bspline3((-rk - rho) / dr);
+        const double t = rk_pow(rk, eps - 1.0);
+        N += (k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0)) * (rk * t) * (bp + bm) * dr;
+        if (k <= S.k1) S.w[j] = t * (bp + par * bm);
     }
-    S.N = N;
+    const double inv = 1.0 / N;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) S.w[j] *= inv;
     if (D.m == 0) {
         S.ar = 0.5 / M_PI;
         S.ai = 0.0;
@@ -483,11 +493,6 @@ __device__ __forceinline__ SampleShape sample_shape(const ProbDesc &D, double rh
         S.ai = -ci / M_PI;
     }
     return S;
-}
-__device__ __forceinline__ double radial_weight(const ProbDesc &D, const SampleShape &S, double rho, double eps, int k)
-{
-    const double rk = (k + 0.5) * D.dr;
-    return rk_pow(rk, eps - 1.0) * (bspline3((rk - rho) / D.dr) + S.par * bspline3((-rk - rho) / D.dr)) / S.N;
 }
 // The z shape of a position x (in cells) spans nodes floor(x) - 1 .. floor(x) + 2, which must lie on the grid.
 __device__ __forceinline__ bool z_on_grid(const ProbDesc &D, double x)
@@ -570,6 +575,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
         const bool use_tile = (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
         R *jz = (R *)A.j[p] + 2 * 2 * D.plane;               // plane 2, interleaved complex
+        const double inv_dt = 1.0 / D.dt, par_s = (D.m % 2 == 0) ? 1.0 : -1.0;
         if (use_tile) {
             for (int c = threadIdx.x; c < 2 * tz * tr; c += 256) tile[c] = 0.0;
             __syncthreads();
@@ -581,13 +587,15 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
             double dF[8];
             double Fp = 0.0, Fm = 0.0;
             for (int v = 0; v <= hi[u] - lo[u]; ++v) {
-                dF[v] = (Fm - Fp) / D.dt;
+                dF[v] = (Fm - Fp) * inv_dt;
                 Fp += bspline3(lo[u] + v - zp);
                 Fm += bspline3(lo[u] + v - zm);
             }
-            const SampleShape S = sample_shape(D, sm[u].rho, sm[u].x, sm[u].y, A.eps);
-            for (int k = S.k0; k <= S.k1; ++k) {
-                const double rs = radial_weight(D, S, sm[u].rho, A.eps, k);
+            const SampleShape S = sample_shape(D, sm[u].rho, sm[u].x, sm[u].y, A.eps, par_s);
+#pragma unroll
+            for (int jr = 0; jr < 7; ++jr) {
+                const int k = S.kc - 3 + jr;
+                const double rs = S.w[jr];
                 if (rs == 0.0) continue;
                 for (int v = 0; v <= hi[u] - lo[u]; ++v) {
                     const double w = sm[u].qw * dF[v] * rs;
@@ -676,6 +684,8 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             for (int c = threadIdx.x; c < 2 * npl * tz * tr; c += 256) tile[c] = 0.0;
             __syncthreads();
         }
+        const double inv_dt = 1.0 / D.dt, inv_dz = 1.0 / D.dz;
+        const double par_s = (D.m % 2 == 0) ? 1.0 : -1.0, par_a = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;
         auto add = [&](int plane, int k, int i, double re, double im) {
             if (use_tile) {
                 double *c = tile + 2 * ((plane * tr + k - fp[2]) * tz + i - fp[0]);
@@ -697,17 +707,20 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             const double vr = r0 > 0.0 ? (x * vx + y * vy) / r0 : 0.0, vt = r0 > 0.0 ? (x * vy - y * vx) / r0 : 0.0;
             const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
             const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym);
-            const SampleShape Sp = sample_shape(D, rp, xp, yp, A.eps), Sm = sample_shape(D, rm, xm, ym, A.eps);
             // transverse currents at the sample (m_A fold)
             if (vr != 0.0 || vt != 0.0) {
-                SampleShape S0 = sample_shape(D, r0, x, y, A.eps);
-                S0.par = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;
+                const SampleShape S0 = sample_shape(D, r0, x, y, A.eps, par_a);
                 const int lo = (int)floor(zc) - 1;
-                for (int k = S0.k0; k <= S0.k1; ++k) {
-                    const double rs = radial_weight(D, S0, r0, A.eps, k);
+                double wz[4];
+#pragma unroll
+                for (int u2 = 0; u2 < 4; ++u2) wz[u2] = qw * bspline3(lo + u2 - zc) * inv_dz;
+#pragma unroll
+                for (int jr = 0; jr < 7; ++jr) {
+                    const int k = S0.kc - 3 + jr;
+                    const double rs = S0.w[jr];
                     if (rs == 0.0) continue;
                     for (int u2 = 0; u2 < 4; ++u2) {
-                        const double w = qw * bspline3(lo + u2 - zc) / D.dz * rs;
+                        const double w = wz[u2] * rs;
                         if (w == 0.0) continue;
                         add(0, k, lo + u2, w * vr * S0.ar, w * vr * S0.ai);
                         add(1, k, lo + u2, w * vt * S0.ar, w * vt * S0.ai);
@@ -716,22 +729,34 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             }
             // longitudinal current and planar density differential over the nodes of both z shapes
             const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
-            double dF[8], sz[8];
+            double dF[8], sz[8];  // nodes lo .. hi (at most 8), 0 beyond
             double Fp = 0.0, Fm = 0.0;
-            for (int v = 0; v <= hi - lo; ++v) {
-                dF[v] = (Fm - Fp) / D.dt;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                dF[v] = sz[v] = 0.0;
+                if (v > hi - lo) continue;
+                dF[v] = (Fm - Fp) * inv_dt;
                 const double bp = bspline3(lo + v - zp), bm = bspline3(lo + v - zm);
                 Fp += bp;
                 Fm += bm;
-                sz[v] = 0.5 * (bp + bm) / D.dz;
+                sz[v] = 0.5 * (bp + bm) * inv_dz;
             }
+            // rows of both shapes
+            const SampleShape Sp = sample_shape(D, rp, xp, yp, A.eps, par_s), Sm = sample_shape(D, rm, xm, ym, A.eps, par_s);
             const int k0 = min(Sp.k0, Sm.k0), k1 = max(Sp.k1, Sm.k1);
             for (int k = k0; k <= k1; ++k) {
-                const double wp = radial_weight(D, Sp, rp, A.eps, k), wm = radial_weight(D, Sm, rm, A.eps, k);
+                const int jp = k - Sp.kc + 3, jm = k - Sm.kc + 3;
+                double wp = 0.0, wm = 0.0;  // selects with static indices keep the shapes in registers
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    wp = jp == q ? Sp.w[q] : wp;
+                    wm = jm == q ? Sm.w[q] : wm;
+                }
                 if (wp == 0.0 && wm == 0.0) continue;
                 const double sr = 0.5 * (wp * Sp.ar + wm * Sm.ar), si = 0.5 * (wp * Sp.ai + wm * Sm.ai);
-                const double dr_ = (wp * Sp.ar - wm * Sm.ar) / D.dt, di = (wp * Sp.ai - wm * Sm.ai) / D.dt;
-                for (int v = 0; v <= hi - lo; ++v) {
+                const double dr_ = (wp * Sp.ar - wm * Sm.ar) * inv_dt, di = (wp * Sp.ai - wm * Sm.ai) * inv_dt;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
                     if (dF[v] != 0.0) add(2, k, lo + v, qw * dF[v] * sr, qw * dF[v] * si);
                     if (A.rho_xy && sz[v] != 0.0) add(3, k, lo + v, qw * sz[v] * dr_, qw * sz[v] * di);
                 }
@@ -769,10 +794,12 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
         const int lo = (int)floor(zc) - 1;
         double wz[4];
         for (int u = 0; u < 4; ++u) wz[u] = bspline3(lo + u - zc) / D.dz;
-        const SampleShape S = sample_shape(D, rho, x, y, A.eps);
+        const SampleShape S = sample_shape(D, rho, x, y, A.eps, (D.m % 2 == 0) ? 1.0 : -1.0);
         R *rp = (R *)A.j[p];
-        for (int k = S.k0; k <= S.k1; ++k) {
-            const double rs = radial_weight(D, S, rho, A.eps, k);
+#pragma unroll
+        for (int jr = 0; jr < 7; ++jr) {
+            const int k = S.kc - 3 + jr;
+            const double rs = S.w[jr];
             if (rs == 0.0) continue;
             for (int u = 0; u < 4; ++u) {
                 const double v = qw * wz[u] * rs;
