@@ -977,48 +977,51 @@ __global__ __launch_bounds__(256) void k_seg_solve(SolveArgs S, int fwd)
     }
 }
 
-// k_seg_fix: one thread per column sweeps the segments in the order of the pass and writes the true
-// boundary values of each (but the first) to wbuf: those of the segment before it (forward) or after it
-// (backward), formed as the zero-start value plus that segment's response to its own boundary values.
+// k_seg_fix: a group of GS >= N_D lanes per column (lane t forms boundary value t) sweeps the segments in
+// the order of the pass and writes the true boundary values of each (but the first) to wbuf: those of the
+// segment before it (forward) or after it (backward), formed as the zero-start value plus that segment's
+// response to its own boundary values, which the group exchanges by lane shuffles.  The zero-start value
+// of the next segment is loaded a step ahead.
+constexpr int seg_fix_group(int nd) { return nd <= 1 ? 1 : nd <= 2 ? 2 : nd <= 4 ? 4 : nd <= 8 ? 8 : 16; }
 template <int ND>
 __global__ __launch_bounds__(256) void k_seg_fix(SolveArgs S, int fwd)
 {
+    constexpr int GS = seg_fix_group(ND);
     const auto &P = S.p[blockIdx.y];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= P.nz) return;
+    const int t = threadIdx.x % GS, base = (threadIdx.x % 64) - t;  // lane of boundary value 0 of the group
+    const int i = blockIdx.x * (256 / GS) + threadIdx.x / GS;
+    if (i >= P.nz) return;  // the whole group: shuffles only read lanes of the same column
     const int nr = P.nr, seg = P.seg, ns = P.nseg;
     const size_t nz = (size_t)P.nz;
     const double *G = fwd ? P.gf : P.gb;
-    double2 w[ND];  // boundary values of the segment the sweep has just passed
-#pragma unroll
-    for (int t = 0; t < ND; ++t) w[t] = double2{0.0, 0.0};
+    auto row_of = [&](int step) {  // row of boundary value t of the segment formed at this step
+        const int sg = fwd ? step : ns - 1 - step;
+        return fwd ? sg * seg - 1 - t : (sg + 1) * seg + t;
+    };
+    auto load = [&](int step) {
+        const int k = row_of(step);
+        return (t < ND && step < ns && k >= 0 && k < nr) ? P.work[(size_t)k * nz + i] : double2{0.0, 0.0};
+    };
+    double2 w = double2{0.0, 0.0};  // this lane's boundary value of the segment the sweep has just passed
+    double2 next = load(1);
     for (int step = 1; step < ns; ++step) {
         const int sg = fwd ? step : ns - 1 - step;   // segment whose boundary values are formed
         const int src = fwd ? sg - 1 : sg + 1;        // the segment they lie in
         const bool src_has = fwd ? src >= 1 : src <= ns - 2;  // src itself has boundary values
-        double2 nw[ND];
+        const int k = row_of(step);
+        double2 v = next;
+        next = load(step + 1);
+        if (src_has) {  // + response row of this value to the group's previous values
 #pragma unroll
-        for (int t = 0; t < ND; ++t) {
-            const int k = fwd ? sg * seg - 1 - t : (sg + 1) * seg + t;
-            double2 v = double2{0.0, 0.0};
-            if (k >= 0 && k < nr) {
-                v = P.work[(size_t)k * nz + i];
-                if (src_has) {
-#pragma unroll
-                    for (int u = 0; u < ND; ++u) {
-                        const double g = G[(size_t)k * ND + u];
-                        v.x += g * w[u].x;
-                        v.y += g * w[u].y;
-                    }
-                }
+            for (int u = 0; u < ND; ++u) {
+                const double wx = __shfl(w.x, base + u, 64), wy = __shfl(w.y, base + u, 64);
+                const double g = (t < ND && k >= 0 && k < nr) ? G[(size_t)k * ND + u] : 0.0;
+                v.x += g * wx;
+                v.y += g * wy;
             }
-            nw[t] = v;
         }
-#pragma unroll
-        for (int t = 0; t < ND; ++t) {
-            w[t] = nw[t];
-            P.wbuf[((size_t)sg * ND + t) * nz + i] = nw[t];
-        }
+        w = v;
+        if (t < ND) P.wbuf[((size_t)sg * ND + t) * nz + i] = v;
     }
 }
 
@@ -1524,11 +1527,13 @@ hipError_t correct_solve_nd(const SolveArgs &a, hipStream_t s)
     int nzmax = 0;
     for (int p = 0; p < a.nprob; ++p) nzmax = a.p[p].nz > nzmax ? a.p[p].nz : nzmax;
     const unsigned bx = (unsigned)((nzmax + 255) / 256);
-    const dim3 seg(bx, (unsigned)a.nprob, (unsigned)a.smax), cols(bx, (unsigned)a.nprob);
+    const dim3 seg(bx, (unsigned)a.nprob, (unsigned)a.smax);
+    constexpr int per = 256 / seg_fix_group(ND);  // columns per block of k_seg_fix
+    const dim3 fix((unsigned)((nzmax + per - 1) / per), (unsigned)a.nprob);
     for (int fwd = 1; fwd >= 0; --fwd) {
         hipLaunchKernelGGL(k_seg_solve<ND>, seg, dim3(256), 0, s, a, fwd);
         if (a.smax > 1) {
-            hipLaunchKernelGGL(k_seg_fix<ND>, cols, dim3(256), 0, s, a, fwd);
+            hipLaunchKernelGGL(k_seg_fix<ND>, fix, dim3(256), 0, s, a, fwd);
             hipLaunchKernelGGL(k_seg_apply<ND>, seg, dim3(256), 0, s, a, fwd);
         }
     }
