@@ -1025,29 +1025,39 @@ __global__ __launch_bounds__(256) void k_seg_fix(SolveArgs S, int fwd)
     }
 }
 
-// k_seg_apply: rows of every segment but the first of the pass += response x boundary values.
+// k_seg_apply: rows of every segment but the first of the pass += response x boundary values.  One thread
+// per column and chunk of SEG_APPLY_ROWS rows of a segment (blockIdx.z = segment * chunks + chunk); the
+// chunk's loads are issued before its stores.
+constexpr int SEG_APPLY_ROWS = 8;
 template <int ND>
-__global__ __launch_bounds__(256) void k_seg_apply(SolveArgs S, int fwd)
+__global__ __launch_bounds__(256) void k_seg_apply(SolveArgs S, int fwd, int chunks)
 {
     const auto &P = S.p[blockIdx.y];
-    const int i = blockIdx.x * 256 + threadIdx.x, sg = blockIdx.z;
+    const int i = blockIdx.x * 256 + threadIdx.x, sg = blockIdx.z / chunks, ch = blockIdx.z % chunks;
     if (sg >= P.nseg || i >= P.nz || sg == (fwd ? 0 : P.nseg - 1)) return;
-    const int a = sg * P.seg, b = min(P.nr, a + P.seg);
+    const int a = sg * P.seg + ch * SEG_APPLY_ROWS, b = min(min(P.nr, (sg + 1) * P.seg), a + SEG_APPLY_ROWS);
+    if (a >= b) return;
     const size_t nz = (size_t)P.nz;
     const double *G = fwd ? P.gf : P.gb;
     double2 w[ND];
 #pragma unroll
     for (int t = 0; t < ND; ++t) w[t] = P.wbuf[((size_t)sg * ND + t) * nz + i];
-    for (int k = a; k < b; ++k) {
-        double2 v = P.work[(size_t)k * nz + i];
+    double2 v[SEG_APPLY_ROWS];
+#pragma unroll
+    for (int c = 0; c < SEG_APPLY_ROWS; ++c) v[c] = a + c < b ? P.work[(size_t)(a + c) * nz + i] : double2{0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < SEG_APPLY_ROWS; ++c) {
+        const int k = min(a + c, b - 1);
 #pragma unroll
         for (int u = 0; u < ND; ++u) {
             const double g = G[(size_t)k * ND + u];
-            v.x += g * w[u].x;
-            v.y += g * w[u].y;
+            v[c].x += g * w[u].x;
+            v[c].y += g * w[u].y;
         }
-        P.work[(size_t)k * nz + i] = v;
     }
+#pragma unroll
+    for (int c = 0; c < SEG_APPLY_ROWS; ++c)
+        if (a + c < b) P.work[(size_t)(a + c) * nz + i] = v[c];
 }
 
 // Jbar_rho(k) += sum_j a_j (phi(k + j - 1) - phi(k - j)) / dr on the staggered rows k >= 1 (phi on the
@@ -1527,14 +1537,17 @@ hipError_t correct_solve_nd(const SolveArgs &a, hipStream_t s)
     int nzmax = 0;
     for (int p = 0; p < a.nprob; ++p) nzmax = a.p[p].nz > nzmax ? a.p[p].nz : nzmax;
     const unsigned bx = (unsigned)((nzmax + 255) / 256);
-    const dim3 seg(bx, (unsigned)a.nprob, (unsigned)a.smax);
+    int segmax = 0;
+    for (int p = 0; p < a.nprob; ++p) segmax = a.p[p].seg > segmax ? a.p[p].seg : segmax;
+    const int chunks = (segmax + SEG_APPLY_ROWS - 1) / SEG_APPLY_ROWS;
+    const dim3 seg(bx, (unsigned)a.nprob, (unsigned)a.smax), app(bx, (unsigned)a.nprob, (unsigned)(a.smax * chunks));
     constexpr int per = 256 / seg_fix_group(ND);  // columns per block of k_seg_fix
     const dim3 fix((unsigned)((nzmax + per - 1) / per), (unsigned)a.nprob);
     for (int fwd = 1; fwd >= 0; --fwd) {
         hipLaunchKernelGGL(k_seg_solve<ND>, seg, dim3(256), 0, s, a, fwd);
         if (a.smax > 1) {
             hipLaunchKernelGGL(k_seg_fix<ND>, fix, dim3(256), 0, s, a, fwd);
-            hipLaunchKernelGGL(k_seg_apply<ND>, seg, dim3(256), 0, s, a, fwd);
+            hipLaunchKernelGGL(k_seg_apply<ND>, app, dim3(256), 0, s, a, fwd, chunks);
         }
     }
     return hipGetLastError();
