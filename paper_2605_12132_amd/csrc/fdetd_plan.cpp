@@ -1259,12 +1259,14 @@ int gather_impl(fdetd_plan_t plan, void *const *psi, const double *samples, int6
             return fail(plan, FDETD_E_ARG, "fdetd_gather: problem %d is not a mode of the same grid as problem 0", p);
         if (!aligned(psi[p], eb)) return fail(plan, FDETD_E_ARG, "fdetd_gather: psi[%d] NULL or misaligned", p);
     }
+    if (ss != 0 && 4 * plan->probs[0].cells > (size_t)INT32_MAX)
+        return fail(plan, FDETD_E_ARG, "fdetd_gather_supersampled: grid of %zu cells too large (at most 2^29)",
+                    plan->probs[0].cells);
     if (n == 0) return FDETD_OK;
     const int prec = prec_code(plan->precision);
-    // the nodes and rows the samples' shapes touch; the destagger passes compute only those (grown by the
-    // rows the second pass of B_theta reads from the first)
-    // (box and the partial boxes of its reduction sit in planes 1..5 of problem 0's second stage vector,
-    // which the gather does not otherwise use)
+    // The nodes and rows the samples' shapes touch: the destagger passes compute only those (rows grown
+    // where a later pass reads more).  The box and the partial boxes of its reduction sit in planes 1..5
+    // of problem 0's second stage vector, which the gather does not otherwise use.
     const size_t pb0 = plan->probs[0].cells * elem_bytes(plan->precision);
     int *box = (int *)((char *)plan->probs[0].buf[1] + pb0);
     const size_t room = (5 * pb0) / (4 * sizeof(int)) - 1;
@@ -1347,9 +1349,6 @@ int gather_supersampled(fdetd_plan_t plan, void *const *psi, const double *sampl
     const size_t eb = elem_bytes(plan->precision);
     const int prec = prec_code(plan->precision);
     const fdetd_problem_desc &d0 = plan->probs[0].d;
-    if (4 * plan->probs[0].cells > (size_t)INT32_MAX)
-        return fail(plan, FDETD_E_ARG, "fdetd_gather_supersampled: grid of %zu cells too large (at most 2^29)",
-                    plan->probs[0].cells);
     for (int p = 0; p < np; ++p) {
         Prob &q = plan->probs[p];
         if (!q.fine && hipMalloc(&q.fine, 24 * q.cells * eb) != hipSuccess) {
