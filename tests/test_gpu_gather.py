@@ -186,3 +186,27 @@ def test_supersampled_gather_exact_for_linear_fields(ss):
             odd = (pA if POLAR[c] else pS) == -1
             want = want + np.real((r if odd else 1.0) * (Fm[c, 0] + Fm[c, 1] * z / 5) * np.exp(1j * m * th))
         assert np.max(np.abs(got[:, c] - want)) < 1e-11 * max(1.0, np.max(np.abs(want))), (ss, c)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gather_minimal_grids(precision):
+    """The smallest grids a plan accepts (nz = 2 N_D + 1, nr = N_D + 1): every stencil and the axis rule
+    reach the grid edges; plain and supersampled gathers against the oracle."""
+    import torch
+    for order in (2, 8, 32):
+        nd = order // 2
+        w = workload([0, 1, 2], order, nz=2 * nd + 1, nr=nd + 1)
+        rng = np.random.default_rng(order + 10 * precision)
+        states = [rng.uniform(-1, 1, (6, w.nr[0], w.nz[0])) + 1j * rng.uniform(-1, 1, (6, w.nr[0], w.nz[0]))
+                  for _ in range(w.n)]
+        s = samples(rng, 1500, w.nz[0], w.nr[0], w.dz, w.dr)
+        cd = torch.complex128 if precision == F.FP64 else torch.complex64
+        plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
+        psi = [dev(x, cd) for x in states]
+        sd = dev(s, torch.float64)
+        for ss in (0, 1, 2, 3):
+            got = plan.gather(psi, sd, supersample=ss).cpu().numpy()
+            want = oracle.gather_fine(grids(w), states, s, ss)
+            err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+            assert err < (1e-12 if precision == F.FP64 else 1e-5), (order, ss, err)
+        plan.close()
