@@ -301,7 +301,8 @@ def envelope_pass(steps, layer=32):
     FP32C plans, graph replay of `steps` steps.  Its working set (about 220 MB in FP64) mostly fits the
     256 MB Infinity Cache, so the rate is reported without an HBM fraction.  Each precision is also run
     with absorbing layers (`layer` cells at both z ends and at the outer rho edge, sigma_max half the
-    largest the plan's stability bound admits, quadratic grading)."""
+    largest the plan's stability bound admits, quadratic grading).  The ponderomotive field of the final
+    state (envelope_ponderomotive) is timed apart."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -334,16 +335,29 @@ def envelope_pass(steps, layer=32):
             ev1.record(stream)
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1)
+            # ponderomotive field of the final state (|a|^2, A~_rho, A~_z), 20 calls
+            pond = plan.ponderomotive([a])
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(20):
+                plan.ponderomotive([a], pond)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            pond_us = ev0.elapsed_time(ev1) / 20 * 1e3
             plan.close()
-        return ms, smax, a, at
+        return ms, smax, a, at, pond_us
 
     for tag, prec, cd, rd in (("fp64", F.FP64, torch.complex128, torch.float64),
                               ("fp32c", F.FP32C, torch.complex64, torch.float32)):
-        ms, _, a, at = run(prec, cd, rd, False)
-        out[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps)
+        ms, _, a, at, pond_us = run(prec, cd, rd, False)
+        # ponderomotive algorithmic bytes per cell: the complex envelope read once, three real planes written
+        pond_bytes = cells * (2 + 3) * (8 if prec == F.FP64 else 4)
+        out[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps,
+                        ponderomotive_us=round(pond_us, 2), ponderomotive_GBs=round(pond_bytes / (pond_us * 1e3), 1))
         res[tag] = (a.cpu().numpy().astype(np.complex128), at.cpu().numpy().astype(np.complex128))
-        log(f"envelope {tag}: {ms / steps:.4f} ms/step, {out[tag]['value']:.4g} cell-updates/s")
-        ms, smax, _, _ = run(prec, cd, rd, True)
+        log(f"envelope {tag}: {ms / steps:.4f} ms/step, {out[tag]['value']:.4g} cell-updates/s; ponderomotive "
+            f"field {pond_us:.1f} us ({out[tag]['ponderomotive_GBs']:.0f} GB/s algorithmic)")
+        ms, smax, _, _, _ = run(prec, cd, rd, True)
         out[tag]["absorbing"] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, lz=layer, lr=layer,
                                      sigma_max=round(smax, 4))
         log(f"envelope {tag} with absorbing layers: {ms / steps:.4f} ms/step")

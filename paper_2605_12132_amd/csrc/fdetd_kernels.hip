@@ -813,36 +813,52 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
 }
 
 // --------------------------------------------------------------------------------------------------
-// Ponderomotive field of the envelope model (section 4.3), m = 0, one thread per cell:
+// Ponderomotive field of the envelope model (section 4.3), m = 0:
 //   |a|^2,  A~_rho(k) = -sum_j a_j (I(k + j - 1) - I(k - j)) / dr (staggered rows k >= 1, row 0 = 0),
 //   A~_z(i) = -sum_j a_j (I(i + j - 1) - I(i - j)) / dz (staggered columns);
 // I = |a|^2 with rows below the axis mirrored (even), rows from nr on and columns outside the grid 0.
+// Blocks of PON_Z columns x PON_R rows: I over the block and its N_D-wide halo is formed once into LDS,
+// then each thread takes PON_R / 4 rows of one column.
 // --------------------------------------------------------------------------------------------------
+constexpr int PON_Z = 64, PON_R = 16;
 template <typename R>
 __global__ __launch_bounds__(256) void k_ponderomotive(const ProbDesc *Dp, const void *av, void *outv, int nd)
 {
     using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+    constexpr int TW = PON_Z + 2 * kMaxND, TH = PON_R + 2 * kMaxND;
+    __shared__ double T[TH * TW];
     const ProbDesc &D = *Dp;
-    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
-    if (i >= D.nz) return;
+    const int i0 = blockIdx.x * PON_Z, k0 = blockIdx.y * PON_R;
+    const int tw = PON_Z + 2 * nd, th = PON_R + 2 * nd;  // tile: rows k0 - nd .., columns i0 - nd ..
     const V *a = (const V *)av;
-    auto I = [&](int q, int c) -> double {
-        if (c < 0 || c >= D.nz) return 0.0;
+    for (int e = threadIdx.x; e < tw * th; e += 256) {
+        const int c = i0 - nd + e % tw, q = k0 - nd + e / tw;
         const int qq = q < 0 ? -1 - q : q;
-        if (qq >= D.nr) return 0.0;
-        const V v = a[(size_t)qq * D.nz + c];
-        return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-    };
-    double gr = 0.0, gz = 0.0;
-    for (int j = 1; j <= nd; ++j) {
-        if (k >= 1) gr += D.ar[j - 1] * (I(k + j - 1, i) - I(k - j, i));
-        gz += D.az[j - 1] * (I(k, i + j - 1) - I(k, i - j));
+        double v = 0.0;
+        if (c >= 0 && c < D.nz && qq < D.nr) {
+            const V x = a[(size_t)qq * D.nz + c];
+            v = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+        }
+        T[(e / tw) * TW + e % tw] = v;
     }
+    __syncthreads();
+    const int ci = threadIdx.x % PON_Z, i = i0 + ci;
+    if (i >= D.nz) return;
     R *out = (R *)outv;
-    const size_t o = (size_t)k * D.nz + i;
-    out[o] = (R)I(k, i);
-    out[D.plane + o] = (R)(-gr);
-    out[2 * D.plane + o] = (R)(-gz);
+    for (int r = threadIdx.x / PON_Z; r < PON_R; r += 256 / PON_Z) {
+        const int k = k0 + r;
+        if (k >= D.nr) break;
+        auto I = [&](int dq, int dc) { return T[(r + nd + dq) * TW + ci + nd + dc]; };  // I(k + dq, i + dc)
+        double gr = 0.0, gz = 0.0;
+        for (int j = 1; j <= nd; ++j) {
+            if (k >= 1) gr += D.ar[j - 1] * (I(j - 1, 0) - I(-j, 0));
+            gz += D.az[j - 1] * (I(0, j - 1) - I(0, -j));
+        }
+        const size_t o = (size_t)k * D.nz + i;
+        out[o] = (R)I(0, 0);
+        out[D.plane + o] = (R)(-gr);
+        out[2 * D.plane + o] = (R)(-gz);
+    }
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -1509,7 +1525,8 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
 hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,
                                 hipStream_t s)
 {
-    const dim3 grid((unsigned)((nz + 255) / 256), (unsigned)nr);
+    if (nd < 1 || nd > kMaxND) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((nz + PON_Z - 1) / PON_Z), (unsigned)((nr + PON_R - 1) / PON_R));
     if (prec == P64) hipLaunchKernelGGL(k_ponderomotive<double>, grid, dim3(256), 0, s, d, a, out, nd);
     else hipLaunchKernelGGL(k_ponderomotive<float>, grid, dim3(256), 0, s, d, a, out, nd);
     return hipGetLastError();
