@@ -1,0 +1,34 @@
+"""Host-side checks of the benchmark script (no GPU): the one-GPU contract and the rule that reports the
+committed HBM traffic only for the kernel sources and segment lengths it was measured on."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stdout
+
+
+def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
+    text = open(bench.TRAFFIC_FILE).read()
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_"))
+    seg64 = int(fields["traffic_seg_rows_fp64"])
+    seg32 = int(fields["traffic_seg_rows_fp32c"])
+    t64 = bench.measured_traffic("fp64", seg64)
+    t32 = bench.measured_traffic("fp32c", seg32)
+    if fields["traffic_source_hash"].strip() == bench.kernel_source_hash():  # counters taken on these sources
+        assert t64 == int(float(fields["traffic_bytes_per_launch_fp64"])) and t64 > 0
+        assert t32 == int(float(fields["traffic_bytes_per_launch_fp32c"])) and t32 > 0
+    else:  # the kernel changed since: no traffic figure until the counters are taken again
+        assert t64 is None and t32 is None
+    # another tiling, or other sources: no traffic figure
+    assert bench.measured_traffic("fp64", seg64 * 2) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("fp64", seg64) is None
