@@ -779,35 +779,83 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
 
 // Charge density of mode m of the samples shifted along z, one plane per problem (sections 3.2, 3.5):
 //   rho(z_i, rho_k) += q w S3(i - z'/dz) / dz * R_k * A_m,  z' = z + shift.
+// DEP_PER_THREAD consecutive samples per thread; as for J_z, a block whose samples' shapes touch at most
+// DEP_TILE cells of a problem sums its adds in an FP64 LDS tile and adds the tile to the plane once,
+// otherwise every add is a global atomic.
 template <typename R>
 __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
 {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= A.n) return;
-    const double z = A.samples[4 * s] + A.shift, x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
-    const double qw = A.samples[4 * s + 3];
-    const double rho = sqrt(x * x + y * y);
+    __shared__ double tile[2 * DEP_TILE];
+    __shared__ int red[16];
+    const int64_t s0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * DEP_PER_THREAD;
     for (int p = 0; p < A.nprob; ++p) {
         const ProbDesc &D = A.probs[p];
-        const double zc = z / D.dz;
-        if (!z_on_grid(D, zc)) continue;
-        const int lo = (int)floor(zc) - 1;
-        double wz[4];
-        for (int u = 0; u < 4; ++u) wz[u] = bspline3(lo + u - zc) / D.dz;
-        const SampleShape S = sample_shape(D, rho, x, y, A.eps, (D.m % 2 == 0) ? 1.0 : -1.0);
-        R *rp = (R *)A.j[p];
+        int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};  // zmin, zmax, kmin, kmax
 #pragma unroll
-        for (int jr = 0; jr < 7; ++jr) {
-            const int k = S.kc - 3 + jr;
-            const double rs = S.w[jr];
-            if (rs == 0.0) continue;
-            for (int u = 0; u < 4; ++u) {
-                const double v = qw * wz[u] * rs;
-                if (v == 0.0) continue;
-                R *c = rp + 2 * ((size_t)k * D.nz + lo + u);
-                atomicAdd(c, (R)(v * S.ar));
-                atomicAdd(c + 1, (R)(v * S.ai));
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            const int64_t s = s0 + u;
+            if (s >= A.n) continue;
+            const double zc = (A.samples[4 * s] + A.shift) / D.dz;
+            if (!z_on_grid(D, zc)) continue;
+            const double x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+            const int kc = (int)floor(sqrt(x * x + y * y) / D.dr);
+            fp[0] = min(fp[0], (int)floor(zc) - 1);
+            fp[1] = max(fp[1], (int)floor(zc) + 2);
+            fp[2] = min(fp[2], max(kc - 3, 0));
+            fp[3] = max(fp[3], min(kc + 3, D.nr - 1));
+        }
+        block_minmax(fp, red);
+        if (fp[1] < fp[0]) continue;  // no sample of the block is deposited into this problem
+        const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
+        const bool use_tile = (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
+        R *rp = (R *)A.j[p];
+        if (use_tile) {
+            for (int c = threadIdx.x; c < 2 * tz * tr; c += 256) tile[c] = 0.0;
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (int u = 0; u < DEP_PER_THREAD; ++u) {
+            const int64_t s = s0 + u;
+            if (s >= A.n) continue;
+            const double z = A.samples[4 * s] + A.shift, x = A.samples[4 * s + 1], y = A.samples[4 * s + 2];
+            const double qw = A.samples[4 * s + 3];
+            const double zc = z / D.dz;
+            if (!z_on_grid(D, zc)) continue;
+            const double rho = sqrt(x * x + y * y);
+            const int lo = (int)floor(zc) - 1;
+            double wz[4];
+            for (int v = 0; v < 4; ++v) wz[v] = bspline3(lo + v - zc) / D.dz;
+            const SampleShape S = sample_shape(D, rho, x, y, A.eps, (D.m % 2 == 0) ? 1.0 : -1.0);
+#pragma unroll
+            for (int jr = 0; jr < 7; ++jr) {
+                const int k = S.kc - 3 + jr;
+                const double rs = S.w[jr];
+                if (rs == 0.0) continue;
+                for (int v = 0; v < 4; ++v) {
+                    const double w = qw * wz[v] * rs;
+                    if (w == 0.0) continue;
+                    if (use_tile) {
+                        double *c = tile + 2 * ((k - fp[2]) * tz + lo + v - fp[0]);
+                        atomicAdd(c, w * S.ar);
+                        atomicAdd(c + 1, w * S.ai);
+                    } else {
+                        R *c = rp + 2 * ((size_t)k * D.nz + lo + v);
+                        atomicAdd(c, (R)(w * S.ar));
+                        atomicAdd(c + 1, (R)(w * S.ai));
+                    }
+                }
             }
+        }
+        if (use_tile) {
+            __syncthreads();
+            for (int c = threadIdx.x; c < tz * tr; c += 256) {
+                const double re = tile[2 * c], im = tile[2 * c + 1];
+                if (re == 0.0 && im == 0.0) continue;
+                R *g = rp + 2 * ((size_t)(fp[2] + c / tz) * D.nz + fp[0] + c % tz);
+                atomicAdd(g, (R)re);
+                atomicAdd(g + 1, (R)im);
+            }
+            __syncthreads();  // the tile is reused by the next problem
         }
     }
 }
@@ -1704,7 +1752,8 @@ hipError_t launch_deposit_current(int prec, const DepositArgs &a, hipStream_t s)
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256));
+    const int64_t per_block = 256 * DEP_PER_THREAD;
+    const dim3 grid((unsigned)((a.n + per_block - 1) / per_block));
     if (prec == P64) hipLaunchKernelGGL(k_deposit_rho<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_deposit_rho<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();

@@ -73,11 +73,13 @@ def test_deposit_rejects_bad_arguments():
     plan.close()
 
 
+@pytest.mark.parametrize("ordered", [False, True])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_deposit_rho_matches_oracle_and_continuity(precision):
+def test_deposit_rho_matches_oracle_and_continuity(precision, ordered):
     """Charge densities of the samples shifted by -+ vz dt/2 against the oracle (same tolerances as J_z),
     and, FP64, the discrete continuity equation between the GPU's two densities and its J_z:
-    (rho_+(i) - rho_-(i)) / dt + (J_z(i + 1/2) - J_z(i - 1/2)) / dz = 0 to rounding."""
+    (rho_+(i) - rho_-(i)) / dt + (J_z(i + 1/2) - J_z(i - 1/2)) / dz = 0 to rounding.  Samples in z order
+    go through the LDS tiles, unordered ones through global atomics."""
     import torch
     dz = I.LAMBDA0 / 20
     nz, nr = 260, 40
@@ -85,6 +87,8 @@ def test_deposit_rho_matches_oracle_and_continuity(precision):
     w = I.Workload("dep", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [8] * 3, 8, dz, 2 * dz, dt, 1)
     rng = np.random.default_rng(33)
     s = samples(rng, 12000, nz, nr, dz, 2 * dz)
+    if ordered:
+        s = s[np.argsort(s[:, 0], kind="stable")]
     sd = dev(s, torch.float64)
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     plan = F.Plan(w.problems(), precision=precision, flags=1)
@@ -102,7 +106,7 @@ def test_deposit_rho_matches_oracle_and_continuity(precision):
         want = oracle.deposit_rho(g, s, 0.5 * vz * dt, eps=0.5)
         got = rp[p].cpu().numpy().astype(np.complex128)
         err = rel_l2(got, want)
-        log(f"deposit rho m={p} precision={precision}: rel L2 {err:.2e}")
+        log(f"deposit rho m={p} precision={precision} ordered={ordered}: rel L2 {err:.2e}")
         assert err < tol
         if precision == F.FP64:
             # samples skipped by the current (shape past a z end at either position) are also skipped by
