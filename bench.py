@@ -424,7 +424,8 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
     each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
     of peak density n_b) moving at c, in z order, deposited with fdetd_deposit_jz (timed separately,
     including the advance of the sample positions; all currents and rho_xy of the same samples with a
-    transverse velocity spread, fdetd_deposit_current, timed apart), then graph replay of `steps` field
+    transverse velocity spread, fdetd_deposit_current, and their charge density, fdetd_deposit_rho, timed
+    apart), then graph replay of `steps` field
     steps, then the fields of the final state at the samples (fdetd_gather, timed apart, also with 2x
     supersampling along z and rho).  FP64 and FP32C; the FP32C error against FP64 after the same steps."""
     import torch
@@ -478,8 +479,18 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
             ev1.record(stream)
             torch.cuda.synchronize()
             dep_cur_ms = ev0.elapsed_time(ev1) / 5
+            # charge density of the same samples (fdetd_deposit_rho), 5 calls
+            R1 = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            plan.deposit_rho(smp, R1)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                plan.deposit_rho(smp, R1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            dep_rho_ms = ev0.elapsed_time(ev1) / 5
             plan.close()
-            del J4, s8
+            del J4, s8, R1
         psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
         del J
         torch.cuda.empty_cache()
@@ -508,11 +519,12 @@ def lwfa_pass(steps, warmup, n_samples=10 ** 6):
         res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
                         frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms, gather_ms=gather_ms,
                         gather_supersampled_ms=gather_ss_ms, deposit_current_ms=dep_cur_ms,
+                        deposit_rho_ms=dep_rho_ms,
                         seg_rows=info["seg_rows"])
         psis[tag] = psi
         log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
             f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step (all currents and rho_xy "
-            f"{dep_cur_ms:.3f} ms); gather {gather_ms:.3f} ms, "
+            f"{dep_cur_ms:.3f} ms, charge density {dep_rho_ms:.3f} ms); gather {gather_ms:.3f} ms, "
             f"2x supersampled (z and rho) {gather_ss_ms:.3f} ms")
     num = den = 0.0
     for a, b in zip(psis["fp64"], psis["fp32c"]):
