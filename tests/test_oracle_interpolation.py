@@ -202,3 +202,64 @@ def test_supersampling_quarters_the_shape_smoothing(ss):
     scale = np.max(np.abs(pred_fine))
     assert np.max(np.abs(err_plain - pred_plain)) < 0.02 * np.max(np.abs(pred_plain))
     assert np.max(np.abs(err_fine - pred_fine)) < 0.02 * scale, (np.max(np.abs(err_fine - pred_fine)), scale)
+
+
+def table1():
+    """Rows of the paper's Table 1 (tests/golden): component -> (rho stagger, z stagger, symmetry, q for
+    m = 0, 1, 2)."""
+    import os
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_staggering_symmetry.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, sr, sz, sym, *q = line.split()
+        rows[name] = (Fraction(sr), Fraction(sz), sym, [int(v) for v in q])
+    return rows
+
+
+def test_component_layout_matches_table1():
+    """The staggering and symmetry types the interpolation tests (and the GPU gather tests that import
+    them) assume are the printed ones, and the printed exponents are |m - 1| (mA) or m (mS)."""
+    t = table1()
+    names = ["E_rho", "E_theta", "E_z", "B_rho", "B_theta", "B_z"]
+    for c, name in enumerate(names):
+        sr, sz, sym, q = t[name]
+        assert RST[c] == (sr != 0) and ZST[c] == (sz != 0), name
+        assert POLAR[c] == (sym == "mA"), name
+        assert q == [abs(m - 1) if sym == "mA" else m for m in range(3)], name
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_half_shifts_follow_table1_near_the_axis(m):
+    """For each component and m = 0, 1, 2, a field rho^q (1 + (rho/4)^2) with q from Table 1, sampled on
+    the component's rho positions, is shifted exactly by the oracle's half shift towards the other rho
+    positions on every row next to the axis: S^(+) with the component's parity and axis rule (extrapolate
+    exactly when the table says constant on the axis) for staggered components, S^(-) on rows k >= 1 for
+    primary ones.  Order 8."""
+    t = table1()
+    g = grid(m, 8)
+    pS = 1 if m % 2 == 0 else -1
+    pA = 1 if abs(m - 1) % 2 == 0 else -1
+    r_st = np.arange(g.nr) * g.dr
+    r_pr = (np.arange(g.nr) + 0.5) * g.dr
+    rows = slice(0, g.nr - 4)
+    for name, (sr, _, sym, qs) in t.items():
+        if name == "phi":
+            continue
+        q = qs[m]
+        f = lambda r: r ** q * (1.0 + (r / 4) ** 2)
+        parity = pA if sym == "mA" else pS
+        if sr != 0:  # stored on the staggered rows: S^(+) to the primary rows
+            plane = np.repeat(f(r_st)[:, None], g.nz, 1).astype(complex)
+            plane[0] = 77.0  # axis slot: derived, never read
+            out = oracle.apply_op(g, oracle.OP_SHIFT_PLUS_RHO, plane, parity, q == 0)
+            want = f(r_pr)
+        else:  # stored on the primary rows: S^(-) to the staggered rows k >= 1
+            plane = np.repeat(f(r_pr)[:, None], g.nz, 1).astype(complex)
+            out = oracle.apply_op(g, oracle.OP_SHIFT_MINUS, plane, parity)
+            want = f(r_st)
+            out, want = out[1:], want[1:]
+        err = np.max(np.abs(out[rows] - want[rows, None]))
+        assert err < 1e-12 * max(1.0, np.max(np.abs(want))), (name, m, err)
