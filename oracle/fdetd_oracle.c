@@ -868,11 +868,17 @@ static double bspline3(double x)
     return 0.0;
 }
 
+/* Sign with which the part of a sample's radial shape at rho < 0 is folded back (section 3.5): the
+ * component's m_S or m_A type for m = 0, 1, and antisymmetric for every m > 1, so that a sample on the axis
+ * deposits nothing into those modes. */
+static int fold_mS(int m) { return m > 1 ? -1 : parity_mS(m); }
+static int fold_mA(int m) { return m > 1 ? -1 : parity_mA(m); }
+
 /* Quadrature weights of the radial integral from the axis on the primary rows (section 3.5). */
 static double h_weight(int k) { return k == 0 ? 7.0 / 8.0 : (k == 1 ? 73.0 / 72.0 : 1.0); }
 
 /* Radial shape of section 3.5 of a sample at rho_p on primary row k >= 0 (rho_k = (k + 1/2) dr), with
- * the part at rho < 0 folded back onto row k with the component's parity p (a reading: the mirror rule of
+ * the part at rho < 0 folded back onto row k with the sign p of fold_mS / fold_mA (the mirror rule of
  * section 3.5 applied to the shape):
  *   N^-1 rho_k^(eps - 1) (w_k + p w_(-1-k)),   w_j = S3((rho_j - rho_p) / dr),
  *   N = sum_(k >= 0) h_k rho_k^eps (w_k + w_(-1-k)) dr   (the sample's shape on the folded grid). */
@@ -910,12 +916,12 @@ static int z_inside(const oracle_problem *P, double zc)
     return floor(zc) - 1 >= 0 && floor(zc) + 2 <= P->nz - 1;
 }
 
-/* Charge density of mode m (m_S parity) of the samples shifted by dz_shift along z, added into rho. */
+/* Charge density of mode m (m_S fold) of the samples shifted by dz_shift along z, added into rho. */
 int oracle_deposit_rho(const oracle_problem *P, const double *samples, long n, double dz_shift, double eps,
                        double complex *rho)
 {
     if (check_problem(P) || !samples || !rho || n < 0) return -1;
-    const int nz = P->nz, nr = P->nr, p = parity_mS(P->m);
+    const int nz = P->nz, nr = P->nr, p = fold_mS(P->m);
     for (long s = 0; s < n; ++s) {
         const double z = samples[4 * s] + dz_shift, x = samples[4 * s + 1], y = samples[4 * s + 2];
         if (!z_inside(P, z / P->dz)) continue;
@@ -943,7 +949,7 @@ int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, do
                       double complex *j)
 {
     if (check_problem(P) || !samples || !j || n < 0 || !(P->dt > 0)) return -1;
-    const int nz = P->nz, nr = P->nr, p = parity_mS(P->m);
+    const int nz = P->nz, nr = P->nr, p = fold_mS(P->m);
     double complex *jz = j + 2 * (size_t)nz * nr;
     double *dF = malloc(sizeof(double) * (size_t)nz);
     if (!dF) return -2;
@@ -990,7 +996,7 @@ int oracle_deposit_current(const oracle_problem *P, const double *samples, long 
                            double complex *rho_xy)
 {
     if (check_problem(P) || !samples || !j || n < 0 || !(P->dt > 0)) return -1;
-    const int nz = P->nz, nr = P->nr, pS = parity_mS(P->m), pA = parity_mA(P->m);
+    const int nz = P->nz, nr = P->nr, pS = fold_mS(P->m), pA = fold_mA(P->m);
     const size_t np = (size_t)nz * nr;
     double *dF = malloc(sizeof(double) * (size_t)nz);
     if (!dF) return -2;

@@ -81,13 +81,20 @@ def test_deposit_ring_and_reconstruction():
     del rng
 
 
-@pytest.mark.parametrize("m", [1, 3])
-def test_deposit_on_axis_has_no_odd_modes(m):
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_deposit_on_axis_only_in_mode_0(m):
+    """Section 3.5 folds the part of the shape below the axis back antisymmetrically in every mode m > 1
+    (and with the m_S type, odd, for m = 1), so that a sample on the axis deposits nothing outside m = 0:
+    charge, J_z, and all currents and rho_xy of a sample moving along the axis."""
     g = grid(m)
     s = np.array([[6.0, 0.0, 0.0, 1.0]])
     assert np.max(np.abs(oracle.deposit_rho(g, s))) == 0.0
     assert np.max(np.abs(oracle.deposit_jz(g, s))) == 0.0
+    s8 = np.array([[6.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.9, 0.0]])
+    j, rxy = oracle.deposit_current(g, s8)
+    assert np.max(np.abs(j)) == 0.0 and np.max(np.abs(rxy)) == 0.0
     assert np.max(np.abs(oracle.deposit_rho(grid(0), s))) > 0
+    assert np.max(np.abs(oracle.deposit_current(grid(0), s8)[0][2])) > 0
 
 
 def test_deposit_skips_samples_at_the_z_ends():
