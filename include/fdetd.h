@@ -163,7 +163,8 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
  * with F_-+(i) the cubic-spline weight of the positions z -+ vz dt/2 on the nodes left of z_i - dz/2 (the
  * integrated shape of section 3.6, signed by the discrete continuity equation), R_k the radial shape of
  * section 3.5 (rho_k^(eps-1) times the spline weight, the part beyond the axis folded back with the mode's
- * m_S parity, normalised with the quadrature weights h_0 = 7/8, h_1 = 73/72, h_k = 1) and A_m the
+ * m_S type for m = 0, 1 and antisymmetrically for every m > 1, so that a sample on the axis deposits only
+ * into m = 0; normalised with the quadrature weights h_0 = 7/8, h_1 = 73/72, h_k = 1) and A_m the
  * deposition form of the angular shape of section 3.2 (1/(2 pi) for m = 0, e^(-i m theta)/pi otherwise,
  * for the mode convention of fdetd_step).  Samples move along z only; a sample whose shape reaches past
  * a z end of a grid is not deposited into it.
@@ -186,8 +187,9 @@ FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t
  *   rho_xy  += q w (S(z_i - z+) + S(z_i - z-)) / 2 * (R_S(rho+) A_m(theta+) - R_S(rho-) A_m(theta-)) / dt
  *                                                   (plane 3, only for plans with FDETD_PLAN_CURRENT_CORRECTION)
  * S(x) = S3(x/dz)/dz; F_-+ and A_m as for fdetd_deposit_jz; R_A / R_S the radial shape of fdetd_deposit_jz
- * folded with the m_A (J_rho, J_theta) / m_S (J_z, rho_xy) parity; v_rho = (x v_x + y v_y)/rho and
- * v_theta = (x v_y - y v_x)/rho at the sample, 0 on the axis.  With these, the densities at the end
+ * folded with the m_A (J_rho, J_theta) / m_S (J_z, rho_xy) type for m = 0, 1, antisymmetrically for m > 1;
+ * v_rho = (x v_x + y v_y)/rho and v_theta = (x v_y - y v_x)/rho at the sample, 0 on the axis.  With
+ * these, the densities at the end
  * positions satisfy (rho+ - rho-)/dt + D_z^(+) J_z - rho_xy = 0.  A sample whose z shapes reach past a z
  * end, or that moves more than 3 cells along z in dt, is not deposited.
  *   samples  device array of n x 8 doubles: z, x, y, q w, v_x, v_y, v_z, unused; 8-byte aligned.

@@ -418,8 +418,9 @@ dim3 tile_grid(int nz, int nr) { return dim3((nz + TZ - 1) / TZ, (nr + TR - 1) /
 // Deposition of point samples moving with vz along z (sections 3.2, 3.5, 3.6): J_z(i - 1/2, k) of mode m
 // gains q w (F_-(i) - F_+(i)) / dt * R_k * A_m, where F_-+ are the cubic-spline weights left of i - 1/2 of
 // the positions z -+ vz dt/2 (the integrated shape, with the sign of the discrete continuity equation),
-// R_k the radial shape (rho_k^(eps-1) times the spline weight, the part beyond the axis folded back with the
-// m_S parity (-1)^m, normalised by sum_k h_k rho_k^eps (folded weight) dr with h_0 = 7/8, h_1 = 73/72)
+// R_k the radial shape (rho_k^(eps-1) times the spline weight, the part beyond the axis folded back with
+// fold_mS: the m_S type (-1)^m for m <= 1, antisymmetric for m > 1; normalised by sum_k h_k rho_k^eps (even
+// fold of the weight) dr with h_0 = 7/8, h_1 = 73/72)
 // and A_m the angular shape: 1/(2 pi) for m = 0, e^(-i m theta)/pi otherwise.  A sample whose z shape
 // reaches past a z end is not deposited.  One thread per sample; shapes in FP64; atomic adds.
 // --------------------------------------------------------------------------------------------------
@@ -445,6 +446,12 @@ __device__ __forceinline__ double rk_pow(double rk, double e)
     if (e == -0.5) return 1.0 / sqrt(rk);
     return pow(rk, e);
 }
+
+// Sign with which the part of a sample's radial shape below the axis is folded back (section 3.5): the
+// component's m_S or m_A type for m = 0, 1, antisymmetric for every m > 1 (a sample on the axis then
+// deposits nothing into those modes).
+__device__ __forceinline__ double fold_mS(int m) { return m > 1 ? -1.0 : (m % 2 == 0 ? 1.0 : -1.0); }
+__device__ __forceinline__ double fold_mA(int m) { return m > 1 ? -1.0 : (m == 1 ? 1.0 : -1.0); }
 
 // Radial shape of a sample at rho on the primary rows k = kc - 3 + j, j = 0..6 (folded with parity par,
 // normalised by N; w[j] = 0 off [k0, k1]) and the angular shape of mode m at the sample's angle theta,
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
         const bool use_tile = (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
         R *jz = (R *)A.j[p] + 2 * 2 * D.plane;               // plane 2, interleaved complex
-        const double inv_dt = 1.0 / D.dt, par_s = (D.m % 2 == 0) ? 1.0 : -1.0;
+        const double inv_dt = 1.0 / D.dt, par_s = fold_mS(D.m);
         if (use_tile) {
             for (int c = threadIdx.x; c < 2 * tz * tr; c += 256) tile[c] = 0.0;
             __syncthreads();
@@ -631,7 +638,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 //   J_rho, J_theta += q w v_rho|theta S(z_p) R_A(rho_p) A(theta_p)          (planes 0, 1)
 //   J_z(i - 1/2)   += q w dF(i) (R_S(rho+) A(theta+) + R_S(rho-) A(theta-)) / 2  (plane 2)
 //   rho_xy         += q w (S(z+) + S(z-)) / 2 (R_S(rho+) A(theta+) - R_S(rho-) A(theta-)) / dt  (plane 3)
-// R_A / R_S: radial shape folded with the m_A / m_S parity.  Samples whose z shapes leave the grid or that
+// R_A / R_S: radial shape folded with fold_mA / fold_mS.  Samples whose z shapes leave the grid or that
 // move more than 3 cells along z are skipped.
 // As k_deposit_jz, blocks of DEP_PER_THREAD x 256 consecutive samples accumulate in an LDS tile of
 // DEP_TILE_CUR cells (all planes) when their footprint fits.
@@ -685,7 +692,7 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             __syncthreads();
         }
         const double inv_dt = 1.0 / D.dt, inv_dz = 1.0 / D.dz;
-        const double par_s = (D.m % 2 == 0) ? 1.0 : -1.0, par_a = ((D.m > 1 ? D.m - 1 : 1 - D.m) % 2 == 0) ? 1.0 : -1.0;
+        const double par_s = fold_mS(D.m), par_a = fold_mA(D.m);
         auto add = [&](int plane, int k, int i, double re, double im) {
             if (use_tile) {
                 double *c = tile + 2 * ((plane * tr + k - fp[2]) * tz + i - fp[0]);
@@ -825,7 +832,7 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepositArgs A)
             const int lo = (int)floor(zc) - 1;
             double wz[4];
             for (int v = 0; v < 4; ++v) wz[v] = bspline3(lo + v - zc) / D.dz;
-            const SampleShape S = sample_shape(D, rho, x, y, A.eps, (D.m % 2 == 0) ? 1.0 : -1.0);
+            const SampleShape S = sample_shape(D, rho, x, y, A.eps, fold_mS(D.m));
 #pragma unroll
             for (int jr = 0; jr < 7; ++jr) {
                 const int k = S.kc - 3 + jr;

@@ -193,3 +193,33 @@ def test_deposit_jz_position_ordered_samples(precision):
         log(f"ordered deposit m={p} precision={precision}: rel L2 {err:.2e}")
         assert err < tol
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_samples_on_the_axis_deposit_only_into_mode_0(precision):
+    """Section 3.5 folds the shape below the axis antisymmetrically for m > 1 (m_S / m_A type for m <= 1):
+    samples on the axis deposit nothing into modes 1..4, through every deposition kernel; mode 0 gets it."""
+    import torch
+    dz = I.LAMBDA0 / 20
+    nz, nr = 120, 24
+    modes = [0, 1, 2, 3, 4]
+    w = I.Workload("axis", 0, [nz] * 5, [nr] * 5, modes, [8] * 5, 8, dz, 2 * dz, 0.5 * dz, 1)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY | F.PLAN_CURRENT_CORRECTION)
+    z = np.linspace(40 * dz, 80 * dz, 64)
+    s4 = np.stack([z, np.zeros(64), np.zeros(64), np.ones(64)], axis=1)
+    s8 = np.column_stack([s4, np.zeros((64, 2)), np.full(64, 0.9), np.zeros(64)])
+    J3 = [torch.zeros((3, nr, nz), dtype=cd, device="cuda") for _ in modes]
+    J4 = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in modes]
+    R1 = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in modes]
+    plan.deposit_jz(dev(s4, torch.float64), J3, vz=0.9, eps=0.5)
+    plan.deposit_current(dev(s8, torch.float64), J4, eps=0.5)
+    plan.deposit_rho(dev(s4, torch.float64), R1, eps=0.5)
+    torch.cuda.synchronize()
+    for p, m in enumerate(modes):
+        peak = max(float(torch.max(torch.abs(x[p]))) for x in (J3, J4, R1))
+        if m == 0:
+            assert peak > 0
+        else:
+            assert peak == 0.0, (m, peak)
+    plan.close()
