@@ -102,6 +102,7 @@ def lib():
         L.oracle_destagger.argtypes = [P, vp, vp]
         L.oracle_interpolate.argtypes = [P, vp, vp, C.c_long, vp]
         L.oracle_gather_fine.argtypes = [P, vp, vp, C.c_long, C.c_int, vp]
+        L.oracle_envelope_gather.argtypes = [P, vp, vp, C.c_long, vp]
         _lib = L
     return _lib
 
@@ -250,6 +251,19 @@ def ponderomotive(g: Grid, a):
     out = np.zeros((3, g.nr, g.nz))
     P = g.c()
     _chk(lib().oracle_ponderomotive(C.byref(P), _ptr(x), _ptr(out)), "ponderomotive")
+    return out
+
+
+def envelope_gather(g: Grid, pond, samples):
+    """|a|^2, A~_rho, A~_z of an m = 0 envelope ([3, nr, nz] real, as `ponderomotive` returns) at the
+    samples ([n, 4]: z, x, y, unused) (section 4.3): [n, 3] doubles."""
+    x = np.ascontiguousarray(pond, dtype=np.float64)
+    assert x.shape == (3, g.nr, g.nz)
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    assert s.ndim == 2 and s.shape[1] == 4
+    out = np.zeros((s.shape[0], 3))
+    P = g.c()
+    _chk(lib().oracle_envelope_gather(C.byref(P), _ptr(x), _ptr(s), s.shape[0], _ptr(out)), "envelope_gather")
     return out
 
 

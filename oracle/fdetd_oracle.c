@@ -1234,3 +1234,51 @@ int oracle_gather_fine(const oracle_problem *P, const double complex *psi, const
     free(buf);
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Ponderomotive fields at sample positions (section 4.3: |a|^2 and A~ are interpolated at the      */
+/* particles alongside E and B).  The m = 0 planes of oracle_ponderomotive, |a|^2 (primary), A~_rho */
+/* (staggered rows, odd in rho, 0 on the axis) and A~_z (staggered columns), are brought to the     */
+/* primary grid with S_rho^(+) and S_z^(+) as in oracle_destagger, then interpolated with the cubic */
+/* shapes of oracle_interpolate over the grid extended below the axis (|a|^2, A~_z even, A~_rho     */
+/* odd); no angular factor (m = 0).  Writes out[3 s + c].                                          */
+/* ------------------------------------------------------------------------------------------ */
+int oracle_envelope_gather(const oracle_problem *P, const double *pond, const double *samples, long n, double *out)
+{
+    if (check_problem(P) || P->m != 0 || n < 0) return -1;
+    const int nd = P->fd_order / 2;
+    const size_t np = (size_t)P->nr * P->nz;
+    double s[16], c[16];
+    oracle_coef_halfshift(nd, s);
+    oracle_coef_axis(nd, c);
+    cplx *in = malloc(3 * np * sizeof(cplx)), *prim = malloc(3 * np * sizeof(cplx));
+    if (!in || !prim) {
+        free(in);
+        free(prim);
+        return -2;
+    }
+    for (size_t q = 0; q < 3 * np; ++q) in[q] = pond[q];
+    memcpy(prim, in, np * sizeof(cplx));
+    op_shift_plus_rho(P, s, c, nd, -1, 0, in + np, prim + np);
+    op_shift_plus_z(P, s, nd, in + 2 * np, prim + 2 * np);
+    const int par[3] = {+1, -1, +1};
+    for (long q = 0; q < n; ++q) {
+        const double z = samples[4 * q], x = samples[4 * q + 1], y = samples[4 * q + 2];
+        const double rho = sqrt(x * x + y * y);
+        for (int f = 0; f < 3; ++f) {
+            double v = 0.0;
+            for (int k = -P->nr; k < P->nr; ++k) {
+                const double wr = bspline3(((k + 0.5) * P->dr - rho) / P->dr);
+                if (wr == 0.0) continue;
+                for (int i = 0; i < P->nz; ++i) {
+                    const double wz = bspline3(i - z / P->dz);
+                    if (wz != 0.0) v += wz * wr * creal(prim_val(P, prim + f * np, par[f], k, i));
+                }
+            }
+            out[3 * q + f] = v;
+        }
+    }
+    free(in);
+    free(prim);
+    return 0;
+}

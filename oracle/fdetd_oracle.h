@@ -119,6 +119,10 @@ int oracle_interpolate(const oracle_problem *P, const double complex *prim, cons
 int oracle_gather_fine(const oracle_problem *P, const double complex *psi, const double *samples, long n, int ss,
                        double *fields);
 
+/* |a|^2, A~_rho, A~_z of an m = 0 envelope ([3][nr][nz] real, as oracle_ponderomotive writes them) at n
+ * samples (section 4.3): destaggered to the primary grid and interpolated with cubic shapes; out is n x 3. */
+int oracle_envelope_gather(const oracle_problem *P, const double *pond, const double *samples, long n, double *out);
+
 int oracle_num_threads(void);
 
 #ifdef __cplusplus

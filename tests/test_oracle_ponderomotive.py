@@ -71,3 +71,57 @@ def test_gaussian_converges(order):
 def test_only_mode_zero():
     with pytest.raises(ValueError):
         oracle.ponderomotive(grid(4, m=1), np.ones((30, 60), complex))
+
+
+def test_envelope_gather_exact_on_linear_fields():
+    """Section 4.3 interpolates |a|^2 and A~ at the particles: planes that are linear in z and of the
+    right parity in rho (|a|^2, A~_z: a + b z; A~_rho: rho (c + d z), 0 on the axis), sampled on their
+    own positions (A~_rho on the staggered rows, A~_z on the staggered columns), come out exactly at
+    samples away from the grid ends, next to the axis included."""
+    import math
+    g = oracle.Grid(nz=80, nr=36, m=0, fd_order=8, taylor_order=4, dz=0.3, dr=0.4, dt=0.1, k0=1.0)
+    rng = np.random.default_rng(12)
+    a, b, c, d, e, f = rng.standard_normal(6)
+    zp, zs = np.arange(g.nz) * g.dz, (np.arange(g.nz) - 0.5) * g.dz
+    rp, rs = (np.arange(g.nr) + 0.5) * g.dr, np.arange(g.nr) * g.dr
+    pond = np.zeros((3, g.nr, g.nz))
+    pond[0] = (a + b * zp / 5)[None, :] * np.ones((g.nr, 1))
+    pond[1] = rs[:, None] * (c + d * zp / 5)[None, :]
+    pond[2] = (e + f * zs / 5)[None, :] * np.ones((g.nr, 1))
+    n = 400
+    z = rng.uniform(8 * g.dz, (g.nz - 9) * g.dz, n)
+    r = rng.uniform(0, (g.nr - 8) * g.dr, n)
+    r[:60] = rng.uniform(0, 1.5 * g.dr, 60)
+    th = rng.uniform(-math.pi, math.pi, n)
+    s = np.stack([z, r * np.cos(th), r * np.sin(th), np.ones(n)], axis=1)
+    got = oracle.envelope_gather(g, pond, s)
+    assert np.max(np.abs(got[:, 0] - (a + b * z / 5))) < 1e-12
+    assert np.max(np.abs(got[:, 1] - r * (c + d * z / 5))) < 1e-12
+    assert np.max(np.abs(got[:, 2] - (e + f * z / 5))) < 1e-12
+
+
+def test_envelope_gather_of_a_gaussian_converges():
+    """End to end: the ponderomotive planes of a Gaussian envelope gathered at samples approach |a|^2 and
+    -grad |a|^2 of the continuous Gaussian; the cubic shape's smoothing (h^2/6) f'' dominates the error,
+    which falls about fourfold when the cells halve."""
+    import math
+    errs = []
+    for h in (0.4, 0.2):
+        nz, nr = int(24 / h), int(8 / h)
+        g = oracle.Grid(nz=nz, nr=nr, m=0, fd_order=8, taylor_order=4, dz=h, dr=h, dt=0.5 * h, k0=1.0)
+        zc, L, w = 12.0, 2.5, 2.0
+        z = np.arange(nz) * h
+        r = (np.arange(nr) + 0.5) * h
+        amp = np.exp(-((z[None, :] - zc) / L) ** 2 - (r[:, None] / w) ** 2)
+        pond = oracle.ponderomotive(g, amp.astype(complex))
+        rng = np.random.default_rng(5)
+        n = 200
+        zs = rng.uniform(zc - 4, zc + 4, n)
+        rs = rng.uniform(0, 3.0, n)
+        s = np.stack([zs, rs, np.zeros(n), np.ones(n)], axis=1)
+        got = oracle.envelope_gather(g, pond, s)
+        I = np.exp(-2 * ((zs - zc) / L) ** 2 - 2 * (rs / w) ** 2)
+        want = np.stack([I, 4 * rs / w ** 2 * I, 4 * (zs - zc) / L ** 2 * I], axis=1)  # |a|^2, -d_rho, -d_z
+        errs.append(np.max(np.abs(got - want)))
+    assert errs[0] / errs[1] > 3.0, errs
+    assert errs[1] < 2e-2, errs
