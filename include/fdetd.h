@@ -257,6 +257,22 @@ FDETD_API int fdetd_gather_supersampled(fdetd_plan_t plan, void *const *psi, con
  * FDETD_E_ARG for a Maxwell plan or a problem with m != 0.  Enqueue only. */
 FDETD_API int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, void *const *out);
 
+/* The ponderomotive planes of one m = 0 problem of an envelope plan at n sample positions (section 4.3:
+ * |a|^2 and A~ are interpolated at the particles alongside E and B): A~_rho is brought from the staggered
+ * rows to the primary ones with S_rho^(+) (odd extension, 0 on the axis), A~_z from the staggered columns
+ * with S_z^(+) (0 outside the grid), and the three primary planes are interpolated with the cubic shapes
+ * of fdetd_gather over the grid extended below the axis (|a|^2 and A~_z even, A~_rho odd), no angular
+ * factor:  out[s][c] = sum_(i,k) S3(i - z_s/dz) S3(k + 1/2 - rho_s/dr) F_c(k, i).
+ *   problem  index of an m = 0 problem of the plan.
+ *   pond     device pointer to its 3 real planes [nr][nz] (|a|^2, A~_rho, A~_z as envelope_ponderomotive
+ *            writes them), the plan's real precision (double for FP64, float for FP32C); read only.
+ *   samples  device array of n x 4 doubles (z, x, y, unused), 8-byte aligned.
+ *   out      device array of n x 3 doubles, overwritten.
+ * FDETD_E_ARG for a Maxwell plan, a problem out of range or with m != 0, or misaligned pointers.
+ * Enqueue only. */
+FDETD_API int envelope_gather(fdetd_plan_t plan, int32_t problem, const void *pond, const double *samples, int64_t n,
+                              double *out);
+
 /* Absorbing layers of envelope problems (appendix on the scalar absorbing layer, which the envelope
  * solver of section 4.2 may use): from the next envelope_step on, every step of the problem is
  *     psi_a(t + dt) = exp(-sigma dt/4) T_N(dt H_a(chi~)) exp(-sigma dt/4) psi_a(t),   chi~ = chi + sigma^2,

@@ -23,6 +23,7 @@ PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
+           "envelope_gather",
            "fdetd_deposit_jz", "fdetd_deposit_rho",
            "fdetd_deposit_current", "fdetd_gather", "fdetd_gather_supersampled", "fdetd_query",
            "fdetd_export_state",
@@ -86,6 +87,7 @@ def _load():
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
     L.fdetd_gather_supersampled.argtypes = [vp, pp, vp, C.c_int64, vp, C.c_int32]
+    L.envelope_gather.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp]
     L.envelope_ponderomotive.argtypes = [vp, pp, pp]
     L.fdetd_deposit_current.argtypes = [vp, vp, C.c_int64, C.c_double, pp]
     L.envelope_absorber.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double]
@@ -164,6 +166,10 @@ def fdetd_gather(plan, psi_ptrs, samples_ptr, n: int, fields_ptr):
 
 def fdetd_gather_supersampled(plan, psi_ptrs, samples_ptr, n: int, fields_ptr, supersample: int):
     _check(lib.fdetd_gather_supersampled(plan, _ptrs(psi_ptrs), samples_ptr, n, fields_ptr, supersample), plan)
+
+
+def envelope_gather(plan, problem: int, pond_ptr, samples_ptr, n: int, out_ptr):
+    _check(lib.envelope_gather(plan, problem, pond_ptr, samples_ptr, n, out_ptr), plan)
 
 
 def envelope_absorber(plan, problem: int, lz: int, lr: int, sigma_max: float, power: float = 2.0):
@@ -345,6 +351,24 @@ class Plan:
             out = [torch.empty((3, p.nr, p.nz), dtype=self._rdtype(), device=x.device) for x, p in zip(a, self.problems)]
         op = [self._chk(x, (3, p.nr, p.nz), self._rdtype(), "out") for x, p in zip(out, self.problems)]
         envelope_ponderomotive(self._h, ap, op)
+        return out
+
+    def envelope_gather(self, problem: int, pond, samples, out=None):
+        """|a|^2, A~_rho, A~_z of problem `problem` (its [3, nr, nz] real ponderomotive planes, as
+        `ponderomotive` returns them) at the samples (float64 [n, 4] cuda tensor of z, x, y, w): float64
+        [n, 3] cuda tensor."""
+        import torch
+        if not (samples.is_cuda and samples.dtype == torch.float64 and samples.dim() == 2 and samples.shape[1] == 4
+                and samples.is_contiguous()):
+            raise ValueError("samples: contiguous float64 cuda tensor [n, 4]")
+        p = self.problems[problem]
+        pp = self._chk(pond, (3, p.nr, p.nz), self._rdtype(), "pond")
+        if out is None:
+            out = torch.empty((samples.shape[0], 3), dtype=torch.float64, device=samples.device)
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and tuple(out.shape) == (samples.shape[0], 3)):
+            raise ValueError("out: contiguous float64 cuda tensor [n, 3]")
+        envelope_gather(self._h, problem, pp, samples.data_ptr(), samples.shape[0], out.data_ptr())
         return out
 
     def query(self) -> dict:

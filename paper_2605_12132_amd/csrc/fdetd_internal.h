@@ -237,6 +237,18 @@ struct GatherArgs {
     const void *fine[kMaxGather];
 };
 hipError_t launch_gather(int prec, const GatherArgs &a, hipStream_t s);
+// Envelope ponderomotive planes (|a|^2, A~_rho on the staggered rows, A~_z on the staggered columns; real,
+// storage precision) at n samples: destaggered on the fly and interpolated, out n x 3 doubles.
+struct EnvGatherArgs {
+    int64_t n;
+    const double *samples;  // n x 4: z, x, y, (unused)
+    double *out;
+    const void *pond;       // 3 real planes [nr][nz]
+    int nz, nr, nd;
+    double dz, dr;
+    double s[kMaxND];       // half-shift weights s_j
+};
+hipError_t launch_envelope_gather(int prec, const EnvGatherArgs &a, hipStream_t s);
 
 // Ponderomotive field of an m = 0 envelope problem (section 4.3): 3 real planes |a|^2, A~_rho, A~_z.
 hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,

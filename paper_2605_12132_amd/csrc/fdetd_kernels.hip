@@ -1575,7 +1575,65 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
     }
 }
 
+// Ponderomotive fields at samples (section 4.3), one thread per sample: |a|^2 read on the primary grid,
+// A~_rho and A~_z destaggered at each node on the fly (S_rho^(+) from the staggered rows, odd, 0 on the
+// axis; S_z^(+) from the staggered columns, 0 outside the grid), then the cubic shapes over the grid
+// extended below the axis (|a|^2 and A~_z even, A~_rho odd), as k_gather does for m = 0.
+template <typename R>
+__global__ __launch_bounds__(256) void k_envelope_gather(EnvGatherArgs A)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= A.n) return;
+    const double z = A.samples[4 * q], x = A.samples[4 * q + 1], y = A.samples[4 * q + 2];
+    const double rho = sqrt(x * x + y * y);
+    const size_t plane = (size_t)A.nz * A.nr;
+    const R *I = (const R *)A.pond, *Ar = I + plane, *Az = I + 2 * plane;
+    const double zc = z / A.dz, rc = rho / A.dr - 0.5;
+    const int i0 = (int)floor(zc) - 1, k0 = (int)floor(rc) - 1;
+    auto arow = [&](int r, int i) -> double {  // A~_rho on staggered row r: 0 on the axis and from nr on
+        const int a = r < 0 ? -r : r;
+        if (r == 0 || a >= A.nr) return 0.0;
+        const double v = (double)Ar[(size_t)a * A.nz + i];
+        return r < 0 ? -v : v;
+    };
+    auto zcol = [&](int k, int c) -> double { return (c < 0 || c >= A.nz) ? 0.0 : (double)Az[(size_t)k * A.nz + c]; };
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const int k = k0 + a, kk = k < 0 ? -1 - k : k;
+        if (kk >= A.nr) continue;
+        const double wr = bspline3(k - rc), sg = k < 0 ? -1.0 : 1.0;  // row k at (k + 1/2) drho
+        if (wr == 0.0) continue;
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + b;
+            if (i < 0 || i >= A.nz) continue;
+            const double wz = bspline3(i - zc);
+            if (wz == 0.0) continue;
+            double vr = 0.0, vz = 0.0;
+            for (int j = 1; j <= A.nd; ++j) {
+                vr += A.s[j - 1] * (arow(kk + j, i) + arow(kk - j + 1, i));
+                vz += A.s[j - 1] * (zcol(kk, i + j) + zcol(kk, i - j + 1));
+            }
+            acc0 += wz * wr * (double)I[(size_t)kk * A.nz + i];
+            acc1 += wz * wr * (sg * vr);
+            acc2 += wz * wr * vz;
+        }
+    }
+    A.out[3 * q] = acc0;
+    A.out[3 * q + 1] = acc1;
+    A.out[3 * q + 2] = acc2;
+}
+
 }  // namespace
+
+hipError_t launch_envelope_gather(int prec, const EnvGatherArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (a.nd < 1 || a.nd > kMaxND) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    if (prec == P64) hipLaunchKernelGGL(k_envelope_gather<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_envelope_gather<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_ponderomotive(int prec, const ProbDesc *d, int nz, int nr, int nd, const void *a, void *out,
                                 hipStream_t s)

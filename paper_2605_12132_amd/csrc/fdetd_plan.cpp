@@ -1449,6 +1449,35 @@ int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, void *const 
     return FDETD_OK;
 }
 
+int envelope_gather(fdetd_plan_t plan, int32_t problem, const void *pond, const double *samples, int64_t n,
+                    double *out)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_gather: NULL plan");
+    if (plan->kind != FDETD_ENVELOPE) return fail(plan, FDETD_E_ARG, "envelope_gather: plan is not an envelope plan");
+    if (problem < 0 || problem >= (int)plan->probs.size())
+        return fail(plan, FDETD_E_ARG, "envelope_gather: problem %d out of range", problem);
+    const Prob &q = plan->probs[problem];
+    if (q.d.m != 0) return fail(plan, FDETD_E_ARG, "envelope_gather: problem %d has m = %d (needs m = 0)", problem, q.d.m);
+    const size_t eb = elem_bytes(plan->precision);
+    if (n < 0 || !aligned(pond, eb / 2) || (n > 0 && (!aligned(samples, 8) || !aligned(out, 8))))
+        return fail(plan, FDETD_E_ARG, "envelope_gather: bad arguments");
+    if (n == 0) return FDETD_OK;
+    EnvGatherArgs G;
+    std::memset(&G, 0, sizeof G);
+    G.n = n;
+    G.samples = samples;
+    G.out = out;
+    G.pond = pond;
+    G.nz = q.d.nz;
+    G.nr = q.d.nr;
+    G.nd = q.nd;
+    G.dz = q.d.dz;
+    G.dr = q.d.dr;
+    for (int j = 0; j < q.nd; ++j) G.s[j] = q.s[j];
+    HIPCHK(plan, launch_envelope_gather(prec_code(plan->precision), G, plan->stream));
+    return FDETD_OK;
+}
+
 int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max, double power)
 {
     if (!plan) return fail(nullptr, FDETD_E_ARG, "envelope_absorber: NULL plan");

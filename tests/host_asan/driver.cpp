@@ -24,6 +24,7 @@ hipError_t launch_deposit_rho(int, const DepositArgs &, hipStream_t) { return hi
 hipError_t launch_deposit_current(int, const DepositArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_absorb_damp(int, const DampArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_destagger(int, const DestaggerArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_envelope_gather(int, const EnvGatherArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ponderomotive(int, const ProbDesc *, int, int, int, const void *, void *, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_div(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_correct_apply(int, const CorrectArgs &, hipStream_t) { return hipErrorInvalidValue; }

@@ -125,3 +125,43 @@ def test_ponderomotive_field(precision):
     with pytest.raises(F.FdetdError):
         plan.ponderomotive([torch.zeros((20, 64), dtype=cd, device="cuda")])
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_envelope_gather(precision):
+    """The ponderomotive planes of two m = 0 problems (orders 8 and 16) at samples spread over each grid,
+    a fifth next to the axis and some past the z ends (envelope_gather, section 4.3), against the oracle
+    on the planes as the GPU holds them: FP64 to 1e-12 of the field scale, FP32C (float planes, FP64
+    sums) to 1e-12 as well; bad arguments are rejected."""
+    import math
+    import torch
+    import paper_2605_12132_amd as F
+    from helpers import dev
+    from oracle import Grid, envelope_gather
+    dz = I.LAMBDA0 / 5
+    w = I.Workload("pgather", 1, [300, 211], [60, 45], [0, 0], [8, 16], 4, dz, 0.2 * I.UM, 0.5 * dz, 1)
+    rng = np.random.default_rng(21)
+    a0 = [rng.uniform(-1, 1, (w.nr[p], w.nz[p])) + 1j * rng.uniform(-1, 1, (w.nr[p], w.nz[p])) for p in range(2)]
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    pond = plan.ponderomotive([dev(x, cd) for x in a0])
+    for p in range(2):
+        n = 4000
+        z = rng.uniform(-2 * w.dz, (w.nz[p] + 1) * w.dz, n)
+        r = np.sqrt(rng.uniform(0, (w.nr[p] + 1) ** 2, n)) * w.dr
+        r[: n // 5] = rng.uniform(0, 2 * w.dr, n // 5)
+        th = rng.uniform(-math.pi, math.pi, n)
+        s = np.stack([z, r * np.cos(th), r * np.sin(th), np.ones(n)], axis=1)
+        got = plan.envelope_gather(p, pond[p], dev(s, torch.float64)).cpu().numpy()
+        g = Grid(nz=w.nz[p], nr=w.nr[p], m=0, fd_order=w.fd_order[p], taylor_order=4, dz=w.dz, dr=w.dr, dt=w.dt)
+        want = envelope_gather(g, pond[p].cpu().numpy().astype(np.float64), s)
+        for c in range(3):
+            err = np.max(np.abs(got[:, c] - want[:, c])) / np.max(np.abs(want[:, c]))
+            log(f"envelope gather problem {p} component {c} precision {precision}: {err:.2e}")
+            assert err < 1e-12
+    empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    assert plan.envelope_gather(0, pond[0], empty).shape == (0, 3)
+    with pytest.raises(F.FdetdError):
+        F.envelope_gather(plan._h, 2, pond[0].data_ptr(), empty.data_ptr(), 0, 0)  # problem out of range
+    torch.cuda.synchronize()
+    plan.close()
