@@ -302,7 +302,8 @@ def envelope_pass(steps, layer=32):
     256 MB Infinity Cache, so the rate is reported without an HBM fraction.  Each precision is also run
     with absorbing layers (`layer` cells at both z ends and at the outer rho edge, sigma_max half the
     largest the plan's stability bound admits, quadratic grading).  The ponderomotive field of the final
-    state (envelope_ponderomotive) is timed apart."""
+    state (envelope_ponderomotive) is timed apart, and so are those planes at 10^6 samples spread over the
+    pulse region (envelope_gather)."""
     import torch
     import paper_2605_12132_amd as F
     import paper_2605_12132_amd.inputs as I
@@ -344,19 +345,38 @@ def envelope_pass(steps, layer=32):
             ev1.record(stream)
             torch.cuda.synchronize()
             pond_us = ev0.elapsed_time(ev1) / 20 * 1e3
+            # the same planes at 10^6 samples spread over the pulse (envelope_gather), 5 calls
+            n = 10 ** 6
+            gs = torch.Generator(device="cuda")
+            gs.manual_seed(w.seed)
+            smp = torch.rand((n, 4), generator=gs, device="cuda", dtype=torch.float64)
+            smp[:, 0] = (0.2 + 0.6 * smp[:, 0]) * w.nz[0] * w.dz
+            smp[:, 1] = (smp[:, 1] - 0.5) * w.nr[0] * w.dr
+            smp[:, 2] = (smp[:, 2] - 0.5) * w.nr[0] * w.dr
+            smp = smp[torch.argsort(smp[:, 0])].contiguous()
+            gout = plan.envelope_gather(0, pond[0], smp)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                plan.envelope_gather(0, pond[0], smp, gout)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            egather_us = ev0.elapsed_time(ev1) / 5 * 1e3
             plan.close()
-        return ms, smax, a, at, pond_us
+        return ms, smax, a, at, (pond_us, egather_us)
 
     for tag, prec, cd, rd in (("fp64", F.FP64, torch.complex128, torch.float64),
                               ("fp32c", F.FP32C, torch.complex64, torch.float32)):
-        ms, _, a, at, pond_us = run(prec, cd, rd, False)
+        ms, _, a, at, (pond_us, egather_us) = run(prec, cd, rd, False)
         # ponderomotive algorithmic bytes per cell: the complex envelope read once, three real planes written
         pond_bytes = cells * (2 + 3) * (8 if prec == F.FP64 else 4)
         out[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps,
-                        ponderomotive_us=round(pond_us, 2), ponderomotive_GBs=round(pond_bytes / (pond_us * 1e3), 1))
+                        ponderomotive_us=round(pond_us, 2), ponderomotive_GBs=round(pond_bytes / (pond_us * 1e3), 1),
+                        envelope_gather_1M_samples_us=round(egather_us, 1))
         res[tag] = (a.cpu().numpy().astype(np.complex128), at.cpu().numpy().astype(np.complex128))
         log(f"envelope {tag}: {ms / steps:.4f} ms/step, {out[tag]['value']:.4g} cell-updates/s; ponderomotive "
-            f"field {pond_us:.1f} us ({out[tag]['ponderomotive_GBs']:.0f} GB/s algorithmic)")
+            f"field {pond_us:.1f} us ({out[tag]['ponderomotive_GBs']:.0f} GB/s algorithmic), at 10^6 samples "
+            f"{egather_us:.1f} us")
         ms, smax, _, _, _ = run(prec, cd, rd, True)
         out[tag]["absorbing"] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, lz=layer, lr=layer,
                                      sigma_max=round(smax, 4))

@@ -269,7 +269,7 @@ FDETD_API int envelope_ponderomotive(fdetd_plan_t plan, const void *const *a, vo
  *   samples  device array of n x 4 doubles (z, x, y, unused), 8-byte aligned.
  *   out      device array of n x 3 doubles, overwritten.
  * FDETD_E_ARG for a Maxwell plan, a problem out of range or with m != 0, or misaligned pointers.
- * Enqueue only. */
+ * Uses the problem's stage buffer as scratch (ordered on the plan's stream).  Enqueue only. */
 FDETD_API int envelope_gather(fdetd_plan_t plan, int32_t problem, const void *pond, const double *samples, int64_t n,
                               double *out);
 

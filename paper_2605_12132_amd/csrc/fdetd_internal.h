@@ -244,6 +244,7 @@ struct EnvGatherArgs {
     const double *samples;  // n x 4: z, x, y, (unused)
     double *out;
     const void *pond;       // 3 real planes [nr][nz]
+    double *prim;           // scratch: A~_rho and A~_z on the primary grid (2 planes of doubles)
     int nz, nr, nd;
     double dz, dr;
     double s[kMaxND];       // half-shift weights s_j

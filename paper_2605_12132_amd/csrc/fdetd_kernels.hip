@@ -1575,10 +1575,34 @@ __global__ __launch_bounds__(GATHER_BLOCK) __attribute__((amdgpu_waves_per_eu(4)
     }
 }
 
-// Ponderomotive fields at samples (section 4.3), one thread per sample: |a|^2 read on the primary grid,
-// A~_rho and A~_z destaggered at each node on the fly (S_rho^(+) from the staggered rows, odd, 0 on the
-// axis; S_z^(+) from the staggered columns, 0 outside the grid), then the cubic shapes over the grid
-// extended below the axis (|a|^2 and A~_z even, A~_rho odd), as k_gather does for m = 0.
+// Ponderomotive fields at samples (section 4.3).  First A~_rho and A~_z are brought to the primary grid,
+// one thread per cell (S_rho^(+) from the staggered rows, odd, 0 on the axis; S_z^(+) from the staggered
+// columns, 0 outside the grid; FP64), then one thread per sample interpolates |a|^2 and the two primary
+// planes with the cubic shapes over the grid extended below the axis (|a|^2 and A~_z even, A~_rho odd),
+// as k_gather does for m = 0.
+template <typename R>
+__global__ __launch_bounds__(256) void k_envelope_destagger(EnvGatherArgs A)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (i >= A.nz) return;
+    const size_t plane = (size_t)A.nz * A.nr;
+    const R *Ar = (const R *)A.pond + plane, *Az = (const R *)A.pond + 2 * plane;
+    auto arow = [&](int r) -> double {  // A~_rho on staggered row r: 0 on the axis and from nr on
+        const int a = r < 0 ? -r : r;
+        if (r == 0 || a >= A.nr) return 0.0;
+        const double v = (double)Ar[(size_t)a * A.nz + i];
+        return r < 0 ? -v : v;
+    };
+    auto zcol = [&](int c) -> double { return (c < 0 || c >= A.nz) ? 0.0 : (double)Az[(size_t)k * A.nz + c]; };
+    double vr = 0.0, vz = 0.0;
+    for (int j = 1; j <= A.nd; ++j) {
+        vr += A.s[j - 1] * (arow(k + j) + arow(k - j + 1));
+        vz += A.s[j - 1] * (zcol(i + j) + zcol(i - j + 1));
+    }
+    A.prim[(size_t)k * A.nz + i] = vr;
+    A.prim[plane + (size_t)k * A.nz + i] = vz;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_envelope_gather(EnvGatherArgs A)
 {
@@ -1587,16 +1611,10 @@ __global__ __launch_bounds__(256) void k_envelope_gather(EnvGatherArgs A)
     const double z = A.samples[4 * q], x = A.samples[4 * q + 1], y = A.samples[4 * q + 2];
     const double rho = sqrt(x * x + y * y);
     const size_t plane = (size_t)A.nz * A.nr;
-    const R *I = (const R *)A.pond, *Ar = I + plane, *Az = I + 2 * plane;
+    const R *I = (const R *)A.pond;
+    const double *Pr = A.prim, *Pz = A.prim + plane;
     const double zc = z / A.dz, rc = rho / A.dr - 0.5;
     const int i0 = (int)floor(zc) - 1, k0 = (int)floor(rc) - 1;
-    auto arow = [&](int r, int i) -> double {  // A~_rho on staggered row r: 0 on the axis and from nr on
-        const int a = r < 0 ? -r : r;
-        if (r == 0 || a >= A.nr) return 0.0;
-        const double v = (double)Ar[(size_t)a * A.nz + i];
-        return r < 0 ? -v : v;
-    };
-    auto zcol = [&](int k, int c) -> double { return (c < 0 || c >= A.nz) ? 0.0 : (double)Az[(size_t)k * A.nz + c]; };
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     for (int a = 0; a < 4; ++a) {
         const int k = k0 + a, kk = k < 0 ? -1 - k : k;
@@ -1608,14 +1626,10 @@ __global__ __launch_bounds__(256) void k_envelope_gather(EnvGatherArgs A)
             if (i < 0 || i >= A.nz) continue;
             const double wz = bspline3(i - zc);
             if (wz == 0.0) continue;
-            double vr = 0.0, vz = 0.0;
-            for (int j = 1; j <= A.nd; ++j) {
-                vr += A.s[j - 1] * (arow(kk + j, i) + arow(kk - j + 1, i));
-                vz += A.s[j - 1] * (zcol(kk, i + j) + zcol(kk, i - j + 1));
-            }
-            acc0 += wz * wr * (double)I[(size_t)kk * A.nz + i];
-            acc1 += wz * wr * (sg * vr);
-            acc2 += wz * wr * vz;
+            const size_t o = (size_t)kk * A.nz + i;
+            acc0 += wz * wr * (double)I[o];
+            acc1 += wz * wr * (sg * Pr[o]);
+            acc2 += wz * wr * Pz[o];
         }
     }
     A.out[3 * q] = acc0;
@@ -1628,10 +1642,15 @@ __global__ __launch_bounds__(256) void k_envelope_gather(EnvGatherArgs A)
 hipError_t launch_envelope_gather(int prec, const EnvGatherArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    if (a.nd < 1 || a.nd > kMaxND) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.n + 255) / 256));
-    if (prec == P64) hipLaunchKernelGGL(k_envelope_gather<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_envelope_gather<float>, grid, dim3(256), 0, s, a);
+    if (a.nd < 1 || a.nd > kMaxND || !a.prim) return hipErrorInvalidValue;
+    const dim3 cells((unsigned)((a.nz + 255) / 256), (unsigned)a.nr), grid((unsigned)((a.n + 255) / 256));
+    if (prec == P64) {
+        hipLaunchKernelGGL(k_envelope_destagger<double>, cells, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_envelope_gather<double>, grid, dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_envelope_destagger<float>, cells, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_envelope_gather<float>, grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -1468,6 +1468,7 @@ int envelope_gather(fdetd_plan_t plan, int32_t problem, const void *pond, const 
     G.samples = samples;
     G.out = out;
     G.pond = pond;
+    G.prim = (double *)q.buf[0];  // 2 planes of doubles fit the stage vector (a, a~) in either precision
     G.nz = q.d.nz;
     G.nr = q.d.nr;
     G.nd = q.nd;
