@@ -80,6 +80,7 @@ def test_entry_points_reject_a_null_plan():
         lambda: F.fdetd_deposit_current(None, 0, 0, 0.5, [0]),
         lambda: F.envelope_ponderomotive(None, [0], [0]),
         lambda: F.envelope_absorber(None, -1, 4, 4, 1.0, 2.0),
+        lambda: F.envelope_gather(None, 0, 0, 0, 0, 0),
     ]
     for call in calls:
         with pytest.raises(F.FdetdError) as e:
