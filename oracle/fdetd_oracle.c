@@ -990,8 +990,8 @@ int oracle_deposit_jz(const oracle_problem *P, const double *samples, long n, do
  * with S(z) = S3(i - z/dz)/dz, F_+- the integrated z shape of z+- (as for oracle_deposit_jz), R_A / R_S the
  * radial shape folded with the m_A (polar components) / m_S (z component, densities) parity, A the angular
  * shape; v_rho = (x v_x + y v_y)/rho, v_theta = (x v_y - y v_x)/rho at the sample (0 on the axis).  A sample
- * whose z shapes at z+- reach past a z end, or that moves more than 3 cells along z in a step, is not
- * deposited. */
+ * whose z shapes at z+- reach past a z end is not deposited.  The integrated shape of section 3.6 spans
+ * every node between the two positions, however far apart they are. */
 int oracle_deposit_current(const oracle_problem *P, const double *samples, long n, double eps, double complex *j,
                            double complex *rho_xy)
 {
@@ -1005,7 +1005,7 @@ int oracle_deposit_current(const oracle_problem *P, const double *samples, long 
         const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5], vz = q[6];
         const double h = 0.5 * P->dt;
         const double zp = (z + h * vz) / P->dz, zm = (z - h * vz) / P->dz;
-        if (!z_inside(P, zp) || !z_inside(P, zm) || fabs(zp - zm) > 3.0) continue;
+        if (!z_inside(P, zp) || !z_inside(P, zm)) continue;
         const double xp = x + h * vx, yp = y + h * vy, xm = x - h * vx, ym = y - h * vy;
         const double rp = sqrt(xp * xp + yp * yp), rm = sqrt(xm * xm + ym * ym), r0 = sqrt(x * x + y * y);
         const cplx ap = angular_shape(P->m, atan2(yp, xp)), am = angular_shape(P->m, atan2(ym, xm));

@@ -100,3 +100,33 @@ def test_uniform_drift_next_to_axis():
     for g in (g0, g2):
         j, _ = oracle.deposit_current(g, s)
         assert np.max(np.abs(j[:2, rows, i])) < 1e-3 * v
+
+
+def test_fast_samples_keep_the_whole_integrated_shape():
+    """Samples that move 3 to 9 cells along z in one step (large dt or |v| > c): the integrated shape of
+    section 3.6 spans every node between the two positions, so the continuity equation still holds exactly
+    and the z current integrates to q w v_z times the (radial, angular) shape, i.e. the charge moved per
+    unit time."""
+    rng = np.random.default_rng(5)
+    for m in (0, 1, 2):
+        g = oracle.Grid(nz=60, nr=16, m=m, fd_order=8, taylor_order=4, dz=0.3, dr=0.4, dt=0.15)
+        s = moving(rng, 200, g)
+        s[:, 0] = rng.uniform(12 * g.dz, (g.nz - 13) * g.dz, s.shape[0])
+        s[:, 6] = rng.choice([-1.0, 1.0], s.shape[0]) * rng.uniform(6.0, 18.0, s.shape[0])  # 3 .. 9 cells
+        assert np.min(np.abs(s[:, 6])) * g.dt / g.dz > 3.0
+        j, rxy = oracle.deposit_current(g, s)
+        h = 0.5 * g.dt
+        plus, minus = s[:, :4].copy(), s[:, :4].copy()
+        plus[:, :3] += h * s[:, [6, 4, 5]]
+        minus[:, :3] -= h * s[:, [6, 4, 5]]
+        rp, rm = oracle.deposit_rho(g, plus), oracle.deposit_rho(g, minus)
+        dzj = np.zeros_like(j[2])
+        dzj[:, :-1] = (j[2][:, 1:] - j[2][:, :-1]) / g.dz
+        res = (rp - rm) / g.dt + dzj - rxy
+        assert np.max(np.abs(res[:, 2:g.nz - 3])) < 1e-12 * np.max(np.abs(rp - rm) / g.dt), m
+        # one sample: sum_i J_z dz = q w v_z * (mean of the two end-position shapes) on every row
+        one = s[:1].copy()
+        one[0, 4:6] = 0.0
+        j1, _ = oracle.deposit_current(g, one)
+        shape = oracle.deposit_rho(g, one[:, :4]).sum(axis=1) * g.dz  # q w R_k A_m
+        assert np.max(np.abs(j1[2].sum(axis=1) * g.dz - one[0, 6] * shape)) < 1e-12 * np.max(np.abs(one[0, 6] * shape))
