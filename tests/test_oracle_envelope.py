@@ -127,24 +127,33 @@ def test_printed_real_form_propagates_the_conjugate_envelope():
 
 
 @pytest.mark.slow
-def test_envelope_group_velocity_in_plasma():
-    """Gaussian envelope (k0 = 1, w0 = 12) in chi = n0/n_c = 0.02: the centroid of |a~ - i k0 a|^2
-    moves at (c - v_g)/c = n0/(2 n_c) + (1/(k0 w0))^2 (section 5.2 formula; paraxial, not exact)."""
-    k0, chi0, w0 = 1.0, 0.02, 12.0
-    g = oracle.Grid(nz=420, nr=48, m=0, fd_order=8, taylor_order=4, dz=0.5, dr=1.0, dt=0.25, k0=k0)
+def test_envelope_group_velocity_in_plasma_paper_case():
+    """The plasma propagation test of section 5.2 with the paper's parameters: lambda = 0.8 um, n0 = 1e-3 n_c
+    (chi = 1e-3), w0 = 16 um, field envelope length c tau = 10 um, 8th-order differences, 4th-order
+    exponential, dt = dz / 2 with dz = lambda / 5.  The centroid of |a~ - i k0 a|^2, from its time derivative
+    between t1 = T/10 and T, moves at (c - v_g)/c = n0/(2 n_c) + (lambda/(2 pi w0))^2 = 5.634e-4 (eq.
+    test_am_plasma_vg), which the paper's envelope runs reproduce.  The formula is paraxial, not exact; its
+    leading corrections here (finite bandwidth, O(chi^2)) are below 0.1 %.  Band: 2 %."""
+    um = 2 * math.pi / 0.8
+    k0, chi0, w0, L = 1.0, 1e-3, 16 * um, 10 * um
+    dz, dr, T = 2 * math.pi / 5, 5.0, 600.0
+    nr = int(math.ceil(2.6 * w0 / dr))                  # the beam's intensity is e^-13 at the outer edge
+    zc = 3.2 * L
+    nz = int(math.ceil((6.4 * L + T) / dz))
+    g = oracle.Grid(nz=nz, nr=nr, m=0, fd_order=8, taylor_order=4, dz=dz, dr=dr, dt=0.5 * dz, k0=k0)
     z = np.arange(g.nz) * g.dz
     rho = (np.arange(g.nr) + 0.5) * g.dr
-    zc, L = 50.0, 12.0
     a = np.exp(-(rho[:, None] / w0) ** 2 - ((z[None, :] - zc) / L) ** 2).astype(complex)
     # forward pulse: a~ = d a/dt ~ -v dz a - i (sqrt(k0^2 + chi) - k0) a
     om = math.sqrt(k0 ** 2 + chi0)
-    dz_a = np.gradient(a, g.dz, axis=1)
-    at = -(k0 / om) * dz_a - 1j * (om - k0) * a
+    at = -(k0 / om) * np.gradient(a, g.dz, axis=1) - 1j * (om - k0) * a
     chi = np.full((g.nr, g.nz), chi0)
-    e0, c0 = oracle.envelope_energy(g, a, at)
-    nsteps = 400
-    a1, t1 = oracle.envelope_step(g, a, at, chi, nsteps)
-    e1, c1 = oracle.envelope_energy(g, a1, t1)
-    v = (c1 - c0) / (nsteps * g.dt)
-    want = chi0 / (2 * k0 ** 2) + (1 / (k0 * w0)) ** 2
-    assert abs((1 - v) - want) < 0.06 * want, (1 - v, want)
+    n1, n2 = int(round(0.1 * T / g.dt)), int(round(T / g.dt))
+    a1, t1 = oracle.envelope_step(g, a, at, chi, n1)
+    _, c1 = oracle.envelope_energy(g, a1, t1)
+    a2, t2 = oracle.envelope_step(g, a1, t1, chi, n2 - n1)
+    _, c2 = oracle.envelope_energy(g, a2, t2)
+    delay = 1 - (c2 - c1) / ((n2 - n1) * g.dt)
+    want = chi0 / 2 + (0.8 / (2 * math.pi * 16)) ** 2
+    assert abs(want - 5.634e-4) < 1e-7
+    assert abs(delay / want - 1) < 0.02, (delay, want)

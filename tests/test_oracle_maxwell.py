@@ -10,6 +10,10 @@
 * On tiny grids the step equals the dense matrix exponential within the Taylor remainder bound, and the
   midpoint source term matches the exact (Van Loan) integral up to the known O(dt^3) quadrature error.
 * The stored rho = 0 slots are never read; the source-free step conserves the field energy.
+* Gaussian-beam vacuum propagation (section 5.1): the energy centroid of an m = 1 pulse falls behind the
+  light front at (c - v_g)/c = (lambda / (2 pi w0))^2.
+* The stability bound: with dt above X_N / rho(H) the step's matrix has a norm above 1 and the field grows;
+  below it the step stays bounded.
 """
 import math
 
@@ -290,3 +294,53 @@ def test_cropped_window_equals_full_grid(m, order, steps):
     g2 = oracle.Grid(nz=40, nr=150, m=m, fd_order=order, taylor_order=4, dz=dz, dr=2 * dz, dt=0.5 * dz)
     small = oracle.step(g2, np.ascontiguousarray(psi0[:, :, 190:230]), np.ascontiguousarray(J[..., 190:230]), steps)
     assert not np.array_equal(small[:, :20, 14:26], full[:, :20, 204:216])
+
+
+@pytest.mark.slow
+def test_gaussian_beam_centroid_delay_in_vacuum():
+    """Section 5.1: the pulse centroid of a Gaussian beam moves at (c - v_g)/c = (lambda/(2 pi w0))^2 (eq.
+    test_am_vacuum_vg), 6.33e-5 for the paper's w0 = 16 um.  Reduced case: w0 = 4 lambda (1.58e-3), field
+    envelope length 3 lambda, focus at the initial pulse centre, 16th-order differences, Taylor order 8,
+    dt = dz/2 with dz = lambda/16, radial box 3 w0.  The centroid of |E|^2 + |B|^2 over 100 c/omega_0 of
+    propagation.  The formula is paraxial; for this beam its leading corrections, the spread of 1/k^2 over
+    the pulse spectrum (+3/(k0 L)^2 = +0.8 %) and the next term of the angular average (-3/(k0 w0)^2 of the
+    formula, -0.5 %), are applied to the expected value.  Band: 2 % of that, 3 % of the bare formula."""
+    from paper_2605_12132_amd.inputs import gaussian_pulse
+    lam = 2 * math.pi
+    w0, L, T = 4 * lam, 3 * lam, 100.0
+    dz, dr = lam / 16, lam / 4
+    nr = int(math.ceil(3 * w0 / dr))
+    zc = 3.2 * L
+    nz = int(math.ceil((6.4 * L + T) / dz))
+    g = oracle.Grid(nz=nz, nr=nr, m=1, fd_order=16, taylor_order=8, dz=dz, dr=dr, dt=0.5 * dz)
+    psi = gaussian_pulse(nz, nr, 1, dz, dr, w0, L, zc, 1.0)
+    W0, c0 = oracle.energy(g, psi)
+    steps = int(round(T / g.dt))
+    W1, c1 = oracle.energy(g, oracle.step(g, psi, None, steps))
+    delay = 1 - (c1 - c0) / (steps * g.dt)
+    formula = (1 / w0) ** 2
+    assert abs(formula - (lam / (2 * math.pi * w0)) ** 2) < 1e-18
+    expected = formula * (1 + 3 / L ** 2) - 3 / w0 ** 4
+    assert abs(delay / expected - 1) < 0.02, (delay, expected)
+    assert abs(delay / formula - 1) < 0.03, (delay, formula)
+    assert abs(W1 / W0 - 1) < 1e-3
+
+
+def test_unstable_dt_grows_and_stable_dt_does_not():
+    """Tiny grid, m = 1, order 8, Taylor order 8: rho(H) from the dense eigenvalues of oracle.apply_H.  The
+    step's matrix T_8(dt H) has spectral radius above 1 for dt = 1.1 X_8 / rho(H), and a random state grows
+    by orders of magnitude within 400 steps; at dt = 0.9 X_8 / rho(H) it stays within a few times its size
+    (X_8 = 3.3951, the largest x with |T_8(i y)| <= 1 for |y| <= x)."""
+    g = oracle.Grid(nz=14, nr=7, m=1, fd_order=8, taylor_order=8, dz=0.3, dr=0.6, dt=0.0)
+    lam = np.linalg.eigvals(dense_H(g))
+    rho = np.max(np.abs(lam))
+    x8 = 3.3951
+    rng = np.random.default_rng(77)
+    psi = rng.standard_normal((6, g.nr, g.nz)) + 1j * rng.standard_normal((6, g.nr, g.nz))
+    n0 = np.linalg.norm(psi)
+    g.dt = 1.1 * x8 / rho
+    grow = np.linalg.norm(oracle.step(g, psi, None, 400)) / n0
+    g.dt = 0.9 * x8 / rho
+    keep = np.linalg.norm(oracle.step(g, psi, None, 400)) / n0
+    assert grow > 1e3, grow
+    assert keep < 10, keep
