@@ -167,9 +167,10 @@ FDETD_API int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_ti
  * into m = 0; normalised with the quadrature weights h_0 = 7/8, h_1 = 73/72, h_k = 1) and A_m the
  * deposition form of the angular shape of section 3.2 (1/(2 pi) for m = 0, e^(-i m theta)/pi otherwise,
  * for the mode convention of fdetd_step).  Samples move along z only; a sample whose shape reaches past
- * a z end of a grid is not deposited into it.
+ * a z end of a grid is not deposited into it.  F_- - F_+ is non-zero on every node between the two
+ * positions, however far apart (a step of more than 3 cells takes a slower path with global atomics).
  *   samples  device array of n x 4 doubles: z, x, y, charge * weight (normalised units), 8-byte aligned.
- *   vz       velocity along z, |vz| dt <= 3 dz for every problem; eps in [0, 1] (0.5 in the paper).
+ *   vz       velocity along z (finite); eps in [0, 1] (0.5 in the paper).
  *   j_half   n_probs device pointers as for fdetd_step (3 planes each, the plan's precision).
  * Enqueue only.  The adds are atomic, so the order of the summation, and the last bits, vary between runs.
  * Blocks of 1024 consecutive samples whose shapes touch at most 4096 cells of a grid sum their adds in an
@@ -191,7 +192,8 @@ FDETD_API int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t
  * v_rho = (x v_x + y v_y)/rho and v_theta = (x v_y - y v_x)/rho at the sample, 0 on the axis.  With
  * these, the densities at the end
  * positions satisfy (rho+ - rho-)/dt + D_z^(+) J_z - rho_xy = 0.  A sample whose z shapes reach past a z
- * end, or that moves more than 3 cells along z in dt, is not deposited.
+ * end is not deposited.  A sample moving more than 3 cells along z in dt (its integrated shape spans
+ * more than 8 nodes) is deposited in full with global atomics, outside the LDS tiles.
  *   samples  device array of n x 8 doubles: z, x, y, q w, v_x, v_y, v_z, unused; 8-byte aligned.
  *   eps      in [0, 1].
  *   j_half   n_probs device pointers to current blocks as for fdetd_step (3 planes, 4 with

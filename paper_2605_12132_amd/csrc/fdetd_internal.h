@@ -269,6 +269,9 @@ hipError_t launch_absorb_damp(int prec, const DampArgs &a, hipStream_t s);
 // Per-block partial sums of |x|^2 over n complex values (double2 or float2); nblocks written to partial.
 hipError_t launch_norm2(int prec, const void *x, size_t n, double *partial, int nblocks, hipStream_t s);
 hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s);
+// E part of w_N = psi + beta_in Jbar of every problem of a batch (a.psi, a.aux = the step's currents,
+// a.beta_in) into the E planes of each problem's buf[1]; max_cells: the largest problem's nz * nr.
+hipError_t launch_form_wn(int prec, const BatchArgs &a, size_t max_cells, hipStream_t s);
 // Device-to-device copy of a multiple of 8 bytes by kernel (graph-capture friendly).
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 

@@ -372,6 +372,32 @@ __global__ __launch_bounds__(256) void k_copy8(const uint2 *src, uint2 *dst, siz
     for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) dst[q] = src[q];
 }
 
+// E part of w_N = psi + beta_in Jbar (the argument of the highest power of H in the Horner form of the
+// midpoint solution of section 2.1) for every problem of a batch, into the E planes of the problem's
+// second stage buffer: the input of the B half of a step's first Horner stage.  Jbar_rho is the staged
+// plane, J_theta the corrected one when the plan corrects the current, J_z the caller's.  FP64 arithmetic,
+// one rounding to the storage precision.  Each block strides over the cells of every problem in turn.
+template <typename V>
+__global__ __launch_bounds__(256) void k_form_wn(BatchArgs A)
+{
+    using R = typename storage<V>::R;
+    for (int p = 0; p < A.nprob; ++p) {
+        const ProbDesc &D = A.probs[p];
+        const size_t n = D.plane;
+        const V *psi = (const V *)A.psi[p];
+        const V *jc = (const V *)A.aux[p];
+        const V *src[3] = {(const V *)D.jbar, D.jth ? (const V *)D.jth : jc + n, jc + 2 * n};
+        V *w = (V *)D.buf[1];
+        for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const V x = psi[c * n + q], j = src[c][q];
+                w[c * n + q] = V{(R)((double)x.x + A.beta_in * (double)j.x), (R)((double)x.y + A.beta_in * (double)j.y)};
+            }
+        }
+    }
+}
+
 // compile-time dispatch over the stencil half width N_D = 1..16
 template <template <typename, int> class L, typename V, typename Args>
 hipError_t dispatch_nd(int nd, const Args &a, dim3 grid, dim3 block, hipStream_t s)
@@ -531,6 +557,41 @@ __device__ __forceinline__ void block_minmax(int v[4], int *red)
     __syncthreads();
 }
 
+// J_z (plane jz) and, when rxy is not null, the planar density differential of one sample whose
+// integrated z shape spans more than 8 nodes (it moves more than 3 cells in a step): the nodes lo .. hi
+// one by one, F_-+ summed on the way, every add a global atomic.  The radial and angular factors of the
+// two half-step positions are Sp, Sm (the same shape twice for a sample moving along z only), averaged
+// for J_z and differenced for rho_xy, as in the narrow path.
+template <typename R>
+__device__ void deposit_z_wide(R *jz, R *rxy, const ProbDesc &D, const SampleShape &Sp, const SampleShape &Sm,
+                               double qw, double zp, double zm, int lo, int hi, double inv_dt, double inv_dz)
+{
+    const int k0 = min(Sp.k0, Sm.k0), k1 = max(Sp.k1, Sm.k1);
+    double Fp = 0.0, Fm = 0.0;
+    for (int i = lo; i <= hi; ++i) {
+        const double dF = (Fm - Fp) * inv_dt;
+        const double bp = bspline3(i - zp), bm = bspline3(i - zm);
+        Fp += bp;
+        Fm += bm;
+        const double sz = 0.5 * (bp + bm) * inv_dz;
+        if (dF == 0.0 && (rxy == nullptr || sz == 0.0)) continue;
+        for (int k = k0; k <= k1; ++k) {
+            const int jp = k - Sp.kc + 3, jm = k - Sm.kc + 3;
+            const double wp = (jp >= 0 && jp < 7) ? Sp.w[jp] : 0.0, wm = (jm >= 0 && jm < 7) ? Sm.w[jm] : 0.0;
+            if (wp == 0.0 && wm == 0.0) continue;
+            const size_t o = 2 * ((size_t)k * D.nz + i);
+            if (dF != 0.0) {
+                atomicAdd(jz + o, (R)(qw * dF * 0.5 * (wp * Sp.ar + wm * Sm.ar)));
+                atomicAdd(jz + o + 1, (R)(qw * dF * 0.5 * (wp * Sp.ai + wm * Sm.ai)));
+            }
+            if (rxy != nullptr && sz != 0.0) {
+                atomicAdd(rxy + o, (R)(qw * sz * (wp * Sp.ar - wm * Sm.ar) * inv_dt));
+                atomicAdd(rxy + o + 1, (R)(qw * sz * (wp * Sp.ai - wm * Sm.ai) * inv_dt));
+            }
+        }
+    }
+}
+
 // J_z of the samples of a block (DEP_PER_THREAD per thread, consecutive).  For each problem the block
 // forms the footprint of its samples (the nodes and rows their shapes touch); when it fits an LDS tile of
 // DEP_TILE cells -- samples given in position order, as PIC codes keep them, make the footprint of a block
@@ -561,16 +622,21 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         const ProbDesc &D = A.probs[p];
         // footprints: nodes lo .. hi, rows kc - 3 .. kc + 3 (clipped)
         int lo[DEP_PER_THREAD], hi[DEP_PER_THREAD];
+        bool wide[DEP_PER_THREAD];
         int fp[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};  // zmin, zmax, kmin, kmax
 #pragma unroll
         for (int u = 0; u < DEP_PER_THREAD; ++u) {
             const double zp = (sm[u].z + 0.5 * A.vz * D.dt) / D.dz, zm = (sm[u].z - 0.5 * A.vz * D.dt) / D.dz;
             lo[u] = (int)floor(fmin(zp, zm)) - 1;
             hi[u] = (int)floor(fmax(zp, zm)) + 2;
-            if (!sm[u].ok || !z_on_grid(D, zp) || !z_on_grid(D, zm) || hi[u] - lo[u] + 1 > 8) {
+            wide[u] = false;
+            if (!sm[u].ok || !z_on_grid(D, zp) || !z_on_grid(D, zm)) {
                 hi[u] = lo[u] - 1;  // nothing to deposit
                 continue;
             }
+            // more than 8 nodes: deposited by deposit_z_wide, outside the block's tile
+            wide[u] = hi[u] - lo[u] + 1 > 8;
+            if (wide[u]) continue;
             const int kc = (int)floor(sm[u].rho / D.dr);
             fp[0] = min(fp[0], lo[u]);
             fp[1] = max(fp[1], hi[u]);
@@ -578,9 +644,9 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
             fp[3] = max(fp[3], min(kc + 3, D.nr - 1));
         }
         block_minmax(fp, red);
-        if (fp[1] < fp[0]) continue;  // no sample of the block is deposited into this problem
-        const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
-        const bool use_tile = (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
+        // fp covers the narrow samples only; without any the tile is empty (wide samples add directly)
+        const int tz = fp[1] >= fp[0] ? fp[1] - fp[0] + 1 : 0, tr = fp[1] >= fp[0] ? fp[3] - fp[2] + 1 : 0;
+        const bool use_tile = tz > 0 && (int64_t)tz * tr <= DEP_TILE;  // uniform across the block
         R *jz = (R *)A.j[p] + 2 * 2 * D.plane;               // plane 2, interleaved complex
         const double inv_dt = 1.0 / D.dt, par_s = fold_mS(D.m);
         if (use_tile) {
@@ -591,6 +657,11 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         for (int u = 0; u < DEP_PER_THREAD; ++u) {
             if (hi[u] < lo[u]) continue;
             const double zp = (sm[u].z + 0.5 * A.vz * D.dt) / D.dz, zm = (sm[u].z - 0.5 * A.vz * D.dt) / D.dz;
+            if (wide[u]) {
+                const SampleShape S = sample_shape(D, sm[u].rho, sm[u].x, sm[u].y, A.eps, par_s);
+                deposit_z_wide<R>(jz, nullptr, D, S, S, sm[u].qw, zp, zm, lo[u], hi[u], inv_dt, 1.0 / D.dz);
+                continue;
+            }
             double dF[8];
             double Fp = 0.0, Fm = 0.0;
             for (int v = 0; v <= hi[u] - lo[u]; ++v) {
@@ -638,10 +709,11 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
 //   J_rho, J_theta += q w v_rho|theta S(z_p) R_A(rho_p) A(theta_p)          (planes 0, 1)
 //   J_z(i - 1/2)   += q w dF(i) (R_S(rho+) A(theta+) + R_S(rho-) A(theta-)) / 2  (plane 2)
 //   rho_xy         += q w (S(z+) + S(z-)) / 2 (R_S(rho+) A(theta+) - R_S(rho-) A(theta-)) / dt  (plane 3)
-// R_A / R_S: radial shape folded with fold_mA / fold_mS.  Samples whose z shapes leave the grid or that
-// move more than 3 cells along z are skipped.
+// R_A / R_S: radial shape folded with fold_mA / fold_mS.  Samples whose z shapes leave the grid are
+// skipped.
 // As k_deposit_jz, blocks of DEP_PER_THREAD x 256 consecutive samples accumulate in an LDS tile of
-// DEP_TILE_CUR cells (all planes) when their footprint fits.
+// DEP_TILE_CUR cells (all planes) when their footprint fits.  A sample whose integrated z shape spans more
+// than 8 nodes (it moves more than 3 cells in a step) adds everything with global atomics instead.
 constexpr int DEP_TILE_CUR = 1024;
 template <typename R>
 __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
@@ -658,7 +730,10 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             const double *q = sample(u);
             zp = (q[0] + h * q[6]) / D.dz;
             zm = (q[0] - h * q[6]) / D.dz;
-            return s0 + u < A.n && z_on_grid(D, zp) && z_on_grid(D, zm) && fabs(zp - zm) <= 3.0;
+            return s0 + u < A.n && z_on_grid(D, zp) && z_on_grid(D, zm);
+        };
+        auto is_wide = [&](double zp, double zm) {
+            return (int)floor(fmax(zp, zm)) + 2 - ((int)floor(fmin(zp, zm)) - 1) + 1 > 8;
         };
         auto rows_of = [&](double r, int &k0, int &k1) {
             const int kc = (int)floor(r / D.dr);
@@ -669,7 +744,7 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
 #pragma unroll
         for (int u = 0; u < DEP_PER_THREAD; ++u) {
             double zp, zm;
-            if (!on_grid(u, zp, zm)) continue;
+            if (!on_grid(u, zp, zm) || is_wide(zp, zm)) continue;
             const double *q = sample(u);
             fp[0] = min(fp[0], (int)floor(fmin(zp, zm)) - 1);
             fp[1] = max(fp[1], (int)floor(fmax(zp, zm)) + 2);
@@ -682,9 +757,9 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             }
         }
         block_minmax(fp, red);
-        if (fp[1] < fp[0]) continue;
-        const int tz = fp[1] - fp[0] + 1, tr = fp[3] - fp[2] + 1;
-        const bool use_tile = (int64_t)tz * tr <= DEP_TILE_CUR;  // uniform across the block
+        // fp covers the narrow samples only; without any the tile is empty (wide samples add directly)
+        const int tz = fp[1] >= fp[0] ? fp[1] - fp[0] + 1 : 0, tr = fp[1] >= fp[0] ? fp[3] - fp[2] + 1 : 0;
+        const bool use_tile = tz > 0 && (int64_t)tz * tr <= DEP_TILE_CUR;  // uniform across the block
         R *j = (R *)A.j[p];
         const size_t pl = 2 * D.plane;  // one plane in R units (interleaved complex)
         if (use_tile) {
@@ -693,8 +768,9 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
         }
         const double inv_dt = 1.0 / D.dt, inv_dz = 1.0 / D.dz;
         const double par_s = fold_mS(D.m), par_a = fold_mA(D.m);
+        bool tiled = use_tile;  // false for a wide sample
         auto add = [&](int plane, int k, int i, double re, double im) {
-            if (use_tile) {
+            if (tiled) {
                 double *c = tile + 2 * ((plane * tr + k - fp[2]) * tz + i - fp[0]);
                 atomicAdd(c, re);
                 atomicAdd(c + 1, im);
@@ -708,6 +784,8 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
         for (int u = 0; u < DEP_PER_THREAD; ++u) {
             double zp, zm;
             if (!on_grid(u, zp, zm)) continue;
+            const bool wide = is_wide(zp, zm);
+            tiled = use_tile && !wide;
             const double *q = sample(u);
             const double z = q[0], x = q[1], y = q[2], qw = q[3], vx = q[4], vy = q[5];
             const double r0 = sqrt(x * x + y * y), zc = z / D.dz;
@@ -736,6 +814,11 @@ __global__ __launch_bounds__(256) void k_deposit_current(DepositArgs A)
             }
             // longitudinal current and planar density differential over the nodes of both z shapes
             const int lo = (int)floor(fmin(zp, zm)) - 1, hi = (int)floor(fmax(zp, zm)) + 2;
+            if (wide) {
+                const SampleShape Sp = sample_shape(D, rp, xp, yp, A.eps, par_s), Sm = sample_shape(D, rm, xm, ym, A.eps, par_s);
+                deposit_z_wide<R>(j + 2 * pl, A.rho_xy ? j + 3 * pl : nullptr, D, Sp, Sm, qw, zp, zm, lo, hi, inv_dt, inv_dz);
+                continue;
+            }
             double dF[8], sz[8];  // nodes lo .. hi (at most 8), 0 beyond
             double Fp = 0.0, Fm = 0.0;
 #pragma unroll
@@ -1880,6 +1963,15 @@ hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s
         hipLaunchKernelGGL(k_scale<double2>, dim3(nb), dim3(256), 0, s, (double2 *)x, n, alpha);
     else
         hipLaunchKernelGGL(k_scale<float2>, dim3(nb), dim3(256), 0, s, (float2 *)x, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_form_wn(int prec, const BatchArgs &a, size_t max_cells, hipStream_t s)
+{
+    const size_t nb = (max_cells + 255) / 256;
+    const dim3 g((unsigned)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096));
+    if (prec == P64) hipLaunchKernelGGL(k_form_wn<double2>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_form_wn<float2>, g, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -86,6 +86,39 @@ __device__ __forceinline__ lv<AR, K> times_i(AR s, lv<AR, K> x)
     return r;
 }
 
+// A coefficient of the Horner recurrence (dt/(n+1), the source weight -dt 2^-n) given in FP64 and applied
+// to values in the arithmetic type AR.  Float arithmetic splits it, c = hi + lo with hi = float(c) and
+// lo = float(c - hi), and forms c x as hi x + lo x: the product then carries c to about 2^-48 instead of
+// rounding it to 2^-24, which would otherwise shift the effective time step the same way every stage.
+template <typename AR>
+struct Coef {
+    AR hi, lo;
+};
+template <typename AR>
+__device__ __forceinline__ Coef<AR> split_coef(double c)
+{
+    if constexpr (sizeof(AR) == 8) {
+        return Coef<AR>{c, 0.0};
+    } else {
+        const float h = (float)c;
+        return Coef<AR>{h, (float)(c - (double)h)};
+    }
+}
+// c x
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> cmul(Coef<AR> c, lv<AR, K> x)
+{
+    if constexpr (sizeof(AR) == 8) return c.hi * x;
+    else return fmav(c.lo, x, c.hi * x);
+}
+// c x + acc
+template <typename AR, int K>
+__device__ __forceinline__ lv<AR, K> cfma(Coef<AR> c, lv<AR, K> x, lv<AR, K> acc)
+{
+    if constexpr (sizeof(AR) == 8) return fmav(c.hi, x, acc);
+    else return fmav(c.lo, x, fmav(c.hi, x, acc));
+}
+
 // FP32 storage read in lane pairs (one float part per lane, 32 columns per wave, as FP64 storage is read):
 // the layout of the FP32C near-axis tiles, whose FP64 arithmetic on a whole complex value per lane would
 // need twice the registers.
@@ -335,11 +368,10 @@ __device__ __forceinline__ typename elem<V>::E ld_elem(const void *base, int c, 
 }
 
 // One row of a plane as this lane contributes it to an LDS row with N_D columns of halo on each side:
-// its own element and (lanes < 2 N_D S) one halo element, with the matching current elements when the
-// row is w_N = psi + beta_in Jbar.  Raw loads; put_row forms and masks them.
+// its own element and (lanes < 2 N_D S) one halo element.  Raw loads; put_row masks them.
 template <typename V>
 struct RowPart {
-    typename elem<V>::E own, halo, jown, jhalo;
+    typename elem<V>::E own, halo;
 };
 // Where this lane's halo element comes from and where it goes in the LDS row (fixed for a tile).
 struct Halo {
@@ -358,9 +390,8 @@ __device__ __forceinline__ Halo halo_of(int i0, int nz, const Lane<V> &L)
     h.idx = (unsigned)((h.ok ? ii : 0) * S + h.slot % S);
     return h;
 }
-template <typename V, bool ADDJ>
-__device__ __forceinline__ RowPart<V> fetch_row(const typename stor<V>::T *plane, const typename stor<V>::T *jplane, int nz,
-                                                int q, const Lane<V> &L,
+template <typename V>
+__device__ __forceinline__ RowPart<V> fetch_row(const typename stor<V>::T *plane, int nz, int q, const Lane<V> &L,
                                                 const Halo &H)
 {
     using E = typename elem<V>::E;
@@ -369,39 +400,16 @@ __device__ __forceinline__ RowPart<V> fetch_row(const typename stor<V>::T *plane
     RowPart<V> r;
     r.own = gld<E>(prow, (unsigned)L.eidx);
     r.halo = gld<E>(prow, H.idx);
-    if constexpr (ADDJ) {
-        const E *jrow = row_ptr<E>(jplane, 0, 0, nz, S, q);
-        r.jown = gld<E>(jrow, (unsigned)L.eidx);
-        r.jhalo = gld<E>(jrow, H.idx);
-    } else {
-        r.jown = r.jhalo = E{};
-    }
     return r;
 }
-// x + beta_in j in storage precision (the w_N input of a first stage), or x.
-template <bool ADDJ, typename E>
-__device__ __forceinline__ E form_in(E x, E j, double beta_in)
-{
-    if constexpr (ADDJ) {
-        if constexpr (std::is_same<E, float2>::value) {
-            x.x += (float)beta_in * j.x;
-            x.y += (float)beta_in * j.y;
-        } else {
-            x += beta_in * j;
-        }
-    }
-    return x;
-}
 // Columns outside the grid enter the z stencils as zeros.
-template <typename V, int ND, bool ADDJ>
-__device__ __forceinline__ void put_row(const RowPart<V> &r, double beta_in, const Lane<V> &L, const Halo &H,
-                                        typename elem<V>::E *row)
+template <typename V, int ND>
+__device__ __forceinline__ void put_row(const RowPart<V> &r, const Lane<V> &L, const Halo &H, typename elem<V>::E *row)
 {
     using E = typename elem<V>::E;
     constexpr int S = elem<V>::S;
-    const E own = form_in<ADDJ>(r.own, r.jown, beta_in), halo = form_in<ADDJ>(r.halo, r.jhalo, beta_in);
-    row[L.lane + ND * S] = L.col ? own : E{};
-    if (L.lane < 2 * ND * S) row[H.slot] = H.ok ? halo : E{};
+    row[L.lane + ND * S] = L.col ? r.own : E{};
+    if (L.lane < 2 * ND * S) row[H.slot] = H.ok ? r.halo : E{};
 }
 
 template <typename AR, typename V>
@@ -473,8 +481,8 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qc = qn < nr ? qn : nr - 1;
         x.bz = ldraw<V>(Bz, nz, qc, L);
         x.bt = ldraw<V>(Bth, nz, qc, L);
-        x.th = fetch_row<V, false>(Bth, nullptr, nz, k, L, H);
-        x.br = fetch_row<V, false>(Br, nullptr, nz, k, L, H);
+        x.th = fetch_row<V>(Bth, nz, k, L, H);
+        x.br = fetch_row<V>(Br, nz, k, L, H);
         x.j0 = x.j1 = x.j2 = E{};
         if constexpr (SRC) {
             x.j0 = ldraw<V>((const SV *)A.jr, nz, k, L);
@@ -496,8 +504,8 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qn = k + ND;  // the window's new row
         Wz[2 * ND - 1] = keep_if(qn < nr, to_lv<AR>(cu.bz));
         Wg[2 * ND - 1] = keep_if(qn < nr, ((AR)qn * dr) * to_lv<AR>(cu.bt));
-        put_row<V, ND, false>(cu.th, 0.0, L, H, lds[0]);
-        put_row<V, ND, false>(cu.br, 0.0, L, H, lds[1]);
+        put_row<V, ND>(cu.th, L, H, lds[0]);
+        put_row<V, ND>(cu.br, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
         // D_z^(+) at primary column i: staggered columns i + j and i - j + 1
@@ -521,10 +529,10 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const L_ t2 = times_i(mm * rip, br);
         __syncthreads();
         if (L.col && live) {
-            const AR coef = (AR)A.coef, beta = (AR)A.beta;
-            const L_ i0v = fmav(beta, to_lv<AR>(cu.j0), coef * (t0 - zth));
-            const L_ i1v = fmav(beta, to_lv<AR>(cu.j1), coef * (zr - rz));
-            const L_ i2v = fmav(beta, to_lv<AR>(cu.j2), coef * (rip * rg - t2));
+            const Coef<AR> coef = split_coef<AR>(A.coef), beta = split_coef<AR>(A.beta);
+            const L_ i0v = cfma(beta, to_lv<AR>(cu.j0), cmul(coef, t0 - zth));
+            const L_ i1v = cfma(beta, to_lv<AR>(cu.j1), cmul(coef, zr - rz));
+            const L_ i2v = cfma(beta, to_lv<AR>(cu.j2), cmul(coef, rip * rg - t2));
             store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, cu.p0, cu.l0);
             store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, cu.p1, cu.l1);
             store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, cu.p2, cu.l2);
@@ -543,10 +551,10 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 //          dB_theta = -D_z^(-) E_rho   + D_rho^(-,mS) E_z              (staggered rows k >= 1)
 //          dB_z     =  (i m / rho_(-)) E_rho - rho_(-)^-1 D^(-) (rho E_theta)   (k >= 1)
 // Window (primary rows q = k - N_D + t, t = 0 .. 2N_D-1): E_z and g = rho E_theta.
-// In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed while
-// loading (FIRST); without a current, or in later stages, the input is read as it is.
+// In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed before
+// the launch (k_form_wn); otherwise psi or the previous stage's output.
 // --------------------------------------------------------------------------------------------------
-template <typename V, typename AR, int ND, bool FIRST, bool COMP>
+template <typename V, typename AR, int ND, bool COMP>
 __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     constexpr int K = elem<V>::K, S = elem<V>::S;
@@ -558,15 +566,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     using SV = typename stor<V>::T;
     const SV *vin = (const SV *)A.vin;
     const SV *Er = vin + ER * P, *Eth = vin + ETH * P, *Ez = vin + EZ * P;
-    const SV *Jr = (const SV *)A.jr, *Jt = (const SV *)A.jt, *Jz = (const SV *)A.jz;
     const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
-    const AR bin = (AR)A.beta_in;
     const L_ zero = zero_lv<AR, K>();
-    auto ldw = [&](const SV *f, const SV *jf, int q) -> L_ {
-        L_ x = ldrow<V, AR>(f, nz, q, L);
-        if constexpr (FIRST) x = fmav(bin, ldrow<V, AR>(jf, nz, q, L), x);
-        return x;
-    };
     L_ Wz[2 * ND], Wg[2 * ND];
     // filled after the ring's first loads are issued, so that both arrive within one latency
     auto fill = [&]() {
@@ -576,8 +577,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         for (int t = 0; t < 2 * ND - 1; ++t) {
             const int q = k0 - ND + t;
             const int r = min(q < 0 ? -1 - q : q, nr - 1);
-            Wz[t] = ldw(Ez, Jz, r);
-            Wg[t] = ldw(Eth, Jt, r);
+            Wz[t] = ldrow<V, AR>(Ez, nz, r, L);
+            Wg[t] = ldrow<V, AR>(Eth, nz, r, L);
         }
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
@@ -591,7 +592,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     using E = typename elem<V>::E;
     const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
-        E ez, et, jz, jt;
+        E ez, et;
         RowPart<V> th, er;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
@@ -602,13 +603,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qc = qn < nr ? qn : nr - 1;
         x.ez = ldraw<V>(Ez, nz, qc, L);
         x.et = ldraw<V>(Eth, nz, qc, L);
-        x.jz = x.jt = E{};
-        if constexpr (FIRST) {
-            x.jz = ldraw<V>(Jz, nz, qc, L);
-            x.jt = ldraw<V>(Jt, nz, qc, L);
-        }
-        x.th = fetch_row<V, FIRST>(Eth, Jt, nz, k, L, H);
-        x.er = fetch_row<V, FIRST>(Er, Jr, nz, k, L, H);
+        x.th = fetch_row<V>(Eth, nz, k, L, H);
+        x.er = fetch_row<V>(Er, nz, k, L, H);
         x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
         x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
         x.p2 = ld_elem<V>(A.psi, BZ, k, D, L);
@@ -622,15 +618,11 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     };
     auto row = [&](const In &cu, int k, bool live) {
         const int qn = k + ND - 1;  // the window's new row
-        L_ ez = to_lv<AR>(cu.ez), et = to_lv<AR>(cu.et);
-        if constexpr (FIRST) {
-            ez = fmav(bin, to_lv<AR>(cu.jz), ez);
-            et = fmav(bin, to_lv<AR>(cu.jt), et);
-        }
+        const L_ ez = to_lv<AR>(cu.ez), et = to_lv<AR>(cu.et);
         Wz[2 * ND - 1] = keep_if(qn < nr, ez);
         Wg[2 * ND - 1] = keep_if(qn < nr, (((AR)qn + (AR)0.5) * dr) * et);
-        put_row<V, ND, FIRST>(cu.th, A.beta_in, L, H, lds[0]);
-        put_row<V, ND, FIRST>(cu.er, A.beta_in, L, H, lds[1]);
+        put_row<V, ND>(cu.th, L, H, lds[0]);
+        put_row<V, ND>(cu.er, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
         // D_z^(-) at staggered column i: primary columns i + j - 1 and i - j
@@ -647,17 +639,17 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             rz = fmav(ar, Wz[ND + j - 1] - Wz[ND - j], rz);
             rg = fmav(ar, Wg[ND + j - 1] - Wg[ND - j], rg);
         }
-        const L_ erk = to_lv<AR>(form_in<FIRST>(cu.er.own, cu.er.jown, A.beta_in));
+        const L_ erk = to_lv<AR>(cu.er.own);
         const L_ ezk = Wz[ND];
         const AR rip = (AR)cld(D.rinv_p, k), ris = (AR)cld(D.rinv_s, k);
         const L_ t0 = times_i(mm * rip, ezk);
         const L_ t2 = times_i(mm * ris, erk);
         __syncthreads();
         if (L.col && live) {
-            const AR coef = (AR)A.coef;
-            store_out<V, AR, COMP>(A, BR, k, L, coef * (zth - t0), false, cu.p0, cu.l0);
-            store_out<V, AR, COMP>(A, BTH, k, L, coef * (rz - zr), k == 0, cu.p1, cu.l1);
-            store_out<V, AR, COMP>(A, BZ, k, L, coef * (t2 - ris * rg), k == 0, cu.p2, cu.l2);
+            const Coef<AR> coef = split_coef<AR>(A.coef);
+            store_out<V, AR, COMP>(A, BR, k, L, cmul(coef, zth - t0), false, cu.p0, cu.l0);
+            store_out<V, AR, COMP>(A, BTH, k, L, cmul(coef, rz - zr), k == 0, cu.p1, cu.l1);
+            store_out<V, AR, COMP>(A, BZ, k, L, cmul(coef, t2 - ris * rg), k == 0, cu.p2, cu.l2);
         }
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
@@ -665,7 +657,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR, ND, FIRST || COMP>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 // Tile of block b.  Tiles are numbered problem by problem, (half,) segment, strip -- strips fastest --
@@ -699,7 +691,7 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
 // AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage; V = float2 or,
 // for wide stencils, f2pair read in lane pairs): rows 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the
 // axis and its 1/rho factors, in FP64 arithmetic.
-template <typename V, int ND, bool FIRST, bool SRC, bool COMP, bool AXIS>
+template <typename V, int ND, bool SRC, bool COMP, bool AXIS>
 __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     constexpr int S = elem<V>::S, CPW = WAVE / S;
@@ -712,7 +704,9 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.D = &D;
     const bool first = A.n == A.N - 1;
     C.psi = A.psi[p];
-    C.vin = first ? C.psi : D.buf[(A.N - 2 - A.n) & 1];
+    // the first stage reads psi, except the B half of a step with a current: it reads the E part of
+    // w_N = psi + beta_in Jbar, which k_form_wn wrote into the second stage buffer before the launch
+    C.vin = first ? ((A.has_src && half == 1) ? D.buf[1] : C.psi) : D.buf[(A.N - 2 - A.n) & 1];
     C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
     C.has_src = A.has_src;
     const size_t pb = D.plane * sizeof(typename stor<V>::T);
@@ -725,7 +719,7 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.coef = A.coef;
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
     if (half == 0) e_half<V, AR, ND, SRC, COMP>(C, i0, k0, k1, lds);
-    else b_half<V, AR, ND, FIRST, COMP>(C, i0, k0, k1, lds);
+    else b_half<V, AR, ND, COMP>(C, i0, k0, k1, lds);
 }
 
 // One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
@@ -737,7 +731,7 @@ constexpr int lds_row_bytes()
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
+template <typename V, int ND, bool SRC, bool COMP>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
     // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
@@ -750,12 +744,12 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, FIRST, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, FIRST, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -816,7 +810,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         In x;
         const int qn = k + ND;
         x.an = ldraw<V>(va, nz, qn < nr ? qn : nr - 1, L);
-        x.a = fetch_row<V, false>(va, nullptr, nz, k, L, H);
+        x.a = fetch_row<V>(va, nz, k, L, H);
         x.tin = ldraw<V>(vt, nz, k, L);
         x.chi = gld<R>((const R *)A.chi + (size_t)k * nz, (unsigned)cc);
         const unsigned o = (unsigned)L.eidx;
@@ -834,7 +828,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         const int qn = k + ND;
         Wa[W - 1] = keep_if(qn < nr, to_lv<AR>(cu.an));
         const L_ tin = to_lv<AR>(cu.tin);
-        put_row<V, ND, false>(cu.a, 0.0, L, H, lds);
+        put_row<V, ND>(cu.a, L, H, lds);
         __syncthreads();
         const L_ a0 = Wa[ND];
         L_ lz = (AR)D.bz[0] * a0, d1z = zero;
@@ -858,8 +852,8 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         __syncthreads();
         if (L.col && live) {
             const L_ dtv = lr + (AR)cld(D.rinv_p, k) * d1r + lz - pot * a0 + rot;
-            const AR coef = (AR)A.coef;
-            const L_ ia = coef * tin, it = coef * dtv;
+            const Coef<AR> coef = split_coef<AR>(A.coef);
+            const L_ ia = cmul(coef, tin), it = cmul(coef, dtv);
             const unsigned o = (unsigned)L.eidx;
             void *ra = (void *)row_ptr<E>(A.out_a, 0, 0, nz, S, k), *rt = (void *)row_ptr<E>(A.out_t, 0, 0, nz, S, k);
             if constexpr (S == 1) {
@@ -1034,11 +1028,11 @@ hipError_t go_stagger(const BatchArgs &a, hipStream_t s)
 }
 
 // Launch stage n of a batch with the kernel variant its flags select.
-template <typename V, int ND, bool FIRST, bool SRC, bool COMP>
+template <typename V, int ND, bool SRC, bool COMP>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
-    hipLaunchKernelGGL((k_maxwell_stage<V, ND, FIRST, SRC, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE),
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE),
                        0, s, a);
     return hipGetLastError();
 }
@@ -1046,19 +1040,15 @@ hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 template <typename V, int ND>
 hipError_t go_maxwell(const BatchArgs &a, hipStream_t s)
 {
-    // FIRST adds beta_in * Jbar while loading the E input: only in the first stage, and only with a current
-    const bool first = a.n == a.N - 1 && a.has_src;
     const bool comp = sizeof(typename scal<V>::R) == 4 && a.compensated && a.n == 0;
     if (comp) {
         if constexpr (sizeof(typename scal<V>::R) == 4) {
-            if (first) return go_maxwell_v<V, ND, true, true, true>(a, s);
-            if (a.has_src) return go_maxwell_v<V, ND, false, true, true>(a, s);
-            return go_maxwell_v<V, ND, false, false, true>(a, s);
+            if (a.has_src) return go_maxwell_v<V, ND, true, true>(a, s);
+            return go_maxwell_v<V, ND, false, true>(a, s);
         }
     }
-    if (first) return go_maxwell_v<V, ND, true, true, false>(a, s);
-    if (a.has_src) return go_maxwell_v<V, ND, false, true, false>(a, s);
-    return go_maxwell_v<V, ND, false, false, false>(a, s);
+    if (a.has_src) return go_maxwell_v<V, ND, true, false>(a, s);
+    return go_maxwell_v<V, ND, false, false>(a, s);
 }
 
 template <typename V, int ND, bool COMP>

@@ -283,13 +283,21 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     A.N = b.N;
     A.has_src = j != nullptr;
     A.compensated = P->precision == FDETD_FP32C;
+    if (j && b.ntiles + b.ntiles_ax) {
+        // E part of w_N = psi + beta_in Jbar into buf[1]: read by the B half of the first stage
+        A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
+        size_t max_cells = 0;
+        for (int t = 0; t < b.count; ++t) max_cells = std::max(max_cells, P->probs[b.members[t]].cells);
+        HIPCHK(P, launch_form_wn(prec, A, max_cells, s));
+    }
     for (int n = b.N - 1; n >= 0; --n) {
         A.n = n;
         A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
         A.beta = -b.dt * std::ldexp(1.0, -n);
         A.coef = b.dt / (n + 1);
-        // algorithmic bytes: vin (6c) + psi (6c; the same data in the first stage) + Jbar (3c) + vout (6c)
-        const double cvals = (n == b.N - 1 ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
+        // algorithmic bytes: vin (6c) + psi (6c) + Jbar (3c) + vout (6c); the first stage without a current
+        // reads psi once as vin and as psi (12c); with one, its B half reads w_N from buf[1]
+        const double cvals = (n == b.N - 1 && !j ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
         const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
         int rc = profile_begin(P, bytes);
         if (rc) return rc;
@@ -805,15 +813,16 @@ int autotune(fdetd_plan_t P, double &ms_spent)
 
 // Spectral radius of H by power iteration on -H^2 over a grid of at most 64 x 64 cells with the same
 // mode, orders and spacings (the extreme eigenvectors live at the grid scale and near the axis, both
-// present in the reduced grid).
+// present in the reduced grid).  FP64 arithmetic whatever the plan's precision: the estimate decides the
+// time step a plan accepts (the norm of H grows with m, end of section 2.5).
 int estimate_rho(fdetd_plan_t P, Prob &q, double &rho)
 {
     Prob r = q;  // shares coefficients; own small buffers below
     r.d.nz = std::min(q.d.nz, 64);
     r.d.nr = std::min(q.d.nr, 64);
     r.cells = (size_t)r.d.nz * r.d.nr;
-    const int prec = prec_code(P->precision);
-    const size_t eb = elem_bytes(P->precision);
+    const int prec = P64;
+    const size_t eb = elem_bytes(FDETD_FP64);
     const int np = planes(P->kind);
     const size_t n = np * r.cells;
     void *x = nullptr, *t = nullptr, *y = nullptr, *zero = nullptr, *chi = nullptr;
@@ -860,11 +869,9 @@ int estimate_rho(fdetd_plan_t P, Prob &q, double &rho)
             z ^= z >> 31;
             v = (double)(z >> 11) * 0x1.0p-53 - 0.5;
         }
-        if (P->precision == FDETD_FP64) {
-            if (hipMemcpy(x, h.data(), n * 16, hipMemcpyHostToDevice)) { rc = FDETD_E_HIP; break; }
-        } else {
-            std::vector<float> hf(h.begin(), h.end());
-            if (hipMemcpy(x, hf.data(), n * 8, hipMemcpyHostToDevice)) { rc = FDETD_E_HIP; break; }
+        if (hipMemcpy(x, h.data(), n * 16, hipMemcpyHostToDevice)) {
+            rc = fail(P, FDETD_E_HIP, "stability estimate: copy failed");
+            break;
         }
         auto applyH = [&](const void *in, void *out) -> int {
             if (P->kind == FDETD_MAXWELL) {
@@ -1079,7 +1086,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         const int N = q.d.taylor_order;
         cells += q.cells;
         if (P->kind == FDETD_MAXWELL) {
-            // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w
+            // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w.
+            // (The w_N pass, 9c, is not counted: it is an implementation overhead of the first stage.)
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
             launches += 1;  // axis rule (staging and stage launches are counted per batch below)
         } else {
@@ -1119,8 +1127,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.cells = cells;
     P->info.bytes_per_step = bytes_step;
     P->info.scratch_bytes = scratch;
-    for (const Batch &b : P->batches)
-        launches += (int64_t)(b.N + (P->kind == FDETD_MAXWELL)) * (b.ntiles + b.ntiles_ax > 0);
+    for (const Batch &b : P->batches)  // Maxwell: N stages, staging and w_N per batch
+        launches += (int64_t)(b.N + (P->kind == FDETD_MAXWELL ? 2 : 0)) * (b.ntiles + b.ntiles_ax > 0);
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
@@ -1146,12 +1154,8 @@ int fdetd_deposit_jz(fdetd_plan_t plan, const double *samples, int64_t n, double
         return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: bad arguments");
     const size_t eb = elem_bytes(plan->precision);
     for (size_t p = 0; p < plan->probs.size(); ++p) {
-        const Prob &q = plan->probs[p];
         if (!aligned(j_half[p], eb))
             return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: j_half[%zu] NULL or not %zu-byte aligned", p, eb);
-        // the two shapes of a sample span at most 8 nodes
-        if (std::fabs(vz) * q.d.dt > 3.0 * q.d.dz)
-            return fail(plan, FDETD_E_ARG, "fdetd_deposit_jz: problem %zu: |vz| dt exceeds 3 cells", p);
     }
     if (n == 0) return FDETD_OK;
     for (const Batch &b : plan->batches) {

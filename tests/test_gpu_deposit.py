@@ -64,7 +64,7 @@ def test_deposit_rejects_bad_arguments():
     plan = F.Plan(w.problems(), precision=F.FP64, flags=1)
     J = [torch.zeros((3, 16, 64), dtype=torch.complex128, device="cuda")]
     s = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
-    for kw in (dict(vz=1e3), dict(eps=1.5)):
+    for kw in (dict(vz=float("inf")), dict(vz=float("nan")), dict(eps=1.5)):
         with pytest.raises(F.FdetdError):
             plan.deposit_jz(s, J, **kw)
     plan.deposit_jz(s[:0], J)  # no samples: nothing to do
@@ -223,3 +223,49 @@ def test_samples_on_the_axis_deposit_only_into_mode_0(precision):
         else:
             assert peak == 0.0, (m, peak)
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fast_samples_deposit_their_whole_shape(precision):
+    """Samples that move 3 to 9 cells in a step (integrated z shapes over more than 8 nodes) take the
+    kernels' global-atomic path; J_z of fdetd_deposit_jz (uniform vz) and all currents and rho_xy of
+    fdetd_deposit_current (per-sample velocities, mixed with slow ones in the same blocks) equal the
+    oracle's (tolerances as above)."""
+    import torch
+    dz = I.LAMBDA0 / 20
+    nz, nr = 200, 24
+    w = I.Workload("fast", 0, [nz] * 3, [nr] * 3, [0, 1, 2], [8] * 3, 8, dz, 2 * dz, 0.5 * dz, 1)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    tol = 1e-12 if precision == F.FP64 else 1e-5
+    rng = np.random.default_rng(33)
+    n = 3000
+    z = rng.uniform(14 * dz, (nz - 15) * dz, n)
+    r = np.abs(rng.normal(0, 4 * dz, n))
+    th = rng.uniform(-math.pi, math.pi, n)
+    s4 = np.stack([z, r * np.cos(th), r * np.sin(th), rng.uniform(-1, 1, n) * 1e-2], axis=1)
+    plan0 = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_SKIP_STABILITY | F.PLAN_CURRENT_CORRECTION)
+    vz = 13.0  # 6.5 cells per step
+    J = [torch.zeros((3, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    plan0.deposit_jz(dev(s4, torch.float64), J, vz=vz, eps=0.5)
+    s8 = np.zeros((n, 8))
+    s8[:, :4] = s4
+    s8[:, 4:6] = rng.uniform(-0.3, 0.3, (n, 2))
+    s8[:, 6] = rng.choice([-1.0, 1.0], n) * np.where(rng.uniform(0, 1, n) < 0.5, rng.uniform(6.5, 18.0, n),
+                                                     rng.uniform(0.0, 0.9, n))
+    J8 = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(3)]
+    plan.deposit_current(dev(s8, torch.float64), J8, eps=0.5)
+    torch.cuda.synchronize()
+    for p in range(3):
+        g = oracle.Grid(nz=nz, nr=nr, m=p, fd_order=8, taylor_order=8, dz=dz, dr=2 * dz, dt=0.5 * dz)
+        want = oracle.deposit_jz(g, s4, vz=vz, eps=0.5)
+        got = J[p].cpu().numpy().astype(np.complex128)
+        e1 = rel_l2(got[2], want[2])
+        wj, wr = oracle.deposit_current(g, s8, eps=0.5)
+        got8 = J8[p].cpu().numpy().astype(np.complex128)
+        e2 = max(rel_l2(got8[c], wj[c]) for c in range(3))
+        e3 = rel_l2(got8[3], wr)
+        log(f"fast samples m={p} precision={precision}: J_z {e1:.2e}, currents {e2:.2e}, rho_xy {e3:.2e}")
+        assert np.max(np.abs(want[2])) > 0 and e1 < tol and e2 < tol and e3 < tol
+    plan.close()
+    plan0.close()
