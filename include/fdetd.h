@@ -28,7 +28,7 @@
  *
  * Errors: every call returns FDETD_OK (0) or a negative code; no exception crosses the ABI.
  * fdetd_last_error() returns a human-readable message for the last failure on that plan
- * (or of the last failed fdetd_plan() on this thread when called with NULL).
+ * (or of the last failed fdetd_plan() or fdetd_step_noalloc() on this thread when called with NULL).
  * ---------------------------------------------------------------------------------------------------
  */
 #ifndef FDETD_H
@@ -292,6 +292,23 @@ FDETD_API int envelope_gather(fdetd_plan_t plan, int32_t problem, const void *po
  * FP32C: the damping scales each (value, compensation word) pair in FP64. */
 FDETD_API int envelope_absorber(fdetd_plan_t plan, int32_t problem, int32_t lz, int32_t lr, double sigma_max,
                                 double power);
+
+/* For callers that cannot allocate device memory -- code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc: fdetd_step for ONE Maxwell problem without a plan, allocating nothing.
+ * The step is that of fdetd_step (same kernels, same results bit for bit) with FDETD_PLAN_SKIP_STABILITY
+ * and the default tiling.  What a plan would own -- the problem's descriptor, its 1/rho tables, the two
+ * stage vectors, the staged current and the FP32C compensation words -- lives in one static device
+ * array of 13.7 MB that the library holds on every GPU it runs on until the process ends.
+ *   prob     host pointer to the problem (kind FDETD_MAXWELL); nz * nr <= 65536 and nr <= 4096, else
+ *            FDETD_E_ARG.
+ *   precision, stream: as for fdetd_plan; psi, j_half, j_step_blocks, n_steps: as for fdetd_step with one
+ *            problem (single pointers here).
+ * FP32C: the compensation words start at zero on every call (they are not carried from one call to the
+ * next).  All calls on one GPU share the array: calls that overlap on one GPU (other streams, other host
+ * threads) race and give wrong results; calls in order on one stream are safe.  Errors: FDETD_E_ARG (also
+ * for sizes beyond the limit), FDETD_E_HIP; the message is fdetd_last_error(NULL).  Enqueue only. */
+FDETD_API int fdetd_step_noalloc(const fdetd_problem_desc *prob, int32_t precision, void *stream, void *psi,
+                                 const void *j_half, int64_t j_step_blocks, int32_t n_steps);
 
 /* Plan facts (stability estimate, algorithmic bytes per step, scratch size).  Host only. */
 FDETD_API int fdetd_query(fdetd_plan_t plan, fdetd_plan_info *info);

@@ -8,4 +8,5 @@ from .binding import (ENVELOPE, FDETD_E_ARG, FDETD_E_HIP, FDETD_E_NOMEM, FDETD_E
                       envelope_absorber, envelope_gather, envelope_ponderomotive, envelope_step, fdetd_coefficients,
                       fdetd_deposit_current, fdetd_deposit_jz, fdetd_deposit_rho, fdetd_destroy, fdetd_export_state,
                       fdetd_gather, fdetd_gather_supersampled, fdetd_import_state, fdetd_last_error, fdetd_plan, fdetd_query, fdetd_step,
+                      fdetd_step_noalloc,
                       fdetd_taylor_stability_bound)

@@ -22,7 +22,7 @@ PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_ST
 PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
+EXPORTS = ("fdetd_plan", "fdetd_step", "fdetd_step_noalloc", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
            "envelope_gather",
            "fdetd_deposit_jz", "fdetd_deposit_rho",
            "fdetd_deposit_current", "fdetd_gather", "fdetd_gather_supersampled", "fdetd_query",
@@ -83,6 +83,7 @@ def _load():
     L.fdetd_plan.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.c_int32, C.c_uint32, vp, C.POINTER(vp)]
     L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
+    L.fdetd_step_noalloc.argtypes = [C.POINTER(ProblemDesc), C.c_int32, vp, vp, vp, C.c_int64, C.c_int32]
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_gather.argtypes = [vp, pp, vp, C.c_int64, vp]
@@ -136,6 +137,15 @@ def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_blocks: int = 0, n_steps: int
     rc = lib.fdetd_step(plan, _ptrs(psi_ptrs), _ptrs(j_ptrs) if j_ptrs is not None else None,
                         j_step_blocks, n_steps)
     _check(rc, plan)
+
+
+def fdetd_step_noalloc(problem: Problem, precision: int, stream: int, psi_ptr: int, j_ptr=None,
+                       j_step_blocks: int = 0, n_steps: int = 1):
+    """fdetd_step of one Maxwell problem without a plan and without device allocation (raw pointers)."""
+    d = problem.c()
+    rc = lib.fdetd_step_noalloc(C.byref(d), precision, C.c_void_p(stream), C.c_void_p(psi_ptr),
+                                C.c_void_p(j_ptr) if j_ptr is not None else None, j_step_blocks, n_steps)
+    _check(rc, None)
 
 
 def envelope_step(plan, a_ptrs, at_ptrs, chi_ptrs, chi_step_planes: int = 0, n_steps: int = 1):

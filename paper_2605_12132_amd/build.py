@@ -22,7 +22,8 @@ LIB = os.path.join(OUT_DIR, "libfdetd.so")
 ND_RANGES = [(1, 3), (4, 6), (7, 8), (9, 10), (11, 12), (13, 14), (15, 15), (16, 16)]
 SOURCES = ([("fdetd_march.hip", f"fdetd_march_nd{lo}_{hi}", [f"-DFDETD_ND_LO={lo}", f"-DFDETD_ND_HI={hi}"])
             for lo, hi in ND_RANGES]
-           + [(f, f, []) for f in ("fdetd_kernels.hip", "fdetd_plan.cpp", "fdetd_coeffs.cpp", "fdetd_dispatch.cpp")])
+           + [(f, f, []) for f in ("fdetd_kernels.hip", "fdetd_noalloc.hip", "fdetd_plan.cpp", "fdetd_coeffs.cpp",
+                                   "fdetd_dispatch.cpp")])
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "../../include/fdetd.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -101,6 +103,13 @@ struct ProbDesc {
     double sh[kMaxND];                                   // half-shift weights s_j (current staging)
     double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
 };
+
+// Descriptor of one problem (sizes, tiling with seg rows per segment, coefficient tables; pointers and
+// tile offsets zero), and the default segment length of a single-problem plan.  fdetd_plan.cpp.
+void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbDesc &D);
+int default_segment_rows(int precision, const fdetd_problem_desc &d);
+// The message fdetd_last_error(NULL) returns on this thread.
+void set_last_error(const char *msg);
 
 // One launch: stage n of every problem in the batch.
 struct BatchArgs {

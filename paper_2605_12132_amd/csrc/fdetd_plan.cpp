@@ -581,28 +581,9 @@ int build_batches(fdetd_plan_t P)
         for (int v = t; v < u; ++v) {
             const Prob &q = P->probs[order[v]];
             ProbDesc D;
-            std::memset(&D, 0, sizeof D);
-            D.nz = q.d.nz;
-            D.nr = q.d.nr;
-            D.m = q.d.m;
-            D.taylor = q.d.taylor_order;
-            D.nstrip = (q.d.nz + cpw - 1) / cpw;
-            if (P->precision == FDETD_FP32C) {
-                D.ax_rows = std::min(q.d.nr, axis_rows(q));
-                D.seg_ax = std::min(kSegAxis, D.ax_rows);
-                D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
-                D.nstrip_ax = (q.d.nz + axis_columns(q.nd) - 1) / axis_columns(q.nd);
-            }
-            D.seg_rows = seg;
-            D.nseg = (q.d.nr - D.ax_rows + seg - 1) / seg;
+            describe_problem(q.d, P->precision, seg, D);
             D.tile_begin = tiles;
             D.tile_begin_ax = tiles_ax;
-            D.plane = q.cells;
-            D.dr = q.d.dr;
-            D.dz = q.d.dz;
-            D.dt = q.d.dt;
-            D.pS = parity_mS(q.d.m);
-            D.k0 = q.d.k0;
             D.buf[0] = q.buf[0];
             D.buf[1] = q.buf[1];
             D.jbar = q.jbar;
@@ -613,18 +594,6 @@ int build_batches(fdetd_plan_t P)
             D.sz = q.sz;
             D.jth = q.jth;
             D.sr = q.sr;
-            for (int k = 0; k < q.nd; ++k) {
-                D.az[k] = q.a[k] / q.d.dz;
-                D.ar[k] = q.a[k] / q.d.dr;
-                D.cax[k] = q.c[k];
-                D.sh[k] = q.s[k];
-                D.dzc[k] = q.d1[k] / q.d.dz;
-                D.drc[k] = q.d1[k] / q.d.dr;
-            }
-            for (int k = 0; k <= q.nd; ++k) {
-                D.bz[k] = q.d2[k] / (q.d.dz * q.d.dz);
-                D.br[k] = q.d2[k] / (q.d.dr * q.d.dr);
-            }
             tiles += halves * D.nseg * D.nstrip;
             tiles_ax += halves * D.nseg_ax * D.nstrip_ax;
             P->desc.push_back(D);
@@ -1757,3 +1726,63 @@ int fdetd_import_state(fdetd_plan_t plan, const void *host_blob, size_t bytes)
 }
 
 }  // extern "C"
+
+namespace fdetd {
+
+// Sizes, tiling and coefficient tables of one problem's descriptor (pointers and tile offsets left zero):
+// strips of the wavefront width, segments of seg rows below the FP32C near-axis rows (rows 0 .. 2 N_D - 1
+// in segments of 8 rows and strips of the near-axis width), the staggered, half-shift, centred and axis
+// weights of section 2.3 / 2.4 scaled by the cell sizes.
+void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbDesc &D)
+{
+    std::memset(&D, 0, sizeof D);
+    const int nd = d.fd_order / 2;
+    const int cpw = march_columns_per_wave(prec_code(precision));
+    D.nz = d.nz;
+    D.nr = d.nr;
+    D.m = d.m;
+    D.taylor = d.taylor_order;
+    D.nstrip = (d.nz + cpw - 1) / cpw;
+    if (precision == FDETD_FP32C) {
+        D.ax_rows = std::min(d.nr, 2 * nd);
+        D.seg_ax = std::min(kSegAxis, D.ax_rows);
+        D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
+        D.nstrip_ax = (d.nz + axis_columns(nd) - 1) / axis_columns(nd);
+    }
+    D.seg_rows = seg;
+    D.nseg = (d.nr - D.ax_rows + seg - 1) / seg;
+    D.plane = (size_t)d.nz * d.nr;
+    D.dr = d.dr;
+    D.dz = d.dz;
+    D.dt = d.dt;
+    D.pS = parity_mS(d.m);
+    D.k0 = d.k0;
+    double a[kMaxND], sh[kMaxND], c[kMaxND], d1[kMaxND], d2[kMaxND + 1];
+    make_coefficients(COEF_STAGGERED, nd, a);
+    make_coefficients(COEF_HALFSHIFT, nd, sh);
+    make_coefficients(COEF_AXIS, nd, c);
+    make_coefficients(COEF_CENTRED_D1, nd, d1);
+    make_coefficients(COEF_CENTRED_D2, nd, d2);
+    for (int k = 0; k < nd; ++k) {
+        D.az[k] = a[k] / d.dz;
+        D.ar[k] = a[k] / d.dr;
+        D.cax[k] = c[k];
+        D.sh[k] = sh[k];
+        D.dzc[k] = d1[k] / d.dz;
+        D.drc[k] = d1[k] / d.dr;
+    }
+    for (int k = 0; k <= nd; ++k) {
+        D.bz[k] = d2[k] / (d.dz * d.dz);
+        D.br[k] = d2[k] / (d.dr * d.dr);
+    }
+}
+
+void set_last_error(const char *msg) { g_last_error = msg; }
+
+int default_segment_rows(int precision, const fdetd_problem_desc &d)
+{
+    const int cpw = march_columns_per_wave(prec_code(precision));
+    return default_seg_rows((int64_t)2 * ((d.nz + cpw - 1) / cpw) * d.nr);
+}
+
+}  // namespace fdetd

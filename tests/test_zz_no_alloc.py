@@ -1,0 +1,63 @@
+"""fdetd_step_noalloc (one Maxwell problem, no plan, no device allocation; its scratch is a static device
+array) against fdetd_step of a plan on the same inputs: two calls in a row, the second on a smaller grid,
+in FP64 and FP32C, with a current over several steps.  Both run the same kernels on the same data, so
+the states agree bit for bit; FP64 also matches the oracle (relative L2 <= 1e-12)."""
+import numpy as np
+import pytest
+
+from helpers import dev, log, rel_l2
+
+import oracle
+import paper_2605_12132_amd as F
+import paper_2605_12132_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(prob, precision, psi0, J, steps):
+    import torch
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    stream = torch.cuda.current_stream()
+    a = dev(psi0, cd)
+    ja = dev(J, cd)
+    F.fdetd_step_noalloc(prob, precision, stream.cuda_stream, a.data_ptr(), ja.data_ptr(), 1, steps)
+    b = dev(psi0, cd)
+    jb = dev(J, cd)
+    plan = F.Plan([prob], precision=precision, flags=F.PLAN_SKIP_STABILITY)
+    plan.step([b], [jb], n_steps=steps)
+    torch.cuda.synchronize()
+    plan.close()
+    return a.cpu().numpy(), b.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_noalloc_step_equals_planned_step(precision):
+    dz = I.LAMBDA0 / 20
+    rng = np.random.default_rng(91)
+    cases = [(512, 96, 1, 16, 8, 3), (200, 40, 0, 8, 12, 2)]  # the second call on a smaller grid
+    for nz, nr, m, order, N, steps in cases:
+        prob = F.Problem(nz, nr, m, order, N, dz, 2 * dz, 0.5 * dz)
+        psi0 = rng.uniform(-1, 1, (6, nr, nz)) + 1j * rng.uniform(-1, 1, (6, nr, nz))
+        J = 0.1 * (rng.uniform(-1, 1, (steps, 3, nr, nz)) + 1j * rng.uniform(-1, 1, (steps, 3, nr, nz)))
+        got, want = run_both(prob, precision, psi0, J, steps)
+        log(f"noalloc {nz}x{nr} m={m} order {order} N={N} precision={precision}: "
+            f"max |noalloc - plan| {np.max(np.abs(got - want)):.3e}")
+        assert np.array_equal(got, want)
+        if precision == F.FP64:
+            g = oracle.Grid(nz=nz, nr=nr, m=m, fd_order=order, taylor_order=N, dz=dz, dr=2 * dz, dt=0.5 * dz)
+            ref = psi0
+            for s in range(steps):
+                ref = oracle.step(g, ref, J[s], 1)
+            err = rel_l2(got, ref)
+            log(f"  vs oracle: rel L2 {err:.2e}")
+            assert err < 1e-12
+
+
+def test_noalloc_rejects_grids_beyond_the_scratch():
+    import torch
+    dz = I.LAMBDA0 / 20
+    x = torch.zeros((6, 300, 256), dtype=torch.complex128, device="cuda")  # 76800 > 65536 cells
+    with pytest.raises(F.FdetdError) as e:
+        F.fdetd_step_noalloc(F.Problem(256, 300, 0, 8, 8, dz, 2 * dz, 0.5 * dz), F.FP64,
+                             torch.cuda.current_stream().cuda_stream, x.data_ptr(), None, 0, 1)
+    assert e.value.code == F.FDETD_E_ARG and "scratch limit" in str(e.value)
