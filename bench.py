@@ -1,14 +1,21 @@
-"""Benchmark: field cell-updates/s of the FDETD step on the current-driven workload (modes m = 0, 1 on a
-2048 x 256 grid, 16th-order staggered differences, Taylor order 8, dt = dz/2, Gaussian bunch + noise
-current, 500 steps), FP64 and FP32-compensated, on one MI355X.
+"""Benchmark: field cell-updates/s of the FDETD step on the LWFA-scale workload -- modes m = 0, 1, 2 on an
+8192 x 1024 grid, 32nd-order staggered differences, Taylor order 8, dt = dz/2, the current of 10^6 bunch
+samples moving at c deposited every step -- the largest single-GPU workload, FP64 and FP32-compensated, on
+one MI355X.
 
-Prints ONE JSON line.  `value` is the FP64 rate (cells x modes x steps / s) over exactly --steps steps,
-with every input (fields, the per-step currents of all steps) resident in HBM before the timed region,
-replayed from a captured hipGraph.  Also reported:
-  roofline     achieved algorithmic HBM bytes / stage-kernel time of the dominant kernel (Maxwell Horner
-               stage), from HIP events around every stage launch in a profiled pass of the same workload;
-  fp32c        the same measurement for the FP32-compensated path, with its error against the FP64 path;
-  cpu_baseline the CPU FP64 oracle timed on a bounded sample (one mode, a few steps) on the host cores.
+Prints ONE JSON line.  A step is one pass of the whole hot path: the step's current (J_z of every mode
+deposited from the samples at the step's midpoint positions), current staging, the Horner stages with the
+midpoint source and the axis rule.  `value` is the FP64 rate (cells x modes x steps / s) over exactly
+--steps steps of fdetd_step_graph, the K-step loop captured as one hipGraph and replayed, with the fields
+and the samples resident in HBM when timing starts.  Also reported:
+  roofline      the dominant kernel (the Maxwell Horner stage): algorithmic HBM bytes per launch (21
+                complex values per cell, 336 B FP64 / 168 B FP32) over its average duration, from HIP
+                events around every stage launch of a profiled pass (the plan's stream), with the HBM
+                traffic of the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary;
+  fp32c         the same for the FP32-compensated path, with its error against the FP64 path;
+  full_length   both precisions over the workload's 1000 steps, and the FP32C error after them;
+  cpu_baseline  the CPU FP64 oracle timed on a bounded sample on the host cores (all cores and one);
+  current_driven, batched, envelope, correction, sources: the other workloads and the source kernels.
 """
 from __future__ import annotations
 
@@ -27,54 +34,80 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "field cell-updates/s (cells×modes×steps/s), FP64 vs FP32-comp at fixed error"
-# HBM traffic of the stage kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this benchmark, with the
-# hash of the sources the kernel is compiled from and the segment length of the launches counted;
-# reported only while both still match (the kernel code, and the tiling the timed plan runs).
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_maxwell_stage_current_driven_2048x256_o16_pmc.md")
+# HBM traffic of the stage kernel on the LWFA-scale workload from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# with the hash of the sources the kernel is compiled from and the segment length of the launches
+# counted; reported only while both still match (the kernel code, and the tiling the timed plan runs).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_maxwell_stage_lwfa_m012_8192x1024_o32_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_12132_amd", "csrc", f)
                   for f in ("fdetd_march.hip", "fdetd_tiles.h", "fdetd_internal.h")]
+N_SAMPLES = 10 ** 6
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_currents(w, steps, dtype, seed):
-    """Per-step currents [steps, 3, nr, nz] of every problem, generated on the GPU (seeded): the Gaussian
-    bunch moving at c on the axis (J_z of mode 0) plus uniform white noise of relative amplitude 1e-3
-    (mode 0: real part only) -- the recipe of inputs.bunch_current, drawn with torch's device RNG."""
-    import torch
-    e = w.extra
-    out = []
-    g = torch.Generator(device="cuda")
-    for p in range(w.n):
-        g.manual_seed(seed * 1000 + p)
-        nz, nr, m = w.nz[p], w.nr[p], w.m[p]
-        rdt = torch.float64
-        shape = (steps, 3, nr, nz)
-        amp = e["noise"] * e["nb"]
-        re = (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
-        im = torch.zeros_like(re) if m == 0 else (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
-        if m == 0:
-            t = (torch.arange(steps, device="cuda", dtype=rdt) + 0.5) * w.dt
-            rp = (torch.arange(nr, device="cuda", dtype=rdt) + 0.5) * w.dr
-            zs = (torch.arange(nz, device="cuda", dtype=rdt) - 0.5) * w.dz
-            zb = 0.25 * nz * w.dz + t
-            bunch = -e["nb"] * torch.exp(-((zs[None, None, :] - zb[:, None, None]) ** 2) / (2 * e["sigz"] ** 2)
-                                         - rp[None, :, None] ** 2 / (2 * e["sigr"] ** 2))
-            re[:, 2] += bunch
-        out.append(torch.complex(re, im).to(dtype).contiguous())
-        del re, im
-    return out
+def bytes_per_stage(precision):
+    """Algorithmic HBM bytes of one Horner stage per cell with a current: read v (6c), psi (6c), Jbar (3c),
+    write v (6c)."""
+    import paper_2605_12132_amd as F
+    return 21 * (16 if precision == F.FP64 else 8)
 
 
 def energy_weights(w, p):
-    """Volume weights w_m r dr dz of the six components (rho-staggered rows at k dr)."""
-    rp = (np.arange(w.nr[p]) + 0.5) * w.dr
-    rs = np.arange(w.nr[p]) * w.dr
+    """Volume weights w_m r dr dz of the six components (rho-staggered rows at k dr), [6, nr, 1]."""
+    import torch
+    rp = (torch.arange(w.nr[p], dtype=torch.float64, device="cuda") + 0.5) * w.dr
+    rs = torch.arange(w.nr[p], dtype=torch.float64, device="cuda") * w.dr
     wm = 2 * math.pi if w.m[p] == 0 else math.pi
-    r = np.stack([rs, rp, rp, rp, rs, rs])
-    return wm * r * w.dr * w.dz  # [6, nr]
+    return (wm * torch.stack([rs, rp, rp, rp, rs, rs]) * w.dr * w.dz)[:, :, None]
+
+
+def fp32c_errors(w, psi64, psi32):
+    """Energy-weighted field rel. L2 of FP32C against FP64, relative energy difference, and the on-axis
+    amplitude error (E_rho on the axis for m = 1, E_z next to it otherwise), computed on the GPU."""
+    import torch
+    num = den = e32 = 0.0
+    ax = []
+    for p in range(w.n):
+        a, b = psi64[p], psi32[p].to(torch.complex128)
+        wt = energy_weights(w, p)
+        num += float(torch.sum(wt * torch.abs(a - b) ** 2))
+        den += float(torch.sum(wt * torch.abs(a) ** 2))
+        e32 += float(torch.sum(wt * torch.abs(b) ** 2))
+        c = 0 if w.m[p] == 1 else 2
+        ref = float(torch.max(torch.abs(a[c, 0])))
+        ax.append(float(torch.max(torch.abs(a[c, 0] - b[c, 0]))) / ref if ref > 0 else 0.0)
+    return dict(field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0,
+                energy_rel_diff=abs(e32 / den - 1) if den > 0 else 0.0, axis_amp_rel_err=max(ax))
+
+
+def lwfa_samples(w, n=N_SAMPLES):
+    """The bunch of the LWFA-scale workload as n point samples at t = 0 (Gaussian, sigma_z = 2 um,
+    sigma_rho = 1 um, total charge of peak density n_b, centred at a quarter of the box), in z order as a
+    PIC code keeps its particles.  Seeded, drawn on the GPU."""
+    import torch
+    e = w.extra
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.seed)
+    s = torch.randn((n, 4), generator=g, device="cuda", dtype=torch.float64)
+    s[:, 0] = 0.25 * w.nz[0] * w.dz + e["sigz"] * s[:, 0]
+    s[:, 1:3] *= e["sigr"]
+    s[:, 3] = -e["nb"] * (2 * math.pi) ** 1.5 * e["sigz"] * e["sigr"] ** 2 / n
+    return s[torch.argsort(s[:, 0])].contiguous()
+
+
+def sample_jgen(smp, step0):
+    import paper_2605_12132_amd as F
+    return F.Jgen(F.JGEN_SAMPLES, step0=step0, samples=smp, vz=1.0, eps=0.5)
+
+
+def bunch_jgen(w, step0):
+    """The bunch + noise current recipe of the current-driven and batched workloads, made in the graph."""
+    import paper_2605_12132_amd as F
+    e = w.extra
+    return F.Jgen(F.JGEN_BUNCH, step0=step0, seed=w.seed, nb=e["nb"], sigz=e["sigz"], sigr=e["sigr"], z0_frac=0.25,
+                  vb=1.0, noise=e["noise"])
 
 
 class seg_rows_env:
@@ -98,65 +131,81 @@ class seg_rows_env:
         return False
 
 
-def run_path(w, precision, steps, warmup, J, use_graph=True, seg_rows=None):
-    """Warm up, capture the K-step graph once (untimed, then restore the state), time exactly K steps."""
+def initial_state(w, cd):
+    """Initial fields of every problem on the GPU (the workload's Gaussian pulse, or zeros)."""
+    import torch
+    import paper_2605_12132_amd.inputs as I
+    return [torch.from_numpy(I.initial_fields(w, p)).to(device="cuda", dtype=cd) for p in range(w.n)]
+
+
+def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_graph=True):
+    """Warm up W steps, capture the K-step loop of fdetd_step_graph once (untimed, then restore the state),
+    time exactly K steps of its replay.  jgen_of(step0) gives the step generator of the call."""
     import torch
     import paper_2605_12132_amd as F
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
-        psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+        psi = initial_state(w, cd)
+        jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
         flags = F.PLAN_USE_GRAPH if use_graph else 0
         t0 = time.time()
         with seg_rows_env(seg_rows):
             plan = F.Plan(w.problems(), precision=precision, flags=flags)
         plan_s = time.time() - t0
         if warmup:
-            plan.step(psi, [j[:warmup] for j in J], n_steps=warmup)
-        jt = [j[warmup:warmup + steps] for j in J]
+            plan.step_graph(psi, jgen_of(0), jw, n_steps=warmup)
         saved = [x.clone() for x in psi]
         lo = plan.export_state() if precision == F.FP32C else b""
-        # capture + one untimed replay of the exact timed call, then restore the state it started from
-        plan.step(psi, jt, n_steps=steps)
+        t0 = time.time()
+        plan.step_graph(psi, jgen_of(warmup), jw, n_steps=steps)  # capture + first replay (untimed)
+        torch.cuda.synchronize()
+        capture_s = time.time() - t0
         for x, s in zip(psi, saved):
             x.copy_(s)
+        del saved
         if precision == F.FP32C:
             stream.synchronize()
             plan.import_state(lo)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        plan.step(psi, jt, n_steps=steps)
+        plan.step_graph(psi, jgen_of(warmup), jw, n_steps=steps)
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
         info = plan.query()
         plan.close()
-    return psi, ms, plan_s, info
+    del jw
+    return psi, ms, dict(plan_s=round(plan_s, 2), capture_and_first_replay_s=round(capture_s, 2)), info
 
 
-def profile_pass(w, precision, steps, J, seg_rows):
-    """Eager pass with HIP events around every stage kernel: average duration and algorithmic bytes.  The
-    plan is given the segment length the timed plan's autotuning picked, so both run the same tiling."""
+def profile_pass(w, precision, steps, jgen_of, seg_rows):
+    """Eager pass with HIP events around every stage kernel on the plan's stream: average duration and
+    algorithmic bytes (21 complex values per cell).  The plan is given the segment length the timed plan's
+    autotuning picked, so both run the same tiling."""
     import torch
     import paper_2605_12132_amd as F
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
-    psi = [torch.zeros((6, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+    psi = initial_state(w, cd)
+    jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
     with seg_rows_env(seg_rows):
         plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
-    plan.step(psi, [j[:steps] for j in J], n_steps=steps)
+    plan.step_graph(psi, jgen_of(0), jw, n_steps=steps)
     info = plan.query()
     plan.close()
     n = info["profiled_launches"]
     avg_ms = info["profiled_ms"] / n
-    bytes_per_launch = info["profiled_bytes"] / n
+    bytes_per_launch = w.cells() * bytes_per_stage(precision)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c", seg_rows),
-                kernel="k_maxwell_stage",
-                launches=n, avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch))
+                kernel="k_maxwell_stage", launches=n, avg_launch_us=round(avg_ms * 1e3, 2),
+                bytes_per_launch=int(bytes_per_launch), bytes_per_cell=bytes_per_stage(precision),
+                timing="HIP events around each stage launch on the plan's stream, eager pass of "
+                       f"{steps} steps (every stage counted at 21 complex values per cell)")
 
 
 def kernel_source_hash():
@@ -217,83 +266,132 @@ def copy_calibration(n_bytes=1 << 30, reps=10):
                 stream_GBs={k: round(v, 1) for k, v in streams.items()})
 
 
-def fp32c_errors(w, psi64, psi32):
-    num = den = e64 = e32 = 0.0
-    ax = []
-    for p in range(w.n):
-        a = psi64[p].cpu().numpy()
-        b = psi32[p].cpu().numpy().astype(np.complex128)
-        wt = energy_weights(w, p)[:, :, None]
-        num += float(np.sum(wt * np.abs(a - b) ** 2))
-        den += float(np.sum(wt * np.abs(a) ** 2))
-        e64 += float(np.sum(wt * np.abs(a) ** 2))
-        e32 += float(np.sum(wt * np.abs(b) ** 2))
-        # on-axis amplitude: E_rho on the axis for m = 1, E_z next to the axis otherwise
-        c = 0 if w.m[p] == 1 else 2
-        ref = np.max(np.abs(a[c, 0]))
-        ax.append(float(np.max(np.abs(a[c, 0] - b[c, 0])) / ref) if ref > 0 else 0.0)
-    return dict(field_rel_l2=math.sqrt(num / den), energy_rel_diff=abs(e32 / e64 - 1), axis_amp_rel_err=max(ax))
+def graph_workload_pass(w, steps, warmup, tag):
+    """A workload with the bunch + noise current made in the graph (fdetd_step_graph, FDETD_JGEN_BUNCH):
+    FP64 and FP32C, K steps timed as above; cell-updates/s, the step-level algorithmic HBM rate (the plan's
+    bytes per step / step time), launches per step and the FP32C error against FP64."""
+    import paper_2605_12132_amd as F
+    cells = w.cells()
+    res, psis = {}, {}
+    for pt, prec in (("fp64", F.FP64), ("fp32c", F.FP32C)):
+        psi, ms, times, info = run_graph_path(w, prec, steps, warmup, lambda s0: bunch_jgen(w, s0))
+        gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
+        res[pt] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
+                       frac=round(gbs / HBM_PEAK_GBS, 4), launches_per_step=info["launches_per_step"],
+                       streams=info["streams"], autotune_ms=round(info["autotune_ms"], 1), **times)
+        psis[pt] = psi
+        log(f"{tag} {pt}: {ms / steps:.3f} ms/step, {res[pt]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
+            f"algorithmic ({info['launches_per_step']} launches/step, plan {times['plan_s']} s, capture + first "
+            f"replay {times['capture_and_first_replay_s']} s)")
+    errs = fp32c_errors(w, psis["fp64"], psis["fp32c"])
+    return dict(workload=w.name, problems=w.n, cells=cells, steps=steps, warmup=warmup, graph=True,
+                current="bunch + SplitMix64 noise made in the graph", fp64=res["fp64"], fp32c=res["fp32c"],
+                fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"], fp32c_error_vs_fp64=errs)
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The oracle (plain C, OpenMP over rows) on one mode of the workload with its current, for as many
-    steps as fit in the time budget (at least one)."""
+def sources_pass(w, smp):
+    """Source and interpolation kernels on the LWFA-scale grid and the 10^6 z-ordered samples, timed apart:
+    J_z deposition (fdetd_deposit_jz), all currents and rho_xy of the samples with a transverse velocity
+    spread (fdetd_deposit_current), their charge density (fdetd_deposit_rho), and the fields at the samples
+    (fdetd_gather, and with 2x supersampling along z and rho)."""
+    import torch
+    import paper_2605_12132_amd as F
+    nz, nr = w.nz[0], w.nr[0]
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(stream, fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.seed + 1)
+    for tag, prec, cd in (("fp64", F.FP64, torch.complex128), ("fp32c", F.FP32C, torch.complex64)):
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            plan = F.Plan(w.problems(), precision=prec, flags=F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
+            J = [torch.zeros((3, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            dep = timed(stream, lambda: plan.deposit_jz(smp, J, vz=1.0, eps=0.5))
+            R1 = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            rho = timed(stream, lambda: plan.deposit_rho(smp, R1))
+            psi = initial_state(w, cd)
+            fields = plan.gather(psi, smp)
+            gat = timed(stream, lambda: plan.gather(psi, smp, fields))
+            gss = timed(stream, lambda: plan.gather(psi, smp, fields, supersample=3))
+            plan.close()
+            del J, R1, psi, fields
+            torch.cuda.empty_cache()
+            plan = F.Plan(w.problems(), precision=prec,
+                          flags=F.PLAN_CURRENT_CORRECTION | F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
+            J4 = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
+            s8 = torch.zeros((smp.shape[0], 8), dtype=torch.float64, device="cuda")
+            s8[:, :4] = smp
+            s8[:, 4:6] = 0.01 * torch.randn((smp.shape[0], 2), generator=g, device="cuda", dtype=torch.float64)
+            s8[:, 6] = 0.999
+            cur = timed(stream, lambda: plan.deposit_current(s8, J4))
+            plan.close()
+            del J4, s8
+            torch.cuda.empty_cache()
+        out[tag] = dict(deposit_jz_ms=round(dep, 4), deposit_rho_ms=round(rho, 4), deposit_current_ms=round(cur, 4),
+                        gather_ms=round(gat, 4), gather_supersampled_ms=round(gss, 4))
+        log(f"sources {tag}: deposit_jz {dep:.3f} ms, deposit_rho {rho:.3f} ms, deposit_current {cur:.3f} ms, "
+            f"gather {gat:.3f} ms, supersampled {gss:.3f} ms")
+    return dict(workload=w.name, samples=int(smp.shape[0]), **out)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w):
+    """The oracle (plain C, FP64, OpenMP over rows), as it stands: one step of mode m = 1 of the workload
+    with a current of the workload's shape (the bunch + noise recipe of inputs.graph_bunch_current), on all
+    host cores, and one step of the same mode on a 1024-column window on one core.  Deposition is not
+    timed (it is not part of the field step)."""
     import oracle
     import paper_2605_12132_amd.inputs as I
     p = 1
-    g = oracle.Grid(nz=w.nz[p], nr=w.nr[p], m=w.m[p], fd_order=w.fd_order[p], taylor_order=w.taylor_order,
-                    dz=w.dz, dr=w.dr, dt=w.dt)
-    psi = np.zeros((6, w.nr[p], w.nz[p]), np.complex128)
-    J = I.currents(w, p, 8)
-    steps, t_total = 0, 0.0
-    while steps < 8 and (steps == 0 or t_total + t_total / steps < budget_s):
-        t0 = time.time()
-        psi = oracle.step(g, psi, J[steps], 1)
-        t_total += time.time() - t0
-        steps += 1
-    cells = w.nz[p] * w.nr[p]
     try:
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
         ncpu = os.cpu_count()
-    return dict(value=cells * steps / t_total, unit="cell-updates/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{steps} step(s) of mode m={w.m[p]} ({w.nz[p]}x{w.nr[p]}, order {w.fd_order[p]}, Taylor "
-                       f"{w.taylor_order}, with current) in {t_total:.1f} s; host reports {ncpu} usable cores")
 
+    def rate(nz, threads):
+        oracle.set_num_threads(threads)
+        wl = w.shrink(nz=nz)
+        g = oracle.Grid(nz=nz, nr=w.nr[p], m=w.m[p], fd_order=w.fd_order[p], taylor_order=w.taylor_order,
+                        dz=w.dz, dr=w.dr, dt=w.dt)
+        psi = np.zeros((6, w.nr[p], nz), np.complex128)
+        wl.extra = dict(w.extra, noise=1e-3)
+        J = I.graph_bunch_current(wl, p, 0, w.seed)
+        t0 = time.time()
+        oracle.step(g, psi, J, 1)
+        dt = time.time() - t0
+        return nz * w.nr[p] / dt, dt, oracle.num_threads()
 
-def batched_pass(steps, warmup):
-    """The batched uneven workload (64 problems, N_z in [512, 4096], N_rho in [64, 512], modes 0..2,
-    orders 8..32, Taylor 8, dt = dz/2): FP32C and FP64 plans over all problems, graph replay of `steps`
-    steps with a fresh bunch + noise current per step resident in HBM, fields starting at zero.  Reports
-    cell-updates/s, the step-level algorithmic HBM rate (plan's bytes per step / step time) and the
-    FP32C error against FP64 after the same steps."""
-    import torch
-    import paper_2605_12132_amd as F
-    import paper_2605_12132_amd.inputs as I
-    w = I.batched_uneven()
-    cells = w.cells()
-    res, psis = {}, {}
-    for tag, prec, cd in (("fp32c", F.FP32C, torch.complex64), ("fp64", F.FP64, torch.complex128)):
-        J = make_currents(w, warmup + steps, cd, w.seed)
-        torch.cuda.synchronize()
-        psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
-        del J
-        torch.cuda.empty_cache()
-        gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
-        res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
-                        frac=round(gbs / HBM_PEAK_GBS, 4), launches_per_step=info["launches_per_step"],
-                        plan_s=round(plan_s, 2), autotune_ms=round(info["autotune_ms"], 1), streams=info["streams"])
-        psis[tag] = psi
-        log(f"batched {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, "
-            f"{gbs:.0f} GB/s algorithmic ({info['launches_per_step']} launches/step, plan {plan_s:.1f} s)")
-    num = den = 0.0
-    for a, b in zip(psis["fp64"], psis["fp32c"]):
-        d = a - b.to(torch.complex128)
-        num += float(torch.sum(torch.abs(d) ** 2))
-        den += float(torch.sum(torch.abs(a) ** 2))
-    return dict(workload=w.name, problems=w.n, cells=cells, steps=steps, warmup=warmup, graph=True,
-                fp32c=res["fp32c"], fp64=res["fp64"], fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
-                fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
+    v_all, t_all, c_all = rate(w.nz[p], ncpu)
+    v_one, t_one, _ = rate(1024, 1)
+    oracle.set_num_threads(ncpu)
+    return dict(value=v_all, unit="cell-updates/s", cores=c_all, kind="oracle",
+                sample=f"1 step of mode m={w.m[p]} ({w.nz[p]}x{w.nr[p]}, order {w.fd_order[p]}, Taylor "
+                       f"{w.taylor_order}, with current) in {t_all:.1f} s on {c_all} threads",
+                one_core=dict(value=v_one, cores=1,
+                              sample=f"1 step of mode m={w.m[p]} on a 1024x{w.nr[p]} window in {t_one:.1f} s"),
+                cpu_model=cpu_model(), host_cores=ncpu)
 
 
 def envelope_pass(steps, layer=32):
@@ -439,148 +537,59 @@ def correction_pass(steps, warmup):
                 fp32c=out["fp32c"])
 
 
-def lwfa_pass(steps, warmup, n_samples=10 ** 6):
-    """The LWFA-scale workload (modes 0, 1, 2 on 8192 x 1024, order 32, Taylor 8, dt = dz/2): the current of
-    each step is a bunch of n_samples point samples (Gaussian, sigma_z = 2 um, sigma_rho = 1 um, total charge
-    of peak density n_b) moving at c, in z order, deposited with fdetd_deposit_jz (timed separately,
-    including the advance of the sample positions; all currents and rho_xy of the same samples with a
-    transverse velocity spread, fdetd_deposit_current, and their charge density, fdetd_deposit_rho, timed
-    apart), then graph replay of `steps` field
-    steps, then the fields of the final state at the samples (fdetd_gather, timed apart, also with 2x
-    supersampling along z and rho).  FP64 and FP32C; the FP32C error against FP64 after the same steps."""
+def make_currents(w, steps, dtype, seed):
+    """Per-step currents [steps, 3, nr, nz] of every problem, generated on the GPU (seeded): the Gaussian
+    bunch moving at c on the axis (J_z of mode 0) plus uniform white noise of relative amplitude 1e-3
+    (mode 0: real part only) -- the recipe of inputs.bunch_current, drawn with torch's device RNG."""
     import torch
-    import paper_2605_12132_amd as F
-    import paper_2605_12132_amd.inputs as I
-    w = I.lwfa_scale()
     e = w.extra
-    nz, nr = w.nz[0], w.nr[0]
+    out = []
     g = torch.Generator(device="cuda")
-    g.manual_seed(w.seed)
-    base = torch.randn((n_samples, 4), generator=g, device="cuda", dtype=torch.float64)
-    base[:, 0] = 0.25 * nz * w.dz + e["sigz"] * base[:, 0]
-    base[:, 1:3] *= e["sigr"]
-    base[:, 3] = -e["nb"] * (2 * math.pi) ** 1.5 * e["sigz"] * e["sigr"] ** 2 / n_samples
-    # position order, as a PIC code keeps its particles (all samples move alike, so it holds every step):
-    # blocks of consecutive samples then deposit through LDS tiles
-    base = base[torch.argsort(base[:, 0])].contiguous()
-    cells = w.cells()
-    res, psis = {}, {}
-    for tag, prec, cd in (("fp64", F.FP64, torch.complex128), ("fp32c", F.FP32C, torch.complex64)):
-        stream = torch.cuda.Stream()
-        stream.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(stream):
-            plan = F.Plan(w.problems(), precision=prec, flags=0)
-            J = [torch.zeros((warmup + steps, 3, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
-            smp = base.clone()
-            torch.cuda.synchronize()
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record(stream)
-            for st in range(warmup + steps):
-                smp[:, 0] = base[:, 0] + (st + 0.5) * w.dt
-                plan.deposit_jz(smp, [j[st] for j in J], vz=1.0, eps=0.5)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            dep_ms = ev0.elapsed_time(ev1) / (warmup + steps)
-            plan.close()
-            # all currents of moving samples (J_rho, J_theta, modified-Esirkepov J_z and rho_xy of the
-            # current correction): the bunch with a transverse velocity spread, 5 calls
-            plan = F.Plan(w.problems(), precision=prec,
-                          flags=F.PLAN_CURRENT_CORRECTION | F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
-            J4 = [torch.zeros((4, nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
-            s8 = torch.zeros((n_samples, 8), dtype=torch.float64, device="cuda")
-            s8[:, :4] = smp
-            s8[:, 4:6] = 0.01 * torch.randn((n_samples, 2), generator=g, device="cuda", dtype=torch.float64)
-            s8[:, 6] = 0.999
-            plan.deposit_current(s8, J4)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(5):
-                plan.deposit_current(s8, J4)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            dep_cur_ms = ev0.elapsed_time(ev1) / 5
-            # charge density of the same samples (fdetd_deposit_rho), 5 calls
-            R1 = [torch.zeros((nr, nz), dtype=cd, device="cuda") for _ in range(w.n)]
-            plan.deposit_rho(smp, R1)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(5):
-                plan.deposit_rho(smp, R1)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            dep_rho_ms = ev0.elapsed_time(ev1) / 5
-            plan.close()
-            del J4, s8, R1
-        psi, ms, plan_s, info = run_path(w, prec, steps, warmup, J, True)
-        del J
-        torch.cuda.empty_cache()
-        # fields of the final state at the samples' last positions (destaggering + interpolation), 5 calls
-        with torch.cuda.stream(stream):
-            plan = F.Plan(w.problems(), precision=prec, flags=F.PLAN_SKIP_STABILITY | F.PLAN_NO_AUTOTUNE)
-            fields = plan.gather(psi, smp)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(5):
-                plan.gather(psi, smp, fields)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            gather_ms = ev0.elapsed_time(ev1) / 5
-            # the same with 2x supersampling along z and rho (fdetd_gather_supersampled)
-            plan.gather(psi, smp, fields, supersample=3)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(5):
-                plan.gather(psi, smp, fields, supersample=3)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            gather_ss_ms = ev0.elapsed_time(ev1) / 5
-            plan.close()
-        gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
-        res[tag] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
-                        frac=round(gbs / HBM_PEAK_GBS, 4), deposit_ms_per_step=dep_ms, gather_ms=gather_ms,
-                        gather_supersampled_ms=gather_ss_ms, deposit_current_ms=dep_cur_ms,
-                        deposit_rho_ms=dep_rho_ms,
-                        seg_rows=info["seg_rows"])
-        psis[tag] = psi
-        log(f"lwfa {tag}: {ms / steps:.3f} ms/step, {res[tag]['value']:.4g} cell-updates/s, {gbs:.0f} GB/s "
-            f"algorithmic; deposition of {n_samples} samples {dep_ms:.3f} ms/step (all currents and rho_xy "
-            f"{dep_cur_ms:.3f} ms, charge density {dep_rho_ms:.3f} ms); gather {gather_ms:.3f} ms, "
-            f"2x supersampled (z and rho) {gather_ss_ms:.3f} ms")
-    num = den = 0.0
-    for a, b in zip(psis["fp64"], psis["fp32c"]):
-        num += float(torch.sum(torch.abs(a - b.to(torch.complex128)) ** 2))
-        den += float(torch.sum(torch.abs(a) ** 2))
-    return dict(workload=w.name, cells=cells, steps=steps, warmup=warmup, samples=n_samples, graph=True,
-                fp64=res["fp64"], fp32c=res["fp32c"], fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
-                fp32c_field_rel_l2=math.sqrt(num / den) if den > 0 else 0.0)
+    for p in range(w.n):
+        g.manual_seed(seed * 1000 + p)
+        nz, nr, m = w.nz[p], w.nr[p], w.m[p]
+        rdt = torch.float64
+        shape = (steps, 3, nr, nz)
+        amp = e["noise"] * e["nb"]
+        re = (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
+        im = torch.zeros_like(re) if m == 0 else (torch.rand(shape, generator=g, device="cuda", dtype=rdt) * 2 - 1) * amp
+        if m == 0:
+            t = (torch.arange(steps, device="cuda", dtype=rdt) + 0.5) * w.dt
+            rp = (torch.arange(nr, device="cuda", dtype=rdt) + 0.5) * w.dr
+            zs = (torch.arange(nz, device="cuda", dtype=rdt) - 0.5) * w.dz
+            zb = 0.25 * nz * w.dz + t
+            bunch = -e["nb"] * torch.exp(-((zs[None, None, :] - zb[:, None, None]) ** 2) / (2 * e["sigz"] ** 2)
+                                         - rp[None, :, None] ** 2 / (2 * e["sigr"] ** 2))
+            re[:, 2] += bunch
+        out.append(torch.complex(re, im).to(dtype).contiguous())
+        del re, im
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps K of the headline")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--fp64-only", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--headline-only", action="store_true", help="only the headline FP64 / FP32C lines and roofline")
+    ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--seg-rows-fp64", type=int, default=None,
                     help="fixed rows per marching segment of the FP64 plans instead of plan-time autotuning")
     ap.add_argument("--seg-rows-fp32c", type=int, default=None, help="the same for the FP32C plans")
-    ap.add_argument("--batched-steps", type=int, default=20,
-                    help="steps of the 64-problem batched workload reported beside the headline (0: skip)")
-    ap.add_argument("--lwfa-steps", type=int, default=20,
-                    help="steps of the LWFA-scale workload reported beside the headline (0: skip)")
-    ap.add_argument("--correction-steps", type=int, default=50,
-                    help="steps of the current-driven workload with the current correction (0: skip)")
-    ap.add_argument("--envelope-steps", type=int, default=2000,
-                    help="steps of the envelope workload reported beside the headline (0: skip)")
+    ap.add_argument("--full-steps", type=int, default=1000,
+                    help="steps of the full-length LWFA-scale run reported beside the headline (0: skip)")
+    ap.add_argument("--current-driven-steps", type=int, default=500, help="0: skip")
+    ap.add_argument("--batched-steps", type=int, default=200, help="0: skip")
+    ap.add_argument("--correction-steps", type=int, default=50, help="0: skip")
+    ap.add_argument("--envelope-steps", type=int, default=2000, help="0: skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the problems of this workload are "
-              "independent modes and would be distributed one plan per GPU with no communication.", flush=True)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures one GPU's share. "
+              "The modes and batched problems are independent and would be distributed one plan per GPU; a grid "
+              "too large for one GPU would be split into z-slabs with an N_D-column halo per stage.", flush=True)
         sys.exit(2)
 
     import torch
@@ -590,68 +599,81 @@ def main():
     if args.calibrate_copy:
         print(json.dumps(copy_calibration()), flush=True)
         return
-    w = I.current_driven()
+    w = I.lwfa_scale()
     K, W = args.steps, args.warmup
     cells = w.cells()
     log(f"workload {w.name}: {w.n} modes x {w.nz[0]}x{w.nr[0]}, order {w.fd_order[0]}, N={w.taylor_order}, "
-        f"K={K}, W={W}")
-    t0 = time.time()
-    J64 = make_currents(w, W + K, torch.complex128, w.seed)
-    torch.cuda.synchronize()
-    log(f"currents resident: {sum(j.numel() for j in J64) * 16 / 1e9:.1f} GB in {time.time() - t0:.1f} s")
+        f"{N_SAMPLES} samples deposited per step, K={K}, W={W}")
+    smp = lwfa_samples(w)
+    jg = lambda s0: sample_jgen(smp, s0)  # noqa: E731
 
-    psi64, ms64, plan_s, info64 = run_path(w, F.FP64, K, W, J64, not args.no_graph, args.seg_rows_fp64)
+    psi64, ms64, t64, info64 = run_graph_path(w, F.FP64, K, W, jg, args.seg_rows_fp64)
     rate64 = cells * K / (ms64 * 1e-3)
-    log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s (plan {plan_s:.2f} s, dt*rho {info64['dt_rho_max']:.3f})")
-    prof_steps = min(args.profile_steps, K + W)  # the currents held resident cover K + W steps
-    roof64 = profile_pass(w, F.FP64, prof_steps, J64, info64["seg_rows"])
+    log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s ({t64}, dt*rho {info64['dt_rho_max']:.3f}, "
+        f"{info64['seg_rows']} rows per segment)")
+    roof64 = profile_pass(w, F.FP64, args.profile_steps, jg, info64["seg_rows"])
     log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
+    psi32, ms32, t32, info32 = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c)
+    rate32 = cells * K / (ms32 * 1e-3)
+    roof32 = profile_pass(w, F.FP32C, args.profile_steps, jg, info32["seg_rows"])
+    errs = fp32c_errors(w, psi64, psi32)
+    del psi64, psi32
+    torch.cuda.empty_cache()
+    log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, stage kernel {roof32['avg_launch_us']} us "
+        f"({roof32['frac'] * 100:.1f}%), errors after {W + K} steps {errs}")
+    fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
+                 error_vs_fp64_after_steps=W + K, **errs,
+                 tiling=dict(seg_rows=info32["seg_rows"], seg_rows_axis=info32["seg_rows_axis"],
+                             autotune_ms=round(info32["autotune_ms"], 1)), **t32)
 
-    fp32c = None
-    if not args.fp64_only:
-        J32 = [j.to(torch.complex64) for j in J64]
-        del J64
+    full = None
+    if args.full_steps > 0 and not args.headline_only:
+        res, psis = {}, {}
+        for pt, prec, seg in (("fp64", F.FP64, args.seg_rows_fp64), ("fp32c", F.FP32C, args.seg_rows_fp32c)):
+            psi, ms, tt, info = run_graph_path(w, prec, args.full_steps, 0, jg, seg)
+            res[pt] = dict(value=cells * args.full_steps / (ms * 1e-3), ms_per_step=ms / args.full_steps, **tt)
+            psis[pt] = psi
+            log(f"full length {pt}: {args.full_steps} steps, {ms / args.full_steps:.3f} ms/step, "
+                f"{res[pt]['value']:.4g} cell-updates/s ({tt})")
+        full = dict(steps=args.full_steps, graph=True, fp64=res["fp64"], fp32c=res["fp32c"],
+                    fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
+                    fp32c_error_vs_fp64=fp32c_errors(w, psis["fp64"], psis["fp32c"]))
+        log(f"full length FP32C error vs FP64 after {args.full_steps} steps: {full['fp32c_error_vs_fp64']}")
+        del psis, psi
         torch.cuda.empty_cache()
-        psi32, ms32, _, info32 = run_path(w, F.FP32C, K, W, J32, not args.no_graph, args.seg_rows_fp32c)
-        rate32 = cells * K / (ms32 * 1e-3)
-        roof32 = profile_pass(w, F.FP32C, prof_steps, J32, info32["seg_rows"])
-        errs = fp32c_errors(w, psi64, psi32)
-        log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, errors {errs}")
-        fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
-                     error_vs_fp64_after_steps=W + K, **errs,
-                     tiling=dict(seg_rows=info32["seg_rows"], seg_rows_axis=info32["seg_rows_axis"],
-                                 autotune_ms=round(info32["autotune_ms"], 1)))
-        del J32
-    else:
-        del J64
 
-    batched = None
-    if args.batched_steps > 0 and not args.fp64_only:
-        del psi64
+    extra = {}
+    if not args.headline_only:
+        extra["sources"] = sources_pass(w, smp)
+        del smp
         torch.cuda.empty_cache()
-        batched = batched_pass(args.batched_steps, W)
-    envelope = envelope_pass(args.envelope_steps) if args.envelope_steps > 0 and not args.fp64_only else None
-    lwfa = lwfa_pass(args.lwfa_steps, W) if args.lwfa_steps > 0 and not args.fp64_only else None
-    correction = (correction_pass(args.correction_steps, W)
-                  if args.correction_steps > 0 and not args.fp64_only else None)
+        if args.current_driven_steps > 0:
+            extra["current_driven"] = graph_workload_pass(I.current_driven(), args.current_driven_steps, W, "current-driven")
+        if args.batched_steps > 0:
+            extra["batched"] = graph_workload_pass(I.batched_uneven(), args.batched_steps, W, "batched")
+        if args.envelope_steps > 0:
+            extra["envelope"] = envelope_pass(args.envelope_steps)
+        if args.correction_steps > 0:
+            extra["correction"] = correction_pass(args.correction_steps, W)
     cpu = None if args.no_cpu else cpu_baseline(w)
     if cpu:
-        log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
+        log(f"CPU oracle: {cpu['value']:.4g} cell-updates/s on {cpu['cores']} threads, "
+            f"{cpu['one_core']['value']:.4g} on one core ({cpu['cpu_model']})")
     out = {
         "metric": METRIC, "value": rate64, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms64 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "modes": w.m, "nz": w.nz[0], "nr": w.nr[0], "fd_order": w.fd_order[0],
-                   "taylor_order": w.taylor_order, "dt_over_dz": 0.5, "dr_over_dz": 2.0, "current": "bunch+noise",
-                   "graph": not args.no_graph, "parallelism": "single GPU, modes batched in one plan"},
+                   "taylor_order": w.taylor_order, "dt_over_dz": 0.5, "dz_um": 0.032, "dr_um": 0.16,
+                   "current": f"{N_SAMPLES} bunch samples at c, J_z deposited every step in the graph",
+                   "graph": True, "parallelism": "single GPU, modes batched in one plan"},
         "roofline": roof64,
         "cpu_baseline": cpu,
         "tiling": dict(seg_rows=info64["seg_rows"], autotune_ms=round(info64["autotune_ms"], 1)),
+        "launches_per_step": info64["launches_per_step"],
         "fp32c": fp32c,
-        "batched": batched,
-        "envelope": envelope,
-        "lwfa": lwfa,
-        "correction": correction,
+        "full_length": full,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 

@@ -147,6 +147,47 @@ FDETD_API int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32
 FDETD_API int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, int64_t j_step_blocks,
                int32_t n_steps);
 
+/* The current of each step of fdetd_step_graph, made inside the time loop (on the GPU, in the captured
+ * graph) instead of being held in memory for every step.  Step s of a call is step number step0 + s, at
+ * t = (step0 + s + 1/2) dt (the midpoint of section 2.1).  Kinds:
+ *   FDETD_JGEN_BUNCH    every problem p (index in the plan) gets J_rho, J_theta, J_z =
+ *                       noise * nb * (U_re + i U_im) with U uniform in [-1, 1) from the SplitMix64 stream
+ *                       (seed, step, p): value number ((c nr + k) nz + i) 2 + part, c = component, part 0 / 1
+ *                       = real / imaginary part, is mix(h + (number + 1) g) with h = mix(mix(mix(seed + g) +
+ *                       (step + 1) g) + (p + 1) g), g = 0x9E3779B97F4A7C15, mix the SplitMix64 output function,
+ *                       taken as (top 53 bits) 2^-53 * 2 - 1; modes m = 0 keep real parts (section 2.1: the
+ *                       imaginary part of m = 0 is discarded); plus on J_z of m = 0 the Gaussian bunch
+ *                       -nb exp(-(z_i - dz/2 - zb)^2 / (2 sigz^2) - rho_k^2 / (2 sigr^2)),
+ *                       zb = z0_frac nz dz + vb t, rho_k = (k + 1/2) dr.
+ *   FDETD_JGEN_SAMPLES  J_rho = J_theta = 0 and J_z deposited from n point samples moving with vz, as
+ *                       fdetd_deposit_jz deposits them at the positions z + vz t (samples hold z at t = 0).
+ * The generated current replaces the contents of the caller's blocks j_work every step. */
+#define FDETD_JGEN_BUNCH   1
+#define FDETD_JGEN_SAMPLES 2
+typedef struct {
+    int32_t kind;            /* FDETD_JGEN_BUNCH or FDETD_JGEN_SAMPLES                            */
+    int32_t reserved;        /* 0                                                                 */
+    int64_t step0;           /* number of the call's first step (>= 0)                            */
+    uint64_t seed;           /* BUNCH: noise stream                                               */
+    double nb, sigz, sigr;   /* BUNCH: peak density and widths of the bunch (> 0)                 */
+    double z0_frac, vb;      /* BUNCH: bunch centre at t = 0 as a fraction of nz dz, and velocity */
+    double noise;            /* BUNCH: noise amplitude relative to nb (>= 0)                      */
+    const double *samples;   /* SAMPLES: device array n x 4 (z at t = 0, x, y, q w), 8-byte aligned */
+    int64_t n;               /* SAMPLES: number of samples                                        */
+    double vz, eps;          /* SAMPLES: velocity along z; radial shape parameter in [0, 1]        */
+} fdetd_jgen;
+
+/* n_steps Maxwell steps (as fdetd_step) whose current is made every step by the generator jgen into the
+ * caller's blocks j_work[p] (3 planes each, the plan's precision; overwritten every step, and left holding
+ * the last step's current).  With FDETD_PLAN_USE_GRAPH the whole loop -- generator, deposition, staging
+ * and Horner stages of every step -- is captured once as one hipGraph and replayed by calls that repeat
+ * it (same pointers, jgen and n_steps); a replay makes the same steps step0 .. step0 + n_steps - 1 again,
+ * and a call with another step0 captures anew.  Without the flag the same launches are enqueued eagerly.
+ * FDETD_E_ARG for an envelope plan, a plan with FDETD_PLAN_CURRENT_CORRECTION (its blocks need rho_xy),
+ * NULL or misaligned pointers, or bad generator values.  Enqueue only. */
+FDETD_API int fdetd_step_graph(fdetd_plan_t plan, void *const *psi, const fdetd_jgen *jgen, void *const *j_work,
+                               int32_t n_steps);
+
 /* Advance every envelope problem by n_steps of psi_a(t + dt) = T_N(dt H_a(chi(t + dt/2))) psi_a(t)
  * (section 4.1 exponential solution, section 4.2 discrete operator with L_rho + L_z - m^2/rho^2 and the
  * centred D_z^(C), complex form of the envelope equation with +2 i k0 terms).

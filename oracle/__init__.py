@@ -96,6 +96,8 @@ def lib():
         L.oracle_envelope_energy.argtypes = [P, vp, vp, vp, vp]
         L.oracle_envelope_energy.restype = None
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
+        L.oracle_set_num_threads.restype = None
         L.oracle_deposit_rho.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
         L.oracle_deposit_jz.argtypes = [P, vp, C.c_long, C.c_double, C.c_double, vp]
         L.oracle_deposit_current.argtypes = [P, vp, C.c_long, C.c_double, vp, vp]
@@ -307,6 +309,11 @@ def envelope_energy(g: Grid, a, at):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def destagger(g: Grid, psi):

@@ -42,6 +42,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the OpenMP loops from now on (the CPU baseline times the oracle on one core and on all). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Coefficients.  All are Lagrange-interpolation weights written as closed products.           */
 /* ------------------------------------------------------------------------------------------ */

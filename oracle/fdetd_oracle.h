@@ -124,6 +124,7 @@ int oracle_gather_fine(const oracle_problem *P, const double complex *psi, const
 int oracle_envelope_gather(const oracle_problem *P, const double *pond, const double *samples, long n, double *out);
 
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ PLAN_SKIP_STABILITY, PLAN_USE_GRAPH, PLAN_PROFILE, PLAN_NO_AUTOTUNE, PLAN_ONE_ST
 PLAN_CURRENT_CORRECTION = 32
 
 # every symbol declared in include/fdetd.h
-EXPORTS = ("fdetd_plan", "fdetd_step", "fdetd_step_noalloc", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
+EXPORTS = ("fdetd_plan", "fdetd_step", "fdetd_step_graph", "fdetd_step_noalloc", "envelope_step", "envelope_absorber", "envelope_ponderomotive",
            "envelope_gather",
            "fdetd_deposit_jz", "fdetd_deposit_rho",
            "fdetd_deposit_current", "fdetd_gather", "fdetd_gather_supersampled", "fdetd_query",
@@ -50,6 +50,45 @@ class PlanInfo(C.Structure):
                 ("profiled_launches", C.c_int64), ("profiled_ms", C.c_double), ("profiled_bytes", C.c_double),
                 ("seg_rows", C.c_int32), ("seg_rows_axis", C.c_int32), ("autotune_ms", C.c_double),
                 ("streams", C.c_int32)]
+
+
+JGEN_BUNCH, JGEN_SAMPLES = 1, 2
+
+
+class JgenDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("step0", C.c_int64), ("seed", C.c_uint64),
+                ("nb", C.c_double), ("sigz", C.c_double), ("sigr", C.c_double), ("z0_frac", C.c_double),
+                ("vb", C.c_double), ("noise", C.c_double), ("samples", C.c_void_p), ("n", C.c_int64),
+                ("vz", C.c_double), ("eps", C.c_double)]
+
+
+@dataclass
+class Jgen:
+    """In-graph current of fdetd_step_graph: kind JGEN_BUNCH (bunch + SplitMix64 noise) or JGEN_SAMPLES
+    (a float64 [n, 4] cuda tensor of samples (z at t = 0, x, y, q w) moving with vz, deposited each step)."""
+    kind: int
+    step0: int = 0
+    seed: int = 0
+    nb: float = 0.0
+    sigz: float = 0.0
+    sigr: float = 0.0
+    z0_frac: float = 0.25
+    vb: float = 1.0
+    noise: float = 0.0
+    samples: object = None
+    vz: float = 1.0
+    eps: float = 0.5
+
+    def c(self) -> JgenDesc:
+        ptr, n = 0, 0
+        if self.samples is not None:
+            import torch
+            x = self.samples
+            if not (x.is_cuda and x.dtype == torch.float64 and x.dim() == 2 and x.shape[1] == 4 and x.is_contiguous()):
+                raise ValueError("samples: contiguous float64 cuda tensor [n, 4]")
+            ptr, n = x.data_ptr(), x.shape[0]
+        return JgenDesc(self.kind, 0, self.step0, self.seed % 2 ** 64, self.nb, self.sigz, self.sigr, self.z0_frac,
+                        self.vb, self.noise, ptr, n, self.vz, self.eps)
 
 
 @dataclass
@@ -83,6 +122,7 @@ def _load():
     L.fdetd_plan.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.c_int32, C.c_uint32, vp, C.POINTER(vp)]
     L.fdetd_step.argtypes = [vp, pp, pp, C.c_int64, C.c_int32]
     L.envelope_step.argtypes = [vp, pp, pp, pp, C.c_int64, C.c_int32]
+    L.fdetd_step_graph.argtypes = [vp, pp, C.POINTER(JgenDesc), pp, C.c_int32]
     L.fdetd_step_noalloc.argtypes = [C.POINTER(ProblemDesc), C.c_int32, vp, vp, vp, C.c_int64, C.c_int32]
     L.fdetd_deposit_jz.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
     L.fdetd_deposit_rho.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, pp]
@@ -136,6 +176,12 @@ def fdetd_plan(problems: Sequence[Problem], precision: int = FP64, flags: int = 
 def fdetd_step(plan, psi_ptrs, j_ptrs=None, j_step_blocks: int = 0, n_steps: int = 1):
     rc = lib.fdetd_step(plan, _ptrs(psi_ptrs), _ptrs(j_ptrs) if j_ptrs is not None else None,
                         j_step_blocks, n_steps)
+    _check(rc, plan)
+
+
+def fdetd_step_graph(plan, psi_ptrs, jgen: "JgenDesc | None", jw_ptrs, n_steps: int):
+    rc = lib.fdetd_step_graph(plan, _ptrs(psi_ptrs), C.byref(jgen) if jgen is not None else None,
+                              _ptrs(jw_ptrs) if jw_ptrs is not None else None, n_steps)
     _check(rc, plan)
 
 
@@ -272,6 +318,19 @@ class Plan:
                     raise ValueError("j_half has fewer steps than n_steps")
                 stride = 1
         fdetd_step(self._h, pp, jp, stride, n_steps)
+
+    def step_graph(self, psi, jgen: "Jgen | None", j_work=None, n_steps: int = 1):
+        """n_steps steps whose current jgen makes every step into j_work (list of [3, nr, nz] tensors of the
+        plan's precision, overwritten); captured as one hipGraph with PLAN_USE_GRAPH."""
+        cd = self._cdtype()
+        self._nchk(psi, "psi")
+        pp = [self._chk(x, (6, p.nr, p.nz), cd, "psi") for x, p in zip(psi, self.problems)]
+        jp = None
+        if jgen is not None:
+            self._nchk(j_work, "j_work")
+            jp = [self._chk(x, (3, p.nr, p.nz), cd, "j_work") for x, p in zip(j_work, self.problems)]
+        self._jgen_keep = jgen.c() if jgen is not None else None  # alive while the call reads it
+        fdetd_step_graph(self._h, pp, self._jgen_keep, jp, n_steps)
 
     def deposit_jz(self, samples, j_half, vz: float = 1.0, eps: float = 0.5):
         """Add the longitudinal current of point samples (float64 [n, 4] cuda tensor of z, x, y, q w) into

@@ -158,11 +158,26 @@ struct DepositArgs {
     int64_t n;              // samples
     const double *samples;  // n x 4: z, x, y, q w
     double vz, eps;
-    double shift;           // charge density: shift of the sample positions along z
+    double shift;           // shift of the sample positions along z (charge density; J_z of the in-graph
+                            // sample current)
     int rho_xy;             // moving samples: also deposit the planar density differential into plane 3
     void *j[kMaxBatch];     // the problems' current (3 planes; J_z is plane 2), or charge density (1 plane)
 };
 hipError_t launch_deposit_jz(int prec, const DepositArgs &a, hipStream_t s);
+// The current of one step of fdetd_step_graph for the problems of a batch, overwriting their 3-plane
+// blocks j[t]: zero (mode 0), or the bunch recipe (mode 1): noise amp (U[-1, 1) of the SplitMix64 stream
+// (seed, step, pidx[t]), value ((c nr + k) nz + i) 2 + part; m = 0 keeps real parts) plus, for m = 0,
+// -nb exp(-(z - zb)^2 / (2 sigz^2) - rho^2 / (2 sigr^2)) on J_z, zb = z0f nz dz + vb t, t = (step + 1/2) dt.
+struct JgenArgs {
+    const ProbDesc *probs;
+    int nprob, mode;
+    int64_t step;
+    uint64_t seed;
+    double nb, sigz, sigr, z0f, vb, amp;
+    int pidx[kMaxBatch];
+    void *j[kMaxBatch];
+};
+hipError_t launch_jgen(int prec, const JgenArgs &a, size_t max_cells, hipStream_t s);
 hipError_t launch_deposit_rho(int prec, const DepositArgs &a, hipStream_t s);
 hipError_t launch_deposit_current(int prec, const DepositArgs &a, hipStream_t s);  // 8 doubles per sample
 // Current correction (section 3.7) of one problem's staged current, three steps:

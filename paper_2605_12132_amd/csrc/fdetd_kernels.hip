@@ -372,6 +372,52 @@ __global__ __launch_bounds__(256) void k_copy8(const uint2 *src, uint2 *dst, siz
     for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) dst[q] = src[q];
 }
 
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the generator's output function applied to a counter.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr unsigned long long kSplitMixGamma = 0x9E3779B97F4A7C15ull;
+
+// Current blocks of one step of the captured time loop (see JgenArgs): each block strides over the cells
+// of every problem in turn, each cell's three components written at once.
+template <typename V>
+__global__ __launch_bounds__(256) void k_jgen(JgenArgs A)
+{
+    using R = typename storage<V>::R;
+    const double t = (A.step + 0.5);
+    for (int p = 0; p < A.nprob; ++p) {
+        const ProbDesc &D = A.probs[p];
+        const size_t n = D.plane;
+        V *j = (V *)A.j[p];
+        unsigned long long h = splitmix64(A.seed + kSplitMixGamma);
+        h = splitmix64(h + (unsigned long long)(A.step + 1) * kSplitMixGamma);
+        h = splitmix64(h + (unsigned long long)(A.pidx[p] + 1) * kSplitMixGamma);
+        const double tb = t * D.dt, zb = A.z0f * D.nz * D.dz + A.vb * tb;
+        for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+            const int k = (int)(q / D.nz), i = (int)(q % D.nz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double re = 0.0, im = 0.0;
+                if (A.mode == 1) {
+                    const unsigned long long v = (((unsigned long long)c * D.nr + k) * D.nz + i) * 2;
+                    const unsigned long long ur = splitmix64(h + (v + 1) * kSplitMixGamma);
+                    const unsigned long long ui = splitmix64(h + (v + 2) * kSplitMixGamma);
+                    re = ((double)(ur >> 11) * 0x1p-53 * 2.0 - 1.0) * A.amp;
+                    im = D.m == 0 ? 0.0 : ((double)(ui >> 11) * 0x1p-53 * 2.0 - 1.0) * A.amp;
+                    if (c == 2 && D.m == 0) {
+                        const double zs = (i - 0.5) * D.dz, rp = (k + 0.5) * D.dr;
+                        re += -A.nb * exp(-((zs - zb) * (zs - zb)) / (2 * A.sigz * A.sigz) - rp * rp / (2 * A.sigr * A.sigr));
+                    }
+                }
+                j[c * n + q] = V{(R)re, (R)im};
+            }
+        }
+    }
+}
+
 // E part of w_N = psi + beta_in Jbar (the argument of the highest power of H in the Horner form of the
 // midpoint solution of section 2.1) for every problem of a batch, into the E planes of the problem's
 // second stage buffer: the input of the B half of a step's first Horner stage.  Jbar_rho is the staged
@@ -612,7 +658,7 @@ __global__ __launch_bounds__(256) void k_deposit_jz(DepositArgs A)
         sm[u].ok = s < A.n;
         const int64_t sc = sm[u].ok ? s : 0;
         const double x = A.samples[4 * sc + 1], y = A.samples[4 * sc + 2];
-        sm[u].z = A.samples[4 * sc];
+        sm[u].z = A.samples[4 * sc] + A.shift;  // samples moved along z (0 for fdetd_deposit_jz)
         sm[u].qw = A.samples[4 * sc + 3];
         sm[u].rho = sqrt(x * x + y * y);
         sm[u].x = x;
@@ -1963,6 +2009,15 @@ hipError_t launch_scale(int prec, void *x, size_t n, double alpha, hipStream_t s
         hipLaunchKernelGGL(k_scale<double2>, dim3(nb), dim3(256), 0, s, (double2 *)x, n, alpha);
     else
         hipLaunchKernelGGL(k_scale<float2>, dim3(nb), dim3(256), 0, s, (float2 *)x, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_jgen(int prec, const JgenArgs &a, size_t max_cells, hipStream_t s)
+{
+    const size_t nb = (max_cells + 255) / 256;
+    const dim3 g((unsigned)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096));
+    if (prec == P64) hipLaunchKernelGGL(k_jgen<double2>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_jgen<float2>, g, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -120,8 +120,18 @@ int planes(int kind) { return kind == FDETD_MAXWELL ? 6 : 2; }
 
 double parity_mS(int m) { return (m % 2 == 0) ? 1.0 : -1.0; }
 
-// rows whose stencils reach the axis region: arithmetic kept in FP64 for FP32C
-int axis_rows(const Prob &q) { return 2 * q.nd; }
+// Rows next to the axis that FP32C plans compute in FP64 arithmetic: the 2 N_D rows whose stencils reach
+// the axis ghosts and the largest 1/rho factors, or the count in FDETD_AXIS_ROWS (0 .. 4096; 0 = none), read
+// when a plan is made (for measuring what the FP64 band buys).
+int axis_band_rows(int nd)
+{
+    if (const char *e = std::getenv("FDETD_AXIS_ROWS")) {
+        char *end = nullptr;
+        const long v = std::strtol(e, &end, 10);
+        if (end != e && *end == '\0' && v >= 0 && v <= 4096) return (int)v;
+    }
+    return 2 * nd;
+}
 
 void free_prob(Prob &q)
 {
@@ -151,7 +161,7 @@ void fill_maxwell_args(const fdetd_plan_t P, const Prob &q, MaxwellStageArgs &A)
     A.nz = q.d.nz;
     A.nr = q.d.nr;
     A.m = q.d.m;
-    A.axis_rows = P->precision == FDETD_FP32C ? axis_rows(q) : 0;
+    A.axis_rows = P->precision == FDETD_FP32C ? axis_band_rows(q.nd) : 0;
     for (int j = 0; j < q.nd; ++j) {
         A.az[j] = q.a[j] / q.d.dz;
         A.ar[j] = q.a[j] / q.d.dr;
@@ -168,7 +178,7 @@ void fill_envelope_args(const fdetd_plan_t P, const Prob &q, EnvelopeStageArgs &
     A.pS = parity_mS(q.d.m);
     A.nz = q.d.nz;
     A.nr = q.d.nr;
-    A.axis_rows = P->precision == FDETD_FP32C ? axis_rows(q) : 0;
+    A.axis_rows = P->precision == FDETD_FP32C ? axis_band_rows(q.nd) : 0;
     for (int j = 0; j <= q.nd; ++j) {
         A.bz[j] = q.d2[j] / (q.d.dz * q.d.dz);
         A.br[j] = q.d2[j] / (q.d.dr * q.d.dr);
@@ -1563,6 +1573,70 @@ int step_body(fdetd_plan_t P, void *vctx)
     return rc ? rc : rj;
 }
 
+// The generated current of step `step` for the problems of batch b (fdetd_step_graph), on stream s: the
+// generator kernel overwrites their blocks (the bunch recipe, or zeros), then the samples' J_z is added.
+int enqueue_jgen(fdetd_plan_t P, const Batch &b, const fdetd_jgen &g, int64_t step, void *const *jw, hipStream_t s)
+{
+    const int prec = prec_code(P->precision);
+    JgenArgs J;
+    std::memset(&J, 0, sizeof J);
+    J.probs = P->ddesc + b.d0;
+    J.nprob = b.count;
+    J.mode = g.kind == FDETD_JGEN_BUNCH ? 1 : 0;
+    J.step = step;
+    J.seed = g.seed;
+    J.nb = g.nb;
+    J.sigz = g.sigz;
+    J.sigr = g.sigr;
+    J.z0f = g.z0_frac;
+    J.vb = g.vb;
+    J.amp = g.noise * g.nb;
+    size_t max_cells = 0;
+    for (int t = 0; t < b.count; ++t) {
+        J.pidx[t] = b.members[t];
+        J.j[t] = jw[b.members[t]];
+        max_cells = std::max(max_cells, P->probs[b.members[t]].cells);
+    }
+    HIPCHK(P, launch_jgen(prec, J, max_cells, s));
+    if (g.kind == FDETD_JGEN_SAMPLES && g.n > 0) {
+        DepositArgs A;
+        std::memset(&A, 0, sizeof A);
+        A.probs = P->ddesc + b.d0;
+        A.nprob = b.count;
+        A.n = g.n;
+        A.samples = g.samples;
+        A.vz = g.vz;
+        A.eps = g.eps;
+        A.shift = g.vz * ((step + 0.5) * b.dt);  // positions at the step's midpoint
+        for (int t = 0; t < b.count; ++t) A.j[t] = jw[b.members[t]];
+        HIPCHK(P, launch_deposit_jz(prec, A, s));
+    }
+    return FDETD_OK;
+}
+
+struct GraphCtx {
+    void *const *psi;
+    const fdetd_jgen *g;
+    void *const *jw;
+    int n_steps;
+};
+
+int graph_body(fdetd_plan_t P, void *vctx)
+{
+    GraphCtx &c = *(GraphCtx *)vctx;
+    int rc = fork_lanes(P);
+    for (int s = 0; s < c.n_steps && !rc; ++s)
+        for (size_t b = 0; b < P->batches.size() && !rc; ++b) {
+            const hipStream_t st = lane_stream(P, P->batches[b]);
+            if (c.g) rc = enqueue_jgen(P, P->batches[b], *c.g, c.g->step0 + s, c.jw, st);
+            if (!rc)
+                rc = enqueue_maxwell_batch(P, P->batches[b], c.psi, c.g ? (const void *const *)c.jw : nullptr,
+                                           s == c.n_steps - 1, st);
+        }
+    const int rj = join_lanes(P);
+    return rc ? rc : rj;
+}
+
 int env_body(fdetd_plan_t P, void *vctx)
 {
     EnvCtx &c = *(EnvCtx *)vctx;
@@ -1648,6 +1722,68 @@ int fdetd_step(fdetd_plan_t plan, void *const *psi, const void *const *j_half, i
         key.push_back(j_half ? j_half[p] : nullptr);
     }
     return run_maybe_graph(plan, key, step_body, &c);
+}
+
+int fdetd_step_graph(fdetd_plan_t plan, void *const *psi, const fdetd_jgen *jgen, void *const *j_work, int32_t n_steps)
+{
+    if (!plan) return fail(nullptr, FDETD_E_ARG, "fdetd_step_graph: NULL plan");
+    if (plan->kind != FDETD_MAXWELL) return fail(plan, FDETD_E_ARG, "fdetd_step_graph: plan is not a Maxwell plan");
+    if (plan->flags & FDETD_PLAN_CURRENT_CORRECTION)
+        return fail(plan, FDETD_E_ARG, "fdetd_step_graph: the generated blocks carry no rho_xy for the current correction");
+    if (!psi || n_steps < 0 || (jgen && !j_work)) return fail(plan, FDETD_E_ARG, "fdetd_step_graph: bad arguments");
+    const size_t eb = elem_bytes(plan->precision);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        if (!aligned(psi[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: psi[%zu] NULL or not %zu-byte aligned", p, eb);
+        if (jgen && !aligned(j_work[p], eb))
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: j_work[%zu] NULL or not %zu-byte aligned", p, eb);
+    }
+    if (jgen) {
+        const fdetd_jgen &g = *jgen;
+        if (g.kind != FDETD_JGEN_BUNCH && g.kind != FDETD_JGEN_SAMPLES)
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: unknown generator kind %d", g.kind);
+        if (g.step0 < 0 || g.step0 > ((int64_t)1 << 52))
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: step0 out of range");
+        if (g.kind == FDETD_JGEN_BUNCH &&
+            (!(g.nb > 0) || !(g.sigz > 0) || !(g.sigr > 0) || !(g.noise >= 0) ||
+             !std::isfinite(g.nb + g.sigz + g.sigr + g.noise + g.z0_frac + g.vb)))
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: bunch needs finite nb, sigz, sigr > 0, noise >= 0");
+        if (g.kind == FDETD_JGEN_SAMPLES &&
+            (g.n < 0 || (g.n > 0 && !aligned(g.samples, 8)) || !(g.eps >= 0.0 && g.eps <= 1.0) || !std::isfinite(g.vz)))
+            return fail(plan, FDETD_E_ARG, "fdetd_step_graph: samples need n >= 0, aligned samples, eps in [0, 1], finite vz");
+    }
+    if (n_steps == 0) return FDETD_OK;
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        Prob &q = plan->probs[p];
+        if (plan->precision == FDETD_FP32C && q.last_state != psi[p] && !plan->adopt_next) {
+            int rc = zero_device(plan, q.lo, 6 * q.cells * 8);
+            if (rc) return rc;
+        }
+        q.last_state = psi[p];
+    }
+    plan->adopt_next = false;
+    GraphCtx c{psi, jgen, j_work, n_steps};
+    // the key of a captured step_graph loop starts with a marker no fdetd_step key has (n_steps >= 1 there)
+    std::vector<const void *> key;
+    key.push_back((const void *)(intptr_t)-1);
+    key.push_back((const void *)(intptr_t)n_steps);
+    for (size_t p = 0; p < plan->probs.size(); ++p) {
+        key.push_back(psi[p]);
+        key.push_back(jgen ? j_work[p] : nullptr);
+    }
+    if (jgen) {
+        const fdetd_jgen &g = *jgen;
+        auto bits = [](double x) {
+            uint64_t u;
+            std::memcpy(&u, &x, sizeof u);
+            return (const void *)(uintptr_t)u;
+        };
+        for (const void *v : {(const void *)(intptr_t)g.kind, (const void *)(intptr_t)g.step0, (const void *)(uintptr_t)g.seed,
+                              bits(g.nb), bits(g.sigz), bits(g.sigr), bits(g.z0_frac), bits(g.vb), bits(g.noise),
+                              (const void *)g.samples, (const void *)(intptr_t)g.n, bits(g.vz), bits(g.eps)})
+            key.push_back(v);
+    }
+    return run_maybe_graph(plan, key, graph_body, &c);
 }
 
 int envelope_step(fdetd_plan_t plan, void *const *a, void *const *a_tilde, const void *const *chi_half,
@@ -1744,10 +1880,12 @@ void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbD
     D.taylor = d.taylor_order;
     D.nstrip = (d.nz + cpw - 1) / cpw;
     if (precision == FDETD_FP32C) {
-        D.ax_rows = std::min(d.nr, 2 * nd);
-        D.seg_ax = std::min(kSegAxis, D.ax_rows);
-        D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
-        D.nstrip_ax = (d.nz + axis_columns(nd) - 1) / axis_columns(nd);
+        D.ax_rows = std::min(d.nr, axis_band_rows(nd));
+        if (D.ax_rows > 0) {
+            D.seg_ax = std::min(kSegAxis, D.ax_rows);
+            D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
+            D.nstrip_ax = (d.nz + axis_columns(nd) - 1) / axis_columns(nd);
+        }
     }
     D.seg_rows = seg;
     D.nseg = (d.nr - D.ax_rows + seg - 1) / seg;

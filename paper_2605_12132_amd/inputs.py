@@ -215,3 +215,60 @@ def envelope_chi(w: Workload, p: int = 0) -> np.ndarray:
         g += np.cos(kr * rp[:, None] + ph[0]) * np.cos(kz * z[None, :] + ph[1])
     g /= np.max(np.abs(g))
     return e["chi0"] * (1 + e["mod"] * g)
+
+
+# ---------------------------------------------------------------------------------------------------
+# Counter-based current of the captured time loop (fdetd_step_graph, FDETD_JGEN_BUNCH): the bunch recipe
+# above with its noise drawn by SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+# generators", OOPSLA 2014) from a counter, so that the library's generator kernel and this host copy
+# produce the same values without sharing code.
+# ---------------------------------------------------------------------------------------------------
+SPLITMIX_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(z):
+    """The SplitMix64 output function (the generator's mixing of its state), on uint64 values (arithmetic
+    modulo 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(z, dtype=np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def counter_key(seed: int, step: int, problem: int):
+    """Stream key of one (seed, step, problem): h0 = mix(seed + g), h1 = mix(h0 + (step + 1) g),
+    h2 = mix(h1 + (problem + 1) g), g the SplitMix64 increment."""
+    with np.errstate(over="ignore"):
+        h = splitmix64(np.uint64(seed % 2 ** 64) + SPLITMIX_GAMMA)
+        h = splitmix64(h + np.uint64(step + 1) * SPLITMIX_GAMMA)
+        return splitmix64(h + np.uint64(problem + 1) * SPLITMIX_GAMMA)
+
+
+def counter_uniform(seed: int, step: int, problem: int, shape) -> np.ndarray:
+    """U[-1, 1) values number v = 0 .. prod(shape) - 1 of a stream: mix(key + (v + 1) g), top 53 bits."""
+    key = counter_key(seed, step, problem)
+    n = int(np.prod(shape))
+    v = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        u = splitmix64(key + v * SPLITMIX_GAMMA)
+    return ((u >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 * 2.0 - 1.0).reshape(shape)
+
+
+def graph_bunch_current(w: Workload, p: int, step: int, seed: int) -> np.ndarray:
+    """Current of step `step` (t = (step + 1/2) dt) as the library's FDETD_JGEN_BUNCH generator forms it:
+    uniform noise of amplitude noise * n_b on the real and imaginary parts of J_rho, J_theta, J_z (value
+    number ((c nr + k) nz + i) 2 + part of the stream (seed, step, p); mode 0 keeps the real parts only),
+    plus on J_z of mode 0 the Gaussian bunch -n_b exp(-(z - z_b)^2 / (2 sigma_z^2) - rho^2 / (2 sigma_r^2)),
+    z_b = 0.25 nz dz + t, at (rho_k, z_i - dz/2)."""
+    e = w.extra
+    nz, nr, m = w.nz[p], w.nr[p], w.m[p]
+    u = counter_uniform(seed, step, p, (3, nr, nz, 2)) * (e["noise"] * e["nb"])
+    j = u[..., 0] + 1j * (u[..., 1] if m != 0 else 0.0)
+    if m == 0:
+        t = (step + 0.5) * w.dt
+        rp = (np.arange(nr) + 0.5) * w.dr
+        zs = (np.arange(nz) - 0.5) * w.dz
+        zb = 0.25 * nz * w.dz + t
+        j[2] += -e["nb"] * np.exp(-((zs[None, :] - zb) ** 2) / (2 * e["sigz"] ** 2) - rp[:, None] ** 2 / (2 * e["sigr"] ** 2))
+    return j

@@ -38,6 +38,7 @@ hipError_t launch_norm2(int, const void *, size_t, double *, int, hipStream_t) {
 hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_copy(const void *, void *, size_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_form_wn(int, const BatchArgs &, size_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_jgen(int, const JgenArgs &, size_t, hipStream_t) { return hipErrorInvalidValue; }
 }  // namespace fdetd
 
 static int failures = 0;

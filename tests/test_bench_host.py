@@ -17,6 +17,9 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
+    if not os.path.exists(bench.TRAFFIC_FILE):  # counters not taken: no traffic figure
+        assert bench.measured_traffic("fp64", 64) is None and bench.measured_traffic("fp32c", 64) is None
+        return
     text = open(bench.TRAFFIC_FILE).read()
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_"))
     seg64 = int(fields["traffic_seg_rows_fp64"])
