@@ -402,6 +402,20 @@ __device__ __forceinline__ RowPart<V> fetch_row(const typename stor<V>::T *plane
     r.halo = gld<E>(prow, H.idx);
     return r;
 }
+// The halo element of row q for this lane (the own element comes from a register window or an LDS ring).
+template <typename V>
+__device__ __forceinline__ typename elem<V>::E fetch_halo(const typename stor<V>::T *plane, int nz, int q, const Halo &H)
+{
+    using E = typename elem<V>::E;
+    return gld<E>(row_ptr<E>(plane, 0, 0, nz, elem<V>::S, q), H.idx);
+}
+// A window value as the storage element it was loaded from (exact: an unscaled window of loaded values).
+template <typename E, typename AR, int K>
+__device__ __forceinline__ E from_lv(lv<AR, K> x)
+{
+    if constexpr (std::is_same<E, float2>::value) return float2{(float)x.p[0], (float)x.p[1]};
+    else return (E)x.p[0];
+}
 // Columns outside the grid enter the z stencils as zeros.
 template <typename V, int ND>
 __device__ __forceinline__ void put_row(const RowPart<V> &r, const Lane<V> &L, const Halo &H, typename elem<V>::E *row)
@@ -427,6 +441,10 @@ __device__ __forceinline__ lv<AR, elem<V>::K> lds_at(const typename elem<V>::E *
 template <typename V, typename AR, int ND, bool SRC, bool COMP>
 __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
+    // ring of the last N_D + 1 raw B_theta rows (own elements): the z stencil of row k reads row k from here,
+    // where it was put when it entered the rho window N_D rows earlier, instead of loading it again
+    constexpr int RD = ND + 1;
+    typename elem<V>::E *ring = &lds[2][0];
     constexpr int K = elem<V>::K, S = elem<V>::S;
     using L_ = lv<AR, K>;
     CDesc &D = *A.D;
@@ -457,6 +475,9 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             Wz[t] = ldrow<V, AR>(Bz, nz, r, L);
             Wg[t] = ldrow<V, AR>(Bth, nz, r, L);
         }
+        // rows k0 .. k0 + N_D - 1 of B_theta, as loaded, for their z stencils
+#pragma unroll
+        for (int t = ND - 1; t < 2 * ND - 1; ++t) ring[((k0 - ND + 1 + t) % RD) * WAVE + L.lane] = from_lv<typename elem<V>::E>(Wg[t]);
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
             const int q = k0 - ND + 1 + t;
@@ -470,8 +491,8 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
     const Halo H = halo_of<V, ND>(i0, nz, L);
     // everything row k needs from memory: loads of valid rows only (indices clamped), formed in row()
     struct In {
-        E bz, bt, j0, j1, j2;
-        RowPart<V> th, br;
+        E bz, bt, j0, j1, j2, thh;
+        RowPart<V> br;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
     };
@@ -481,7 +502,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qc = qn < nr ? qn : nr - 1;
         x.bz = ldraw<V>(Bz, nz, qc, L);
         x.bt = ldraw<V>(Bth, nz, qc, L);
-        x.th = fetch_row<V>(Bth, nz, k, L, H);
+        x.thh = fetch_halo<V>(Bth, nz, k, H);
         x.br = fetch_row<V>(Br, nz, k, L, H);
         x.j0 = x.j1 = x.j2 = E{};
         if constexpr (SRC) {
@@ -504,7 +525,8 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qn = k + ND;  // the window's new row
         Wz[2 * ND - 1] = keep_if(qn < nr, to_lv<AR>(cu.bz));
         Wg[2 * ND - 1] = keep_if(qn < nr, ((AR)qn * dr) * to_lv<AR>(cu.bt));
-        put_row<V, ND>(cu.th, L, H, lds[0]);
+        ring[(qn % RD) * WAVE + L.lane] = cu.bt;
+        put_row<V, ND>(RowPart<V>{ring[(k % RD) * WAVE + L.lane], cu.thh}, L, H, lds[0]);
         put_row<V, ND>(cu.br, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
@@ -557,6 +579,9 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 template <typename V, typename AR, int ND, bool COMP>
 __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
+    // ring of the last N_D + 1 raw E_theta rows (own elements), as in e_half
+    constexpr int RD = ND + 1;
+    typename elem<V>::E *ring = &lds[2][0];
     constexpr int K = elem<V>::K, S = elem<V>::S;
     using L_ = lv<AR, K>;
     CDesc &D = *A.D;
@@ -580,6 +605,9 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wz[t] = ldrow<V, AR>(Ez, nz, r, L);
             Wg[t] = ldrow<V, AR>(Eth, nz, r, L);
         }
+        // rows k0 .. k0 + N_D - 2 of E_theta, as loaded, for their z stencils
+#pragma unroll
+        for (int t = ND; t < 2 * ND - 1; ++t) ring[((k0 - ND + t) % RD) * WAVE + L.lane] = from_lv<typename elem<V>::E>(Wg[t]);
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
             const int q = k0 - ND + t;
@@ -592,8 +620,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     using E = typename elem<V>::E;
     const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
-        E ez, et;
-        RowPart<V> th, er;
+        E ez, et, thh;
+        RowPart<V> er;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
     };
@@ -603,7 +631,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         const int qc = qn < nr ? qn : nr - 1;
         x.ez = ldraw<V>(Ez, nz, qc, L);
         x.et = ldraw<V>(Eth, nz, qc, L);
-        x.th = fetch_row<V>(Eth, nz, k, L, H);
+        x.thh = fetch_halo<V>(Eth, nz, k, H);
         x.er = fetch_row<V>(Er, nz, k, L, H);
         x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
         x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
@@ -621,7 +649,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         const L_ ez = to_lv<AR>(cu.ez), et = to_lv<AR>(cu.et);
         Wz[2 * ND - 1] = keep_if(qn < nr, ez);
         Wg[2 * ND - 1] = keep_if(qn < nr, (((AR)qn + (AR)0.5) * dr) * et);
-        put_row<V, ND>(cu.th, L, H, lds[0]);
+        ring[(qn % RD) * WAVE + L.lane] = cu.et;
+        put_row<V, ND>(RowPart<V>{ring[(k % RD) * WAVE + L.lane], cu.thh}, L, H, lds[0]);
         put_row<V, ND>(cu.er, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
@@ -730,14 +759,20 @@ constexpr int lds_row_bytes()
     return (WAVE + 2 * ND * elem<V>::S) * (int)sizeof(typename elem<V>::E);
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// LDS of one stage wavefront: the two z-stencil rows, then N_D + 1 rows of own elements (the theta ring)
+template <typename V, int ND>
+constexpr int stage_lds_bytes()
+{
+    return 2 * lds_row_bytes<V, ND>() + (ND + 1) * WAVE * (int)sizeof(typename elem<V>::E);
+}
 
 template <typename V, int ND, bool SRC, bool COMP>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
     // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
     using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
-    // two LDS rows, sized for the main layout and the near-axis one
-    __shared__ __align__(16) unsigned char smem[2 * cmax(lds_row_bytes<V, ND>(), lds_row_bytes<VA, ND>())];
+    // two LDS rows and the ring of raw theta rows, sized for the main layout and the near-axis one
+    __shared__ __align__(16) unsigned char smem[cmax(stage_lds_bytes<V, ND>(), stage_lds_bytes<VA, ND>())];
     bool axis;
     const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
     if (t < 0) return;
@@ -800,8 +835,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
     const AR szi = (AR)gld<double>(D.sz, (unsigned)cc);  // absorbing layer: sigma_z of this column
     const Halo H = halo_of<V, ND>(i0, nz, L);
     struct In {
-        E an, tin;
-        RowPart<V> a;
+        E an, tin, ah;
         R chi;
         E pa, pt;
         typename elem<V>::Lo la, lt;
@@ -810,7 +844,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         In x;
         const int qn = k + ND;
         x.an = ldraw<V>(va, nz, qn < nr ? qn : nr - 1, L);
-        x.a = fetch_row<V>(va, nz, k, L, H);
+        x.ah = fetch_halo<V>(va, nz, k, H);
         x.tin = ldraw<V>(vt, nz, k, L);
         x.chi = gld<R>((const R *)A.chi + (size_t)k * nz, (unsigned)cc);
         const unsigned o = (unsigned)L.eidx;
@@ -828,7 +862,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         const int qn = k + ND;
         Wa[W - 1] = keep_if(qn < nr, to_lv<AR>(cu.an));
         const L_ tin = to_lv<AR>(cu.tin);
-        put_row<V, ND>(cu.a, L, H, lds);
+        put_row<V, ND>(RowPart<V>{from_lv<E>(Wa[ND]), cu.ah}, L, H, lds);  // own element: the window's row k
         __syncthreads();
         const L_ a0 = Wa[ND];
         L_ lz = (AR)D.bz[0] * a0, d1z = zero;

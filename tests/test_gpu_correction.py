@@ -1,12 +1,12 @@
 """GPU current correction (section 3.7) inside fdetd_step (FDETD_PLAN_CURRENT_CORRECTION: current blocks
 of J_rho, J_theta, J_z, rho_xy) against the oracle's corrected step: FP64 to relative L2 <= 1e-12 (the
 banded solve without pivoting differs from the oracle's pivoted dense solve by ~cond(A) eps, cond(A) ~
-1e3 on these 40-row grids), FP32C to 2e-5; a density consistent with the current leaves the step as it
+1e3 on these 40-row grids), FP32C to helpers.tol_fp32c(steps, N); a density consistent with the current leaves the step as it
 is; graph replay and several streams give the eager result bit for bit."""
 import numpy as np
 import pytest
 
-from helpers import gpu_maxwell, log, rel_l2
+from helpers import gpu_maxwell, log, rel_l2, tol_fp32c
 
 import oracle
 import paper_2605_12132_amd as F
@@ -49,7 +49,7 @@ def test_corrected_step_matches_oracle(precision):
     rng = np.random.default_rng(11 + precision)
     psi0, J4 = inputs(w, 3, rng)
     got, info = gpu_maxwell(w, psi0, J4, 3, precision=precision, flags=1 | F.PLAN_CURRENT_CORRECTION)
-    tol = 1e-12 if precision == F.FP64 else 2e-5
+    tol = 1e-12 if precision == F.FP64 else tol_fp32c(3, w.taylor_order)
     for p in range(w.n):
         want = oracle.step_corrected(grid(w, p), psi0[p], J4[p], 3)
         plain = oracle.step(grid(w, p), psi0[p], J4[p][:, :3], 3)
