@@ -138,7 +138,7 @@ def initial_state(w, cd):
     return [torch.from_numpy(I.initial_fields(w, p)).to(device="cuda", dtype=cd) for p in range(w.n)]
 
 
-def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_graph=True):
+def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_graph=True, extra_flags=0):
     """Warm up W steps, capture the K-step loop of fdetd_step_graph once (untimed, then restore the state),
     time exactly K steps of its replay.  jgen_of(step0) gives the step generator of the call."""
     import torch
@@ -149,7 +149,7 @@ def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_grap
     with torch.cuda.stream(stream):
         psi = initial_state(w, cd)
         jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
-        flags = F.PLAN_USE_GRAPH if use_graph else 0
+        flags = (F.PLAN_USE_GRAPH if use_graph else 0) | extra_flags
         t0 = time.time()
         with seg_rows_env(seg_rows):
             plan = F.Plan(w.problems(), precision=precision, flags=flags)
@@ -266,7 +266,7 @@ def copy_calibration(n_bytes=1 << 30, reps=10):
                 stream_GBs={k: round(v, 1) for k, v in streams.items()})
 
 
-def graph_workload_pass(w, steps, warmup, tag):
+def graph_workload_pass(w, steps, warmup, tag, extra_flags=0):
     """A workload with the bunch + noise current made in the graph (fdetd_step_graph, FDETD_JGEN_BUNCH):
     FP64 and FP32C, K steps timed as above; cell-updates/s, the step-level algorithmic HBM rate (the plan's
     bytes per step / step time), launches per step and the FP32C error against FP64."""
@@ -274,7 +274,8 @@ def graph_workload_pass(w, steps, warmup, tag):
     cells = w.cells()
     res, psis = {}, {}
     for pt, prec in (("fp64", F.FP64), ("fp32c", F.FP32C)):
-        psi, ms, times, info = run_graph_path(w, prec, steps, warmup, lambda s0: bunch_jgen(w, s0))
+        psi, ms, times, info = run_graph_path(w, prec, steps, warmup, lambda s0: bunch_jgen(w, s0),
+                                              extra_flags=extra_flags)
         gbs = info["bytes_per_step"] * steps / (ms * 1e-3) / 1e9
         res[pt] = dict(value=cells * steps / (ms * 1e-3), ms_per_step=ms / steps, algorithmic_GBs=round(gbs, 1),
                        frac=round(gbs / HBM_PEAK_GBS, 4), launches_per_step=info["launches_per_step"],
@@ -650,7 +651,14 @@ def main():
         if args.current_driven_steps > 0:
             extra["current_driven"] = graph_workload_pass(I.current_driven(), args.current_driven_steps, W, "current-driven")
         if args.batched_steps > 0:
-            extra["batched"] = graph_workload_pass(I.batched_uneven(), args.batched_steps, W, "batched")
+            extra["batched"] = graph_workload_pass(I.batched_uneven(), args.batched_steps, W,
+                                                   "batched, default grouping")
+            extra["batched_per_width"] = graph_workload_pass(I.batched_uneven(), args.batched_steps, W,
+                                                             "batched, one launch batch per width",
+                                                             F.PLAN_PER_WIDTH)
+            extra["batched_mixed_widths"] = graph_workload_pass(I.batched_uneven(), args.batched_steps, W,
+                                                                "batched, one launch batch for all widths",
+                                                                F.PLAN_MIXED_WIDTHS)
         if args.envelope_steps > 0:
             extra["envelope"] = envelope_pass(args.envelope_steps)
         if args.correction_steps > 0:

@@ -67,6 +67,14 @@ extern "C" {
 #define FDETD_PLAN_ONE_STREAM    16u  /* enqueue every launch on the plan's stream (no side streams)    */
 #define FDETD_PLAN_CURRENT_CORRECTION 32u /* Maxwell: current blocks carry rho_xy; fdetd_step corrects the
                                              staged current every step (section 3.7, see fdetd_step)      */
+#define FDETD_PLAN_MIXED_WIDTHS 64u  /* Maxwell: one launch batch for all problems of equal Taylor order and
+                                        dt whatever their stencil widths (one launch per stage, two for
+                                        FP32C: main and near-axis tiles), instead of one batch per width
+                                        on up to four streams; ignored with the current correction        */
+#define FDETD_PLAN_PER_WIDTH   128u  /* Maxwell: one launch batch per stencil width.  Without either flag
+                                        FP64 plans mix widths and FP32C plans batch per width (the faster
+                                        grouping of each on a 64-problem batch of 13 widths); with both,
+                                        FDETD_PLAN_PER_WIDTH wins                                          */
 
 typedef struct fdetd_plan_s *fdetd_plan_t;
 

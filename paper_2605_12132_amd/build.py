@@ -22,6 +22,8 @@ LIB = os.path.join(OUT_DIR, "libfdetd.so")
 ND_RANGES = [(1, 3), (4, 6), (7, 8), (9, 10), (11, 12), (13, 14), (15, 15), (16, 16)]
 SOURCES = ([("fdetd_march.hip", f"fdetd_march_nd{lo}_{hi}", [f"-DFDETD_ND_LO={lo}", f"-DFDETD_ND_HI={hi}"])
             for lo, hi in ND_RANGES]
+           + [("fdetd_march.hip", f"fdetd_march_any{a}", ["-DFDETD_ND_LO=1", "-DFDETD_ND_HI=0", f"-DFDETD_ANY_WIDTH={a}"])
+              for a in (0, 1, 2)]  # launches that mix stencil widths: FP64, FP32, FP32 compensated last stage
            + [(f, f, []) for f in ("fdetd_kernels.hip", "fdetd_noalloc.hip", "fdetd_plan.cpp", "fdetd_coeffs.cpp",
                                    "fdetd_dispatch.cpp")])
 ARCH = "gfx950"

@@ -37,6 +37,17 @@ hipError_t launch_stagger_march(int prec, int nd, const BatchArgs &a, hipStream_
     }
 }
 
+hipError_t launch_maxwell_any(int prec, const BatchArgs &a, hipStream_t s)
+{
+    if (prec == P64) return march_maxwell_any_p64(a, s);
+    return a.compensated && a.n == 0 ? march_maxwell_any_p32c(a, s) : march_maxwell_any_p32(a, s);
+}
+
+hipError_t launch_stagger_any(int prec, const BatchArgs &a, hipStream_t s)
+{
+    return prec == P64 ? march_stagger_any_p64(a, s) : march_stagger_any_p32(a, s);
+}
+
 // A wavefront of 64 lanes covers 32 z columns in FP64 (a lane pair per complex value) and 64 in FP32 (one
 // lane per value); the kernels' lane mapping (elem<double2>::S = 2, elem<float2>::S = 1) matches this.
 int march_columns_per_wave(int prec) { return prec == P64 ? 32 : 64; }

@@ -82,6 +82,7 @@ constexpr int kMaxBatch = 64;  // problems per launch (pointer arrays travel in 
 // Static per-problem facts, uploaded once at plan time.
 struct ProbDesc {
     int nz, nr, m, taylor;
+    int nd;                                  // stencil half width N_D (launches that mix widths)
     int nstrip;                              // tiling: strips of z columns ...
     int seg_rows, nseg;                      // ... x segments of seg_rows rows from row ax_rows down (main tiles)
     int seg_ax, nseg_ax, ax_rows, nstrip_ax; // FP32C: rows 0 .. ax_rows-1 (= 2 N_D) in segments of seg_ax rows
@@ -146,10 +147,24 @@ hipError_t launch_maxwell_march(int prec, int nd, const BatchArgs &a, hipStream_
 hipError_t launch_envelope_march(int prec, int nd, const BatchArgs &a, hipStream_t s);
 hipError_t launch_stagger_march(int prec, int nd, const BatchArgs &a, hipStream_t s);  // aux = the step's currents
 int march_columns_per_wave(int prec);  // z columns covered by one wavefront (32 FP64, 64 FP32)
+// Launches over batches whose problems differ in N_D (each tile runs its problem's width), in the
+// translation units of fdetd_march.hip built with FDETD_ANY_WIDTH = 0 (FP64), 1 (FP32), 2 (FP32 with the
+// compensated last stage); dispatched by launch_maxwell_any / launch_stagger_any (fdetd_dispatch.cpp).
+hipError_t march_maxwell_any_p64(const BatchArgs &a, hipStream_t s);
+hipError_t march_maxwell_any_p32(const BatchArgs &a, hipStream_t s);
+hipError_t march_maxwell_any_p32c(const BatchArgs &a, hipStream_t s);
+hipError_t march_stagger_any_p64(const BatchArgs &a, hipStream_t s);
+hipError_t march_stagger_any_p32(const BatchArgs &a, hipStream_t s);
+hipError_t launch_maxwell_any(int prec, const BatchArgs &a, hipStream_t s);
+hipError_t launch_stagger_any(int prec, const BatchArgs &a, hipStream_t s);
 
 hipError_t launch_maxwell_stage(int prec, int nd, const MaxwellStageArgs &a, hipStream_t s);
 hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, hipStream_t s);
 hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s);
+// The axis rule (section 2.4) on the state of every problem of a batch (a.psi; widths may differ), one
+// launch: row 0 of E_rho, B_theta, B_z of problem p = sum_k' c_k' F_k' where the component is constant on
+// the axis, else 0.  max_nz: the largest problem's nz.
+hipError_t launch_axis_fix_batch(int prec, const BatchArgs &a, int max_nz, hipStream_t s);
 
 // Deposition of point samples into J_z of every problem of a batch (atomic adds in the storage precision).
 struct DepositArgs {

@@ -339,6 +339,29 @@ __global__ __launch_bounds__(256) void k_axis_fix(AxisArgs A)
     }
 }
 
+// The axis rule for every problem of a batch: grid.y = problem, threads over the columns; the weights and
+// N_D come from the problem's descriptor, the sum runs in the order of k_axis_fix (same results).
+template <typename V>
+__global__ __launch_bounds__(256) void k_axis_fix_batch(BatchArgs A)
+{
+    using R = typename storage<V>::R;
+    const ProbDesc &D = A.probs[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= D.nz) return;
+    const size_t P = D.plane;
+    V *psi = (V *)A.psi[blockIdx.y];
+    const int comps[3] = {ER, BTH, BZ};
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int c = comps[t];
+        const bool extrap = (c == BZ) ? (D.m == 0) : (D.m == 1);
+        cx<double> s = {0, 0};
+        if (extrap)
+            for (int q = 1; q <= D.nd; ++q) s = s + D.cax[q - 1] * ld<double>(psi + c * P, (size_t)q * D.nz + i);
+        psi[c * P + i] = V{(R)s.x, (R)s.y};
+    }
+}
+
 // --------------------------------------------------------------------------------------------------
 // Reductions for the plan-time power iteration: per-block sums of |x|^2 (wave shuffles, then LDS).
 // --------------------------------------------------------------------------------------------------
@@ -1984,6 +2007,14 @@ hipError_t launch_envelope_stage(int prec, int nd, const EnvelopeStageArgs &a, h
     const dim3 g = tile_grid(a.nz, a.nr), b(TZ, TR, 1);
     return prec == P64 ? dispatch_nd<EnvelopeL, double2>(nd, a, g, b, s)
                        : dispatch_nd<EnvelopeL, float2>(nd, a, g, b, s);
+}
+
+hipError_t launch_axis_fix_batch(int prec, const BatchArgs &a, int max_nz, hipStream_t s)
+{
+    const dim3 g((unsigned)((max_nz + 255) / 256), (unsigned)a.nprob), b(256, 1, 1);
+    if (prec == P64) hipLaunchKernelGGL(k_axis_fix_batch<double2>, g, b, 0, s, a);
+    else hipLaunchKernelGGL(k_axis_fix_batch<float2>, g, b, 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_axis_fix(int prec, int nd, const AxisArgs &a, hipStream_t s)

@@ -1102,6 +1102,91 @@ hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
     return go_envelope_v<V, ND, false>(a, s);
 }
 
+// --------------------------------------------------------------------------------------------------
+// Launches that mix stencil widths: every problem of the batch keeps its own N_D, and each tile runs the
+// code specialised for its problem's N_D (the same code, and so the same results, as the per-width
+// launches).  One launch per stage for all problems of equal Taylor order and time step.
+// --------------------------------------------------------------------------------------------------
+#ifdef FDETD_ANY_WIDTH
+template <typename V, bool SRC, bool COMP, bool AXIS, int ND>
+__device__ __forceinline__ void stage_tile_any(const BatchArgs &A, int t, unsigned char *smem)
+{
+    using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if constexpr (AXIS) {
+            using EA = typename elem<VA>::E;
+            maxwell_tile<VA, ND, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            return;
+        }
+    }
+    using E = typename elem<V>::E;
+    maxwell_tile<V, ND, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+}
+
+// AXIS: the launch covers the FP32C near-axis tiles only (their FP64-arithmetic code for all widths in one
+// kernel would not fit the registers of two wavefronts per SIMD); otherwise the main tiles only.
+template <typename V, bool SRC, bool COMP, bool AXIS>
+__global__ __launch_bounds__(WAVE) void k_maxwell_stage_any(BatchArgs A)
+{
+    __shared__ __align__(16) unsigned char smem[cmax(stage_lds_bytes<V, kMaxND>(), stage_lds_bytes<f2pair, kMaxND>())];
+    bool axis;
+    const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
+    if (t < 0 || axis != AXIS) return;
+    const int p = problem_of_tile<AXIS>(A, t);
+    switch (((CDesc *)A.probs)[p].nd) {
+#define FDETD_C(N) \
+    case N: stage_tile_any<V, SRC, COMP, AXIS, N>(A, t, smem); break;
+        FDETD_C(1) FDETD_C(2) FDETD_C(3) FDETD_C(4) FDETD_C(5) FDETD_C(6) FDETD_C(7) FDETD_C(8) FDETD_C(9) FDETD_C(10)
+        FDETD_C(11) FDETD_C(12) FDETD_C(13) FDETD_C(14) FDETD_C(15) FDETD_C(16)
+#undef FDETD_C
+    default: break;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(WAVE) void k_stagger_march_any(BatchArgs A)
+{
+    bool axis;
+    const int t = tile_of_block(A.ntiles_ax, A.ntiles, axis);
+    if (t < 0) return;
+    const int p = axis ? problem_of_tile<true>(A, t) : problem_of_tile<false>(A, t);
+    switch (((CDesc *)A.probs)[p].nd) {
+#define FDETD_C(N)                                                                                                    \
+    case N:                                                                                                           \
+        if constexpr (sizeof(typename scal<V>::R) == 4) {                                                              \
+            if (axis) {                                                                                                \
+                stagger_tile<typename std::conditional<(N <= kAxisWholeND), float2, f2pair>::type, N, true>(A, t);   \
+                break;                                                                                                 \
+            }                                                                                                          \
+        }                                                                                                              \
+        stagger_tile<V, N, false>(A, t);                                                                               \
+        break;
+        FDETD_C(1) FDETD_C(2) FDETD_C(3) FDETD_C(4) FDETD_C(5) FDETD_C(6) FDETD_C(7) FDETD_C(8) FDETD_C(9) FDETD_C(10)
+        FDETD_C(11) FDETD_C(12) FDETD_C(13) FDETD_C(14) FDETD_C(15) FDETD_C(16)
+#undef FDETD_C
+    default: break;
+    }
+}
+
+// The main tiles, then (FP32 storage) the near-axis tiles in a second launch.
+template <typename V, bool SRC, bool COMP>
+hipError_t go_maxwell_any_v(const BatchArgs &a, hipStream_t s)
+{
+    if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
+    BatchArgs m = a;
+    m.ntiles_ax = 0;
+    if (m.ntiles) hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, false>), dim3(blocks_of(0, m.ntiles)), dim3(WAVE), 0, s, m);
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (a.ntiles_ax) {
+            BatchArgs x = a;
+            x.ntiles = 0;
+            hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, true>), dim3(blocks_of(x.ntiles_ax, 0)), dim3(WAVE), 0, s, x);
+        }
+    }
+    return hipGetLastError();
+}
+#endif
+
 }  // namespace
 
 // Per-N_D entry points; fdetd_march.hip is compiled once per N_D range (FDETD_ND_LO .. FDETD_ND_HI) so
@@ -1126,6 +1211,35 @@ hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
 #ifndef FDETD_ND_LO
 #define FDETD_ND_LO 1
 #define FDETD_ND_HI 16
+#endif
+#ifdef FDETD_ANY_WIDTH
+// FDETD_ANY_WIDTH = 0: FP64 launches; 1: FP32 storage without, 2: with the compensated last stage
+#if FDETD_ANY_WIDTH == 0
+hipError_t march_maxwell_any_p64(const BatchArgs &a, hipStream_t s)
+{
+    return a.has_src ? go_maxwell_any_v<double2, true, false>(a, s) : go_maxwell_any_v<double2, false, false>(a, s);
+}
+hipError_t march_stagger_any_p64(const BatchArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stagger_march_any<double2>, dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0, s, a);
+    return hipGetLastError();
+}
+#elif FDETD_ANY_WIDTH == 1
+hipError_t march_maxwell_any_p32(const BatchArgs &a, hipStream_t s)
+{
+    return a.has_src ? go_maxwell_any_v<float2, true, false>(a, s) : go_maxwell_any_v<float2, false, false>(a, s);
+}
+hipError_t march_stagger_any_p32(const BatchArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stagger_march_any<float2>, dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0, s, a);
+    return hipGetLastError();
+}
+#else
+hipError_t march_maxwell_any_p32c(const BatchArgs &a, hipStream_t s)
+{
+    return a.has_src ? go_maxwell_any_v<float2, true, true>(a, s) : go_maxwell_any_v<float2, false, true>(a, s);
+}
+#endif
 #endif
 #if FDETD_ND_LO <= 1 && 1 <= FDETD_ND_HI
 FDETD_MARCH_INST(1)

@@ -226,7 +226,10 @@ int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A, hipStream_t s)
     A.ntiles = b.ntiles;
     A.ntiles_ax = b.ntiles_ax;
     if (A.ntiles + A.ntiles_ax == 0) return FDETD_OK;
-    HIPCHK(P, P->kind == FDETD_MAXWELL ? launch_maxwell_march(prec, b.nd, A, s) : launch_envelope_march(prec, b.nd, A, s));
+    if (P->kind == FDETD_MAXWELL)
+        HIPCHK(P, b.nd > 0 ? launch_maxwell_march(prec, b.nd, A, s) : launch_maxwell_any(prec, A, s));
+    else
+        HIPCHK(P, launch_envelope_march(prec, b.nd, A, s));
     return FDETD_OK;
 }
 
@@ -249,7 +252,8 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         A.aux[t] = j ? j[b.members[t]] : nullptr;
         cells += P->probs[b.members[t]].cells;
     }
-    if (j && b.ntiles + b.ntiles_ax) HIPCHK(P, launch_stagger_march(prec, b.nd, A, s));
+    if (j && b.ntiles + b.ntiles_ax)
+        HIPCHK(P, b.nd > 0 ? launch_stagger_march(prec, b.nd, A, s) : launch_stagger_any(prec, A, s));
     if (j && (P->flags & FDETD_PLAN_CURRENT_CORRECTION)) {
         // divergence error per problem, the banded solves of up to kMaxSolve problems per launch, then the
         // corrected currents per problem
@@ -314,20 +318,14 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         if ((rc = launch_stage(P, b, A, s))) return rc;
         if ((rc = profile_end(P))) return rc;
     }
+    int max_nz = 0;
     for (int t = 0; t < b.count; ++t) {
         const int p = b.members[t];
         const Prob &q = P->probs[p];
         if (q.d.taylor_order == 1) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, s));
-        if (last_step_of_call) {
-            AxisArgs X{};
-            X.psi = psi[p];
-            X.nz = q.d.nz;
-            X.nr = q.d.nr;
-            X.m = q.d.m;
-            for (int u = 0; u < q.nd; ++u) X.cax[u] = q.c[u];
-            HIPCHK(P, launch_axis_fix(prec, q.nd, X, s));
-        }
+        max_nz = std::max(max_nz, q.d.nz);
     }
+    if (last_step_of_call) HIPCHK(P, launch_axis_fix_batch(prec, A, max_nz, s));
     return FDETD_OK;
 }
 
@@ -499,6 +497,16 @@ int join_lanes(fdetd_plan_t P)
 
 hipStream_t lane_stream(fdetd_plan_t P, const Batch &b) { return b.lane ? P->lanes[b.lane - 1] : P->stream; }
 
+// Launch batches that mix stencil widths: Maxwell plans in FP64 or with FDETD_PLAN_MIXED_WIDTHS, unless
+// FDETD_PLAN_PER_WIDTH, and never with the current correction, whose banded solves are batched per width.
+// FP32C plans batch per width by default: their mixed launches split main and near-axis tiles into two
+// launches per stage on one stream, and per-width batches on four streams overlapped those better.
+bool mixed_widths(const fdetd_plan_t P)
+{
+    if (P->kind != FDETD_MAXWELL || (P->flags & (FDETD_PLAN_CURRENT_CORRECTION | FDETD_PLAN_PER_WIDTH))) return false;
+    return (P->flags & FDETD_PLAN_MIXED_WIDTHS) || P->precision == FDETD_FP64;
+}
+
 // Streams of a plan with more than one launch batch: longest-processing-time assignment of the batches
 // (work ~ cells x (N + 1)) to at most kMaxLanes streams, the plan's own stream being lane 0.  Profiled
 // plans and FDETD_PLAN_ONE_STREAM keep every launch on the plan's stream.
@@ -562,11 +570,15 @@ int build_batches(fdetd_plan_t P)
     const int n = (int)P->probs.size();
     std::vector<int> order(n);
     for (int p = 0; p < n; ++p) order[p] = p;
+    // FDETD_PLAN_MIXED_WIDTHS: a batch holds problems of any stencil width (sorted by width inside it, so
+    // that each XCD's contiguous tile range mostly runs one width's code); otherwise one width per batch
+    const bool mixed = mixed_widths(P);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const auto &a = P->probs[x].d, &b = P->probs[y].d;
-        if (a.fd_order != b.fd_order) return a.fd_order < b.fd_order;
+        if (!mixed && a.fd_order != b.fd_order) return a.fd_order < b.fd_order;
         if (a.taylor_order != b.taylor_order) return a.taylor_order < b.taylor_order;
-        return a.dt < b.dt;
+        if (a.dt != b.dt) return a.dt < b.dt;
+        return a.fd_order < b.fd_order;
     });
     const int halves = P->kind == FDETD_MAXWELL ? 2 : 1;
     const int cpw = march_columns_per_wave(prec_code(P->precision));
@@ -581,7 +593,7 @@ int build_batches(fdetd_plan_t P)
         int u = t;
         while (u < n && u - t < kMaxBatch) {
             const auto &du = P->probs[order[u]].d;
-            if (du.fd_order != d0.fd_order || du.taylor_order != d0.taylor_order || du.dt != d0.dt) break;
+            if ((!mixed && du.fd_order != d0.fd_order) || du.taylor_order != d0.taylor_order || du.dt != d0.dt) break;
             row_strips += (int64_t)halves * ((du.nz + cpw - 1) / cpw) * du.nr;
             ++u;
         }
@@ -610,6 +622,8 @@ int build_batches(fdetd_plan_t P)
             b.members.push_back(order[v]);
         }
         b.count = u - t;
+        for (int v = t; v < u; ++v)
+            if (P->probs[order[v]].nd != b.nd) b.nd = -1;  // several widths: the launches that mix them
         b.seg = seg;
         b.ntiles = tiles;
         b.ntiles_ax = tiles_ax;
@@ -626,7 +640,7 @@ int build_batches(fdetd_plan_t P)
             const int units = (D.nz + kAxisColumns - 1) / kAxisColumns;
             std::vector<unsigned char> seen((size_t)halves * units * D.nr, 0);
             for (int axis = 0; axis < 2; ++axis) {
-                const int w = axis ? axis_columns(b.nd) : cpw;
+                const int w = axis ? axis_columns(D.nd) : cpw;
                 const int nl = halves * (axis ? D.nseg_ax * D.nstrip_ax : D.nseg * D.nstrip);
                 int begin = 0;
                 for (int u = 0; u < t; ++u) {
@@ -977,6 +991,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if (probs[p].kind != probs[0].kind)
             return fail(nullptr, FDETD_E_ARG, "fdetd_plan: all problems of a plan must have the same kind");
     }
+    if (flags & ~(FDETD_PLAN_PER_WIDTH * 2u - 1u))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_PER_WIDTH * 2u - 1u));
     if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: graph capture needs a non-default stream");
     if ((flags & FDETD_PLAN_CURRENT_CORRECTION) && probs[0].kind != FDETD_MAXWELL)
@@ -1068,7 +1084,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w.
             // (The w_N pass, 9c, is not counted: it is an implementation overhead of the first stage.)
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
-            launches += 1;  // axis rule (staging and stage launches are counted per batch below)
+            // (staging, w_N, stage and axis-rule launches are counted per batch below)
         } else {
             // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
             bytes_step += (int64_t)q.cells * (eb * 6 + eb / 2) * N + (precision == FDETD_FP32C ? q.cells * 2 * 8 * 2 : 0);
@@ -1106,8 +1122,11 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.cells = cells;
     P->info.bytes_per_step = bytes_step;
     P->info.scratch_bytes = scratch;
-    for (const Batch &b : P->batches)  // Maxwell: N stages, staging and w_N per batch
-        launches += (int64_t)(b.N + (P->kind == FDETD_MAXWELL ? 2 : 0)) * (b.ntiles + b.ntiles_ax > 0);
+    for (const Batch &b : P->batches) {  // Maxwell: N stages (two launches each when a batch that mixes
+                                         // widths has FP32C near-axis tiles), staging and w_N per batch
+        const int per_stage = (b.nd < 0 && b.ntiles && b.ntiles_ax) ? 2 : 1;
+        launches += (int64_t)(per_stage * b.N + (P->kind == FDETD_MAXWELL ? 2 : 0)) * (b.ntiles + b.ntiles_ax > 0);
+    }
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
@@ -1878,6 +1897,7 @@ void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbD
     D.nr = d.nr;
     D.m = d.m;
     D.taylor = d.taylor_order;
+    D.nd = nd;
     D.nstrip = (d.nz + cpw - 1) / cpw;
     if (precision == FDETD_FP32C) {
         D.ax_rows = std::min(d.nr, axis_band_rows(nd));

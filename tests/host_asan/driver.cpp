@@ -39,6 +39,12 @@ hipError_t launch_scale(int, void *, size_t, double, hipStream_t) { return hipEr
 hipError_t launch_copy(const void *, void *, size_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_form_wn(int, const BatchArgs &, size_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_jgen(int, const JgenArgs &, size_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_axis_fix_batch(int, const BatchArgs &, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t march_maxwell_any_p64(const BatchArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t march_maxwell_any_p32(const BatchArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t march_maxwell_any_p32c(const BatchArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t march_stagger_any_p64(const BatchArgs &, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t march_stagger_any_p32(const BatchArgs &, hipStream_t) { return hipErrorInvalidValue; }
 }  // namespace fdetd
 
 static int failures = 0;

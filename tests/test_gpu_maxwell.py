@@ -246,8 +246,9 @@ def test_concurrent_batches_equal_one_stream(precision):
     J = [random_current(w, 0, 3, rng) for w in ws]
     batch = I.Workload("mix5", 0, [w.nz[0] for w in ws], [w.nr[0] for w in ws], [w.m[0] for w in ws],
                        [w.fd_order[0] for w in ws], 8, ws[0].dz, ws[0].dr, ws[0].dt, 3)
-    lanes, info = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1)
-    one, info1 = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1 | F.PLAN_ONE_STREAM)
+    pw = F.PLAN_PER_WIDTH
+    lanes, info = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1 | pw)
+    one, info1 = gpu_maxwell(batch, psi0, J, 3, precision=precision, flags=1 | pw | F.PLAN_ONE_STREAM)
     log(f"five batches: {info['streams']} streams, one-stream plan {info1['streams']}")
     assert info["streams"] == 4 and info1["streams"] == 1
     for p in range(batch.n):
@@ -263,8 +264,8 @@ def test_concurrent_batches_equal_one_stream(precision):
         jd = [dev(j, cd) for j in J]
         g_psi = [dev(x, cd) for x in psi0]
         e_psi = [dev(x, cd) for x in psi0]
-        g = F.Plan(batch.problems(), precision=precision, flags=F.PLAN_USE_GRAPH | 1)
-        e = F.Plan(batch.problems(), precision=precision, flags=1)
+        g = F.Plan(batch.problems(), precision=precision, flags=F.PLAN_USE_GRAPH | 1 | pw)
+        e = F.Plan(batch.problems(), precision=precision, flags=1 | pw)
         assert g.query()["streams"] == 4
         for call in range(4):  # the same pointers each call: one capture, then replays
             g.step(g_psi, [j[0] for j in jd], n_steps=1)

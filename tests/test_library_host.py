@@ -98,6 +98,9 @@ def test_plan_rejects_mixed_kinds_and_bad_flags():
         F.fdetd_plan([a], flags=F.PLAN_USE_GRAPH, stream=0)   # graphs need a real stream
     with pytest.raises(F.FdetdError):
         F.fdetd_plan([a], precision=7)
+    with pytest.raises(F.FdetdError):
+        F.fdetd_plan([a], flags=256)
+    assert "unknown flag" in F.fdetd_last_error(None)
 
 
 def test_header_layout_matches_binding(tmp_path):
@@ -121,7 +124,8 @@ def test_header_layout_matches_binding(tmp_path):
               "FDETD_PLAN_SKIP_STABILITY": binding.PLAN_SKIP_STABILITY, "FDETD_PLAN_USE_GRAPH": binding.PLAN_USE_GRAPH,
               "FDETD_PLAN_PROFILE": binding.PLAN_PROFILE, "FDETD_PLAN_NO_AUTOTUNE": binding.PLAN_NO_AUTOTUNE,
               "FDETD_PLAN_ONE_STREAM": binding.PLAN_ONE_STREAM,
-              "FDETD_PLAN_CURRENT_CORRECTION": binding.PLAN_CURRENT_CORRECTION}
+              "FDETD_PLAN_CURRENT_CORRECTION": binding.PLAN_CURRENT_CORRECTION,
+              "FDETD_PLAN_MIXED_WIDTHS": binding.PLAN_MIXED_WIDTHS, "FDETD_PLAN_PER_WIDTH": binding.PLAN_PER_WIDTH}
     for k in consts:
         lines.append(f'printf("const {k} %lld\\n", (long long)({k}));')
     lines.append("return 0; }")
