@@ -103,6 +103,9 @@ struct ProbDesc {
     double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
     double sh[kMaxND];                                   // half-shift weights s_j (current staging)
     double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
+    // the same stencil tables rounded to float, for float arithmetic (its operands are these roundings)
+    float azf[kMaxND], arf[kMaxND];
+    float bzf[kMaxND + 1], brf[kMaxND + 1], dzcf[kMaxND], drcf[kMaxND];
 };
 
 // Descriptor of one problem (sizes, tiling with seg rows per segment, coefficient tables; pointers and

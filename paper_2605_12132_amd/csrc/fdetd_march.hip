@@ -142,17 +142,21 @@ template <> struct ibits<float2> { using I = unsigned long long; };
 template <> struct ibits<float> { using I = unsigned int; };
 // Element i of the array at p.  Callers pass a wave-uniform p (a row start, kept in scalar registers) and a
 // small per-lane i, so the loads use the scalar-base + 32-bit-vector-offset addressing form.
+// The byte offset is formed in 32 bits (a row of a plane is far below 4 GiB), which is what that addressing
+// form adds to the scalar base.
 template <typename T>
 __device__ __forceinline__ T gld(const void *p, unsigned i)
 {
     using I = typename ibits<T>::I;
-    return __builtin_bit_cast(T, ((const FDETD_GLOBAL I *)p)[i]);
+    const unsigned off = i * (unsigned)sizeof(I);
+    return __builtin_bit_cast(T, *(const FDETD_GLOBAL I *)((const FDETD_GLOBAL char *)p + off));
 }
 template <typename T>
 __device__ __forceinline__ void gst(void *p, unsigned i, T v)
 {
     using I = typename ibits<T>::I;
-    ((FDETD_GLOBAL I *)p)[i] = __builtin_bit_cast(I, v);
+    const unsigned off = i * (unsigned)sizeof(I);
+    *(FDETD_GLOBAL I *)((FDETD_GLOBAL char *)p + off) = __builtin_bit_cast(I, v);
 }
 // Start of row q of component c of a vector of planes of P elements each (row length nz S elements).
 template <typename E>
@@ -166,6 +170,14 @@ __device__ __forceinline__ const E *row_ptr(const void *base, int c, size_t P, i
 #define FDETD_CONST __attribute__((address_space(4)))
 using CDesc = const FDETD_CONST ProbDesc;
 __device__ __forceinline__ double cld(const double *p, int i) { return ((const FDETD_CONST double *)p)[i]; }
+// Stencil coefficient j of a table in the arithmetic type: the float copy for float arithmetic (no
+// conversion per tap), the double table otherwise.
+template <typename AR>
+__device__ __forceinline__ AR tap(const FDETD_CONST double *d, const FDETD_CONST float *f, int j)
+{
+    if constexpr (sizeof(AR) == 4) return f[j];
+    else return d[j];
+}
 
 // Storage access.  FP64 (double2 storage, K = 1): element = one double, index 2*(row*nz + col) + part.
 // FP32 (float2 storage, K = 2): element = one float2, index row*nz + col.
@@ -317,14 +329,17 @@ __device__ __forceinline__ lv<AR, K> keep_if(bool c, lv<AR, K> x)
 }
 
 // March rows k0 .. k1-1: fill() loads the window of rows above k0, row(in, k, live) consumes the inputs of
-// row k, fetch(k) issues the loads of row k.  FDETD_PREFETCH rows are in flight.  The loop is unrolled by the ring length and each slot is
+// row k, fetch(k) issues the loads of row k.  PF rows are in flight, in a ring of PF slots; each slot is
 // refilled in place once its row has been consumed: moving a slot whose loads are still in flight to
 // another register would make the wave wait for them.  For the same reason a slot holds the loaded words
-// only; masks, scale factors and sums are applied in row().  Rows past the segment end (fewer than
-// FDETD_PREFETCH) run on the clamped last row with live = false and store nothing.
-template <typename In, int PF, typename Fetch, typename Row, typename Fill>
+// only; masks, scale factors and sums are applied in row().  The loop body holds U rows (a multiple of PF):
+// inside it the rho windows slide by renaming, and only at its end do they move between registers, so
+// the moves per row fall as 1/U.  Rows past the segment end (fewer than U) run on the clamped last row
+// with live = false and store nothing.
+template <typename In, int PF, int U, typename Fetch, typename Row, typename Fill>
 __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &row, Fill &fill)
 {
+    static_assert(U % PF == 0, "the loop body holds whole rounds of the ring");
     In ring[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) ring[p] = fetch(k0 + p < k1 ? k0 + p : k1 - 1);
@@ -333,16 +348,20 @@ __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &ro
     // ring's loads outstanding in another order than the loop issues them would have every row wait as if
     // for its slot being the newest.  (vmcnt 0; expcnt and lgkmcnt left at their maxima 7 and 15.)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    for (int kb = k0; kb < k1; kb += PF) {
+    for (int kb = k0; kb < k1; kb += U) {
 #pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const int k = kb + p;
-            row(ring[p], k < k1 ? k : k1 - 1, k < k1);
+        for (int u = 0; u < U; ++u) {
+            const int k = kb + u;
+            row(ring[u % PF], k < k1 ? k : k1 - 1, k < k1);
             const int kn = k + PF;
-            ring[p] = fetch(kn < k1 ? kn : k1 - 1);
+            ring[u % PF] = fetch(kn < k1 ? kn : k1 - 1);
         }
     }
 }
+// Rows per loop body of a code path: FDETD_ROW_UNROLL rounds of its prefetch ring.
+#ifndef FDETD_ROW_UNROLL
+#define FDETD_ROW_UNROLL 2
+#endif
 
 // Prefetch depth of a code path.  HEAVY paths (the first
 // stage's current rows, the last stage's compensation words) carry more words per row and keep one row
@@ -533,14 +552,14 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         // D_z^(+) at primary column i: staggered columns i + j and i - j + 1
 #pragma unroll 4
         for (int j = 1; j <= ND; ++j) {
-            const AR az = (AR)D.az[j - 1];
+            const AR az = tap<AR>(D.az, D.azf, j - 1);
             zth = fmav(az, lds_at<AR, V>(lds[0], own + j * S) - lds_at<AR, V>(lds[0], own - (j - 1) * S), zth);
             zr = fmav(az, lds_at<AR, V>(lds[1], own + j * S) - lds_at<AR, V>(lds[1], own - (j - 1) * S), zr);
         }
         // D^(+) along rho at primary row k: staggered rows k + j (slot ND-1+j) and k - j + 1 (slot ND-j)
 #pragma unroll
         for (int j = 1; j <= ND; ++j) {
-            const AR ar = (AR)D.ar[j - 1];
+            const AR ar = tap<AR>(D.ar, D.arf, j - 1);
             rz = fmav(ar, Wz[ND - 1 + j] - Wz[ND - j], rz);
             rg = fmav(ar, Wg[ND - 1 + j] - Wg[ND - j], rg);
         }
@@ -565,7 +584,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>(), FDETD_ROW_UNROLL * prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -657,14 +676,14 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         // D_z^(-) at staggered column i: primary columns i + j - 1 and i - j
 #pragma unroll 4
         for (int j = 1; j <= ND; ++j) {
-            const AR az = (AR)D.az[j - 1];
+            const AR az = tap<AR>(D.az, D.azf, j - 1);
             zth = fmav(az, lds_at<AR, V>(lds[0], own + (j - 1) * S) - lds_at<AR, V>(lds[0], own - j * S), zth);
             zr = fmav(az, lds_at<AR, V>(lds[1], own + (j - 1) * S) - lds_at<AR, V>(lds[1], own - j * S), zr);
         }
         // D^(-) along rho at staggered row k: primary rows k + j - 1 (slot ND+j-1) and k - j (slot ND-j)
 #pragma unroll
         for (int j = 1; j <= ND; ++j) {
-            const AR ar = (AR)D.ar[j - 1];
+            const AR ar = tap<AR>(D.ar, D.arf, j - 1);
             rz = fmav(ar, Wz[ND + j - 1] - Wz[ND - j], rz);
             rg = fmav(ar, Wg[ND + j - 1] - Wg[ND - j], rg);
         }
@@ -686,7 +705,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>(), FDETD_ROW_UNROLL * prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 // Tile of block b.  Tiles are numbered problem by problem, (half,) segment, strip -- strips fastest --
@@ -865,19 +884,19 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         put_row<V, ND>(RowPart<V>{from_lv<E>(Wa[ND]), cu.ah}, L, H, lds);  // own element: the window's row k
         __syncthreads();
         const L_ a0 = Wa[ND];
-        L_ lz = (AR)D.bz[0] * a0, d1z = zero;
+        L_ lz = tap<AR>(D.bz, D.bzf, 0) * a0, d1z = zero;
 #pragma unroll 4
         for (int j = 1; j <= ND; ++j) {
             const L_ zp = lds_at<AR, V>(lds, own + j * S), zm = lds_at<AR, V>(lds, own - j * S);
-            lz = fmav((AR)D.bz[j], zp + zm, lz);
-            d1z = fmav((AR)D.dzc[j - 1], zp - zm, d1z);
+            lz = fmav(tap<AR>(D.bz, D.bzf, j), zp + zm, lz);
+            d1z = fmav(tap<AR>(D.dzc, D.dzcf, j - 1), zp - zm, d1z);
         }
-        L_ lr = (AR)D.br[0] * a0, d1r = zero;
+        L_ lr = tap<AR>(D.br, D.brf, 0) * a0, d1r = zero;
 #pragma unroll
         for (int j = 1; j <= ND; ++j) {
             const L_ rp = Wa[ND + j], rm = Wa[ND - j];
-            lr = fmav((AR)D.br[j], rp + rm, lr);
-            d1r = fmav((AR)D.drc[j - 1], rp - rm, d1r);
+            lr = fmav(tap<AR>(D.br, D.brf, j), rp + rm, lr);
+            d1r = fmav(tap<AR>(D.drc, D.drcf, j - 1), rp - rm, d1r);
         }
         // m^2 / rho^2 + chi~ with chi~ = chi + sigma^2 (absorbing layer; sigma = 0 outside it)
         const AR sig = szi + (AR)cld(D.sr, k);
@@ -926,7 +945,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
 #pragma unroll
         for (int t = 0; t < W - 1; ++t) Wa[t] = Wa[t + 1];
     };
-    march_rows<In, prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
+    march_rows<In, prefetch_of<V, AR, ND, COMP>(), FDETD_ROW_UNROLL * prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
 template <typename V, int ND, bool COMP, bool AXIS>
@@ -1035,7 +1054,7 @@ __device__ __forceinline__ void stagger_tile(const BatchArgs &A, int t)
 #pragma unroll
         for (int t2 = 0; t2 < 2 * ND - 1; ++t2) W[t2] = W[t2 + 1];
     };
-    march_rows<In, FDETD_PREFETCH>(k0, k1, fetch, row, fill);
+    march_rows<In, FDETD_PREFETCH, FDETD_PREFETCH>(k0, k1, fetch, row, fill);
 }
 
 template <typename V, int ND>

@@ -1933,6 +1933,16 @@ void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbD
         D.bz[k] = d2[k] / (d.dz * d.dz);
         D.br[k] = d2[k] / (d.dr * d.dr);
     }
+    for (int k = 0; k < kMaxND; ++k) {
+        D.azf[k] = (float)D.az[k];
+        D.arf[k] = (float)D.ar[k];
+        D.dzcf[k] = (float)D.dzc[k];
+        D.drcf[k] = (float)D.drc[k];
+    }
+    for (int k = 0; k <= kMaxND; ++k) {
+        D.bzf[k] = (float)D.bz[k];
+        D.brf[k] = (float)D.br[k];
+    }
 }
 
 void set_last_error(const char *msg) { g_last_error = msg; }
