@@ -219,8 +219,8 @@ def kernel_source_hash():
 
 def measured_traffic(precision_tag, seg_rows):
     """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration) from
-    the committed PMC summary, or None when it is missing, was taken on other kernel sources or at
-    another segment length than seg_rows."""
+    the committed PMC summary, or None when it is missing, was taken on other kernel sources or holds no
+    figure for segments of seg_rows rows."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -229,9 +229,7 @@ def measured_traffic(precision_tag, seg_rows):
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_") and ":" in line)
     if fields.get("traffic_source_hash", "").strip() != kernel_source_hash():
         return None
-    if fields.get(f"traffic_seg_rows_{precision_tag}", "").strip() != str(seg_rows):
-        return None
-    v = fields.get(f"traffic_bytes_per_launch_{precision_tag}")
+    v = fields.get(f"traffic_bytes_per_launch_{precision_tag}_seg{seg_rows}")
     return int(float(v)) if v else None
 
 
@@ -288,6 +286,57 @@ def graph_workload_pass(w, steps, warmup, tag, extra_flags=0):
     return dict(workload=w.name, problems=w.n, cells=cells, steps=steps, warmup=warmup, graph=True,
                 current="bunch + SplitMix64 noise made in the graph", fp64=res["fp64"], fp32c=res["fp32c"],
                 fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"], fp32c_error_vs_fp64=errs)
+
+
+def batched_profile(w, precision, steps, extra_flags=0):
+    """Eager pass of the batched workload with HIP events around every stage launch (one stream): the
+    stage kernels' aggregate rate at 21 complex values per cell and stage, and the launches per step."""
+    import torch
+    import paper_2605_12132_amd as F
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    psi = initial_state(w, cd)
+    jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+    plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE | extra_flags)
+    plan.step_graph(psi, bunch_jgen(w, 0), jw, n_steps=steps)
+    info = plan.query()
+    plan.close()
+    n, ms = info["profiled_launches"], info["profiled_ms"]
+    bytes_total = steps * w.taylor_order * w.cells() * bytes_per_stage(precision)
+    achieved = bytes_total / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_maxwell_stage",
+                launches=n, avg_launch_us=round(ms / n * 1e3, 2), stage_ms_per_step=round(ms / steps, 4),
+                bytes_per_step=int(bytes_total / steps), bytes_per_cell=bytes_per_stage(precision),
+                timing=f"HIP events around each stage launch, eager pass of {steps} steps on one stream "
+                       "(every stage counted at 21 complex values per cell)")
+
+
+def batched_main(args):
+    """--workload batched: the 64-problem uneven batch alone (graph path, default launch grouping), with the
+    stage kernels' aggregate rate from an eager pass; for profiling its launches apart from the headline."""
+    import paper_2605_12132_amd as F
+    import paper_2605_12132_amd.inputs as I
+    w = I.batched_uneven()
+    K, W = args.steps, args.warmup
+    extra = F.PLAN_PER_WIDTH if args.grouping == "per-width" else (F.PLAN_MIXED_WIDTHS if args.grouping == "mixed" else 0)
+    res = graph_workload_pass(w, K, W, f"batched ({args.grouping} grouping)", extra)
+    roof = {pt: batched_profile(w, prec, args.profile_steps, extra) for pt, prec in (("fp64", F.FP64), ("fp32c", F.FP32C))}
+    for pt in roof:
+        log(f"batched {pt} stage kernels: {roof[pt]['stage_ms_per_step']} ms per step, {roof[pt]['achieved']} GB/s "
+            f"({roof[pt]['frac'] * 100:.1f}% of HBM), {roof[pt]['launches'] // args.profile_steps} stage launches per step")
+    r64, r32 = res["fp64"], res["fp32c"]
+    out = {
+        "metric": METRIC, "value": r64["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "problems": w.n, "cells": w.cells(), "taylor_order": w.taylor_order,
+                   "fd_orders": sorted(set(w.fd_order)), "grouping": args.grouping, "graph": True,
+                   "current": "bunch + SplitMix64 noise made in the graph", "parallelism": "single GPU"},
+        "roofline": roof["fp64"], "cpu_baseline": None, "launches_per_step": r64["launches_per_step"],
+        "fp32c": dict(r32, roofline=roof["fp32c"], dtype="f32+comp"),
+        "fp32c_error_vs_fp64": res["fp32c_error_vs_fp64"],
+    }
+    print(json.dumps(out), flush=True)
 
 
 def sources_pass(w, smp):
@@ -584,6 +633,10 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200, help="0: skip")
     ap.add_argument("--correction-steps", type=int, default=50, help="0: skip")
     ap.add_argument("--envelope-steps", type=int, default=2000, help="0: skip")
+    ap.add_argument("--workload", choices=("lwfa", "batched"), default="lwfa",
+                    help="lwfa: the headline (LWFA-scale grid); batched: the 64-problem uneven batch alone")
+    ap.add_argument("--grouping", choices=("default", "per-width", "mixed"), default="default",
+                    help="launch grouping of the batched workload's stencil widths")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain 1 GiB device copy used to scale the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -599,6 +652,9 @@ def main():
 
     if args.calibrate_copy:
         print(json.dumps(copy_calibration()), flush=True)
+        return
+    if args.workload == "batched":
+        batched_main(args)
         return
     w = I.lwfa_scale()
     K, W = args.steps, args.warmup

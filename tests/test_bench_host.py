@@ -22,16 +22,18 @@ def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
         return
     text = open(bench.TRAFFIC_FILE).read()
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_"))
-    seg64 = int(fields["traffic_seg_rows_fp64"])
-    seg32 = int(fields["traffic_seg_rows_fp32c"])
-    t64 = bench.measured_traffic("fp64", seg64)
-    t32 = bench.measured_traffic("fp32c", seg32)
-    if fields["traffic_source_hash"].strip() == bench.kernel_source_hash():  # counters taken on these sources
-        assert t64 == int(float(fields["traffic_bytes_per_launch_fp64"])) and t64 > 0
-        assert t32 == int(float(fields["traffic_bytes_per_launch_fp32c"])) and t32 > 0
-    else:  # the kernel changed since: no traffic figure until the counters are taken again
-        assert t64 is None and t32 is None
-    # another tiling, or other sources: no traffic figure
-    assert bench.measured_traffic("fp64", seg64 * 2) is None
+    entries = [(k[len("traffic_bytes_per_launch_"):].split("_seg"), v) for k, v in fields.items()
+               if k.startswith("traffic_bytes_per_launch_")]
+    assert entries
+    current = fields["traffic_source_hash"].strip() == bench.kernel_source_hash()
+    for (tag, seg), v in entries:
+        t = bench.measured_traffic(tag, int(seg))
+        if current:  # counters taken on these sources
+            assert t == int(float(v)) and t > 0
+        else:  # the kernel changed since: no traffic figure until the counters are taken again
+            assert t is None
+    # a tiling without counters, or other sources: no traffic figure
+    (tag, seg), _ = entries[0]
+    assert bench.measured_traffic(tag, 3 * int(seg)) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic("fp64", seg64) is None
+    assert bench.measured_traffic(tag, int(seg)) is None
