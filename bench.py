@@ -674,28 +674,44 @@ def main():
     rate32 = cells * K / (ms32 * 1e-3)
     roof32 = profile_pass(w, F.FP32C, args.profile_steps, jg, info32["seg_rows"])
     errs = fp32c_errors(w, psi64, psi32)
-    del psi64, psi32
+    del psi32
     torch.cuda.empty_cache()
+    psi32i, ms32i, t32i, info32i = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c,
+                                                  extra_flags=F.PLAN_INCREMENT_FORM)
+    rate32i = cells * K / (ms32i * 1e-3)
+    errs_i = fp32c_errors(w, psi64, psi32i)
+    del psi64, psi32i
+    torch.cuda.empty_cache()
+    log(f"FP32C increment form: {ms32i / K:.4f} ms/step, {rate32i:.4g} cell-updates/s "
+        f"({info32i['launches_per_step']} launches per step), errors after {W + K} steps {errs_i}")
     log(f"FP32C: {ms32 / K:.4f} ms/step, {rate32:.4g} cell-updates/s, stage kernel {roof32['avg_launch_us']} us "
         f"({roof32['frac'] * 100:.1f}%), errors after {W + K} steps {errs}")
     fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
                  error_vs_fp64_after_steps=W + K, **errs,
                  tiling=dict(seg_rows=info32["seg_rows"], seg_rows_axis=info32["seg_rows_axis"],
                              autotune_ms=round(info32["autotune_ms"], 1)), **t32)
+    fp32c_inc = dict(value=rate32i, ms_per_step=ms32i / K, dtype="f32+comp, increment form", vs_fp64=rate32i / rate64,
+                     vs_fp32c=rate32i / rate32, launches_per_step=info32i["launches_per_step"],
+                     error_vs_fp64_after_steps=W + K, **errs_i, **t32i)
 
     full = None
     if args.full_steps > 0 and not args.headline_only:
         res, psis = {}, {}
-        for pt, prec, seg in (("fp64", F.FP64, args.seg_rows_fp64), ("fp32c", F.FP32C, args.seg_rows_fp32c)):
-            psi, ms, tt, info = run_graph_path(w, prec, args.full_steps, 0, jg, seg)
+        for pt, prec, seg, fl in (("fp64", F.FP64, args.seg_rows_fp64, 0), ("fp32c", F.FP32C, args.seg_rows_fp32c, 0),
+                                  ("fp32c_increment", F.FP32C, args.seg_rows_fp32c, F.PLAN_INCREMENT_FORM)):
+            psi, ms, tt, info = run_graph_path(w, prec, args.full_steps, 0, jg, seg, extra_flags=fl)
             res[pt] = dict(value=cells * args.full_steps / (ms * 1e-3), ms_per_step=ms / args.full_steps, **tt)
             psis[pt] = psi
             log(f"full length {pt}: {args.full_steps} steps, {ms / args.full_steps:.3f} ms/step, "
                 f"{res[pt]['value']:.4g} cell-updates/s ({tt})")
         full = dict(steps=args.full_steps, graph=True, fp64=res["fp64"], fp32c=res["fp32c"],
+                    fp32c_increment=res["fp32c_increment"],
                     fp32c_vs_fp64=res["fp32c"]["value"] / res["fp64"]["value"],
-                    fp32c_error_vs_fp64=fp32c_errors(w, psis["fp64"], psis["fp32c"]))
-        log(f"full length FP32C error vs FP64 after {args.full_steps} steps: {full['fp32c_error_vs_fp64']}")
+                    fp32c_error_vs_fp64=fp32c_errors(w, psis["fp64"], psis["fp32c"]),
+                    fp32c_increment_vs_fp64=res["fp32c_increment"]["value"] / res["fp64"]["value"],
+                    fp32c_increment_error_vs_fp64=fp32c_errors(w, psis["fp64"], psis["fp32c_increment"]))
+        log(f"full length FP32C error vs FP64 after {args.full_steps} steps: {full['fp32c_error_vs_fp64']}; "
+            f"increment form {full['fp32c_increment_error_vs_fp64']}")
         del psis, psi
         torch.cuda.empty_cache()
 
@@ -736,6 +752,7 @@ def main():
         "tiling": dict(seg_rows=info64["seg_rows"], autotune_ms=round(info64["autotune_ms"], 1)),
         "launches_per_step": info64["launches_per_step"],
         "fp32c": fp32c,
+        "fp32c_increment": fp32c_inc,
         "full_length": full,
         **extra,
     }

@@ -100,6 +100,8 @@ struct ProbDesc {
                                              // instead of the caller's (null without correction)
     const double *sz, *sr;                   // envelope absorbing layer: sigma_z per column, sigma_rho per
                                              // row (all zero without a layer); null for Maxwell problems
+    void *pbuf;                              // FP32C increment form: P = H psi of the step (6 planes)
+    const void *zero;                        // FP32C increment form: 6 zero planes of at least this size
     double az[kMaxND], ar[kMaxND], cax[kMaxND];          // Maxwell
     double sh[kMaxND];                                   // half-shift weights s_j (current staging)
     double bz[kMaxND + 1], br[kMaxND + 1], dzc[kMaxND], drc[kMaxND];  // envelope
@@ -122,6 +124,10 @@ struct BatchArgs {
     int ntiles, ntiles_ax;  // main tiles and (FP32 storage) near-axis tiles, FP64 arithmetic, in one launch
     int n, N;               // stage index n (N-1 .. 0) and Taylor order N
     int has_src, compensated;
+    // FP32C increment form (Maxwell): the stage vector is the increment d = v - psi, and stage n writes
+    // d_n = beta_n Jbar + coef (P + H d_{n+1}) with P = H psi formed once per step (role 1: P = H psi_lo
+    // from zero, role 2: P += H psi_hi; role 0: a Horner stage), the last stage TwoSum(psi_hi, lo + d_0)
+    int increment, role;
     double beta_in, beta, coef;
     const void *psi[kMaxBatch];  // Maxwell psi, or envelope a
     const void *aux[kMaxBatch];  // Maxwell: current of this step (3 planes) or null; envelope: a_tilde

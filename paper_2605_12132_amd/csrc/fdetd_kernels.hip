@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void k_form_wn(BatchArgs A)
         for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const V x = psi[c * n + q], j = src[c][q];
+                const V x = A.increment ? V{0, 0} : psi[c * n + q], j = src[c][q];
                 w[c * n + q] = V{(R)((double)x.x + A.beta_in * (double)j.x), (R)((double)x.y + A.beta_in * (double)j.y)};
             }
         }

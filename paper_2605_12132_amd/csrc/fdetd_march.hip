@@ -222,6 +222,7 @@ struct Ctx {
     const void *vin, *psi;
     void *vout;
     const void *jr, *jt, *jz;  // Jbar planes (null without source)
+    const void *hi;            // increment form: the stored psi (hi words), read by the last stage
     int has_src, compensated;
     double beta_in, beta, coef;
 };
@@ -299,6 +300,23 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
         if (zero_slot) w = 0.0;
         gst<double>(orow, o, w);
     }
+}
+
+// The bracket coef multiplies: H v, or in the increment form P + H v (P = H psi of the step).
+template <bool INC, typename AR, typename V>
+__device__ __forceinline__ lv<AR, elem<V>::K> with_p(typename elem<V>::E p, lv<AR, elem<V>::K> hv)
+{
+    if constexpr (INC) return to_lv<AR>(p) + hv;
+    else return hv;
+}
+// What store_out adds the increment to: psi (Horner on v), nothing (increment form, stages n > 0: the
+// output is the increment itself), or the stored psi_hi (increment form, last stage, with lo).
+template <bool INC, bool COMP, typename E>
+__device__ __forceinline__ E out_base(E p, E h)
+{
+    if constexpr (!INC) return p;
+    else if constexpr (COMP) return h;
+    else return E{};
 }
 
 // Rows of input held in flight ahead of the row being computed.  One row of one wave is ~3 KB, and the
@@ -457,7 +475,7 @@ __device__ __forceinline__ lv<AR, elem<V>::K> lds_at(const typename elem<V>::E *
 //          dE_z     = -(i m / rho) B_rho + rho^-1 D^(+) (rho_(-) B_theta)
 // Window (staggered rows q = k - N_D + 1 + t, t = 0 .. 2N_D-1): B_z and g = rho_(-) B_theta.
 // --------------------------------------------------------------------------------------------------
-template <typename V, typename AR, int ND, bool SRC, bool COMP>
+template <typename V, typename AR, int ND, bool SRC, bool COMP, bool INC>
 __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     // ring of the last N_D + 1 raw B_theta rows (own elements): the z stencil of row k reads row k from here,
@@ -514,6 +532,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         RowPart<V> br;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
+        E h0, h1, h2;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -537,6 +556,12 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             x.l0 = ld_elem<V>(D.lo, ER, k, D, L);
             x.l1 = ld_elem<V>(D.lo, ETH, k, D, L);
             x.l2 = ld_elem<V>(D.lo, EZ, k, D, L);
+        }
+        x.h0 = x.h1 = x.h2 = E{};
+        if constexpr (INC && COMP) {
+            x.h0 = ld_elem<V>(A.hi, ER, k, D, L);
+            x.h1 = ld_elem<V>(A.hi, ETH, k, D, L);
+            x.h2 = ld_elem<V>(A.hi, EZ, k, D, L);
         }
         return x;
     };
@@ -571,12 +596,12 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
         __syncthreads();
         if (L.col && live) {
             const Coef<AR> coef = split_coef<AR>(A.coef), beta = split_coef<AR>(A.beta);
-            const L_ i0v = cfma(beta, to_lv<AR>(cu.j0), cmul(coef, t0 - zth));
-            const L_ i1v = cfma(beta, to_lv<AR>(cu.j1), cmul(coef, zr - rz));
-            const L_ i2v = cfma(beta, to_lv<AR>(cu.j2), cmul(coef, rip * rg - t2));
-            store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, cu.p0, cu.l0);
-            store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, cu.p1, cu.l1);
-            store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, cu.p2, cu.l2);
+            const L_ i0v = cfma(beta, to_lv<AR>(cu.j0), cmul(coef, with_p<INC, AR, V>(cu.p0, t0 - zth)));
+            const L_ i1v = cfma(beta, to_lv<AR>(cu.j1), cmul(coef, with_p<INC, AR, V>(cu.p1, zr - rz)));
+            const L_ i2v = cfma(beta, to_lv<AR>(cu.j2), cmul(coef, with_p<INC, AR, V>(cu.p2, rip * rg - t2)));
+            store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, out_base<INC, COMP>(cu.p0, cu.h0), cu.l0);
+            store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, out_base<INC, COMP>(cu.p1, cu.h1), cu.l1);
+            store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, out_base<INC, COMP>(cu.p2, cu.h2), cu.l2);
         }
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
@@ -595,7 +620,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 // In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed before
 // the launch (k_form_wn); otherwise psi or the previous stage's output.
 // --------------------------------------------------------------------------------------------------
-template <typename V, typename AR, int ND, bool COMP>
+template <typename V, typename AR, int ND, bool COMP, bool INC>
 __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     // ring of the last N_D + 1 raw E_theta rows (own elements), as in e_half
@@ -643,6 +668,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         RowPart<V> er;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
+        E h0, h1, h2;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -660,6 +686,12 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             x.l0 = ld_elem<V>(D.lo, BR, k, D, L);
             x.l1 = ld_elem<V>(D.lo, BTH, k, D, L);
             x.l2 = ld_elem<V>(D.lo, BZ, k, D, L);
+        }
+        x.h0 = x.h1 = x.h2 = E{};
+        if constexpr (INC && COMP) {
+            x.h0 = ld_elem<V>(A.hi, BR, k, D, L);
+            x.h1 = ld_elem<V>(A.hi, BTH, k, D, L);
+            x.h2 = ld_elem<V>(A.hi, BZ, k, D, L);
         }
         return x;
     };
@@ -695,9 +727,12 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         __syncthreads();
         if (L.col && live) {
             const Coef<AR> coef = split_coef<AR>(A.coef);
-            store_out<V, AR, COMP>(A, BR, k, L, cmul(coef, zth - t0), false, cu.p0, cu.l0);
-            store_out<V, AR, COMP>(A, BTH, k, L, cmul(coef, rz - zr), k == 0, cu.p1, cu.l1);
-            store_out<V, AR, COMP>(A, BZ, k, L, cmul(coef, t2 - ris * rg), k == 0, cu.p2, cu.l2);
+            store_out<V, AR, COMP>(A, BR, k, L, cmul(coef, with_p<INC, AR, V>(cu.p0, zth - t0)), false,
+                                   out_base<INC, COMP>(cu.p0, cu.h0), cu.l0);
+            store_out<V, AR, COMP>(A, BTH, k, L, cmul(coef, with_p<INC, AR, V>(cu.p1, rz - zr)), k == 0,
+                                   out_base<INC, COMP>(cu.p1, cu.h1), cu.l1);
+            store_out<V, AR, COMP>(A, BZ, k, L, cmul(coef, with_p<INC, AR, V>(cu.p2, t2 - ris * rg)), k == 0,
+                                   out_base<INC, COMP>(cu.p2, cu.h2), cu.l2);
         }
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
@@ -739,7 +774,7 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
 // AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage; V = float2 or,
 // for wide stencils, f2pair read in lane pairs): rows 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the
 // axis and its 1/rho factors, in FP64 arithmetic.
-template <typename V, int ND, bool SRC, bool COMP, bool AXIS>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool AXIS>
 __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     constexpr int S = elem<V>::S, CPW = WAVE / S;
@@ -751,23 +786,45 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     Ctx C;
     C.D = &D;
     const bool first = A.n == A.N - 1;
-    C.psi = A.psi[p];
-    // the first stage reads psi, except the B half of a step with a current: it reads the E part of
-    // w_N = psi + beta_in Jbar, which k_form_wn wrote into the second stage buffer before the launch
-    C.vin = first ? ((A.has_src && half == 1) ? D.buf[1] : C.psi) : D.buf[(A.N - 2 - A.n) & 1];
-    C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
+    if constexpr (INC) {
+        // increment form: the psi slot holds P.  Role 1: P = H lo (from the zero planes); role 2: P += H
+        // psi_hi, in place (P is read only at the output position).  Stages: vin = d_{n+1}; the first
+        // stage's d_N is beta_in Jbar in its E part (k_form_wn, second stage buffer) and zero in its B
+        // part; the last stage adds d_0 into (psi_hi, lo) in place.
+        if (A.role == 1) {
+            C.vin = D.lo;
+            C.psi = D.zero;
+            C.vout = D.pbuf;
+        } else if (A.role == 2) {
+            C.vin = A.psi[p];
+            C.psi = D.pbuf;
+            C.vout = D.pbuf;
+        } else {
+            C.vin = first ? ((A.has_src && half == 1) ? D.buf[1] : D.zero) : D.buf[(A.N - 2 - A.n) & 1];
+            C.psi = D.pbuf;
+            C.vout = A.n == 0 ? (void *)A.psi[p] : D.buf[(A.N - 1 - A.n) & 1];
+        }
+        C.hi = A.psi[p];
+    } else {
+        C.psi = A.psi[p];
+        // the first stage reads psi, except the B half of a step with a current: it reads the E part of
+        // w_N = psi + beta_in Jbar, which k_form_wn wrote into the second stage buffer before the launch
+        C.vin = first ? ((A.has_src && half == 1) ? D.buf[1] : C.psi) : D.buf[(A.N - 2 - A.n) & 1];
+        C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
+        C.hi = nullptr;
+    }
     C.has_src = A.has_src;
     const size_t pb = D.plane * sizeof(typename stor<V>::T);
     C.jr = A.has_src ? D.jbar : nullptr;
     C.jt = A.has_src ? (D.jth ? D.jth : (const char *)A.aux[p] + pb) : nullptr;  // corrected J_theta if any
     C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
-    C.compensated = A.compensated && A.n == 0;
+    C.compensated = A.compensated && A.n == 0 && A.role == 0;
     C.beta_in = A.beta_in;
     C.beta = A.beta;
     C.coef = A.coef;
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
-    if (half == 0) e_half<V, AR, ND, SRC, COMP>(C, i0, k0, k1, lds);
-    else b_half<V, AR, ND, COMP>(C, i0, k0, k1, lds);
+    if (half == 0) e_half<V, AR, ND, SRC, COMP, INC>(C, i0, k0, k1, lds);
+    else b_half<V, AR, ND, COMP, INC>(C, i0, k0, k1, lds);
 }
 
 // One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
@@ -785,7 +842,7 @@ constexpr int stage_lds_bytes()
     return 2 * lds_row_bytes<V, ND>() + (ND + 1) * WAVE * (int)sizeof(typename elem<V>::E);
 }
 
-template <typename V, int ND, bool SRC, bool COMP>
+template <typename V, int ND, bool SRC, bool COMP, bool INC>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
     // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
@@ -798,12 +855,12 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, INC, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, INC, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -1081,27 +1138,39 @@ hipError_t go_stagger(const BatchArgs &a, hipStream_t s)
 }
 
 // Launch stage n of a batch with the kernel variant its flags select.
-template <typename V, int ND, bool SRC, bool COMP>
+template <typename V, int ND, bool SRC, bool COMP, bool INC>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
-    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE),
-                       0, s, a);
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, INC>), dim3(blocks_of(a.ntiles_ax, a.ntiles)),
+                       dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 
+template <typename V, int ND, bool INC>
+hipError_t go_maxwell_i(const BatchArgs &a, hipStream_t s)
+{
+    const bool comp = sizeof(typename scal<V>::R) == 4 && a.compensated && a.n == 0 && a.role == 0;
+    if (comp) {
+        if constexpr (sizeof(typename scal<V>::R) == 4) {
+            if (a.has_src) return go_maxwell_v<V, ND, true, true, INC>(a, s);
+            return go_maxwell_v<V, ND, false, true, INC>(a, s);
+        }
+    }
+    if (a.has_src) return go_maxwell_v<V, ND, true, false, INC>(a, s);
+    return go_maxwell_v<V, ND, false, false, INC>(a, s);
+}
+
+// The increment form exists for FP32 storage (FP32C plans) only.
 template <typename V, int ND>
 hipError_t go_maxwell(const BatchArgs &a, hipStream_t s)
 {
-    const bool comp = sizeof(typename scal<V>::R) == 4 && a.compensated && a.n == 0;
-    if (comp) {
-        if constexpr (sizeof(typename scal<V>::R) == 4) {
-            if (a.has_src) return go_maxwell_v<V, ND, true, true>(a, s);
-            return go_maxwell_v<V, ND, false, true>(a, s);
-        }
+    if constexpr (sizeof(typename scal<V>::R) == 4) {
+        if (a.increment) return go_maxwell_i<V, ND, true>(a, s);
+    } else {
+        if (a.increment) return hipErrorInvalidValue;
     }
-    if (a.has_src) return go_maxwell_v<V, ND, true, false>(a, s);
-    return go_maxwell_v<V, ND, false, false>(a, s);
+    return go_maxwell_i<V, ND, false>(a, s);
 }
 
 template <typename V, int ND, bool COMP>
@@ -1134,12 +1203,12 @@ __device__ __forceinline__ void stage_tile_any(const BatchArgs &A, int t, unsign
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if constexpr (AXIS) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, false, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, false, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // AXIS: the launch covers the FP32C near-axis tiles only (their FP64-arithmetic code for all widths in one

@@ -44,6 +44,7 @@ struct Prob {
     double *gresp = nullptr;              // ... segment responses, forward then backward ([nr][nd] each)
     int seg = 0, nseg = 0;                // ... rows per segment of the partitioned solve, segments
     void *jth = nullptr;                  // current correction: corrected J_theta plane
+    void *pbuf = nullptr;                 // FP32C increment form: P = H psi of the step (6 planes of float2)
     void *fine = nullptr;                 // 2x supersampled gather: 24 planes (4 position sets per component),
                                           // allocated on first use
     int lz = 0, lr = 0;                   // its widths (0, 0: no layer)
@@ -88,6 +89,7 @@ struct fdetd_plan_s {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
+    void *zero = nullptr;  // FP32C increment form: 6 zero planes of the largest problem
 };
 
 namespace {
@@ -148,6 +150,7 @@ void free_prob(Prob &q)
     if (q.jth) (void)hipFree(q.jth);
     if (q.sr) (void)hipFree(q.sr);
     if (q.fine) (void)hipFree(q.fine);
+    if (q.pbuf) (void)hipFree(q.pbuf);
     q = Prob{};
 }
 
@@ -297,8 +300,29 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     A.N = b.N;
     A.has_src = j != nullptr;
     A.compensated = P->precision == FDETD_FP32C;
+    A.increment = (P->flags & FDETD_PLAN_INCREMENT_FORM) ? 1 : 0;
+    if (A.increment && b.ntiles + b.ntiles_ax) {
+        // P = H psi of the step in two passes, H lo from zero, then P += H psi_hi (coef 1, no current), with
+        // the stages' own operator (float stencils, FP64 near-axis rows): an operator for P that differed
+        // from the stages' by the rounding of its coefficients would put that difference into the step's
+        // dt^2 term, a steady drift of the energy instead of rounding noise
+        A.has_src = 0;
+        A.n = b.N - 1;
+        A.beta_in = A.beta = 0.0;
+        A.coef = 1.0;
+        for (int role = 1; role <= 2; ++role) {
+            A.role = role;
+            int rc = profile_begin(P, 18.0 * cells * eb);
+            if (rc) return rc;
+            if ((rc = launch_stage(P, b, A, s))) return rc;
+            if ((rc = profile_end(P))) return rc;
+        }
+        A.role = 0;
+        A.has_src = j != nullptr;
+    }
     if (j && b.ntiles + b.ntiles_ax) {
-        // E part of w_N = psi + beta_in Jbar into buf[1]: read by the B half of the first stage
+        // E part of w_N = psi + beta_in Jbar into buf[1] (increment form: of d_N = beta_in Jbar): read by the
+        // B half of the first stage
         A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
         size_t max_cells = 0;
         for (int t = 0; t < b.count; ++t) max_cells = std::max(max_cells, P->probs[b.members[t]].cells);
@@ -312,7 +336,8 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         // algorithmic bytes: vin (6c) + psi (6c) + Jbar (3c) + vout (6c); the first stage without a current
         // reads psi once as vin and as psi (12c); with one, its B half reads w_N from buf[1]
         const double cvals = (n == b.N - 1 && !j ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
-        const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0);
+        const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0) +
+                             (A.increment && n == 0 ? 6.0 * cells * eb : 0.0);
         int rc = profile_begin(P, bytes);
         if (rc) return rc;
         if ((rc = launch_stage(P, b, A, s))) return rc;
@@ -322,7 +347,7 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     for (int t = 0; t < b.count; ++t) {
         const int p = b.members[t];
         const Prob &q = P->probs[p];
-        if (q.d.taylor_order == 1) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, s));
+        if (q.d.taylor_order == 1 && !A.increment) HIPCHK(P, launch_copy(q.buf[0], psi[p], 6 * q.cells * eb, s));
         max_nz = std::max(max_nz, q.d.nz);
     }
     if (last_step_of_call) HIPCHK(P, launch_axis_fix_batch(prec, A, max_nz, s));
@@ -503,7 +528,9 @@ hipStream_t lane_stream(fdetd_plan_t P, const Batch &b) { return b.lane ? P->lan
 // launches per stage on one stream, and per-width batches on four streams overlapped those better.
 bool mixed_widths(const fdetd_plan_t P)
 {
-    if (P->kind != FDETD_MAXWELL || (P->flags & (FDETD_PLAN_CURRENT_CORRECTION | FDETD_PLAN_PER_WIDTH))) return false;
+    if (P->kind != FDETD_MAXWELL ||
+        (P->flags & (FDETD_PLAN_CURRENT_CORRECTION | FDETD_PLAN_PER_WIDTH | FDETD_PLAN_INCREMENT_FORM)))
+        return false;
     return (P->flags & FDETD_PLAN_MIXED_WIDTHS) || P->precision == FDETD_FP64;
 }
 
@@ -610,6 +637,8 @@ int build_batches(fdetd_plan_t P)
             D.buf[1] = q.buf[1];
             D.jbar = q.jbar;
             D.lo = q.lo;
+            D.pbuf = q.pbuf;
+            D.zero = P->zero;
             D.rinv_p = q.rinv_p;
             D.rinv_s = q.rinv_s;
             D.m2rinv2 = q.m2rinv2;
@@ -973,6 +1002,7 @@ void fdetd_destroy(fdetd_plan_t plan)
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
+    if (plan->zero) (void)hipFree(plan->zero);
     if (plan->ddesc) (void)hipFree(plan->ddesc);
     delete plan;
 }
@@ -991,8 +1021,10 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if (probs[p].kind != probs[0].kind)
             return fail(nullptr, FDETD_E_ARG, "fdetd_plan: all problems of a plan must have the same kind");
     }
-    if (flags & ~(FDETD_PLAN_PER_WIDTH * 2u - 1u))
-        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_PER_WIDTH * 2u - 1u));
+    if (flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u));
+    if ((flags & FDETD_PLAN_INCREMENT_FORM) && (precision != FDETD_FP32C || probs[0].kind != FDETD_MAXWELL))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_INCREMENT_FORM needs an FP32C Maxwell plan");
     if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: graph capture needs a non-default stream");
     if ((flags & FDETD_PLAN_CURRENT_CORRECTION) && probs[0].kind != FDETD_MAXWELL)
@@ -1030,14 +1062,16 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             (e = hipMalloc((void **)&q.rinv_s, q.d.nr * sizeof(double))) ||
             (e = hipMalloc((void **)&q.m2rinv2, q.d.nr * sizeof(double))) ||
             (P->kind == FDETD_ENVELOPE && ((e = hipMalloc((void **)&q.sz, q.d.nz * sizeof(double))) ||
-                                           (e = hipMalloc((void **)&q.sr, q.d.nr * sizeof(double)))))) {
+                                           (e = hipMalloc((void **)&q.sr, q.d.nr * sizeof(double))))) ||
+            ((flags & FDETD_PLAN_INCREMENT_FORM) && (e = hipMalloc(&q.pbuf, 6 * q.cells * 8)))) {
             rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
                       hipGetErrorString(e));
             break;
         }
         scratch += 2 * vec_b + (P->kind == FDETD_MAXWELL ? q.cells * eb : 0) +
                    (precision == FDETD_FP32C ? np * q.cells * 8 : 0) + 3 * q.d.nr * 8 +
-                   (P->kind == FDETD_ENVELOPE ? (q.d.nz + q.d.nr) * 8 : 0);
+                   (P->kind == FDETD_ENVELOPE ? (q.d.nz + q.d.nr) * 8 : 0) +
+                   ((flags & FDETD_PLAN_INCREMENT_FORM) ? 6 * q.cells * 8 : 0);
         std::vector<double> hr(q.d.nr), hs(q.d.nr), hm(q.d.nr);
         for (int k = 0; k < q.d.nr; ++k) {
             const double rho_k = (k + 0.5) * q.d.dr;
@@ -1084,6 +1118,9 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w.
             // (The w_N pass, 9c, is not counted: it is an implementation overhead of the first stage.)
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
+            // increment form: P = H lo (zeros, lo, P: 18c), P += H psi (psi, P, P: 18c); the last stage also
+            // reads psi (6c)
+            if (flags & FDETD_PLAN_INCREMENT_FORM) bytes_step += (int64_t)q.cells * eb * 42;
             // (staging, w_N, stage and axis-rule launches are counted per batch below)
         } else {
             // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
@@ -1106,6 +1143,14 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             }
         }
     }
+    if (rc == FDETD_OK && (flags & FDETD_PLAN_INCREMENT_FORM)) {
+        size_t zb = 0;
+        for (const Prob &q : P->probs) zb = std::max(zb, 6 * q.cells * 8);
+        hipError_t e = hipSuccess;
+        if ((e = hipMalloc(&P->zero, zb)) || (e = hipMemset(P->zero, 0, zb)))
+            rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: %s", hipGetErrorString(e));
+        scratch += zb;
+    }
     if (rc == FDETD_OK) rc = build_batches(P);
     double tune_ms = 0.0;
     if (rc == FDETD_OK) rc = autotune(P, tune_ms);
@@ -1125,7 +1170,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     for (const Batch &b : P->batches) {  // Maxwell: N stages (two launches each when a batch that mixes
                                          // widths has FP32C near-axis tiles), staging and w_N per batch
         const int per_stage = (b.nd < 0 && b.ntiles && b.ntiles_ax) ? 2 : 1;
-        launches += (int64_t)(per_stage * b.N + (P->kind == FDETD_MAXWELL ? 2 : 0)) * (b.ntiles + b.ntiles_ax > 0);
+        const int prepass = (flags & FDETD_PLAN_INCREMENT_FORM) ? 2 : 0;
+        launches += (int64_t)(per_stage * b.N + (P->kind == FDETD_MAXWELL ? 2 : 0) + prepass) * (b.ntiles + b.ntiles_ax > 0);
     }
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
