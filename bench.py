@@ -633,8 +633,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200, help="0: skip")
     ap.add_argument("--correction-steps", type=int, default=50, help="0: skip")
     ap.add_argument("--envelope-steps", type=int, default=2000, help="0: skip")
-    ap.add_argument("--workload", choices=("lwfa", "batched"), default="lwfa",
-                    help="lwfa: the headline (LWFA-scale grid); batched: the 64-problem uneven batch alone")
+    ap.add_argument("--workload", choices=("lwfa", "batched", "envelope"), default="lwfa",
+                    help="lwfa: the headline (LWFA-scale grid); batched: the 64-problem uneven batch alone; "
+                         "envelope: the envelope-in-plasma workload alone")
     ap.add_argument("--grouping", choices=("default", "per-width", "mixed"), default="default",
                     help="launch grouping of the batched workload's stencil widths")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -655,6 +656,14 @@ def main():
         return
     if args.workload == "batched":
         batched_main(args)
+        return
+    if args.workload == "envelope":
+        env = envelope_pass(args.envelope_steps)
+        print(json.dumps({"metric": METRIC, "value": env["fp64"]["value"], "unit": "cell-updates/s", "n_gpus": 1,
+                          "steps": args.envelope_steps, "ms_per_step": env["fp64"]["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": env["workload"]}, "roofline": None,
+                          "cpu_baseline": None, "envelope": env}), flush=True)
         return
     w = I.lwfa_scale()
     K, W = args.steps, args.warmup

@@ -144,19 +144,32 @@ template <> struct ibits<float> { using I = unsigned int; };
 // small per-lane i, so the loads use the scalar-base + 32-bit-vector-offset addressing form.
 // The byte offset is formed in 32 bits (a row of a plane is far below 4 GiB), which is what that addressing
 // form adds to the scalar base.
+// They go through a buffer resource whose base is that row start (four scalar registers built by scalar
+// instructions) and take the lane's byte offset as the vector offset: no per-load vector address
+// arithmetic.  Word 3 of the resource is the gfx9-family value for raw (untyped) buffer access; the
+// record count is left at its maximum, every offset being a lane's position within its row.
+constexpr int kBufWord3 = 0x00020000;
 template <typename T>
 __device__ __forceinline__ T gld(const void *p, unsigned i)
 {
     using I = typename ibits<T>::I;
     const unsigned off = i * (unsigned)sizeof(I);
-    return __builtin_bit_cast(T, *(const FDETD_GLOBAL I *)((const FDETD_GLOBAL char *)p + off));
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff, kBufWord3);
+    if constexpr (sizeof(I) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 template <typename T>
 __device__ __forceinline__ void gst(void *p, unsigned i, T v)
 {
     using I = typename ibits<T>::I;
     const unsigned off = i * (unsigned)sizeof(I);
-    *(FDETD_GLOBAL I *)((FDETD_GLOBAL char *)p + off) = __builtin_bit_cast(I, v);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, 0x7fffffff, kBufWord3);
+    if constexpr (sizeof(I) == 8) {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+    }
 }
 // Start of row q of component c of a vector of planes of P elements each (row length nz S elements).
 template <typename E>
