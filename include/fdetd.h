@@ -75,14 +75,14 @@ extern "C" {
                                         FP64 plans mix widths and FP32C plans batch per width (the faster
                                         grouping of each on a 64-problem batch of 13 widths); with both,
                                         FDETD_PLAN_PER_WIDTH wins                                          */
-#define FDETD_PLAN_INCREMENT_FORM 256u /* FP32C Maxwell plans: the Horner stages carry the increment
-                                        d_n = v_n - psi instead of v_n (the series of section 2.1 summed at
-                                        the size of its terms, not of psi), with P = H (psi + compensation
-                                        words) formed once per step by two extra launches with the stages'
-                                        own operator; the last stage adds d_0 into the stored (psi,
-                                        compensation word) pair by TwoSum.  About a fifth more HBM traffic
-                                        per step; per-width launch batches.  FDETD_E_ARG for FP64 or
-                                        envelope plans                                                     */
+#define FDETD_PLAN_INCREMENT_FORM 256u /* FP32C plans (Maxwell and envelope): the Horner stages carry the
+                                        increment d_n = v_n - psi instead of v_n (the series of sections
+                                        2.1 and 4.2 summed at the size of its terms, not of psi), with
+                                        P = H (psi + compensation words) formed once per step by two extra
+                                        launches with the stages' own operator; the last stage adds d_0
+                                        into the stored (psi, compensation word) pair by TwoSum.  About a
+                                        fifth more HBM traffic per step; per-width launch batches.
+                                        FDETD_E_ARG for FP64 plans                                         */
 
 typedef struct fdetd_plan_s *fdetd_plan_t;
 

@@ -884,12 +884,13 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 struct EnvCtx {
     CDesc *D;
     const void *vin_a, *vin_t, *psi_a, *psi_t, *chi;
+    const void *hi_a, *hi_t;  // increment form: the stored a, a~ (hi words), read by the last stage
     void *out_a, *out_t;
     int compensated;
     double coef;
 };
 
-template <typename V, typename AR, int ND, bool COMP>
+template <typename V, typename AR, int ND, bool COMP, bool INC>
 __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k1, typename elem<V>::E *lds)
 {
     constexpr int K = elem<V>::K, S = elem<V>::S;
@@ -928,6 +929,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         R chi;
         E pa, pt;
         typename elem<V>::Lo la, lt;
+        E ha, ht;
     };
     auto fetch = [&](int k) -> In {
         In x;
@@ -944,6 +946,11 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
             using Lo = typename elem<V>::Lo;
             x.la = gld<Lo>(row_ptr<Lo>(D.lo, 0, D.plane, nz, S, k), o);
             x.lt = gld<Lo>(row_ptr<Lo>(D.lo, 1, D.plane, nz, S, k), o);
+        }
+        x.ha = x.ht = E{};
+        if constexpr (INC && COMP) {
+            x.ha = gld<E>(row_ptr<E>(A.hi_a, 0, 0, nz, S, k), o);
+            x.ht = gld<E>(row_ptr<E>(A.hi_t, 0, 0, nz, S, k), o);
         }
         return x;
     };
@@ -976,40 +983,42 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
         if (L.col && live) {
             const L_ dtv = lr + (AR)cld(D.rinv_p, k) * d1r + lz - pot * a0 + rot;
             const Coef<AR> coef = split_coef<AR>(A.coef);
-            const L_ ia = cmul(coef, tin), it = cmul(coef, dtv);
+            const L_ ia = cmul(coef, with_p<INC, AR, V>(cu.pa, tin)), it = cmul(coef, with_p<INC, AR, V>(cu.pt, dtv));
+            // what the increment is added to: psi, nothing (increment form, n > 0) or the stored psi_hi
+            const E ba = out_base<INC, COMP>(cu.pa, cu.ha), bt = out_base<INC, COMP>(cu.pt, cu.ht);
             const unsigned o = (unsigned)L.eidx;
             void *ra = (void *)row_ptr<E>(A.out_a, 0, 0, nz, S, k), *rt = (void *)row_ptr<E>(A.out_t, 0, 0, nz, S, k);
             if constexpr (S == 1) {
                 if constexpr (COMP) {
                     float s0, e0, s1, e1, s2, e2, s3, e3;
-                    two_sum(cu.pa.x, (float)(ia.p[0] + (AR)cu.la.x), s0, e0);
-                    two_sum(cu.pa.y, (float)(ia.p[1] + (AR)cu.la.y), s1, e1);
-                    two_sum(cu.pt.x, (float)(it.p[0] + (AR)cu.lt.x), s2, e2);
-                    two_sum(cu.pt.y, (float)(it.p[1] + (AR)cu.lt.y), s3, e3);
+                    two_sum(ba.x, (float)(ia.p[0] + (AR)cu.la.x), s0, e0);
+                    two_sum(ba.y, (float)(ia.p[1] + (AR)cu.la.y), s1, e1);
+                    two_sum(bt.x, (float)(it.p[0] + (AR)cu.lt.x), s2, e2);
+                    two_sum(bt.y, (float)(it.p[1] + (AR)cu.lt.y), s3, e3);
                     gst<float2>(ra, o, float2{s0, s1});
                     gst<float2>(rt, o, float2{s2, s3});
                     gst<float2>((void *)row_ptr<float2>(D.lo, 0, D.plane, nz, 1, k), o, float2{e0, e1});
                     gst<float2>((void *)row_ptr<float2>(D.lo, 1, D.plane, nz, 1, k), o, float2{e2, e3});
                 } else {
-                    gst<float2>(ra, o, float2{(float)((AR)cu.pa.x + ia.p[0]), (float)((AR)cu.pa.y + ia.p[1])});
-                    gst<float2>(rt, o, float2{(float)((AR)cu.pt.x + it.p[0]), (float)((AR)cu.pt.y + it.p[1])});
+                    gst<float2>(ra, o, float2{(float)((AR)ba.x + ia.p[0]), (float)((AR)ba.y + ia.p[1])});
+                    gst<float2>(rt, o, float2{(float)((AR)bt.x + it.p[0]), (float)((AR)bt.y + it.p[1])});
                 }
             } else if constexpr (std::is_same<E, float>::value) {  // FP32 storage in lane pairs
                 if constexpr (COMP) {
                     float s0, e0, s1, e1;
-                    two_sum(cu.pa, (float)(ia.p[0] + (AR)cu.la), s0, e0);
-                    two_sum(cu.pt, (float)(it.p[0] + (AR)cu.lt), s1, e1);
+                    two_sum(ba, (float)(ia.p[0] + (AR)cu.la), s0, e0);
+                    two_sum(bt, (float)(it.p[0] + (AR)cu.lt), s1, e1);
                     gst<float>(ra, o, s0);
                     gst<float>(rt, o, s1);
                     gst<float>((void *)row_ptr<float>(D.lo, 0, D.plane, nz, 2, k), o, e0);
                     gst<float>((void *)row_ptr<float>(D.lo, 1, D.plane, nz, 2, k), o, e1);
                 } else {
-                    gst<float>(ra, o, (float)((AR)cu.pa + ia.p[0]));
-                    gst<float>(rt, o, (float)((AR)cu.pt + it.p[0]));
+                    gst<float>(ra, o, (float)((AR)ba + ia.p[0]));
+                    gst<float>(rt, o, (float)((AR)bt + it.p[0]));
                 }
             } else {
-                gst<double>(ra, o, (double)((AR)cu.pa + ia.p[0]));
-                gst<double>(rt, o, (double)((AR)cu.pt + it.p[0]));
+                gst<double>(ra, o, (double)((AR)ba + ia.p[0]));
+                gst<double>(rt, o, (double)((AR)bt + it.p[0]));
             }
         }
 #pragma unroll
@@ -1018,7 +1027,7 @@ __device__ __forceinline__ void env_march(const EnvCtx &A, int i0, int k0, int k
     march_rows<In, prefetch_of<V, AR, ND, COMP>(), FDETD_ROW_UNROLL * prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
 }
 
-template <typename V, int ND, bool COMP, bool AXIS>
+template <typename V, int ND, bool COMP, bool INC, bool AXIS>
 __device__ __forceinline__ void envelope_tile(const BatchArgs &A, int t, typename elem<V>::E *lds)
 {
     constexpr int S = elem<V>::S, CPW = WAVE / S;
@@ -1034,19 +1043,51 @@ __device__ __forceinline__ void envelope_tile(const BatchArgs &A, int t, typenam
     C.psi_a = A.psi[p];
     C.psi_t = A.aux[p];
     const void *ib = D.buf[(A.N - 2 - A.n) & 1], *ob = D.buf[(A.N - 1 - A.n) & 1];
-    C.vin_a = first ? C.psi_a : ib;
-    C.vin_t = first ? C.psi_t : (const char *)ib + pb;
-    const bool in_place = A.n == 0 && A.N > 1;
-    C.out_a = in_place ? (void *)C.psi_a : (void *)ob;
-    C.out_t = in_place ? (void *)C.psi_t : (void *)((const char *)ob + pb);
+    C.hi_a = C.psi_a;
+    C.hi_t = C.psi_t;
+    if constexpr (INC) {
+        // increment form (no source: d_N = 0): the psi slots hold P = H_a psi.  Role 1: P = H_a lo (from
+        // the zero planes); role 2: P += H_a psi_hi in place; stages read d_{n+1}, the first the zero
+        // planes; the last adds d_0 into (psi_hi, lo) in place.
+        const char *pbuf = (const char *)D.pbuf, *zero = (const char *)D.zero;
+        const char *lo = (const char *)D.lo;
+        if (A.role == 1) {
+            C.vin_a = lo;
+            C.vin_t = lo + pb;
+            C.psi_a = zero;
+            C.psi_t = zero + pb;
+            C.out_a = (void *)pbuf;
+            C.out_t = (void *)(pbuf + pb);
+        } else if (A.role == 2) {
+            C.vin_a = C.hi_a;
+            C.vin_t = C.hi_t;
+            C.psi_a = pbuf;
+            C.psi_t = pbuf + pb;
+            C.out_a = (void *)pbuf;
+            C.out_t = (void *)(pbuf + pb);
+        } else {
+            C.vin_a = first ? (const void *)zero : ib;
+            C.vin_t = first ? (const void *)(zero + pb) : (const char *)ib + pb;
+            C.psi_a = pbuf;
+            C.psi_t = pbuf + pb;
+            C.out_a = A.n == 0 ? (void *)C.hi_a : (void *)ob;
+            C.out_t = A.n == 0 ? (void *)C.hi_t : (void *)((const char *)ob + pb);
+        }
+    } else {
+        C.vin_a = first ? C.psi_a : ib;
+        C.vin_t = first ? C.psi_t : (const char *)ib + pb;
+        const bool in_place = A.n == 0 && A.N > 1;
+        C.out_a = in_place ? (void *)C.psi_a : (void *)ob;
+        C.out_t = in_place ? (void *)C.psi_t : (void *)((const char *)ob + pb);
+    }
     C.chi = A.chi[p];
-    C.compensated = A.compensated && A.n == 0;
+    C.compensated = A.compensated && A.n == 0 && A.role == 0;
     C.coef = A.coef;
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
-    env_march<V, AR, ND, COMP>(C, i0, k0, k1, lds);
+    env_march<V, AR, ND, COMP, INC>(C, i0, k0, k1, lds);
 }
 
-template <typename V, int ND, bool COMP>
+template <typename V, int ND, bool COMP, bool INC>
 __global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
 {
     using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
@@ -1056,11 +1097,11 @@ __global__ __launch_bounds__(WAVE) void k_envelope_stage(BatchArgs A)
     if (t < 0) return;
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
-            envelope_tile<VA, ND, COMP, true>(A, t, (typename elem<VA>::E *)smem);
+            envelope_tile<VA, ND, COMP, INC, true>(A, t, (typename elem<VA>::E *)smem);
             return;
         }
     }
-    envelope_tile<V, ND, COMP, false>(A, t, (typename elem<V>::E *)smem);
+    envelope_tile<V, ND, COMP, INC, false>(A, t, (typename elem<V>::E *)smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -1186,21 +1227,27 @@ hipError_t go_maxwell(const BatchArgs &a, hipStream_t s)
     return go_maxwell_i<V, ND, false>(a, s);
 }
 
-template <typename V, int ND, bool COMP>
+template <typename V, int ND, bool COMP, bool INC>
 hipError_t go_envelope_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
-    hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0, s, a);
+    hipLaunchKernelGGL((k_envelope_stage<V, ND, COMP, INC>), dim3(blocks_of(a.ntiles_ax, a.ntiles)), dim3(WAVE), 0,
+                       s, a);
     return hipGetLastError();
 }
 
+// The increment form exists for FP32 storage (FP32C plans) only.
 template <typename V, int ND>
 hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
 {
     if constexpr (sizeof(typename scal<V>::R) == 4) {
-        if (a.compensated && a.n == 0) return go_envelope_v<V, ND, true>(a, s);
+        const bool comp = a.compensated && a.n == 0 && a.role == 0;
+        if (a.increment) return comp ? go_envelope_v<V, ND, true, true>(a, s) : go_envelope_v<V, ND, false, true>(a, s);
+        if (comp) return go_envelope_v<V, ND, true, false>(a, s);
+    } else {
+        if (a.increment) return hipErrorInvalidValue;
     }
-    return go_envelope_v<V, ND, false>(a, s);
+    return go_envelope_v<V, ND, false, false>(a, s);
 }
 
 // --------------------------------------------------------------------------------------------------

@@ -398,6 +398,20 @@ int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void 
     }
     int rc = damp_layers(P, b, a, at, s);  // first factor exp(-sigma dt/4) of the split step
     if (rc) return rc;
+    A.increment = (P->flags & FDETD_PLAN_INCREMENT_FORM) ? 1 : 0;
+    if (A.increment && b.ntiles + b.ntiles_ax) {
+        // P = H_a psi of the step (of the damped state), H_a lo from zero, then P += H_a psi_hi, with the
+        // stages' own operator; chi of the step in both
+        A.n = b.N - 1;
+        A.coef = 1.0;
+        for (int role = 1; role <= 2; ++role) {
+            A.role = role;
+            if ((rc = profile_begin(P, 6.5 * cells * eb))) return rc;
+            if ((rc = launch_stage(P, b, A, s))) return rc;
+            if ((rc = profile_end(P))) return rc;
+        }
+        A.role = 0;
+    }
     for (int n = b.N - 1; n >= 0; --n) {
         A.n = n;
         A.coef = b.dt / (n + 1);
@@ -411,7 +425,7 @@ int enqueue_envelope_batch(fdetd_plan_t P, const Batch &b, void *const *a, void 
     for (int t = 0; t < b.count; ++t) {
         const int p = b.members[t];
         const Prob &q = P->probs[p];
-        if (q.d.taylor_order == 1) {
+        if (q.d.taylor_order == 1 && !A.increment) {
             const size_t plane_b = q.cells * eb;
             HIPCHK(P, launch_copy(q.buf[0], a[p], plane_b, s));
             HIPCHK(P, launch_copy((char *)q.buf[0] + plane_b, at[p], plane_b, s));
@@ -1023,8 +1037,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     }
     if (flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u))
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u));
-    if ((flags & FDETD_PLAN_INCREMENT_FORM) && (precision != FDETD_FP32C || probs[0].kind != FDETD_MAXWELL))
-        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_INCREMENT_FORM needs an FP32C Maxwell plan");
+    if ((flags & FDETD_PLAN_INCREMENT_FORM) && precision != FDETD_FP32C)
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_INCREMENT_FORM needs an FP32C plan");
     if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: graph capture needs a non-default stream");
     if ((flags & FDETD_PLAN_CURRENT_CORRECTION) && probs[0].kind != FDETD_MAXWELL)
@@ -1063,7 +1077,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
             (e = hipMalloc((void **)&q.m2rinv2, q.d.nr * sizeof(double))) ||
             (P->kind == FDETD_ENVELOPE && ((e = hipMalloc((void **)&q.sz, q.d.nz * sizeof(double))) ||
                                            (e = hipMalloc((void **)&q.sr, q.d.nr * sizeof(double))))) ||
-            ((flags & FDETD_PLAN_INCREMENT_FORM) && (e = hipMalloc(&q.pbuf, 6 * q.cells * 8)))) {
+            ((flags & FDETD_PLAN_INCREMENT_FORM) && (e = hipMalloc(&q.pbuf, np * q.cells * 8)))) {
             rc = fail(P, e == hipErrorOutOfMemory ? FDETD_E_NOMEM : FDETD_E_HIP, "fdetd_plan: problem %d: %s", p,
                       hipGetErrorString(e));
             break;
@@ -1071,7 +1085,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         scratch += 2 * vec_b + (P->kind == FDETD_MAXWELL ? q.cells * eb : 0) +
                    (precision == FDETD_FP32C ? np * q.cells * 8 : 0) + 3 * q.d.nr * 8 +
                    (P->kind == FDETD_ENVELOPE ? (q.d.nz + q.d.nr) * 8 : 0) +
-                   ((flags & FDETD_PLAN_INCREMENT_FORM) ? 6 * q.cells * 8 : 0);
+                   ((flags & FDETD_PLAN_INCREMENT_FORM) ? np * q.cells * 8 : 0);
         std::vector<double> hr(q.d.nr), hs(q.d.nr), hm(q.d.nr);
         for (int k = 0; k < q.d.nr; ++k) {
             const double rho_k = (k + 0.5) * q.d.dr;
@@ -1125,6 +1139,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         } else {
             // per stage: read v (2c), psi (2c), chi (1 real), write v (2c)
             bytes_step += (int64_t)q.cells * (eb * 6 + eb / 2) * N + (precision == FDETD_FP32C ? q.cells * 2 * 8 * 2 : 0);
+            // increment form: two P passes (6c + chi each) and psi_hi in the last stage (2c)
+            if (flags & FDETD_PLAN_INCREMENT_FORM) bytes_step += (int64_t)q.cells * (eb * 14 + eb);
         }
         if (!(flags & FDETD_PLAN_SKIP_STABILITY)) {
             double rho = 0.0;
@@ -1170,7 +1186,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     for (const Batch &b : P->batches) {  // Maxwell: N stages (two launches each when a batch that mixes
                                          // widths has FP32C near-axis tiles), staging and w_N per batch
         const int per_stage = (b.nd < 0 && b.ntiles && b.ntiles_ax) ? 2 : 1;
-        const int prepass = (flags & FDETD_PLAN_INCREMENT_FORM) ? 2 : 0;
+        const int prepass = (flags & FDETD_PLAN_INCREMENT_FORM) ? 2 : 0;  // the two P passes
         launches += (int64_t)(per_stage * b.N + (P->kind == FDETD_MAXWELL ? 2 : 0) + prepass) * (b.ntiles + b.ntiles_ax > 0);
     }
     P->info.launches_per_step = launches;

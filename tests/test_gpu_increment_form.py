@@ -15,7 +15,7 @@ pair by TwoSum.
 import numpy as np
 import pytest
 
-from helpers import dev, gpu_maxwell, grid_of, log, oracle_maxwell, rel_l2, tol_fp32c
+from helpers import dev, gpu_envelope, gpu_maxwell, grid_of, log, oracle_envelope, oracle_maxwell, rel_l2, tol_fp32c
 
 import oracle
 import paper_2605_12132_amd as F
@@ -158,3 +158,46 @@ def test_increment_form_step_graph_with_generated_current():
         d = rel_l2(got[p], eager[p])
         log(f"step_graph increment form m={w.m[p]}: vs eager with the host current {d:.2e}")
         assert d < 1e-6  # the generator's exp may differ from the host's in the last bits
+
+
+@pytest.mark.parametrize("order,m,N", [(8, 0, 4), (24, 1, 4), (4, 2, 1)])
+def test_envelope_increment_form_matches_oracle_on_random_fields(order, m, N):
+    dz = I.LAMBDA0 / 5
+    steps = 5
+    w = I.Workload("env_inc", 1, [203], [41], [m], [order], N, dz, 0.2 * I.UM, 0.5 * dz, steps, seed=8,
+                   extra=dict(a0=2.0, w0=4 * I.UM, ctau=3 * I.UM, zc=10 * I.UM, chi0=1e-3, mod=0.05))
+    rng = np.random.default_rng(order + 10 * m + N)
+    a0 = rand_state((41, 203), rng, 1)
+    at0 = rand_state((41, 203), rng, 1)
+    chi = I.envelope_chi(w)
+    ga, gt, info = gpu_envelope(w, [a0], [at0], [chi], steps, precision=F.FP32C, flags=1 | INC)
+    oa, ot = oracle_envelope(w, [a0], [at0], [chi], steps)
+    err = rel_l2(np.concatenate([ga[0].ravel(), gt[0].ravel()]), np.concatenate([oa[0].ravel(), ot[0].ravel()]))
+    log(f"envelope increment form order {order} m={m} N={N}: rel L2 {err:.2e} "
+        f"(bound {tol_fp32c(steps, N, envelope=True):.2e}), {info['launches_per_step']} launches per step")
+    assert err < tol_fp32c(steps, N, envelope=True)
+    assert info["launches_per_step"] == N + 2
+
+
+def test_envelope_increment_form_on_the_plasma_pulse_with_and_without_layers():
+    """The envelope-in-plasma pulse on a cut-down grid (1024 x 96), with and without absorbing layers: no
+    less accurate than plain FP32C (measured 1.1x more), graph == eager bit for bit.  The envelope's float
+    error sits mostly inside H_a, whose 2 i k0 (D_z a + a~) terms nearly cancel for a forward pulse, not in
+    the Horner intermediates the increment form keeps small."""
+    w = I.envelope_plasma().shrink(nz=1024, nr=96)
+    steps = 100
+    a0, at0 = I.envelope_initial(w)
+    chi = I.envelope_chi(w)
+    for lay in ((), ((0, 24, 16, 0.05, 2.0),)):
+        oa, ot = oracle_envelope(w, [a0], [at0], [chi], steps, absorbers=lay)
+        want = np.concatenate([oa[0].ravel(), ot[0].ravel()])
+        res = {}
+        for tag, flags in (("plain", 1), ("increment", 1 | INC), ("increment graph", 1 | INC | F.PLAN_USE_GRAPH)):
+            ga, gt, _ = gpu_envelope(w, [a0], [at0], [chi], steps, precision=F.FP32C, flags=flags, absorbers=lay)
+            res[tag] = (rel_l2(np.concatenate([ga[0].ravel(), gt[0].ravel()]), want), ga[0], gt[0])
+        ep, ei = res["plain"][0], res["increment"][0]
+        log(f"envelope pulse{' with absorbing layers' if lay else ''}, {steps} steps: FP32C {ep:.2e}, "
+            f"increment form {ei:.2e} (x{ep / ei:.1f})")
+        assert ei < 1.05 * ep
+        assert np.array_equal(res["increment"][1], res["increment graph"][1])
+        assert np.array_equal(res["increment"][2], res["increment graph"][2])
