@@ -181,7 +181,7 @@ def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_grap
     return psi, ms, dict(plan_s=round(plan_s, 2), capture_and_first_replay_s=round(capture_s, 2)), info
 
 
-def profile_pass(w, precision, steps, jgen_of, seg_rows):
+def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0):
     """Eager pass with HIP events around every stage kernel on the plan's stream: average duration and
     algorithmic bytes (21 complex values per cell).  The plan is given the segment length the timed plan's
     autotuning picked, so both run the same tiling."""
@@ -201,7 +201,7 @@ def profile_pass(w, precision, steps, jgen_of, seg_rows):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c", seg_rows),
+                traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c", seg_rows, seg_axis),
                 kernel="k_maxwell_stage", launches=n, avg_launch_us=round(avg_ms * 1e3, 2),
                 bytes_per_launch=int(bytes_per_launch), bytes_per_cell=bytes_per_stage(precision),
                 timing="HIP events around each stage launch on the plan's stream, eager pass of "
@@ -217,10 +217,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision_tag, seg_rows):
+def measured_traffic(precision_tag, seg_rows, seg_axis=0):
     """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration) from
-    the committed PMC summary, or None when it is missing, was taken on other kernel sources or holds no
-    figure for segments of seg_rows rows."""
+    the committed PMC summary, or None when it is missing, was taken on other kernel sources, holds no
+    figure for segments of seg_rows rows, or (FP32C) was taken with other near-axis segments."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -228,6 +228,8 @@ def measured_traffic(precision_tag, seg_rows):
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_") and ":" in line)
     if fields.get("traffic_source_hash", "").strip() != kernel_source_hash():
+        return None
+    if seg_axis and fields.get("traffic_seg_axis_fp32c", "").strip() != str(seg_axis):
         return None
     v = fields.get(f"traffic_bytes_per_launch_{precision_tag}_seg{seg_rows}")
     return int(float(v)) if v else None
@@ -681,11 +683,12 @@ def main():
     log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
     psi32, ms32, t32, info32 = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c)
     rate32 = cells * K / (ms32 * 1e-3)
-    roof32 = profile_pass(w, F.FP32C, args.profile_steps, jg, info32["seg_rows"])
+    roof32 = profile_pass(w, F.FP32C, args.profile_steps, jg, info32["seg_rows"], info32["seg_rows_axis"])
     errs = fp32c_errors(w, psi64, psi32)
     del psi32
     torch.cuda.empty_cache()
-    psi32i, ms32i, t32i, info32i = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c,
+    # the increment form takes the FP32C plan's tuned segment length (no second autotuning)
+    psi32i, ms32i, t32i, info32i = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c or info32["seg_rows"],
                                                   extra_flags=F.PLAN_INCREMENT_FORM)
     rate32i = cells * K / (ms32i * 1e-3)
     errs_i = fp32c_errors(w, psi64, psi32i)

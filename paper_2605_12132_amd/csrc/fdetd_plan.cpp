@@ -599,7 +599,17 @@ int default_seg_rows(int64_t row_strips_total)
     while (s < 64 && row_strips_total / (2 * s) >= 1024) s *= 2;
     return s;
 }
-constexpr int kSegAxis = 8;  // rows per segment of the FP32C near-axis launch
+constexpr int kSegAxis = 16;  // rows per segment of the FP32C near-axis tiles (16: 1-2 % faster than 8 on
+                               // the 64-problem batch and the LWFA-scale grid; 32 alike)
+// FDETD_SEG_AXIS overrides it (1 .. 64 rows)
+int axis_segment_rows()
+{
+    if (const char *e = std::getenv("FDETD_SEG_AXIS")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 64) return v;
+    }
+    return kSegAxis;
+}
 
 // Group problems into launch batches, fill the descriptor table and upload it.  P->seg_rows gives the
 // segment length of each batch; when it does not match the batch count the defaults are taken.
@@ -1964,7 +1974,7 @@ void describe_problem(const fdetd_problem_desc &d, int precision, int seg, ProbD
     if (precision == FDETD_FP32C) {
         D.ax_rows = std::min(d.nr, axis_band_rows(nd));
         if (D.ax_rows > 0) {
-            D.seg_ax = std::min(kSegAxis, D.ax_rows);
+            D.seg_ax = std::min(axis_segment_rows(), D.ax_rows);
             D.nseg_ax = (D.ax_rows + D.seg_ax - 1) / D.seg_ax;
             D.nstrip_ax = (d.nz + axis_columns(nd) - 1) / axis_columns(nd);
         }

@@ -26,8 +26,11 @@ def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
                if k.startswith("traffic_bytes_per_launch_")]
     assert entries
     current = fields["traffic_source_hash"].strip() == bench.kernel_source_hash()
+    seg_axis = int(fields["traffic_seg_axis_fp32c"])
     for (tag, seg), v in entries:
-        t = bench.measured_traffic(tag, int(seg))
+        t = bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0)
+        if tag == "fp32c":  # another near-axis segment length: no figure
+            assert bench.measured_traffic(tag, int(seg), seg_axis + 1) is None
         if current:  # counters taken on these sources
             assert t == int(float(v)) and t > 0
         else:  # the kernel changed since: no traffic figure until the counters are taken again

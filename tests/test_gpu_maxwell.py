@@ -176,8 +176,8 @@ def test_single_hip_runtime_in_process():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
     """Every output is formed by the same operations whatever the marching segment length, so plans with
-    forced segment lengths, the default and the autotuned one give bitwise equal fields (FP64 and FP32C,
-    eager and graph)."""
+    forced segment lengths (main and, in FP32C, near-axis tiles), the default and the autotuned one give
+    bitwise equal fields (FP64 and FP32C, eager and graph)."""
     import paper_2605_12132_amd as F
     w = small(1, 16, 8, nz=300, nr=90, steps=2, seed=4)
     rng = np.random.default_rng(71)
@@ -194,7 +194,13 @@ def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
     runs["graph"], _ = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=3)
     log(f"autotuned: {info['seg_rows']} rows per segment (near-axis {info['seg_rows_axis']}), {info['autotune_ms']:.1f} ms")
     assert info["seg_rows"] in (8, 16, 32, 64, 128, 256) and info["autotune_ms"] > 0
-    assert info["seg_rows_axis"] == (0 if precision == 0 else 8)
+    assert info["seg_rows_axis"] == (0 if precision == 0 else 16)  # min(16, 2 N_D) for order 16
+    if precision == 1:  # the near-axis segment length (FP32C) does not change results either
+        for sa in ("1", "5", "32"):
+            monkeypatch.setenv("FDETD_SEG_AXIS", sa)
+            runs["axis" + sa], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1 | F.PLAN_NO_AUTOTUNE)
+            assert info["seg_rows_axis"] == min(int(sa), 16)
+        monkeypatch.delenv("FDETD_SEG_AXIS")
     for k, v in runs.items():
         assert np.array_equal(v[0], runs["1"][0]), k
     if precision == 0:
