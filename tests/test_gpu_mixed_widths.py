@@ -63,3 +63,28 @@ def test_mixed_widths_with_generated_current():
         outs.append([x.cpu().numpy() for x in psi])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_widths_minimal_grids_against_the_oracle(precision):
+    """One launch batch of minimal grids of every order 2..32 (N_z = 2 N_D + 1, N_rho = N_D + 1), modes 0..3:
+    against the oracle (FP64 1e-12, FP32C the stated bound)."""
+    from helpers import oracle_maxwell, rel_l2, tol_fp32c
+    orders = list(range(2, 33, 2))
+    dz = I.LAMBDA0 / 20
+    w = I.Workload("mixed_min", 0, [o + 1 for o in orders], [o // 2 + 1 for o in orders], [k % 4 for k in range(16)],
+                   orders, 8, dz, 2 * dz, 0.5 * dz, 2)
+    rng = np.random.default_rng(3)
+    psi0, J = [], []
+    for p in range(w.n):
+        shape = (6, w.nr[p], w.nz[p])
+        x = rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+        psi0.append(x.real + 0j if w.m[p] == 0 else x)
+        j = 0.1 * (rng.uniform(-1, 1, (2, 3) + shape[1:]) + 1j * rng.uniform(-1, 1, (2, 3) + shape[1:]))
+        J.append(j.real + 0j if w.m[p] == 0 else j)
+    got, info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=F.PLAN_MIXED_WIDTHS | F.PLAN_SKIP_STABILITY)
+    want = oracle_maxwell(w, psi0, J, 2)
+    tol = 1e-12 if precision == F.FP64 else tol_fp32c(2, 8)
+    worst = max(rel_l2(got[p], want[p]) for p in range(w.n))
+    log(f"mixed-width minimal grids, precision {precision}: {info['launches_per_step']} launches per step, worst rel L2 {worst:.2e}")
+    assert worst < tol

@@ -17,7 +17,7 @@ import os
 import numpy as np
 import pytest
 
-from helpers import dev, grid_of, log, rel_l2, tol_fp32c
+from helpers import dev, gpu_maxwell, grid_of, log, rel_l2, tol_fp32c
 
 import oracle
 import paper_2605_12132_amd as F
@@ -163,3 +163,36 @@ def test_envelope_full_length_against_oracle_reference():
         err = rel_l2(got.astype(np.complex128), want)
         log(f"envelope {steps} steps precision={prec}: vs oracle rel L2 {err:.2e}")
         assert err < (TOL64 if prec == F.FP64 else tol_fp32c(steps, w.taylor_order, envelope=True))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_graph_degenerate_calls(precision):
+    """Zero steps leave the fields and the work block untouched; a sample generator with no samples is a
+    zero current (the same fields as steps without one); negative step counts are rejected on the host."""
+    import torch
+    w = small_bunch_workload().shrink(nz=120, nr=24)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    rng = np.random.default_rng(8)
+    psi0 = [I.noise((6, w.nr[p], w.nz[p]), 1.0, rng, real_only=(w.m[p] == 0)) for p in range(w.n)]
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_USE_GRAPH)
+        psi = [dev(x, cd) for x in psi0]
+        jw = [torch.full((3, w.nr[p], w.nz[p]), 7.0, dtype=cd, device="cuda") for p in range(w.n)]
+        before = [x.clone() for x in psi]
+        plan.step_graph(psi, bunch_jgen(w, 0), jw, n_steps=0)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(psi, before))
+        assert all(bool((j == 7.0).all()) for j in jw)
+        with pytest.raises(F.FdetdError):
+            F.fdetd_step_graph(plan._h, [x.data_ptr() for x in psi], bunch_jgen(w, 0).c(),
+                               [j.data_ptr() for j in jw], -1)
+        empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+        plan.step_graph(psi, F.Jgen(F.JGEN_SAMPLES, step0=0, samples=empty, vz=1.0, eps=0.5), jw, n_steps=3)
+        torch.cuda.synchronize()
+        plan.close()
+        assert all(bool((j == 0).all()) for j in jw)  # the step's current: zeroed, nothing deposited
+    nosrc, _ = gpu_maxwell(w, psi0, None, 3, precision=precision, flags=F.PLAN_USE_GRAPH)
+    for p in range(w.n):
+        assert rel_l2(psi[p].cpu().numpy().astype(np.complex128), nosrc[p]) < (1e-15 if precision == F.FP64 else 1e-7)
