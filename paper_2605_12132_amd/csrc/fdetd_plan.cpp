@@ -838,6 +838,7 @@ int autotune(fdetd_plan_t P, double &ms_spent)
             }
         }
     std::vector<int> best(nb, kCand[0]);
+    const bool log = std::getenv("FDETD_AUTOTUNE_LOG") != nullptr;  // per-candidate times on stderr
     for (size_t bi = 0; bi < nb; ++bi) {
         double bm = 1e300;
         for (int ci = 0; ci < kNC; ++ci)
@@ -845,6 +846,13 @@ int autotune(fdetd_plan_t P, double &ms_spent)
                 bm = t_ms[bi * kNC + ci];
                 best[bi] = kCand[ci];
             }
+        if (log) {
+            std::fprintf(stderr, "fdetd autotune batch %zu (N_D %d, %d problems):", bi, P->batches[bi].nd,
+                         P->batches[bi].count);
+            for (int ci = 0; ci < kNC; ++ci)
+                if (distinct(ci, bi)) std::fprintf(stderr, " %d rows %.4f ms", kCand[ci], t_ms[bi * kNC + ci]);
+            std::fprintf(stderr, " -> %d\n", best[bi]);
+        }
     }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
