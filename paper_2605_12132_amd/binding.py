@@ -23,6 +23,7 @@ PLAN_CURRENT_CORRECTION = 32
 PLAN_MIXED_WIDTHS = 64
 PLAN_PER_WIDTH = 128
 PLAN_INCREMENT_FORM = 256
+PLAN_SEPARATE_WN = 512
 
 # every symbol declared in include/fdetd.h
 EXPORTS = ("fdetd_plan", "fdetd_step", "fdetd_step_graph", "fdetd_step_noalloc", "envelope_step", "envelope_absorber", "envelope_ponderomotive",

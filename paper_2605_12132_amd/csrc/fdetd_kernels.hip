@@ -461,7 +461,8 @@ __global__ __launch_bounds__(256) void k_form_wn(BatchArgs A)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const V x = A.increment ? V{0, 0} : psi[c * n + q], j = src[c][q];
-                w[c * n + q] = V{(R)((double)x.x + A.beta_in * (double)j.x), (R)((double)x.y + A.beta_in * (double)j.y)};
+                w[c * n + q] = V{(R)__builtin_fma(A.beta_in, (double)j.x, (double)x.x),
+                                 (R)__builtin_fma(A.beta_in, (double)j.y, (double)x.y)};
             }
         }
     }

@@ -315,6 +315,28 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
     }
 }
 
+// The E part of w_N = psi + beta_in Jbar (the argument of the highest power of H in the Horner form of
+// the midpoint solution, section 2.1) for one loaded element: FP64 arithmetic, one rounding to the
+// storage precision, the same operation as the separate w_N pass, so that both give the same bits.
+__device__ __forceinline__ double wn_elem(double p, double j, double b) { return __builtin_fma(b, j, p); }
+__device__ __forceinline__ float wn_elem(float p, float j, double b) { return (float)__builtin_fma(b, (double)j, (double)p); }
+__device__ __forceinline__ float2 wn_elem(float2 p, float2 j, double b) { return float2{wn_elem(p.x, j.x, b), wn_elem(p.y, j.y, b)}; }
+// Makes the value's computation happen here (an empty asm that takes and gives the value back).
+__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(float &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(float2 &x)
+{
+    asm volatile("" : "+v"(x.x));
+    asm volatile("" : "+v"(x.y));
+}
+// WN: the element of w_N from psi and Jbar; otherwise the loaded element itself.
+template <bool WN, typename E>
+__device__ __forceinline__ E wn_of(E p, E j, double b)
+{
+    if constexpr (WN) return wn_elem(p, j, b);
+    else return p;
+}
+
 // The bracket coef multiplies: H v, or in the increment form P + H v (P = H psi of the step).
 template <bool INC, typename AR, typename V>
 __device__ __forceinline__ lv<AR, elem<V>::K> with_p(typename elem<V>::E p, lv<AR, elem<V>::K> hv)
@@ -633,7 +655,10 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 // In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed before
 // the launch (k_form_wn); otherwise psi or the previous stage's output.
 // --------------------------------------------------------------------------------------------------
-template <typename V, typename AR, int ND, bool COMP, bool INC>
+// WN: the first stage of a step with a current, whose input E part is w_N = psi + beta_in Jbar: vin is psi
+// and each loaded E element is combined with the Jbar element at the same place as it arrives, instead of
+// being read from a w_N plane formed by a separate pass.
+template <typename V, typename AR, int ND, bool COMP, bool INC, bool WN>
 __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     // ring of the last N_D + 1 raw E_theta rows (own elements), as in e_half
@@ -648,6 +673,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     using SV = typename stor<V>::T;
     const SV *vin = (const SV *)A.vin;
     const SV *Er = vin + ER * P, *Eth = vin + ETH * P, *Ez = vin + EZ * P;
+    const SV *Jr = (const SV *)A.jr, *Jt = (const SV *)A.jt, *Jz = (const SV *)A.jz;  // WN only
+    const double bw = A.beta_in;
     const AR dr = (AR)D.dr, pS = (AR)D.pS, pA = -(AR)D.pS, mm = (AR)D.m;
     const L_ zero = zero_lv<AR, K>();
     L_ Wz[2 * ND], Wg[2 * ND];
@@ -659,8 +686,20 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         for (int t = 0; t < 2 * ND - 1; ++t) {
             const int q = k0 - ND + t;
             const int r = min(q < 0 ? -1 - q : q, nr - 1);
-            Wz[t] = ldrow<V, AR>(Ez, nz, r, L);
-            Wg[t] = ldrow<V, AR>(Eth, nz, r, L);
+            if constexpr (WN) {
+                // each sum formed (pinned) as its row arrives: otherwise the compiler sinks every sum to
+                // the end of the fill, and the psi and Jbar elements of all 2 N_D - 1 rows are held in
+                // registers at once beside the window (two wavefronts per SIMD would no longer fit)
+                typename elem<V>::E wz = wn_elem(ldraw<V>(Ez, nz, r, L), ldraw<V>(Jz, nz, r, L), bw);
+                typename elem<V>::E wt = wn_elem(ldraw<V>(Eth, nz, r, L), ldraw<V>(Jt, nz, r, L), bw);
+                pin(wz);
+                pin(wt);
+                Wz[t] = to_lv<AR>(wz);
+                Wg[t] = to_lv<AR>(wt);
+            } else {
+                Wz[t] = ldrow<V, AR>(Ez, nz, r, L);
+                Wg[t] = ldrow<V, AR>(Eth, nz, r, L);
+            }
         }
         // rows k0 .. k0 + N_D - 2 of E_theta, as loaded, for their z stencils
 #pragma unroll
@@ -679,6 +718,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     struct In {
         E ez, et, thh;
         RowPart<V> er;
+        E jez, jet, jthh;  // WN: the Jbar elements at the same places
+        RowPart<V> jer;
         E p0, p1, p2;
         typename elem<V>::Lo l0, l1, l2;
         E h0, h1, h2;
@@ -691,6 +732,14 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         x.et = ldraw<V>(Eth, nz, qc, L);
         x.thh = fetch_halo<V>(Eth, nz, k, H);
         x.er = fetch_row<V>(Er, nz, k, L, H);
+        x.jez = x.jet = x.jthh = E{};
+        x.jer = RowPart<V>{E{}, E{}};
+        if constexpr (WN) {
+            x.jez = ldraw<V>(Jz, nz, qc, L);
+            x.jet = ldraw<V>(Jt, nz, qc, L);
+            x.jthh = fetch_halo<V>(Jt, nz, k, H);
+            x.jer = fetch_row<V>(Jr, nz, k, L, H);
+        }
         x.p0 = ld_elem<V>(A.psi, BR, k, D, L);
         x.p1 = ld_elem<V>(A.psi, BTH, k, D, L);
         x.p2 = ld_elem<V>(A.psi, BZ, k, D, L);
@@ -710,12 +759,14 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
     };
     auto row = [&](const In &cu, int k, bool live) {
         const int qn = k + ND - 1;  // the window's new row
-        const L_ ez = to_lv<AR>(cu.ez), et = to_lv<AR>(cu.et);
+        const E etw = wn_of<WN>(cu.et, cu.jet, bw);
+        const RowPart<V> erw{wn_of<WN>(cu.er.own, cu.jer.own, bw), wn_of<WN>(cu.er.halo, cu.jer.halo, bw)};
+        const L_ ez = to_lv<AR>(wn_of<WN>(cu.ez, cu.jez, bw)), et = to_lv<AR>(etw);
         Wz[2 * ND - 1] = keep_if(qn < nr, ez);
         Wg[2 * ND - 1] = keep_if(qn < nr, (((AR)qn + (AR)0.5) * dr) * et);
-        ring[(qn % RD) * WAVE + L.lane] = cu.et;
-        put_row<V, ND>(RowPart<V>{ring[(k % RD) * WAVE + L.lane], cu.thh}, L, H, lds[0]);
-        put_row<V, ND>(cu.er, L, H, lds[1]);
+        ring[(qn % RD) * WAVE + L.lane] = etw;
+        put_row<V, ND>(RowPart<V>{ring[(k % RD) * WAVE + L.lane], wn_of<WN>(cu.thh, cu.jthh, bw)}, L, H, lds[0]);
+        put_row<V, ND>(erw, L, H, lds[1]);
         __syncthreads();
         L_ zth = zero, zr = zero, rz = zero, rg = zero;
         // D_z^(-) at staggered column i: primary columns i + j - 1 and i - j
@@ -732,7 +783,7 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             rz = fmav(ar, Wz[ND + j - 1] - Wz[ND - j], rz);
             rg = fmav(ar, Wg[ND + j - 1] - Wg[ND - j], rg);
         }
-        const L_ erk = to_lv<AR>(cu.er.own);
+        const L_ erk = to_lv<AR>(erw.own);
         const L_ ezk = Wz[ND];
         const AR rip = (AR)cld(D.rinv_p, k), ris = (AR)cld(D.rinv_s, k);
         const L_ t0 = times_i(mm * rip, ezk);
@@ -753,7 +804,8 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
             Wg[t] = Wg[t + 1];
         }
     };
-    march_rows<In, prefetch_of<V, AR, ND, COMP>(), FDETD_ROW_UNROLL * prefetch_of<V, AR, ND, COMP>()>(k0, k1, fetch, row, fill);
+    constexpr int PF = prefetch_of<V, AR, ND, COMP>();
+    march_rows<In, PF, FDETD_ROW_UNROLL * PF>(k0, k1, fetch, row, fill);
 }
 
 // Tile of block b.  Tiles are numbered problem by problem, (half,) segment, strip -- strips fastest --
@@ -787,7 +839,7 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
 // AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage; V = float2 or,
 // for wide stencils, f2pair read in lane pairs): rows 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the
 // axis and its 1/rho factors, in FP64 arithmetic.
-template <typename V, int ND, bool SRC, bool COMP, bool INC, bool AXIS>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool AXIS, bool WN>
 __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     constexpr int S = elem<V>::S, CPW = WAVE / S;
@@ -821,8 +873,9 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     } else {
         C.psi = A.psi[p];
         // the first stage reads psi, except the B half of a step with a current: it reads the E part of
-        // w_N = psi + beta_in Jbar, which k_form_wn wrote into the second stage buffer before the launch
-        C.vin = first ? ((A.has_src && half == 1) ? D.buf[1] : C.psi) : D.buf[(A.N - 2 - A.n) & 1];
+        // w_N = psi + beta_in Jbar, which k_form_wn wrote into the second stage buffer before the launch,
+        // or (WN) forms it from psi and Jbar as it loads them
+        C.vin = first ? ((A.has_src && half == 1 && !WN) ? D.buf[1] : C.psi) : D.buf[(A.N - 2 - A.n) & 1];
         C.vout = (A.n == 0 && A.N > 1) ? (void *)C.psi : D.buf[(A.N - 1 - A.n) & 1];
         C.hi = nullptr;
     }
@@ -837,7 +890,7 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.coef = A.coef;
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
     if (half == 0) e_half<V, AR, ND, SRC, COMP, INC>(C, i0, k0, k1, lds);
-    else b_half<V, AR, ND, COMP, INC>(C, i0, k0, k1, lds);
+    else b_half<V, AR, ND, COMP, INC, WN>(C, i0, k0, k1, lds);
 }
 
 // One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
@@ -855,7 +908,7 @@ constexpr int stage_lds_bytes()
     return 2 * lds_row_bytes<V, ND>() + (ND + 1) * WAVE * (int)sizeof(typename elem<V>::E);
 }
 
-template <typename V, int ND, bool SRC, bool COMP, bool INC>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool WN>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
     // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
@@ -868,12 +921,12 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, INC, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, INC, true, WN>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, INC, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, INC, false, WN>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -1192,11 +1245,11 @@ hipError_t go_stagger(const BatchArgs &a, hipStream_t s)
 }
 
 // Launch stage n of a batch with the kernel variant its flags select.
-template <typename V, int ND, bool SRC, bool COMP, bool INC>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool WN = false>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
-    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, INC>), dim3(blocks_of(a.ntiles_ax, a.ntiles)),
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, INC, WN>), dim3(blocks_of(a.ntiles_ax, a.ntiles)),
                        dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
@@ -1211,7 +1264,12 @@ hipError_t go_maxwell_i(const BatchArgs &a, hipStream_t s)
             return go_maxwell_v<V, ND, false, true, INC>(a, s);
         }
     }
-    if (a.has_src) return go_maxwell_v<V, ND, true, false, INC>(a, s);
+    if (a.has_src) {
+        // the first stage of a step with a current forms w_N itself when the plan left out the w_N pass
+        if constexpr (!INC)
+            if (a.fuse_wn && a.n == a.N - 1) return go_maxwell_v<V, ND, true, false, false, true>(a, s);
+        return go_maxwell_v<V, ND, true, false, INC>(a, s);
+    }
     return go_maxwell_v<V, ND, false, false, INC>(a, s);
 }
 
@@ -1263,12 +1321,12 @@ __device__ __forceinline__ void stage_tile_any(const BatchArgs &A, int t, unsign
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if constexpr (AXIS) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, false, true>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, false, true, false>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, false, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, false, false, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // AXIS: the launch covers the FP32C near-axis tiles only (their FP64-arithmetic code for all widths in one

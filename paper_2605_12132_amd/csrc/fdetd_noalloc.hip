@@ -157,12 +157,15 @@ extern "C" FDETD_API int fdetd_step_noalloc(const fdetd_problem_desc *prob, int3
     A.compensated = precision == FDETD_FP32C;
     A.psi[0] = psi;
     const int N = d.taylor_order;
+    // the first stage forms w_N as it loads psi and Jbar, except FP32C at N = 1 (its first stage is the
+    // compensated last one): then a pass of its own writes w_N first
+    A.fuse_wn = j_half != nullptr && !(precision == FDETD_FP32C && N == 1);
     for (int st = 0; st < n_steps; ++st) {
         A.aux[0] = j_half ? (const char *)j_half + (size_t)(j_step_blocks * st) * 3 * cells * eb : nullptr;
         A.beta_in = -d.dt * std::ldexp(1.0, -N);
         if (j_half) {
             if ((e = launch_stagger_march(prec, nd, A, s)) != hipSuccess ||
-                (e = launch_form_wn(prec, A, cells, s)) != hipSuccess)
+                (!A.fuse_wn && (e = launch_form_wn(prec, A, cells, s)) != hipSuccess))
                 return fail(FDETD_E_HIP, "fdetd_step_noalloc: current staging: %s", hipGetErrorString(e));
         }
         for (int n = N - 1; n >= 0; --n) {

@@ -236,6 +236,15 @@ int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A, hipStream_t s)
     return FDETD_OK;
 }
 
+// Whether the first Horner stage of batch b forms the E part of w_N itself (as it loads psi and Jbar)
+// instead of reading it from a plane that a separate pass wrote: per-width launches in the Horner form,
+// except FP32C at N = 1, where the first stage is also the compensated last one.
+bool fuse_wn(const fdetd_plan_t P, const Batch &b, bool has_current)
+{
+    return has_current && b.nd > 0 && !(P->flags & FDETD_PLAN_INCREMENT_FORM) &&
+           !(P->precision == FDETD_FP32C && b.N == 1) && !(P->flags & FDETD_PLAN_SEPARATE_WN);
+}
+
 // One Maxwell step of the problems of batch b on stream s: stage the currents, N Horner stages, then the
 // N = 1 copy and, at the end of a call, the axis rule of each problem.
 int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, const void *const *j,
@@ -301,6 +310,7 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     A.has_src = j != nullptr;
     A.compensated = P->precision == FDETD_FP32C;
     A.increment = (P->flags & FDETD_PLAN_INCREMENT_FORM) ? 1 : 0;
+    A.fuse_wn = fuse_wn(P, b, j != nullptr);
     if (A.increment && b.ntiles + b.ntiles_ax) {
         // P = H psi of the step in two passes, H lo from zero, then P += H psi_hi (coef 1, no current), with
         // the stages' own operator (float stencils, FP64 near-axis rows): an operator for P that differed
@@ -320,7 +330,7 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         A.role = 0;
         A.has_src = j != nullptr;
     }
-    if (j && b.ntiles + b.ntiles_ax) {
+    if (j && b.ntiles + b.ntiles_ax && !A.fuse_wn) {
         // E part of w_N = psi + beta_in Jbar into buf[1] (increment form: of d_N = beta_in Jbar): read by the
         // B half of the first stage
         A.beta_in = -b.dt * std::ldexp(1.0, -b.N);
@@ -334,8 +344,9 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
         A.beta = -b.dt * std::ldexp(1.0, -n);
         A.coef = b.dt / (n + 1);
         // algorithmic bytes: vin (6c) + psi (6c) + Jbar (3c) + vout (6c); the first stage without a current
-        // reads psi once as vin and as psi (12c); with one, its B half reads w_N from buf[1]
-        const double cvals = (n == b.N - 1 && !j ? 12.0 : 18.0) + (j ? 3.0 : 0.0);
+        // reads psi once as vin and as psi (12c); with one, its B half reads w_N from buf[1], or, fused,
+        // psi's E part and Jbar again (3c more)
+        const double cvals = (n == b.N - 1 && !j ? 12.0 : 18.0) + (j ? 3.0 : 0.0) + (n == b.N - 1 && A.fuse_wn ? 3.0 : 0.0);
         const double bytes = cvals * cells * eb + (A.compensated && n == 0 ? 2.0 * 6 * cells * 8 : 0.0) +
                              (A.increment && n == 0 ? 6.0 * cells * eb : 0.0);
         int rc = profile_begin(P, bytes);
@@ -1053,8 +1064,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         if (probs[p].kind != probs[0].kind)
             return fail(nullptr, FDETD_E_ARG, "fdetd_plan: all problems of a plan must have the same kind");
     }
-    if (flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u))
-        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_INCREMENT_FORM * 2u - 1u));
+    if (flags & ~(FDETD_PLAN_SEPARATE_WN * 2u - 1u))
+        return fail(nullptr, FDETD_E_ARG, "fdetd_plan: unknown flag bits 0x%x", flags & ~(FDETD_PLAN_SEPARATE_WN * 2u - 1u));
     if ((flags & FDETD_PLAN_INCREMENT_FORM) && precision != FDETD_FP32C)
         return fail(nullptr, FDETD_E_ARG, "fdetd_plan: FDETD_PLAN_INCREMENT_FORM needs an FP32C plan");
     if ((flags & FDETD_PLAN_USE_GRAPH) && !stream)
@@ -1205,7 +1216,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
                                          // widths has FP32C near-axis tiles), staging and w_N per batch
         const int per_stage = (b.nd < 0 && b.ntiles && b.ntiles_ax) ? 2 : 1;
         const int prepass = (flags & FDETD_PLAN_INCREMENT_FORM) ? 2 : 0;  // the two P passes
-        launches += (int64_t)(per_stage * b.N + (P->kind == FDETD_MAXWELL ? 2 : 0) + prepass) * (b.ntiles + b.ntiles_ax > 0);
+        const int staging = P->kind == FDETD_MAXWELL ? (fuse_wn(P, b, true) ? 1 : 2) : 0;  // J_rho, w_N
+        launches += (int64_t)(per_stage * b.N + staging + prepass) * (b.ntiles + b.ntiles_ax > 0);
     }
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;

@@ -1,0 +1,101 @@
+"""The first Horner stage of a step with a current forms the E part of w_N = psi + beta_N Jbar (the
+argument of the highest power of H in the Horner form of the midpoint solution, section 2.1) as it loads
+psi and Jbar, instead of reading it from a plane that a pass of its own wrote before the stage
+(FDETD_PLAN_SEPARATE_WN keeps that pass; launches that mix stencil widths always use it).  Both round the
+same FP64 fused multiply-add once to the storage precision, so the states agree bit for bit:
+
+* FP64 and FP32C, stencil half widths 1, 4, 9 and 16 (the FP32C near-axis layout switches from whole
+  complex values per lane to lane pairs above 8), modes 0 .. 3, ragged grids, resident currents;
+* the current made in the captured time loop (bunch generator);
+* the current correction, whose first stage reads the corrected J_theta;
+* N = 1, where FP32C keeps the separate pass (its first stage is the compensated last one).
+
+The fused plan makes one launch per step and batch fewer, and its state matches the oracle."""
+import numpy as np
+import pytest
+
+from helpers import dev, gpu_maxwell, log, oracle_maxwell, rel_l2, tol_fp32c
+
+import paper_2605_12132_amd as F
+import paper_2605_12132_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def widths(N, steps):
+    dz = I.LAMBDA0 / 20
+    return I.Workload("fused_wn_widths", 0, [150, 203, 97, 130], [37, 70, 41, 66], [0, 1, 2, 3], [2, 8, 18, 32], N,
+                      dz, 2 * dz, 0.5 * dz, steps, seed=11)
+
+
+def random_inputs(w, steps, rng, planes=3):
+    psi0, J = [], []
+    for p in range(w.n):
+        sh = (w.nr[p], w.nz[p])
+        psi0.append(rng.uniform(-1, 1, (6,) + sh) + 1j * rng.uniform(-1, 1, (6,) + sh))
+        J.append(0.1 * (rng.uniform(-1, 1, (steps, planes) + sh) + 1j * rng.uniform(-1, 1, (steps, planes) + sh)))
+    return psi0, J
+
+
+@pytest.mark.parametrize("precision", [F.FP64, F.FP32C])
+@pytest.mark.parametrize("N", [8, 1])
+def test_fused_first_stage_equals_separate_pass(precision, N):
+    steps = 3
+    w = widths(N, steps)
+    psi0, J = random_inputs(w, steps, np.random.default_rng(31 + 2 * N + precision))
+    base = F.PLAN_USE_GRAPH | F.PLAN_PER_WIDTH | (F.PLAN_SKIP_STABILITY if N == 1 else 0)  # N = 1 is not stable
+    fused, info_f = gpu_maxwell(w, psi0, J, steps, precision=precision, flags=base)
+    sep, info_s = gpu_maxwell(w, psi0, J, steps, precision=precision, flags=base | F.PLAN_SEPARATE_WN)
+    fuses = not (precision == F.FP32C and N == 1)
+    log(f"precision {precision} N={N}: {info_f['launches_per_step']} launches per step fused, "
+        f"{info_s['launches_per_step']} with the separate w_N pass")
+    assert info_s["launches_per_step"] == w.n * (N + 2)
+    assert info_f["launches_per_step"] == w.n * (N + 1 if fuses else N + 2)
+    for p in range(w.n):
+        assert np.array_equal(fused[p], sep[p]), (p, w.fd_order[p])
+    want = oracle_maxwell(w, psi0, J, steps)
+    tol = 1e-12 if precision == F.FP64 else tol_fp32c(steps, N)
+    for p in range(w.n):
+        err = rel_l2(fused[p], want[p])
+        log(f"  m={w.m[p]} order={w.fd_order[p]}: rel L2 vs oracle {err:.2e} (bound {tol:.1e})")
+        assert err < tol
+
+
+@pytest.mark.parametrize("precision", [F.FP64, F.FP32C])
+def test_fused_first_stage_with_generated_current(precision):
+    import torch
+    w = widths(8, 4)
+    jg = F.Jgen(F.JGEN_BUNCH, step0=1, seed=5, nb=0.01, sigz=2.0 * I.UM, sigr=1.0 * I.UM, noise=1e-3)
+    cd = torch.complex128 if precision == F.FP64 else torch.complex64
+    psi0, _ = random_inputs(w, 1, np.random.default_rng(53 + precision))
+    outs = []
+    for flags in (F.PLAN_USE_GRAPH | F.PLAN_PER_WIDTH, F.PLAN_USE_GRAPH | F.PLAN_PER_WIDTH | F.PLAN_SEPARATE_WN):
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            plan = F.Plan(w.problems(), precision=precision, flags=flags)
+            psi = [dev(x, cd) for x in psi0]
+            jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
+            plan.step_graph(psi, jg, jw, n_steps=4)
+            torch.cuda.synchronize()
+            state = plan.export_state() if precision == F.FP32C else b""
+            plan.close()
+        outs.append(([x.cpu().numpy() for x in psi], state))
+    log(f"generated current, precision {precision}: fused and separate w_N compared over 4 steps")
+    for p in range(w.n):
+        assert np.array_equal(outs[0][0][p], outs[1][0][p]), p
+    assert outs[0][1] == outs[1][1]  # FP32C: the compensation words too
+
+
+def test_fused_first_stage_with_current_correction():
+    w = widths(8, 2)
+    psi0, J4 = random_inputs(w, 2, np.random.default_rng(77), planes=4)
+    flags = F.PLAN_USE_GRAPH | F.PLAN_CURRENT_CORRECTION
+    for precision in (F.FP64, F.FP32C):
+        fused, info_f = gpu_maxwell(w, psi0, J4, 2, precision=precision, flags=flags)
+        sep, info_s = gpu_maxwell(w, psi0, J4, 2, precision=precision, flags=flags | F.PLAN_SEPARATE_WN)
+        log(f"current correction, precision {precision}: {info_f['launches_per_step']} vs "
+            f"{info_s['launches_per_step']} launches per step")
+        assert info_f["launches_per_step"] == info_s["launches_per_step"] - w.n
+        for p in range(w.n):
+            assert np.array_equal(fused[p], sep[p]), (precision, p)

@@ -99,7 +99,7 @@ def test_plan_rejects_mixed_kinds_and_bad_flags():
     with pytest.raises(F.FdetdError):
         F.fdetd_plan([a], precision=7)
     with pytest.raises(F.FdetdError):
-        F.fdetd_plan([a], flags=512)
+        F.fdetd_plan([a], flags=1024)
     assert "unknown flag" in F.fdetd_last_error(None)
     with pytest.raises(F.FdetdError):  # the increment form is an FP32C Maxwell plan option
         F.fdetd_plan([a], precision=F.FP64, flags=F.PLAN_INCREMENT_FORM)
@@ -129,7 +129,8 @@ def test_header_layout_matches_binding(tmp_path):
               "FDETD_PLAN_ONE_STREAM": binding.PLAN_ONE_STREAM,
               "FDETD_PLAN_CURRENT_CORRECTION": binding.PLAN_CURRENT_CORRECTION,
               "FDETD_PLAN_MIXED_WIDTHS": binding.PLAN_MIXED_WIDTHS, "FDETD_PLAN_PER_WIDTH": binding.PLAN_PER_WIDTH,
-              "FDETD_PLAN_INCREMENT_FORM": binding.PLAN_INCREMENT_FORM}
+              "FDETD_PLAN_INCREMENT_FORM": binding.PLAN_INCREMENT_FORM,
+              "FDETD_PLAN_SEPARATE_WN": binding.PLAN_SEPARATE_WN}
     for k in consts:
         lines.append(f'printf("const {k} %lld\\n", (long long)({k}));')
     lines.append("return 0; }")
