@@ -85,8 +85,8 @@ extern "C" {
                                         FDETD_E_ARG for FP64 plans                                         */
 #define FDETD_PLAN_SEPARATE_WN 512u  /* Maxwell, steps with a current: form the E part of w_N = psi +
                                         beta_N Jbar (section 2.1) in a pass of its own before the first
-                                        Horner stage, as launches that mix widths always do, instead of in
-                                        the first stage of a per-width launch as it loads psi and Jbar.
+                                        Horner stage, instead of in the first stage as it loads psi and
+                                        Jbar.
                                         Same results bit for bit; one more launch and ~9 complex values
                                         per cell more traffic per step                                    */
 

@@ -40,7 +40,6 @@ hipError_t launch_stagger_march(int prec, int nd, const BatchArgs &a, hipStream_
 hipError_t launch_maxwell_any(int prec, const BatchArgs &a, hipStream_t s)
 {
     if (a.increment) return hipErrorInvalidValue;  // increment-form plans batch per width
-    if (a.fuse_wn) return hipErrorInvalidValue;    // launches that mix widths read w_N from its own pass
     if (prec == P64) return march_maxwell_any_p64(a, s);
     return a.compensated && a.n == 0 ? march_maxwell_any_p32c(a, s) : march_maxwell_any_p32(a, s);
 }

@@ -129,7 +129,7 @@ struct BatchArgs {
     // from zero, role 2: P += H psi_hi; role 0: a Horner stage), the last stage TwoSum(psi_hi, lo + d_0)
     int increment, role;
     // the first stage with a current forms the E part of w_N from psi and Jbar as it loads them (no
-    // k_form_wn pass before it): per-width launches of the Horner form, not the compensated N = 1 stage
+    // k_form_wn pass before it): the Horner form, not the compensated N = 1 stage
     int fuse_wn;
     double beta_in, beta, coef;
     const void *psi[kMaxBatch];  // Maxwell psi, or envelope a

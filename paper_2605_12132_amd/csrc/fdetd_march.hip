@@ -1314,24 +1314,24 @@ hipError_t go_envelope(const BatchArgs &a, hipStream_t s)
 // launches).  One launch per stage for all problems of equal Taylor order and time step.
 // --------------------------------------------------------------------------------------------------
 #ifdef FDETD_ANY_WIDTH
-template <typename V, bool SRC, bool COMP, bool AXIS, int ND>
+template <typename V, bool SRC, bool COMP, bool AXIS, bool WN, int ND>
 __device__ __forceinline__ void stage_tile_any(const BatchArgs &A, int t, unsigned char *smem)
 {
     using VA = typename std::conditional<(ND <= kAxisWholeND), float2, f2pair>::type;
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if constexpr (AXIS) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, false, true, false>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, false, true, WN>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, false, false, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, false, false, WN>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // AXIS: the launch covers the FP32C near-axis tiles only (their FP64-arithmetic code for all widths in one
 // kernel would not fit the registers of two wavefronts per SIMD); otherwise the main tiles only.
-template <typename V, bool SRC, bool COMP, bool AXIS>
+template <typename V, bool SRC, bool COMP, bool AXIS, bool WN>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage_any(BatchArgs A)
 {
     __shared__ __align__(16) unsigned char smem[cmax(stage_lds_bytes<V, kMaxND>(), stage_lds_bytes<f2pair, kMaxND>())];
@@ -1341,7 +1341,7 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage_any(BatchArgs A)
     const int p = problem_of_tile<AXIS>(A, t);
     switch (((CDesc *)A.probs)[p].nd) {
 #define FDETD_C(N) \
-    case N: stage_tile_any<V, SRC, COMP, AXIS, N>(A, t, smem); break;
+    case N: stage_tile_any<V, SRC, COMP, AXIS, WN, N>(A, t, smem); break;
         FDETD_C(1) FDETD_C(2) FDETD_C(3) FDETD_C(4) FDETD_C(5) FDETD_C(6) FDETD_C(7) FDETD_C(8) FDETD_C(9) FDETD_C(10)
         FDETD_C(11) FDETD_C(12) FDETD_C(13) FDETD_C(14) FDETD_C(15) FDETD_C(16)
 #undef FDETD_C
@@ -1375,18 +1375,18 @@ __global__ __launch_bounds__(WAVE) void k_stagger_march_any(BatchArgs A)
 }
 
 // The main tiles, then (FP32 storage) the near-axis tiles in a second launch.
-template <typename V, bool SRC, bool COMP>
+template <typename V, bool SRC, bool COMP, bool WN = false>
 hipError_t go_maxwell_any_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
     BatchArgs m = a;
     m.ntiles_ax = 0;
-    if (m.ntiles) hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, false>), dim3(blocks_of(0, m.ntiles)), dim3(WAVE), 0, s, m);
+    if (m.ntiles) hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, false, WN>), dim3(blocks_of(0, m.ntiles)), dim3(WAVE), 0, s, m);
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (a.ntiles_ax) {
             BatchArgs x = a;
             x.ntiles = 0;
-            hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, true>), dim3(blocks_of(x.ntiles_ax, 0)), dim3(WAVE), 0, s, x);
+            hipLaunchKernelGGL((k_maxwell_stage_any<V, SRC, COMP, true, WN>), dim3(blocks_of(x.ntiles_ax, 0)), dim3(WAVE), 0, s, x);
         }
     }
     return hipGetLastError();
@@ -1423,7 +1423,9 @@ hipError_t go_maxwell_any_v(const BatchArgs &a, hipStream_t s)
 #if FDETD_ANY_WIDTH == 0
 hipError_t march_maxwell_any_p64(const BatchArgs &a, hipStream_t s)
 {
-    return a.has_src ? go_maxwell_any_v<double2, true, false>(a, s) : go_maxwell_any_v<double2, false, false>(a, s);
+    if (!a.has_src) return go_maxwell_any_v<double2, false, false>(a, s);
+    return a.fuse_wn && a.n == a.N - 1 ? go_maxwell_any_v<double2, true, false, true>(a, s)
+                                       : go_maxwell_any_v<double2, true, false>(a, s);
 }
 hipError_t march_stagger_any_p64(const BatchArgs &a, hipStream_t s)
 {
@@ -1433,7 +1435,9 @@ hipError_t march_stagger_any_p64(const BatchArgs &a, hipStream_t s)
 #elif FDETD_ANY_WIDTH == 1
 hipError_t march_maxwell_any_p32(const BatchArgs &a, hipStream_t s)
 {
-    return a.has_src ? go_maxwell_any_v<float2, true, false>(a, s) : go_maxwell_any_v<float2, false, false>(a, s);
+    if (!a.has_src) return go_maxwell_any_v<float2, false, false>(a, s);
+    return a.fuse_wn && a.n == a.N - 1 ? go_maxwell_any_v<float2, true, false, true>(a, s)
+                                       : go_maxwell_any_v<float2, true, false>(a, s);
 }
 hipError_t march_stagger_any_p32(const BatchArgs &a, hipStream_t s)
 {

@@ -237,11 +237,11 @@ int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A, hipStream_t s)
 }
 
 // Whether the first Horner stage of batch b forms the E part of w_N itself (as it loads psi and Jbar)
-// instead of reading it from a plane that a separate pass wrote: per-width launches in the Horner form,
-// except FP32C at N = 1, where the first stage is also the compensated last one.
+// instead of reading it from a plane that a separate pass wrote: the Horner form, except FP32C at N = 1,
+// where the first stage is also the compensated last one.
 bool fuse_wn(const fdetd_plan_t P, const Batch &b, bool has_current)
 {
-    return has_current && b.nd > 0 && !(P->flags & FDETD_PLAN_INCREMENT_FORM) &&
+    return has_current && !(P->flags & FDETD_PLAN_INCREMENT_FORM) &&
            !(P->precision == FDETD_FP32C && b.N == 1) && !(P->flags & FDETD_PLAN_SEPARATE_WN);
 }
 

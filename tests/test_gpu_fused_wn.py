@@ -1,11 +1,12 @@
 """The first Horner stage of a step with a current forms the E part of w_N = psi + beta_N Jbar (the
 argument of the highest power of H in the Horner form of the midpoint solution, section 2.1) as it loads
 psi and Jbar, instead of reading it from a plane that a pass of its own wrote before the stage
-(FDETD_PLAN_SEPARATE_WN keeps that pass; launches that mix stencil widths always use it).  Both round the
+(FDETD_PLAN_SEPARATE_WN keeps that pass).  Both round the
 same FP64 fused multiply-add once to the storage precision, so the states agree bit for bit:
 
 * FP64 and FP32C, stencil half widths 1, 4, 9 and 16 (the FP32C near-axis layout switches from whole
-  complex values per lane to lane pairs above 8), modes 0 .. 3, ragged grids, resident currents;
+  complex values per lane to lane pairs above 8), modes 0 .. 3, ragged grids, resident currents, in
+  per-width launches and in launches that mix the widths;
 * the current made in the captured time loop (bunch generator);
 * the current correction, whose first stage reads the corrected J_theta;
 * N = 1, where FP32C keeps the separate pass (its first stage is the compensated last one).
@@ -39,18 +40,22 @@ def random_inputs(w, steps, rng, planes=3):
 
 @pytest.mark.parametrize("precision", [F.FP64, F.FP32C])
 @pytest.mark.parametrize("N", [8, 1])
-def test_fused_first_stage_equals_separate_pass(precision, N):
+@pytest.mark.parametrize("grouping", ["per-width", "mixed"])
+def test_fused_first_stage_equals_separate_pass(precision, N, grouping):
     steps = 3
     w = widths(N, steps)
     psi0, J = random_inputs(w, steps, np.random.default_rng(31 + 2 * N + precision))
-    base = F.PLAN_USE_GRAPH | F.PLAN_PER_WIDTH | (F.PLAN_SKIP_STABILITY if N == 1 else 0)  # N = 1 is not stable
+    base = (F.PLAN_USE_GRAPH | (F.PLAN_PER_WIDTH if grouping == "per-width" else F.PLAN_MIXED_WIDTHS)
+            | (F.PLAN_SKIP_STABILITY if N == 1 else 0))  # N = 1 is not stable
     fused, info_f = gpu_maxwell(w, psi0, J, steps, precision=precision, flags=base)
     sep, info_s = gpu_maxwell(w, psi0, J, steps, precision=precision, flags=base | F.PLAN_SEPARATE_WN)
     fuses = not (precision == F.FP32C and N == 1)
-    log(f"precision {precision} N={N}: {info_f['launches_per_step']} launches per step fused, "
+    log(f"precision {precision} N={N} {grouping}: {info_f['launches_per_step']} launches per step fused, "
         f"{info_s['launches_per_step']} with the separate w_N pass")
-    assert info_s["launches_per_step"] == w.n * (N + 2)
-    assert info_f["launches_per_step"] == w.n * (N + 1 if fuses else N + 2)
+    # per width: one batch per problem here; mixed: one batch, FP32C with its near-axis tiles apart
+    batches, per_stage = (w.n, 1) if grouping == "per-width" else (1, 1 if precision == F.FP64 else 2)
+    assert info_s["launches_per_step"] == batches * (per_stage * N + 2)
+    assert info_f["launches_per_step"] == batches * (per_stage * N + (1 if fuses else 2))
     for p in range(w.n):
         assert np.array_equal(fused[p], sep[p]), (p, w.fd_order[p])
     want = oracle_maxwell(w, psi0, J, steps)

@@ -2,8 +2,9 @@
 problems of every stencil width (each tile runs the code of its problem's width), against the per-width
 batches (FDETD_PLAN_PER_WIDTH) on up to four streams.  The same code runs on the
 same data in the same order per output value, so the states agree bit for bit, in FP64 and FP32C, with
-resident currents and with the current made in the captured time loop; the launch counts drop to N + 2
-per step (FP32C: 2 N + 2, the near-axis tiles in a launch of their own)."""
+resident currents and with the current made in the captured time loop; the launch counts drop to N + 1
+per step with a current (the staged J_rho and N stages; FP32C: 2 N + 1, the near-axis tiles in a launch of
+their own)."""
 import numpy as np
 import pytest
 
@@ -38,7 +39,7 @@ def test_mixed_widths_equal_per_width_batches(precision):
         f"mixed {info_m['launches_per_step']} on {info_m['streams']}")
     N = w.taylor_order
     assert info_m["streams"] == 1
-    assert info_m["launches_per_step"] == (N + 2 if precision == F.FP64 else 2 * N + 2)
+    assert info_m["launches_per_step"] == (N + 1 if precision == F.FP64 else 2 * N + 1)
     assert info_p["streams"] == 4
     for p in range(w.n):
         assert np.array_equal(per[p], mix[p]) and np.array_equal(per[p], dflt[p]), p
