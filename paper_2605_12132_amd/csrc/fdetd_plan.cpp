@@ -89,6 +89,10 @@ struct fdetd_plan_s {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
+    // FP32C batches that mix widths: the near-axis launch of each stage runs on this stream beside the
+    // main launch, forked and joined around the stage
+    hipStream_t axis_stream = nullptr;
+    hipEvent_t axis_fork = nullptr, axis_join = nullptr;
     void *zero = nullptr;  // FP32C increment form: 6 zero planes of the largest problem
 };
 
@@ -229,6 +233,21 @@ int launch_stage(fdetd_plan_t P, const Batch &b, BatchArgs &A, hipStream_t s)
     A.ntiles = b.ntiles;
     A.ntiles_ax = b.ntiles_ax;
     if (A.ntiles + A.ntiles_ax == 0) return FDETD_OK;
+    if (P->kind == FDETD_MAXWELL && b.nd < 0 && P->axis_stream && A.ntiles && A.ntiles_ax) {
+        // widths mixed in FP32 storage: the near-axis tiles (FP64 arithmetic, a launch of their own) run on
+        // the axis stream beside the main tiles.  Both read only vectors that the stage does not write
+        // (the previous stage's, psi, Jbar) away from their own rows, and write disjoint rows.
+        BatchArgs X = A, M = A;
+        X.ntiles = 0;
+        M.ntiles_ax = 0;
+        HIPCHK(P, hipEventRecord(P->axis_fork, s));
+        HIPCHK(P, hipStreamWaitEvent(P->axis_stream, P->axis_fork, 0));
+        HIPCHK(P, launch_maxwell_any(prec, X, P->axis_stream));
+        HIPCHK(P, launch_maxwell_any(prec, M, s));
+        HIPCHK(P, hipEventRecord(P->axis_join, P->axis_stream));
+        HIPCHK(P, hipStreamWaitEvent(s, P->axis_join, 0));
+        return FDETD_OK;
+    }
     if (P->kind == FDETD_MAXWELL)
         HIPCHK(P, b.nd > 0 ? launch_maxwell_march(prec, b.nd, A, s) : launch_maxwell_any(prec, A, s));
     else
@@ -550,7 +569,8 @@ hipStream_t lane_stream(fdetd_plan_t P, const Batch &b) { return b.lane ? P->lan
 // Launch batches that mix stencil widths: Maxwell plans in FP64 or with FDETD_PLAN_MIXED_WIDTHS, unless
 // FDETD_PLAN_PER_WIDTH, and never with the current correction, whose banded solves are batched per width.
 // FP32C plans batch per width by default: their mixed launches split main and near-axis tiles into two
-// launches per stage on one stream, and per-width batches on four streams overlapped those better.
+// launches per stage (the near-axis one on a stream of its own beside the main one), and per-width batches
+// on four streams still measured ~3 % faster on the 64-problem batch.
 bool mixed_widths(const fdetd_plan_t P)
 {
     if (P->kind != FDETD_MAXWELL ||
@@ -562,6 +582,20 @@ bool mixed_widths(const fdetd_plan_t P)
 // Streams of a plan with more than one launch batch: longest-processing-time assignment of the batches
 // (work ~ cells x (N + 1)) to at most kMaxLanes streams, the plan's own stream being lane 0.  Profiled
 // plans and FDETD_PLAN_ONE_STREAM keep every launch on the plan's stream.
+// The stream of the near-axis launches of FP32C batches that mix widths (not when profiling or on one
+// stream: then they follow the main launch on the batch's stream).
+int make_axis_stream(fdetd_plan_t P)
+{
+    if (P->flags & (FDETD_PLAN_PROFILE | FDETD_PLAN_ONE_STREAM)) return FDETD_OK;
+    bool need = false;
+    for (const Batch &b : P->batches) need = need || (b.nd < 0 && b.ntiles && b.ntiles_ax);
+    if (!need) return FDETD_OK;
+    HIPCHK(P, hipStreamCreateWithFlags(&P->axis_stream, hipStreamNonBlocking));
+    HIPCHK(P, hipEventCreateWithFlags(&P->axis_fork, hipEventDisableTiming));
+    HIPCHK(P, hipEventCreateWithFlags(&P->axis_join, hipEventDisableTiming));
+    return FDETD_OK;
+}
+
 int assign_lanes(fdetd_plan_t P)
 {
     constexpr int kMaxLanes = 4;
@@ -1042,6 +1076,12 @@ void fdetd_destroy(fdetd_plan_t plan)
     }
     for (hipEvent_t e : plan->join_ev) (void)hipEventDestroy(e);
     if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
+    if (plan->axis_stream) {
+        (void)hipStreamSynchronize(plan->axis_stream);
+        (void)hipStreamDestroy(plan->axis_stream);
+    }
+    if (plan->axis_fork) (void)hipEventDestroy(plan->axis_fork);
+    if (plan->axis_join) (void)hipEventDestroy(plan->axis_join);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     for (auto &q : plan->probs) free_prob(q);
@@ -1200,6 +1240,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     double tune_ms = 0.0;
     if (rc == FDETD_OK) rc = autotune(P, tune_ms);
     if (rc == FDETD_OK) rc = assign_lanes(P);
+    if (rc == FDETD_OK) rc = make_axis_stream(P);
     if (rc != FDETD_OK) {
         g_last_error = P->err;
         fdetd_destroy(P);
