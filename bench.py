@@ -209,11 +209,16 @@ def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0):
 
 
 def kernel_source_hash():
+    """Hash of the stage kernel's sources without their comments (the text from // to the end of a line)
+    and blank lines, so that an edit of a comment keeps the counters taken on the same code."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

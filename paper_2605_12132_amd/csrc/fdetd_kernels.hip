@@ -443,7 +443,8 @@ __global__ __launch_bounds__(256) void k_jgen(JgenArgs A)
 
 // E part of w_N = psi + beta_in Jbar (the argument of the highest power of H in the Horner form of the
 // midpoint solution of section 2.1) for every problem of a batch, into the E planes of the problem's
-// second stage buffer: the input of the B half of a step's first Horner stage.  Jbar_rho is the staged
+// second stage buffer: the input of the B half of a step's first Horner stage where that stage does not
+// form it itself (increment form, FP32C at N = 1, FDETD_PLAN_SEPARATE_WN).  Jbar_rho is the staged
 // plane, J_theta the corrected one when the plan corrects the current, J_z the caller's.  FP64 arithmetic,
 // one rounding to the storage precision.  Each block strides over the cells of every problem in turn.
 template <typename V>

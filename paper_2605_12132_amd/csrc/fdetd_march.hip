@@ -652,8 +652,9 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 //          dB_theta = -D_z^(-) E_rho   + D_rho^(-,mS) E_z              (staggered rows k >= 1)
 //          dB_z     =  (i m / rho_(-)) E_rho - rho_(-)^-1 D^(-) (rho E_theta)   (k >= 1)
 // Window (primary rows q = k - N_D + t, t = 0 .. 2N_D-1): E_z and g = rho E_theta.
-// In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed before
-// the launch (k_form_wn); otherwise psi or the previous stage's output.
+// In the first stage of a step with a current the E input is w_N = psi + beta_in Jbar, formed as psi and
+// Jbar are loaded (WN) or, where the plan forms it in a pass of its own (k_form_wn), read from that pass's
+// plane; otherwise psi or the previous stage's output.
 // --------------------------------------------------------------------------------------------------
 // WN: the first stage of a step with a current, whose input E part is w_N = psi + beta_in Jbar: vin is psi
 // and each loaded E element is combined with the Jbar element at the same place as it arrives, instead of

@@ -1199,7 +1199,8 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
         cells += q.cells;
         if (P->kind == FDETD_MAXWELL) {
             // per stage: read v, psi (6c each), Jbar (3c), write v (6c); staging J_rho: 2c; FP32C: lo r+w.
-            // (The w_N pass, 9c, is not counted: it is an implementation overhead of the first stage.)
+            // (Forming w_N -- in the first stage, 3c more, or in a pass of its own, 9c -- is not counted:
+            // it is an implementation overhead of the first stage.)
             bytes_step += (int64_t)q.cells * eb * (21 * N + 2) + (precision == FDETD_FP32C ? q.cells * 6 * 8 * 2 : 0);
             // increment form: P = H lo (zeros, lo, P: 18c), P += H psi (psi, P, P: 18c); the last stage also
             // reads psi (6c)
