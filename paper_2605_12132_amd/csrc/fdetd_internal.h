@@ -131,6 +131,7 @@ struct BatchArgs {
     // the first stage with a current forms the E part of w_N from psi and Jbar as it loads them (no
     // k_form_wn pass before it): the Horner form, not the compensated N = 1 stage
     int fuse_wn;
+    int nt_store;  // Maxwell stages store their outputs non-temporal (chosen per batch by the plan's tuning)
     double beta_in, beta, coef;
     const void *psi[kMaxBatch];  // Maxwell psi, or envelope a
     const void *aux[kMaxBatch];  // Maxwell: current of this step (3 planes) or null; envelope: a_tilde

@@ -158,7 +158,7 @@ __device__ __forceinline__ T gld(const void *p, unsigned i)
     if constexpr (sizeof(I) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
     else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
-template <typename T>
+template <typename T, int POL = 0>
 __device__ __forceinline__ void gst(void *p, unsigned i, T v)
 {
     using I = typename ibits<T>::I;
@@ -166,10 +166,19 @@ __device__ __forceinline__ void gst(void *p, unsigned i, T v)
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, 0x7fffffff, kBufWord3);
     if constexpr (sizeof(I) == 8) {
         using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, POL);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, POL);
     }
+}
+// Store of a stage output: non-temporal (bit 1 of the cache-policy operand on this target family) when the
+// plan measured that faster for the batch -- on grids far larger than the caches, outputs that the L2 keeps
+// only evict the rows other wavefronts read again -- else the default policy.  nt is wave-uniform.
+template <typename T>
+__device__ __forceinline__ void gst_out(void *p, unsigned i, T v, int nt)
+{
+    if (nt) gst<T, 2>(p, i, v);
+    else gst<T>(p, i, v);
 }
 // Start of row q of component c of a vector of planes of P elements each (row length nz S elements).
 template <typename E>
@@ -237,6 +246,7 @@ struct Ctx {
     const void *jr, *jt, *jz;  // Jbar planes (null without source)
     const void *hi;            // increment form: the stored psi (hi words), read by the last stage
     int has_src, compensated;
+    int nt_store;  // outputs stored non-temporal
     double beta_in, beta, coef;
 };
 
@@ -289,29 +299,29 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
             two_sum(psi_v.x, (float)(inc.p[0] + (AR)lo_v.x), sx, ex);
             two_sum(psi_v.y, (float)(inc.p[1] + (AR)lo_v.y), sy, ey);
             if (zero_slot) sx = sy = ex = ey = 0.f;
-            gst<float2>(orow, o, float2{sx, sy});
-            gst<float2>(lrow, o, float2{ex, ey});
+            gst_out<float2>(orow, o, float2{sx, sy}, A.nt_store);
+            gst_out<float2>(lrow, o, float2{ex, ey}, A.nt_store);
             return;
         }
         float2 w{(float)((AR)psi_v.x + inc.p[0]), (float)((AR)psi_v.y + inc.p[1])};
         if (zero_slot) w = float2{0.f, 0.f};
-        gst<float2>(orow, o, w);
+        gst_out<float2>(orow, o, w, A.nt_store);
     } else if constexpr (std::is_same<E, float>::value) {  // FP32 storage in lane pairs
         if constexpr (COMP) {
             float sx, ex;
             two_sum(psi_v, (float)(inc.p[0] + (AR)lo_v), sx, ex);
             if (zero_slot) sx = ex = 0.f;
-            gst<float>(orow, o, sx);
-            gst<float>(lrow, o, ex);
+            gst_out<float>(orow, o, sx, A.nt_store);
+            gst_out<float>(lrow, o, ex, A.nt_store);
             return;
         }
         float w = (float)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.f;
-        gst<float>(orow, o, w);
+        gst_out<float>(orow, o, w, A.nt_store);
     } else {
         double w = (double)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.0;
-        gst<double>(orow, o, w);
+        gst_out<double>(orow, o, w, A.nt_store);
     }
 }
 
@@ -423,7 +433,14 @@ __device__ __forceinline__ void march_rows(int k0, int k1, Fetch &fetch, Row &ro
 template <typename V, typename AR, int ND, bool HEAVY>
 constexpr int prefetch_of()
 {
+#ifdef FDETD_ANY_WIDTH
+    // one kernel for every width has the registers of the widest, two wavefronts per SIMD whatever the ring
     constexpr int base = ND <= 8 ? FDETD_PREFETCH : (ND <= 12 ? FDETD_PREFETCH - 1 : FDETD_PREFETCH - 2);
+#else
+    // per width: two rows at N_D >= 9 (at 9 .. 12 3.4-4.8 % faster than three, partly from a third
+    // wavefront per SIMD; one row at 13 .. 16 and three at <= 8 were slower)
+    constexpr int base = ND <= 8 ? FDETD_PREFETCH : FDETD_PREFETCH - 2;
+#endif
     // FP64 arithmetic on whole complex values per lane (near-axis tiles of narrow stencils): 2 rows
     constexpr bool wide = sizeof(AR) > sizeof(typename scal<V>::R) && elem<V>::K == 2;
     constexpr int pf = wide ? 2 : (HEAVY ? base - 1 : base);
@@ -886,6 +903,7 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.jt = A.has_src ? (D.jth ? D.jth : (const char *)A.aux[p] + pb) : nullptr;  // corrected J_theta if any
     C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
     C.compensated = A.compensated && A.n == 0 && A.role == 0;
+    C.nt_store = A.nt_store;
     C.beta_in = A.beta_in;
     C.beta = A.beta;
     C.coef = A.coef;

@@ -60,6 +60,7 @@ struct Prob {
 struct Batch {
     int nd, N, d0, count, ntiles, ntiles_ax;
     int seg;                   // rows per marching segment of the main launch
+    int nt_store = 0;          // Maxwell stage outputs stored non-temporal (autotuned)
     int lane = 0;              // stream of the batch's launches: 0 = the plan's stream, l > 0 = lanes[l - 1]
     double dt;
     std::vector<int> members;  // user indices, in table order
@@ -85,6 +86,7 @@ struct fdetd_plan_s {
     std::vector<double> ev_bytes;
     bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
     std::vector<int> seg_rows;  // per launch batch: rows per marching segment of the main launch
+    std::vector<int> nt_store;  // per launch batch: store policy of the Maxwell stage outputs
     // side streams of a plan whose launch batches run concurrently, with the fork and join events
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
@@ -330,6 +332,7 @@ int enqueue_maxwell_batch(fdetd_plan_t P, const Batch &b, void *const *psi, cons
     A.compensated = P->precision == FDETD_FP32C;
     A.increment = (P->flags & FDETD_PLAN_INCREMENT_FORM) ? 1 : 0;
     A.fuse_wn = fuse_wn(P, b, j != nullptr);
+    A.nt_store = b.nt_store;
     if (A.increment && b.ntiles + b.ntiles_ax) {
         // P = H psi of the step in two passes, H lo from zero, then P += H psi_hi (coef 1, no current), with
         // the stages' own operator (float stencils, FP64 near-axis rows): an operator for P that differed
@@ -629,6 +632,16 @@ int assign_lanes(fdetd_plan_t P)
 // Rows per marching segment: long segments load each rho-stencilled row once per segment (the window
 // warm-up costs 2 N_D - 1 extra rows), short ones give more wavefronts.  Default before autotuning: the
 // longest segment (8 .. 64 rows) that still gives every SIMD of the chip (1024) one wavefront.
+// FDETD_STORE_POLICY = 0 or 1 fixes the store policy of the Maxwell stage outputs (no timing); -1: unset.
+int forced_store_policy()
+{
+    if (const char *e = std::getenv("FDETD_STORE_POLICY")) {
+        if (e[0] == '0' && e[1] == 0) return 0;
+        if (e[0] == '1' && e[1] == 0) return 1;
+    }
+    return -1;
+}
+
 int forced_seg_rows()
 {
     if (const char *e = std::getenv("FDETD_SEG_ROWS")) {
@@ -695,6 +708,7 @@ int build_batches(fdetd_plan_t P)
         }
         const size_t bi = P->batches.size();
         const int seg = have_segs && bi < P->seg_rows.size() ? P->seg_rows[bi] : default_seg_rows(row_strips);
+        b.nt_store = bi < P->nt_store.size() ? P->nt_store[bi] : std::max(0, forced_store_policy());
         int tiles = 0, tiles_ax = 0;
         for (int v = t; v < u; ++v) {
             const Prob &q = P->probs[order[v]];
@@ -899,11 +913,54 @@ int autotune(fdetd_plan_t P, double &ms_spent)
             std::fprintf(stderr, " -> %d\n", best[bi]);
         }
     }
+    if (!rc) {
+        P->seg_rows = best;
+        rc = build_batches(P);
+    }
+    // Store policy of the stage outputs, at the chosen segment length: pairs of consecutive stages (N - 2
+    // and N - 3, each reading the other's output as in a step), outputs stored with the default policy and
+    // non-temporal, two passes in opposite orders, the faster kept.  Non-temporal outputs pay on grids far
+    // larger than the caches and cost where the next stage would find them there; only timing tells.
+    if (!rc && P->kind == FDETD_MAXWELL && forced_store_policy() < 0) {
+        P->nt_store.assign(nb, 0);
+        std::vector<double> tp(2 * nb, 1e300);
+        for (int pass = 0; pass < 2 && !rc; ++pass)
+            for (int k = 0; k < 2 && !rc; ++k) {
+                const int pol = pass == 0 ? k : 1 - k;
+                for (size_t bi = 0; bi < nb && !rc; ++bi) {
+                    const Batch &b = P->batches[bi];
+                    if (b.N < 4) continue;  // the pair needs two stages before the last
+                    BatchArgs A = tuning_args(P, b, scratch);
+                    A.nt_store = pol;
+                    constexpr int kPairs = 2;
+                    for (int r = 0; r <= kPairs && !rc; ++r) {  // one untimed pair, then kPairs timed
+                        if (r == 1 && (e = hipEventRecord(ev[0], P->stream)))
+                            rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+                        for (int n = b.N - 2; n >= b.N - 3 && !rc; --n) {
+                            A.n = n;
+                            A.beta = -b.dt * std::ldexp(1.0, -n);
+                            A.coef = b.dt / (n + 1);
+                            rc = launch_stage(P, b, A, P->stream);
+                        }
+                    }
+                    float ms = 0.f;
+                    if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
+                                (e = hipEventElapsedTime(&ms, ev[0], ev[1]))))
+                        rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
+                    if (!rc) tp[2 * bi + pol] = std::min(tp[2 * bi + pol], (double)ms / (2 * kPairs));
+                }
+            }
+        for (size_t bi = 0; bi < nb && !rc; ++bi) {
+            P->nt_store[bi] = tp[2 * bi + 1] < tp[2 * bi] ? 1 : 0;
+            if (log && P->batches[bi].N >= 4)
+                std::fprintf(stderr, "fdetd autotune batch %zu store policy: default %.4f ms, non-temporal %.4f ms -> %s\n",
+                             bi, tp[2 * bi], tp[2 * bi + 1], P->nt_store[bi] ? "non-temporal" : "default");
+        }
+        if (!rc) rc = build_batches(P);
+    }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
     if (rc) return rc;
-    P->seg_rows = best;
-    if ((rc = build_batches(P))) return rc;
     for (const Prob &q : P->probs)
         if (q.lo) HIPCHK(P, hipMemsetAsync(q.lo, 0, np * q.cells * 8, P->stream));
     ms_spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1264,6 +1321,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.launches_per_step = launches;
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
+    P->info.store_policy = P->batches.empty() ? 0 : P->batches[0].nt_store;
     P->info.autotune_ms = tune_ms;
     P->info.streams = 1 + (int32_t)P->lanes.size();
     hipError_t e = hipDeviceSynchronize();

@@ -1,5 +1,5 @@
 """Host-side checks of the benchmark script (no GPU): the one-GPU contract and the rule that reports the
-committed HBM traffic only for the kernel sources and segment lengths it was measured on."""
+committed HBM traffic only for the kernel sources, segment lengths and store policy it was measured on."""
 import os
 import subprocess
 import sys
@@ -28,9 +28,12 @@ def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
     current = fields["traffic_source_hash"].strip() == bench.kernel_source_hash()
     seg_axis = int(fields["traffic_seg_axis_fp32c"])
     for (tag, seg), v in entries:
-        t = bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0)
+        pol = int(fields.get(f"traffic_store_policy_{tag}", "0"))
+        t = bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0, pol)
         if tag == "fp32c":  # another near-axis segment length: no figure
-            assert bench.measured_traffic(tag, int(seg), seg_axis + 1) is None
+            assert bench.measured_traffic(tag, int(seg), seg_axis + 1, pol) is None
+        # another store policy of the stage outputs: no figure
+        assert bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0, 1 - pol) is None
         if current:  # counters taken on these sources
             assert t == int(float(v)) and t > 0
         else:  # the kernel changed since: no traffic figure until the counters are taken again

@@ -176,8 +176,8 @@ def test_single_hip_runtime_in_process():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
     """Every output is formed by the same operations whatever the marching segment length, so plans with
-    forced segment lengths (main and, in FP32C, near-axis tiles), the default and the autotuned one give
-    bitwise equal fields (FP64 and FP32C, eager and graph)."""
+    forced segment lengths (main and, in FP32C, near-axis tiles) or store policies of the stage outputs,
+    the default and the autotuned one give bitwise equal fields (FP64 and FP32C, eager and graph)."""
     import paper_2605_12132_amd as F
     w = small(1, 16, 8, nz=300, nr=90, steps=2, seed=4)
     rng = np.random.default_rng(71)
@@ -201,6 +201,11 @@ def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
             runs["axis" + sa], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1 | F.PLAN_NO_AUTOTUNE)
             assert info["seg_rows_axis"] == min(int(sa), 16)
         monkeypatch.delenv("FDETD_SEG_AXIS")
+    for pol in ("0", "1"):  # the store policy of the stage outputs changes no value either
+        monkeypatch.setenv("FDETD_STORE_POLICY", pol)
+        runs["store" + pol], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1)
+        assert info["store_policy"] == int(pol)
+    monkeypatch.delenv("FDETD_STORE_POLICY")
     for k, v in runs.items():
         assert np.array_equal(v[0], runs["1"][0]), k
     if precision == 0:
