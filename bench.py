@@ -111,15 +111,18 @@ def bunch_jgen(w, step0):
 
 
 class seg_rows_env:
-    """Plans built inside get FDETD_SEG_ROWS = n (no autotuning) when n is given, and the store policy of
-    the stage outputs FDETD_STORE_POLICY = store_policy when that is given (0 default, 1 non-temporal)."""
+    """Plans built inside get FDETD_SEG_ROWS = n (no autotuning) when n is given, the store policy of the
+    stage outputs FDETD_STORE_POLICY = store_policy (0 default, 1 non-temporal) and the tile numbering
+    FDETD_TILE_ORDER = tile_order (0 half first, 1 segment first) when those are given."""
 
-    def __init__(self, n, store_policy=None):
+    def __init__(self, n, store_policy=None, tile_order=None):
         self.set = {}
         if n:
             self.set["FDETD_SEG_ROWS"] = str(n)
         if store_policy is not None:
             self.set["FDETD_STORE_POLICY"] = str(int(store_policy))
+        if tile_order is not None:
+            self.set["FDETD_TILE_ORDER"] = str(int(tile_order))
         self.old = {}
 
     def __enter__(self):
@@ -145,7 +148,7 @@ def initial_state(w, cd):
 
 
 def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_graph=True, extra_flags=0,
-                   store_policy=None):
+                   store_policy=None, tile_order=None):
     """Warm up W steps, capture the K-step loop of fdetd_step_graph once (untimed, then restore the state),
     time exactly K steps of its replay.  jgen_of(step0) gives the step generator of the call."""
     import torch
@@ -158,7 +161,7 @@ def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_grap
         jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
         flags = (F.PLAN_USE_GRAPH if use_graph else 0) | extra_flags
         t0 = time.time()
-        with seg_rows_env(seg_rows, store_policy):
+        with seg_rows_env(seg_rows, store_policy, tile_order):
             plan = F.Plan(w.problems(), precision=precision, flags=flags)
         plan_s = time.time() - t0
         if warmup:
@@ -188,7 +191,7 @@ def run_graph_path(w, precision, steps, warmup, jgen_of, seg_rows=None, use_grap
     return psi, ms, dict(plan_s=round(plan_s, 2), capture_and_first_replay_s=round(capture_s, 2)), info
 
 
-def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0, store_policy=None):
+def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0, store_policy=None, tile_order=None):
     """Eager pass with HIP events around every stage kernel on the plan's stream: average duration and
     algorithmic bytes (21 complex values per cell).  The plan is given the segment length the timed plan's
     autotuning picked, so both run the same tiling."""
@@ -197,7 +200,7 @@ def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0, store_polic
     cd = torch.complex128 if precision == F.FP64 else torch.complex64
     psi = initial_state(w, cd)
     jw = [torch.zeros((3, w.nr[p], w.nz[p]), dtype=cd, device="cuda") for p in range(w.n)]
-    with seg_rows_env(seg_rows, store_policy):
+    with seg_rows_env(seg_rows, store_policy, tile_order):
         plan = F.Plan(w.problems(), precision=precision, flags=F.PLAN_PROFILE)
     plan.step_graph(psi, jgen_of(0), jw, n_steps=steps)
     info = plan.query()
@@ -209,7 +212,7 @@ def profile_pass(w, precision, steps, jgen_of, seg_rows, seg_axis=0, store_polic
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic("fp64" if precision == F.FP64 else "fp32c", seg_rows, seg_axis,
-                                         info["store_policy"]),
+                                         info["store_policy"], info["tile_order"]),
                 kernel="k_maxwell_stage", launches=n, avg_launch_us=round(avg_ms * 1e3, 2),
                 bytes_per_launch=int(bytes_per_launch), bytes_per_cell=bytes_per_stage(precision),
                 timing="HIP events around each stage launch on the plan's stream, eager pass of "
@@ -230,10 +233,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision_tag, seg_rows, seg_axis=0, store_policy=0):
+def measured_traffic(precision_tag, seg_rows, seg_axis=0, store_policy=0, tile_order=0):
     """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration) from
     the committed PMC summary, or None when it is missing, was taken on other kernel sources, holds no
-    figure for segments of seg_rows rows, was taken with another store policy of the stage outputs, or
+    figure for this tiling (segments of seg_rows rows, store policy of the stage outputs, tile order), or
     (FP32C) was taken with other near-axis segments."""
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -245,9 +248,7 @@ def measured_traffic(precision_tag, seg_rows, seg_axis=0, store_policy=0):
         return None
     if seg_axis and fields.get("traffic_seg_axis_fp32c", "").strip() != str(seg_axis):
         return None
-    if fields.get(f"traffic_store_policy_{precision_tag}", "0").strip() != str(int(store_policy)):
-        return None
-    v = fields.get(f"traffic_bytes_per_launch_{precision_tag}_seg{seg_rows}")
+    v = fields.get(f"traffic_bytes_per_launch_{precision_tag}_seg{seg_rows}_pol{int(store_policy)}_ord{int(tile_order)}")
     return int(float(v)) if v else None
 
 
@@ -695,19 +696,20 @@ def main():
     rate64 = cells * K / (ms64 * 1e-3)
     log(f"FP64: {ms64 / K:.4f} ms/step, {rate64:.4g} cell-updates/s ({t64}, dt*rho {info64['dt_rho_max']:.3f}, "
         f"{info64['seg_rows']} rows per segment)")
-    roof64 = profile_pass(w, F.FP64, args.profile_steps, jg, info64["seg_rows"], 0, info64["store_policy"])
+    roof64 = profile_pass(w, F.FP64, args.profile_steps, jg, info64["seg_rows"], 0, info64["store_policy"],
+                          info64["tile_order"])
     log(f"FP64 stage kernel: {roof64['avg_launch_us']} us/launch, {roof64['achieved']} GB/s ({roof64['frac'] * 100:.1f}% of HBM)")
     psi32, ms32, t32, info32 = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c)
     rate32 = cells * K / (ms32 * 1e-3)
     roof32 = profile_pass(w, F.FP32C, args.profile_steps, jg, info32["seg_rows"], info32["seg_rows_axis"],
-                          info32["store_policy"])
+                          info32["store_policy"], info32["tile_order"])
     errs = fp32c_errors(w, psi64, psi32)
     del psi32
     torch.cuda.empty_cache()
     # the increment form takes the FP32C plan's tuned segment length (no second autotuning)
     psi32i, ms32i, t32i, info32i = run_graph_path(w, F.FP32C, K, W, jg, args.seg_rows_fp32c or info32["seg_rows"],
                                                   extra_flags=F.PLAN_INCREMENT_FORM,
-                                                  store_policy=info32["store_policy"])
+                                                  store_policy=info32["store_policy"], tile_order=info32["tile_order"])
     rate32i = cells * K / (ms32i * 1e-3)
     errs_i = fp32c_errors(w, psi64, psi32i)
     del psi64, psi32i
@@ -719,7 +721,8 @@ def main():
     fp32c = dict(value=rate32, ms_per_step=ms32 / K, dtype="f32+comp", vs_fp64=rate32 / rate64, roofline=roof32,
                  error_vs_fp64_after_steps=W + K, **errs,
                  tiling=dict(seg_rows=info32["seg_rows"], seg_rows_axis=info32["seg_rows_axis"],
-                             store_policy=info32["store_policy"], autotune_ms=round(info32["autotune_ms"], 1)),
+                             store_policy=info32["store_policy"], tile_order=info32["tile_order"],
+                             autotune_ms=round(info32["autotune_ms"], 1)),
                  **t32)
     fp32c_inc = dict(value=rate32i, ms_per_step=ms32i / K, dtype="f32+comp, increment form", vs_fp64=rate32i / rate64,
                      vs_fp32c=rate32i / rate32, launches_per_step=info32i["launches_per_step"],
@@ -781,7 +784,7 @@ def main():
         "roofline": roof64,
         "cpu_baseline": cpu,
         "tiling": dict(seg_rows=info64["seg_rows"], store_policy=info64["store_policy"],
-                       autotune_ms=round(info64["autotune_ms"], 1)),
+                       tile_order=info64["tile_order"], autotune_ms=round(info64["autotune_ms"], 1)),
         "launches_per_step": info64["launches_per_step"],
         "fp32c": fp32c,
         "fp32c_increment": fp32c_inc,

@@ -123,7 +123,10 @@ typedef struct {
     int32_t streams;  /* streams a step call runs on: 1, or up to 4 when the plan has several launch batches */
     int32_t store_policy;  /* Maxwell stage outputs of the first launch batch: 0 default, 1 non-temporal
                               (timed at plan time with the segment length; FDETD_STORE_POLICY = 0 or 1
-                              in the environment fixes it)                                            */
+                              in the environment fixes it; always 0 for launches that mix widths and for
+                              the increment form)                                                   */
+    int32_t tile_order;    /* numbering of the Maxwell tiles of the first launch batch: 0 half, segment,
+                              strip; 1 segment, half, strip (timed at plan time; FDETD_TILE_ORDER fixes it) */
 } fdetd_plan_info;
 
 /* Build a plan for n_probs problems (all FDETD_MAXWELL or all FDETD_ENVELOPE).

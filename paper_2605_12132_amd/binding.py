@@ -53,7 +53,7 @@ class PlanInfo(C.Structure):
                 ("scratch_bytes", C.c_int64), ("launches_per_step", C.c_int64),
                 ("profiled_launches", C.c_int64), ("profiled_ms", C.c_double), ("profiled_bytes", C.c_double),
                 ("seg_rows", C.c_int32), ("seg_rows_axis", C.c_int32), ("autotune_ms", C.c_double),
-                ("streams", C.c_int32), ("store_policy", C.c_int32)]
+                ("streams", C.c_int32), ("store_policy", C.c_int32), ("tile_order", C.c_int32)]
 
 
 JGEN_BUNCH, JGEN_SAMPLES = 1, 2

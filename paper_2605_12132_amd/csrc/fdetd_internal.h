@@ -89,6 +89,7 @@ struct ProbDesc {
                                              // and strips of kAxisColumns columns, FP64 arithmetic (near-axis
                                              // tiles); FP64 plans: 0, 0, 0, 0
     int tile_begin, tile_begin_ax;           // first tile of this problem in the main / near-axis launch
+    int tile_order;                          // 0: tiles numbered half, segment, strip; 1: segment, half, strip
     size_t plane;                            // nz * nr
     double dr, pS, k0;
     double dz, dt;                           // cell length in z and time step (sample deposition)

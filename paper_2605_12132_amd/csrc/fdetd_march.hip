@@ -171,14 +171,13 @@ __device__ __forceinline__ void gst(void *p, unsigned i, T v)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, POL);
     }
 }
-// Store of a stage output: non-temporal (bit 1 of the cache-policy operand on this target family) when the
-// plan measured that faster for the batch -- on grids far larger than the caches, outputs that the L2 keeps
-// only evict the rows other wavefronts read again -- else the default policy.  nt is wave-uniform.
-template <typename T>
-__device__ __forceinline__ void gst_out(void *p, unsigned i, T v, int nt)
+// Store of a stage output: non-temporal (bit 1 of the cache-policy operand on this target family) in the
+// kernel variants the plan picks when it measured them faster for a batch -- on grids far larger than the
+// caches, outputs that the L2 keeps only evict the rows other wavefronts read again -- else the default.
+template <typename T, bool NT>
+__device__ __forceinline__ void gst_out(void *p, unsigned i, T v)
 {
-    if (nt) gst<T, 2>(p, i, v);
-    else gst<T>(p, i, v);
+    gst<T, NT ? 2 : 0>(p, i, v);
 }
 // Start of row q of component c of a vector of planes of P elements each (row length nz S elements).
 template <typename E>
@@ -246,7 +245,6 @@ struct Ctx {
     const void *jr, *jt, *jz;  // Jbar planes (null without source)
     const void *hi;            // increment form: the stored psi (hi words), read by the last stage
     int has_src, compensated;
-    int nt_store;  // outputs stored non-temporal
     double beta_in, beta, coef;
 };
 
@@ -283,7 +281,7 @@ __device__ __forceinline__ lv<AR, elem<V>::K> ldrow(const typename stor<V>::T *p
 // Store one output value: out = psi + inc (inc already holds beta*Jbar + coef*H v), or, in the last stage
 // of an FP32C step, the exact TwoSum of (psi_hi, lo + inc) into (psi_hi, lo).  psi_v / lo_v are the values
 // at the output position, loaded one row ahead.
-template <typename V, typename AR, bool COMP>
+template <typename V, typename AR, bool COMP, bool NT>
 __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane<V> &L, lv<AR, elem<V>::K> inc,
                                           bool zero_slot, typename elem<V>::E psi_v, typename elem<V>::Lo lo_v)
 {
@@ -299,29 +297,29 @@ __device__ __forceinline__ void store_out(const Ctx &A, int c, int k, const Lane
             two_sum(psi_v.x, (float)(inc.p[0] + (AR)lo_v.x), sx, ex);
             two_sum(psi_v.y, (float)(inc.p[1] + (AR)lo_v.y), sy, ey);
             if (zero_slot) sx = sy = ex = ey = 0.f;
-            gst_out<float2>(orow, o, float2{sx, sy}, A.nt_store);
-            gst_out<float2>(lrow, o, float2{ex, ey}, A.nt_store);
+            gst_out<float2, NT>(orow, o, float2{sx, sy});
+            gst_out<float2, NT>(lrow, o, float2{ex, ey});
             return;
         }
         float2 w{(float)((AR)psi_v.x + inc.p[0]), (float)((AR)psi_v.y + inc.p[1])};
         if (zero_slot) w = float2{0.f, 0.f};
-        gst_out<float2>(orow, o, w, A.nt_store);
+        gst_out<float2, NT>(orow, o, w);
     } else if constexpr (std::is_same<E, float>::value) {  // FP32 storage in lane pairs
         if constexpr (COMP) {
             float sx, ex;
             two_sum(psi_v, (float)(inc.p[0] + (AR)lo_v), sx, ex);
             if (zero_slot) sx = ex = 0.f;
-            gst_out<float>(orow, o, sx, A.nt_store);
-            gst_out<float>(lrow, o, ex, A.nt_store);
+            gst_out<float, NT>(orow, o, sx);
+            gst_out<float, NT>(lrow, o, ex);
             return;
         }
         float w = (float)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.f;
-        gst_out<float>(orow, o, w, A.nt_store);
+        gst_out<float, NT>(orow, o, w);
     } else {
         double w = (double)((AR)psi_v + inc.p[0]);
         if (zero_slot) w = 0.0;
-        gst_out<double>(orow, o, w, A.nt_store);
+        gst_out<double, NT>(orow, o, w);
     }
 }
 
@@ -527,7 +525,7 @@ __device__ __forceinline__ lv<AR, elem<V>::K> lds_at(const typename elem<V>::E *
 //          dE_z     = -(i m / rho) B_rho + rho^-1 D^(+) (rho_(-) B_theta)
 // Window (staggered rows q = k - N_D + 1 + t, t = 0 .. 2N_D-1): B_z and g = rho_(-) B_theta.
 // --------------------------------------------------------------------------------------------------
-template <typename V, typename AR, int ND, bool SRC, bool COMP, bool INC>
+template <typename V, typename AR, int ND, bool SRC, bool COMP, bool INC, bool NT>
 __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     // ring of the last N_D + 1 raw B_theta rows (own elements): the z stencil of row k reads row k from here,
@@ -651,9 +649,9 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
             const L_ i0v = cfma(beta, to_lv<AR>(cu.j0), cmul(coef, with_p<INC, AR, V>(cu.p0, t0 - zth)));
             const L_ i1v = cfma(beta, to_lv<AR>(cu.j1), cmul(coef, with_p<INC, AR, V>(cu.p1, zr - rz)));
             const L_ i2v = cfma(beta, to_lv<AR>(cu.j2), cmul(coef, with_p<INC, AR, V>(cu.p2, rip * rg - t2)));
-            store_out<V, AR, COMP>(A, ER, k, L, i0v, k == 0, out_base<INC, COMP>(cu.p0, cu.h0), cu.l0);
-            store_out<V, AR, COMP>(A, ETH, k, L, i1v, false, out_base<INC, COMP>(cu.p1, cu.h1), cu.l1);
-            store_out<V, AR, COMP>(A, EZ, k, L, i2v, false, out_base<INC, COMP>(cu.p2, cu.h2), cu.l2);
+            store_out<V, AR, COMP, NT>(A, ER, k, L, i0v, k == 0, out_base<INC, COMP>(cu.p0, cu.h0), cu.l0);
+            store_out<V, AR, COMP, NT>(A, ETH, k, L, i1v, false, out_base<INC, COMP>(cu.p1, cu.h1), cu.l1);
+            store_out<V, AR, COMP, NT>(A, EZ, k, L, i2v, false, out_base<INC, COMP>(cu.p2, cu.h2), cu.l2);
         }
 #pragma unroll
         for (int t = 0; t < 2 * ND - 1; ++t) {
@@ -676,7 +674,7 @@ __device__ __forceinline__ void e_half(const Ctx &A, int i0, int k0, int k1, typ
 // WN: the first stage of a step with a current, whose input E part is w_N = psi + beta_in Jbar: vin is psi
 // and each loaded E element is combined with the Jbar element at the same place as it arrives, instead of
 // being read from a w_N plane formed by a separate pass.
-template <typename V, typename AR, int ND, bool COMP, bool INC, bool WN>
+template <typename V, typename AR, int ND, bool COMP, bool INC, bool WN, bool NT>
 __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     // ring of the last N_D + 1 raw E_theta rows (own elements), as in e_half
@@ -809,11 +807,11 @@ __device__ __forceinline__ void b_half(const Ctx &A, int i0, int k0, int k1, typ
         __syncthreads();
         if (L.col && live) {
             const Coef<AR> coef = split_coef<AR>(A.coef);
-            store_out<V, AR, COMP>(A, BR, k, L, cmul(coef, with_p<INC, AR, V>(cu.p0, zth - t0)), false,
+            store_out<V, AR, COMP, NT>(A, BR, k, L, cmul(coef, with_p<INC, AR, V>(cu.p0, zth - t0)), false,
                                    out_base<INC, COMP>(cu.p0, cu.h0), cu.l0);
-            store_out<V, AR, COMP>(A, BTH, k, L, cmul(coef, with_p<INC, AR, V>(cu.p1, rz - zr)), k == 0,
+            store_out<V, AR, COMP, NT>(A, BTH, k, L, cmul(coef, with_p<INC, AR, V>(cu.p1, rz - zr)), k == 0,
                                    out_base<INC, COMP>(cu.p1, cu.h1), cu.l1);
-            store_out<V, AR, COMP>(A, BZ, k, L, cmul(coef, with_p<INC, AR, V>(cu.p2, t2 - ris * rg)), k == 0,
+            store_out<V, AR, COMP, NT>(A, BZ, k, L, cmul(coef, with_p<INC, AR, V>(cu.p2, t2 - ris * rg)), k == 0,
                                    out_base<INC, COMP>(cu.p2, cu.h2), cu.l2);
         }
 #pragma unroll
@@ -857,7 +855,7 @@ __device__ __forceinline__ int problem_of_tile(const BatchArgs &A, int t)
 // AXIS = false: rows ax_rows .. nr-1 in the storage precision; AXIS = true (FP32 storage; V = float2 or,
 // for wide stencils, f2pair read in lane pairs): rows 0 .. ax_rows-1 (= 2 N_D), whose stencils reach the
 // axis and its 1/rho factors, in FP64 arithmetic.
-template <typename V, int ND, bool SRC, bool COMP, bool INC, bool AXIS, bool WN>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool AXIS, bool WN, bool NT>
 __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename elem<V>::E (*lds)[WAVE + 2 * ND * elem<V>::S])
 {
     constexpr int S = elem<V>::S, CPW = WAVE / S;
@@ -903,13 +901,12 @@ __device__ __forceinline__ void maxwell_tile(const BatchArgs &A, int t, typename
     C.jt = A.has_src ? (D.jth ? D.jth : (const char *)A.aux[p] + pb) : nullptr;  // corrected J_theta if any
     C.jz = A.has_src ? (const char *)A.aux[p] + 2 * pb : nullptr;
     C.compensated = A.compensated && A.n == 0 && A.role == 0;
-    C.nt_store = A.nt_store;
     C.beta_in = A.beta_in;
     C.beta = A.beta;
     C.coef = A.coef;
     using AR = typename std::conditional<AXIS, double, typename scal<V>::R>::type;
-    if (half == 0) e_half<V, AR, ND, SRC, COMP, INC>(C, i0, k0, k1, lds);
-    else b_half<V, AR, ND, COMP, INC, WN>(C, i0, k0, k1, lds);
+    if (half == 0) e_half<V, AR, ND, SRC, COMP, INC, NT>(C, i0, k0, k1, lds);
+    else b_half<V, AR, ND, COMP, INC, WN, NT>(C, i0, k0, k1, lds);
 }
 
 // One Horner stage of every problem of a batch, near-axis and main tiles in one launch.
@@ -927,7 +924,7 @@ constexpr int stage_lds_bytes()
     return 2 * lds_row_bytes<V, ND>() + (ND + 1) * WAVE * (int)sizeof(typename elem<V>::E);
 }
 
-template <typename V, int ND, bool SRC, bool COMP, bool INC, bool WN>
+template <typename V, int ND, bool SRC, bool COMP, bool INC, bool WN, bool NT>
 __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
 {
     // layout of the near-axis tiles (FP32 storage only): whole complex values per lane or lane pairs
@@ -940,12 +937,12 @@ __global__ __launch_bounds__(WAVE) void k_maxwell_stage(BatchArgs A)
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if (axis) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, INC, true, WN>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, INC, true, WN, NT>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, INC, false, WN>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, INC, false, WN, NT>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -1264,12 +1261,19 @@ hipError_t go_stagger(const BatchArgs &a, hipStream_t s)
 }
 
 // Launch stage n of a batch with the kernel variant its flags select.
+// The Horner form (INC false) also exists with non-temporal output stores (the plan's choice per batch).
 template <typename V, int ND, bool SRC, bool COMP, bool INC, bool WN = false>
 hipError_t go_maxwell_v(const BatchArgs &a, hipStream_t s)
 {
     if (sizeof(typename scal<V>::R) == 8 && a.ntiles_ax) return hipErrorInvalidValue;  // FP32 storage only
-    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, INC, WN>), dim3(blocks_of(a.ntiles_ax, a.ntiles)),
-                       dim3(WAVE), 0, s, a);
+    const dim3 grid(blocks_of(a.ntiles_ax, a.ntiles));
+    if constexpr (!INC) {
+        if (a.nt_store) {
+            hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, false, WN, true>), grid, dim3(WAVE), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_maxwell_stage<V, ND, SRC, COMP, INC, WN, false>), grid, dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1340,12 +1344,12 @@ __device__ __forceinline__ void stage_tile_any(const BatchArgs &A, int t, unsign
     if constexpr (sizeof(typename scal<V>::R) == 4) {
         if constexpr (AXIS) {
             using EA = typename elem<VA>::E;
-            maxwell_tile<VA, ND, SRC, COMP, false, true, WN>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
+            maxwell_tile<VA, ND, SRC, COMP, false, true, WN, false>(A, t, (EA(*)[WAVE + 2 * ND * elem<VA>::S])smem);
             return;
         }
     }
     using E = typename elem<V>::E;
-    maxwell_tile<V, ND, SRC, COMP, false, false, WN>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
+    maxwell_tile<V, ND, SRC, COMP, false, false, WN, false>(A, t, (E(*)[WAVE + 2 * ND * elem<V>::S])smem);
 }
 
 // AXIS: the launch covers the FP32C near-axis tiles only (their FP64-arithmetic code for all widths in one

@@ -61,6 +61,7 @@ struct Batch {
     int nd, N, d0, count, ntiles, ntiles_ax;
     int seg;                   // rows per marching segment of the main launch
     int nt_store = 0;          // Maxwell stage outputs stored non-temporal (autotuned)
+    int tile_order = 0;        // numbering of the Maxwell tiles (ProbDesc::tile_order, autotuned)
     int lane = 0;              // stream of the batch's launches: 0 = the plan's stream, l > 0 = lanes[l - 1]
     double dt;
     std::vector<int> members;  // user indices, in table order
@@ -87,6 +88,7 @@ struct fdetd_plan_s {
     bool adopt_next = false;  // fdetd_import_state: the next call keeps the imported words for its pointers
     std::vector<int> seg_rows;  // per launch batch: rows per marching segment of the main launch
     std::vector<int> nt_store;  // per launch batch: store policy of the Maxwell stage outputs
+    std::vector<int> tile_order;  // per launch batch: tile numbering
     // side streams of a plan whose launch batches run concurrently, with the fork and join events
     std::vector<hipStream_t> lanes;
     hipEvent_t fork_ev = nullptr;
@@ -632,10 +634,27 @@ int assign_lanes(fdetd_plan_t P)
 // Rows per marching segment: long segments load each rho-stencilled row once per segment (the window
 // warm-up costs 2 N_D - 1 extra rows), short ones give more wavefronts.  Default before autotuning: the
 // longest segment (8 .. 64 rows) that still gives every SIMD of the chip (1024) one wavefront.
+// Whether a batch's stage kernels exist with non-temporal output stores: per-width Maxwell launches of the
+// Horner form (launches that mix widths and the increment form keep the default stores).
+bool store_policy_applies(const fdetd_plan_t P, const Batch &b)
+{
+    return P->kind == FDETD_MAXWELL && b.nd > 0 && !(P->flags & FDETD_PLAN_INCREMENT_FORM);
+}
+
 // FDETD_STORE_POLICY = 0 or 1 fixes the store policy of the Maxwell stage outputs (no timing); -1: unset.
 int forced_store_policy()
 {
     if (const char *e = std::getenv("FDETD_STORE_POLICY")) {
+        if (e[0] == '0' && e[1] == 0) return 0;
+        if (e[0] == '1' && e[1] == 0) return 1;
+    }
+    return -1;
+}
+
+// FDETD_TILE_ORDER = 0 or 1 fixes the numbering of the Maxwell tiles (no timing); -1: unset.
+int forced_tile_order()
+{
+    if (const char *e = std::getenv("FDETD_TILE_ORDER")) {
         if (e[0] == '0' && e[1] == 0) return 0;
         if (e[0] == '1' && e[1] == 0) return 1;
     }
@@ -709,6 +728,7 @@ int build_batches(fdetd_plan_t P)
         const size_t bi = P->batches.size();
         const int seg = have_segs && bi < P->seg_rows.size() ? P->seg_rows[bi] : default_seg_rows(row_strips);
         b.nt_store = bi < P->nt_store.size() ? P->nt_store[bi] : std::max(0, forced_store_policy());
+        b.tile_order = bi < P->tile_order.size() ? P->tile_order[bi] : std::max(0, forced_tile_order());
         int tiles = 0, tiles_ax = 0;
         for (int v = t; v < u; ++v) {
             const Prob &q = P->probs[order[v]];
@@ -716,6 +736,7 @@ int build_batches(fdetd_plan_t P)
             describe_problem(q.d, P->precision, seg, D);
             D.tile_begin = tiles;
             D.tile_begin_ax = tiles_ax;
+            D.tile_order = P->kind == FDETD_MAXWELL ? b.tile_order : 0;
             D.buf[0] = q.buf[0];
             D.buf[1] = q.buf[1];
             D.jbar = q.jbar;
@@ -739,6 +760,7 @@ int build_batches(fdetd_plan_t P)
         b.seg = seg;
         b.ntiles = tiles;
         b.ntiles_ax = tiles_ax;
+        if (!store_policy_applies(P, b)) b.nt_store = 0;
         P->batches.push_back(b);
         t = u;
     }
@@ -917,19 +939,28 @@ int autotune(fdetd_plan_t P, double &ms_spent)
         P->seg_rows = best;
         rc = build_batches(P);
     }
-    // Store policy of the stage outputs, at the chosen segment length: pairs of consecutive stages (N - 2
-    // and N - 3, each reading the other's output as in a step), outputs stored with the default policy and
-    // non-temporal, two passes in opposite orders, the faster kept.  Non-temporal outputs pay on grids far
-    // larger than the caches and cost where the next stage would find them there; only timing tells.
-    if (!rc && P->kind == FDETD_MAXWELL && forced_store_policy() < 0) {
-        P->nt_store.assign(nb, 0);
-        std::vector<double> tp(2 * nb, 1e300);
+    // Store policy of the stage outputs and numbering of the tiles, at the chosen segment length: pairs of
+    // consecutive stages (N - 2 and N - 3, each reading the other's output as in a step) under each of the
+    // four combinations, two passes in opposite orders, the fastest kept.  Non-temporal outputs pay on grids
+    // far larger than the caches and cost where the next stage would find them there; the tile numbering
+    // changes which tiles share an XCD's L2 at a time; only timing tells.  FDETD_STORE_POLICY and
+    // FDETD_TILE_ORDER fix either.
+    if (!rc && P->kind == FDETD_MAXWELL && (forced_store_policy() < 0 || forced_tile_order() < 0)) {
+        std::vector<double> tc(4 * nb, 1e300);
         for (int pass = 0; pass < 2 && !rc; ++pass)
-            for (int k = 0; k < 2 && !rc; ++k) {
-                const int pol = pass == 0 ? k : 1 - k;
+            for (int k = 0; k < 4 && !rc; ++k) {
+                const int combo = pass == 0 ? k : 3 - k;
+                const int pol = combo & 1, ord = combo >> 1;
+                if ((forced_store_policy() >= 0 && pol != forced_store_policy()) ||
+                    (forced_tile_order() >= 0 && ord != forced_tile_order()))
+                    continue;
+                P->nt_store.assign(nb, pol);
+                P->tile_order.assign(nb, ord);
+                if ((rc = build_batches(P))) break;
                 for (size_t bi = 0; bi < nb && !rc; ++bi) {
                     const Batch &b = P->batches[bi];
                     if (b.N < 4) continue;  // the pair needs two stages before the last
+                    if (pol && !store_policy_applies(P, b)) continue;
                     BatchArgs A = tuning_args(P, b, scratch);
                     A.nt_store = pol;
                     constexpr int kPairs = 2;
@@ -947,16 +978,28 @@ int autotune(fdetd_plan_t P, double &ms_spent)
                     if (!rc && ((e = hipEventRecord(ev[1], P->stream)) || (e = hipEventSynchronize(ev[1])) ||
                                 (e = hipEventElapsedTime(&ms, ev[0], ev[1]))))
                         rc = fail(P, FDETD_E_HIP, "autotune: %s", hipGetErrorString(e));
-                    if (!rc) tp[2 * bi + pol] = std::min(tp[2 * bi + pol], (double)ms / (2 * kPairs));
+                    if (!rc) tc[4 * bi + combo] = std::min(tc[4 * bi + combo], (double)ms / (2 * kPairs));
                 }
             }
+        std::vector<int> pol_best(nb, std::max(0, forced_store_policy())), ord_best(nb, std::max(0, forced_tile_order()));
         for (size_t bi = 0; bi < nb && !rc; ++bi) {
-            P->nt_store[bi] = tp[2 * bi + 1] < tp[2 * bi] ? 1 : 0;
-            if (log && P->batches[bi].N >= 4)
-                std::fprintf(stderr, "fdetd autotune batch %zu store policy: default %.4f ms, non-temporal %.4f ms -> %s\n",
-                             bi, tp[2 * bi], tp[2 * bi + 1], P->nt_store[bi] ? "non-temporal" : "default");
+            int cb = -1;
+            for (int c = 0; c < 4; ++c)
+                if (tc[4 * bi + c] < 1e299 && (cb < 0 || tc[4 * bi + c] < tc[4 * bi + cb])) cb = c;
+            if (cb < 0) continue;  // not timed (Taylor order below 4): the defaults
+            pol_best[bi] = cb & 1;
+            ord_best[bi] = cb >> 1;
+            if (log)
+                std::fprintf(stderr, "fdetd autotune batch %zu store policy x tile order: %.4f / %.4f / %.4f / %.4f ms "
+                             "(default, non-temporal; half first, segment first) -> %s, %s\n", bi, tc[4 * bi],
+                             tc[4 * bi + 1], tc[4 * bi + 2], tc[4 * bi + 3], pol_best[bi] ? "non-temporal" : "default",
+                             ord_best[bi] ? "segment first" : "half first");
         }
-        if (!rc) rc = build_batches(P);
+        if (!rc) {
+            P->nt_store = pol_best;
+            P->tile_order = ord_best;
+            rc = build_batches(P);
+        }
     }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
@@ -1322,6 +1365,7 @@ int fdetd_plan(const fdetd_problem_desc *probs, int32_t n_probs, int32_t precisi
     P->info.seg_rows = P->batches.empty() ? 0 : P->batches[0].seg;
     P->info.seg_rows_axis = P->desc.empty() ? 0 : P->desc[0].seg_ax;
     P->info.store_policy = P->batches.empty() ? 0 : P->batches[0].nt_store;
+    P->info.tile_order = P->batches.empty() ? 0 : P->batches[0].tile_order;
     P->info.autotune_ms = tune_ms;
     P->info.streams = 1 + (int32_t)P->lanes.size();
     hipError_t e = hipDeviceSynchronize();

@@ -1,5 +1,6 @@
 """Host-side checks of the benchmark script (no GPU): the one-GPU contract and the rule that reports the
-committed HBM traffic only for the kernel sources, segment lengths and store policy it was measured on."""
+committed HBM traffic only for the kernel sources and tilings (segment length, store policy of the stage
+outputs, tile order) it was measured on."""
 import os
 import subprocess
 import sys
@@ -22,24 +23,30 @@ def test_traffic_only_for_the_measured_sources_and_tiling(monkeypatch):
         return
     text = open(bench.TRAFFIC_FILE).read()
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("traffic_"))
-    entries = [(k[len("traffic_bytes_per_launch_"):].split("_seg"), v) for k, v in fields.items()
-               if k.startswith("traffic_bytes_per_launch_")]
+    entries = []  # (tag, segment rows, store policy, tile order), figure
+    for k, v in fields.items():
+        if k.startswith("traffic_bytes_per_launch_"):
+            tag, rest = k[len("traffic_bytes_per_launch_"):].split("_seg")
+            seg, pol, ordr = rest.replace("_pol", " ").replace("_ord", " ").split()
+            entries.append(((tag, int(seg), int(pol), int(ordr)), v))
     assert entries
     current = fields["traffic_source_hash"].strip() == bench.kernel_source_hash()
     seg_axis = int(fields["traffic_seg_axis_fp32c"])
-    for (tag, seg), v in entries:
-        pol = int(fields.get(f"traffic_store_policy_{tag}", "0"))
-        t = bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0, pol)
+    keys = {e[0] for e in entries}
+    for (tag, seg, pol, ordr), v in entries:
+        sa = seg_axis if tag == "fp32c" else 0
+        t = bench.measured_traffic(tag, seg, sa, pol, ordr)
         if tag == "fp32c":  # another near-axis segment length: no figure
-            assert bench.measured_traffic(tag, int(seg), seg_axis + 1, pol) is None
-        # another store policy of the stage outputs: no figure
-        assert bench.measured_traffic(tag, int(seg), seg_axis if tag == "fp32c" else 0, 1 - pol) is None
+            assert bench.measured_traffic(tag, seg, seg_axis + 1, pol, ordr) is None
+        for other in ((tag, seg, 1 - pol, ordr), (tag, seg, pol, 1 - ordr)):  # a tiling not measured: none
+            if other not in keys:
+                assert bench.measured_traffic(tag, seg, sa, other[2], other[3]) is None
         if current:  # counters taken on these sources
             assert t == int(float(v)) and t > 0
         else:  # the kernel changed since: no traffic figure until the counters are taken again
             assert t is None
     # a tiling without counters, or other sources: no traffic figure
-    (tag, seg), _ = entries[0]
-    assert bench.measured_traffic(tag, 3 * int(seg)) is None
+    (tag, seg, pol, ordr), _ = entries[0]
+    assert bench.measured_traffic(tag, 3 * seg, 0, pol, ordr) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic(tag, int(seg)) is None
+    assert bench.measured_traffic(tag, seg, seg_axis if tag == "fp32c" else 0, pol, ordr) is None

@@ -176,8 +176,9 @@ def test_single_hip_runtime_in_process():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
     """Every output is formed by the same operations whatever the marching segment length, so plans with
-    forced segment lengths (main and, in FP32C, near-axis tiles) or store policies of the stage outputs,
-    the default and the autotuned one give bitwise equal fields (FP64 and FP32C, eager and graph)."""
+    forced segment lengths (main and, in FP32C, near-axis tiles), store policies of the stage outputs or
+    tile orders, the default and the autotuned one give bitwise equal fields (FP64 and FP32C, eager and
+    graph)."""
     import paper_2605_12132_amd as F
     w = small(1, 16, 8, nz=300, nr=90, steps=2, seed=4)
     rng = np.random.default_rng(71)
@@ -206,6 +207,11 @@ def test_tiling_and_autotune_do_not_change_results(precision, monkeypatch):
         runs["store" + pol], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=1)
         assert info["store_policy"] == int(pol)
     monkeypatch.delenv("FDETD_STORE_POLICY")
+    for order in ("0", "1"):  # nor the numbering of the tiles
+        monkeypatch.setenv("FDETD_TILE_ORDER", order)
+        runs["order" + order], info = gpu_maxwell(w, psi0, J, 2, precision=precision, flags=3)
+        assert info["tile_order"] == int(order)
+    monkeypatch.delenv("FDETD_TILE_ORDER")
     for k, v in runs.items():
         assert np.array_equal(v[0], runs["1"][0]), k
     if precision == 0:

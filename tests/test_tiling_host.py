@@ -1,7 +1,7 @@
 """The tile decoding shared by the row-marching kernels (csrc/fdetd_tiles.h), compiled for the host with
 g++ and checked over random tilings: every (half, z column, rho row) of a problem is produced exactly once
-by the near-axis tiles (32 columns wide) and the main tiles together, and no tile leaves the grid or
-its kind's rows.  This is the same
+by the near-axis tiles (32 columns wide) and the main tiles together, in either tile order, and no tile
+leaves the grid or its kind's rows.  This is the same
 function the kernels call, so a decoding mistake is caught here before it reaches the GPU."""
 import os
 import subprocess
@@ -25,6 +25,7 @@ int main() {
     for (int trial = 0; trial < 20000; ++trial) {
         ProbDesc D; std::memset(&D, 0, sizeof D);
         const int cpw = rnd(0, 1) ? 32 : 64, cpw_ax = 32, halves = rnd(1, 2);
+        D.tile_order = rnd(0, 1);
         D.nz = rnd(1, 700); D.nr = rnd(1, 300); D.seg_rows = rnd(1, 70);
         D.nstrip = (D.nz + cpw - 1) / cpw;
         if (rnd(0, 1)) {  // FP32C: near-axis tiles over the first rows, 32 columns wide
