@@ -90,6 +90,16 @@ extern "C" {
                                         Same results bit for bit; one more launch and ~9 complex values
                                         per cell more traffic per step                                    */
 
+/* Environment variables read when a plan is made (tuning and measurement; none changes a result value):
+ *   FDETD_SEG_ROWS      1..4096: rows per marching segment of the main tiles (no autotuning)
+ *   FDETD_SEG_AXIS      1..64: rows per segment of the FP32C near-axis tiles (default 16)
+ *   FDETD_STORE_POLICY  0 or 1: Maxwell stage outputs stored with the default or non-temporal cache policy
+ *                       (otherwise timed at plan time with the segment length)
+ *   FDETD_TILE_ORDER    0 or 1: Maxwell tiles numbered half first or segment first (otherwise timed)
+ *   FDETD_AUTOTUNE_LOG  set: the tuning's per-candidate times on stderr
+ * and one that changes FP32C results, for measuring what the FP64 near-axis band buys:
+ *   FDETD_AXIS_ROWS     0..4096: rows next to the axis that FP32C plans compute in FP64 (default 2 N_D) */
+
 typedef struct fdetd_plan_s *fdetd_plan_t;
 
 /* One independent problem: one grid and one azimuthal mode (modes never couple, section 2.1). */
